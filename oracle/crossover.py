@@ -1,0 +1,173 @@
+"""Crossover from an interior-point iterate to the exact optimum (oracle).
+
+At the optimum of the build's Eq. 1 instance every eligible coordinate either
+sits on a bound / kink of its piecewise-linear trade cost (fixed) or lies
+inside one linear piece (free, with a known slope).  Given that classification
+and the set of binding bands and cap, w* solves one equality-constrained QP:
+
+  gamma (Sigma w)_F - mu_F + slope_F + lam_cap sgn_F - nu 1 + A_F^T lam = 0
+  1^T w = 1,   (A w)_g = bound_g (binding g),   sgn^T (w - w0) = tau (cap)
+
+solved here in float64 (dense for moderate |F|, factor-space Woodbury
+otherwise).  The classification is read off the interior-point iterate with
+a snap tolerance; several tolerances are tried and the candidate with the
+smallest external KKT residual (``oracle.kkt``) is kept.
+
+Test infrastructure only.
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.linalg as sla
+
+from .problem import AccountProblem, kinks_and_slopes
+from .kkt import residuals
+
+
+def _classify(P: AccountProblem, w, tol):
+    n = P.n
+    fixed = np.zeros(n, dtype=bool)
+    val = np.zeros(n)
+    slope = np.zeros(n)
+    sgn = np.zeros(n)
+    taxed = {int(i) for i in P.tax_asset}
+    lb, ub = P.lb, P.ub
+    for i in range(n):
+        if not P.eligible[i]:
+            fixed[i] = True
+            val[i] = 0.0
+            continue
+        if i in taxed or P.kappa > 0 or np.isfinite(P.tau):
+            kinks, slopes = kinks_and_slopes(P, i, 0.0)
+        else:
+            kinks, slopes = np.zeros(0), np.zeros(1)
+        pts = [lb, ub] + [c for c in kinks if lb < c < ub]
+        pts = np.asarray(pts)
+        dist = np.abs(pts - w[i])
+        j = int(np.argmin(dist))
+        if dist[j] <= tol:
+            fixed[i] = True
+            val[i] = pts[j]
+        else:
+            piece = int(np.searchsorted(kinks, w[i])) if len(kinks) else 0
+            slope[i] = slopes[piece]
+            sgn[i] = 1.0 if w[i] > P.w0[i] else -1.0
+    return fixed, val, slope, sgn
+
+
+def _solve_reduced(P: AccountProblem, F, rhs, C, h, eta0):
+    """Solve [gamma Sigma_FF, C^T; C, 0][w_F; eta] = [rhs; h].
+
+    Eliminating w_F gives S eta = C H^-1 rhs - h with S = C H^-1 C^T.  When
+    the free set does not pin every multiplier (an active band with no free
+    member, or budget and cap rows parallel on F) S is singular; the system
+    is then consistent and the minimum-norm correction of the interior-point
+    multipliers eta0 is taken.  w_F does not depend on that choice.
+    """
+    g = P.gamma
+    BF = P.B[F]
+    dF = P.d[F]
+    nF = len(F)
+    if nF == 0:
+        return np.zeros(0), np.asarray(eta0, dtype=np.float64)
+    if nF <= 3000:
+        H = g * ((BF * P.f) @ BF.T + np.diag(dF))
+        cho_h = sla.cho_factor(H)
+
+        def Hinv(V):
+            return sla.cho_solve(cho_h, V)
+    else:
+        # Woodbury in factor space: H^-1 = (1/g)(D^-1 - D^-1 B Kf^-1 B^T D^-1)
+        Kf = np.diag(1.0 / P.f) + (BF / dF[:, None]).T @ BF
+        cho = sla.cho_factor(Kf)
+
+        def Hinv(V):
+            V2 = V if V.ndim == 2 else V[:, None]
+            DV = V2 / dF[:, None]
+            out = (DV - (BF / dF[:, None]) @ sla.cho_solve(cho, BF.T @ DV)) / g
+            return out if V.ndim == 2 else out[:, 0]
+
+    Hr = Hinv(rhs)
+    HC = Hinv(C.T)
+    S = C @ HC
+    r = C @ Hr - h
+    corr = np.linalg.lstsq(S, r - S @ eta0, rcond=1e-13)[0]
+    eta = eta0 + corr
+    return Hr - HC @ eta, eta
+
+
+def crossover_once(P: AccountProblem, w, tol, tol_con, nu0=0.0,
+                   lam_band0=None, lam_cap0=0.0):
+    n = P.n
+    fixed, val, slope, sgn = _classify(P, w, tol)
+    F = np.nonzero(~fixed)[0]
+    X = np.nonzero(fixed)[0]
+    wX = val[X]
+    G = P.n_groups
+    # binding bands
+    act = []
+    if G:
+        Aw = np.bincount(P.group, weights=w, minlength=G)
+        for g_ in range(G):
+            if abs(Aw[g_] - P.band_hi[g_]) <= tol_con:
+                act.append((g_, P.band_hi[g_]))
+            elif abs(Aw[g_] - P.band_lo[g_]) <= tol_con:
+                act.append((g_, P.band_lo[g_]))
+    cap_on = bool(np.isfinite(P.tau) and
+                  abs(np.abs(w - P.w0).sum() - P.tau) <= tol_con)
+    rows, hs = [np.ones(len(F))], [1.0 - wX.sum()]
+    for g_, bnd in act:
+        inF = (P.group[F] == g_).astype(float)
+        inX = P.group[X] == g_
+        rows.append(inF)
+        hs.append(bnd - wX[inX].sum())
+    if cap_on:
+        rows.append(sgn[F])
+        hs.append(P.tau + float(sgn[F] @ P.w0[F]) -
+                  float(np.abs(wX - P.w0[X]).sum()))
+    C = np.vstack(rows)
+    h = np.asarray(hs)
+    # gamma Sigma_FX w_X = gamma B_F F (B_X^T w_X)   (d is diagonal)
+    cross = P.gamma * (P.B[F] @ (P.f * (P.B[X].T @ wX))) if len(X) else 0.0
+    rhs = P.mu[F] - slope[F] - cross
+    eta0 = [-nu0]
+    for g_, _ in act:
+        eta0.append(0.0 if lam_band0 is None else lam_band0[g_])
+    if cap_on:
+        eta0.append(lam_cap0)
+    wF, eta = _solve_reduced(P, F, rhs, C, h, np.asarray(eta0, float))
+    wf = val.copy()
+    wf[F] = wF
+    nu = -eta[0]
+    lam_band = np.zeros(G)
+    for j, (g_, _) in enumerate(act):
+        lam_band[g_] = eta[1 + j]
+    lam_cap = float(eta[-1]) if cap_on else 0.0
+    return wf, (nu, lam_band, lam_cap)
+
+
+def crossover(P: AccountProblem, w, nu, lam_band, lam_cap,
+              tols=(1e-9, 1e-8, 1e-10, 1e-7, 1e-11, 1e-6)):
+    """Best of several snap tolerances; falls back to the input point."""
+    best = dict(w=np.asarray(w, float), nu=nu, lam_band=lam_band,
+                lam_cap=lam_cap, res=residuals(P, w, nu, lam_band, lam_cap),
+                method="ipm")
+    best_score = max(best["res"]["r_prim"], best["res"]["r_dual"],
+                     best["res"]["r_comp"])
+    for tol in tols:
+        try:
+            wf, mult = crossover_once(P, w, tol, max(tol, 1e-9), nu,
+                                      lam_band, lam_cap)
+        except (np.linalg.LinAlgError, ValueError):
+            continue
+        if mult is None:
+            continue
+        r = residuals(P, wf, *mult)
+        score = max(r["r_prim"], r["r_dual"], r["r_comp"])
+        if score < best_score:
+            best = dict(w=wf, nu=mult[0], lam_band=mult[1], lam_cap=mult[2],
+                        res=r, method="crossover")
+            best_score = score
+        if best_score < 1e-13:
+            break
+    return best
