@@ -1,0 +1,171 @@
+/*
+ * fqp.h -- C-ABI of the MI355X batched factor-model rebalancing solver.
+ *
+ * Each account a of a book solves the paper's problem class (Eq. 1, Sec.
+ * "Benchmark Problem Class") in this instantiation:
+ *
+ *   min_w (gamma_a/2) w^T Sigma w - mu_a^T w + sum_i phi_ai(w_i - w0_ai)
+ *   s.t.  1^T w = 1                                  (budget)
+ *         lb_a <= w_i <= ub_a, w_i = 0 if excluded    (box, exclusion mask)
+ *         band_lo_a <= A w <= band_hi_a               (one-hot exposure bands)
+ *         sum_i |w_i - w0_ai| <= tau_a                (turnover cap)
+ *
+ *   Sigma  = B diag(f) B^T + diag(d)   (factor risk model shared by the book)
+ *   phi_ai(D) = kappa_a |D| + T_ai((-D)_+), T_ai the convex piecewise-linear
+ *              tax on the sold amount (four lots, three breakpoints).
+ *
+ * The solver returns weights, a status per account, iteration counts and
+ * the external diagnostics of Sec. "External Diagnostics" recomputed in
+ * float64 (budget/box/exposure/turnover residuals, nonsmooth stationarity,
+ * complementarity) -- the observables of the public evaluation boundary
+ * (Sec. "Public Evaluation Boundary").  Status codes follow the status
+ * vocabulary of Sec. "Status Vocabulary and Objective Agreement".
+ *
+ * Memory: every array pointer in fqp_universe, fqp_book and fqp_result is a
+ * DEVICE pointer on the handle's device, caller-owned, row-major, densely
+ * packed (no strides).  Inputs are never modified.  The handle owns its
+ * workspace (grown on demand, freed by fqp_destroy).
+ *
+ * Errors: call-level problems (null pointers, non-positive sizes, HIP
+ * failures, allocation failure) return a negative fqp_error and leave the
+ * outputs undefined; fqp_last_error() describes the last one.  Problems of
+ * one account (invalid data, provable infeasibility, non-finite values) are
+ * reported in status[a] and never fail the batch.
+ *
+ * Threading: one handle per host thread.  The call is synchronous: it
+ * enqueues on `stream` (a hipStream_t, NULL = default stream), synchronises
+ * it at convergence checks, and returns once every output is written.
+ */
+#ifndef FQP_H
+#define FQP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#if defined(__GNUC__)
+#define FQP_API __attribute__((visibility("default")))
+#else
+#define FQP_API
+#endif
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fqp_handle fqp_handle;
+
+typedef enum {
+  FQP_OK = 0,
+  FQP_ERR_INVALID_ARG = -1,
+  FQP_ERR_ALLOC = -2,
+  FQP_ERR_HIP = -3,
+  FQP_ERR_UNSUPPORTED = -4
+} fqp_error;
+
+/* Per-account status (Sec. "Status Vocabulary and Objective Agreement"). */
+typedef enum {
+  FQP_SOLVED = 0,               /* certified: float64 KKT residuals <= eps */
+  FQP_FEASIBLE_UNCERTIFIED = 1, /* quality gates pass, certificate missing */
+  FQP_MAX_ITER = 2,             /* iteration cap reached, gates fail       */
+  FQP_TIME_LIMIT = 3,           /* declared time limit reached             */
+  FQP_PRIMAL_INFEASIBLE = 4,    /* proven on input: no feasible portfolio  */
+  FQP_INVALID_INPUT = 5,        /* malformed data (lb > ub, bad tax lots)   */
+  FQP_NUMERICAL_ERROR = 6       /* non-finite input or breakdown           */
+} fqp_status;
+
+/* Universe shared by all accounts of a book. */
+typedef struct fqp_universe {
+  int32_t n;             /* assets, >= 1                                   */
+  int32_t k;             /* factors, 1..128                                */
+  int32_t n_groups;      /* exposure groups, 0..64 (0 = no bands)          */
+  const float *B;        /* [n][k] factor loadings                         */
+  const float *f;        /* [k]   factor variances, > 0                    */
+  const float *d;        /* [n]   idiosyncratic variances, > 0             */
+  const int32_t *group;  /* [n]   labels in [0, n_groups); NULL if none    */
+} fqp_universe;
+
+/* Per-account data of Eq. 1 for m accounts. */
+typedef struct fqp_book {
+  int32_t m;                 /* accounts, >= 1                              */
+  const float *mu;           /* [m][n] expected returns                    */
+  const float *w0;           /* [m][n] current weights                     */
+  const float *lb, *ub;      /* [m] box bounds (lb <= 0 <= ub)              */
+  const uint32_t *eligible;  /* [m][ceil(n/32)] bit i%32 of word i/32 set =
+                                asset i eligible; NULL = all eligible       */
+  const float *gamma;        /* [m] risk aversion, > 0                     */
+  const float *kappa;        /* [m] L1 turnover cost, >= 0                 */
+  const float *tau;          /* [m] turnover cap; +INF = no cap            */
+  const float *band_lo;      /* [m][n_groups] or NULL (no bands)           */
+  const float *band_hi;      /* [m][n_groups] or NULL                      */
+  const int32_t *tax_ptr;    /* [m+1] CSR of tax lots; NULL = no tax       */
+  const int32_t *tax_asset;  /* [nnz] asset of each entry, strictly
+                                increasing within an account, w0 > 0 there */
+  const float *tax_brk;      /* [nnz][3] cumulative sale breakpoints,
+                                0 < b1 < b2 < b3                            */
+  const float *tax_slope;    /* [nnz][4] lot slopes, 0 <= s0 <= .. <= s3     */
+} fqp_book;
+
+typedef struct fqp_settings {
+  double eps_prim;       /* absolute primal residual target (1e-6)        */
+  double eps_dual;       /* scaled stationarity target (1e-6)             */
+  double eps_comp;       /* scaled complementarity target (1e-6)          */
+  int32_t max_iter;      /* ADMM iteration cap per account                 */
+  int32_t check_every;   /* iterations between polish / certification     */
+  float rho;             /* ADMM penalty on the asset split (<= 0: auto)  */
+  float rho_band;        /* ADMM penalty on the band split (<= 0: auto)   */
+  float alpha;           /* over-relaxation in (0, 2)                     */
+  float cap_beta;        /* damping of the turnover-cap multiplier update */
+  int32_t polish_rounds; /* active-set refinement rounds per polish       */
+  int32_t use_graph;     /* capture each block of iterations in a hipGraph */
+  int32_t profile;       /* time every fused iteration launch with events */
+  double time_limit_ms;  /* wall-clock limit of the call (<= 0: none)     */
+} fqp_settings;
+
+/* Outputs (device pointers, caller-owned).  Any may be NULL except w and
+ * status. */
+typedef struct fqp_result {
+  double *w;          /* [m][n] weights                                    */
+  int32_t *status;    /* [m] fqp_status                                    */
+  int32_t *iters;     /* [m] ADMM iterations run                           */
+  double *r_prim;     /* [m] max(budget, box, exposure, turnover) residual */
+  double *r_dual;     /* [m] nonsmooth stationarity / gradient scale       */
+  double *r_comp;     /* [m] complementarity / gradient scale              */
+  double *obj;        /* [m] objective recomputed in float64               */
+  double *nu;         /* [m] budget multiplier                             */
+  double *lam_cap;    /* [m] turnover-cap multiplier (>= 0)                */
+  double *lam_band;   /* [m][n_groups] band multipliers (> 0: upper binds) */
+} fqp_result;
+
+/* Host-side counters of the last fqp_solve_batch call. */
+typedef struct fqp_stats {
+  int32_t iterations;       /* ADMM iterations run (max over accounts)      */
+  int32_t iter_launches;    /* fused iteration kernel launches              */
+  int32_t polish_calls;     /* polish / certification kernel launches       */
+  int32_t n_solved;         /* accounts with status SOLVED                  */
+  double iter_kernel_ms;    /* summed event time of fused launches
+                               (settings.profile only, else 0)             */
+  double account_iters;     /* sum over accounts of iterations run          */
+  double total_ms;          /* host wall-clock of the call                  */
+  size_t workspace_bytes;   /* device workspace held by the handle          */
+} fqp_stats;
+
+FQP_API void fqp_default_settings(fqp_settings *s);
+
+FQP_API fqp_error fqp_create(fqp_handle **h, int device);
+
+FQP_API fqp_error fqp_solve_batch(fqp_handle *h, const fqp_universe *U,
+                          const fqp_book *P, const fqp_settings *S,
+                          fqp_result *R, void *stream);
+
+FQP_API fqp_error fqp_get_stats(const fqp_handle *h, fqp_stats *out);
+
+FQP_API const char *fqp_error_string(int e);
+FQP_API const char *fqp_status_string(int s);
+FQP_API const char *fqp_last_error(const fqp_handle *h);
+
+FQP_API void fqp_destroy(fqp_handle *h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FQP_H */

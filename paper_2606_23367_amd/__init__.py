@@ -1,0 +1,14 @@
+"""MI355X-native batched factor-model rebalancing solver.
+
+The solver itself is the HIP library ``libfqp.so`` (kernels for gfx950 and a
+C-ABI declared in ``include/fqp.h``); this package is its thin binding.
+"""
+from ._lib import STATUS_NAMES, SOLVED  # noqa: F401
+
+
+def __getattr__(name):
+    if name in ("Solver", "solve_batch", "to_device", "DeviceProblem",
+                "pack_eligibility"):
+        from . import solver
+        return getattr(solver, name)
+    raise AttributeError(name)

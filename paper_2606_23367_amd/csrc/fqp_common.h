@@ -1,0 +1,83 @@
+// Device-side layout shared by the fqp kernels (gfx950).
+//
+// Book state lives in HBM as account-major float32 arrays [m][n] (an
+// account's row of assets is contiguous), so a wavefront half reading 32
+// consecutive assets of one account issues one 128-byte line.  The factor
+// block B~ = [B | A^T | 1 | 0-pad] is float32 [n][kp] with kp a multiple of
+// 32: B (k columns), one one-hot column per exposure group (bands enter the
+// x-update as extra low-rank directions), one column of ones (its
+// contraction gives 1^T Delta^-1 r for the budget border), zero padding.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fqp {
+
+constexpr int kTM = 32;        // accounts per workgroup tile (MFMA M)
+constexpr int kWaves = 4;      // waves per workgroup
+constexpr int kRowsPerChunk = 32 * kWaves;  // rows per chunk (MFMA N x waves)
+constexpr int kMaxKp = 192;    // padded factor width limit
+constexpr int kMaxK = 128;     // factor limit (polish keeps K_F in LDS)
+constexpr int kMaxG = 64;      // exposure groups limit
+
+// per-account float parameters, [m][kNPar]
+enum AccPar {
+  P_GAMMA = 0, P_RHO, P_KAPPA, P_LAM, P_NU, P_LB, P_UB, P_TAU,
+  P_ALPHA, P_RHOB, P_CLASS, P_HASTAX, kNPar = 12
+};
+
+// per-account integer state
+enum AccState { S_ACTIVE = 0, S_STATUS, S_ITERS, kNState = 4 };
+
+// fused-iteration statistics per (row tile, account), [n_rt][m][kNStat]
+enum Stat { ST_RPRIM = 0, ST_RDUAL, ST_TURN, ST_NFREE, kNStat = 4 };
+
+// held-asset record: w0 and, when taxed, the lot data
+struct HoldRec {
+  float w0;
+  int32_t tax;   // index into tax arrays or -1
+};
+
+// ---------------------------------------------------------------------------
+// separable proximal step of phi_i + lam|. - w0| + box  (float32)
+//
+// For a convex piecewise-linear g with kinks c_1 < ... < c_m and slopes
+// s_0 < ... < s_m, argmin_z g(z) + (rho/2)(z - v)^2 is
+//   min(v - s_0/rho, max(c_1, min(v - s_1/rho, max(c_2, ... max(c_m,
+//       v - s_m/rho)))))
+// and adding the box [lb, ub] clips the result (1-D convexity).
+// ---------------------------------------------------------------------------
+struct TaxLots {
+  float b1, b2, b3;        // cumulative sale breakpoints
+  float s0, s1, s2, s3;    // lot slopes (non-decreasing)
+};
+
+__device__ __forceinline__ float prox_plain(float v, float w0, float th,
+                                            float lb, float ub) {
+  // kink at w0 with slopes -th*rho, +th*rho (th = (kappa+lam)/rho)
+  float z = fminf(v + th, fmaxf(w0, v - th));
+  return fminf(fmaxf(z, lb), ub);
+}
+
+__device__ __forceinline__ float prox_taxed(float v, float w0, float th,
+                                            float irho, const TaxLots& t,
+                                            float lb, float ub) {
+  // kinks w0-b3 < w0-b2 < w0-b1 < w0; slopes (times 1/rho):
+  //   -(th + s3/rho), -(th + s2/rho), -(th + s1/rho), -(th + s0/rho), +th
+  float acc = v - th;
+  acc = fmaxf(w0, acc);
+  acc = fminf(v + th + t.s0 * irho, acc);
+  acc = fmaxf(w0 - t.b1, acc);
+  acc = fminf(v + th + t.s1 * irho, acc);
+  acc = fmaxf(w0 - t.b2, acc);
+  acc = fminf(v + th + t.s2 * irho, acc);
+  acc = fmaxf(w0 - t.b3, acc);
+  acc = fminf(v + th + t.s3 * irho, acc);
+  return fminf(fmaxf(acc, lb), ub);
+}
+
+__device__ __forceinline__ int popc_below(uint32_t word, int bit) {
+  return __popc(word & ((1u << bit) - 1u));
+}
+
+}  // namespace fqp

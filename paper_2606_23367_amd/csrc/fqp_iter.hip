@@ -1,0 +1,591 @@
+// ADMM iteration kernels for the batched factor-model QP (gfx950).
+//
+// Splitting (project's choice; the paper's engine is closed, Sec. "Claim
+// Boundary"): x carries the smooth risk/return part of Eq. 1 plus the budget,
+// z carries every separable term (box, exclusion, L1 turnover, piecewise-
+// linear tax) and the turnover cap, and y = A x carries the exposure bands:
+//
+//   x-step   (gamma Sigma + rho I + rho_b A^T A) x = mu + rho(z - u)
+//            + rho_b A^T (y - v) + nu 1,   1^T x = 1
+//   relax    xh = alpha x + (1 - alpha) z
+//   z-step   z = prox_{psi/rho}(xh + u)  with the cap multiplier lam
+//   duals    u += xh - z;   band block: OSQP-style relaxation on A x
+//
+// Sigma = B diag(f) B^T + diag(d) and the one-hot A^T A are both low rank,
+// so with B~ = [B | A^T] and Delta = gamma d + rho the x-step is a Woodbury
+// solve in the (k+G)-dimensional factor space:
+//
+//   t = B~^T Delta^-1 r,  s0 = 1^T Delta^-1 r,
+//   nu = (1 - s0 + q^T t) / sigma1,  p = K^-1 (t + nu c),
+//   x = Delta^-1 (r + nu 1 - B~ p),
+//   K = F~^-1 + B~^T Delta^-1 B~,  c = B~^T Delta^-1 1,  q = K^-1 c,
+//   sigma1 = 1^T Delta^-1 1 - c^T q.
+//
+// One fused kernel per iteration streams the book once: back-projection
+// B~ p (MFMA), x, relaxation, prox, dual update, and the contraction
+// B~^T Delta^-1 r of the NEXT iteration (MFMA), with per-account partials.
+// A small per-account kernel then reduces the partials and solves in factor
+// space.  The cap multiplier is updated between passes by a damped Newton
+// step on the turnover of the current z (the prox uses the previous value).
+#include "fqp_common.h"
+#include "fqp_kernels.h"
+
+namespace fqp {
+
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+
+// ---------------------------------------------------------------------------
+// universe packing:  B~ = [B | onehot(group) | 1 | 0]
+// ---------------------------------------------------------------------------
+__global__ void build_bt_kernel(int n, int k, int G, int kp, const float* B,
+                                const int32_t* group, float* Bt) {
+  size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  size_t total = (size_t)n * kp;
+  if (e >= total) return;
+  int i = (int)(e / kp), j = (int)(e % kp);
+  float v = 0.f;
+  if (j < k) v = B[(size_t)i * k + j];
+  else if (j < k + G) v = (group[i] == j - k) ? 1.f : 0.f;
+  else if (j == k + G) v = 1.f;
+  Bt[e] = v;
+}
+
+// partial Gram  sum_i B~_ij B~_il / Delta_i  over a chunk of rows, for
+// j, l <= kg (kg = k + G; index kg is the ones column), float64.  Grid:
+// x = row chunk, y = tile of 8192 matrix entries (32 per thread).
+__global__ __launch_bounds__(256) void gram_partial_kernel(
+    int n, int kp, int kg, int rows_per_blk, const float* Bt, const float* d,
+    double gamma, double rho, double* part) {
+  extern __shared__ float sB[];               // [64][kp]
+  const int nk = kg + 1;
+  const int ne = nk * nk;
+  const int e0 = blockIdx.y * 8192;
+  const int r_begin = blockIdx.x * rows_per_blk;
+  const int r_end = min(n, r_begin + rows_per_blk);
+  double acc[32];
+  int jj[32], ll[32];
+#pragma unroll
+  for (int c = 0; c < 32; ++c) {
+    acc[c] = 0.0;
+    int e = e0 + threadIdx.x + 256 * c;
+    jj[c] = (e < ne) ? e / nk : 0;
+    ll[c] = (e < ne) ? e % nk : 0;
+  }
+  for (int r0 = r_begin; r0 < r_end; r0 += 64) {
+    __syncthreads();
+    int rows = min(64, r_end - r0);
+    for (int e = threadIdx.x; e < rows * kp; e += blockDim.x)
+      sB[e] = Bt[(size_t)r0 * kp + e];
+    __syncthreads();
+    for (int rr = 0; rr < rows; ++rr) {
+      const double idl = 1.0 / (gamma * (double)d[r0 + rr] + rho);
+      const float* row = sB + rr * kp;
+#pragma unroll
+      for (int c = 0; c < 32; ++c)
+        acc[c] += (double)row[jj[c]] * (double)row[ll[c]] * idl;
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < 32; ++c) {
+    int e = e0 + threadIdx.x + 256 * c;
+    if (e < ne) part[(size_t)blockIdx.x * ne + e] = acc[c];
+  }
+}
+
+// sum the partials, add F~^-1, Cholesky, inverse, border vectors.
+// One workgroup per class.  Everything in float64 in global scratch.
+__global__ void kfactor_kernel(int k, int G, int kp, int nparts,
+                               const double* part, const float* f,
+                               double gamma, double rho_b, double* Kw,
+                               float* Kinv_out, float* c_out, float* q_out,
+                               float* sig_out, float* mbg_out) {
+  const int kg = k + G, nk = kg + 1, ne = nk * nk;
+  double* Gm = Kw;                   // [nk][nk]
+  double* L = Kw + ne;               // [kg][kg] Cholesky factor
+  double* X = L + kg * kg;           // [kg][kg] inverse
+  double* qv = X + kg * kg;          // [kg]
+  for (int e = threadIdx.x; e < ne; e += blockDim.x) {
+    double s = 0.0;
+    for (int p = 0; p < nparts; ++p) s += part[(size_t)p * ne + e];
+    Gm[e] = s;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < kg * kg; e += blockDim.x) {
+    int j = e / kg, l = e % kg;
+    double v = Gm[j * nk + l];
+    if (j == l) v += (j < k) ? 1.0 / (gamma * (double)f[j]) : 1.0 / rho_b;
+    L[e] = v;
+  }
+  __syncthreads();
+  // right-looking Cholesky, lower triangle of L
+  for (int j = 0; j < kg; ++j) {
+    if (threadIdx.x == 0) L[j * kg + j] = sqrt(fmax(L[j * kg + j], 1e-300));
+    __syncthreads();
+    double djj = L[j * kg + j];
+    for (int i = j + 1 + threadIdx.x; i < kg; i += blockDim.x)
+      L[i * kg + j] /= djj;
+    __syncthreads();
+    for (int e = threadIdx.x; e < (kg - j - 1) * (kg - j - 1); e += blockDim.x) {
+      int i = j + 1 + e / (kg - j - 1), l = j + 1 + e % (kg - j - 1);
+      if (l <= i) L[i * kg + l] -= L[i * kg + j] * L[l * kg + j];
+    }
+    __syncthreads();
+  }
+  // inverse: solve L L^T X = I column by column (threads over columns)
+  for (int col = threadIdx.x; col < kg; col += blockDim.x) {
+    for (int i = 0; i < kg; ++i) {         // forward
+      double s = (i == col) ? 1.0 : 0.0;
+      for (int l = 0; l < i; ++l) s -= L[i * kg + l] * X[l * kg + col];
+      X[i * kg + col] = s / L[i * kg + i];
+    }
+    for (int i = kg - 1; i >= 0; --i) {    // backward
+      double s = X[i * kg + col];
+      for (int l = i + 1; l < kg; ++l) s -= L[l * kg + i] * X[l * kg + col];
+      X[i * kg + col] = s / L[i * kg + i];
+    }
+  }
+  __syncthreads();
+  // q = K^-1 c, sigma1 = 1^T Delta^-1 1 - c^T q
+  for (int j = threadIdx.x; j < kg; j += blockDim.x) {
+    double s = 0.0;
+    for (int l = 0; l < kg; ++l) s += X[j * kg + l] * Gm[l * nk + kg];
+    qv[j] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = Gm[kg * nk + kg];
+    for (int l = 0; l < kg; ++l) s -= Gm[l * nk + kg] * qv[l];
+    sig_out[0] = (float)s;
+  }
+  for (int e = threadIdx.x; e < kp * kp; e += blockDim.x) {
+    int j = e / kp, l = e % kp;
+    Kinv_out[e] = (j < kg && l < kg) ? (float)X[j * kg + l] : 0.f;
+  }
+  for (int j = threadIdx.x; j < kp; j += blockDim.x) {
+    c_out[j] = (j < kg) ? (float)Gm[j * nk + kg] : 0.f;
+    q_out[j] = (j < kg) ? (float)qv[j] : 0.f;
+  }
+  for (int e = threadIdx.x; e < kp * G; e += blockDim.x) {
+    int j = e / G, g = e % G;
+    mbg_out[e] = (j < kg) ? (float)Gm[j * nk + (k + g)] : 0.f;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// the fused iteration
+// ---------------------------------------------------------------------------
+template <int NCH, bool INIT>
+__global__ __launch_bounds__(256, 2) void iter_kernel(IterArgs A) {
+  constexpr int kp = NCH * 32;
+  constexpr int BS = kp + 1;            // LDS row stride (odd: no conflicts)
+  extern __shared__ float smem[];
+  float* Bs = smem;                     // [128][BS]
+  float* Ps = Bs + kRowsPerChunk * BS;  // [32][BS]
+  float* Rt = Ps + kTM * BS;            // [4][32][33]
+  float* Par = Rt + kWaves * 32 * 33;   // [32][kNPar]
+  int* Aid = (int*)(Par + kTM * kNPar); // [32]
+
+  const int m_act = *A.m_act;
+  const int slot0 = blockIdx.y * kTM;
+  if (slot0 >= m_act) return;
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+  const int l32 = lane & 31, hi = lane >> 5;
+  const int n = A.n;
+
+  if (tid < kTM) {
+    int s = slot0 + tid;
+    Aid[tid] = (s < m_act) ? A.act[s] : -1;
+  }
+  __syncthreads();
+  for (int e = tid; e < kTM * kNPar; e += 256) {
+    int j = e / kNPar, p = e % kNPar;
+    int a = Aid[j];
+    Par[e] = (a >= 0) ? A.par[(size_t)a * kNPar + p] : 0.f;
+  }
+  if (!INIT) {
+    for (int e = tid; e < kTM * kp; e += 256) {
+      int j = e / kp, c = e % kp;
+      int a = Aid[j];
+      Ps[j * BS + c] = (a >= 0) ? A.pp[(size_t)a * kp + c] : 0.f;
+    }
+  }
+
+  floatx16 T[NCH];
+#pragma unroll
+  for (int c = 0; c < NCH; ++c)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) T[c][r] = 0.f;
+  float st_rp[16], st_rd[16], st_tv[16], st_nf[16];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) st_rp[r] = st_rd[r] = st_tv[r] = st_nf[r] = 0.f;
+
+  float* Rw = Rt + w * 32 * 33;
+  const int row_begin = blockIdx.x * A.rows_per_wg;
+  const int W = A.W;
+
+  for (int ch = 0; ch < A.chunks_per_wg; ++ch) {
+    const int r0 = row_begin + ch * kRowsPerChunk;
+    if (r0 >= n) break;
+    __syncthreads();
+    for (int e = tid; e < kRowsPerChunk * (kp / 4); e += 256) {
+      int rr = e / (kp / 4), c4 = e % (kp / 4);
+      int row = r0 + rr;
+      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (row < n) v = reinterpret_cast<const float4*>(A.Bt + (size_t)row * kp)[c4];
+      float* dst = Bs + rr * BS + 4 * c4;
+      dst[0] = v.x; dst[1] = v.y; dst[2] = v.z; dst[3] = v.w;
+    }
+    __syncthreads();
+
+    const int row = r0 + 32 * w + l32;
+    const bool row_ok = row < n;
+    const float d_i = row_ok ? A.d[row] : 1.f;
+
+    floatx16 X;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) X[r] = 0.f;
+    if (!INIT) {
+      const float* pa = Ps + l32 * BS + hi;
+      const float* pb = Bs + (32 * w + l32) * BS + hi;
+#pragma unroll 8
+      for (int s = 0; s < kp / 2; ++s)
+        X = __builtin_amdgcn_mfma_f32_32x32x2f32(pa[2 * s], pb[2 * s], X, 0, 0, 0);
+    }
+
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int m = 8 * (r >> 2) + 4 * hi + (r & 3);
+      const int a = Aid[m];
+      float Rp = 0.f;
+      if (a >= 0 && row_ok) {
+        const float* pr = Par + m * kNPar;
+        const float rho = pr[P_RHO];
+        const float Delta = pr[P_GAMMA] * d_i + rho;
+        const size_t off = (size_t)a * n + row;
+        const float mu = A.mu[off];
+        if (INIT) {
+          Rp = mu / Delta;
+        } else {
+          const float z = A.z[off], u = A.u[off];
+          const float x = (mu + rho * (z - u) + pr[P_NU] - X[r]) / Delta;
+          const float alpha = pr[P_ALPHA];
+          const float v = alpha * x + (1.f - alpha) * z + u;
+          const int wd = row >> 5;
+          const uint32_t ew = A.elig ? A.elig[(size_t)a * W + wd] : 0xffffffffu;
+          const bool el = (ew >> l32) & 1u;
+          const float lb = el ? pr[P_LB] : 0.f, ub = el ? pr[P_UB] : 0.f;
+          const uint32_t hw = A.hold[(size_t)a * W + wd];
+          float w0 = 0.f;
+          int ti = -1;
+          if ((hw >> l32) & 1u) {
+            int idx = A.hold_ptr[a] + A.hold_pre[(size_t)a * W + wd] + popc_below(hw, l32);
+            w0 = A.hold_w0[idx];
+            ti = A.hold_tax[idx];
+          }
+          const float irho = 1.f / rho;
+          const float th = (pr[P_KAPPA] + pr[P_LAM]) * irho;
+          float zn;
+          bool at_kink;
+          if (ti >= 0) {
+            TaxLots t;
+            t.b1 = A.tax_brk[3 * ti]; t.b2 = A.tax_brk[3 * ti + 1]; t.b3 = A.tax_brk[3 * ti + 2];
+            t.s0 = A.tax_slope[4 * ti]; t.s1 = A.tax_slope[4 * ti + 1];
+            t.s2 = A.tax_slope[4 * ti + 2]; t.s3 = A.tax_slope[4 * ti + 3];
+            zn = prox_taxed(v, w0, th, irho, t, lb, ub);
+            at_kink = (zn == w0) || (zn == w0 - t.b1) || (zn == w0 - t.b2) || (zn == w0 - t.b3);
+          } else {
+            zn = prox_plain(v, w0, th, lb, ub);
+            at_kink = (zn == w0);
+          }
+          const float un = v - zn;
+          A.z[off] = zn;
+          A.u[off] = un;
+          Rp = (mu + rho * (zn - un)) / Delta;
+          st_rp[r] = fmaxf(st_rp[r], fabsf(x - zn));
+          st_rd[r] = fmaxf(st_rd[r], fabsf(zn - z));
+          st_tv[r] += fabsf(zn - w0);
+          st_nf[r] += (el && zn > lb && zn < ub && !at_kink) ? 1.f : 0.f;
+        }
+      }
+      Rw[m * 33 + l32] = Rp;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    {
+      const float* ra = Rw + l32 * 33 + hi;
+      const float* rb = Bs + (32 * w + hi) * BS + l32;
+#pragma unroll 4
+      for (int s = 0; s < 16; ++s) {
+        const float av = ra[2 * s];
+#pragma unroll
+        for (int c = 0; c < NCH; ++c)
+          T[c] = __builtin_amdgcn_mfma_f32_32x32x2f32(av, rb[(2 * s) * BS + 32 * c], T[c], 0, 0, 0);
+      }
+    }
+    __builtin_amdgcn_wave_barrier();
+  }
+
+  // ---- statistics: reduce over the 32 rows held by each half-wave --------
+  if (!INIT) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+#pragma unroll
+      for (int o = 16; o >= 1; o >>= 1) {
+        st_rp[r] = fmaxf(st_rp[r], __shfl_xor(st_rp[r], o, 32));
+        st_rd[r] = fmaxf(st_rd[r], __shfl_xor(st_rd[r], o, 32));
+        st_tv[r] += __shfl_xor(st_tv[r], o, 32);
+        st_nf[r] += __shfl_xor(st_nf[r], o, 32);
+      }
+    }
+  }
+  __syncthreads();                       // all waves done with Bs / Rt
+  float* red = Bs;                       // [4][32][kp]
+  float* sred = Rt;                      // [4][32][4]
+#pragma unroll
+  for (int c = 0; c < NCH; ++c)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int m = 8 * (r >> 2) + 4 * hi + (r & 3);
+      red[(w * kTM + m) * kp + 32 * c + l32] = T[c][r];
+    }
+  if (l32 == 0) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int m = 8 * (r >> 2) + 4 * hi + (r & 3);
+      float* s = sred + (w * kTM + m) * kNStat;
+      s[ST_RPRIM] = st_rp[r]; s[ST_RDUAL] = st_rd[r];
+      s[ST_TURN] = st_tv[r]; s[ST_NFREE] = st_nf[r];
+    }
+  }
+  __syncthreads();
+  const size_t M = A.m_total;
+  for (int e = tid; e < kTM * kp; e += 256) {
+    const int m = e / kp, c = e % kp;
+    const int a = Aid[m];
+    if (a < 0) continue;
+    float s = red[(0 * kTM + m) * kp + c] + red[(1 * kTM + m) * kp + c] +
+              red[(2 * kTM + m) * kp + c] + red[(3 * kTM + m) * kp + c];
+    A.part[((size_t)blockIdx.x * M + a) * kp + c] = s;
+  }
+  if (tid < kTM * kNStat) {
+    const int m = tid / kNStat, q = tid % kNStat;
+    const int a = Aid[m];
+    if (a >= 0) {
+      float v;
+      if (INIT) {
+        v = (q == ST_NFREE) ? -1.f : 0.f;
+      } else if (q == ST_RPRIM || q == ST_RDUAL) {
+        v = fmaxf(fmaxf(sred[(0 * kTM + m) * kNStat + q], sred[(1 * kTM + m) * kNStat + q]),
+                  fmaxf(sred[(2 * kTM + m) * kNStat + q], sred[(3 * kTM + m) * kNStat + q]));
+      } else {
+        v = sred[(0 * kTM + m) * kNStat + q] + sred[(1 * kTM + m) * kNStat + q] +
+            sred[(2 * kTM + m) * kNStat + q] + sred[(3 * kTM + m) * kNStat + q];
+      }
+      A.stat[((size_t)blockIdx.x * M + a) * kNStat + q] = v;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// per-account factor-space solve
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void ksolve_kernel(KArgs A) {
+  __shared__ double t[kMaxKp], rhs[kMaxKp], red[256];
+  __shared__ float pprime[kMaxKp];
+  __shared__ double s_nu;
+  __shared__ float sst[kNStat];
+  const int slot = blockIdx.x;
+  if (slot >= *A.m_act) return;
+  const int a = A.act[slot];
+  const int tid = threadIdx.x;
+  const int kp = A.kp, k = A.k, G = A.G, kg = k + G;
+  const size_t M = A.m_total;
+  float* par = A.par + (size_t)a * kNPar;
+  const int cls = (int)par[P_CLASS];
+  const float* Kinv = A.Kinv + (size_t)cls * kp * kp;
+  const float* cv = A.cvec + (size_t)cls * kp;
+  const float* qv = A.qvec + (size_t)cls * kp;
+  const float sig1 = A.sig1[cls];
+  const float rhob = par[P_RHOB];
+
+  for (int j = tid; j < kp; j += 256) {
+    float s = 0.f;
+    for (int rt = 0; rt < A.n_rt; ++rt) s += A.part[((size_t)rt * M + a) * kp + j];
+    t[j] = s;
+  }
+  if (tid < kNStat) {
+    float v = (tid == ST_RPRIM || tid == ST_RDUAL) ? 0.f : 0.f;
+    for (int rt = 0; rt < A.n_rt; ++rt) {
+      float x = A.stat[((size_t)rt * M + a) * kNStat + tid];
+      v = (tid == ST_RPRIM || tid == ST_RDUAL) ? fmaxf(v, x) : v + x;
+    }
+    sst[tid] = v;
+  }
+  __syncthreads();
+  // band terms: t += (K - F~^-1)[:, G] rho_b (zb - vb);  s0 += c_G . same
+  double s0 = t[kg];
+  if (G > 0) {
+    const float* mbg = A.mbg + (size_t)cls * kp * G;
+    const float* zb = A.zb + (size_t)a * G;
+    const float* vb = A.vb + (size_t)a * G;
+    for (int j = tid; j < kg; j += 256) {
+      double s = 0.0;
+      for (int g = 0; g < G; ++g) s += (double)mbg[j * G + g] * rhob * ((double)zb[g] - vb[g]);
+      rhs[j] = s;
+    }
+    __syncthreads();
+    double cs = 0.0;
+    for (int g = 0; g < G; ++g) cs += (double)cv[k + g] * rhob * ((double)zb[g] - vb[g]);
+    s0 += cs;
+    for (int j = tid; j < kg; j += 256) t[j] += rhs[j];
+    __syncthreads();
+  }
+  // nu = (1 - s0 + q^T t) / sigma1
+  double part = 0.0;
+  for (int j = tid; j < kg; j += 256) part += (double)qv[j] * t[j];
+  red[tid] = part;
+  __syncthreads();
+  for (int o = 128; o >= 1; o >>= 1) {
+    if (tid < o) red[tid] += red[tid + o];
+    __syncthreads();
+  }
+  if (tid == 0) s_nu = (1.0 - s0 + red[0]) / (double)sig1;
+  __syncthreads();
+  const double nu = s_nu;
+  for (int j = tid; j < kg; j += 256) rhs[j] = t[j] + nu * (double)cv[j];
+  __syncthreads();
+  for (int j = tid; j < kp; j += 256) {
+    double s = 0.0;
+    if (j < kg)
+      for (int l = 0; l < kg; ++l) s += (double)Kinv[j * kp + l] * rhs[l];
+    pprime[j] = (float)s;
+  }
+  __syncthreads();
+  // back-projection coefficients: band directions carry -rho_b (zb - vb)
+  float* pp = A.pp + (size_t)a * kp;
+  for (int j = tid; j < kp; j += 256) {
+    float v = 0.f;
+    if (j < k) v = pprime[j];
+    else if (j < kg) v = pprime[j] - rhob * (A.zb[(size_t)a * G + (j - k)] - A.vb[(size_t)a * G + (j - k)]);
+    pp[j] = v;
+  }
+  __syncthreads();
+  // band ADMM block:  A x = p'_G / rho_b
+  float band_res = 0.f;
+  if (G > 0 && tid < G) {
+    const int g = tid;
+    const float alpha = par[P_ALPHA];
+    float* zb = A.zb + (size_t)a * G;
+    float* vb = A.vb + (size_t)a * G;
+    const float ax = pprime[k + g] / rhob;
+    const float zh = alpha * ax + (1.f - alpha) * zb[g];
+    float zn = zh + vb[g];
+    zn = fminf(fmaxf(zn, A.blo[(size_t)a * G + g]), A.bhi[(size_t)a * G + g]);
+    vb[g] = vb[g] + zh - zn;
+    band_res = fabsf(ax - zn);
+    zb[g] = zn;
+  }
+  red[tid] = band_res;
+  __syncthreads();
+  for (int o = 128; o >= 1; o >>= 1) {
+    if (tid < o) red[tid] = fmax(red[tid], red[tid + o]);
+    __syncthreads();
+  }
+  if (tid == 0) {
+    par[P_NU] = (float)nu;
+    const float tau = par[P_TAU];
+    const float nfree = sst[ST_NFREE];
+    if (nfree >= 0.f && isfinite(tau)) {
+      float lam = par[P_LAM];
+      const float rho = par[P_RHO];
+      lam += A.cap_beta * rho * (sst[ST_TURN] - tau) / fmaxf(nfree, 1.f);
+      par[P_LAM] = fmaxf(lam, 0.f);
+    }
+    if (nfree >= 0.f) {
+      A.res[(size_t)a * 4 + 0] = fmaxf(sst[ST_RPRIM], (float)red[0]);
+      A.res[(size_t)a * 4 + 1] = par[P_RHO] * sst[ST_RDUAL];
+      A.res[(size_t)a * 4 + 2] = sst[ST_TURN];
+      A.iters[a] += 1;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+template <int NCH>
+static size_t iter_smem() {
+  constexpr int kp = NCH * 32, BS = kp + 1;
+  return sizeof(float) * ((size_t)kRowsPerChunk * BS + kTM * BS + kWaves * 32 * 33 +
+                          kTM * kNPar) + sizeof(int) * kTM;
+}
+
+template <int NCH>
+static hipError_t launch_iter_t(const IterArgs& A, bool init, dim3 grid, hipStream_t st) {
+  size_t smem = iter_smem<NCH>();
+  if (init) {
+    hipLaunchKernelGGL((iter_kernel<NCH, true>), grid, dim3(256), smem, st, A);
+  } else {
+    hipLaunchKernelGGL((iter_kernel<NCH, false>), grid, dim3(256), smem, st, A);
+  }
+  return hipGetLastError();
+}
+
+hipError_t configure_iter_kernels() {
+  hipError_t e = hipSuccess;
+#define FQP_CFG(N)                                                                     \
+  e = hipFuncSetAttribute((const void*)iter_kernel<N, true>,                           \
+                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)iter_smem<N>()); \
+  if (e != hipSuccess) return e;                                                       \
+  e = hipFuncSetAttribute((const void*)iter_kernel<N, false>,                          \
+                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)iter_smem<N>()); \
+  if (e != hipSuccess) return e;
+  FQP_CFG(1) FQP_CFG(2) FQP_CFG(3) FQP_CFG(4) FQP_CFG(5) FQP_CFG(6)
+#undef FQP_CFG
+  return e;
+}
+
+hipError_t launch_iter(const IterArgs& A, int kp, bool init, dim3 grid, hipStream_t st) {
+  switch (kp / 32) {
+    case 1: return launch_iter_t<1>(A, init, grid, st);
+    case 2: return launch_iter_t<2>(A, init, grid, st);
+    case 3: return launch_iter_t<3>(A, init, grid, st);
+    case 4: return launch_iter_t<4>(A, init, grid, st);
+    case 5: return launch_iter_t<5>(A, init, grid, st);
+    case 6: return launch_iter_t<6>(A, init, grid, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_ksolve(const KArgs& A, int m_total, hipStream_t st) {
+  hipLaunchKernelGGL(ksolve_kernel, dim3(m_total), dim3(256), 0, st, A);
+  return hipGetLastError();
+}
+
+hipError_t launch_build_bt(int n, int k, int G, int kp, const float* B, const int32_t* group,
+                           float* Bt, hipStream_t st) {
+  size_t total = (size_t)n * kp;
+  hipLaunchKernelGGL(build_bt_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st,
+                     n, k, G, kp, B, group, Bt);
+  return hipGetLastError();
+}
+
+hipError_t launch_gram(int n, int kp, int kg, int nparts, int rows_per_blk, const float* Bt,
+                       const float* d, double gamma, double rho, double* part, hipStream_t st) {
+  const int ne = (kg + 1) * (kg + 1);
+  hipLaunchKernelGGL(gram_partial_kernel, dim3(nparts, (ne + 8191) / 8192), dim3(256),
+                     64 * kp * sizeof(float), st, n, kp, kg, rows_per_blk, Bt, d, gamma, rho,
+                     part);
+  return hipGetLastError();
+}
+
+hipError_t launch_kfactor(int k, int G, int kp, int nparts, const double* part, const float* f,
+                          double gamma, double rho_b, double* Kw, float* Kinv, float* c,
+                          float* q, float* sig, float* mbg, hipStream_t st) {
+  hipLaunchKernelGGL(kfactor_kernel, dim3(1), dim3(256), 0, st, k, G, kp, nparts, part, f,
+                     gamma, rho_b, Kw, Kinv, c, q, sig, mbg);
+  return hipGetLastError();
+}
+
+}  // namespace fqp

@@ -1,0 +1,134 @@
+// Kernel argument blocks and launchers (internal to libfqp).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fqp {
+
+struct IterArgs {
+  int n, W;                  // assets, bitmask words per account
+  int rows_per_wg, chunks_per_wg;
+  int m_total;               // accounts in the book (partials are indexed by id)
+  const int* m_act;          // device: number of active accounts
+  const int* act;            // device: active account ids [m_act]
+  const float* Bt;           // [n][kp]
+  const float* d;            // [n]
+  const float* mu;           // [m][n]
+  float* z;                  // [m][n]
+  float* u;                  // [m][n]
+  const uint32_t* elig;      // [m][W] or null
+  const uint32_t* hold;      // [m][W]
+  const int32_t* hold_pre;   // [m][W]
+  const int32_t* hold_ptr;   // [m+1]
+  const float* hold_w0;      // [nnz_h]
+  const int32_t* hold_tax;   // [nnz_h]
+  const float* tax_brk;      // [nnz_t][3]
+  const float* tax_slope;    // [nnz_t][4]
+  const float* pp;           // [m][kp]
+  const float* par;          // [m][kNPar]
+  float* part;               // [n_rt][m][kp]
+  float* stat;               // [n_rt][m][kNStat]
+};
+
+struct KArgs {
+  int kp, k, G, n_rt, m_total;
+  const int* m_act;
+  const int* act;
+  const float* part;
+  const float* stat;
+  float* par;                // [m][kNPar]
+  float* pp;                 // [m][kp]
+  const float* Kinv;         // [ncls][kp][kp]
+  const float* cvec;         // [ncls][kp]
+  const float* qvec;         // [ncls][kp]
+  const float* sig1;         // [ncls]
+  const float* mbg;          // [ncls][kp][G]
+  float* zb;                 // [m][G]
+  float* vb;                 // [m][G]
+  const float* blo;          // [m][G]
+  const float* bhi;          // [m][G]
+  float cap_beta;
+  float* res;                // [m][4]  ADMM residual estimates
+  int* iters;                // [m]
+};
+
+hipError_t configure_iter_kernels();
+hipError_t launch_iter(const IterArgs& A, int kp, bool init, dim3 grid, hipStream_t st);
+hipError_t launch_ksolve(const KArgs& A, int m_total, hipStream_t st);
+hipError_t launch_build_bt(int n, int k, int G, int kp, const float* B, const int32_t* group,
+                           float* Bt, hipStream_t st);
+hipError_t launch_gram(int n, int kp, int kg, int nparts, int rows_per_blk, const float* Bt,
+                       const float* d, double gamma, double rho, double* part, hipStream_t st);
+hipError_t launch_kfactor(int k, int G, int kp, int nparts, const double* part, const float* f,
+                          double gamma, double rho_b, double* Kw, float* Kinv, float* c,
+                          float* q, float* sig, float* mbg, hipStream_t st);
+
+// ---- packing / validation -------------------------------------------------
+struct PackArgs {
+  int n, W, m, G;
+  const float* mu;
+  const float* w0;
+  const float* lb;
+  const float* ub;
+  const uint32_t* elig;
+  const float* gamma;
+  const float* kappa;
+  const float* tau;
+  const float* blo;
+  const float* bhi;
+  const int32_t* tax_ptr;
+  const int32_t* tax_asset;
+  const float* tax_brk;
+  const float* tax_slope;
+  // outputs
+  uint32_t* hold;
+  int32_t* hold_pre;
+  int32_t* hold_cnt;        // [m]
+  int32_t* hold_ptr;        // [m+1]
+  float* hold_w0;
+  int32_t* hold_tax;
+  int32_t* status;          // [m]
+  float* par;               // [m][kNPar]
+};
+hipError_t launch_pack_count(const PackArgs& A, hipStream_t st);
+hipError_t launch_pack_scan(const PackArgs& A, hipStream_t st);
+hipError_t launch_pack_fill(const PackArgs& A, hipStream_t st);
+
+// ---- polish / certification (float64) -------------------------------------
+struct PolishArgs {
+  int n, k, G, kp, W, m_total;
+  const int* m_act;
+  const int* act;
+  const float* Bt;           // [n][kp] (first k columns = B)
+  const float* f;            // [k]
+  const float* d;            // [n]
+  const int32_t* group;      // [n] or null
+  const float* mu;           // [m][n]
+  const float* z;            // [m][n]  ADMM iterate
+  const uint32_t* elig;
+  const uint32_t* hold;
+  const int32_t* hold_pre;
+  const int32_t* hold_ptr;
+  const float* hold_w0;
+  const int32_t* hold_tax;
+  const float* tax_brk;
+  const float* tax_slope;
+  const float* par;          // [m][kNPar]
+  const float* zb;           // [m][G] ADMM band state
+  const float* vb;           // [m][G] ADMM band scaled duals
+  const float* blo;
+  const float* bhi;
+  int8_t* code;              // [m][n] active-set codes
+  int32_t* flist;            // [m][n] free list
+  double* wk;                // [m][wk_stride] per-account scratch
+  size_t wk_stride;
+  double* wout;              // [m][n] polished weights (caller output)
+  double* mult;              // [m][2 + G] nu, lam_cap, lam_band
+  int32_t* pstate;           // [m][8] polish bookkeeping
+  double eps_prim, eps_dual, eps_comp;
+  int first_round;           // classify from z when nonzero
+};
+hipError_t launch_polish_solve(const PolishArgs& A, hipStream_t st);
+size_t polish_wk_stride(int k, int G);
+
+}  // namespace fqp

@@ -1,0 +1,811 @@
+// Float64 polish and certification on the GPU (gfx950).
+//
+// At the optimum of the build's Eq. 1 instance every eligible coordinate
+// either sits at a bound or at a kink of its piecewise-linear trade cost
+// ("fixed") or inside one linear piece ("free", known slope).  Given that
+// pattern and which bands / cap bind, the optimum solves one equality-
+// constrained QP in float64:
+//
+//   gamma Sigma_FF w_F + C_F^T eta = mu_F - slope_F - gamma Sigma_FX w_X
+//   C_F w_F = h      (budget, binding bands, binding cap)
+//
+// H = gamma Sigma_FF = gamma (B_F diag(f) B_F^T + D_F) is inverted through
+// the factor space: H^-1 = (D^-1 - D^-1 B_F Kf^-1 B_F^T D^-1)/gamma with
+// Kf = diag(f)^-1 + B_F^T D_F^-1 B_F (k x k, Cholesky in LDS), and the
+// multipliers eta come from the Schur complement S = C H^-1 C^T.  When the
+// free set does not pin every multiplier (S singular) the ADMM estimates are
+// corrected by the minimum-norm step, as the fixed coordinates then decide.
+//
+// The certification kernel recomputes the external diagnostics of Sec.
+// "External Diagnostics" in float64 (budget, box, exposure and turnover
+// residuals; nonsmooth stationarity against the subdifferential of the
+// trade cost and the normal cone of the box; complementarity of bands and
+// cap).  A pattern that fails is refined primal-dual active-set style:
+// free coordinates that left their piece are fixed at the crossed point,
+// fixed coordinates whose stationarity is violated move into the adjacent
+// piece, and bands / cap are switched on when violated or off when their
+// multiplier has the wrong sign.
+#include "fqp_common.h"
+#include "fqp_kernels.h"
+#include "../../include/fqp.h"
+
+namespace fqp {
+
+enum PState {
+  PS_CAP = 0, PS_NF, PS_NX, PS_NC, PS_DONE, PS_ROUNDS,
+  PS_BACT0, PS_BACT1, PS_BUP0, PS_BUP1, PS_FAILS, kNPState = 12
+};
+
+constexpr double kSnap = 1e-10;
+
+struct Geom {
+  int np;            // points on the asset's line: bounds and inner kinks
+  double pt[6];
+  float ptf[6];      // the same points as the float32 prox evaluates them
+  int nk;            // kinks of the trade cost (w0 last when present)
+  double kink[4];
+  double ks[5];      // slope of the trade cost on each side of the kinks
+  double w0;
+};
+
+__device__ void make_geom(Geom& g, bool el, float lbf, float ubf, float w0f, float kap,
+                          bool phi, int ti, const float* brk, const float* slp) {
+  const double lb = el ? (double)lbf : 0.0, ub = el ? (double)ubf : 0.0;
+  g.w0 = w0f;
+  g.nk = 0;
+  float kf[4];
+  if (phi) {
+    if (ti >= 0) {
+      const float b1 = brk[3 * ti], b2 = brk[3 * ti + 1], b3 = brk[3 * ti + 2];
+      const float s0 = slp[4 * ti], s1 = slp[4 * ti + 1], s2 = slp[4 * ti + 2],
+                  s3 = slp[4 * ti + 3];
+      g.nk = 4;
+      g.kink[0] = (double)w0f - b3; kf[0] = w0f - b3;
+      g.kink[1] = (double)w0f - b2; kf[1] = w0f - b2;
+      g.kink[2] = (double)w0f - b1; kf[2] = w0f - b1;
+      g.kink[3] = w0f;              kf[3] = w0f;
+      g.ks[0] = -((double)kap + s3);
+      g.ks[1] = -((double)kap + s2);
+      g.ks[2] = -((double)kap + s1);
+      g.ks[3] = -((double)kap + s0);
+      g.ks[4] = kap;
+    } else {
+      g.nk = 1;
+      g.kink[0] = w0f; kf[0] = w0f;
+      g.ks[0] = -(double)kap;
+      g.ks[1] = kap;
+    }
+  } else {
+    g.ks[0] = 0.0;
+  }
+  g.np = 0;
+  g.pt[g.np] = lb; g.ptf[g.np] = el ? lbf : 0.f; ++g.np;
+  for (int j = 0; j < g.nk; ++j)
+    if (g.kink[j] > lb && g.kink[j] < ub) { g.pt[g.np] = g.kink[j]; g.ptf[g.np] = kf[j]; ++g.np; }
+  if (ub > lb) { g.pt[g.np] = ub; g.ptf[g.np] = el ? ubf : 0.f; ++g.np; }
+}
+
+// slope of the trade cost (without cap) on the piece between points q, q+1
+__device__ __forceinline__ void piece_slope(const Geom& g, int q, double& slope, double& sgn) {
+  const double mid = 0.5 * (g.pt[q] + g.pt[q + 1]);
+  int s = 0;
+  while (s < g.nk && g.kink[s] < mid) ++s;
+  slope = g.ks[s];
+  sgn = (mid > g.w0) ? 1.0 : -1.0;
+}
+
+// subdifferential interval of phi + lam |. - w0| + N_box at x (with snap)
+__device__ __forceinline__ void subdiff(const Geom& g, double x, double lam, double lb,
+                                        double ub, double& lo, double& hi, double& snap) {
+  snap = 0.0;
+  int at = -1;
+  for (int j = 0; j < g.nk; ++j)
+    if (fabs(x - g.kink[j]) <= kSnap) { at = j; break; }
+  if (at >= 0) {
+    lo = g.ks[at] + ((at < g.nk) ? -lam : lam);
+    hi = g.ks[at + 1] + ((at + 1 < g.nk) ? -lam : lam);
+    snap = fabs(x - g.kink[at]);
+  } else {
+    int s = 0;
+    while (s < g.nk && g.kink[s] < x) ++s;
+    lo = hi = g.ks[s] + ((s < g.nk) ? -lam : lam);
+  }
+  if (g.nk == 0) lo = hi = 0.0;
+  if (x <= lb + kSnap) { lo = -INFINITY; snap = fmax(snap, fmax(x - lb, 0.0)); }
+  if (x >= ub - kSnap) { hi = INFINITY; snap = fmax(snap, fmax(ub - x, 0.0)); }
+}
+
+struct RowData {
+  bool el;
+  float w0;
+  int ti;
+};
+
+__device__ __forceinline__ RowData row_data(const PolishArgs& A, int a, int i) {
+  RowData r;
+  const int wd = i >> 5, b = i & 31;
+  r.el = A.elig == nullptr || ((A.elig[(size_t)a * A.W + wd] >> b) & 1u);
+  const uint32_t hw = A.hold[(size_t)a * A.W + wd];
+  r.w0 = 0.f;
+  r.ti = -1;
+  if ((hw >> b) & 1u) {
+    const int idx = A.hold_ptr[a] + A.hold_pre[(size_t)a * A.W + wd] + popc_below(hw, b);
+    r.w0 = A.hold_w0[idx];
+    r.ti = A.hold_tax[idx];
+  }
+  return r;
+}
+
+size_t polish_wk_stride(int k, int G) {
+  const size_t ncol = (size_t)G + 3;
+  // Waug, Y (k x ncol), CV (ncol^2), S (ncol^2), yX, Fy, sol (k), h, eta, eta0
+  // (ncol), misc 16
+  return 2 * (size_t)k * ncol + 2 * ncol * ncol + 3 * (size_t)k + 3 * ncol + 16;
+}
+
+struct Wk {
+  double *Waug, *Y, *CV, *S, *yX, *Fy, *sol, *h, *eta, *eta0, *misc;
+};
+__device__ __forceinline__ Wk wk_of(const PolishArgs& A, int a) {
+  Wk w;
+  const int k = A.k;
+  const size_t ncol = (size_t)A.G + 3;
+  double* p = A.wk + (size_t)a * A.wk_stride;
+  w.Waug = p; p += (size_t)k * ncol;
+  w.Y = p; p += (size_t)k * ncol;
+  w.CV = p; p += ncol * ncol;
+  w.S = p; p += ncol * ncol;
+  w.yX = p; p += k;
+  w.Fy = p; p += k;
+  w.sol = p; p += k;
+  w.h = p; p += ncol;
+  w.eta = p; p += ncol;
+  w.eta0 = p; p += ncol;
+  w.misc = p;
+  return w;
+}
+
+__device__ __forceinline__ bool band_active(const int* ps, int g) {
+  return g < 32 ? ((ps[PS_BACT0] >> g) & 1) : ((ps[PS_BACT1] >> (g - 32)) & 1);
+}
+__device__ __forceinline__ bool band_upper(const int* ps, int g) {
+  return g < 32 ? ((ps[PS_BUP0] >> g) & 1) : ((ps[PS_BUP1] >> (g - 32)) & 1);
+}
+__device__ __forceinline__ void set_band(int* ps, int g, bool act, bool up) {
+  const int w = g < 32 ? 0 : 1, b = g & 31;
+  int* pa = ps + PS_BACT0 + w;
+  int* pu = ps + PS_BUP0 + w;
+  *pa = act ? (*pa | (1 << b)) : (*pa & ~(1 << b));
+  *pu = up ? (*pu | (1 << b)) : (*pu & ~(1 << b));
+}
+
+template <typename T>
+__device__ T bsum(T v, T* sh) {
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int o = 128; o >= 1; o >>= 1) {
+    if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+    __syncthreads();
+  }
+  T r = sh[0];
+  __syncthreads();
+  return r;
+}
+template <typename T>
+__device__ T bmax(T v, T* sh) {
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int o = 128; o >= 1; o >>= 1) {
+    if (threadIdx.x < o) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + o]);
+    __syncthreads();
+  }
+  T r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+// exclusive block scan of an int flag; returns the prefix, total in *tot
+__device__ int bscan(int v, int* sh, int* tot) {
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int o = 1; o < 256; o <<= 1) {
+    int t = (threadIdx.x >= o) ? sh[threadIdx.x - o] : 0;
+    __syncthreads();
+    sh[threadIdx.x] += t;
+    __syncthreads();
+  }
+  const int incl = sh[threadIdx.x];
+  *tot = sh[255];
+  __syncthreads();
+  return incl - v;
+}
+
+// ---------------------------------------------------------------------------
+// polish_solve: classify (first round), lists, reduced KKT solve, w
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void polish_solve_kernel(PolishArgs A) {
+  extern __shared__ double smem_d[];
+  const int k = A.k, G = A.G, n = A.n;
+  double* Kf = smem_d;                      // [k][k]
+  double* stg = Kf + k * k;                 // staging: 16 rows x (k + 4)
+  __shared__ double shd[256];
+  __shared__ int shi[256];
+  __shared__ int s_cnt[2];
+  const int slot = blockIdx.x;
+  if (slot >= *A.m_act) return;
+  const int a = A.act[slot];
+  const int tid = threadIdx.x;
+  int* ps = A.pstate + (size_t)a * kNPState;
+  const float* par = A.par + (size_t)a * kNPar;
+  const float lbf = par[P_LB], ubf = par[P_UB], kap = par[P_KAPPA], tauf = par[P_TAU];
+  const double gam = par[P_GAMMA];
+  const bool phi = (kap > 0.f) || isfinite(tauf) || (par[P_HASTAX] != 0.f);
+  Wk wk = wk_of(A, a);
+  int8_t* code = A.code + (size_t)a * n;
+  int32_t* flist = A.flist + (size_t)a * n;         // free rows from the front
+  double* w = A.wout + (size_t)a * n;
+
+  if (A.first_round) {
+    if (tid == 0) {
+      ps[PS_CAP] = isfinite(tauf) && par[P_LAM] > 0.f;
+      ps[PS_DONE] = 0;
+      ps[PS_ROUNDS] = 0;
+      ps[PS_BACT0] = ps[PS_BACT1] = ps[PS_BUP0] = ps[PS_BUP1] = 0;
+      double* mult = A.mult + (size_t)a * (2 + G);
+      mult[0] = par[P_NU];
+      mult[1] = fmax((double)par[P_LAM], 0.0);
+      for (int g = 0; g < G; ++g) {
+        const float zb = A.zb[(size_t)a * G + g];
+        const float lo = A.blo[(size_t)a * G + g], hi = A.bhi[(size_t)a * G + g];
+        if (zb >= hi) set_band(ps, g, true, true);
+        else if (zb <= lo) set_band(ps, g, true, false);
+        mult[2 + g] = (double)par[P_RHOB] * (double)A.vb[(size_t)a * G + g];
+      }
+    }
+    for (int i = tid; i < n; i += 256) {
+      RowData r = row_data(A, a, i);
+      Geom g;
+      make_geom(g, r.el, lbf, ubf, r.w0, kap, phi, r.ti, A.tax_brk, A.tax_slope);
+      const float z = A.z[(size_t)a * n + i];
+      int c = -1;
+      for (int j = 0; j < g.np; ++j)
+        if (z == g.ptf[j]) { c = 2 * j; break; }
+      if (c < 0) {
+        int q = 0;
+        while (q + 2 < g.np && (double)z > g.pt[q + 1]) ++q;
+        c = (g.np == 1) ? 0 : 2 * q + 1;
+        if (g.np > 1 && (double)z <= g.pt[0]) c = 0;
+        if (g.np > 1 && (double)z >= g.pt[g.np - 1]) c = 2 * (g.np - 1);
+      }
+      code[i] = (int8_t)c;
+    }
+    __syncthreads();
+  }
+  if (ps[PS_DONE]) return;
+  const int cap_on = ps[PS_CAP];
+
+  // ---- pass 1: fixed values, free list, nonzero-fixed list --------------
+  // free rows are listed from the front of flist, nonzero fixed rows from
+  // the back.
+  if (tid == 0) { s_cnt[0] = 0; s_cnt[1] = 0; }
+  __syncthreads();
+  for (int base = 0; base < n; base += 256) {
+    const int i = base + tid;
+    int isfree = 0, isnz = 0;
+    if (i < n) {
+      const int c = code[i];
+      if (c & 1) {
+        isfree = 1;
+        w[i] = 0.0;
+      } else {
+        RowData r = row_data(A, a, i);
+        Geom g;
+        make_geom(g, r.el, lbf, ubf, r.w0, kap, phi, r.ti, A.tax_brk, A.tax_slope);
+        const double v = g.pt[c >> 1];
+        w[i] = v;
+        isnz = (v != 0.0);
+      }
+    }
+    int tf, tn;
+    const int pf = bscan(isfree, shi, &tf);
+    const int pn = bscan(isnz, shi, &tn);
+    if (isfree) flist[s_cnt[0] + pf] = i;
+    if (isnz) flist[n - 1 - (s_cnt[1] + pn)] = i;
+    __syncthreads();
+    if (tid == 0) { s_cnt[0] += tf; s_cnt[1] += tn; }
+    __syncthreads();
+  }
+  const int nF = s_cnt[0], nX = s_cnt[1];
+
+  // ---- fixed contributions ----------------------------------------------
+  // yX = B_X^T w_X, budget / band / cap sums of the fixed rows
+  for (int j = tid; j < k; j += 256) {
+    double s = 0.0;
+    for (int t = 0; t < nX; ++t) {
+      const int i = flist[n - 1 - t];
+      s += (double)A.Bt[(size_t)i * A.kp + j] * w[i];
+    }
+    wk.yX[j] = s;
+    wk.Fy[j] = s * (double)A.f[j];            // F yX
+  }
+  // active constraint columns: 0 budget, bands (active order), cap
+  int nb = 0;
+  for (int g = 0; g < G; ++g) nb += band_active(ps, g) ? 1 : 0;
+  const int nc = 1 + nb + (cap_on ? 1 : 0);
+  const int ncol = nc + 1;                      // + rhs column
+  {
+    double sx = 0.0, sturn = 0.0;
+    for (int t = tid; t < nX; t += 256) sx += w[flist[n - 1 - t]];
+    // turnover of fixed rows: every row not free (including zeros)
+    for (int i = tid; i < n; i += 256) {
+      if (code[i] & 1) continue;
+      RowData r = row_data(A, a, i);
+      sturn += fabs(w[i] - (double)r.w0);
+    }
+    sx = bsum<double>(sx, shd);
+    sturn = bsum<double>(sturn, shd);
+    if (tid == 0) {
+      wk.h[0] = 1.0 - sx;
+      int col = 1;
+      for (int g = 0; g < G; ++g) {
+        if (!band_active(ps, g)) continue;
+        double sg = 0.0;
+        for (int t = 0; t < nX; ++t) {
+          const int i = flist[n - 1 - t];
+          if (A.group[i] == g) sg += w[i];
+        }
+        const double bnd = band_upper(ps, g) ? A.bhi[(size_t)a * G + g] : A.blo[(size_t)a * G + g];
+        wk.h[col] = bnd - sg;
+        ++col;
+      }
+      if (cap_on) wk.h[col] = (double)tauf - sturn;   // + sum_F sgn w0 added below
+      ps[PS_NF] = nF;
+      ps[PS_NX] = nX;
+      ps[PS_NC] = nc;
+    }
+  }
+  __syncthreads();
+
+  // ---- Kf = diag(1/f) + sum_F b b^T / d  (lower triangle, LDS) -----------
+  const int ntri = k * (k + 1) / 2;
+  for (int e = tid; e < k * k; e += 256) Kf[e] = 0.0;
+  __syncthreads();
+  const int SR = 16, SS = k + 4;
+  {
+    double acc[33];
+    int ej[33], el_[33];
+#pragma unroll
+    for (int c = 0; c < 33; ++c) {
+      acc[c] = 0.0;
+      const int e = tid + 256 * c;
+      int j = (int)((sqrt(8.0 * e + 1.0) - 1.0) * 0.5);
+      while ((j + 1) * (j + 2) / 2 <= e) ++j;
+      while (j * (j + 1) / 2 > e) --j;
+      ej[c] = (e < ntri) ? j : 0;
+      el_[c] = (e < ntri) ? e - j * (j + 1) / 2 : 0;
+    }
+    for (int f0 = 0; f0 < nF; f0 += SR) {
+      const int rows = min(SR, nF - f0);
+      __syncthreads();
+      for (int e = tid; e < rows * k; e += 256) {
+        const int rr = e / k, j = e % k;
+        const int i = flist[f0 + rr];
+        stg[rr * SS + j] = (double)A.Bt[(size_t)i * A.kp + j];
+      }
+      for (int rr = tid; rr < rows; rr += 256) stg[rr * SS + k] = 1.0 / (double)A.d[flist[f0 + rr]];
+      __syncthreads();
+      for (int rr = 0; rr < rows; ++rr) {
+        const double* b = stg + rr * SS;
+        const double id = b[k];
+#pragma unroll
+        for (int c = 0; c < 33; ++c) acc[c] += b[ej[c]] * b[el_[c]] * id;
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < 33; ++c) {
+      const int e = tid + 256 * c;
+      if (e < ntri) {
+        const int j = ej[c], l = el_[c];
+        double v = acc[c];
+        if (j == l) v += 1.0 / (double)A.f[j];
+        Kf[j * k + l] = v;
+      }
+    }
+  }
+  __syncthreads();
+
+  // ---- Waug = sum_F b V^T / d,  CV = sum_F V V^T / d  ---------------------
+  // V_i = [1, band indicators (active order), sgn_i (cap), rhs_i],
+  // rhs_i = mu_i - slope_i - gamma b_i . F yX
+  double sgn_w0 = 0.0;
+  {
+    const int nW = k * ncol, nCV = ncol * ncol, ne2 = nW + nCV;
+    double acc[48];
+#pragma unroll
+    for (int c = 0; c < 48; ++c) acc[c] = 0.0;
+    double* vst = stg + SR * SS;       // per staged row: ncol values
+    for (int f0 = 0; f0 < nF; f0 += SR) {
+      const int rows = min(SR, nF - f0);
+      __syncthreads();
+      for (int e = tid; e < rows * k; e += 256) {
+        const int rr = e / k, j = e % k;
+        const int i = flist[f0 + rr];
+        stg[rr * SS + j] = (double)A.Bt[(size_t)i * A.kp + j];
+      }
+      __syncthreads();
+      if (tid < rows) {
+        const int rr = tid;
+        const int i = flist[f0 + rr];
+        RowData r = row_data(A, a, i);
+        Geom g;
+        make_geom(g, r.el, lbf, ubf, r.w0, kap, phi, r.ti, A.tax_brk, A.tax_slope);
+        double slope, sgn;
+        piece_slope(g, code[i] >> 1, slope, sgn);
+        double cross = 0.0;
+        for (int j = 0; j < k; ++j) cross += stg[rr * SS + j] * wk.Fy[j];
+        double* v = vst + rr * ncol;
+        v[0] = 1.0;
+        int col = 1;
+        for (int gg = 0; gg < G; ++gg) {
+          if (!band_active(ps, gg)) continue;
+          v[col++] = (A.group[i] == gg) ? 1.0 : 0.0;
+        }
+        if (cap_on) v[col++] = sgn;
+        v[col] = (double)A.mu[(size_t)a * n + i] - slope - gam * cross;
+        stg[rr * SS + k] = 1.0 / (double)A.d[i];
+        sgn_w0 += sgn * (double)r.w0;
+      }
+      __syncthreads();
+      for (int rr = 0; rr < rows; ++rr) {
+        const double* b = stg + rr * SS;
+        const double* v = vst + rr * ncol;
+        const double id = b[k];
+#pragma unroll
+        for (int c = 0; c < 48; ++c) {
+          const int e = tid + 256 * c;
+          if (e < nW) {
+            acc[c] += b[e / ncol] * v[e % ncol] * id;
+          } else if (e < ne2) {
+            const int q = e - nW;
+            acc[c] += v[q / ncol] * v[q % ncol] * id;
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < 48; ++c) {
+      const int e = tid + 256 * c;
+      if (e < nW) wk.Waug[e] = acc[c];
+      else if (e < ne2) wk.CV[e - nW] = acc[c];
+    }
+  }
+  sgn_w0 = bsum<double>(sgn_w0, shd);
+  if (tid == 0 && cap_on) wk.h[nc - 1] += sgn_w0;
+  __syncthreads();
+
+  // ---- Cholesky of Kf (lower, in LDS) -------------------------------------
+  for (int j = 0; j < k; ++j) {
+    if (tid == 0) Kf[j * k + j] = sqrt(fmax(Kf[j * k + j], 1e-300));
+    __syncthreads();
+    const double djj = Kf[j * k + j];
+    for (int i = j + 1 + tid; i < k; i += 256) Kf[i * k + j] /= djj;
+    __syncthreads();
+    const int m = k - j - 1;
+    for (int e = tid; e < m * m; e += 256) {
+      const int i = j + 1 + e / m, l = j + 1 + e % m;
+      if (l <= i) Kf[i * k + l] -= Kf[i * k + j] * Kf[l * k + j];
+    }
+    __syncthreads();
+  }
+  // ---- Y = Kf^-1 Waug (columns in parallel) -------------------------------
+  for (int col = tid; col < ncol; col += 256) {
+    for (int i = 0; i < k; ++i) {
+      double s = wk.Waug[i * ncol + col];
+      for (int l = 0; l < i; ++l) s -= Kf[i * k + l] * wk.Y[l * ncol + col];
+      wk.Y[i * ncol + col] = s / Kf[i * k + i];
+    }
+    for (int i = k - 1; i >= 0; --i) {
+      double s = wk.Y[i * ncol + col];
+      for (int l = i + 1; l < k; ++l) s -= Kf[l * k + i] * wk.Y[l * ncol + col];
+      wk.Y[i * ncol + col] = s / Kf[i * k + i];
+    }
+  }
+  __syncthreads();
+  // ---- Schur system on the constraint columns ------------------------------
+  // gamma * C H^-1 V = CV[C, V] - Waug[:, C]^T Y[:, V]
+  for (int e = tid; e < nc * ncol; e += 256) {
+    const int p = e / ncol, q = e % ncol;
+    double s = wk.CV[p * ncol + q];
+    for (int j = 0; j < k; ++j) s -= wk.Waug[j * ncol + p] * wk.Y[j * ncol + q];
+    wk.S[p * ncol + q] = s / gam;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    // eta0 from the ADMM iterate: -nu, band duals, lam_cap
+    // eta0: multipliers of the previous pattern (first pattern: ADMM's)
+    double* e0 = wk.eta0;
+    const double* m0 = A.mult + (size_t)a * (2 + G);
+    e0[0] = -m0[0];
+    int col = 1;
+    for (int g = 0; g < G; ++g) {
+      if (!band_active(ps, g)) continue;
+      e0[col++] = m0[2 + g];
+    }
+    if (cap_on) e0[col++] = fmax(m0[1], 0.0);
+    // r = C H^-1 rhs - h - S eta0 ;  solve (S + eps I) corr = r  (Cholesky)
+    double* Sm = wk.misc;   // not enough room for big nc: reuse CV (consumed)
+    Sm = wk.CV;
+    double dmax = 0.0;
+    for (int p = 0; p < nc; ++p) dmax = fmax(dmax, fabs(wk.S[p * ncol + p]));
+    const double eps = 1e-13 * fmax(dmax, 1e-300);
+    double* rr = wk.eta;
+    for (int p = 0; p < nc; ++p) {
+      double s = wk.S[p * ncol + nc] - wk.h[p];
+      for (int q = 0; q < nc; ++q) s -= wk.S[p * ncol + q] * e0[q];
+      rr[p] = s;
+      for (int q = 0; q < nc; ++q) Sm[p * nc + q] = wk.S[p * ncol + q] + (p == q ? eps : 0.0);
+    }
+    // Cholesky (lower) of Sm
+    bool ok = true;
+    for (int j = 0; j < nc && ok; ++j) {
+      double s = Sm[j * nc + j];
+      for (int l = 0; l < j; ++l) s -= Sm[j * nc + l] * Sm[j * nc + l];
+      if (!(s > 0.0)) { ok = false; break; }
+      s = sqrt(s);
+      Sm[j * nc + j] = s;
+      for (int i = j + 1; i < nc; ++i) {
+        double t = Sm[i * nc + j];
+        for (int l = 0; l < j; ++l) t -= Sm[i * nc + l] * Sm[j * nc + l];
+        Sm[i * nc + j] = t / s;
+      }
+    }
+    if (ok) {
+      for (int i = 0; i < nc; ++i) {
+        double s = rr[i];
+        for (int l = 0; l < i; ++l) s -= Sm[i * nc + l] * rr[l];
+        rr[i] = s / Sm[i * nc + i];
+      }
+      for (int i = nc - 1; i >= 0; --i) {
+        double s = rr[i];
+        for (int l = i + 1; l < nc; ++l) s -= Sm[l * nc + i] * rr[l];
+        rr[i] = s / Sm[i * nc + i];
+      }
+      for (int p = 0; p < nc; ++p) rr[p] += e0[p];
+    } else {
+      for (int p = 0; p < nc; ++p) rr[p] = e0[p];
+    }
+    // multipliers in the build's convention
+    double* mult = A.mult + (size_t)a * (2 + G);
+    mult[0] = -rr[0];
+    col = 1;
+    for (int g = 0; g < G; ++g) {
+      if (band_active(ps, g)) mult[2 + g] = rr[col++];
+      else mult[2 + g] = 0.0;
+    }
+    mult[1] = cap_on ? rr[col] : 0.0;
+  }
+  __syncthreads();
+  // sol = Y[:, rhs] - Y[:, C] eta
+  for (int j = tid; j < k; j += 256) {
+    double s = wk.Y[j * ncol + nc];
+    for (int p = 0; p < nc; ++p) s -= wk.Y[j * ncol + p] * wk.eta[p];
+    wk.sol[j] = s;
+  }
+  __syncthreads();
+  // ---- free rows: w_i = (rhs_i - C_i^T eta - b_i . sol) / (gamma d_i) ----
+  for (int t = tid; t < nF; t += 256) {
+    const int i = flist[t];
+    RowData r = row_data(A, a, i);
+    Geom g;
+    make_geom(g, r.el, lbf, ubf, r.w0, kap, phi, r.ti, A.tax_brk, A.tax_slope);
+    double slope, sgn;
+    piece_slope(g, code[i] >> 1, slope, sgn);
+    double cross = 0.0, bs = 0.0;
+    for (int j = 0; j < k; ++j) {
+      const double b = (double)A.Bt[(size_t)i * A.kp + j];
+      cross += b * wk.Fy[j];
+      bs += b * wk.sol[j];
+    }
+    const double rhs = (double)A.mu[(size_t)a * n + i] - slope - gam * cross;
+    double ct = wk.eta[0];
+    int col = 1;
+    for (int gg = 0; gg < G; ++gg) {
+      if (!band_active(ps, gg)) continue;
+      if (A.group[i] == gg) ct += wk.eta[col];
+      ++col;
+    }
+    if (cap_on) ct += sgn * wk.eta[col];
+    w[i] = (rhs - ct - bs) / (gam * (double)A.d[i]);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// polish_check: external diagnostics in float64 and refinement
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void polish_check_kernel(PolishArgs A, fqp_result R,
+                                                          int final_pass) {
+  __shared__ double shd[256];
+  __shared__ double s_y[kMaxK];
+  __shared__ double s_gs[kMaxG];
+  const int k = A.k, G = A.G, n = A.n;
+  const int slot = blockIdx.x;
+  if (slot >= *A.m_act) return;
+  const int a = A.act[slot];
+  const int tid = threadIdx.x;
+  int* ps = A.pstate + (size_t)a * kNPState;
+  if (ps[PS_DONE]) return;
+  const float* par = A.par + (size_t)a * kNPar;
+  const float lbf = par[P_LB], ubf = par[P_UB], kap = par[P_KAPPA], tauf = par[P_TAU];
+  const double gam = par[P_GAMMA];
+  const bool phi = (kap > 0.f) || isfinite(tauf) || (par[P_HASTAX] != 0.f);
+  const int8_t* code_r = A.code + (size_t)a * n;
+  int8_t* code = A.code + (size_t)a * n;
+  const int32_t* flist = A.flist + (size_t)a * n;
+  const double* w = A.wout + (size_t)a * n;
+  const double* mult = A.mult + (size_t)a * (2 + G);
+  const double nu = mult[0], lam = mult[1];
+  const int nF = ps[PS_NF], nX = ps[PS_NX];
+
+  // y = B^T w over the rows with w != 0 (free list + nonzero fixed list)
+  for (int j = tid; j < k; j += 256) {
+    double s = 0.0;
+    for (int t = 0; t < nF; ++t) { const int i = flist[t]; s += (double)A.Bt[(size_t)i * A.kp + j] * w[i]; }
+    for (int t = 0; t < nX; ++t) { const int i = flist[n - 1 - t]; s += (double)A.Bt[(size_t)i * A.kp + j] * w[i]; }
+    s_y[j] = s * (double)A.f[j];
+  }
+  // group sums (deterministic: one thread per group over the lists)
+  for (int g = tid; g < G; g += 256) {
+    double s = 0.0;
+    for (int t = 0; t < nF; ++t) { const int i = flist[t]; if (A.group[i] == g) s += w[i]; }
+    for (int t = 0; t < nX; ++t) { const int i = flist[n - 1 - t]; if (A.group[i] == g) s += w[i]; }
+    s_gs[g] = s;
+  }
+  __syncthreads();
+
+  double sw = 0.0, turn = 0.0, gmax = 0.0, mumax = 0.0, dmax = 0.0, box = 0.0, snapm = 0.0,
+         obj = 0.0;
+  for (int i = tid; i < n; i += 256) {
+    RowData r = row_data(A, a, i);
+    Geom g;
+    make_geom(g, r.el, lbf, ubf, r.w0, kap, phi, r.ti, A.tax_brk, A.tax_slope);
+    const double lb = r.el ? (double)lbf : 0.0, ub = r.el ? (double)ubf : 0.0;
+    const double wi = w[i];
+    double sig = 0.0;
+    for (int j = 0; j < k; ++j) sig += (double)A.Bt[(size_t)i * A.kp + j] * s_y[j];
+    sig += (double)A.d[i] * wi;
+    const double mui = A.mu[(size_t)a * n + i];
+    double gi = gam * sig - mui - nu;
+    if (G) gi += mult[2 + A.group[i]];
+    double lo, hi, snap;
+    subdiff(g, wi, lam, lb, ub, lo, hi, snap);
+    const double t = -gi;
+    const double dist = fmax(fmax(lo - t, t - hi), 0.0);
+    sw += wi;
+    turn += fabs(wi - g.w0);
+    gmax = fmax(gmax, fabs(gam * sig));
+    mumax = fmax(mumax, fabs(mui));
+    dmax = fmax(dmax, dist);
+    box = fmax(box, fmax(lb - wi, wi - ub));
+    snapm = fmax(snapm, snap);
+    // objective: (gamma/2) w.Sigma w - mu w + trade cost
+    double tc = (double)kap * fabs(wi - g.w0);
+    if (r.ti >= 0 && wi < g.w0) {
+      const double s = g.w0 - wi;
+      const double e[5] = {0.0, (double)A.tax_brk[3 * r.ti], (double)A.tax_brk[3 * r.ti + 1],
+                           (double)A.tax_brk[3 * r.ti + 2], INFINITY};
+      for (int L = 0; L < 4; ++L)
+        if (s > e[L]) tc += (double)A.tax_slope[4 * r.ti + L] * (fmin(s, e[L + 1]) - e[L]);
+    }
+    obj += 0.5 * gam * wi * sig - mui * wi + tc;
+    // refinement proposal (applied only if the pattern fails)
+    const int c = code_r[i];
+    if (g.np > 1) {
+      const double tolm = A.eps_dual * 0.1;
+      if (c & 1) {
+        const int q = c >> 1;
+        if (wi > g.pt[q + 1]) code[i] = (int8_t)(2 * (q + 1));
+        else if (wi < g.pt[q]) code[i] = (int8_t)(2 * q);
+      } else {
+        // move off a point when -g lies outside its subdifferential
+        const int j = c >> 1;
+        double l2, h2, sn2;
+        subdiff(g, g.pt[j], lam, lb, ub, l2, h2, sn2);
+        const double sc = fmax(fabs(mui), 1e-12);
+        if (t > h2 + tolm * sc && j + 1 < g.np) code[i] = (int8_t)(2 * j + 1);
+        else if (t < l2 - tolm * sc && j > 0) code[i] = (int8_t)(2 * (j - 1) + 1);
+      }
+    }
+  }
+  sw = bsum<double>(sw, shd);
+  turn = bsum<double>(turn, shd);
+  obj = bsum<double>(obj, shd);
+  gmax = bmax<double>(gmax, shd);
+  mumax = bmax<double>(mumax, shd);
+  dmax = bmax<double>(dmax, shd);
+  box = bmax<double>(box, shd);
+  snapm = bmax<double>(snapm, shd);
+
+  if (tid == 0) {
+    const double scale = fmax(fmax(gmax, mumax), 1e-12);
+    double rexp = 0.0, comp = 0.0;
+    for (int g = 0; g < G; ++g) {
+      const double lo = A.blo[(size_t)a * G + g], hi = A.bhi[(size_t)a * G + g];
+      rexp = fmax(rexp, fmax(lo - s_gs[g], s_gs[g] - hi));
+      const double lg = mult[2 + g];
+      const double slack = (lg > 0.0) ? hi - s_gs[g] : s_gs[g] - lo;
+      comp = fmax(comp, fabs(lg) * fabs(slack));
+    }
+    const double tau = tauf;
+    double rturn = 0.0;
+    if (isfinite(tauf)) {
+      rturn = fmax(turn - tau, 0.0);
+      comp = fmax(comp, fmax(lam, 0.0) * fabs(tau - turn));
+    } else {
+      comp = fmax(comp, fabs(lam));
+    }
+    const double r_prim = fmax(fmax(fabs(sw - 1.0), fmax(box, 0.0)), fmax(rexp, rturn)) + snapm;
+    const double r_dual = fmax(dmax, fmax(-lam, 0.0)) / scale;
+    const double r_comp = comp / scale;
+    const bool ok = r_prim <= A.eps_prim && r_dual <= A.eps_dual && r_comp <= A.eps_comp;
+    ps[PS_ROUNDS] += 1;
+    // keep the diagnostics of the latest pattern in the result arrays
+    if (ok || final_pass) {
+      if (R.r_prim) R.r_prim[a] = r_prim;
+      if (R.r_dual) R.r_dual[a] = r_dual;
+      if (R.r_comp) R.r_comp[a] = r_comp;
+      if (R.obj) R.obj[a] = obj;
+      if (R.nu) R.nu[a] = nu;
+      if (R.lam_cap) R.lam_cap[a] = lam;
+    }
+    if (ok) {
+      ps[PS_DONE] = 1;
+      R.status[a] = FQP_SOLVED;
+    } else if (final_pass) {
+      // the paper's quality gates (Sec. "Quality Gates and Failure
+      // Vocabulary"): budget <= 1e-4 and bound violation <= 1e-6
+      const bool gates = fabs(sw - 1.0) <= 1e-4 && box <= 1e-6 && rexp <= 1e-6 && rturn <= 1e-6;
+      R.status[a] = gates ? FQP_FEASIBLE_UNCERTIFIED : FQP_MAX_ITER;
+    } else {
+      // bands / cap refinement
+      for (int g = 0; g < G; ++g) {
+        const double lo = A.blo[(size_t)a * G + g], hi = A.bhi[(size_t)a * G + g];
+        const bool act = band_active(ps, g), up = band_upper(ps, g);
+        const double lg = mult[2 + g];
+        if (act && ((up && lg < 0.0) || (!up && lg > 0.0))) set_band(ps, g, false, false);
+        else if (!act && s_gs[g] > hi + 0.1 * A.eps_prim) set_band(ps, g, true, true);
+        else if (!act && s_gs[g] < lo - 0.1 * A.eps_prim) set_band(ps, g, true, false);
+      }
+      if (isfinite(tauf)) {
+        if (ps[PS_CAP] && lam < 0.0) ps[PS_CAP] = 0;
+        else if (!ps[PS_CAP] && turn > tau + 0.1 * A.eps_prim) ps[PS_CAP] = 1;
+      }
+    }
+  }
+  __syncthreads();
+  if (final_pass || ps[PS_DONE]) {
+    if (R.lam_band && G) {
+      for (int g = tid; g < G; g += 256) R.lam_band[(size_t)a * G + g] = mult[2 + g];
+    }
+  }
+}
+
+static size_t polish_smem(int k) {
+  return sizeof(double) * ((size_t)k * k + 16 * (size_t)(k + 4) + 16 * (size_t)(kMaxG + 3));
+}
+
+hipError_t launch_polish_solve(const PolishArgs& A, hipStream_t st) {
+  const size_t smem = polish_smem(A.k);
+  hipError_t e = hipFuncSetAttribute((const void*)polish_solve_kernel,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(polish_solve_kernel, dim3(A.m_total), dim3(256), smem, st, A);
+  return hipGetLastError();
+}
+
+hipError_t launch_polish_check_r(const PolishArgs& A, const fqp_result& R, int final_pass,
+                                 hipStream_t st) {
+  hipLaunchKernelGGL(polish_check_kernel, dim3(A.m_total), dim3(256), 0, st, A, R, final_pass);
+  return hipGetLastError();
+}
+
+}  // namespace fqp

@@ -1,0 +1,594 @@
+// Host runtime of libfqp: handle, workspace, setup, the iteration / polish
+// schedule, and the C-ABI declared in include/fqp.h.
+//
+// Schedule of one fqp_solve_batch call (all on the caller's stream):
+//   pack   universe block B~, per-account validation and held-asset records
+//   setup  one factor-space Cholesky/inverse per distinct (gamma, rho) class
+//   init   z = u = 0, contraction of mu for the first x-step
+//   loop   blocks of `check_every` iterations [k-solve, fused pass] (captured
+//          once in a hipGraph and replayed), then float64 polish and
+//          certification rounds on every active account, then compaction
+//          of the active list; the host reads the number still active
+//   final  one last polish + diagnostics pass for accounts not certified
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "fqp_common.h"
+#include "fqp_kernels.h"
+#include "../../include/fqp.h"
+
+namespace fqp {
+hipError_t launch_polish_check_r(const PolishArgs& A, const fqp_result& R, int final_pass,
+                                 hipStream_t st);
+
+// ---------------------------------------------------------------------------
+// small bookkeeping kernels
+// ---------------------------------------------------------------------------
+__global__ void init_accounts_kernel(int m, int G, const int* cls, const float* rho_cls,
+                                     const float* gamma, const float* kappa, const float* lb,
+                                     const float* ub, const float* tau, const int32_t* tax_ptr,
+                                     float alpha, float rho_b, float* par, float* zb, float* vb,
+                                     const float* blo, const float* bhi, int* iters,
+                                     int32_t* pstate, int npstate) {
+  const int a = blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= m) return;
+  float* p = par + (size_t)a * kNPar;
+  const int c = cls[a];
+  p[P_GAMMA] = gamma[a];
+  p[P_RHO] = rho_cls[c];
+  p[P_KAPPA] = kappa[a];
+  p[P_LAM] = 0.f;
+  p[P_NU] = 0.f;
+  p[P_LB] = lb[a];
+  p[P_UB] = ub[a];
+  p[P_TAU] = tau[a];
+  p[P_ALPHA] = alpha;
+  p[P_RHOB] = rho_b;
+  p[P_CLASS] = (float)c;
+  p[P_HASTAX] = (tax_ptr && tax_ptr[a + 1] > tax_ptr[a]) ? 1.f : 0.f;
+  for (int g = 0; g < G; ++g) {
+    zb[(size_t)a * G + g] = fminf(fmaxf(0.f, blo[(size_t)a * G + g]), bhi[(size_t)a * G + g]);
+    vb[(size_t)a * G + g] = 0.f;
+  }
+  iters[a] = 0;
+  for (int q = 0; q < npstate; ++q) pstate[(size_t)a * npstate + q] = 0;
+}
+
+// active list = accounts whose status is still -1 (valid, not certified)
+__global__ void compact_kernel(int m, const int32_t* status, int* act, int* m_act) {
+  __shared__ int sh[256];
+  __shared__ int carry;
+  if (threadIdx.x == 0) carry = 0;
+  __syncthreads();
+  for (int base = 0; base < m; base += 256) {
+    const int a = base + threadIdx.x;
+    const int v = (a < m && status[a] == -1) ? 1 : 0;
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int o = 1; o < 256; o <<= 1) {
+      int t = (threadIdx.x >= o) ? sh[threadIdx.x - o] : 0;
+      __syncthreads();
+      sh[threadIdx.x] += t;
+      __syncthreads();
+    }
+    if (v) act[carry + sh[threadIdx.x] - 1] = a;
+    __syncthreads();
+    if (threadIdx.x == 255) carry += sh[255];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *m_act = carry;
+}
+
+// outputs of accounts that never ran (invalid / infeasible input)
+__global__ void finalize_kernel(int m, int n, const int32_t* status, const int* iters_dev,
+                                fqp_result R) {
+  const int a = blockIdx.x;
+  const int st = status[a];
+  if (threadIdx.x == 0 && R.iters) R.iters[a] = iters_dev[a];
+  if (st == FQP_SOLVED || st == FQP_FEASIBLE_UNCERTIFIED || st == FQP_MAX_ITER ||
+      st == FQP_TIME_LIMIT)
+    return;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) R.w[(size_t)a * n + i] = 0.0;
+  if (threadIdx.x == 0) {
+    if (R.r_prim) R.r_prim[a] = NAN;
+    if (R.r_dual) R.r_dual[a] = NAN;
+    if (R.r_comp) R.r_comp[a] = NAN;
+    if (R.obj) R.obj[a] = NAN;
+    if (R.nu) R.nu[a] = 0.0;
+    if (R.lam_cap) R.lam_cap[a] = 0.0;
+  }
+}
+
+__global__ void mark_time_limit_kernel(int m, int32_t* status) {
+  const int a = blockIdx.x * blockDim.x + threadIdx.x;
+  if (a < m && status[a] == FQP_MAX_ITER) status[a] = FQP_TIME_LIMIT;
+}
+
+}  // namespace fqp
+
+using namespace fqp;
+
+// ---------------------------------------------------------------------------
+// handle
+// ---------------------------------------------------------------------------
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+struct fqp_handle {
+  int device = 0;
+  hipStream_t stream = nullptr;   // the handle's own stream (capturable)
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  std::string err;
+  fqp_stats stats{};
+  std::map<std::string, DevBuf> bufs;
+  size_t total_bytes = 0;
+  bool configured = false;
+
+  template <typename T>
+  T* get(const char* name, size_t count, fqp_error* e) {
+    DevBuf& b = bufs[name];
+    const size_t need = count * sizeof(T) + 256;
+    if (b.bytes < need) {
+      if (b.p) { (void)hipFree(b.p); total_bytes -= b.bytes; }
+      b.p = nullptr;
+      b.bytes = 0;
+      if (hipMalloc(&b.p, need) != hipSuccess) {
+        (void)hipGetLastError();
+        b.p = nullptr;
+        *e = FQP_ERR_ALLOC;
+        err = std::string("workspace allocation failed: ") + name;
+        return nullptr;
+      }
+      b.bytes = need;
+      total_bytes += need;
+    }
+    return static_cast<T*>(b.p);
+  }
+};
+
+extern "C" {
+
+void fqp_default_settings(fqp_settings* s) {
+  if (!s) return;
+  std::memset(s, 0, sizeof(*s));
+  s->eps_prim = 1e-6;
+  s->eps_dual = 1e-6;
+  s->eps_comp = 1e-6;
+  s->max_iter = 4000;
+  s->check_every = 50;
+  s->rho = 0.f;
+  s->rho_band = 0.f;
+  s->alpha = 1.6f;
+  s->cap_beta = 0.1f;
+  s->polish_rounds = 4;
+  s->use_graph = 1;
+  s->profile = 0;
+  s->time_limit_ms = 0.0;
+}
+
+const char* fqp_error_string(int e) {
+  switch (e) {
+    case FQP_OK: return "ok";
+    case FQP_ERR_INVALID_ARG: return "invalid argument";
+    case FQP_ERR_ALLOC: return "device allocation failed";
+    case FQP_ERR_HIP: return "HIP runtime error";
+    case FQP_ERR_UNSUPPORTED: return "unsupported problem size";
+    default: return "unknown error";
+  }
+}
+
+const char* fqp_status_string(int s) {
+  switch (s) {
+    case FQP_SOLVED: return "certified";
+    case FQP_FEASIBLE_UNCERTIFIED: return "feasible / non-certified";
+    case FQP_MAX_ITER: return "iteration cap, no accepted feasible return";
+    case FQP_TIME_LIMIT: return "timeout";
+    case FQP_PRIMAL_INFEASIBLE: return "primal infeasible";
+    case FQP_INVALID_INPUT: return "invalid input";
+    case FQP_NUMERICAL_ERROR: return "allocation / numerical failure";
+    default: return "unknown status";
+  }
+}
+
+const char* fqp_last_error(const fqp_handle* h) { return h ? h->err.c_str() : "null handle"; }
+
+fqp_error fqp_create(fqp_handle** h, int device) {
+  if (!h) return FQP_ERR_INVALID_ARG;
+  *h = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) {
+    (void)hipGetLastError();
+    return FQP_ERR_INVALID_ARG;
+  }
+  int cur = 0;
+  (void)hipGetDevice(&cur);
+  if (hipSetDevice(device) != hipSuccess) {
+    (void)hipGetLastError();
+    return FQP_ERR_HIP;
+  }
+  fqp_handle* hh = new fqp_handle();
+  hh->device = device;
+  // default priority, non-blocking with respect to the legacy stream
+  if (hipStreamCreateWithFlags(&hh->stream, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&hh->ev_in, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&hh->ev_out, hipEventDisableTiming) != hipSuccess) {
+    (void)hipGetLastError();
+    if (hh->stream) (void)hipStreamDestroy(hh->stream);
+    if (hh->ev_in) (void)hipEventDestroy(hh->ev_in);
+    if (hh->ev_out) (void)hipEventDestroy(hh->ev_out);
+    delete hh;
+    (void)hipSetDevice(cur);
+    return FQP_ERR_HIP;
+  }
+  (void)hipSetDevice(cur);
+  *h = hh;
+  return FQP_OK;
+}
+
+void fqp_destroy(fqp_handle* h) {
+  if (!h) return;
+  int cur = 0;
+  (void)hipGetDevice(&cur);
+  (void)hipSetDevice(h->device);
+  if (h->stream) (void)hipStreamSynchronize(h->stream);
+  for (auto& kv : h->bufs)
+    if (kv.second.p) (void)hipFree(kv.second.p);
+  if (h->stream) (void)hipStreamDestroy(h->stream);
+  if (h->ev_in) (void)hipEventDestroy(h->ev_in);
+  if (h->ev_out) (void)hipEventDestroy(h->ev_out);
+  (void)hipSetDevice(cur);
+  delete h;
+}
+
+fqp_error fqp_get_stats(const fqp_handle* h, fqp_stats* out) {
+  if (!h || !out) return FQP_ERR_INVALID_ARG;
+  *out = h->stats;
+  return FQP_OK;
+}
+
+}  // extern "C"
+
+#define HIP_CHECK(x)                                                              \
+  do {                                                                            \
+    hipError_t _e = (x);                                                          \
+    if (_e != hipSuccess) {                                                       \
+      h->err = std::string("HIP error at " #x ": ") + hipGetErrorString(_e);       \
+      return FQP_ERR_HIP;                                                         \
+    }                                                                             \
+  } while (0)
+
+#define WS(var, T, name, count)                                                   \
+  T* var = h->get<T>(name, (size_t)(count), &e);                                  \
+  if (!var) return e;
+
+static float auto_rho(const fqp_settings* S) { return S->rho > 0.f ? S->rho : 5.0f; }
+
+extern "C" fqp_error fqp_solve_batch(fqp_handle* h, const fqp_universe* U, const fqp_book* P,
+                                     const fqp_settings* S_in, fqp_result* R, void* stream_v) {
+  if (!h) return FQP_ERR_INVALID_ARG;
+  h->err.clear();
+  h->stats = fqp_stats{};
+  auto t_start = std::chrono::steady_clock::now();
+  if (!U || !P || !R) { h->err = "null universe/book/result"; return FQP_ERR_INVALID_ARG; }
+  fqp_settings S;
+  if (S_in) S = *S_in; else fqp_default_settings(&S);
+  const int n = U->n, k = U->k, G = U->n_groups, m = P->m;
+  if (n < 1 || k < 1 || m < 1 || G < 0) { h->err = "non-positive size"; return FQP_ERR_INVALID_ARG; }
+  if (!U->B || !U->f || !U->d || !P->mu || !P->w0 || !P->lb || !P->ub || !P->gamma ||
+      !P->kappa || !P->tau || !R->w || !R->status) {
+    h->err = "required pointer is null";
+    return FQP_ERR_INVALID_ARG;
+  }
+  if (G > 0 && (!U->group || !P->band_lo || !P->band_hi)) {
+    h->err = "n_groups > 0 needs group labels and band bounds";
+    return FQP_ERR_INVALID_ARG;
+  }
+  if (P->tax_ptr && (!P->tax_asset || !P->tax_brk || !P->tax_slope)) {
+    h->err = "tax_ptr given without lot arrays";
+    return FQP_ERR_INVALID_ARG;
+  }
+  if (S.max_iter < 1 || S.check_every < 1 || !(S.alpha > 0.f && S.alpha < 2.f) ||
+      S.polish_rounds < 1) {
+    h->err = "invalid settings";
+    return FQP_ERR_INVALID_ARG;
+  }
+  const int kg = k + (G > 0 ? G : 0);
+  const int kp = ((kg + 1 + 31) / 32) * 32;
+  if (k > kMaxK || G > kMaxG || kp > kMaxKp) {
+    h->err = "factor count / group count beyond the library limits";
+    return FQP_ERR_UNSUPPORTED;
+  }
+  {
+    const long ncol = G + 3;
+    if ((long)k * ncol + ncol * ncol > 48L * 256) {
+      h->err = "factors x groups beyond the polish limits";
+      return FQP_ERR_UNSUPPORTED;
+    }
+  }
+  hipStream_t caller = static_cast<hipStream_t>(stream_v);
+  int prev_dev = 0;
+  (void)hipGetDevice(&prev_dev);
+  HIP_CHECK(hipSetDevice(h->device));
+  struct Restore {
+    int d;
+    ~Restore() { (void)hipSetDevice(d); }
+  } restore{prev_dev};
+  // all work runs on the handle's stream, ordered after the caller's prior
+  // work; the caller's stream waits for it at the end
+  hipStream_t st = h->stream;
+  HIP_CHECK(hipEventRecord(h->ev_in, caller));
+  HIP_CHECK(hipStreamWaitEvent(st, h->ev_in, 0));
+  struct Fence {
+    fqp_handle* h;
+    hipStream_t caller;
+    ~Fence() {
+      if (hipEventRecord(h->ev_out, h->stream) == hipSuccess)
+        (void)hipStreamWaitEvent(caller, h->ev_out, 0);
+    }
+  } fence{h, caller};
+  fqp_error e = FQP_OK;
+  if (!h->configured) {
+    HIP_CHECK(configure_iter_kernels());
+    h->configured = true;
+  }
+  const int W = (n + 31) / 32;
+
+  // ---- classes: distinct gamma values share one factor-space factorisation
+  std::vector<float> gam_h(m);
+  HIP_CHECK(hipMemcpyAsync(gam_h.data(), P->gamma, sizeof(float) * m, hipMemcpyDeviceToHost, st));
+  HIP_CHECK(hipStreamSynchronize(st));
+  std::vector<int> cls_h(m);
+  std::vector<float> cls_gamma;
+  {
+    std::map<float, int> seen;
+    for (int a = 0; a < m; ++a) {
+      float g = gam_h[a];
+      if (!(g > 0.f) || !std::isfinite(g)) g = 1.f;   // invalid: flagged by pack
+      auto it = seen.find(g);
+      if (it == seen.end()) {
+        int id = (int)cls_gamma.size();
+        seen[g] = id;
+        cls_gamma.push_back(g);
+        cls_h[a] = id;
+      } else {
+        cls_h[a] = it->second;
+      }
+    }
+  }
+  const int ncls = (int)cls_gamma.size();
+  const float rho = auto_rho(&S);
+  const float rho_b = S.rho_band > 0.f ? S.rho_band : rho;
+  std::vector<float> rho_cls(ncls, rho);
+
+  // ---- workspace ----------------------------------------------------------
+  WS(Bt, float, "Bt", (size_t)n * kp);
+  const int gram_rows = 2048;
+  const int nparts = (n + gram_rows - 1) / gram_rows;
+  WS(gpart, double, "gram_part", (size_t)nparts * (kg + 1) * (kg + 1));
+  const size_t kw_stride = (size_t)(kg + 1) * (kg + 1) + 2 * (size_t)kg * kg + kg + 16;
+  WS(Kw, double, "kwork", kw_stride * ncls);
+  WS(Kinv, float, "Kinv", (size_t)ncls * kp * kp);
+  WS(cvec, float, "cvec", (size_t)ncls * kp);
+  WS(qvec, float, "qvec", (size_t)ncls * kp);
+  WS(sig1, float, "sig1", (size_t)ncls);
+  WS(mbg, float, "mbg", (size_t)ncls * kp * (G > 0 ? G : 1));
+  WS(rho_d, float, "rho_cls", (size_t)ncls);
+  WS(cls_d, int, "cls", (size_t)m);
+  WS(z, float, "z", (size_t)m * n);
+  WS(u, float, "u", (size_t)m * n);
+  WS(hold, uint32_t, "hold", (size_t)m * W);
+  WS(hold_pre, int32_t, "hold_pre", (size_t)m * W);
+  WS(hold_cnt, int32_t, "hold_cnt", (size_t)m);
+  WS(hold_ptr, int32_t, "hold_ptr", (size_t)m + 1);
+  WS(hold_w0, float, "hold_w0", (size_t)m * n);
+  WS(hold_tax, int32_t, "hold_tax", (size_t)m * n);
+  WS(par, float, "par", (size_t)m * kNPar);
+  WS(pp, float, "pp", (size_t)m * kp);
+  WS(zb, float, "zb", (size_t)m * (G > 0 ? G : 1));
+  WS(vb, float, "vb", (size_t)m * (G > 0 ? G : 1));
+  WS(res, float, "res", (size_t)m * 4);
+  WS(iters, int, "iters", (size_t)m);
+  WS(act, int, "act", (size_t)m);
+  WS(m_act, int, "m_act", 1);
+  WS(code, int8_t, "code", (size_t)m * n);
+  WS(flist, int32_t, "flist", (size_t)m * n);
+  const size_t wks = polish_wk_stride(k, G);
+  WS(wk, double, "polish_wk", (size_t)m * wks);
+  WS(mult, double, "mult", (size_t)m * (2 + G));
+  WS(pstate, int32_t, "pstate", (size_t)m * 12);
+
+  // iteration geometry: ~1024 workgroups over (row tiles x account tiles)
+  const int acc_tiles = (m + kTM - 1) / kTM;
+  const int target_rt = std::max(1, 1024 / acc_tiles);
+  int chunks = (n + kRowsPerChunk * target_rt - 1) / (kRowsPerChunk * target_rt);
+  chunks = std::max(1, std::min(chunks, 64));
+  const int rows_per_wg = chunks * kRowsPerChunk;
+  const int n_rt = (n + rows_per_wg - 1) / rows_per_wg;
+  WS(part, float, "part", (size_t)n_rt * m * kp);
+  WS(stat, float, "stat", (size_t)n_rt * m * kNStat);
+  h->stats.workspace_bytes = h->total_bytes;
+
+  // ---- universe ------------------------------------------------------------
+  HIP_CHECK(launch_build_bt(n, k, G, kp, U->B, U->group, Bt, st));
+  HIP_CHECK(hipMemcpyAsync(rho_d, rho_cls.data(), sizeof(float) * ncls, hipMemcpyHostToDevice, st));
+  HIP_CHECK(hipMemcpyAsync(cls_d, cls_h.data(), sizeof(int) * m, hipMemcpyHostToDevice, st));
+  for (int c = 0; c < ncls; ++c) {
+    HIP_CHECK(launch_gram(n, kp, kg, nparts, gram_rows, Bt, U->d, cls_gamma[c], rho_cls[c], gpart, st));
+    HIP_CHECK(launch_kfactor(k, G, kp, nparts, gpart, U->f, cls_gamma[c], rho_b,
+                             Kw + kw_stride * c, Kinv + (size_t)c * kp * kp, cvec + (size_t)c * kp,
+                             qvec + (size_t)c * kp, sig1 + c, mbg + (size_t)c * kp * (G > 0 ? G : 1),
+                             st));
+  }
+
+  // ---- book -----------------------------------------------------------------
+  PackArgs pk{};
+  pk.n = n; pk.W = W; pk.m = m; pk.G = G;
+  pk.mu = P->mu; pk.w0 = P->w0; pk.lb = P->lb; pk.ub = P->ub; pk.elig = P->eligible;
+  pk.gamma = P->gamma; pk.kappa = P->kappa; pk.tau = P->tau;
+  pk.blo = G ? P->band_lo : nullptr; pk.bhi = G ? P->band_hi : nullptr;
+  pk.tax_ptr = P->tax_ptr; pk.tax_asset = P->tax_asset; pk.tax_brk = P->tax_brk;
+  pk.tax_slope = P->tax_slope;
+  pk.hold = hold; pk.hold_pre = hold_pre; pk.hold_cnt = hold_cnt; pk.hold_ptr = hold_ptr;
+  pk.hold_w0 = hold_w0; pk.hold_tax = hold_tax; pk.status = R->status; pk.par = par;
+  HIP_CHECK(launch_pack_count(pk, st));
+  HIP_CHECK(launch_pack_scan(pk, st));
+  HIP_CHECK(launch_pack_fill(pk, st));
+  hipLaunchKernelGGL(init_accounts_kernel, dim3((m + 255) / 256), dim3(256), 0, st, m, G, cls_d,
+                     rho_d, P->gamma, P->kappa, P->lb, P->ub, P->tau, P->tax_ptr, S.alpha, rho_b,
+                     par, zb, vb, P->band_lo, P->band_hi, iters, pstate, 12);
+  HIP_CHECK(hipGetLastError());
+  HIP_CHECK(hipMemsetAsync(z, 0, sizeof(float) * (size_t)m * n, st));
+  HIP_CHECK(hipMemsetAsync(u, 0, sizeof(float) * (size_t)m * n, st));
+  hipLaunchKernelGGL(compact_kernel, dim3(1), dim3(256), 0, st, m, R->status, act, m_act);
+  HIP_CHECK(hipGetLastError());
+
+  IterArgs ia{};
+  ia.n = n; ia.W = W; ia.rows_per_wg = rows_per_wg; ia.chunks_per_wg = chunks;
+  ia.m_total = m; ia.m_act = m_act; ia.act = act; ia.Bt = Bt; ia.d = U->d; ia.mu = P->mu;
+  ia.z = z; ia.u = u; ia.elig = P->eligible; ia.hold = hold; ia.hold_pre = hold_pre;
+  ia.hold_ptr = hold_ptr; ia.hold_w0 = hold_w0; ia.hold_tax = hold_tax;
+  ia.tax_brk = P->tax_brk; ia.tax_slope = P->tax_slope; ia.pp = pp; ia.par = par;
+  ia.part = part; ia.stat = stat;
+  KArgs ka{};
+  ka.kp = kp; ka.k = k; ka.G = G; ka.n_rt = n_rt; ka.m_total = m; ka.m_act = m_act; ka.act = act;
+  ka.part = part; ka.stat = stat; ka.par = par; ka.pp = pp; ka.Kinv = Kinv; ka.cvec = cvec;
+  ka.qvec = qvec; ka.sig1 = sig1; ka.mbg = mbg; ka.zb = zb; ka.vb = vb;
+  ka.blo = G ? P->band_lo : nullptr; ka.bhi = G ? P->band_hi : nullptr;
+  ka.cap_beta = S.cap_beta; ka.res = res; ka.iters = iters;
+  PolishArgs pa{};
+  pa.n = n; pa.k = k; pa.G = G; pa.kp = kp; pa.W = W; pa.m_total = m; pa.m_act = m_act;
+  pa.act = act; pa.Bt = Bt; pa.f = U->f; pa.d = U->d; pa.group = G ? U->group : nullptr;
+  pa.mu = P->mu; pa.z = z; pa.elig = P->eligible; pa.hold = hold; pa.hold_pre = hold_pre;
+  pa.hold_ptr = hold_ptr; pa.hold_w0 = hold_w0; pa.hold_tax = hold_tax;
+  pa.tax_brk = P->tax_brk; pa.tax_slope = P->tax_slope; pa.par = par; pa.zb = zb; pa.vb = vb;
+  pa.blo = G ? P->band_lo : nullptr; pa.bhi = G ? P->band_hi : nullptr;
+  pa.code = code; pa.flist = flist; pa.wk = wk; pa.wk_stride = wks; pa.wout = R->w;
+  pa.mult = mult; pa.pstate = pstate;
+  pa.eps_prim = S.eps_prim; pa.eps_dual = S.eps_dual; pa.eps_comp = S.eps_comp;
+
+  const dim3 igrid(n_rt, acc_tiles);
+  HIP_CHECK(launch_iter(ia, kp, true, igrid, st));
+
+  // ---- iteration blocks -------------------------------------------------------
+  hipGraphExec_t gexec = nullptr;
+  hipGraph_t graph = nullptr;
+  struct GraphGuard {
+    hipGraphExec_t* ge;
+    hipGraph_t* g;
+    ~GraphGuard() {
+      if (*ge) (void)hipGraphExecDestroy(*ge);
+      if (*g) (void)hipGraphDestroy(*g);
+    }
+  } gguard{&gexec, &graph};
+  const bool use_graph = S.use_graph && !S.profile;
+  std::vector<hipEvent_t> evs;
+  if (S.profile) {
+    evs.resize(2 * S.check_every);
+    for (auto& ev : evs) HIP_CHECK(hipEventCreate(&ev));
+  }
+  struct EvGuard {
+    std::vector<hipEvent_t>* v;
+    ~EvGuard() { for (auto& ev : *v) (void)hipEventDestroy(ev); }
+  } evguard{&evs};
+
+  auto run_block = [&](int count) -> fqp_error {
+    if (use_graph && count == S.check_every) {
+      if (!gexec) {
+        HIP_CHECK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+        for (int c = 0; c < count; ++c) {
+          hipError_t e1 = launch_ksolve(ka, m, st);
+          hipError_t e2 = launch_iter(ia, kp, false, igrid, st);
+          if (e1 != hipSuccess || e2 != hipSuccess) {
+            hipGraph_t tmp = nullptr;
+            (void)hipStreamEndCapture(st, &tmp);
+            if (tmp) (void)hipGraphDestroy(tmp);
+            h->err = "launch failed during graph capture";
+            return FQP_ERR_HIP;
+          }
+        }
+        HIP_CHECK(hipStreamEndCapture(st, &graph));
+        HIP_CHECK(hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0));
+      }
+      HIP_CHECK(hipGraphLaunch(gexec, st));
+    } else {
+      for (int c = 0; c < count; ++c) {
+        HIP_CHECK(launch_ksolve(ka, m, st));
+        if (S.profile) HIP_CHECK(hipEventRecord(evs[2 * c], st));
+        HIP_CHECK(launch_iter(ia, kp, false, igrid, st));
+        if (S.profile) HIP_CHECK(hipEventRecord(evs[2 * c + 1], st));
+      }
+      if (S.profile) {
+        HIP_CHECK(hipEventSynchronize(evs[2 * count - 1]));
+        for (int c = 0; c < count; ++c) {
+          float ms = 0.f;
+          HIP_CHECK(hipEventElapsedTime(&ms, evs[2 * c], evs[2 * c + 1]));
+          h->stats.iter_kernel_ms += ms;
+        }
+      }
+    }
+    h->stats.iter_launches += count;
+    return FQP_OK;
+  };
+
+  int done_iters = 0;
+  int active = 0;
+  HIP_CHECK(hipMemcpyAsync(&active, m_act, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIP_CHECK(hipStreamSynchronize(st));
+  bool timed_out = false;
+  while (active > 0 && done_iters < S.max_iter) {
+    const int count = std::min(S.check_every, S.max_iter - done_iters);
+    fqp_error be = run_block(count);
+    if (be != FQP_OK) return be;
+    done_iters += count;
+    // polish + certification rounds
+    for (int r = 0; r < S.polish_rounds; ++r) {
+      pa.first_round = (r == 0);
+      HIP_CHECK(launch_polish_solve(pa, st));
+      HIP_CHECK(launch_polish_check_r(pa, *R, 0, st));
+      h->stats.polish_calls += 1;
+    }
+    hipLaunchKernelGGL(compact_kernel, dim3(1), dim3(256), 0, st, m, R->status, act, m_act);
+    HIP_CHECK(hipGetLastError());
+    HIP_CHECK(hipMemcpyAsync(&active, m_act, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIP_CHECK(hipStreamSynchronize(st));
+    if (S.time_limit_ms > 0.0) {
+      double el = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() -
+                                                            t_start).count();
+      if (el > S.time_limit_ms) { timed_out = true; break; }
+    }
+  }
+  if (active > 0) {
+    // last pattern from the current iterate, diagnostics, final statuses
+    pa.first_round = 1;
+    HIP_CHECK(launch_polish_solve(pa, st));
+    HIP_CHECK(launch_polish_check_r(pa, *R, 1, st));
+    if (timed_out) {
+      hipLaunchKernelGGL(mark_time_limit_kernel, dim3((m + 255) / 256), dim3(256), 0, st, m,
+                         R->status);
+      HIP_CHECK(hipGetLastError());
+    }
+  }
+  hipLaunchKernelGGL(finalize_kernel, dim3(m), dim3(256), 0, st, m, n, R->status, iters, *R);
+  HIP_CHECK(hipGetLastError());
+  // count solved accounts and account-iterations
+  std::vector<int32_t> st_h(m);
+  std::vector<int> it_h(m);
+  HIP_CHECK(hipMemcpyAsync(st_h.data(), R->status, sizeof(int32_t) * m, hipMemcpyDeviceToHost, st));
+  HIP_CHECK(hipMemcpyAsync(it_h.data(), iters, sizeof(int) * m, hipMemcpyDeviceToHost, st));
+  HIP_CHECK(hipStreamSynchronize(st));
+  for (int a = 0; a < m; ++a) {
+    h->stats.n_solved += (st_h[a] == FQP_SOLVED);
+    h->stats.account_iters += it_h[a];
+  }
+  h->stats.iterations = done_iters;
+  h->stats.total_ms =
+      std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+  return FQP_OK;
+}

@@ -1,0 +1,183 @@
+"""Python binding of fqp_solve_batch: torch device tensors in, torch device
+tensors out.  Every step of the solve runs in libfqp's HIP kernels; this
+module only lays out arrays and marshals pointers.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+import torch
+
+from . import _lib
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def pack_eligibility(elig: np.ndarray) -> np.ndarray:
+    """bool [m, n] -> uint32 [m, ceil(n/32)], bit i%32 of word i//32."""
+    m, n = elig.shape
+    W = (n + 31) // 32
+    by = np.packbits(elig.astype(np.uint8), axis=1, bitorder="little")
+    pad = np.zeros((m, 4 * W), dtype=np.uint8)
+    pad[:, :by.shape[1]] = by
+    return pad.view("<u4").reshape(m, W).copy()
+
+
+@dataclass
+class DeviceProblem:
+    """Universe + book laid out on the device as the C-ABI expects."""
+    n: int
+    k: int
+    G: int
+    m: int
+    B: torch.Tensor
+    f: torch.Tensor
+    d: torch.Tensor
+    group: Optional[torch.Tensor]
+    mu: torch.Tensor
+    w0: torch.Tensor
+    lb: torch.Tensor
+    ub: torch.Tensor
+    eligible: Optional[torch.Tensor]
+    gamma: torch.Tensor
+    kappa: torch.Tensor
+    tau: torch.Tensor
+    band_lo: Optional[torch.Tensor]
+    band_hi: Optional[torch.Tensor]
+    tax_ptr: Optional[torch.Tensor]
+    tax_asset: Optional[torch.Tensor]
+    tax_brk: Optional[torch.Tensor]
+    tax_slope: Optional[torch.Tensor]
+
+
+def to_device(uni, book, device="cuda:0") -> DeviceProblem:
+    """Lay out a (workloads.Universe, workloads.Book) pair on the device."""
+    dev = torch.device(device)
+
+    def f32(x):
+        return torch.as_tensor(np.ascontiguousarray(x, dtype=np.float32),
+                               device=dev)
+
+    def i32(x):
+        return torch.as_tensor(np.ascontiguousarray(x, dtype=np.int32),
+                               device=dev)
+
+    G = uni.n_groups if book.band_lo is not None else 0
+    elig = None
+    if not book.eligible.all():
+        elig = torch.as_tensor(pack_eligibility(book.eligible).view(np.int32),
+                               device=dev)
+    has_tax = book.tax_asset.size > 0
+    return DeviceProblem(
+        n=uni.n, k=uni.k, G=G, m=book.m,
+        B=f32(uni.B), f=f32(uni.f), d=f32(uni.d),
+        group=i32(uni.group) if G else None,
+        mu=f32(book.mu), w0=f32(book.w0), lb=f32(book.lb), ub=f32(book.ub),
+        eligible=elig, gamma=f32(book.gamma), kappa=f32(book.kappa),
+        tau=f32(book.tau),
+        band_lo=f32(book.band_lo) if G else None,
+        band_hi=f32(book.band_hi) if G else None,
+        tax_ptr=i32(book.tax_ptr) if has_tax else None,
+        tax_asset=i32(book.tax_asset) if has_tax else None,
+        tax_brk=f32(book.tax_brk) if has_tax else None,
+        tax_slope=f32(book.tax_slope) if has_tax else None,
+    )
+
+
+SETTING_NAMES = [name for name, _ in _lib.Settings._fields_]
+
+
+class Solver:
+    """Owns one library handle (and its device workspace)."""
+
+    def __init__(self, device: int = 0):
+        self.lib = _lib.load()
+        self.device = device
+        h = ctypes.c_void_p()
+        rc = self.lib.fqp_create(ctypes.byref(h), device)
+        if rc != 0:
+            raise RuntimeError(
+                f"fqp_create failed: {self.lib.fqp_error_string(rc).decode()}")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.fqp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def settings(self, **kw) -> _lib.Settings:
+        s = _lib.Settings()
+        self.lib.fqp_default_settings(ctypes.byref(s))
+        for key, val in kw.items():
+            if key not in SETTING_NAMES:
+                raise KeyError(f"unknown setting {key!r}")
+            setattr(s, key, val)
+        return s
+
+    def solve(self, P: DeviceProblem, out: Optional[dict] = None, stream=None,
+              **settings) -> dict:
+        dev = P.mu.device
+        m, n, G = P.m, P.n, P.G
+        if out is None:
+            out = dict(
+                w=torch.empty((m, n), dtype=torch.float64, device=dev),
+                status=torch.empty(m, dtype=torch.int32, device=dev),
+                iters=torch.empty(m, dtype=torch.int32, device=dev),
+                r_prim=torch.empty(m, dtype=torch.float64, device=dev),
+                r_dual=torch.empty(m, dtype=torch.float64, device=dev),
+                r_comp=torch.empty(m, dtype=torch.float64, device=dev),
+                obj=torch.empty(m, dtype=torch.float64, device=dev),
+                nu=torch.empty(m, dtype=torch.float64, device=dev),
+                lam_cap=torch.empty(m, dtype=torch.float64, device=dev),
+                lam_band=torch.zeros((m, max(G, 1)), dtype=torch.float64,
+                                     device=dev),
+            )
+        U = _lib.Universe(n=n, k=P.k, n_groups=G, B=_ptr(P.B), f=_ptr(P.f),
+                          d=_ptr(P.d), group=_ptr(P.group))
+        Bk = _lib.Book(m=m, mu=_ptr(P.mu), w0=_ptr(P.w0), lb=_ptr(P.lb),
+                       ub=_ptr(P.ub), eligible=_ptr(P.eligible),
+                       gamma=_ptr(P.gamma), kappa=_ptr(P.kappa),
+                       tau=_ptr(P.tau), band_lo=_ptr(P.band_lo),
+                       band_hi=_ptr(P.band_hi), tax_ptr=_ptr(P.tax_ptr),
+                       tax_asset=_ptr(P.tax_asset), tax_brk=_ptr(P.tax_brk),
+                       tax_slope=_ptr(P.tax_slope))
+        R = _lib.Result(w=_ptr(out["w"]), status=_ptr(out["status"]),
+                        iters=_ptr(out["iters"]), r_prim=_ptr(out["r_prim"]),
+                        r_dual=_ptr(out["r_dual"]),
+                        r_comp=_ptr(out["r_comp"]), obj=_ptr(out["obj"]),
+                        nu=_ptr(out["nu"]), lam_cap=_ptr(out["lam_cap"]),
+                        lam_band=_ptr(out["lam_band"]) if G else None)
+        S = self.settings(**settings)
+        if stream is None:
+            stream = torch.cuda.current_stream(dev)
+        rc = self.lib.fqp_solve_batch(self.h, ctypes.byref(U), ctypes.byref(Bk),
+                                      ctypes.byref(S), ctypes.byref(R),
+                                      ctypes.c_void_p(stream.cuda_stream))
+        if rc != 0:
+            raise RuntimeError(
+                f"fqp_solve_batch failed ({self.lib.fqp_error_string(rc).decode()}):"
+                f" {self.lib.fqp_last_error(self.h).decode()}")
+        return out
+
+    def stats(self) -> dict:
+        st = _lib.Stats()
+        self.lib.fqp_get_stats(self.h, ctypes.byref(st))
+        return {name: getattr(st, name) for name, _ in _lib.Stats._fields_}
+
+
+def solve_batch(P: DeviceProblem, solver: Optional[Solver] = None, **settings):
+    """One-shot convenience wrapper: returns (outputs, stats)."""
+    s = solver or Solver(P.mu.device.index or 0)
+    out = s.solve(P, **settings)
+    return out, s.stats()

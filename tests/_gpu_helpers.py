@@ -1,0 +1,53 @@
+"""Shared helpers of the GPU tests: run the HIP solver through the C-ABI and
+compare with the float64 oracle on the same seeded inputs."""
+import numpy as np
+
+import oracle
+from oracle.problem import account
+from oracle.kkt import residuals
+
+# Acceptance of the headline target (1e-6 relative objective, 1e-6 primal
+# and dual residual, measured by the oracle's own checker on the GPU output)
+TOL_OBJ = 1e-6
+TOL_PRIM = 1e-6
+TOL_DUAL = 1e-6
+TOL_COMP = 1e-6
+# Elementwise weight agreement.  A certified GPU result is the float64
+# solution of the same reduced KKT system the oracle's crossover solves, so
+# the two agree to round-off; 1e-7 (absolute, weights sum to 1) is far above
+# that and far below the smallest position size that matters (1e-5).
+TOL_W = 1e-7
+
+
+def run_gpu(uni, book, solver=None, **settings):
+    import torch
+    from paper_2606_23367_amd.solver import Solver, to_device
+    P = to_device(uni, book)
+    s = solver or Solver(0)
+    out = s.solve(P, **settings)
+    torch.cuda.synchronize()
+    host = {k: v.cpu().numpy() for k, v in out.items()}
+    return host, s.stats()
+
+
+def check_account(uni, book, a, host, tol_w=TOL_W):
+    P = account(uni, book, a)
+    orc = oracle.solve_account(P)
+    assert orc["method"] == "crossover"
+    w = host["w"][a]
+    lam_band = host["lam_band"][a] if P.n_groups else None
+    r = residuals(P, w, host["nu"][a], lam_band, host["lam_cap"][a])
+    relobj = abs(r["obj"] - orc["obj"]) / max(abs(orc["obj"]), 1e-300)
+    info = dict(a=a, status=int(host["status"][a]), r_prim=r["r_prim"],
+                r_dual=r["r_dual"], r_comp=r["r_comp"], relobj=relobj,
+                werr=float(np.max(np.abs(w - orc["w"]))))
+    assert host["status"][a] == 0, info
+    assert r["r_prim"] <= TOL_PRIM, info
+    assert r["r_dual"] <= TOL_DUAL, info
+    assert r["r_comp"] <= TOL_COMP, info
+    assert relobj <= TOL_OBJ, info
+    assert info["werr"] <= tol_w, info
+    # the GPU's own float64 diagnostics agree with the oracle's checker
+    assert abs(host["r_prim"][a] - r["r_prim"]) <= 1e-9, info
+    assert abs(host["obj"][a] - r["obj"]) <= 1e-12 * max(1.0, abs(r["obj"])), info
+    return info
