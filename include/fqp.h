@@ -157,6 +157,20 @@ FQP_API fqp_error fqp_solve_batch(fqp_handle *h, const fqp_universe *U,
                           const fqp_book *P, const fqp_settings *S,
                           fqp_result *R, void *stream);
 
+/* Gradients of a loss L(w) through the last fqp_solve_batch call on this
+ * handle (implicit differentiation of the KKT system at each certified
+ * optimum, Eq. 1 with the active pattern held fixed):
+ *   dL_dw  [m][n] float64 device, input  (dL/dw)
+ *   dL_dmu [m][n] float64 device, output (dL/dmu; zero for accounts that are
+ *          not certified and for coordinates fixed at a bound or kink)
+ *   dL_dB  [n][k] float64 device, output (dL/dB summed over certified
+ *          accounts; the factor loadings are shared by the book)
+ * The inputs and outputs of that solve must still be alive and unchanged.
+ * Asynchronous on `stream`; FQP_ERR_INVALID_ARG if no solve preceded it. */
+FQP_API fqp_error fqp_adjoint_batch(fqp_handle *h, const double *dL_dw,
+                                    double *dL_dmu, double *dL_dB,
+                                    void *stream);
+
 FQP_API fqp_error fqp_get_stats(const fqp_handle *h, fqp_stats *out);
 
 FQP_API const char *fqp_error_string(int e);

@@ -8,7 +8,7 @@ from ._lib import STATUS_NAMES, SOLVED  # noqa: F401
 
 def __getattr__(name):
     if name in ("Solver", "solve_batch", "to_device", "DeviceProblem",
-                "pack_eligibility"):
+                "pack_eligibility", "FqpFunction", "solve_differentiable"):
         from . import solver
         return getattr(solver, name)
     raise AttributeError(name)

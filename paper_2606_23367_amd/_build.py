@@ -8,7 +8,8 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
-SOURCES = ["fqp_iter.hip", "fqp_pack.hip", "fqp_polish.hip", "fqp_runtime.hip"]
+SOURCES = ["fqp_iter.hip", "fqp_pack.hip", "fqp_polish.hip", "fqp_adjoint.hip",
+           "fqp_runtime.hip"]
 LIB = os.path.join(HERE, "libfqp.so")
 ARCH = "gfx950"
 FLAGS = [

@@ -64,7 +64,7 @@ class Stats(ctypes.Structure):
 
 
 EXPORTS = ("fqp_default_settings", "fqp_create", "fqp_solve_batch",
-           "fqp_get_stats", "fqp_error_string", "fqp_status_string",
+           "fqp_adjoint_batch", "fqp_get_stats", "fqp_error_string", "fqp_status_string",
            "fqp_last_error", "fqp_destroy")
 
 _lib = None
@@ -89,6 +89,9 @@ def load(path: str = LIB_PATH):
                                     ctypes.POINTER(Settings),
                                     ctypes.POINTER(Result), c_void_p]
     lib.fqp_solve_batch.restype = ctypes.c_int
+    lib.fqp_adjoint_batch.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p,
+                                      c_void_p]
+    lib.fqp_adjoint_batch.restype = ctypes.c_int
     lib.fqp_get_stats.argtypes = [c_void_p, ctypes.POINTER(Stats)]
     lib.fqp_get_stats.restype = ctypes.c_int
     lib.fqp_error_string.argtypes = [ctypes.c_int]

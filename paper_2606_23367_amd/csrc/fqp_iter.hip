@@ -497,10 +497,15 @@ __global__ __launch_bounds__(256) void ksolve_kernel(KArgs A) {
     const float tau = par[P_TAU];
     const float nfree = sst[ST_NFREE];
     if (nfree >= 0.f && isfinite(tau)) {
-      float lam = par[P_LAM];
+      // damped Newton step on turnover(lam) = tau (slope -nfree/rho),
+      // limited to [lam/2, 2 lam + lam_eps] so a pass with few free
+      // coordinates cannot throw the multiplier far off
+      const float lam = par[P_LAM];
       const float rho = par[P_RHO];
-      lam += A.cap_beta * rho * (sst[ST_TURN] - tau) / fmaxf(nfree, 1.f);
-      par[P_LAM] = fmaxf(lam, 0.f);
+      const float lam_eps = 1e-4f;
+      float nl = lam + A.cap_beta * rho * (sst[ST_TURN] - tau) / fmaxf(nfree, 1.f);
+      nl = fminf(fmaxf(nl, 0.5f * lam), 2.f * lam + lam_eps);
+      par[P_LAM] = fmaxf(nl, 0.f);
     }
     if (nfree >= 0.f) {
       A.res[(size_t)a * 4 + 0] = fmaxf(sst[ST_RPRIM], (float)red[0]);

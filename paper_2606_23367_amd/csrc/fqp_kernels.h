@@ -119,6 +119,7 @@ struct PolishArgs {
   const float* blo;
   const float* bhi;
   int8_t* code;              // [m][n] active-set codes
+  int8_t* code_next;         // [m][n] refinement proposals
   int32_t* flist;            // [m][n] free list
   double* wk;                // [m][wk_stride] per-account scratch
   size_t wk_stride;
@@ -127,8 +128,32 @@ struct PolishArgs {
   int32_t* pstate;           // [m][8] polish bookkeeping
   double eps_prim, eps_dual, eps_comp;
   int first_round;           // classify from z when nonzero
+  int nf_gate;               // skip patterns with more free rows (0: never)
 };
 hipError_t launch_polish_solve(const PolishArgs& A, hipStream_t st);
 size_t polish_wk_stride(int k, int G);
+
+// ---- KKT adjoint (float64) ---------------------------------------------------
+struct AdjArgs {
+  int n, k, G, kp, m;
+  const float* Bt;
+  const float* f;
+  const float* d;
+  const int32_t* group;
+  const float* w0in;         // [m][n] caller's w0
+  const float* par;
+  const int32_t* status;     // [m] statuses of the last solve
+  const int32_t* pstate;
+  const int32_t* flist;
+  const int8_t* code;
+  const double* w;           // [m][n] weights of the last solve
+  const double* dLdw;        // [m][n]
+  double* dmu;               // [m][n] out
+  double* dB;                // [n][k] out
+  double* yvw;               // [m][2k] scratch
+  double* wk;
+  size_t wk_stride;
+};
+hipError_t launch_adjoint(const AdjArgs& A, hipStream_t st);
 
 }  // namespace fqp

@@ -33,7 +33,7 @@ namespace fqp {
 
 enum PState {
   PS_CAP = 0, PS_NF, PS_NX, PS_NC, PS_DONE, PS_ROUNDS,
-  PS_BACT0, PS_BACT1, PS_BUP0, PS_BUP1, PS_FAILS, kNPState = 12
+  PS_BACT0, PS_BACT1, PS_BUP0, PS_BUP1, PS_STALL, kNPState = 12
 };
 
 constexpr double kSnap = 1e-10;
@@ -250,6 +250,7 @@ __global__ __launch_bounds__(256) void polish_solve_kernel(PolishArgs A) {
       ps[PS_CAP] = isfinite(tauf) && par[P_LAM] > 0.f;
       ps[PS_DONE] = 0;
       ps[PS_ROUNDS] = 0;
+      ps[PS_STALL] = 0;
       ps[PS_BACT0] = ps[PS_BACT1] = ps[PS_BUP0] = ps[PS_BUP1] = 0;
       double* mult = A.mult + (size_t)a * (2 + G);
       mult[0] = par[P_NU];
@@ -281,41 +282,61 @@ __global__ __launch_bounds__(256) void polish_solve_kernel(PolishArgs A) {
     }
     __syncthreads();
   }
-  if (ps[PS_DONE]) return;
+  if (ps[PS_DONE] || ps[PS_STALL]) return;
   const int cap_on = ps[PS_CAP];
 
   // ---- pass 1: fixed values, free list, nonzero-fixed list --------------
   // free rows are listed from the front of flist, nonzero fixed rows from
-  // the back.
+  // the back (wave ballots + a 4-entry prefix per chunk).
+  __shared__ int s_wc[2][kWaves][2];
   if (tid == 0) { s_cnt[0] = 0; s_cnt[1] = 0; }
   __syncthreads();
-  for (int base = 0; base < n; base += 256) {
-    const int i = base + tid;
-    int isfree = 0, isnz = 0;
-    if (i < n) {
-      const int c = code[i];
-      if (c & 1) {
-        isfree = 1;
-        w[i] = 0.0;
-      } else {
-        RowData r = row_data(A, a, i);
-        Geom g;
-        make_geom(g, r.el, lbf, ubf, r.w0, kap, phi, r.ti, A.tax_brk, A.tax_slope);
-        const double v = g.pt[c >> 1];
-        w[i] = v;
-        isnz = (v != 0.0);
+  {
+    const int lane = tid & 63, wv = tid >> 6;
+    int it = 0;
+    for (int base = 0; base < n; base += 256, ++it) {
+      const int i = base + tid;
+      int isfree = 0, isnz = 0;
+      if (i < n) {
+        const int c = code[i];
+        if (c & 1) {
+          isfree = 1;
+          w[i] = 0.0;
+        } else {
+          RowData r = row_data(A, a, i);
+          Geom g;
+          make_geom(g, r.el, lbf, ubf, r.w0, kap, phi, r.ti, A.tax_brk, A.tax_slope);
+          const double v = g.pt[c >> 1];
+          w[i] = v;
+          isnz = (v != 0.0);
+        }
       }
+      const unsigned long long mf = __ballot(isfree), mn = __ballot(isnz);
+      const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+      const int par_ = it & 1;
+      if (lane == 0) { s_wc[par_][wv][0] = __popcll(mf); s_wc[par_][wv][1] = __popcll(mn); }
+      __syncthreads();
+      int pf = __popcll(mf & below), pn = __popcll(mn & below), tf = 0, tn = 0;
+      for (int q = 0; q < kWaves; ++q) {
+        if (q < wv) { pf += s_wc[par_][q][0]; pn += s_wc[par_][q][1]; }
+        tf += s_wc[par_][q][0];
+        tn += s_wc[par_][q][1];
+      }
+      const int c0 = s_cnt[0], c1 = s_cnt[1];
+      if (isfree) flist[c0 + pf] = i;
+      if (isnz) flist[n - 1 - (c1 + pn)] = i;
+      __syncthreads();
+      if (tid == 0) { s_cnt[0] = c0 + tf; s_cnt[1] = c1 + tn; }
     }
-    int tf, tn;
-    const int pf = bscan(isfree, shi, &tf);
-    const int pn = bscan(isnz, shi, &tn);
-    if (isfree) flist[s_cnt[0] + pf] = i;
-    if (isnz) flist[n - 1 - (s_cnt[1] + pn)] = i;
-    __syncthreads();
-    if (tid == 0) { s_cnt[0] += tf; s_cnt[1] += tn; }
     __syncthreads();
   }
   const int nF = s_cnt[0], nX = s_cnt[1];
+  // a pattern with many free coordinates belongs to an iterate that is far
+  // from the optimum's vertex structure: skip the (costly) solve for now
+  if (A.nf_gate > 0 && nF > A.nf_gate) {
+    if (tid == 0) { ps[PS_STALL] = 1; ps[PS_NF] = nF; }
+    return;
+  }
 
   // ---- fixed contributions ----------------------------------------------
   // yX = B_X^T w_X, budget / band / cap sums of the fixed rows
@@ -421,8 +442,15 @@ __global__ __launch_bounds__(256) void polish_solve_kernel(PolishArgs A) {
   {
     const int nW = k * ncol, nCV = ncol * ncol, ne2 = nW + nCV;
     double acc[48];
+    short ia[48], ib[48];     // (B column or V column, V column); ia < 0: unused
 #pragma unroll
-    for (int c = 0; c < 48; ++c) acc[c] = 0.0;
+    for (int c = 0; c < 48; ++c) {
+      acc[c] = 0.0;
+      const int e = tid + 256 * c;
+      if (e < nW) { ia[c] = (short)(e / ncol); ib[c] = (short)(e % ncol); }
+      else if (e < ne2) { ia[c] = (short)(1000 + (e - nW) / ncol); ib[c] = (short)((e - nW) % ncol); }
+      else { ia[c] = -1; ib[c] = 0; }
+    }
     double* vst = stg + SR * SS;       // per staged row: ncol values
     for (int f0 = 0; f0 < nF; f0 += SR) {
       const int rows = min(SR, nF - f0);
@@ -462,13 +490,9 @@ __global__ __launch_bounds__(256) void polish_solve_kernel(PolishArgs A) {
         const double id = b[k];
 #pragma unroll
         for (int c = 0; c < 48; ++c) {
-          const int e = tid + 256 * c;
-          if (e < nW) {
-            acc[c] += b[e / ncol] * v[e % ncol] * id;
-          } else if (e < ne2) {
-            const int q = e - nW;
-            acc[c] += v[q / ncol] * v[q % ncol] * id;
-          }
+          if (ia[c] < 0) continue;
+          const double x = (ia[c] >= 1000) ? v[ia[c] - 1000] : b[ia[c]];
+          acc[c] += x * v[ib[c]] * id;
         }
       }
     }
@@ -624,6 +648,7 @@ __global__ __launch_bounds__(256) void polish_solve_kernel(PolishArgs A) {
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void polish_check_kernel(PolishArgs A, fqp_result R,
                                                           int final_pass) {
+  extern __shared__ float sBrow[];        // [256][k + 1]
   __shared__ double shd[256];
   __shared__ double s_y[kMaxK];
   __shared__ double s_gs[kMaxG];
@@ -633,13 +658,16 @@ __global__ __launch_bounds__(256) void polish_check_kernel(PolishArgs A, fqp_res
   const int a = A.act[slot];
   const int tid = threadIdx.x;
   int* ps = A.pstate + (size_t)a * kNPState;
-  if (ps[PS_DONE]) return;
+  if (ps[PS_DONE] || (ps[PS_STALL] && !final_pass)) return;
+  __shared__ int s_changed;
+  if (tid == 0) s_changed = 0;
   const float* par = A.par + (size_t)a * kNPar;
   const float lbf = par[P_LB], ubf = par[P_UB], kap = par[P_KAPPA], tauf = par[P_TAU];
   const double gam = par[P_GAMMA];
   const bool phi = (kap > 0.f) || isfinite(tauf) || (par[P_HASTAX] != 0.f);
-  const int8_t* code_r = A.code + (size_t)a * n;
-  int8_t* code = A.code + (size_t)a * n;
+  int changed = 0;
+  int8_t* code_r = A.code + (size_t)a * n;
+  int8_t* code = A.code_next + (size_t)a * n;    // proposals
   const int32_t* flist = A.flist + (size_t)a * n;
   const double* w = A.wout + (size_t)a * n;
   const double* mult = A.mult + (size_t)a * (2 + G);
@@ -664,14 +692,25 @@ __global__ __launch_bounds__(256) void polish_check_kernel(PolishArgs A, fqp_res
 
   double sw = 0.0, turn = 0.0, gmax = 0.0, mumax = 0.0, dmax = 0.0, box = 0.0, snapm = 0.0,
          obj = 0.0;
-  for (int i = tid; i < n; i += 256) {
+  const int BS1 = k + 1;
+  for (int base = 0; base < n; base += 256) {
+    __syncthreads();
+    const int rows = min(256, n - base);
+    for (int e = tid; e < rows * k; e += 256) {
+      const int rr = e / k, j = e % k;
+      sBrow[rr * BS1 + j] = A.Bt[(size_t)(base + rr) * A.kp + j];
+    }
+    __syncthreads();
+    const int i = base + tid;
+    if (i >= n) continue;
     RowData r = row_data(A, a, i);
     Geom g;
     make_geom(g, r.el, lbf, ubf, r.w0, kap, phi, r.ti, A.tax_brk, A.tax_slope);
     const double lb = r.el ? (double)lbf : 0.0, ub = r.el ? (double)ubf : 0.0;
     const double wi = w[i];
     double sig = 0.0;
-    for (int j = 0; j < k; ++j) sig += (double)A.Bt[(size_t)i * A.kp + j] * s_y[j];
+    const float* brow = sBrow + tid * BS1;
+    for (int j = 0; j < k; ++j) sig += (double)brow[j] * s_y[j];
     sig += (double)A.d[i] * wi;
     const double mui = A.mu[(size_t)a * n + i];
     double gi = gam * sig - mui - nu;
@@ -699,23 +738,25 @@ __global__ __launch_bounds__(256) void polish_check_kernel(PolishArgs A, fqp_res
     obj += 0.5 * gam * wi * sig - mui * wi + tc;
     // refinement proposal (applied only if the pattern fails)
     const int c = code_r[i];
+    code[i] = (int8_t)c;
     if (g.np > 1) {
       const double tolm = A.eps_dual * 0.1;
       if (c & 1) {
         const int q = c >> 1;
-        if (wi > g.pt[q + 1]) code[i] = (int8_t)(2 * (q + 1));
-        else if (wi < g.pt[q]) code[i] = (int8_t)(2 * q);
+        if (wi > g.pt[q + 1]) { code[i] = (int8_t)(2 * (q + 1)); ++changed; }
+        else if (wi < g.pt[q]) { code[i] = (int8_t)(2 * q); ++changed; }
       } else {
         // move off a point when -g lies outside its subdifferential
         const int j = c >> 1;
         double l2, h2, sn2;
         subdiff(g, g.pt[j], lam, lb, ub, l2, h2, sn2);
         const double sc = fmax(fabs(mui), 1e-12);
-        if (t > h2 + tolm * sc && j + 1 < g.np) code[i] = (int8_t)(2 * j + 1);
-        else if (t < l2 - tolm * sc && j > 0) code[i] = (int8_t)(2 * (j - 1) + 1);
+        if (t > h2 + tolm * sc && j + 1 < g.np) { code[i] = (int8_t)(2 * j + 1); ++changed; }
+        else if (t < l2 - tolm * sc && j > 0) { code[i] = (int8_t)(2 * (j - 1) + 1); ++changed; }
       }
     }
   }
+  if (changed) atomicAdd(&s_changed, changed);
   sw = bsum<double>(sw, shd);
   turn = bsum<double>(turn, shd);
   obj = bsum<double>(obj, shd);
@@ -767,18 +808,21 @@ __global__ __launch_bounds__(256) void polish_check_kernel(PolishArgs A, fqp_res
       R.status[a] = gates ? FQP_FEASIBLE_UNCERTIFIED : FQP_MAX_ITER;
     } else {
       // bands / cap refinement
+      int nchg = s_changed;
       for (int g = 0; g < G; ++g) {
         const double lo = A.blo[(size_t)a * G + g], hi = A.bhi[(size_t)a * G + g];
         const bool act = band_active(ps, g), up = band_upper(ps, g);
         const double lg = mult[2 + g];
-        if (act && ((up && lg < 0.0) || (!up && lg > 0.0))) set_band(ps, g, false, false);
-        else if (!act && s_gs[g] > hi + 0.1 * A.eps_prim) set_band(ps, g, true, true);
-        else if (!act && s_gs[g] < lo - 0.1 * A.eps_prim) set_band(ps, g, true, false);
+        if (act && ((up && lg < 0.0) || (!up && lg > 0.0))) { set_band(ps, g, false, false); ++nchg; }
+        else if (!act && s_gs[g] > hi + 0.1 * A.eps_prim) { set_band(ps, g, true, true); ++nchg; }
+        else if (!act && s_gs[g] < lo - 0.1 * A.eps_prim) { set_band(ps, g, true, false); ++nchg; }
       }
       if (isfinite(tauf)) {
-        if (ps[PS_CAP] && lam < 0.0) ps[PS_CAP] = 0;
-        else if (!ps[PS_CAP] && turn > tau + 0.1 * A.eps_prim) ps[PS_CAP] = 1;
+        if (ps[PS_CAP] && lam < 0.0) { ps[PS_CAP] = 0; ++nchg; }
+        else if (!ps[PS_CAP] && turn > tau + 0.1 * A.eps_prim) { ps[PS_CAP] = 1; ++nchg; }
       }
+      // no proposal: further rounds on this iterate cannot help
+      if (nchg == 0) ps[PS_STALL] = 1;
     }
   }
   __syncthreads();
@@ -786,6 +830,9 @@ __global__ __launch_bounds__(256) void polish_check_kernel(PolishArgs A, fqp_res
     if (R.lam_band && G) {
       for (int g = tid; g < G; g += 256) R.lam_band[(size_t)a * G + g] = mult[2 + g];
     }
+  } else {
+    // the pattern failed: adopt the proposals for the next round
+    for (int i = tid; i < n; i += 256) code_r[i] = code[i];
   }
 }
 
@@ -804,7 +851,11 @@ hipError_t launch_polish_solve(const PolishArgs& A, hipStream_t st) {
 
 hipError_t launch_polish_check_r(const PolishArgs& A, const fqp_result& R, int final_pass,
                                  hipStream_t st) {
-  hipLaunchKernelGGL(polish_check_kernel, dim3(A.m_total), dim3(256), 0, st, A, R, final_pass);
+  const size_t smem = sizeof(float) * 256 * (size_t)(A.k + 1);
+  hipError_t e = hipFuncSetAttribute((const void*)polish_check_kernel,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(polish_check_kernel, dim3(A.m_total), dim3(256), smem, st, A, R, final_pass);
   return hipGetLastError();
 }
 

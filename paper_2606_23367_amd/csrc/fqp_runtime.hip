@@ -130,6 +130,9 @@ struct fqp_handle {
   std::map<std::string, DevBuf> bufs;
   size_t total_bytes = 0;
   bool configured = false;
+  // context of the last successful solve, for fqp_adjoint_batch
+  bool have_last = false;
+  AdjArgs last{};
 
   template <typename T>
   T* get(const char* name, size_t count, fqp_error* e) {
@@ -276,6 +279,7 @@ extern "C" fqp_error fqp_solve_batch(fqp_handle* h, const fqp_universe* U, const
   h->err.clear();
   h->stats = fqp_stats{};
   auto t_start = std::chrono::steady_clock::now();
+  h->have_last = false;
   if (!U || !P || !R) { h->err = "null universe/book/result"; return FQP_ERR_INVALID_ARG; }
   fqp_settings S;
   if (S_in) S = *S_in; else fqp_default_settings(&S);
@@ -398,6 +402,7 @@ extern "C" fqp_error fqp_solve_batch(fqp_handle* h, const fqp_universe* U, const
   WS(act, int, "act", (size_t)m);
   WS(m_act, int, "m_act", 1);
   WS(code, int8_t, "code", (size_t)m * n);
+  WS(code_next, int8_t, "code_next", (size_t)m * n);
   WS(flist, int32_t, "flist", (size_t)m * n);
   const size_t wks = polish_wk_stride(k, G);
   WS(wk, double, "polish_wk", (size_t)m * wks);
@@ -469,7 +474,7 @@ extern "C" fqp_error fqp_solve_batch(fqp_handle* h, const fqp_universe* U, const
   pa.hold_ptr = hold_ptr; pa.hold_w0 = hold_w0; pa.hold_tax = hold_tax;
   pa.tax_brk = P->tax_brk; pa.tax_slope = P->tax_slope; pa.par = par; pa.zb = zb; pa.vb = vb;
   pa.blo = G ? P->band_lo : nullptr; pa.bhi = G ? P->band_hi : nullptr;
-  pa.code = code; pa.flist = flist; pa.wk = wk; pa.wk_stride = wks; pa.wout = R->w;
+  pa.code = code; pa.code_next = code_next; pa.flist = flist; pa.wk = wk; pa.wk_stride = wks; pa.wout = R->w;
   pa.mult = mult; pa.pstate = pstate;
   pa.eps_prim = S.eps_prim; pa.eps_dual = S.eps_dual; pa.eps_comp = S.eps_comp;
 
@@ -548,6 +553,7 @@ extern "C" fqp_error fqp_solve_batch(fqp_handle* h, const fqp_universe* U, const
     if (be != FQP_OK) return be;
     done_iters += count;
     // polish + certification rounds
+    pa.nf_gate = std::max(4 * k + 64, n / 8 + 4 * k);
     for (int r = 0; r < S.polish_rounds; ++r) {
       pa.first_round = (r == 0);
       HIP_CHECK(launch_polish_solve(pa, st));
@@ -567,6 +573,7 @@ extern "C" fqp_error fqp_solve_batch(fqp_handle* h, const fqp_universe* U, const
   if (active > 0) {
     // last pattern from the current iterate, diagnostics, final statuses
     pa.first_round = 1;
+    pa.nf_gate = 0;
     HIP_CHECK(launch_polish_solve(pa, st));
     HIP_CHECK(launch_polish_check_r(pa, *R, 1, st));
     if (timed_out) {
@@ -588,7 +595,45 @@ extern "C" fqp_error fqp_solve_batch(fqp_handle* h, const fqp_universe* U, const
     h->stats.account_iters += it_h[a];
   }
   h->stats.iterations = done_iters;
+  {
+    AdjArgs& L = h->last;
+    L = AdjArgs{};
+    L.n = n; L.k = k; L.G = G; L.kp = kp; L.m = m;
+    L.Bt = Bt; L.f = U->f; L.d = U->d; L.group = G ? U->group : nullptr; L.w0in = P->w0;
+    L.par = par; L.status = R->status; L.pstate = pstate; L.flist = flist; L.code = code;
+    L.w = R->w; L.wk = wk; L.wk_stride = wks;
+    h->have_last = true;
+  }
   h->stats.total_ms =
       std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+  return FQP_OK;
+}
+
+extern "C" fqp_error fqp_adjoint_batch(fqp_handle* h, const double* dL_dw, double* dL_dmu,
+                                       double* dL_dB, void* stream_v) {
+  if (!h) return FQP_ERR_INVALID_ARG;
+  if (!h->have_last) { h->err = "no solve to differentiate"; return FQP_ERR_INVALID_ARG; }
+  if (!dL_dw || !dL_dmu || !dL_dB) { h->err = "null gradient pointer"; return FQP_ERR_INVALID_ARG; }
+  int prev_dev = 0;
+  (void)hipGetDevice(&prev_dev);
+  HIP_CHECK(hipSetDevice(h->device));
+  struct Restore {
+    int d;
+    ~Restore() { (void)hipSetDevice(d); }
+  } restore{prev_dev};
+  hipStream_t caller = static_cast<hipStream_t>(stream_v);
+  hipStream_t st = h->stream;
+  HIP_CHECK(hipEventRecord(h->ev_in, caller));
+  HIP_CHECK(hipStreamWaitEvent(st, h->ev_in, 0));
+  fqp_error e = FQP_OK;
+  AdjArgs A = h->last;
+  WS(yvw, double, "adj_yvw", (size_t)A.m * 2 * A.k);
+  A.yvw = yvw;
+  A.dLdw = dL_dw;
+  A.dmu = dL_dmu;
+  A.dB = dL_dB;
+  HIP_CHECK(launch_adjoint(A, st));
+  HIP_CHECK(hipEventRecord(h->ev_out, st));
+  HIP_CHECK(hipStreamWaitEvent(caller, h->ev_out, 0));
   return FQP_OK;
 }

@@ -168,7 +168,28 @@ class Solver:
             raise RuntimeError(
                 f"fqp_solve_batch failed ({self.lib.fqp_error_string(rc).decode()}):"
                 f" {self.lib.fqp_last_error(self.h).decode()}")
+        self._last_shape = (m, n, P.k)
+        self._last_keep = (P, out)        # buffers the adjoint reads
         return out
+
+    def adjoint(self, dL_dw: torch.Tensor, stream=None):
+        """dL/dmu [m, n] and dL/dB [n, k] (float64) of a loss with gradient
+        dL_dw through the last solve on this handle."""
+        if not hasattr(self, "_last_shape"):
+            raise RuntimeError("adjoint() needs a preceding solve()")
+        m, n, k = self._last_shape
+        dev = dL_dw.device
+        g = dL_dw.detach().to(torch.float64).contiguous()
+        dmu = torch.empty((m, n), dtype=torch.float64, device=dev)
+        dB = torch.empty((n, k), dtype=torch.float64, device=dev)
+        if stream is None:
+            stream = torch.cuda.current_stream(dev)
+        rc = self.lib.fqp_adjoint_batch(self.h, _ptr(g), _ptr(dmu), _ptr(dB),
+                                        ctypes.c_void_p(stream.cuda_stream))
+        if rc != 0:
+            raise RuntimeError(
+                f"fqp_adjoint_batch failed: {self.lib.fqp_last_error(self.h).decode()}")
+        return dmu, dB
 
     def stats(self) -> dict:
         st = _lib.Stats()
@@ -181,3 +202,31 @@ def solve_batch(P: DeviceProblem, solver: Optional[Solver] = None, **settings):
     s = solver or Solver(P.mu.device.index or 0)
     out = s.solve(P, **settings)
     return out, s.stats()
+
+
+class FqpFunction(torch.autograd.Function):
+    """w = argmin of the build's Eq. 1 instance for every account, as a
+    differentiable function of the returns mu [m, n] and the factor loadings
+    B [n, k]; backward runs the KKT adjoint kernels (dL/dmu, dL/dB)."""
+
+    @staticmethod
+    def forward(ctx, mu, B, problem, solver, settings):
+        from dataclasses import replace
+        P = replace(problem, mu=mu.detach().to(torch.float32).contiguous(),
+                    B=B.detach().to(torch.float32).contiguous())
+        out = solver.solve(P, **settings)
+        ctx.solver = solver
+        ctx.keep = (P, out)
+        ctx.dtypes = (mu.dtype, B.dtype)
+        return out["w"].clone()
+
+    @staticmethod
+    def backward(ctx, grad_w):
+        dmu, dB = ctx.solver.adjoint(grad_w)
+        return dmu.to(ctx.dtypes[0]), dB.to(ctx.dtypes[1]), None, None, None
+
+
+def solve_differentiable(mu, B, problem: DeviceProblem, solver: Solver,
+                         **settings):
+    """Autograd entry: weights of every account as a function of (mu, B)."""
+    return FqpFunction.apply(mu, B, problem, solver, settings)
