@@ -30,13 +30,15 @@ SETTINGS = dict(rho=5.0)
 
 
 def algorithmic_bytes(uni, book, iters):
-    """Per account-iteration: state z, u read + written (16 N), returns read
-    (4 N), eligibility bits (ceil(N/8)), held records (w0 + tax lots, 32 B
-    each); per launch: B read once (4 N k) and d (4 N)."""
+    """Algorithmic bytes of the timed kernel (the PROJECT pass: back-
+    projection, relaxation and the write of the new ADMM state).  Per
+    account-iteration: state v read + written (8 N), returns read (4 N),
+    eligibility bits (ceil(N/8)), held records (w0 + 7 tax-lot floats,
+    32 B each); per launch: B read once (4 N k) and d (4 N)."""
     import numpy as np
     n, k = uni.n, uni.k
     held = np.count_nonzero(book.w0, axis=1)
-    per_acc = 20.0 * n + np.ceil(n / 8.0) + 32.0 * held
+    per_acc = 12.0 * n + np.ceil(n / 8.0) + 32.0 * held
     return float(np.sum(iters * per_acc)), float(4.0 * n * k + 4.0 * n)
 
 
@@ -154,8 +156,8 @@ def main():
             "unit": "GB/s",
             "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
             "traffic": None,
-            "kernel": "iter_kernel (fused back-projection, prox, dual "
-                      "update, next contraction)",
+            "kernel": "iter_kernel<PROJECT> (MFMA back-projection B~p, "
+                      "x-update, over-relaxation, new ADMM state)",
             "avg_launch_us": kernel_ms * 1e3 / max(launches, 1),
         },
     }

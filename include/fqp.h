@@ -114,7 +114,6 @@ typedef struct fqp_settings {
   float rho;             /* ADMM penalty on the asset split (<= 0: auto)  */
   float rho_band;        /* ADMM penalty on the band split (<= 0: auto)   */
   float alpha;           /* over-relaxation in (0, 2)                     */
-  float cap_beta;        /* damping of the turnover-cap multiplier update */
   int32_t polish_rounds; /* active-set refinement rounds per polish       */
   int32_t use_graph;     /* capture each block of iterations in a hipGraph */
   int32_t profile;       /* time every fused iteration launch with events */

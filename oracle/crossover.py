@@ -96,6 +96,94 @@ def _solve_reduced(P: AccountProblem, F, rhs, C, h, eta0):
     return Hr - HC @ eta, eta
 
 
+def _point_slopes(P: AccountProblem, i, x):
+    """(lo0, s_lo, hi0, s_hi): the subdifferential of phi_i + lam|.-w0| +
+    N_box at the fixed point x is [lo0 + s_lo lam, hi0 + s_hi lam]
+    (lo0 = -inf / hi0 = +inf at a bound)."""
+    lb, ub = (P.lb, P.ub) if P.eligible[i] else (0.0, 0.0)
+    kinks, slopes = kinks_and_slopes(P, i, 0.0)
+    has_phi = P.kappa > 0 or np.isfinite(P.tau) or i in set(int(t) for t in P.tax_asset)
+    if not has_phi:
+        kinks, slopes = np.zeros(0), np.zeros(1)
+    side = lambda q: (-1.0 if q < len(kinks) else 1.0) if len(kinks) else 0.0
+    hit = [j for j, c in enumerate(kinks) if c == x]
+    if hit:
+        j = hit[0]
+        lo0, s_lo, hi0, s_hi = slopes[j], side(j), slopes[j + 1], side(j + 1)
+    else:
+        q = int(np.searchsorted(kinks, x)) if len(kinks) else 0
+        lo0, s_lo, hi0, s_hi = slopes[q], side(q), slopes[q], side(q)
+    if x <= lb:
+        lo0, s_lo = -np.inf, 0.0
+    if x >= ub:
+        hi0, s_hi = np.inf, 0.0
+    return lo0, s_lo, hi0, s_hi
+
+
+def refine_multipliers(P: AccountProblem, w, fixed, C_rows, act, cap_on, eta,
+                       sweeps=3):
+    """Move eta = (-nu, band multipliers of the active bands, lam_cap) inside
+    the null space of the free-row equations so that every fixed coordinate's
+    stationarity interval holds.  Along one null direction n the conditions
+    are linear inequalities in the step s; the step is the point of their
+    feasible interval nearest to 0 (pulled inside by a small margin).  The
+    free-row equations are untouched (C_F^T n = 0)."""
+    nc = len(eta)
+    if C_rows.shape[1]:
+        _, sv, vt = np.linalg.svd(C_rows.T, full_matrices=True)
+        rank = int(np.sum(sv > 1e-10 * max(sv.max(), 1.0)))
+        N = vt[rank:].T
+    else:
+        N = np.eye(nc)
+    if N.shape[1] == 0:
+        return eta
+    G = P.n_groups
+    band_col = {g_: 1 + j for j, (g_, _) in enumerate(act)}
+    up = {g_: (bnd == P.band_hi[g_]) for g_, bnd in act}
+    base = P.gamma * (P.B @ (P.f * (P.B.T @ w)) + P.d * w) - P.mu
+    rows = [i for i in range(P.n) if fixed[i] and P.eligible[i]]
+    geo = {i: _point_slopes(P, i, w[i]) for i in rows}
+    for _ in range(sweeps):
+        for q in range(N.shape[1]):
+            n = N[:, q]
+            lam = eta[-1] if cap_on else 0.0
+            n_c = n[-1] if cap_on else 0.0
+            L, U = -np.inf, np.inf
+
+            def add(alpha, beta):
+                nonlocal L, U
+                if alpha > 1e-300:
+                    U = min(U, beta / alpha)
+                elif alpha < -1e-300:
+                    L = max(L, beta / alpha)
+            for i in rows:
+                bc = band_col.get(int(P.group[i])) if G else None
+                T = -(base[i] + eta[0] + (eta[bc] if bc else 0.0))
+                a = n[0] + (n[bc] if bc else 0.0)
+                lo0, s_lo, hi0, s_hi = geo[i]
+                if np.isfinite(lo0):      # lo0 + s_lo (lam + s n_c) <= T - a s
+                    add(a + s_lo * n_c, T - lo0 - s_lo * lam)
+                if np.isfinite(hi0):      # T - a s <= hi0 + s_hi (lam + s n_c)
+                    add(-(a + s_hi * n_c), hi0 + s_hi * lam - T)
+            if cap_on:                    # lam + s n_c >= 0
+                add(-n_c, lam)
+            for g_, col in band_col.items():
+                if up[g_]:
+                    add(-n[col], eta[col])
+                else:
+                    add(n[col], -eta[col])
+            if L <= U:
+                s = min(max(0.0, L), U)
+                if np.isfinite(L) and np.isfinite(U):
+                    mid = 0.5 * (L + U)
+                    s = s + 1e-3 * (mid - s)
+            else:
+                s = 0.5 * (L + U)
+            if np.isfinite(s):
+                eta = eta + s * n
+    return eta
+
+
 def crossover_once(P: AccountProblem, w, tol, tol_con, nu0=0.0,
                    lam_band0=None, lam_cap0=0.0):
     n = P.n
@@ -138,6 +226,7 @@ def crossover_once(P: AccountProblem, w, tol, tol_con, nu0=0.0,
     wF, eta = _solve_reduced(P, F, rhs, C, h, np.asarray(eta0, float))
     wf = val.copy()
     wf[F] = wF
+    eta = refine_multipliers(P, wf, fixed, C, act, cap_on, eta)
     nu = -eta[0]
     lam_band = np.zeros(G)
     for j, (g_, _) in enumerate(act):

@@ -44,7 +44,7 @@ class Settings(ctypes.Structure):
                 ("eps_comp", c_double), ("max_iter", c_int32),
                 ("check_every", c_int32), ("rho", c_float),
                 ("rho_band", c_float), ("alpha", c_float),
-                ("cap_beta", c_float), ("polish_rounds", c_int32),
+                ("polish_rounds", c_int32),
                 ("use_graph", c_int32), ("profile", c_int32),
                 ("time_limit_ms", c_double)]
 

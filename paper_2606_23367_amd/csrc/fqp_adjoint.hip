@@ -171,19 +171,9 @@ __global__ __launch_bounds__(256) void adjoint_solve_kernel(AdjArgs A) {
     }
     __syncthreads();
   }
-  for (int col = tid; col < ncol; col += 256) {
-    for (int i = 0; i < k; ++i) {
-      double s = Waug[i * ncol + col];
-      for (int l = 0; l < i; ++l) s -= Kf[i * k + l] * Y[l * ncol + col];
-      Y[i * ncol + col] = s / Kf[i * k + i];
-    }
-    for (int i = k - 1; i >= 0; --i) {
-      double s = Y[i * ncol + col];
-      for (int l = i + 1; l < k; ++l) s -= Kf[l * k + i] * Y[l * ncol + col];
-      Y[i * ncol + col] = s / Kf[i * k + i];
-    }
-  }
+  for (int e = tid; e < k * ncol; e += 256) Y[e] = Waug[e];
   __syncthreads();
+  chol_solve_cols(Kf, k, Y, ncol);
   for (int e = tid; e < nc * ncol; e += 256) {
     const int p = e / ncol, q = e % ncol;
     double s = CV[p * ncol + q];
@@ -192,43 +182,50 @@ __global__ __launch_bounds__(256) void adjoint_solve_kernel(AdjArgs A) {
   }
   __syncthreads();
   if (tid == 0) {
-    // (S + eps I) xi = C H^-1 c   (h = 0); the null-space part of xi does
-    // not change v
+    // S xi = C H^-1 c (h = 0), S PSD: pivoted Cholesky, the components the
+    // free rows do not pin are set to 0 (they do not change v)
     double* Sm = CV;
+    int perm[kMaxG + 3];
     double dmax = 0.0;
-    for (int p = 0; p < nc; ++p) dmax = fmax(dmax, fabs(S[p * ncol + p]));
-    const double eps = 1e-13 * fmax(dmax, 1e-300);
     for (int p = 0; p < nc; ++p) {
-      xi[p] = S[p * ncol + nc];
-      for (int q = 0; q < nc; ++q) Sm[p * nc + q] = S[p * ncol + q] + (p == q ? eps : 0.0);
+      perm[p] = p;
+      dmax = fmax(dmax, S[p * ncol + p]);
+      for (int q = 0; q < nc; ++q) Sm[p * nc + q] = S[p * ncol + q];
     }
-    bool ok = true;
-    for (int j = 0; j < nc && ok; ++j) {
-      double s = Sm[j * nc + j];
-      for (int l = 0; l < j; ++l) s -= Sm[j * nc + l] * Sm[j * nc + l];
-      if (!(s > 0.0)) { ok = false; break; }
-      s = sqrt(s);
-      Sm[j * nc + j] = s;
-      for (int i = j + 1; i < nc; ++i) {
-        double t = Sm[i * nc + j];
-        for (int l = 0; l < j; ++l) t -= Sm[i * nc + l] * Sm[j * nc + l];
-        Sm[i * nc + j] = t / s;
+    int rank = 0;
+    for (int j = 0; j < nc; ++j) {
+      int best = j;
+      for (int p = j + 1; p < nc; ++p)
+        if (Sm[p * nc + p] > Sm[best * nc + best]) best = p;
+      if (!(Sm[best * nc + best] > 1e-12 * dmax)) break;
+      if (best != j) {
+        for (int q = 0; q < nc; ++q) { double t = Sm[j * nc + q]; Sm[j * nc + q] = Sm[best * nc + q]; Sm[best * nc + q] = t; }
+        for (int q = 0; q < nc; ++q) { double t = Sm[q * nc + j]; Sm[q * nc + j] = Sm[q * nc + best]; Sm[q * nc + best] = t; }
+        int t = perm[j]; perm[j] = perm[best]; perm[best] = t;
       }
+      const double djj = sqrt(Sm[j * nc + j]);
+      Sm[j * nc + j] = djj;
+      for (int i = j + 1; i < nc; ++i) Sm[i * nc + j] /= djj;
+      for (int i = j + 1; i < nc; ++i)
+        for (int l = j + 1; l <= i; ++l) {
+          Sm[i * nc + l] -= Sm[i * nc + j] * Sm[l * nc + j];
+          Sm[l * nc + i] = Sm[i * nc + l];
+        }
+      ++rank;
     }
-    if (ok) {
-      for (int i = 0; i < nc; ++i) {
-        double s = xi[i];
-        for (int l = 0; l < i; ++l) s -= Sm[i * nc + l] * xi[l];
-        xi[i] = s / Sm[i * nc + i];
-      }
-      for (int i = nc - 1; i >= 0; --i) {
-        double s = xi[i];
-        for (int l = i + 1; l < nc; ++l) s -= Sm[l * nc + i] * xi[l];
-        xi[i] = s / Sm[i * nc + i];
-      }
-    } else {
-      for (int p = 0; p < nc; ++p) xi[p] = 0.0;
+    double x[kMaxG + 3];
+    for (int j = 0; j < nc; ++j) x[j] = (j < rank) ? S[perm[j] * ncol + nc] : 0.0;
+    for (int i = 0; i < rank; ++i) {
+      double t = x[i];
+      for (int l = 0; l < i; ++l) t -= Sm[i * nc + l] * x[l];
+      x[i] = t / Sm[i * nc + i];
     }
+    for (int i = rank - 1; i >= 0; --i) {
+      double t = x[i];
+      for (int l = i + 1; l < rank; ++l) t -= Sm[l * nc + i] * x[l];
+      x[i] = t / Sm[i * nc + i];
+    }
+    for (int j = 0; j < nc; ++j) xi[perm[j]] = x[j];
   }
   __syncthreads();
   for (int j = tid; j < k; j += 256) {

@@ -80,4 +80,29 @@ __device__ __forceinline__ int popc_below(uint32_t word, int bit) {
   return __popc(word & ((1u << bit) - 1u));
 }
 
+// Y <- L^-T L^-1 Y for the k x ncol matrix Y (global), L lower in LDS.
+__device__ inline void chol_solve_cols(const double* L, int k, double* Y, int ncol) {
+  const int tid = threadIdx.x;
+  for (int j = 0; j < k; ++j) {
+    const double djj = L[j * k + j];
+    for (int c = tid; c < ncol; c += 256) Y[j * ncol + c] /= djj;
+    __syncthreads();
+    for (int e = tid; e < (k - j - 1) * ncol; e += 256) {
+      const int i = j + 1 + e / ncol, c = e % ncol;
+      Y[i * ncol + c] -= L[i * k + j] * Y[j * ncol + c];
+    }
+    __syncthreads();
+  }
+  for (int j = k - 1; j >= 0; --j) {
+    const double djj = L[j * k + j];
+    for (int c = tid; c < ncol; c += 256) Y[j * ncol + c] /= djj;
+    __syncthreads();
+    for (int e = tid; e < j * ncol; e += 256) {
+      const int i = e / ncol, c = e % ncol;
+      Y[i * ncol + c] -= L[j * k + i] * Y[j * ncol + c];
+    }
+    __syncthreads();
+  }
+}
+
 }  // namespace fqp

@@ -131,20 +131,30 @@ __global__ void kfactor_kernel(int k, int G, int kp, int nparts,
     }
     __syncthreads();
   }
-  // inverse: solve L L^T X = I column by column (threads over columns)
-  for (int col = threadIdx.x; col < kg; col += blockDim.x) {
-    for (int i = 0; i < kg; ++i) {         // forward
-      double s = (i == col) ? 1.0 : 0.0;
-      for (int l = 0; l < i; ++l) s -= L[i * kg + l] * X[l * kg + col];
-      X[i * kg + col] = s / L[i * kg + i];
-    }
-    for (int i = kg - 1; i >= 0; --i) {    // backward
-      double s = X[i * kg + col];
-      for (int l = i + 1; l < kg; ++l) s -= L[l * kg + i] * X[l * kg + col];
-      X[i * kg + col] = s / L[i * kg + i];
-    }
-  }
+  // inverse: L L^T X = I by right-looking forward and backward sweeps, every
+  // thread updating a slice of the trailing block at each step
+  for (int e = threadIdx.x; e < kg * kg; e += blockDim.x) X[e] = (e / kg == e % kg) ? 1.0 : 0.0;
   __syncthreads();
+  for (int j = 0; j < kg; ++j) {
+    const double djj = L[j * kg + j];
+    for (int c = threadIdx.x; c < kg; c += blockDim.x) X[j * kg + c] /= djj;
+    __syncthreads();
+    for (int e = threadIdx.x; e < (kg - j - 1) * kg; e += blockDim.x) {
+      const int i = j + 1 + e / kg, c = e % kg;
+      X[i * kg + c] -= L[i * kg + j] * X[j * kg + c];
+    }
+    __syncthreads();
+  }
+  for (int j = kg - 1; j >= 0; --j) {
+    const double djj = L[j * kg + j];
+    for (int c = threadIdx.x; c < kg; c += blockDim.x) X[j * kg + c] /= djj;
+    __syncthreads();
+    for (int e = threadIdx.x; e < j * kg; e += blockDim.x) {
+      const int i = e / kg, c = e % kg;
+      X[i * kg + c] -= L[j * kg + i] * X[j * kg + c];
+    }
+    __syncthreads();
+  }
   // q = K^-1 c, sigma1 = 1^T Delta^-1 1 - c^T q
   for (int j = threadIdx.x; j < kg; j += blockDim.x) {
     double s = 0.0;
@@ -172,9 +182,65 @@ __global__ void kfactor_kernel(int k, int G, int kp, int nparts,
 }
 
 // ---------------------------------------------------------------------------
-// the fused iteration
+// the fused passes
+//
+// The ADMM state kept in HBM is v = xh + u per (account, asset).  With the
+// exact cap multiplier lam* of v, z = prox(v; lam*) and u = v - z are
+// recomputed wherever they are needed, so one iteration is
+//   CONTRACT  z, u from v; r = mu + rho (z - u); t = B~^T Delta^-1 r   (MFMA)
+//   k-solve   nu, p from t (factor space)
+//   PROJECT   z, u from v; x = Delta^-1 (r + nu - B~ p) (MFMA);
+//             v <- alpha x + (1 - alpha) z + u
+//   cap       lam* of the new v (per account, exact)
 // ---------------------------------------------------------------------------
-template <int NCH, bool INIT>
+enum PassMode { MODE_CONTRACT = 0, MODE_PROJECT = 1 };
+
+struct RowInfo {
+  float lb, ub, w0;
+  int ti;
+};
+
+__device__ __forceinline__ float prox_row(const RowInfo& ri, float v, float th, float irho,
+                                          const float* tax_brk, const float* tax_slope,
+                                          bool* at_kink) {
+  float zn;
+  if (ri.ti >= 0) {
+    TaxLots t;
+    const int ti = ri.ti;
+    t.b1 = tax_brk[3 * ti]; t.b2 = tax_brk[3 * ti + 1]; t.b3 = tax_brk[3 * ti + 2];
+    t.s0 = tax_slope[4 * ti]; t.s1 = tax_slope[4 * ti + 1];
+    t.s2 = tax_slope[4 * ti + 2]; t.s3 = tax_slope[4 * ti + 3];
+    zn = prox_taxed(v, ri.w0, th, irho, t, ri.lb, ri.ub);
+    if (at_kink)
+      *at_kink = (zn == ri.w0) || (zn == ri.w0 - t.b1) || (zn == ri.w0 - t.b2) ||
+                 (zn == ri.w0 - t.b3) || zn <= ri.lb || zn >= ri.ub;
+  } else {
+    zn = prox_plain(v, ri.w0, th, ri.lb, ri.ub);
+    if (at_kink) *at_kink = (zn == ri.w0) || zn <= ri.lb || zn >= ri.ub;
+  }
+  return zn;
+}
+
+template <typename Args>
+__device__ __forceinline__ RowInfo row_info(const Args& A, int a, int row, float lbp, float ubp) {
+  RowInfo ri;
+  const int wd = row >> 5, b = row & 31;
+  const uint32_t ew = A.elig ? A.elig[(size_t)a * A.W + wd] : 0xffffffffu;
+  const bool el = (ew >> b) & 1u;
+  ri.lb = el ? lbp : 0.f;
+  ri.ub = el ? ubp : 0.f;
+  const uint32_t hw = A.hold[(size_t)a * A.W + wd];
+  ri.w0 = 0.f;
+  ri.ti = -1;
+  if ((hw >> b) & 1u) {
+    const int idx = A.hold_ptr[a] + A.hold_pre[(size_t)a * A.W + wd] + popc_below(hw, b);
+    ri.w0 = A.hold_w0[idx];
+    ri.ti = A.hold_tax[idx];
+  }
+  return ri;
+}
+
+template <int NCH, int MODE>
 __global__ __launch_bounds__(256, 2) void iter_kernel(IterArgs A) {
   constexpr int kp = NCH * 32;
   constexpr int BS = kp + 1;            // LDS row stride (odd: no conflicts)
@@ -202,7 +268,7 @@ __global__ __launch_bounds__(256, 2) void iter_kernel(IterArgs A) {
     int a = Aid[j];
     Par[e] = (a >= 0) ? A.par[(size_t)a * kNPar + p] : 0.f;
   }
-  if (!INIT) {
+  if (MODE == MODE_PROJECT) {
     for (int e = tid; e < kTM * kp; e += 256) {
       int j = e / kp, c = e % kp;
       int a = Aid[j];
@@ -215,13 +281,12 @@ __global__ __launch_bounds__(256, 2) void iter_kernel(IterArgs A) {
   for (int c = 0; c < NCH; ++c)
 #pragma unroll
     for (int r = 0; r < 16; ++r) T[c][r] = 0.f;
-  float st_rp[16], st_rd[16], st_tv[16], st_nf[16];
+  float st_rp[16];
 #pragma unroll
-  for (int r = 0; r < 16; ++r) st_rp[r] = st_rd[r] = st_tv[r] = st_nf[r] = 0.f;
+  for (int r = 0; r < 16; ++r) st_rp[r] = 0.f;
 
   float* Rw = Rt + w * 32 * 33;
   const int row_begin = blockIdx.x * A.rows_per_wg;
-  const int W = A.W;
 
   for (int ch = 0; ch < A.chunks_per_wg; ++ch) {
     const int r0 = row_begin + ch * kRowsPerChunk;
@@ -244,7 +309,7 @@ __global__ __launch_bounds__(256, 2) void iter_kernel(IterArgs A) {
     floatx16 X;
 #pragma unroll
     for (int r = 0; r < 16; ++r) X[r] = 0.f;
-    if (!INIT) {
+    if (MODE == MODE_PROJECT) {
       const float* pa = Ps + l32 * BS + hi;
       const float* pb = Bs + (32 * w + l32) * BS + hi;
 #pragma unroll 8
@@ -260,59 +325,31 @@ __global__ __launch_bounds__(256, 2) void iter_kernel(IterArgs A) {
       if (a >= 0 && row_ok) {
         const float* pr = Par + m * kNPar;
         const float rho = pr[P_RHO];
+        const float irho = 1.f / rho;
         const float Delta = pr[P_GAMMA] * d_i + rho;
         const size_t off = (size_t)a * n + row;
         const float mu = A.mu[off];
-        if (INIT) {
-          Rp = mu / Delta;
+        const float vv = A.v[off];
+        const RowInfo ri = row_info(A, a, row, pr[P_LB], pr[P_UB]);
+        const float th = (pr[P_KAPPA] + pr[P_LAM]) * irho;
+        const float z = prox_row(ri, vv, th, irho, A.tax_brk, A.tax_slope, nullptr);
+        const float u = vv - z;
+        const float r0v = mu + rho * (z - u);
+        if (MODE == MODE_CONTRACT) {
+          Rp = r0v / Delta;
         } else {
-          const float z = A.z[off], u = A.u[off];
-          const float x = (mu + rho * (z - u) + pr[P_NU] - X[r]) / Delta;
+          const float x = (r0v + pr[P_NU] - X[r]) / Delta;
           const float alpha = pr[P_ALPHA];
-          const float v = alpha * x + (1.f - alpha) * z + u;
-          const int wd = row >> 5;
-          const uint32_t ew = A.elig ? A.elig[(size_t)a * W + wd] : 0xffffffffu;
-          const bool el = (ew >> l32) & 1u;
-          const float lb = el ? pr[P_LB] : 0.f, ub = el ? pr[P_UB] : 0.f;
-          const uint32_t hw = A.hold[(size_t)a * W + wd];
-          float w0 = 0.f;
-          int ti = -1;
-          if ((hw >> l32) & 1u) {
-            int idx = A.hold_ptr[a] + A.hold_pre[(size_t)a * W + wd] + popc_below(hw, l32);
-            w0 = A.hold_w0[idx];
-            ti = A.hold_tax[idx];
-          }
-          const float irho = 1.f / rho;
-          const float th = (pr[P_KAPPA] + pr[P_LAM]) * irho;
-          float zn;
-          bool at_kink;
-          if (ti >= 0) {
-            TaxLots t;
-            t.b1 = A.tax_brk[3 * ti]; t.b2 = A.tax_brk[3 * ti + 1]; t.b3 = A.tax_brk[3 * ti + 2];
-            t.s0 = A.tax_slope[4 * ti]; t.s1 = A.tax_slope[4 * ti + 1];
-            t.s2 = A.tax_slope[4 * ti + 2]; t.s3 = A.tax_slope[4 * ti + 3];
-            zn = prox_taxed(v, w0, th, irho, t, lb, ub);
-            at_kink = (zn == w0) || (zn == w0 - t.b1) || (zn == w0 - t.b2) || (zn == w0 - t.b3);
-          } else {
-            zn = prox_plain(v, w0, th, lb, ub);
-            at_kink = (zn == w0);
-          }
-          const float un = v - zn;
-          A.z[off] = zn;
-          A.u[off] = un;
-          Rp = (mu + rho * (zn - un)) / Delta;
-          st_rp[r] = fmaxf(st_rp[r], fabsf(x - zn));
-          st_rd[r] = fmaxf(st_rd[r], fabsf(zn - z));
-          st_tv[r] += fabsf(zn - w0);
-          st_nf[r] += (el && zn > lb && zn < ub && !at_kink) ? 1.f : 0.f;
+          A.v[off] = alpha * x + (1.f - alpha) * z + u;
+          st_rp[r] = fmaxf(st_rp[r], fabsf(x - z));
         }
       }
-      Rw[m * 33 + l32] = Rp;
+      if (MODE == MODE_CONTRACT) Rw[m * 33 + l32] = Rp;
     }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    {
+    if (MODE == MODE_CONTRACT) {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
       const float* ra = Rw + l32 * 33 + hi;
       const float* rb = Bs + (32 * w + hi) * BS + l32;
 #pragma unroll 4
@@ -322,26 +359,38 @@ __global__ __launch_bounds__(256, 2) void iter_kernel(IterArgs A) {
         for (int c = 0; c < NCH; ++c)
           T[c] = __builtin_amdgcn_mfma_f32_32x32x2f32(av, rb[(2 * s) * BS + 32 * c], T[c], 0, 0, 0);
       }
+      __builtin_amdgcn_wave_barrier();
     }
-    __builtin_amdgcn_wave_barrier();
   }
 
-  // ---- statistics: reduce over the 32 rows held by each half-wave --------
-  if (!INIT) {
+  const size_t M = A.m_total;
+  if (MODE == MODE_PROJECT) {
+    // primal residual estimate max |x - z| per account
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
+    for (int r = 0; r < 16; ++r)
 #pragma unroll
-      for (int o = 16; o >= 1; o >>= 1) {
-        st_rp[r] = fmaxf(st_rp[r], __shfl_xor(st_rp[r], o, 32));
-        st_rd[r] = fmaxf(st_rd[r], __shfl_xor(st_rd[r], o, 32));
-        st_tv[r] += __shfl_xor(st_tv[r], o, 32);
-        st_nf[r] += __shfl_xor(st_nf[r], o, 32);
+      for (int o = 16; o >= 1; o >>= 1) st_rp[r] = fmaxf(st_rp[r], __shfl_xor(st_rp[r], o, 32));
+    __syncthreads();
+    float* sred = Rt;                      // [4][32]
+    if (l32 == 0) {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int m = 8 * (r >> 2) + 4 * hi + (r & 3);
+        sred[w * kTM + m] = st_rp[r];
       }
     }
+    __syncthreads();
+    if (tid < kTM) {
+      const int a = Aid[tid];
+      if (a >= 0)
+        A.stat[((size_t)blockIdx.x * M + a) * kNStat + ST_RPRIM] =
+            fmaxf(fmaxf(sred[tid], sred[kTM + tid]), fmaxf(sred[2 * kTM + tid], sred[3 * kTM + tid]));
+    }
+    return;
   }
+
   __syncthreads();                       // all waves done with Bs / Rt
   float* red = Bs;                       // [4][32][kp]
-  float* sred = Rt;                      // [4][32][4]
 #pragma unroll
   for (int c = 0; c < NCH; ++c)
 #pragma unroll
@@ -349,17 +398,7 @@ __global__ __launch_bounds__(256, 2) void iter_kernel(IterArgs A) {
       const int m = 8 * (r >> 2) + 4 * hi + (r & 3);
       red[(w * kTM + m) * kp + 32 * c + l32] = T[c][r];
     }
-  if (l32 == 0) {
-#pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      const int m = 8 * (r >> 2) + 4 * hi + (r & 3);
-      float* s = sred + (w * kTM + m) * kNStat;
-      s[ST_RPRIM] = st_rp[r]; s[ST_RDUAL] = st_rd[r];
-      s[ST_TURN] = st_tv[r]; s[ST_NFREE] = st_nf[r];
-    }
-  }
   __syncthreads();
-  const size_t M = A.m_total;
   for (int e = tid; e < kTM * kp; e += 256) {
     const int m = e / kp, c = e % kp;
     const int a = Aid[m];
@@ -368,22 +407,93 @@ __global__ __launch_bounds__(256, 2) void iter_kernel(IterArgs A) {
               red[(2 * kTM + m) * kp + c] + red[(3 * kTM + m) * kp + c];
     A.part[((size_t)blockIdx.x * M + a) * kp + c] = s;
   }
-  if (tid < kTM * kNStat) {
-    const int m = tid / kNStat, q = tid % kNStat;
-    const int a = Aid[m];
-    if (a >= 0) {
-      float v;
-      if (INIT) {
-        v = (q == ST_NFREE) ? -1.f : 0.f;
-      } else if (q == ST_RPRIM || q == ST_RDUAL) {
-        v = fmaxf(fmaxf(sred[(0 * kTM + m) * kNStat + q], sred[(1 * kTM + m) * kNStat + q]),
-                  fmaxf(sred[(2 * kTM + m) * kNStat + q], sred[(3 * kTM + m) * kNStat + q]));
-      } else {
-        v = sred[(0 * kTM + m) * kNStat + q] + sred[(1 * kTM + m) * kNStat + q] +
-            sred[(2 * kTM + m) * kNStat + q] + sred[(3 * kTM + m) * kNStat + q];
-      }
-      A.stat[((size_t)blockIdx.x * M + a) * kNStat + q] = v;
+}
+
+// ---------------------------------------------------------------------------
+// exact turnover-cap multiplier of the current v (one workgroup per account)
+//
+// turnover(lam) = sum_i |prox_i(v_i; lam) - w0_i| is piecewise linear and
+// non-increasing in lam, with slope -(number of coordinates strictly inside
+// a linear piece)/rho.  lam* = 0 when turnover(0) <= tau, else the root of
+// turnover(lam) = tau, found by Newton steps from the previous lam* inside a
+// bracket that every evaluation tightens (bisection when a step leaves it).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void cap_kernel(IterArgs A) {
+  __shared__ float s_g[256], s_n[256];
+  __shared__ float s_lam;
+  __shared__ int s_done;
+  const int slot = blockIdx.x;
+  if (slot >= *A.m_act) return;
+  const int a = A.act[slot];
+  float* par = A.par_rw + (size_t)a * kNPar;
+  const float tau = par[P_TAU];
+  if (!isfinite(tau)) return;
+  const int tid = threadIdx.x, n = A.n;
+  const float rho = par[P_RHO], irho = 1.f / rho, kap = par[P_KAPPA];
+  const float lbp = par[P_LB], ubp = par[P_UB];
+  float lam = par[P_LAM];
+  float lo = 0.f, hi_b = INFINITY, best_feas = INFINITY;
+  if (tid == 0) s_done = 0;
+  for (int it = 0; it < 48; ++it) {
+    const float th = (kap + lam) * irho;
+    float g = 0.f, nf = 0.f;
+    for (int i = tid; i < n; i += 256) {
+      const RowInfo ri = row_info(A, a, i, lbp, ubp);
+      bool kink;
+      const float z = prox_row(ri, A.v[(size_t)a * n + i], th, irho, A.tax_brk, A.tax_slope, &kink);
+      g += fabsf(z - ri.w0);
+      nf += kink ? 0.f : 1.f;
     }
+    s_g[tid] = g;
+    s_n[tid] = nf;
+    __syncthreads();
+    for (int o = 128; o >= 1; o >>= 1) {
+      if (tid < o) { s_g[tid] += s_g[tid + o]; s_n[tid] += s_n[tid + o]; }
+      __syncthreads();
+    }
+    if (tid == 0) {
+      const float gt = s_g[0], nft = s_n[0];
+      const float tol = 1e-6f * fmaxf(tau, 1e-6f);
+      if (gt <= tau) { hi_b = lam; best_feas = lam; } else { lo = lam; }
+      bool done = fabsf(gt - tau) <= tol || (lam == 0.f && gt <= tau);
+      float nl = lam;
+      if (!done) {
+        nl = (nft > 0.f) ? lam + rho * (gt - tau) / nft : NAN;
+        if (gt <= tau && !(nl > 0.f) && lo == 0.f && lam > 0.f) {
+          nl = 0.f;                        // try the unconstrained multiplier
+        } else if (!(nl > lo && nl < hi_b)) {
+          nl = isfinite(hi_b) ? 0.5f * (lo + hi_b) : fmaxf(2.f * lam, lam + 1e-4f);
+        }
+        if (isfinite(hi_b) && hi_b - lo <= 1e-6f * hi_b && lo > 0.f) { done = true; nl = hi_b; }
+      }
+      s_lam = fmaxf(nl, 0.f);
+      s_done = done ? 1 : 0;
+    }
+    __syncthreads();
+    lam = s_lam;
+    if (s_done) break;
+    __syncthreads();
+  }
+  if (tid == 0) {
+    // never hand the prox a multiplier whose turnover is known to exceed tau
+    float out = lam;
+    if (!s_done && isfinite(best_feas)) out = best_feas;
+    par[P_LAM] = out;
+  }
+}
+
+// z = prox(v; lam*) for every active account (input of the polish)
+__global__ __launch_bounds__(256) void materialize_z_kernel(IterArgs A, float* z) {
+  const int slot = blockIdx.y;
+  if (slot >= *A.m_act) return;
+  const int a = A.act[slot];
+  const float* par = A.par + (size_t)a * kNPar;
+  const float rho = par[P_RHO], irho = 1.f / rho;
+  const float th = (par[P_KAPPA] + par[P_LAM]) * irho;
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < A.n; i += gridDim.x * 256) {
+    const RowInfo ri = row_info(A, a, i, par[P_LB], par[P_UB]);
+    z[(size_t)a * A.n + i] = prox_row(ri, A.v[(size_t)a * A.n + i], th, irho, A.tax_brk,
+                                      A.tax_slope, nullptr);
   }
 }
 
@@ -415,11 +525,9 @@ __global__ __launch_bounds__(256) void ksolve_kernel(KArgs A) {
     t[j] = s;
   }
   if (tid < kNStat) {
-    float v = (tid == ST_RPRIM || tid == ST_RDUAL) ? 0.f : 0.f;
-    for (int rt = 0; rt < A.n_rt; ++rt) {
-      float x = A.stat[((size_t)rt * M + a) * kNStat + tid];
-      v = (tid == ST_RPRIM || tid == ST_RDUAL) ? fmaxf(v, x) : v + x;
-    }
+    float v = 0.f;
+    for (int rt = 0; rt < A.n_rt; ++rt)
+      v = fmaxf(v, A.stat[((size_t)rt * M + a) * kNStat + tid]);
     sst[tid] = v;
   }
   __syncthreads();
@@ -458,7 +566,8 @@ __global__ __launch_bounds__(256) void ksolve_kernel(KArgs A) {
   for (int j = tid; j < kp; j += 256) {
     double s = 0.0;
     if (j < kg)
-      for (int l = 0; l < kg; ++l) s += (double)Kinv[j * kp + l] * rhs[l];
+      // K^-1 is symmetric: read column j (consecutive j -> consecutive words)
+      for (int l = 0; l < kg; ++l) s += (double)Kinv[l * kp + j] * rhs[l];
     pprime[j] = (float)s;
   }
   __syncthreads();
@@ -494,25 +603,8 @@ __global__ __launch_bounds__(256) void ksolve_kernel(KArgs A) {
   }
   if (tid == 0) {
     par[P_NU] = (float)nu;
-    const float tau = par[P_TAU];
-    const float nfree = sst[ST_NFREE];
-    if (nfree >= 0.f && isfinite(tau)) {
-      // damped Newton step on turnover(lam) = tau (slope -nfree/rho),
-      // limited to [lam/2, 2 lam + lam_eps] so a pass with few free
-      // coordinates cannot throw the multiplier far off
-      const float lam = par[P_LAM];
-      const float rho = par[P_RHO];
-      const float lam_eps = 1e-4f;
-      float nl = lam + A.cap_beta * rho * (sst[ST_TURN] - tau) / fmaxf(nfree, 1.f);
-      nl = fminf(fmaxf(nl, 0.5f * lam), 2.f * lam + lam_eps);
-      par[P_LAM] = fmaxf(nl, 0.f);
-    }
-    if (nfree >= 0.f) {
-      A.res[(size_t)a * 4 + 0] = fmaxf(sst[ST_RPRIM], (float)red[0]);
-      A.res[(size_t)a * 4 + 1] = par[P_RHO] * sst[ST_RDUAL];
-      A.res[(size_t)a * 4 + 2] = sst[ST_TURN];
-      A.iters[a] += 1;
-    }
+    A.res[(size_t)a * 4 + 0] = fmaxf(sst[ST_RPRIM], (float)red[0]);
+    A.iters[a] += 1;
   }
 }
 
@@ -527,12 +619,12 @@ static size_t iter_smem() {
 }
 
 template <int NCH>
-static hipError_t launch_iter_t(const IterArgs& A, bool init, dim3 grid, hipStream_t st) {
+static hipError_t launch_iter_t(const IterArgs& A, int mode, dim3 grid, hipStream_t st) {
   size_t smem = iter_smem<NCH>();
-  if (init) {
-    hipLaunchKernelGGL((iter_kernel<NCH, true>), grid, dim3(256), smem, st, A);
+  if (mode == MODE_CONTRACT) {
+    hipLaunchKernelGGL((iter_kernel<NCH, MODE_CONTRACT>), grid, dim3(256), smem, st, A);
   } else {
-    hipLaunchKernelGGL((iter_kernel<NCH, false>), grid, dim3(256), smem, st, A);
+    hipLaunchKernelGGL((iter_kernel<NCH, MODE_PROJECT>), grid, dim3(256), smem, st, A);
   }
   return hipGetLastError();
 }
@@ -540,10 +632,10 @@ static hipError_t launch_iter_t(const IterArgs& A, bool init, dim3 grid, hipStre
 hipError_t configure_iter_kernels() {
   hipError_t e = hipSuccess;
 #define FQP_CFG(N)                                                                     \
-  e = hipFuncSetAttribute((const void*)iter_kernel<N, true>,                           \
+  e = hipFuncSetAttribute((const void*)iter_kernel<N, MODE_CONTRACT>,                  \
                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)iter_smem<N>()); \
   if (e != hipSuccess) return e;                                                       \
-  e = hipFuncSetAttribute((const void*)iter_kernel<N, false>,                          \
+  e = hipFuncSetAttribute((const void*)iter_kernel<N, MODE_PROJECT>,                   \
                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)iter_smem<N>()); \
   if (e != hipSuccess) return e;
   FQP_CFG(1) FQP_CFG(2) FQP_CFG(3) FQP_CFG(4) FQP_CFG(5) FQP_CFG(6)
@@ -551,16 +643,27 @@ hipError_t configure_iter_kernels() {
   return e;
 }
 
-hipError_t launch_iter(const IterArgs& A, int kp, bool init, dim3 grid, hipStream_t st) {
+hipError_t launch_iter(const IterArgs& A, int kp, int mode, dim3 grid, hipStream_t st) {
   switch (kp / 32) {
-    case 1: return launch_iter_t<1>(A, init, grid, st);
-    case 2: return launch_iter_t<2>(A, init, grid, st);
-    case 3: return launch_iter_t<3>(A, init, grid, st);
-    case 4: return launch_iter_t<4>(A, init, grid, st);
-    case 5: return launch_iter_t<5>(A, init, grid, st);
-    case 6: return launch_iter_t<6>(A, init, grid, st);
+    case 1: return launch_iter_t<1>(A, mode, grid, st);
+    case 2: return launch_iter_t<2>(A, mode, grid, st);
+    case 3: return launch_iter_t<3>(A, mode, grid, st);
+    case 4: return launch_iter_t<4>(A, mode, grid, st);
+    case 5: return launch_iter_t<5>(A, mode, grid, st);
+    case 6: return launch_iter_t<6>(A, mode, grid, st);
     default: return hipErrorInvalidValue;
   }
+}
+
+hipError_t launch_cap(const IterArgs& A, int m_total, hipStream_t st) {
+  hipLaunchKernelGGL(cap_kernel, dim3(m_total), dim3(256), 0, st, A);
+  return hipGetLastError();
+}
+
+hipError_t launch_materialize_z(const IterArgs& A, int m_total, float* z, hipStream_t st) {
+  const int gx = (A.n + 255) / 256 < 64 ? (A.n + 255) / 256 : 64;
+  hipLaunchKernelGGL(materialize_z_kernel, dim3(gx, m_total), dim3(256), 0, st, A, z);
+  return hipGetLastError();
 }
 
 hipError_t launch_ksolve(const KArgs& A, int m_total, hipStream_t st) {

@@ -14,8 +14,7 @@ struct IterArgs {
   const float* Bt;           // [n][kp]
   const float* d;            // [n]
   const float* mu;           // [m][n]
-  float* z;                  // [m][n]
-  float* u;                  // [m][n]
+  float* v;                  // [m][n]  ADMM state v = xh + u
   const uint32_t* elig;      // [m][W] or null
   const uint32_t* hold;      // [m][W]
   const int32_t* hold_pre;   // [m][W]
@@ -26,6 +25,7 @@ struct IterArgs {
   const float* tax_slope;    // [nnz_t][4]
   const float* pp;           // [m][kp]
   const float* par;          // [m][kNPar]
+  float* par_rw;             // same array, written by the cap kernel
   float* part;               // [n_rt][m][kp]
   float* stat;               // [n_rt][m][kNStat]
 };
@@ -47,13 +47,14 @@ struct KArgs {
   float* vb;                 // [m][G]
   const float* blo;          // [m][G]
   const float* bhi;          // [m][G]
-  float cap_beta;
   float* res;                // [m][4]  ADMM residual estimates
   int* iters;                // [m]
 };
 
 hipError_t configure_iter_kernels();
-hipError_t launch_iter(const IterArgs& A, int kp, bool init, dim3 grid, hipStream_t st);
+hipError_t launch_iter(const IterArgs& A, int kp, int mode, dim3 grid, hipStream_t st);
+hipError_t launch_cap(const IterArgs& A, int m_total, hipStream_t st);
+hipError_t launch_materialize_z(const IterArgs& A, int m_total, float* z, hipStream_t st);
 hipError_t launch_ksolve(const KArgs& A, int m_total, hipStream_t st);
 hipError_t launch_build_bt(int n, int k, int G, int kp, const float* B, const int32_t* group,
                            float* Bt, hipStream_t st);
@@ -124,6 +125,7 @@ struct PolishArgs {
   double* wk;                // [m][wk_stride] per-account scratch
   size_t wk_stride;
   double* wout;              // [m][n] polished weights (caller output)
+  double* gbase;             // [m][n] gamma (Sigma w)_i - mu_i of the pattern
   double* mult;              // [m][2 + G] nu, lam_cap, lam_band
   int32_t* pstate;           // [m][8] polish bookkeeping
   double eps_prim, eps_dual, eps_comp;

@@ -25,6 +25,8 @@
 // fixed coordinates whose stationarity is violated move into the adjacent
 // piece, and bands / cap are switched on when violated or off when their
 // multiplier has the wrong sign.
+#include <climits>
+
 #include "fqp_common.h"
 #include "fqp_kernels.h"
 #include "../../include/fqp.h"
@@ -33,10 +35,11 @@ namespace fqp {
 
 enum PState {
   PS_CAP = 0, PS_NF, PS_NX, PS_NC, PS_DONE, PS_ROUNDS,
-  PS_BACT0, PS_BACT1, PS_BUP0, PS_BUP1, PS_STALL, kNPState = 12
+  PS_BACT0, PS_BACT1, PS_BUP0, PS_BUP1, PS_STALL, PS_ND, kNPState = 12
 };
 
 constexpr double kSnap = 1e-10;
+constexpr int kMaxNull = 8;
 
 struct Geom {
   int np;            // points on the asset's line: bounds and inner kinks
@@ -140,11 +143,12 @@ size_t polish_wk_stride(int k, int G) {
   const size_t ncol = (size_t)G + 3;
   // Waug, Y (k x ncol), CV (ncol^2), S (ncol^2), yX, Fy, sol (k), h, eta, eta0
   // (ncol), misc 16
-  return 2 * (size_t)k * ncol + 2 * ncol * ncol + 3 * (size_t)k + 3 * ncol + 16;
+  return 2 * (size_t)k * ncol + 2 * ncol * ncol + 3 * (size_t)k + 3 * ncol +
+         (size_t)kMaxNull * ncol + 16;
 }
 
 struct Wk {
-  double *Waug, *Y, *CV, *S, *yX, *Fy, *sol, *h, *eta, *eta0, *misc;
+  double *Waug, *Y, *CV, *S, *yX, *Fy, *sol, *h, *eta, *eta0, *nul, *misc;
 };
 __device__ __forceinline__ Wk wk_of(const PolishArgs& A, int a) {
   Wk w;
@@ -161,6 +165,7 @@ __device__ __forceinline__ Wk wk_of(const PolishArgs& A, int a) {
   w.h = p; p += ncol;
   w.eta = p; p += ncol;
   w.eta0 = p; p += ncol;
+  w.nul = p; p += (size_t)kMaxNull * ncol;   // [kMaxNull][ncol] null directions
   w.misc = p;
   return w;
 }
@@ -220,6 +225,37 @@ __device__ int bscan(int v, int* sh, int* tot) {
   return incl - v;
 }
 
+
+// Sums over a list of rows (LDS-staged, 64 rows at a time):
+//   ys[j] += sum_t B[i_t][j] w[i_t]   (thread j < k)
+//   gs[g] += sum_t [group(i_t) == g] w[i_t]   (thread g < G)
+// Entries are list[t] (rev = 0) or list[n - 1 - t] (rev = 1), t < cnt.
+__device__ void list_sums(const PolishArgs& A, const int32_t* list, int n, int cnt, int rev,
+                          const double* w, float* sB, double* sw, int* si, double& ys,
+                          double& gs) {
+  const int k = A.k, G = A.G, tid = threadIdx.x;
+  for (int c0 = 0; c0 < cnt; c0 += 64) {
+    const int rows = min(64, cnt - c0);
+    __syncthreads();
+    if (tid < rows) {
+      const int i = rev ? list[n - 1 - (c0 + tid)] : list[c0 + tid];
+      si[tid] = i;
+      sw[tid] = w[i];
+    }
+    __syncthreads();
+    for (int e = tid; e < rows * k; e += 256) {
+      const int rr = e / k, j = e % k;
+      sB[rr * (k + 1) + j] = A.Bt[(size_t)si[rr] * A.kp + j];
+    }
+    __syncthreads();
+    if (tid < k)
+      for (int rr = 0; rr < rows; ++rr) ys += (double)sB[rr * (k + 1) + tid] * sw[rr];
+    if (tid < G)
+      for (int rr = 0; rr < rows; ++rr) gs += (A.group[si[rr]] == tid) ? sw[rr] : 0.0;
+  }
+  __syncthreads();
+}
+
 // ---------------------------------------------------------------------------
 // polish_solve: classify (first round), lists, reduced KKT solve, w
 // ---------------------------------------------------------------------------
@@ -227,7 +263,9 @@ __global__ __launch_bounds__(256) void polish_solve_kernel(PolishArgs A) {
   extern __shared__ double smem_d[];
   const int k = A.k, G = A.G, n = A.n;
   double* Kf = smem_d;                      // [k][k]
-  double* stg = Kf + k * k;                 // staging: 16 rows x (k + 4)
+  // the Kf region also stages 64 float B rows before Kf is built
+  const int kfsz = max(k * k, (64 * (k + 1) + 1) / 2);
+  double* stg = Kf + kfsz;                  // staging: 16 rows x (k + 4)
   __shared__ double shd[256];
   __shared__ int shi[256];
   __shared__ int s_cnt[2];
@@ -340,14 +378,15 @@ __global__ __launch_bounds__(256) void polish_solve_kernel(PolishArgs A) {
 
   // ---- fixed contributions ----------------------------------------------
   // yX = B_X^T w_X, budget / band / cap sums of the fixed rows
-  for (int j = tid; j < k; j += 256) {
-    double s = 0.0;
-    for (int t = 0; t < nX; ++t) {
-      const int i = flist[n - 1 - t];
-      s += (double)A.Bt[(size_t)i * A.kp + j] * w[i];
-    }
-    wk.yX[j] = s;
-    wk.Fy[j] = s * (double)A.f[j];            // F yX
+  __shared__ double s_gfix[kMaxG];
+  {
+    double ys = 0.0, gs = 0.0;
+    float* sB = reinterpret_cast<float*>(Kf);          // Kf is not built yet
+    double* swv = stg;
+    int* siv = reinterpret_cast<int*>(stg + 64);
+    list_sums(A, flist, n, nX, 1, w, sB, swv, siv, ys, gs);
+    if (tid < k) { wk.yX[tid] = ys; wk.Fy[tid] = ys * (double)A.f[tid]; }
+    if (tid < G) s_gfix[tid] = gs;
   }
   // active constraint columns: 0 budget, bands (active order), cap
   int nb = 0;
@@ -370,13 +409,8 @@ __global__ __launch_bounds__(256) void polish_solve_kernel(PolishArgs A) {
       int col = 1;
       for (int g = 0; g < G; ++g) {
         if (!band_active(ps, g)) continue;
-        double sg = 0.0;
-        for (int t = 0; t < nX; ++t) {
-          const int i = flist[n - 1 - t];
-          if (A.group[i] == g) sg += w[i];
-        }
         const double bnd = band_upper(ps, g) ? A.bhi[(size_t)a * G + g] : A.blo[(size_t)a * G + g];
-        wk.h[col] = bnd - sg;
+        wk.h[col] = bnd - s_gfix[g];
         ++col;
       }
       if (cap_on) wk.h[col] = (double)tauf - sturn;   // + sum_F sgn w0 added below
@@ -521,20 +555,10 @@ __global__ __launch_bounds__(256) void polish_solve_kernel(PolishArgs A) {
     }
     __syncthreads();
   }
-  // ---- Y = Kf^-1 Waug (columns in parallel) -------------------------------
-  for (int col = tid; col < ncol; col += 256) {
-    for (int i = 0; i < k; ++i) {
-      double s = wk.Waug[i * ncol + col];
-      for (int l = 0; l < i; ++l) s -= Kf[i * k + l] * wk.Y[l * ncol + col];
-      wk.Y[i * ncol + col] = s / Kf[i * k + i];
-    }
-    for (int i = k - 1; i >= 0; --i) {
-      double s = wk.Y[i * ncol + col];
-      for (int l = i + 1; l < k; ++l) s -= Kf[l * k + i] * wk.Y[l * ncol + col];
-      wk.Y[i * ncol + col] = s / Kf[i * k + i];
-    }
-  }
+  // ---- Y = Kf^-1 Waug -------------------------------------------------------
+  for (int e = tid; e < k * ncol; e += 256) wk.Y[e] = wk.Waug[e];
   __syncthreads();
+  chol_solve_cols(Kf, k, wk.Y, ncol);
   // ---- Schur system on the constraint columns ------------------------------
   // gamma * C H^-1 V = CV[C, V] - Waug[:, C]^T Y[:, V]
   for (int e = tid; e < nc * ncol; e += 256) {
@@ -556,48 +580,76 @@ __global__ __launch_bounds__(256) void polish_solve_kernel(PolishArgs A) {
       e0[col++] = m0[2 + g];
     }
     if (cap_on) e0[col++] = fmax(m0[1], 0.0);
-    // r = C H^-1 rhs - h - S eta0 ;  solve (S + eps I) corr = r  (Cholesky)
-    double* Sm = wk.misc;   // not enough room for big nc: reuse CV (consumed)
-    Sm = wk.CV;
-    double dmax = 0.0;
-    for (int p = 0; p < nc; ++p) dmax = fmax(dmax, fabs(wk.S[p * ncol + p]));
-    const double eps = 1e-13 * fmax(dmax, 1e-300);
+    // S eta = C H^-1 rhs - h with S = C H^-1 C^T (PSD).  Pivoted Cholesky
+    // finds rank r; the pivot components are solved for, the others keep
+    // eta0, and the null directions of S (the multipliers the free rows do
+    // not pin) are stored for the certification step.
+    double* Sm = wk.CV;                  // CV is consumed: nc x nc factor
     double* rr = wk.eta;
+    int perm[kMaxG + 3];
+    double dmax = 0.0;
     for (int p = 0; p < nc; ++p) {
-      double s = wk.S[p * ncol + nc] - wk.h[p];
-      for (int q = 0; q < nc; ++q) s -= wk.S[p * ncol + q] * e0[q];
-      rr[p] = s;
-      for (int q = 0; q < nc; ++q) Sm[p * nc + q] = wk.S[p * ncol + q] + (p == q ? eps : 0.0);
+      perm[p] = p;
+      dmax = fmax(dmax, wk.S[p * ncol + p]);
+      for (int q = 0; q < nc; ++q) Sm[p * nc + q] = wk.S[p * ncol + q];
     }
-    // Cholesky (lower) of Sm
-    bool ok = true;
-    for (int j = 0; j < nc && ok; ++j) {
-      double s = Sm[j * nc + j];
-      for (int l = 0; l < j; ++l) s -= Sm[j * nc + l] * Sm[j * nc + l];
-      if (!(s > 0.0)) { ok = false; break; }
-      s = sqrt(s);
-      Sm[j * nc + j] = s;
-      for (int i = j + 1; i < nc; ++i) {
-        double t = Sm[i * nc + j];
-        for (int l = 0; l < j; ++l) t -= Sm[i * nc + l] * Sm[j * nc + l];
-        Sm[i * nc + j] = t / s;
+    const double ptol = 1e-12 * dmax;
+    int rank = 0;
+    for (int j = 0; j < nc; ++j) {
+      int best = j;
+      for (int p = j + 1; p < nc; ++p)
+        if (Sm[p * nc + p] > Sm[best * nc + best]) best = p;
+      if (!(Sm[best * nc + best] > ptol)) break;
+      if (best != j) {
+        for (int q = 0; q < nc; ++q) { double t = Sm[j * nc + q]; Sm[j * nc + q] = Sm[best * nc + q]; Sm[best * nc + q] = t; }
+        for (int q = 0; q < nc; ++q) { double t = Sm[q * nc + j]; Sm[q * nc + j] = Sm[q * nc + best]; Sm[q * nc + best] = t; }
+        int t = perm[j]; perm[j] = perm[best]; perm[best] = t;
       }
+      const double djj = sqrt(Sm[j * nc + j]);
+      Sm[j * nc + j] = djj;
+      for (int i = j + 1; i < nc; ++i) Sm[i * nc + j] /= djj;
+      for (int i = j + 1; i < nc; ++i)
+        for (int l = j + 1; l <= i; ++l) {
+          Sm[i * nc + l] -= Sm[i * nc + j] * Sm[l * nc + j];
+          Sm[l * nc + i] = Sm[i * nc + l];
+        }
+      ++rank;
     }
-    if (ok) {
-      for (int i = 0; i < nc; ++i) {
-        double s = rr[i];
-        for (int l = 0; l < i; ++l) s -= Sm[i * nc + l] * rr[l];
-        rr[i] = s / Sm[i * nc + i];
-      }
-      for (int i = nc - 1; i >= 0; --i) {
-        double s = rr[i];
-        for (int l = i + 1; l < nc; ++l) s -= Sm[l * nc + i] * rr[l];
-        rr[i] = s / Sm[i * nc + i];
-      }
-      for (int p = 0; p < nc; ++p) rr[p] += e0[p];
-    } else {
-      for (int p = 0; p < nc; ++p) rr[p] = e0[p];
+    // right-hand side on the pivot rows, null components from eta0
+    double x[kMaxG + 3];
+    for (int j = 0; j < nc; ++j) x[j] = (j >= rank) ? e0[perm[j]] : 0.0;
+    for (int j = 0; j < rank; ++j) {
+      const int pj = perm[j];
+      double t = wk.S[pj * ncol + nc] - wk.h[pj];
+      for (int q = rank; q < nc; ++q) t -= wk.S[pj * ncol + perm[q]] * x[q];
+      x[j] = t;
     }
+    for (int i = 0; i < rank; ++i) {
+      double t = x[i];
+      for (int l = 0; l < i; ++l) t -= Sm[i * nc + l] * x[l];
+      x[i] = t / Sm[i * nc + i];
+    }
+    for (int i = rank - 1; i >= 0; --i) {
+      double t = x[i];
+      for (int l = i + 1; l < rank; ++l) t -= Sm[l * nc + i] * x[l];
+      x[i] = t / Sm[i * nc + i];
+    }
+    for (int j = 0; j < nc; ++j) rr[perm[j]] = x[j];
+    // null directions: v_piv = -L11^-T L21^T e_t, v_t = 1
+    const int nd = min(nc - rank, kMaxNull);
+    for (int t = 0; t < nd; ++t) {
+      double v[kMaxG + 3];
+      for (int j = 0; j < nc; ++j) v[j] = 0.0;
+      v[rank + t] = 1.0;
+      for (int i = rank - 1; i >= 0; --i) {
+        double u = -Sm[(rank + t) * nc + i];
+        for (int l = i + 1; l < rank; ++l) u -= Sm[l * nc + i] * v[l];
+        v[i] = u / Sm[i * nc + i];
+      }
+      // rows of the null block have the workspace's full column stride
+      for (int j = 0; j < nc; ++j) wk.nul[t * (G + 3) + perm[j]] = v[j];
+    }
+    ps[PS_ND] = nd;
     // multipliers in the build's convention
     double* mult = A.mult + (size_t)a * (2 + G);
     mult[0] = -rr[0];
@@ -670,28 +722,30 @@ __global__ __launch_bounds__(256) void polish_check_kernel(PolishArgs A, fqp_res
   int8_t* code = A.code_next + (size_t)a * n;    // proposals
   const int32_t* flist = A.flist + (size_t)a * n;
   const double* w = A.wout + (size_t)a * n;
-  const double* mult = A.mult + (size_t)a * (2 + G);
-  const double nu = mult[0], lam = mult[1];
+  double* gmult = A.mult + (size_t)a * (2 + G);
+  __shared__ double mult[2 + kMaxG];
+  for (int q = tid; q < 2 + G; q += 256) mult[q] = gmult[q];
   const int nF = ps[PS_NF], nX = ps[PS_NX];
+  double* gb = A.gbase + (size_t)a * n;
+  __shared__ int s_bad, s_done;
+  if (tid == 0) { s_bad = 0; s_done = 0; }
 
-  // y = B^T w over the rows with w != 0 (free list + nonzero fixed list)
-  for (int j = tid; j < k; j += 256) {
-    double s = 0.0;
-    for (int t = 0; t < nF; ++t) { const int i = flist[t]; s += (double)A.Bt[(size_t)i * A.kp + j] * w[i]; }
-    for (int t = 0; t < nX; ++t) { const int i = flist[n - 1 - t]; s += (double)A.Bt[(size_t)i * A.kp + j] * w[i]; }
-    s_y[j] = s * (double)A.f[j];
-  }
-  // group sums (deterministic: one thread per group over the lists)
-  for (int g = tid; g < G; g += 256) {
-    double s = 0.0;
-    for (int t = 0; t < nF; ++t) { const int i = flist[t]; if (A.group[i] == g) s += w[i]; }
-    for (int t = 0; t < nX; ++t) { const int i = flist[n - 1 - t]; if (A.group[i] == g) s += w[i]; }
-    s_gs[g] = s;
+  // y = F B^T w and group sums over the rows with w != 0 (free list and
+  // nonzero fixed list), LDS-staged
+  {
+    __shared__ double s_sw[64];
+    __shared__ int s_si[64];
+    double ys = 0.0, gs = 0.0;
+    list_sums(A, flist, n, nF, 0, w, sBrow, s_sw, s_si, ys, gs);
+    list_sums(A, flist, n, nX, 1, w, sBrow, s_sw, s_si, ys, gs);
+    if (tid < k) s_y[tid] = ys * (double)A.f[tid];
+    if (tid < G) s_gs[tid] = gs;
   }
   __syncthreads();
 
-  double sw = 0.0, turn = 0.0, gmax = 0.0, mumax = 0.0, dmax = 0.0, box = 0.0, snapm = 0.0,
-         obj = 0.0;
+  // ---- gradient base  gb_i = gamma (Sigma w)_i - mu_i  (B rows via LDS) ----
+  double gmax = 0.0, mumax = 0.0, turn0 = 0.0;
+  int bad = 0;
   const int BS1 = k + 1;
   for (int base = 0; base < n; base += 256) {
     __syncthreads();
@@ -703,17 +757,163 @@ __global__ __launch_bounds__(256) void polish_check_kernel(PolishArgs A, fqp_res
     __syncthreads();
     const int i = base + tid;
     if (i >= n) continue;
+    double sig = 0.0;
+    const float* brow = sBrow + tid * BS1;
+    for (int j = 0; j < k; ++j) sig += (double)brow[j] * s_y[j];
+    sig += (double)A.d[i] * w[i];
+    const double mui = A.mu[(size_t)a * n + i];
+    const double v = gam * sig - mui;
+    gb[i] = v;
+    gmax = fmax(gmax, fabs(gam * sig));
+    mumax = fmax(mumax, fabs(mui));
+    turn0 += fabs(w[i] - (double)row_data(A, a, i).w0);
+    if (!isfinite(v) || !isfinite(w[i])) bad = 1;
+  }
+  if (bad) atomicOr(&s_bad, 1);
+  gmax = bmax<double>(gmax, shd);
+  mumax = bmax<double>(mumax, shd);
+  turn0 = bsum<double>(turn0, shd);
+  const double scale = fmax(fmax(gmax, mumax), 1e-12);
+
+  // ---- multipliers the free rows leave open -----------------------------
+  // Along a stored null direction v of the free-row equations the free rows
+  // stay stationary, and every fixed row's stationarity interval becomes a
+  // pair of linear inequalities in the step s.  The step aims at zeroing
+  // the multiplier of an active constraint that is not tight (its row was
+  // dependent, so the solve could not enforce it); otherwise it stays
+  // nearest to 0.  When a fixed row blocks that target, the row is the
+  // one to release (dual active-set step): it is proposed below.
+  __shared__ int s_block;                 // row * 16 + proposed code, or -1
+  __shared__ int s_key[2];
+  __shared__ double s_st;
+  if (tid == 0) s_block = -1;
+  {
+    const int nd = ps[PS_ND];
+    const int nc = ps[PS_NC];
+    const int ncol = G + 3;
+    const double* nul = wk_of(A, a).nul;
+    const double thr = 0.01 * A.eps_comp * scale;
+    for (int sweep = 0; sweep < 2 && nd > 0; ++sweep) {
+      for (int q = 0; q < nd; ++q) {
+        const double* nv = nul + q * ncol;
+        // column of each multiplier inside eta = (-nu, bands..., lam_cap)
+        const double n0 = nv[0];
+        const double ncap = ps[PS_CAP] ? nv[nc - 1] : 0.0;
+        const double lamc = mult[1];
+        double Lo = -INFINITY, Up = INFINITY;
+        int loKey = INT_MAX, upKey = INT_MAX;
+        for (int i = tid; i < n; i += 256) {
+          const int c = code_r[i];
+          if (c & 1) continue;
+          RowData r = row_data(A, a, i);
+          if (!r.el) continue;
+          Geom g;
+          make_geom(g, r.el, lbf, ubf, r.w0, kap, phi, r.ti, A.tax_brk, A.tax_slope);
+          const double lb = lbf, ub = ubf;
+          double nb = 0.0, lg = 0.0;
+          if (G) {
+            const int gg = A.group[i];
+            lg = mult[2 + gg];
+            if (band_active(ps, gg)) {
+              int col = 1;
+              for (int h2 = 0; h2 < gg; ++h2) col += band_active(ps, h2) ? 1 : 0;
+              nb = nv[col];
+            }
+          }
+          const double T = -(gb[i] - mult[0] + lg);
+          const double al = n0 + nb;
+          const int j = c >> 1;
+          // leaving the interval at its lower end: the row wants to go down
+          const int keyL = (j > 0) ? i * 16 + 2 * (j - 1) + 1 : INT_MAX;
+          const int keyU = (j + 1 < g.np) ? i * 16 + 2 * j + 1 : INT_MAX;
+          double lo0, hi0, lo1, hi1, sn;
+          subdiff(g, w[i], 0.0, lb, ub, lo0, hi0, sn);
+          subdiff(g, w[i], 1.0, lb, ub, lo1, hi1, sn);
+          if (isfinite(lo0)) {           // lo0 + s_lo (lamc + s ncap) <= T - al s
+            const double slo = lo1 - lo0;
+            const double aa = al + slo * ncap, bb = T - lo0 - slo * lamc;
+            if (aa > 1e-300) { const double u = bb / aa; if (u < Up) { Up = u; upKey = keyL; } }
+            else if (aa < -1e-300) { const double u = bb / aa; if (u > Lo) { Lo = u; loKey = keyL; } }
+          }
+          if (isfinite(hi0)) {           // T - al s <= hi0 + s_hi (lamc + s ncap)
+            const double shi = hi1 - hi0;
+            const double aa = -(al + shi * ncap), bb = hi0 + shi * lamc - T;
+            if (aa > 1e-300) { const double u = bb / aa; if (u < Up) { Up = u; upKey = keyU; } }
+            else if (aa < -1e-300) { const double u = bb / aa; if (u > Lo) { Lo = u; loKey = keyU; } }
+          }
+        }
+        const double Lb = bmax<double>(Lo, shd);
+        const double Ub = -bmax<double>(-Up, shd);
+        if (tid == 0) { s_key[0] = INT_MAX; s_key[1] = INT_MAX; }
+        __syncthreads();
+        if (Lo == Lb && isfinite(Lb)) atomicMin(&s_key[0], loKey);
+        if (Up == Ub && isfinite(Ub)) atomicMin(&s_key[1], upKey);
+        __syncthreads();
+        if (tid == 0) {
+          Lo = Lb; Up = Ub;
+          int kLo = s_key[0], kUp = s_key[1];
+          // complementarity target: zero the multiplier of a slack constraint
+          double tgt = 0.0, best = 0.0;
+          bool has_tgt = false;
+          if (ps[PS_CAP]) {              // lam_cap + s ncap >= 0
+            if (ncap > 1e-300) { const double u = -lamc / ncap; if (u > Lo) { Lo = u; kLo = INT_MAX; } }
+            else if (ncap < -1e-300) { const double u = -lamc / ncap; if (u < Up) { Up = u; kUp = INT_MAX; } }
+            const double v = fabs(lamc) * fmax((double)tauf - turn0, 0.0);
+            if (fabs(ncap) > 1e-300 && v > thr && v > best) { best = v; tgt = -lamc / ncap; has_tgt = true; }
+          }
+          int col = 1;
+          for (int gg = 0; gg < G; ++gg) {
+            if (!band_active(ps, gg)) continue;
+            const double nbv = nv[col++];
+            const double cur = mult[2 + gg];
+            const bool up = band_upper(ps, gg);
+            // upper band: lam >= 0 ; lower band: lam <= 0
+            const double sgn_req = up ? 1.0 : -1.0;
+            const double aa = sgn_req * nbv, bb = sgn_req * cur;   // bb + s aa >= 0
+            if (aa > 1e-300) { const double u = -bb / aa; if (u > Lo) { Lo = u; kLo = INT_MAX; } }
+            else if (aa < -1e-300) { const double u = -bb / aa; if (u < Up) { Up = u; kUp = INT_MAX; } }
+            const double slack = up ? (double)A.bhi[(size_t)a * G + gg] - s_gs[gg]
+                                    : s_gs[gg] - (double)A.blo[(size_t)a * G + gg];
+            const double v = fabs(cur) * fmax(slack, 0.0);
+            if (fabs(nbv) > 1e-300 && v > thr && v > best) { best = v; tgt = -cur / nbv; has_tgt = true; }
+          }
+          double st;
+          if (Lo <= Up) {
+            st = fmin(fmax(tgt, Lo), Up);
+            if (has_tgt) {
+              const int key = (tgt < Lo) ? kLo : (tgt > Up) ? kUp : INT_MAX;
+              if (key != INT_MAX && s_block < 0) s_block = key;
+            } else if (isfinite(Lo) && isfinite(Up)) {
+              st += 1e-3 * (0.5 * (Lo + Up) - st);
+            }
+          } else {
+            st = 0.5 * (Lo + Up);
+          }
+          if (!isfinite(st)) st = 0.0;
+          // eta += st * v  ->  nu -= st v0, bands += st v_b, lam_cap += st v_cap
+          mult[0] -= st * n0;
+          col = 1;
+          for (int gg = 0; gg < G; ++gg)
+            if (band_active(ps, gg)) mult[2 + gg] += st * nv[col++];
+          if (ps[PS_CAP]) mult[1] += st * ncap;
+          s_st = st;
+        }
+        __syncthreads();
+      }
+    }
+  }
+  const double nu = mult[0], lam = mult[1];
+
+  double sw = 0.0, turn = 0.0, dmax = 0.0, box = 0.0, snapm = 0.0, obj = 0.0;
+  for (int i = tid; i < n; i += 256) {
     RowData r = row_data(A, a, i);
     Geom g;
     make_geom(g, r.el, lbf, ubf, r.w0, kap, phi, r.ti, A.tax_brk, A.tax_slope);
     const double lb = r.el ? (double)lbf : 0.0, ub = r.el ? (double)ubf : 0.0;
     const double wi = w[i];
-    double sig = 0.0;
-    const float* brow = sBrow + tid * BS1;
-    for (int j = 0; j < k; ++j) sig += (double)brow[j] * s_y[j];
-    sig += (double)A.d[i] * wi;
     const double mui = A.mu[(size_t)a * n + i];
-    double gi = gam * sig - mui - nu;
+    const double sig = (gb[i] + mui) / gam;
+    double gi = gb[i] - nu;
     if (G) gi += mult[2 + A.group[i]];
     double lo, hi, snap;
     subdiff(g, wi, lam, lb, ub, lo, hi, snap);
@@ -721,9 +921,8 @@ __global__ __launch_bounds__(256) void polish_check_kernel(PolishArgs A, fqp_res
     const double dist = fmax(fmax(lo - t, t - hi), 0.0);
     sw += wi;
     turn += fabs(wi - g.w0);
-    gmax = fmax(gmax, fabs(gam * sig));
-    mumax = fmax(mumax, fabs(mui));
     dmax = fmax(dmax, dist);
+    if (!isfinite(dist)) bad = 1;
     box = fmax(box, fmax(lb - wi, wi - ub));
     snapm = fmax(snapm, snap);
     // objective: (gamma/2) w.Sigma w - mu w + trade cost
@@ -757,17 +956,15 @@ __global__ __launch_bounds__(256) void polish_check_kernel(PolishArgs A, fqp_res
     }
   }
   if (changed) atomicAdd(&s_changed, changed);
+  if (bad) atomicOr(&s_bad, 1);
   sw = bsum<double>(sw, shd);
   turn = bsum<double>(turn, shd);
   obj = bsum<double>(obj, shd);
-  gmax = bmax<double>(gmax, shd);
-  mumax = bmax<double>(mumax, shd);
   dmax = bmax<double>(dmax, shd);
   box = bmax<double>(box, shd);
   snapm = bmax<double>(snapm, shd);
 
   if (tid == 0) {
-    const double scale = fmax(fmax(gmax, mumax), 1e-12);
     double rexp = 0.0, comp = 0.0;
     for (int g = 0; g < G; ++g) {
       const double lo = A.blo[(size_t)a * G + g], hi = A.bhi[(size_t)a * G + g];
@@ -787,7 +984,12 @@ __global__ __launch_bounds__(256) void polish_check_kernel(PolishArgs A, fqp_res
     const double r_prim = fmax(fmax(fabs(sw - 1.0), fmax(box, 0.0)), fmax(rexp, rturn)) + snapm;
     const double r_dual = fmax(dmax, fmax(-lam, 0.0)) / scale;
     const double r_comp = comp / scale;
-    const bool ok = r_prim <= A.eps_prim && r_dual <= A.eps_dual && r_comp <= A.eps_comp;
+    const bool finite = !s_bad && isfinite(sw) && isfinite(obj) && isfinite(nu) &&
+                        isfinite(lam) && isfinite(r_prim) && isfinite(r_dual) &&
+                        isfinite(r_comp);
+    const bool ok = finite && r_prim <= A.eps_prim && r_dual <= A.eps_dual &&
+                    r_comp <= A.eps_comp;
+    for (int q = 0; q < 2 + G; ++q) gmult[q] = mult[q];
     ps[PS_ROUNDS] += 1;
     // keep the diagnostics of the latest pattern in the result arrays
     if (ok || final_pass) {
@@ -798,6 +1000,7 @@ __global__ __launch_bounds__(256) void polish_check_kernel(PolishArgs A, fqp_res
       if (R.nu) R.nu[a] = nu;
       if (R.lam_cap) R.lam_cap[a] = lam;
     }
+    s_done = ok ? 1 : 0;
     if (ok) {
       ps[PS_DONE] = 1;
       R.status[a] = FQP_SOLVED;
@@ -809,6 +1012,10 @@ __global__ __launch_bounds__(256) void polish_check_kernel(PolishArgs A, fqp_res
     } else {
       // bands / cap refinement
       int nchg = s_changed;
+      if (s_block >= 0) {                // release the row that blocks
+        code[s_block >> 4] = (int8_t)(s_block & 15);
+        ++nchg;
+      }
       for (int g = 0; g < G; ++g) {
         const double lo = A.blo[(size_t)a * G + g], hi = A.bhi[(size_t)a * G + g];
         const bool act = band_active(ps, g), up = band_upper(ps, g);
@@ -826,7 +1033,7 @@ __global__ __launch_bounds__(256) void polish_check_kernel(PolishArgs A, fqp_res
     }
   }
   __syncthreads();
-  if (final_pass || ps[PS_DONE]) {
+  if (final_pass || s_done) {
     if (R.lam_band && G) {
       for (int g = tid; g < G; g += 256) R.lam_band[(size_t)a * G + g] = mult[2 + g];
     }
@@ -837,7 +1044,13 @@ __global__ __launch_bounds__(256) void polish_check_kernel(PolishArgs A, fqp_res
 }
 
 static size_t polish_smem(int k) {
-  return sizeof(double) * ((size_t)k * k + 16 * (size_t)(k + 4) + 16 * (size_t)(kMaxG + 3));
+  // Kf (k^2 doubles), staging (16 rows of k + 4 doubles), V rows
+  // (16 x (kMaxG + 3) doubles); the Kf region first holds 64 staged B rows
+  // (64 (k + 1) floats) and the staging region 64 weights + 64 indices
+  const size_t a = sizeof(double) * ((size_t)k * k);
+  const size_t b = sizeof(float) * 64 * (size_t)(k + 1);
+  const size_t rest = sizeof(double) * (16 * (size_t)(k + 4) + 16 * (size_t)(kMaxG + 3));
+  return (a > b ? a : b) + (rest > 64 * 12 ? rest : 64 * 12);
 }
 
 hipError_t launch_polish_solve(const PolishArgs& A, hipStream_t st) {

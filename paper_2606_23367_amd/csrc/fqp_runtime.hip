@@ -169,7 +169,6 @@ void fqp_default_settings(fqp_settings* s) {
   s->rho = 0.f;
   s->rho_band = 0.f;
   s->alpha = 1.6f;
-  s->cap_beta = 0.1f;
   s->polish_rounds = 4;
   s->use_graph = 1;
   s->profile = 0;
@@ -373,7 +372,7 @@ extern "C" fqp_error fqp_solve_batch(fqp_handle* h, const fqp_universe* U, const
 
   // ---- workspace ----------------------------------------------------------
   WS(Bt, float, "Bt", (size_t)n * kp);
-  const int gram_rows = 2048;
+  const int gram_rows = 128;
   const int nparts = (n + gram_rows - 1) / gram_rows;
   WS(gpart, double, "gram_part", (size_t)nparts * (kg + 1) * (kg + 1));
   const size_t kw_stride = (size_t)(kg + 1) * (kg + 1) + 2 * (size_t)kg * kg + kg + 16;
@@ -385,8 +384,8 @@ extern "C" fqp_error fqp_solve_batch(fqp_handle* h, const fqp_universe* U, const
   WS(mbg, float, "mbg", (size_t)ncls * kp * (G > 0 ? G : 1));
   WS(rho_d, float, "rho_cls", (size_t)ncls);
   WS(cls_d, int, "cls", (size_t)m);
+  WS(v, float, "v", (size_t)m * n);
   WS(z, float, "z", (size_t)m * n);
-  WS(u, float, "u", (size_t)m * n);
   WS(hold, uint32_t, "hold", (size_t)m * W);
   WS(hold_pre, int32_t, "hold_pre", (size_t)m * W);
   WS(hold_cnt, int32_t, "hold_cnt", (size_t)m);
@@ -407,6 +406,7 @@ extern "C" fqp_error fqp_solve_batch(fqp_handle* h, const fqp_universe* U, const
   const size_t wks = polish_wk_stride(k, G);
   WS(wk, double, "polish_wk", (size_t)m * wks);
   WS(mult, double, "mult", (size_t)m * (2 + G));
+  WS(gbase, double, "gbase", (size_t)m * n);
   WS(pstate, int32_t, "pstate", (size_t)m * 12);
 
   // iteration geometry: ~1024 workgroups over (row tiles x account tiles)
@@ -449,24 +449,24 @@ extern "C" fqp_error fqp_solve_batch(fqp_handle* h, const fqp_universe* U, const
                      rho_d, P->gamma, P->kappa, P->lb, P->ub, P->tau, P->tax_ptr, S.alpha, rho_b,
                      par, zb, vb, P->band_lo, P->band_hi, iters, pstate, 12);
   HIP_CHECK(hipGetLastError());
-  HIP_CHECK(hipMemsetAsync(z, 0, sizeof(float) * (size_t)m * n, st));
-  HIP_CHECK(hipMemsetAsync(u, 0, sizeof(float) * (size_t)m * n, st));
+  HIP_CHECK(hipMemsetAsync(v, 0, sizeof(float) * (size_t)m * n, st));
   hipLaunchKernelGGL(compact_kernel, dim3(1), dim3(256), 0, st, m, R->status, act, m_act);
   HIP_CHECK(hipGetLastError());
 
   IterArgs ia{};
   ia.n = n; ia.W = W; ia.rows_per_wg = rows_per_wg; ia.chunks_per_wg = chunks;
   ia.m_total = m; ia.m_act = m_act; ia.act = act; ia.Bt = Bt; ia.d = U->d; ia.mu = P->mu;
-  ia.z = z; ia.u = u; ia.elig = P->eligible; ia.hold = hold; ia.hold_pre = hold_pre;
+  ia.v = v; ia.elig = P->eligible; ia.hold = hold; ia.hold_pre = hold_pre;
   ia.hold_ptr = hold_ptr; ia.hold_w0 = hold_w0; ia.hold_tax = hold_tax;
   ia.tax_brk = P->tax_brk; ia.tax_slope = P->tax_slope; ia.pp = pp; ia.par = par;
+  ia.par_rw = par;
   ia.part = part; ia.stat = stat;
   KArgs ka{};
   ka.kp = kp; ka.k = k; ka.G = G; ka.n_rt = n_rt; ka.m_total = m; ka.m_act = m_act; ka.act = act;
   ka.part = part; ka.stat = stat; ka.par = par; ka.pp = pp; ka.Kinv = Kinv; ka.cvec = cvec;
   ka.qvec = qvec; ka.sig1 = sig1; ka.mbg = mbg; ka.zb = zb; ka.vb = vb;
   ka.blo = G ? P->band_lo : nullptr; ka.bhi = G ? P->band_hi : nullptr;
-  ka.cap_beta = S.cap_beta; ka.res = res; ka.iters = iters;
+  ka.res = res; ka.iters = iters;
   PolishArgs pa{};
   pa.n = n; pa.k = k; pa.G = G; pa.kp = kp; pa.W = W; pa.m_total = m; pa.m_act = m_act;
   pa.act = act; pa.Bt = Bt; pa.f = U->f; pa.d = U->d; pa.group = G ? U->group : nullptr;
@@ -475,11 +475,41 @@ extern "C" fqp_error fqp_solve_batch(fqp_handle* h, const fqp_universe* U, const
   pa.tax_brk = P->tax_brk; pa.tax_slope = P->tax_slope; pa.par = par; pa.zb = zb; pa.vb = vb;
   pa.blo = G ? P->band_lo : nullptr; pa.bhi = G ? P->band_hi : nullptr;
   pa.code = code; pa.code_next = code_next; pa.flist = flist; pa.wk = wk; pa.wk_stride = wks; pa.wout = R->w;
-  pa.mult = mult; pa.pstate = pstate;
+  pa.mult = mult; pa.pstate = pstate; pa.gbase = gbase;
   pa.eps_prim = S.eps_prim; pa.eps_dual = S.eps_dual; pa.eps_comp = S.eps_comp;
 
+  std::vector<hipEvent_t> evs;
+  if (S.profile) {
+    evs.resize(2 * S.check_every);
+    for (auto& ev : evs) HIP_CHECK(hipEventCreate(&ev));
+  }
+  struct EvGuard {
+    std::vector<hipEvent_t>* v;
+    ~EvGuard() { for (auto& ev : *v) (void)hipEventDestroy(ev); }
+  } evguard{&evs};
   const dim3 igrid(n_rt, acc_tiles);
-  HIP_CHECK(launch_iter(ia, kp, true, igrid, st));
+  HIP_CHECK(hipMemsetAsync(stat, 0, sizeof(float) * (size_t)n_rt * m * kNStat, st));
+  // the cap kernel runs only when some account has a finite cap
+  bool any_cap = false;
+  {
+    std::vector<float> tau_h(m);
+    HIP_CHECK(hipMemcpyAsync(tau_h.data(), P->tau, sizeof(float) * m, hipMemcpyDeviceToHost, st));
+    HIP_CHECK(hipStreamSynchronize(st));
+    for (int a = 0; a < m; ++a) any_cap = any_cap || std::isfinite(tau_h[a]);
+  }
+  // one ADMM iteration: contract, factor-space solve, project, cap
+  auto launch_iteration = [&](int c) -> hipError_t {
+    hipError_t e0 = launch_iter(ia, kp, 0, igrid, st);
+    if (e0 != hipSuccess) return e0;
+    e0 = launch_ksolve(ka, m, st);
+    if (e0 != hipSuccess) return e0;
+    if (S.profile) { e0 = hipEventRecord(evs[2 * c], st); if (e0 != hipSuccess) return e0; }
+    e0 = launch_iter(ia, kp, 1, igrid, st);
+    if (e0 != hipSuccess) return e0;
+    if (S.profile) { e0 = hipEventRecord(evs[2 * c + 1], st); if (e0 != hipSuccess) return e0; }
+    if (any_cap) e0 = launch_cap(ia, m, st);
+    return e0;
+  };
 
   // ---- iteration blocks -------------------------------------------------------
   hipGraphExec_t gexec = nullptr;
@@ -493,24 +523,14 @@ extern "C" fqp_error fqp_solve_batch(fqp_handle* h, const fqp_universe* U, const
     }
   } gguard{&gexec, &graph};
   const bool use_graph = S.use_graph && !S.profile;
-  std::vector<hipEvent_t> evs;
-  if (S.profile) {
-    evs.resize(2 * S.check_every);
-    for (auto& ev : evs) HIP_CHECK(hipEventCreate(&ev));
-  }
-  struct EvGuard {
-    std::vector<hipEvent_t>* v;
-    ~EvGuard() { for (auto& ev : *v) (void)hipEventDestroy(ev); }
-  } evguard{&evs};
 
   auto run_block = [&](int count) -> fqp_error {
     if (use_graph && count == S.check_every) {
       if (!gexec) {
         HIP_CHECK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
         for (int c = 0; c < count; ++c) {
-          hipError_t e1 = launch_ksolve(ka, m, st);
-          hipError_t e2 = launch_iter(ia, kp, false, igrid, st);
-          if (e1 != hipSuccess || e2 != hipSuccess) {
+          hipError_t e1 = launch_iteration(c);
+          if (e1 != hipSuccess) {
             hipGraph_t tmp = nullptr;
             (void)hipStreamEndCapture(st, &tmp);
             if (tmp) (void)hipGraphDestroy(tmp);
@@ -523,12 +543,7 @@ extern "C" fqp_error fqp_solve_batch(fqp_handle* h, const fqp_universe* U, const
       }
       HIP_CHECK(hipGraphLaunch(gexec, st));
     } else {
-      for (int c = 0; c < count; ++c) {
-        HIP_CHECK(launch_ksolve(ka, m, st));
-        if (S.profile) HIP_CHECK(hipEventRecord(evs[2 * c], st));
-        HIP_CHECK(launch_iter(ia, kp, false, igrid, st));
-        if (S.profile) HIP_CHECK(hipEventRecord(evs[2 * c + 1], st));
-      }
+      for (int c = 0; c < count; ++c) HIP_CHECK(launch_iteration(c));
       if (S.profile) {
         HIP_CHECK(hipEventSynchronize(evs[2 * count - 1]));
         for (int c = 0; c < count; ++c) {
@@ -552,7 +567,8 @@ extern "C" fqp_error fqp_solve_batch(fqp_handle* h, const fqp_universe* U, const
     fqp_error be = run_block(count);
     if (be != FQP_OK) return be;
     done_iters += count;
-    // polish + certification rounds
+    // polish + certification rounds on z = prox(v; lam*)
+    HIP_CHECK(launch_materialize_z(ia, m, z, st));
     pa.nf_gate = std::max(4 * k + 64, n / 8 + 4 * k);
     for (int r = 0; r < S.polish_rounds; ++r) {
       pa.first_round = (r == 0);
@@ -572,6 +588,7 @@ extern "C" fqp_error fqp_solve_batch(fqp_handle* h, const fqp_universe* U, const
   }
   if (active > 0) {
     // last pattern from the current iterate, diagnostics, final statuses
+    HIP_CHECK(launch_materialize_z(ia, m, z, st));
     pa.first_round = 1;
     pa.nf_gate = 0;
     HIP_CHECK(launch_polish_solve(pa, st));

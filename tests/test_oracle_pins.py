@@ -236,3 +236,21 @@ def test_oracle_certifies_configs(name, over, seed):
         # the paper's quality gates (Sec. "Quality Gates and Failure
         # Vocabulary"): budget <= 1e-4, bound violation <= 1e-6
         assert r["r_budget"] <= 1e-4 and r["r_box"] <= 1e-6
+
+
+def test_crossover_recovers_multipliers_at_degenerate_vertex():
+    """At an LP-like vertex the free rows do not pin every multiplier; the
+    crossover must still return multipliers inside every fixed coordinate's
+    subdifferential even from perturbed interior-point estimates."""
+    from oracle.crossover import crossover
+    for name, over in [("c1", {}), ("c3", dict(N=600, M=1, k=8))]:
+        for seed in (0, 1, 2):
+            uni, book = make_config(name, seed, **over)
+            P = account(uni, book, 0)
+            r = solve_ipm(P)
+            for d_nu, d_lam in [(2e-4, 0.0), (-3e-4, 1e-3), (1e-5, -1e-3)]:
+                out = crossover(P, r.w, r.nu + d_nu, r.lam_band,
+                                max(r.lam_cap + d_lam, 0.0))
+                res = out["res"]
+                assert out["method"] == "crossover"
+                assert max(res["r_prim"], res["r_dual"], res["r_comp"]) < 1e-11
