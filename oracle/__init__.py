@@ -25,16 +25,34 @@ from .ipm import solve_ipm
 from .crossover import crossover
 
 
+def _score(out):
+    r = out["res"]
+    return max(r["r_prim"], r["r_dual"], r["r_comp"])
+
+
 def solve_account(P: AccountProblem, route: str = "schur", tol=1e-12,
-                  max_iter=200):
+                  max_iter=200, certify=1e-11):
     """Oracle solution of one account: dict with w, nu, lam_band, lam_cap,
-    res (external diagnostics), method, ipm_iters."""
-    r = solve_ipm(P, route=route, tol=tol, max_iter=max_iter)
-    out = crossover(P, r.w, r.nu, r.lam_band, r.lam_cap)
-    out["ipm_iters"] = r.iters
-    out["ipm_converged"] = r.converged
-    out["obj"] = out["res"]["obj"]
-    return out
+    res (external diagnostics), method, route, ipm_iters.
+
+    When the requested linear-algebra route does not reach a point the
+    crossover certifies to ``certify`` (the dense Schur complement can lose
+    definiteness to cancellation late in the iteration), the other route
+    is run and the better answer kept."""
+    best = None
+    routes = [route] + [r for r in ("schur", "sparse") if r != route]
+    for rt in routes:
+        r = solve_ipm(P, route=rt, tol=tol, max_iter=max_iter)
+        out = crossover(P, r.w, r.nu, r.lam_band, r.lam_cap)
+        out["ipm_iters"] = r.iters
+        out["ipm_converged"] = r.converged
+        out["route"] = rt
+        out["obj"] = out["res"]["obj"]
+        if best is None or _score(out) < _score(best):
+            best = out
+        if r.converged and _score(best) <= certify:
+            break
+    return best
 
 
 def solve_book(uni, book, accounts=None, **kw):

@@ -314,7 +314,18 @@ class SchurSolver:
             self.NLL, self.NLC = NLL, NLC
         else:
             S = NCC
-        self.cho = sla.cho_factor(S, lower=True)
+        # S is positive definite in exact arithmetic; late in the iteration
+        # the elimination of the lifted rows can cancel it to indefinite in
+        # float64, and an LU factorization then takes over
+        try:
+            self.cho, self.lu = sla.cho_factor(S, lower=True), None
+        except np.linalg.LinAlgError:
+            self.cho, self.lu = None, sla.lu_factor(S)
+
+    def _solve_s(self, rc):
+        if self.cho is not None:
+            return sla.cho_solve(self.cho, rc)
+        return sla.lu_solve(self.lu, rc)
 
     def solve(self, r):
         L = self.L
@@ -322,10 +333,10 @@ class SchurSolver:
         rc, rl = r[:m], r[m:]
         if L.lift:
             rc = rc - self.NLC.T @ (rl / self.NLL)
-            uc = sla.cho_solve(self.cho, rc)
+            uc = self._solve_s(rc)
             ul = (rl - self.NLC @ uc) / self.NLL
             return np.concatenate([uc, ul])
-        return sla.cho_solve(self.cho, rc)
+        return self._solve_s(rc)
 
 
 def _newton_sparse(L: Lifted, Asp, h, xi, rp):
@@ -465,6 +476,11 @@ def solve_ipm(P: AccountProblem, route: str = "schur", tol: float = 1e-12,
             if solver is not None:
                 rhs = -rp - amul(xi / h)
                 dlam = solver.solve(rhs)
+                # iterative refinement against the unformed normal matrix
+                # A H^-1 A^T (its formed Schur complement loses digits to
+                # cancellation when h spans many orders of magnitude)
+                for _ in range(2):
+                    dlam = dlam + solver.solve(rhs - amul(atmul(dlam) / h))
                 dx = (xi + atmul(dlam)) / h
             else:
                 dx, dlam = _newton_sparse(L, Asp, h, xi, rp)

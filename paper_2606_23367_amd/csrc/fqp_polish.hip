@@ -852,14 +852,26 @@ __global__ __launch_bounds__(256) void polish_check_kernel(PolishArgs A, fqp_res
         if (tid == 0) {
           Lo = Lb; Up = Ub;
           int kLo = s_key[0], kUp = s_key[1];
-          // complementarity target: zero the multiplier of a slack constraint
-          double tgt = 0.0, best = 0.0;
+          // targets along this direction, by priority: (1) an active
+          // constraint the solve could not enforce (dependent row) and that
+          // is violated: push its multiplier outward until a fixed row
+          // blocks, and release that row; (2) an active constraint that is
+          // slack: zero its multiplier (complementarity)
+          double tgt = 0.0, best = 0.0, worst = 0.0;
           bool has_tgt = false;
+          const double vtol = 0.1 * A.eps_prim;
           if (ps[PS_CAP]) {              // lam_cap + s ncap >= 0
             if (ncap > 1e-300) { const double u = -lamc / ncap; if (u > Lo) { Lo = u; kLo = INT_MAX; } }
             else if (ncap < -1e-300) { const double u = -lamc / ncap; if (u < Up) { Up = u; kUp = INT_MAX; } }
-            const double v = fabs(lamc) * fmax((double)tauf - turn0, 0.0);
-            if (fabs(ncap) > 1e-300 && v > thr && v > best) { best = v; tgt = -lamc / ncap; has_tgt = true; }
+            const double sl = (double)tauf - turn0;
+            if (fabs(ncap) > 1e-300) {
+              if (sl < -vtol && -sl > worst) {
+                worst = -sl; tgt = (ncap > 0.0) ? INFINITY : -INFINITY; has_tgt = true;
+              } else if (worst == 0.0) {
+                const double v = fabs(lamc) * fmax(sl, 0.0);
+                if (v > thr && v > best) { best = v; tgt = -lamc / ncap; has_tgt = true; }
+              }
+            }
           }
           int col = 1;
           for (int gg = 0; gg < G; ++gg) {
@@ -872,10 +884,15 @@ __global__ __launch_bounds__(256) void polish_check_kernel(PolishArgs A, fqp_res
             const double aa = sgn_req * nbv, bb = sgn_req * cur;   // bb + s aa >= 0
             if (aa > 1e-300) { const double u = -bb / aa; if (u > Lo) { Lo = u; kLo = INT_MAX; } }
             else if (aa < -1e-300) { const double u = -bb / aa; if (u < Up) { Up = u; kUp = INT_MAX; } }
-            const double slack = up ? (double)A.bhi[(size_t)a * G + gg] - s_gs[gg]
-                                    : s_gs[gg] - (double)A.blo[(size_t)a * G + gg];
-            const double v = fabs(cur) * fmax(slack, 0.0);
-            if (fabs(nbv) > 1e-300 && v > thr && v > best) { best = v; tgt = -cur / nbv; has_tgt = true; }
+            if (fabs(nbv) <= 1e-300) continue;
+            const double sl = up ? (double)A.bhi[(size_t)a * G + gg] - s_gs[gg]
+                                 : s_gs[gg] - (double)A.blo[(size_t)a * G + gg];
+            if (sl < -vtol && -sl > worst) {
+              worst = -sl; tgt = (aa > 0.0) ? INFINITY : -INFINITY; has_tgt = true;
+            } else if (worst == 0.0) {
+              const double v = fabs(cur) * fmax(sl, 0.0);
+              if (v > thr && v > best) { best = v; tgt = -cur / nbv; has_tgt = true; }
+            }
           }
           double st;
           if (Lo <= Up) {
