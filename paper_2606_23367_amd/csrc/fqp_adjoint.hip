@@ -41,7 +41,7 @@ __global__ __launch_bounds__(256) void adjoint_solve_kernel(AdjArgs A) {
     for (int j = tid; j < 2 * k; j += 256) A.yvw[(size_t)a * 2 * k + j] = 0.0;
     return;
   }
-  const int* ps = A.pstate + (size_t)a * 12;
+  const int* ps = A.pstate + (size_t)a * kPStateStride;
   const int nF = ps[PA_NF], nX = ps[PA_NX];
   const int cap_on = ps[PA_CAP];
   const int32_t* flist = A.flist + (size_t)a * n;

@@ -85,9 +85,9 @@ __device__ inline void chol_solve_cols(const double* L, int k, double* Y, int nc
   const int tid = threadIdx.x;
   for (int j = 0; j < k; ++j) {
     const double djj = L[j * k + j];
-    for (int c = tid; c < ncol; c += 256) Y[j * ncol + c] /= djj;
+    for (int c = tid; c < ncol; c += (int)blockDim.x) Y[j * ncol + c] /= djj;
     __syncthreads();
-    for (int e = tid; e < (k - j - 1) * ncol; e += 256) {
+    for (int e = tid; e < (k - j - 1) * ncol; e += (int)blockDim.x) {
       const int i = j + 1 + e / ncol, c = e % ncol;
       Y[i * ncol + c] -= L[i * k + j] * Y[j * ncol + c];
     }
@@ -95,9 +95,9 @@ __device__ inline void chol_solve_cols(const double* L, int k, double* Y, int nc
   }
   for (int j = k - 1; j >= 0; --j) {
     const double djj = L[j * k + j];
-    for (int c = tid; c < ncol; c += 256) Y[j * ncol + c] /= djj;
+    for (int c = tid; c < ncol; c += (int)blockDim.x) Y[j * ncol + c] /= djj;
     __syncthreads();
-    for (int e = tid; e < j * ncol; e += 256) {
+    for (int e = tid; e < j * ncol; e += (int)blockDim.x) {
       const int i = e / ncol, c = e % ncol;
       Y[i * ncol + c] -= L[j * k + i] * Y[j * ncol + c];
     }

@@ -418,8 +418,10 @@ __global__ __launch_bounds__(256, 2) void iter_kernel(IterArgs A) {
 // turnover(lam) = tau, found by Newton steps from the previous lam* inside a
 // bracket that every evaluation tightens (bisection when a step leaves it).
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void cap_kernel(IterArgs A) {
-  __shared__ float s_g[256], s_n[256];
+constexpr int kCapT = 1024;             // 16 waves per account: latency-bound passes
+
+__global__ __launch_bounds__(kCapT) void cap_kernel(IterArgs A) {
+  __shared__ float s_g[kCapT / 64], s_n[kCapT / 64];
   __shared__ float s_lam;
   __shared__ int s_done;
   const int slot = blockIdx.x;
@@ -437,22 +439,23 @@ __global__ __launch_bounds__(256) void cap_kernel(IterArgs A) {
   for (int it = 0; it < 48; ++it) {
     const float th = (kap + lam) * irho;
     float g = 0.f, nf = 0.f;
-    for (int i = tid; i < n; i += 256) {
+    for (int i = tid; i < n; i += kCapT) {
       const RowInfo ri = row_info(A, a, i, lbp, ubp);
       bool kink;
       const float z = prox_row(ri, A.v[(size_t)a * n + i], th, irho, A.tax_brk, A.tax_slope, &kink);
       g += fabsf(z - ri.w0);
       nf += kink ? 0.f : 1.f;
     }
-    s_g[tid] = g;
-    s_n[tid] = nf;
-    __syncthreads();
-    for (int o = 128; o >= 1; o >>= 1) {
-      if (tid < o) { s_g[tid] += s_g[tid + o]; s_n[tid] += s_n[tid + o]; }
-      __syncthreads();
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+      g += __shfl_xor(g, o, 64);
+      nf += __shfl_xor(nf, o, 64);
     }
+    if ((tid & 63) == 0) { s_g[tid >> 6] = g; s_n[tid >> 6] = nf; }
+    __syncthreads();
     if (tid == 0) {
-      const float gt = s_g[0], nft = s_n[0];
+      float gt = 0.f, nft = 0.f;
+      for (int q = 0; q < kCapT / 64; ++q) { gt += s_g[q]; nft += s_n[q]; }
       const float tol = 1e-6f * fmaxf(tau, 1e-6f);
       if (gt <= tau) { hi_b = lam; best_feas = lam; } else { lo = lam; }
       bool done = fabsf(gt - tau) <= tol || (lam == 0.f && gt <= tau);
@@ -656,7 +659,7 @@ hipError_t launch_iter(const IterArgs& A, int kp, int mode, dim3 grid, hipStream
 }
 
 hipError_t launch_cap(const IterArgs& A, int m_total, hipStream_t st) {
-  hipLaunchKernelGGL(cap_kernel, dim3(m_total), dim3(256), 0, st, A);
+  hipLaunchKernelGGL(cap_kernel, dim3(m_total), dim3(kCapT), 0, st, A);
   return hipGetLastError();
 }
 

@@ -96,6 +96,9 @@ hipError_t launch_pack_scan(const PackArgs& A, hipStream_t st);
 hipError_t launch_pack_fill(const PackArgs& A, hipStream_t st);
 
 // ---- polish / certification (float64) -------------------------------------
+// ints of polish bookkeeping per account
+constexpr int kPStateStride = 16;
+
 struct PolishArgs {
   int n, k, G, kp, W, m_total;
   const int* m_act;
@@ -127,10 +130,11 @@ struct PolishArgs {
   double* wout;              // [m][n] polished weights (caller output)
   double* gbase;             // [m][n] gamma (Sigma w)_i - mu_i of the pattern
   double* mult;              // [m][2 + G] nu, lam_cap, lam_band
-  int32_t* pstate;           // [m][8] polish bookkeeping
+  int32_t* pstate;           // [m][kPStateStride] polish bookkeeping
   double eps_prim, eps_dual, eps_comp;
   int first_round;           // classify from z when nonzero
   int nf_gate;               // skip patterns with more free rows (0: never)
+  int nf_small;              // larger free sets wait for a repeated pattern
 };
 hipError_t launch_polish_solve(const PolishArgs& A, hipStream_t st);
 size_t polish_wk_stride(int k, int G);

@@ -35,11 +35,18 @@ namespace fqp {
 
 enum PState {
   PS_CAP = 0, PS_NF, PS_NX, PS_NC, PS_DONE, PS_ROUNDS,
-  PS_BACT0, PS_BACT1, PS_BUP0, PS_BUP1, PS_STALL, PS_ND, kNPState = 12
+  PS_BACT0, PS_BACT1, PS_BUP0, PS_BUP1, PS_STALL, PS_ND, PS_SIG, kNPState
 };
+static_assert(kNPState <= kPStateStride, "polish bookkeeping does not fit");
 
 constexpr double kSnap = 1e-10;
 constexpr int kMaxNull = 8;
+// one workgroup per account: the row passes are latency bound, so an
+// account gets 16 waves in the solve and 8 in the check (whose per-row
+// geometry needs more than the 128 registers a 16-wave group allows)
+constexpr int kPT = 1024;                 // polish_solve
+constexpr int kPTC = 512;                 // polish_check
+constexpr int kPW = kPT / 64;             // most waves of either
 
 struct Geom {
   int np;            // points on the asset's line: bounds and inner kinks
@@ -184,47 +191,31 @@ __device__ __forceinline__ void set_band(int* ps, int g, bool act, bool up) {
   *pu = up ? (*pu | (1 << b)) : (*pu & ~(1 << b));
 }
 
+// block reductions: wave shuffles, then one partial per wave
 template <typename T>
 __device__ T bsum(T v, T* sh) {
-  sh[threadIdx.x] = v;
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
   __syncthreads();
-  for (int o = 128; o >= 1; o >>= 1) {
-    if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
-    __syncthreads();
-  }
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
   T r = sh[0];
-  __syncthreads();
+  const int nw = (int)(blockDim.x >> 6);
+  for (int q = 1; q < nw; ++q) r += sh[q];
   return r;
 }
 template <typename T>
 __device__ T bmax(T v, T* sh) {
-  sh[threadIdx.x] = v;
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
   __syncthreads();
-  for (int o = 128; o >= 1; o >>= 1) {
-    if (threadIdx.x < o) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + o]);
-    __syncthreads();
-  }
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
   T r = sh[0];
-  __syncthreads();
+  const int nw = (int)(blockDim.x >> 6);
+  for (int q = 1; q < nw; ++q) r = fmax(r, sh[q]);
   return r;
 }
-
-// exclusive block scan of an int flag; returns the prefix, total in *tot
-__device__ int bscan(int v, int* sh, int* tot) {
-  sh[threadIdx.x] = v;
-  __syncthreads();
-  for (int o = 1; o < 256; o <<= 1) {
-    int t = (threadIdx.x >= o) ? sh[threadIdx.x - o] : 0;
-    __syncthreads();
-    sh[threadIdx.x] += t;
-    __syncthreads();
-  }
-  const int incl = sh[threadIdx.x];
-  *tot = sh[255];
-  __syncthreads();
-  return incl - v;
-}
-
 
 // Sums over a list of rows (LDS-staged, 64 rows at a time):
 //   ys[j] += sum_t B[i_t][j] w[i_t]   (thread j < k)
@@ -243,7 +234,7 @@ __device__ void list_sums(const PolishArgs& A, const int32_t* list, int n, int c
       sw[tid] = w[i];
     }
     __syncthreads();
-    for (int e = tid; e < rows * k; e += 256) {
+    for (int e = tid; e < rows * k; e += (int)blockDim.x) {
       const int rr = e / k, j = e % k;
       sB[rr * (k + 1) + j] = A.Bt[(size_t)si[rr] * A.kp + j];
     }
@@ -259,21 +250,21 @@ __device__ void list_sums(const PolishArgs& A, const int32_t* list, int n, int c
 // ---------------------------------------------------------------------------
 // polish_solve: classify (first round), lists, reduced KKT solve, w
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void polish_solve_kernel(PolishArgs A) {
+__global__ __launch_bounds__(kPT) void polish_solve_kernel(PolishArgs A) {
   extern __shared__ double smem_d[];
   const int k = A.k, G = A.G, n = A.n;
   double* Kf = smem_d;                      // [k][k]
   // the Kf region also stages 64 float B rows before Kf is built
   const int kfsz = max(k * k, (64 * (k + 1) + 1) / 2);
   double* stg = Kf + kfsz;                  // staging: 16 rows x (k + 4)
-  __shared__ double shd[256];
-  __shared__ int shi[256];
-  __shared__ int s_cnt[2];
+  __shared__ double shd[kPW];
+  __shared__ unsigned s_sig[kPW];
+  __shared__ int s_cnt[2], s_same;
   const int slot = blockIdx.x;
   if (slot >= *A.m_act) return;
   const int a = A.act[slot];
   const int tid = threadIdx.x;
-  int* ps = A.pstate + (size_t)a * kNPState;
+  int* ps = A.pstate + (size_t)a * kPStateStride;
   const float* par = A.par + (size_t)a * kNPar;
   const float lbf = par[P_LB], ubf = par[P_UB], kap = par[P_KAPPA], tauf = par[P_TAU];
   const double gam = par[P_GAMMA];
@@ -301,7 +292,8 @@ __global__ __launch_bounds__(256) void polish_solve_kernel(PolishArgs A) {
         mult[2 + g] = (double)par[P_RHOB] * (double)A.vb[(size_t)a * G + g];
       }
     }
-    for (int i = tid; i < n; i += 256) {
+    unsigned sig = 0u;                        // signature of the pattern
+    for (int i = tid; i < n; i += kPT) {
       RowData r = row_data(A, a, i);
       Geom g;
       make_geom(g, r.el, lbf, ubf, r.w0, kap, phi, r.ti, A.tax_brk, A.tax_slope);
@@ -317,6 +309,14 @@ __global__ __launch_bounds__(256) void polish_solve_kernel(PolishArgs A) {
         if (g.np > 1 && (double)z >= g.pt[g.np - 1]) c = 2 * (g.np - 1);
       }
       code[i] = (int8_t)c;
+      sig += (unsigned)(c + 1) * ((unsigned)i * 2654435761u + 1u);
+    }
+    sig = bsum<unsigned>(sig, s_sig);
+    if (tid == 0) {
+      sig += (unsigned)ps[PS_CAP] * 97u + (unsigned)ps[PS_BACT0] * 31u + (unsigned)ps[PS_BACT1] * 7u +
+             (unsigned)ps[PS_BUP0] * 5u + (unsigned)ps[PS_BUP1] * 3u;
+      s_same = (unsigned)ps[PS_SIG] == sig;
+      ps[PS_SIG] = (int)sig;
     }
     __syncthreads();
   }
@@ -326,13 +326,13 @@ __global__ __launch_bounds__(256) void polish_solve_kernel(PolishArgs A) {
   // ---- pass 1: fixed values, free list, nonzero-fixed list --------------
   // free rows are listed from the front of flist, nonzero fixed rows from
   // the back (wave ballots + a 4-entry prefix per chunk).
-  __shared__ int s_wc[2][kWaves][2];
+  __shared__ int s_wc[2][kPW][2];
   if (tid == 0) { s_cnt[0] = 0; s_cnt[1] = 0; }
   __syncthreads();
   {
     const int lane = tid & 63, wv = tid >> 6;
     int it = 0;
-    for (int base = 0; base < n; base += 256, ++it) {
+    for (int base = 0; base < n; base += kPT, ++it) {
       const int i = base + tid;
       int isfree = 0, isnz = 0;
       if (i < n) {
@@ -355,7 +355,7 @@ __global__ __launch_bounds__(256) void polish_solve_kernel(PolishArgs A) {
       if (lane == 0) { s_wc[par_][wv][0] = __popcll(mf); s_wc[par_][wv][1] = __popcll(mn); }
       __syncthreads();
       int pf = __popcll(mf & below), pn = __popcll(mn & below), tf = 0, tn = 0;
-      for (int q = 0; q < kWaves; ++q) {
+      for (int q = 0; q < kPW; ++q) {
         if (q < wv) { pf += s_wc[par_][q][0]; pn += s_wc[par_][q][1]; }
         tf += s_wc[par_][q][0];
         tn += s_wc[par_][q][1];
@@ -372,6 +372,12 @@ __global__ __launch_bounds__(256) void polish_solve_kernel(PolishArgs A) {
   // a pattern with many free coordinates belongs to an iterate that is far
   // from the optimum's vertex structure: skip the (costly) solve for now
   if (A.nf_gate > 0 && nF > A.nf_gate) {
+    if (tid == 0) { ps[PS_STALL] = 1; ps[PS_NF] = nF; }
+    return;
+  }
+  // a larger free set is solved only when the iterate shows the same
+  // pattern at two consecutive checks
+  if (A.first_round && A.nf_small > 0 && nF > A.nf_small && !s_same) {
     if (tid == 0) { ps[PS_STALL] = 1; ps[PS_NF] = nF; }
     return;
   }
@@ -395,9 +401,9 @@ __global__ __launch_bounds__(256) void polish_solve_kernel(PolishArgs A) {
   const int ncol = nc + 1;                      // + rhs column
   {
     double sx = 0.0, sturn = 0.0;
-    for (int t = tid; t < nX; t += 256) sx += w[flist[n - 1 - t]];
+    for (int t = tid; t < nX; t += kPT) sx += w[flist[n - 1 - t]];
     // turnover of fixed rows: every row not free (including zeros)
-    for (int i = tid; i < n; i += 256) {
+    for (int i = tid; i < n; i += kPT) {
       if (code[i] & 1) continue;
       RowData r = row_data(A, a, i);
       sturn += fabs(w[i] - (double)r.w0);
@@ -422,77 +428,86 @@ __global__ __launch_bounds__(256) void polish_solve_kernel(PolishArgs A) {
   __syncthreads();
 
   // ---- Kf = diag(1/f) + sum_F b b^T / d  (lower triangle, LDS) -----------
-  const int ntri = k * (k + 1) / 2;
-  for (int e = tid; e < k * k; e += 256) Kf[e] = 0.0;
-  __syncthreads();
-  const int SR = 16, SS = k + 4;
+  // one 4 x 4 register tile of the lower triangle per thread; staged rows
+  // are zero-padded to a multiple of 4 columns, 1/d_i follows them
+  for (int e = tid; e < k * k; e += kPT) Kf[e] = 0.0;
+  const int kt = (k + 3) >> 2;
+  const int SR = 16, SS = 4 * kt + 4;
   {
-    double acc[33];
-    int ej[33], el_[33];
+    double acc[16];
 #pragma unroll
-    for (int c = 0; c < 33; ++c) {
-      acc[c] = 0.0;
-      const int e = tid + 256 * c;
-      int j = (int)((sqrt(8.0 * e + 1.0) - 1.0) * 0.5);
-      while ((j + 1) * (j + 2) / 2 <= e) ++j;
-      while (j * (j + 1) / 2 > e) --j;
-      ej[c] = (e < ntri) ? j : 0;
-      el_[c] = (e < ntri) ? e - j * (j + 1) / 2 : 0;
+    for (int c = 0; c < 16; ++c) acc[c] = 0.0;
+    const int ntile = kt * (kt + 1) / 2;
+    const bool own = tid < ntile;
+    int tj = 0, tl = 0;
+    if (own) {
+      int j = (int)((sqrt(8.0 * tid + 1.0) - 1.0) * 0.5);
+      while ((j + 1) * (j + 2) / 2 <= tid) ++j;
+      while (j * (j + 1) / 2 > tid) --j;
+      tj = j;
+      tl = tid - j * (j + 1) / 2;
     }
     for (int f0 = 0; f0 < nF; f0 += SR) {
       const int rows = min(SR, nF - f0);
       __syncthreads();
-      for (int e = tid; e < rows * k; e += 256) {
-        const int rr = e / k, j = e % k;
+      for (int e = tid; e < rows * 4 * kt; e += kPT) {
+        const int rr = e / (4 * kt), j = e % (4 * kt);
         const int i = flist[f0 + rr];
-        stg[rr * SS + j] = (double)A.Bt[(size_t)i * A.kp + j];
+        stg[rr * SS + j] = (j < k) ? (double)A.Bt[(size_t)i * A.kp + j] : 0.0;
       }
-      for (int rr = tid; rr < rows; rr += 256) stg[rr * SS + k] = 1.0 / (double)A.d[flist[f0 + rr]];
+      for (int rr = tid; rr < rows; rr += kPT) stg[rr * SS + 4 * kt] = 1.0 / (double)A.d[flist[f0 + rr]];
       __syncthreads();
-      for (int rr = 0; rr < rows; ++rr) {
-        const double* b = stg + rr * SS;
-        const double id = b[k];
+      if (own) {
+        for (int rr = 0; rr < rows; ++rr) {
+          const double* b = stg + rr * SS;
+          const double id = b[4 * kt];
+          double bj[4], bl[4];
 #pragma unroll
-        for (int c = 0; c < 33; ++c) acc[c] += b[ej[c]] * b[el_[c]] * id;
+          for (int q = 0; q < 4; ++q) { bj[q] = b[4 * tj + q] * id; bl[q] = b[4 * tl + q]; }
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) acc[q * 4 + r] += bj[q] * bl[r];
+        }
       }
     }
+    if (own) {
 #pragma unroll
-    for (int c = 0; c < 33; ++c) {
-      const int e = tid + 256 * c;
-      if (e < ntri) {
-        const int j = ej[c], l = el_[c];
-        double v = acc[c];
-        if (j == l) v += 1.0 / (double)A.f[j];
-        Kf[j * k + l] = v;
-      }
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int j = 4 * tj + q, l = 4 * tl + r;
+          if (j < k && l <= j) {
+            double v = acc[q * 4 + r];
+            if (j == l) v += 1.0 / (double)A.f[j];
+            Kf[j * k + l] = v;
+          }
+        }
     }
   }
   __syncthreads();
 
   // ---- Waug = sum_F b V^T / d,  CV = sum_F V V^T / d  ---------------------
   // V_i = [1, band indicators (active order), sgn_i (cap), rhs_i],
-  // rhs_i = mu_i - slope_i - gamma b_i . F yX
+  // rhs_i = mu_i - slope_i - gamma b_i . F yX.  With X_i = [b_i | V_i] both
+  // blocks are X^T D^-1 V: one 4 x 4 register tile per thread.
   double sgn_w0 = 0.0;
   {
-    const int nW = k * ncol, nCV = ncol * ncol, ne2 = nW + nCV;
-    double acc[48];
-    short ia[48], ib[48];     // (B column or V column, V column); ia < 0: unused
+    const int kx = k + ncol;
+    const int xt = (kx + 3) >> 2, vt = (ncol + 3) >> 2;
+    const int CS = 4 * xt + 4;                // 1/d_i at index 4 xt
+    const bool own = tid < xt * vt;
+    const int tj = own ? tid / vt : 0, tl = own ? tid % vt : 0;
+    double acc[16];
 #pragma unroll
-    for (int c = 0; c < 48; ++c) {
-      acc[c] = 0.0;
-      const int e = tid + 256 * c;
-      if (e < nW) { ia[c] = (short)(e / ncol); ib[c] = (short)(e % ncol); }
-      else if (e < ne2) { ia[c] = (short)(1000 + (e - nW) / ncol); ib[c] = (short)((e - nW) % ncol); }
-      else { ia[c] = -1; ib[c] = 0; }
-    }
-    double* vst = stg + SR * SS;       // per staged row: ncol values
+    for (int c = 0; c < 16; ++c) acc[c] = 0.0;
     for (int f0 = 0; f0 < nF; f0 += SR) {
       const int rows = min(SR, nF - f0);
       __syncthreads();
-      for (int e = tid; e < rows * k; e += 256) {
-        const int rr = e / k, j = e % k;
+      for (int e = tid; e < rows * 4 * xt; e += kPT) {
+        const int rr = e / (4 * xt), j = e % (4 * xt);
         const int i = flist[f0 + rr];
-        stg[rr * SS + j] = (double)A.Bt[(size_t)i * A.kp + j];
+        stg[rr * CS + j] = (j < k) ? (double)A.Bt[(size_t)i * A.kp + j] : 0.0;
       }
       __syncthreads();
       if (tid < rows) {
@@ -503,9 +518,10 @@ __global__ __launch_bounds__(256) void polish_solve_kernel(PolishArgs A) {
         make_geom(g, r.el, lbf, ubf, r.w0, kap, phi, r.ti, A.tax_brk, A.tax_slope);
         double slope, sgn;
         piece_slope(g, code[i] >> 1, slope, sgn);
+        double* x = stg + rr * CS;
         double cross = 0.0;
-        for (int j = 0; j < k; ++j) cross += stg[rr * SS + j] * wk.Fy[j];
-        double* v = vst + rr * ncol;
+        for (int j = 0; j < k; ++j) cross += x[j] * wk.Fy[j];
+        double* v = x + k;
         v[0] = 1.0;
         int col = 1;
         for (int gg = 0; gg < G; ++gg) {
@@ -514,27 +530,37 @@ __global__ __launch_bounds__(256) void polish_solve_kernel(PolishArgs A) {
         }
         if (cap_on) v[col++] = sgn;
         v[col] = (double)A.mu[(size_t)a * n + i] - slope - gam * cross;
-        stg[rr * SS + k] = 1.0 / (double)A.d[i];
+        x[4 * xt] = 1.0 / (double)A.d[i];
         sgn_w0 += sgn * (double)r.w0;
       }
       __syncthreads();
-      for (int rr = 0; rr < rows; ++rr) {
-        const double* b = stg + rr * SS;
-        const double* v = vst + rr * ncol;
-        const double id = b[k];
+      if (own) {
+        for (int rr = 0; rr < rows; ++rr) {
+          const double* x = stg + rr * CS;
+          const double id = x[4 * xt];
+          double xl[4], vr[4];
 #pragma unroll
-        for (int c = 0; c < 48; ++c) {
-          if (ia[c] < 0) continue;
-          const double x = (ia[c] >= 1000) ? v[ia[c] - 1000] : b[ia[c]];
-          acc[c] += x * v[ib[c]] * id;
+          for (int q = 0; q < 4; ++q) {
+            xl[q] = x[4 * tj + q] * id;
+            vr[q] = (4 * tl + q < ncol) ? x[k + 4 * tl + q] : 0.0;
+          }
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) acc[q * 4 + r] += xl[q] * vr[r];
         }
       }
     }
+    if (own) {
 #pragma unroll
-    for (int c = 0; c < 48; ++c) {
-      const int e = tid + 256 * c;
-      if (e < nW) wk.Waug[e] = acc[c];
-      else if (e < ne2) wk.CV[e - nW] = acc[c];
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int j = 4 * tj + q, l = 4 * tl + r;
+          if (j >= kx || l >= ncol) continue;
+          if (j < k) wk.Waug[j * ncol + l] = acc[q * 4 + r];
+          else wk.CV[(j - k) * ncol + l] = acc[q * 4 + r];
+        }
     }
   }
   sgn_w0 = bsum<double>(sgn_w0, shd);
@@ -546,22 +572,22 @@ __global__ __launch_bounds__(256) void polish_solve_kernel(PolishArgs A) {
     if (tid == 0) Kf[j * k + j] = sqrt(fmax(Kf[j * k + j], 1e-300));
     __syncthreads();
     const double djj = Kf[j * k + j];
-    for (int i = j + 1 + tid; i < k; i += 256) Kf[i * k + j] /= djj;
+    for (int i = j + 1 + tid; i < k; i += kPT) Kf[i * k + j] /= djj;
     __syncthreads();
     const int m = k - j - 1;
-    for (int e = tid; e < m * m; e += 256) {
+    for (int e = tid; e < m * m; e += kPT) {
       const int i = j + 1 + e / m, l = j + 1 + e % m;
       if (l <= i) Kf[i * k + l] -= Kf[i * k + j] * Kf[l * k + j];
     }
     __syncthreads();
   }
   // ---- Y = Kf^-1 Waug -------------------------------------------------------
-  for (int e = tid; e < k * ncol; e += 256) wk.Y[e] = wk.Waug[e];
+  for (int e = tid; e < k * ncol; e += kPT) wk.Y[e] = wk.Waug[e];
   __syncthreads();
   chol_solve_cols(Kf, k, wk.Y, ncol);
   // ---- Schur system on the constraint columns ------------------------------
   // gamma * C H^-1 V = CV[C, V] - Waug[:, C]^T Y[:, V]
-  for (int e = tid; e < nc * ncol; e += 256) {
+  for (int e = tid; e < nc * ncol; e += kPT) {
     const int p = e / ncol, q = e % ncol;
     double s = wk.CV[p * ncol + q];
     for (int j = 0; j < k; ++j) s -= wk.Waug[j * ncol + p] * wk.Y[j * ncol + q];
@@ -662,14 +688,14 @@ __global__ __launch_bounds__(256) void polish_solve_kernel(PolishArgs A) {
   }
   __syncthreads();
   // sol = Y[:, rhs] - Y[:, C] eta
-  for (int j = tid; j < k; j += 256) {
+  for (int j = tid; j < k; j += kPT) {
     double s = wk.Y[j * ncol + nc];
     for (int p = 0; p < nc; ++p) s -= wk.Y[j * ncol + p] * wk.eta[p];
     wk.sol[j] = s;
   }
   __syncthreads();
   // ---- free rows: w_i = (rhs_i - C_i^T eta - b_i . sol) / (gamma d_i) ----
-  for (int t = tid; t < nF; t += 256) {
+  for (int t = tid; t < nF; t += kPT) {
     const int i = flist[t];
     RowData r = row_data(A, a, i);
     Geom g;
@@ -698,10 +724,10 @@ __global__ __launch_bounds__(256) void polish_solve_kernel(PolishArgs A) {
 // ---------------------------------------------------------------------------
 // polish_check: external diagnostics in float64 and refinement
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void polish_check_kernel(PolishArgs A, fqp_result R,
+__global__ __launch_bounds__(kPTC) void polish_check_kernel(PolishArgs A, fqp_result R,
                                                           int final_pass) {
-  extern __shared__ float sBrow[];        // [256][k + 1]
-  __shared__ double shd[256];
+  extern __shared__ float sBrow[];        // [64][k + 1] staged B rows
+  __shared__ double shd[kPW];
   __shared__ double s_y[kMaxK];
   __shared__ double s_gs[kMaxG];
   const int k = A.k, G = A.G, n = A.n;
@@ -709,7 +735,7 @@ __global__ __launch_bounds__(256) void polish_check_kernel(PolishArgs A, fqp_res
   if (slot >= *A.m_act) return;
   const int a = A.act[slot];
   const int tid = threadIdx.x;
-  int* ps = A.pstate + (size_t)a * kNPState;
+  int* ps = A.pstate + (size_t)a * kPStateStride;
   if (ps[PS_DONE] || (ps[PS_STALL] && !final_pass)) return;
   __shared__ int s_changed;
   if (tid == 0) s_changed = 0;
@@ -724,7 +750,7 @@ __global__ __launch_bounds__(256) void polish_check_kernel(PolishArgs A, fqp_res
   const double* w = A.wout + (size_t)a * n;
   double* gmult = A.mult + (size_t)a * (2 + G);
   __shared__ double mult[2 + kMaxG];
-  for (int q = tid; q < 2 + G; q += 256) mult[q] = gmult[q];
+  for (int q = tid; q < 2 + G; q += kPTC) mult[q] = gmult[q];
   const int nF = ps[PS_NF], nX = ps[PS_NX];
   double* gb = A.gbase + (size_t)a * n;
   __shared__ int s_bad, s_done;
@@ -743,31 +769,33 @@ __global__ __launch_bounds__(256) void polish_check_kernel(PolishArgs A, fqp_res
   }
   __syncthreads();
 
-  // ---- gradient base  gb_i = gamma (Sigma w)_i - mu_i  (B rows via LDS) ----
+  // ---- gradient base  gb_i = gamma (Sigma w)_i - mu_i -----------------------
+  // four lanes per row split the dot product b_i . y (a wave reads 16
+  // consecutive rows of B~ at once), then one lane finishes the row
   double gmax = 0.0, mumax = 0.0, turn0 = 0.0;
   int bad = 0;
-  const int BS1 = k + 1;
-  for (int base = 0; base < n; base += 256) {
-    __syncthreads();
-    const int rows = min(256, n - base);
-    for (int e = tid; e < rows * k; e += 256) {
-      const int rr = e / k, j = e % k;
-      sBrow[rr * BS1 + j] = A.Bt[(size_t)(base + rr) * A.kp + j];
+  {
+    const int q4 = tid & 3;
+    for (int base = 0; base < n; base += kPTC / 4) {
+      const int i = base + (tid >> 2);
+      double sig = 0.0;
+      if (i < n) {
+        const float* brow = A.Bt + (size_t)i * A.kp;
+        for (int j = q4; j < k; j += 4) sig += (double)brow[j] * s_y[j];
+      }
+      sig += __shfl_xor(sig, 1, 64);
+      sig += __shfl_xor(sig, 2, 64);
+      if (i < n && q4 == 0) {
+        sig += (double)A.d[i] * w[i];
+        const double mui = A.mu[(size_t)a * n + i];
+        const double v = gam * sig - mui;
+        gb[i] = v;
+        gmax = fmax(gmax, fabs(gam * sig));
+        mumax = fmax(mumax, fabs(mui));
+        turn0 += fabs(w[i] - (double)row_data(A, a, i).w0);
+        if (!isfinite(v) || !isfinite(w[i])) bad = 1;
+      }
     }
-    __syncthreads();
-    const int i = base + tid;
-    if (i >= n) continue;
-    double sig = 0.0;
-    const float* brow = sBrow + tid * BS1;
-    for (int j = 0; j < k; ++j) sig += (double)brow[j] * s_y[j];
-    sig += (double)A.d[i] * w[i];
-    const double mui = A.mu[(size_t)a * n + i];
-    const double v = gam * sig - mui;
-    gb[i] = v;
-    gmax = fmax(gmax, fabs(gam * sig));
-    mumax = fmax(mumax, fabs(mui));
-    turn0 += fabs(w[i] - (double)row_data(A, a, i).w0);
-    if (!isfinite(v) || !isfinite(w[i])) bad = 1;
   }
   if (bad) atomicOr(&s_bad, 1);
   gmax = bmax<double>(gmax, shd);
@@ -802,7 +830,7 @@ __global__ __launch_bounds__(256) void polish_check_kernel(PolishArgs A, fqp_res
         const double lamc = mult[1];
         double Lo = -INFINITY, Up = INFINITY;
         int loKey = INT_MAX, upKey = INT_MAX;
-        for (int i = tid; i < n; i += 256) {
+        for (int i = tid; i < n; i += kPTC) {
           const int c = code_r[i];
           if (c & 1) continue;
           RowData r = row_data(A, a, i);
@@ -922,7 +950,7 @@ __global__ __launch_bounds__(256) void polish_check_kernel(PolishArgs A, fqp_res
   const double nu = mult[0], lam = mult[1];
 
   double sw = 0.0, turn = 0.0, dmax = 0.0, box = 0.0, snapm = 0.0, obj = 0.0;
-  for (int i = tid; i < n; i += 256) {
+  for (int i = tid; i < n; i += kPTC) {
     RowData r = row_data(A, a, i);
     Geom g;
     make_geom(g, r.el, lbf, ubf, r.w0, kap, phi, r.ti, A.tax_brk, A.tax_slope);
@@ -1052,21 +1080,22 @@ __global__ __launch_bounds__(256) void polish_check_kernel(PolishArgs A, fqp_res
   __syncthreads();
   if (final_pass || s_done) {
     if (R.lam_band && G) {
-      for (int g = tid; g < G; g += 256) R.lam_band[(size_t)a * G + g] = mult[2 + g];
+      for (int g = tid; g < G; g += kPTC) R.lam_band[(size_t)a * G + g] = mult[2 + g];
     }
   } else {
     // the pattern failed: adopt the proposals for the next round
-    for (int i = tid; i < n; i += 256) code_r[i] = code[i];
+    for (int i = tid; i < n; i += kPTC) code_r[i] = code[i];
   }
 }
 
 static size_t polish_smem(int k) {
-  // Kf (k^2 doubles), staging (16 rows of k + 4 doubles), V rows
-  // (16 x (kMaxG + 3) doubles); the Kf region first holds 64 staged B rows
-  // (64 (k + 1) floats) and the staging region 64 weights + 64 indices
+  // Kf (k^2 doubles) and a staging region; the Kf region first holds 64
+  // staged B rows (64 (k + 1) floats) and the staging region 64 weights +
+  // 64 indices
   const size_t a = sizeof(double) * ((size_t)k * k);
   const size_t b = sizeof(float) * 64 * (size_t)(k + 1);
-  const size_t rest = sizeof(double) * (16 * (size_t)(k + 4) + 16 * (size_t)(kMaxG + 3));
+  // staging: 16 rows of [b | V | pad | 1/d]
+  const size_t rest = sizeof(double) * 16 * (size_t)(4 * ((k + kMaxG + 3 + 3) / 4) + 4);
   return (a > b ? a : b) + (rest > 64 * 12 ? rest : 64 * 12);
 }
 
@@ -1075,17 +1104,17 @@ hipError_t launch_polish_solve(const PolishArgs& A, hipStream_t st) {
   hipError_t e = hipFuncSetAttribute((const void*)polish_solve_kernel,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(polish_solve_kernel, dim3(A.m_total), dim3(256), smem, st, A);
+  hipLaunchKernelGGL(polish_solve_kernel, dim3(A.m_total), dim3(kPT), smem, st, A);
   return hipGetLastError();
 }
 
 hipError_t launch_polish_check_r(const PolishArgs& A, const fqp_result& R, int final_pass,
                                  hipStream_t st) {
-  const size_t smem = sizeof(float) * 256 * (size_t)(A.k + 1);
+  const size_t smem = sizeof(float) * 64 * (size_t)(A.k + 1);
   hipError_t e = hipFuncSetAttribute((const void*)polish_check_kernel,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(polish_check_kernel, dim3(A.m_total), dim3(256), smem, st, A, R, final_pass);
+  hipLaunchKernelGGL(polish_check_kernel, dim3(A.m_total), dim3(kPTC), smem, st, A, R, final_pass);
   return hipGetLastError();
 }
 

@@ -407,7 +407,7 @@ extern "C" fqp_error fqp_solve_batch(fqp_handle* h, const fqp_universe* U, const
   WS(wk, double, "polish_wk", (size_t)m * wks);
   WS(mult, double, "mult", (size_t)m * (2 + G));
   WS(gbase, double, "gbase", (size_t)m * n);
-  WS(pstate, int32_t, "pstate", (size_t)m * 12);
+  WS(pstate, int32_t, "pstate", (size_t)m * kPStateStride);
 
   // iteration geometry: ~1024 workgroups over (row tiles x account tiles)
   const int acc_tiles = (m + kTM - 1) / kTM;
@@ -447,7 +447,7 @@ extern "C" fqp_error fqp_solve_batch(fqp_handle* h, const fqp_universe* U, const
   HIP_CHECK(launch_pack_fill(pk, st));
   hipLaunchKernelGGL(init_accounts_kernel, dim3((m + 255) / 256), dim3(256), 0, st, m, G, cls_d,
                      rho_d, P->gamma, P->kappa, P->lb, P->ub, P->tau, P->tax_ptr, S.alpha, rho_b,
-                     par, zb, vb, P->band_lo, P->band_hi, iters, pstate, 12);
+                     par, zb, vb, P->band_lo, P->band_hi, iters, pstate, kPStateStride);
   HIP_CHECK(hipGetLastError());
   HIP_CHECK(hipMemsetAsync(v, 0, sizeof(float) * (size_t)m * n, st));
   hipLaunchKernelGGL(compact_kernel, dim3(1), dim3(256), 0, st, m, R->status, act, m_act);
@@ -570,6 +570,7 @@ extern "C" fqp_error fqp_solve_batch(fqp_handle* h, const fqp_universe* U, const
     // polish + certification rounds on z = prox(v; lam*)
     HIP_CHECK(launch_materialize_z(ia, m, z, st));
     pa.nf_gate = std::max(4 * k + 64, n / 8 + 4 * k);
+    pa.nf_small = 2 * k + 32;
     for (int r = 0; r < S.polish_rounds; ++r) {
       pa.first_round = (r == 0);
       HIP_CHECK(launch_polish_solve(pa, st));
@@ -591,6 +592,7 @@ extern "C" fqp_error fqp_solve_batch(fqp_handle* h, const fqp_universe* U, const
     HIP_CHECK(launch_materialize_z(ia, m, z, st));
     pa.first_round = 1;
     pa.nf_gate = 0;
+    pa.nf_small = 0;
     HIP_CHECK(launch_polish_solve(pa, st));
     HIP_CHECK(launch_polish_check_r(pa, *R, 1, st));
     if (timed_out) {
