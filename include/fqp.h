@@ -105,6 +105,16 @@ typedef struct fqp_book {
   const float *tax_slope;    /* [nnz][4] lot slopes, 0 <= s0 <= .. <= s3     */
 } fqp_book;
 
+/* Arithmetic of the factor contractions inside the ADMM iterations (the
+ * polish and the certificate are float64 either way). */
+typedef enum {
+  FQP_PREC_FP32 = 0,    /* float32 MFMA (32x32x2)                           */
+  FQP_PREC_BF16X3 = 1   /* bf16 MFMA on hi/lo splits of each float32 operand:
+                           hi*hi + hi*lo + lo*hi, float32 accumulation
+                           (factor blocks k + n_groups + 1 <= 96; wider ones
+                           run the float32 contraction)                    */
+} fqp_precision;
+
 typedef struct fqp_settings {
   double eps_prim;       /* absolute primal residual target (1e-6)        */
   double eps_dual;       /* scaled stationarity target (1e-6)             */
@@ -118,6 +128,7 @@ typedef struct fqp_settings {
   int32_t use_graph;     /* capture each block of iterations in a hipGraph */
   int32_t profile;       /* time every fused iteration launch with events */
   double time_limit_ms;  /* wall-clock limit of the call (<= 0: none)     */
+  int32_t precision;     /* fqp_precision of the ADMM contractions        */
 } fqp_settings;
 
 /* Outputs (device pointers, caller-owned).  Any may be NULL except w and
@@ -146,6 +157,10 @@ typedef struct fqp_stats {
   double account_iters;     /* sum over accounts of iterations run          */
   double total_ms;          /* host wall-clock of the call                  */
   size_t workspace_bytes;   /* device workspace held by the handle          */
+  int32_t polish_solves;    /* reduced float64 KKT systems formed (accounts
+                               x polish rounds)                            */
+  int32_t polish_gated;     /* polish attempts skipped because the iterate's
+                               pattern was not yet settled                 */
 } fqp_stats;
 
 FQP_API void fqp_default_settings(fqp_settings *s);

@@ -46,7 +46,7 @@ class Settings(ctypes.Structure):
                 ("rho_band", c_float), ("alpha", c_float),
                 ("polish_rounds", c_int32),
                 ("use_graph", c_int32), ("profile", c_int32),
-                ("time_limit_ms", c_double)]
+                ("time_limit_ms", c_double), ("precision", c_int32)]
 
 
 class Result(ctypes.Structure):
@@ -60,7 +60,8 @@ class Stats(ctypes.Structure):
     _fields_ = [("iterations", c_int32), ("iter_launches", c_int32),
                 ("polish_calls", c_int32), ("n_solved", c_int32),
                 ("iter_kernel_ms", c_double), ("account_iters", c_double),
-                ("total_ms", c_double), ("workspace_bytes", c_size_t)]
+                ("total_ms", c_double), ("workspace_bytes", c_size_t),
+                ("polish_solves", c_int32), ("polish_gated", c_int32)]
 
 
 EXPORTS = ("fqp_default_settings", "fqp_create", "fqp_solve_batch",

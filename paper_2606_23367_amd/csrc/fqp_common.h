@@ -19,6 +19,8 @@ constexpr int kRowsPerChunk = 32 * kWaves;  // rows per chunk (MFMA N x waves)
 constexpr int kMaxKp = 192;    // padded factor width limit
 constexpr int kMaxK = 128;     // factor limit (polish keeps K_F in LDS)
 constexpr int kMaxG = 64;      // exposure groups limit
+constexpr int kMaxKpBf = 96;   // widest factor block of the bf16-split passes
+                               // (their B~ and p operands stay in registers)
 
 // per-account float parameters, [m][kNPar]
 enum AccPar {

@@ -27,8 +27,11 @@
 // A small per-account kernel then reduces the partials and solves in factor
 // space.  The cap multiplier is updated between passes by a damped Newton
 // step on the turnover of the current z (the prox uses the previous value).
+#include <algorithm>
+
 #include "fqp_common.h"
 #include "fqp_kernels.h"
+#include "../../include/fqp.h"
 
 namespace fqp {
 
@@ -197,23 +200,18 @@ enum PassMode { MODE_CONTRACT = 0, MODE_PROJECT = 1 };
 
 struct RowInfo {
   float lb, ub, w0;
-  int ti;
+  bool taxed;
+  TaxLots t;
 };
 
 __device__ __forceinline__ float prox_row(const RowInfo& ri, float v, float th, float irho,
-                                          const float* tax_brk, const float* tax_slope,
                                           bool* at_kink) {
   float zn;
-  if (ri.ti >= 0) {
-    TaxLots t;
-    const int ti = ri.ti;
-    t.b1 = tax_brk[3 * ti]; t.b2 = tax_brk[3 * ti + 1]; t.b3 = tax_brk[3 * ti + 2];
-    t.s0 = tax_slope[4 * ti]; t.s1 = tax_slope[4 * ti + 1];
-    t.s2 = tax_slope[4 * ti + 2]; t.s3 = tax_slope[4 * ti + 3];
-    zn = prox_taxed(v, ri.w0, th, irho, t, ri.lb, ri.ub);
+  if (ri.taxed) {
+    zn = prox_taxed(v, ri.w0, th, irho, ri.t, ri.lb, ri.ub);
     if (at_kink)
-      *at_kink = (zn == ri.w0) || (zn == ri.w0 - t.b1) || (zn == ri.w0 - t.b2) ||
-                 (zn == ri.w0 - t.b3) || zn <= ri.lb || zn >= ri.ub;
+      *at_kink = (zn == ri.w0) || (zn == ri.w0 - ri.t.b1) || (zn == ri.w0 - ri.t.b2) ||
+                 (zn == ri.w0 - ri.t.b3) || zn <= ri.lb || zn >= ri.ub;
   } else {
     zn = prox_plain(v, ri.w0, th, ri.lb, ri.ub);
     if (at_kink) *at_kink = (zn == ri.w0) || zn <= ri.lb || zn >= ri.ub;
@@ -221,23 +219,35 @@ __device__ __forceinline__ float prox_row(const RowInfo& ri, float v, float th, 
   return zn;
 }
 
+// box, w0 and tax lots of (account a, row) from its eligibility word, its
+// holding word and the holding prefix word (already loaded) and the
+// account's first record hptr: one more dependent load, only for held rows
 template <typename Args>
-__device__ __forceinline__ RowInfo row_info(const Args& A, int a, int row, float lbp, float ubp) {
+__device__ __forceinline__ RowInfo row_info_w(const Args& A, int row, float lbp, float ubp,
+                                              uint32_t ew, uint32_t hw, int hpre, int hptr) {
   RowInfo ri;
-  const int wd = row >> 5, b = row & 31;
-  const uint32_t ew = A.elig ? A.elig[(size_t)a * A.W + wd] : 0xffffffffu;
+  const int b = row & 31;
   const bool el = (ew >> b) & 1u;
   ri.lb = el ? lbp : 0.f;
   ri.ub = el ? ubp : 0.f;
-  const uint32_t hw = A.hold[(size_t)a * A.W + wd];
   ri.w0 = 0.f;
-  ri.ti = -1;
+  ri.taxed = false;
   if ((hw >> b) & 1u) {
-    const int idx = A.hold_ptr[a] + A.hold_pre[(size_t)a * A.W + wd] + popc_below(hw, b);
-    ri.w0 = A.hold_w0[idx];
-    ri.ti = A.hold_tax[idx];
+    const int idx = hptr + hpre + popc_below(hw, b);
+    const float4 r0 = A.hold_rec[2 * idx], r1 = A.hold_rec[2 * idx + 1];
+    ri.w0 = r0.x;
+    ri.taxed = r0.y > 0.f;
+    ri.t.b1 = r0.y; ri.t.b2 = r0.z; ri.t.b3 = r0.w;
+    ri.t.s0 = r1.x; ri.t.s1 = r1.y; ri.t.s2 = r1.z; ri.t.s3 = r1.w;
   }
   return ri;
+}
+
+template <typename Args>
+__device__ __forceinline__ RowInfo row_info(const Args& A, int a, int row, float lbp, float ubp) {
+  const size_t wi = (size_t)a * A.W + (row >> 5);
+  const uint32_t ew = A.elig ? A.elig[wi] : 0xffffffffu;
+  return row_info_w(A, row, lbp, ubp, ew, A.hold[wi], A.hold_pre[wi], A.hold_ptr[a]);
 }
 
 template <int NCH, int MODE>
@@ -246,10 +256,16 @@ __global__ __launch_bounds__(256, 2) void iter_kernel(IterArgs A) {
   constexpr int BS = kp + 1;            // LDS row stride (odd: no conflicts)
   extern __shared__ float smem[];
   float* Bs = smem;                     // [128][BS]
-  float* Ps = Bs + kRowsPerChunk * BS;  // [32][BS]
-  float* Rt = Ps + kTM * BS;            // [4][32][33]
-  float* Par = Rt + kWaves * 32 * 33;   // [32][kNPar]
-  int* Aid = (int*)(Par + kTM * kNPar); // [32]
+  // mode-specific region: PROJECT keeps p (32 x BS) and a [4][32] max
+  // reduction, CONTRACT the per-wave transposes of R' ([4][32][33])
+  constexpr int kXs = (MODE == MODE_PROJECT) ? kTM * BS + kWaves * kTM : kWaves * 32 * 33;
+  float* Xs = Bs + kRowsPerChunk * BS;
+  float* Ps = Xs;                       // PROJECT: [32][BS]
+  float* Rt = Xs;                       // CONTRACT: [4][32][33]
+  // per tile account: {rho, 1/rho, gamma, (kappa + lam)/rho}, {lb, ub, nu, alpha}
+  float4* Acc = reinterpret_cast<float4*>(Xs + kXs);   // [32][2]
+  int* Aid = (int*)(Acc + 2 * kTM);     // [32]
+  int* Hp = Aid + kTM;                  // [32] first held record of each account
 
   const int m_act = *A.m_act;
   const int slot0 = blockIdx.y * kTM;
@@ -260,14 +276,20 @@ __global__ __launch_bounds__(256, 2) void iter_kernel(IterArgs A) {
 
   if (tid < kTM) {
     int s = slot0 + tid;
-    Aid[tid] = (s < m_act) ? A.act[s] : -1;
+    const int a = (s < m_act) ? A.act[s] : -1;
+    Aid[tid] = a;
+    Hp[tid] = (a >= 0) ? A.hold_ptr[a] : 0;
+    float4 q0 = make_float4(1.f, 1.f, 0.f, 0.f), q1 = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (a >= 0) {
+      const float* p = A.par + (size_t)a * kNPar;
+      const float rho = p[P_RHO], irho = 1.f / rho;
+      q0 = make_float4(rho, irho, p[P_GAMMA], (p[P_KAPPA] + p[P_LAM]) * irho);
+      q1 = make_float4(p[P_LB], p[P_UB], p[P_NU], p[P_ALPHA]);
+    }
+    Acc[2 * tid] = q0;
+    Acc[2 * tid + 1] = q1;
   }
   __syncthreads();
-  for (int e = tid; e < kTM * kNPar; e += 256) {
-    int j = e / kNPar, p = e % kNPar;
-    int a = Aid[j];
-    Par[e] = (a >= 0) ? A.par[(size_t)a * kNPar + p] : 0.f;
-  }
   if (MODE == MODE_PROJECT) {
     for (int e = tid; e < kTM * kp; e += 256) {
       int j = e / kp, c = e % kp;
@@ -317,29 +339,48 @@ __global__ __launch_bounds__(256, 2) void iter_kernel(IterArgs A) {
         X = __builtin_amdgcn_mfma_f32_32x32x2f32(pa[2 * s], pb[2 * s], X, 0, 0, 0);
     }
 
+    // issue every load of the lane's 16 (account, row) elements first, so
+    // that they are in flight together
+    float mu_r[16], v_r[16];
+    uint32_t ew_r[16], hw_r[16];
+    int hp_r[16];
+    const int wd = row >> 5;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int m = 8 * (r >> 2) + 4 * hi + (r & 3);
+      const int a = Aid[m];
+      mu_r[r] = 0.f; v_r[r] = 0.f; ew_r[r] = 0u; hw_r[r] = 0u; hp_r[r] = 0;
+      if (a >= 0 && row_ok) {
+        const size_t off = (size_t)a * n + row;
+        const size_t wi = (size_t)a * A.W + wd;
+        mu_r[r] = A.mu[off];
+        v_r[r] = A.v[off];
+        ew_r[r] = A.elig ? A.elig[wi] : 0xffffffffu;
+        hw_r[r] = A.hold[wi];
+        hp_r[r] = A.hold_pre[wi];
+      }
+    }
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
       const int m = 8 * (r >> 2) + 4 * hi + (r & 3);
       const int a = Aid[m];
       float Rp = 0.f;
       if (a >= 0 && row_ok) {
-        const float* pr = Par + m * kNPar;
-        const float rho = pr[P_RHO];
-        const float irho = 1.f / rho;
-        const float Delta = pr[P_GAMMA] * d_i + rho;
+        const float4 q0 = Acc[2 * m], q1 = Acc[2 * m + 1];
+        const float rho = q0.x, irho = q0.y;
+        const float iDelta = __builtin_amdgcn_rcpf(q0.z * d_i + rho);
         const size_t off = (size_t)a * n + row;
-        const float mu = A.mu[off];
-        const float vv = A.v[off];
-        const RowInfo ri = row_info(A, a, row, pr[P_LB], pr[P_UB]);
-        const float th = (pr[P_KAPPA] + pr[P_LAM]) * irho;
-        const float z = prox_row(ri, vv, th, irho, A.tax_brk, A.tax_slope, nullptr);
+        const float mu = mu_r[r];
+        const float vv = v_r[r];
+        const RowInfo ri = row_info_w(A, row, q1.x, q1.y, ew_r[r], hw_r[r], hp_r[r], Hp[m]);
+        const float z = prox_row(ri, vv, q0.w, irho, nullptr);
         const float u = vv - z;
         const float r0v = mu + rho * (z - u);
         if (MODE == MODE_CONTRACT) {
-          Rp = r0v / Delta;
+          Rp = r0v * iDelta;
         } else {
-          const float x = (r0v + pr[P_NU] - X[r]) / Delta;
-          const float alpha = pr[P_ALPHA];
+          const float x = (r0v + q1.z - X[r]) * iDelta;
+          const float alpha = q1.w;
           A.v[off] = alpha * x + (1.f - alpha) * z + u;
           st_rp[r] = fmaxf(st_rp[r], fabsf(x - z));
         }
@@ -371,7 +412,7 @@ __global__ __launch_bounds__(256, 2) void iter_kernel(IterArgs A) {
 #pragma unroll
       for (int o = 16; o >= 1; o >>= 1) st_rp[r] = fmaxf(st_rp[r], __shfl_xor(st_rp[r], o, 32));
     __syncthreads();
-    float* sred = Rt;                      // [4][32]
+    float* sred = Xs + kTM * BS;           // [4][32]
     if (l32 == 0) {
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
@@ -410,6 +451,281 @@ __global__ __launch_bounds__(256, 2) void iter_kernel(IterArgs A) {
 }
 
 // ---------------------------------------------------------------------------
+// the same two passes with the contractions on bf16 MFMA (32x32x16)
+//
+// Every float32 operand x enters as the pair hi = bf16(x), lo = bf16(x - hi)
+// and each product as hi*hi + hi*lo + lo*hi with float32 accumulation: the
+// dropped lo*lo term and the rounding of lo leave a relative error of about
+// 2^-16 per product, against 2^-24 for the float32 MFMA, at an eighth of the
+// matrix-core time.  B~ is split once per solve into row-major (PROJECT) and
+// column-major (CONTRACT) copies whose rows are padded with zeros to a whole
+// number of chunks, so that the operands come straight from global memory
+// (no LDS staging, no workgroup barrier inside the row loop).
+// ---------------------------------------------------------------------------
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ void split_bf16(float x, __bf16& h, __bf16& l) {
+  h = (__bf16)x;
+  l = (__bf16)(x - (float)h);
+}
+
+constexpr int kRwS = 40;   // bf16 stride of one account's transposed R' (16-B aligned)
+
+template <int NCH, int MODE>
+constexpr int bf_lds_floats() {
+  // CONTRACT: per-wave R' transposes (hi, lo) or, after the row loop, the
+  // cross-wave reduction [4][32][kp]; PROJECT: a [4][32] max reduction
+  return (MODE == MODE_CONTRACT)
+             ? ((kWaves * kTM * NCH * 32 > kWaves * 2 * 32 * kRwS / 2) ? kWaves * kTM * NCH * 32
+                                                                     : kWaves * 2 * 32 * kRwS / 2)
+             : kWaves * kTM;
+}
+
+template <int NCH, int MODE>
+__global__ __launch_bounds__(256, 2) void iter_kernel_bf(IterArgs A) {
+  constexpr int kp = NCH * 32;
+  constexpr int KS = kp / 16;            // K steps of the PROJECT product
+  constexpr int kX = bf_lds_floats<NCH, MODE>();
+  extern __shared__ float smem[];
+  float* Xs = smem;
+  float4* Acc = reinterpret_cast<float4*>(Xs + kX);    // [32][2] as in iter_kernel
+  int* Aid = (int*)(Acc + 2 * kTM);     // [32]
+  int* Hp = Aid + kTM;                  // [32]
+
+  const int m_act = *A.m_act;
+  const int slot0 = blockIdx.y * kTM;
+  if (slot0 >= m_act) return;
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+  const int l32 = lane & 31, hi = lane >> 5;
+  const int n = A.n;
+  const __bf16* bh = reinterpret_cast<const __bf16*>(A.bt_hi);
+  const __bf16* bl = reinterpret_cast<const __bf16*>(A.bt_lo);
+  const __bf16* bth = reinterpret_cast<const __bf16*>(A.btt_hi);
+  const __bf16* btl = reinterpret_cast<const __bf16*>(A.btt_lo);
+
+  if (tid < kTM) {
+    int s = slot0 + tid;
+    const int a = (s < m_act) ? A.act[s] : -1;
+    Aid[tid] = a;
+    Hp[tid] = (a >= 0) ? A.hold_ptr[a] : 0;
+    float4 q0 = make_float4(1.f, 1.f, 0.f, 0.f), q1 = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (a >= 0) {
+      const float* p = A.par + (size_t)a * kNPar;
+      const float rho = p[P_RHO], irho = 1.f / rho;
+      q0 = make_float4(rho, irho, p[P_GAMMA], (p[P_KAPPA] + p[P_LAM]) * irho);
+      q1 = make_float4(p[P_LB], p[P_UB], p[P_NU], p[P_ALPHA]);
+    }
+    Acc[2 * tid] = q0;
+    Acc[2 * tid + 1] = q1;
+  }
+  __syncthreads();
+
+  // PROJECT: the A operand (p of account l32, k = 16 s + 8 hi + t) for every
+  // K step, split once per workgroup
+  bf16x8 pH[MODE == MODE_PROJECT ? KS : 1], pL[MODE == MODE_PROJECT ? KS : 1];
+  if (MODE == MODE_PROJECT) {
+    const int a = Aid[l32];
+#pragma unroll
+    for (int s = 0; s < KS; ++s)
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        const float x = (a >= 0) ? A.pp[(size_t)a * kp + 16 * s + 8 * hi + t] : 0.f;
+        __bf16 h, l;
+        split_bf16(x, h, l);
+        pH[s][t] = h;
+        pL[s][t] = l;
+      }
+  }
+
+  floatx16 T[NCH];
+#pragma unroll
+  for (int c = 0; c < NCH; ++c)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) T[c][r] = 0.f;
+  float st_rp[16];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) st_rp[r] = 0.f;
+
+  __bf16* RwH = reinterpret_cast<__bf16*>(Xs) + w * 2 * 32 * kRwS;
+  __bf16* RwL = RwH + 32 * kRwS;
+  const int row_begin = blockIdx.x * A.rows_per_wg;
+
+  for (int ch = 0; ch < A.chunks_per_wg; ++ch) {
+    const int r0 = row_begin + ch * kRowsPerChunk;
+    if (r0 >= n) break;
+    const int row_base = r0 + 32 * w;     // < npad: rows are padded to whole chunks
+    const int row = row_base + l32;
+    const bool row_ok = row < n;
+    const float d_i = row_ok ? A.d[row] : 1.f;
+
+    // B~ operand loads first (independent of the element work)
+    bf16x8 bH[MODE == MODE_PROJECT ? KS : 2 * NCH], bL[MODE == MODE_PROJECT ? KS : 2 * NCH];
+    if (MODE == MODE_PROJECT) {
+#pragma unroll
+      for (int s = 0; s < KS; ++s) {
+        const size_t o = (size_t)row * kp + 16 * s + 8 * hi;
+        bH[s] = *reinterpret_cast<const bf16x8*>(bh + o);
+        bL[s] = *reinterpret_cast<const bf16x8*>(bl + o);
+      }
+    } else {
+#pragma unroll
+      for (int c = 0; c < NCH; ++c)
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+          const size_t o = (size_t)(32 * c + l32) * A.npad + row_base + 16 * s + 8 * hi;
+          bH[2 * c + s] = *reinterpret_cast<const bf16x8*>(bth + o);
+          bL[2 * c + s] = *reinterpret_cast<const bf16x8*>(btl + o);
+        }
+    }
+
+    float mu_r[16], v_r[16];
+    uint32_t ew_r[16], hw_r[16];
+    int hp_r[16];
+    const int wd = row >> 5;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int m = 8 * (r >> 2) + 4 * hi + (r & 3);
+      const int a = Aid[m];
+      mu_r[r] = 0.f; v_r[r] = 0.f; ew_r[r] = 0u; hw_r[r] = 0u; hp_r[r] = 0;
+      if (a >= 0 && row_ok) {
+        const size_t off = (size_t)a * n + row;
+        const size_t wi = (size_t)a * A.W + wd;
+        mu_r[r] = A.mu[off];
+        v_r[r] = A.v[off];
+        ew_r[r] = A.elig ? A.elig[wi] : 0xffffffffu;
+        hw_r[r] = A.hold[wi];
+        hp_r[r] = A.hold_pre[wi];
+      }
+    }
+
+    floatx16 X;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) X[r] = 0.f;
+    if (MODE == MODE_PROJECT) {
+#pragma unroll
+      for (int s = 0; s < KS; ++s) {
+        X = __builtin_amdgcn_mfma_f32_32x32x16_bf16(pH[s], bH[s], X, 0, 0, 0);
+        X = __builtin_amdgcn_mfma_f32_32x32x16_bf16(pH[s], bL[s], X, 0, 0, 0);
+        X = __builtin_amdgcn_mfma_f32_32x32x16_bf16(pL[s], bH[s], X, 0, 0, 0);
+      }
+    }
+
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int m = 8 * (r >> 2) + 4 * hi + (r & 3);
+      const int a = Aid[m];
+      float Rp = 0.f;
+      if (a >= 0 && row_ok) {
+        const float4 q0 = Acc[2 * m], q1 = Acc[2 * m + 1];
+        const float rho = q0.x, irho = q0.y;
+        const float iDelta = __builtin_amdgcn_rcpf(q0.z * d_i + rho);
+        const size_t off = (size_t)a * n + row;
+        const RowInfo ri = row_info_w(A, row, q1.x, q1.y, ew_r[r], hw_r[r], hp_r[r], Hp[m]);
+        const float vv = v_r[r];
+        const float z = prox_row(ri, vv, q0.w, irho, nullptr);
+        const float u = vv - z;
+        const float r0v = mu_r[r] + rho * (z - u);
+        if (MODE == MODE_CONTRACT) {
+          Rp = r0v * iDelta;
+        } else {
+          const float x = (r0v + q1.z - X[r]) * iDelta;
+          const float alpha = q1.w;
+          A.v[off] = alpha * x + (1.f - alpha) * z + u;
+          st_rp[r] = fmaxf(st_rp[r], fabsf(x - z));
+        }
+      }
+      if (MODE == MODE_CONTRACT) {
+        __bf16 h, l;
+        split_bf16(Rp, h, l);
+        RwH[m * kRwS + l32] = h;
+        RwL[m * kRwS + l32] = l;
+      }
+    }
+    if (MODE == MODE_CONTRACT) {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+      for (int s = 0; s < 2; ++s) {
+        const bf16x8 aH = *reinterpret_cast<const bf16x8*>(RwH + l32 * kRwS + 16 * s + 8 * hi);
+        const bf16x8 aL = *reinterpret_cast<const bf16x8*>(RwL + l32 * kRwS + 16 * s + 8 * hi);
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) {
+          T[c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aH, bH[2 * c + s], T[c], 0, 0, 0);
+          T[c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aH, bL[2 * c + s], T[c], 0, 0, 0);
+          T[c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aL, bH[2 * c + s], T[c], 0, 0, 0);
+        }
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+  }
+
+  const size_t M = A.m_total;
+  if (MODE == MODE_PROJECT) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r)
+#pragma unroll
+      for (int o = 16; o >= 1; o >>= 1) st_rp[r] = fmaxf(st_rp[r], __shfl_xor(st_rp[r], o, 32));
+    float* sred = Xs;                      // [4][32]
+    if (l32 == 0) {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int m = 8 * (r >> 2) + 4 * hi + (r & 3);
+        sred[w * kTM + m] = st_rp[r];
+      }
+    }
+    __syncthreads();
+    if (tid < kTM) {
+      const int a = Aid[tid];
+      if (a >= 0)
+        A.stat[((size_t)blockIdx.x * M + a) * kNStat + ST_RPRIM] =
+            fmaxf(fmaxf(sred[tid], sred[kTM + tid]), fmaxf(sred[2 * kTM + tid], sred[3 * kTM + tid]));
+    }
+    return;
+  }
+
+  __syncthreads();                       // all waves done with their transposes
+  float* red = Xs;                       // [4][32][kp]
+#pragma unroll
+  for (int c = 0; c < NCH; ++c)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int m = 8 * (r >> 2) + 4 * hi + (r & 3);
+      red[(w * kTM + m) * kp + 32 * c + l32] = T[c][r];
+    }
+  __syncthreads();
+  for (int e = tid; e < kTM * kp; e += 256) {
+    const int m = e / kp, c = e % kp;
+    const int a = Aid[m];
+    if (a < 0) continue;
+    float s = red[(0 * kTM + m) * kp + c] + red[(1 * kTM + m) * kp + c] +
+              red[(2 * kTM + m) * kp + c] + red[(3 * kTM + m) * kp + c];
+    A.part[((size_t)blockIdx.x * M + a) * kp + c] = s;
+  }
+}
+
+// hi/lo bf16 copies of B~: row-major [npad][kp] and column-major [kp][npad],
+// rows n..npad-1 zero
+__global__ void split_bt_kernel(int n, int npad, int kp, const float* Bt, uint16_t* bh,
+                                uint16_t* bl, uint16_t* bth, uint16_t* btl) {
+  const size_t total = (size_t)npad * kp;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (size_t)gridDim.x * blockDim.x) {
+    const int row = (int)(e / kp), col = (int)(e % kp);
+    const float x = row < n ? Bt[e] : 0.f;
+    __bf16 h, l;
+    split_bf16(x, h, l);
+    const uint16_t hb = __builtin_bit_cast(uint16_t, h), lb = __builtin_bit_cast(uint16_t, l);
+    bh[e] = hb;
+    bl[e] = lb;
+    bth[(size_t)col * npad + row] = hb;
+    btl[(size_t)col * npad + row] = lb;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // exact turnover-cap multiplier of the current v (one workgroup per account)
 //
 // turnover(lam) = sum_i |prox_i(v_i; lam) - w0_i| is piecewise linear and
@@ -434,17 +750,41 @@ __global__ __launch_bounds__(kCapT) void cap_kernel(IterArgs A) {
   const float rho = par[P_RHO], irho = 1.f / rho, kap = par[P_KAPPA];
   const float lbp = par[P_LB], ubp = par[P_UB];
   float lam = par[P_LAM];
+  const int hptr = A.hold_ptr[a];
   float lo = 0.f, hi_b = INFINITY, best_feas = INFINITY;
   if (tid == 0) s_done = 0;
   for (int it = 0; it < 48; ++it) {
     const float th = (kap + lam) * irho;
     float g = 0.f, nf = 0.f;
-    for (int i = tid; i < n; i += kCapT) {
-      const RowInfo ri = row_info(A, a, i, lbp, ubp);
-      bool kink;
-      const float z = prox_row(ri, A.v[(size_t)a * n + i], th, irho, A.tax_brk, A.tax_slope, &kink);
-      g += fabsf(z - ri.w0);
-      nf += kink ? 0.f : 1.f;
+    // groups of 8 rows per thread: every load of a group is issued before
+    // the group is evaluated
+    for (int i0 = 0; i0 < n; i0 += 8 * kCapT) {
+      float vr[8];
+      uint32_t ew[8], hw[8];
+      int hp[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int i = i0 + q * kCapT + tid;
+        vr[q] = 0.f; ew[q] = 0u; hw[q] = 0u; hp[q] = 0;
+        if (i < n) {
+          const size_t wi = (size_t)a * A.W + (i >> 5);
+          vr[q] = A.v[(size_t)a * n + i];
+          ew[q] = A.elig ? A.elig[wi] : 0xffffffffu;
+          hw[q] = A.hold[wi];
+          hp[q] = A.hold_pre[wi];
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int i = i0 + q * kCapT + tid;
+        if (i < n) {
+          const RowInfo ri = row_info_w(A, i, lbp, ubp, ew[q], hw[q], hp[q], hptr);
+          bool kink;
+          const float z = prox_row(ri, vr[q], th, irho, &kink);
+          g += fabsf(z - ri.w0);
+          nf += kink ? 0.f : 1.f;
+        }
+      }
     }
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) {
@@ -495,8 +835,7 @@ __global__ __launch_bounds__(256) void materialize_z_kernel(IterArgs A, float* z
   const float th = (par[P_KAPPA] + par[P_LAM]) * irho;
   for (int i = blockIdx.x * 256 + threadIdx.x; i < A.n; i += gridDim.x * 256) {
     const RowInfo ri = row_info(A, a, i, par[P_LB], par[P_UB]);
-    z[(size_t)a * A.n + i] = prox_row(ri, A.v[(size_t)a * A.n + i], th, irho, A.tax_brk,
-                                      A.tax_slope, nullptr);
+    z[(size_t)a * A.n + i] = prox_row(ri, A.v[(size_t)a * A.n + i], th, irho, nullptr);
   }
 }
 
@@ -523,7 +862,9 @@ __global__ __launch_bounds__(256) void ksolve_kernel(KArgs A) {
   const float rhob = par[P_RHOB];
 
   for (int j = tid; j < kp; j += 256) {
+    // independent partial loads in flight together
     float s = 0.f;
+#pragma unroll 8
     for (int rt = 0; rt < A.n_rt; ++rt) s += A.part[((size_t)rt * M + a) * kp + j];
     t[j] = s;
   }
@@ -555,13 +896,11 @@ __global__ __launch_bounds__(256) void ksolve_kernel(KArgs A) {
   // nu = (1 - s0 + q^T t) / sigma1
   double part = 0.0;
   for (int j = tid; j < kg; j += 256) part += (double)qv[j] * t[j];
-  red[tid] = part;
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) part += __shfl_xor(part, o, 64);
+  if ((tid & 63) == 0) red[tid >> 6] = part;
   __syncthreads();
-  for (int o = 128; o >= 1; o >>= 1) {
-    if (tid < o) red[tid] += red[tid + o];
-    __syncthreads();
-  }
-  if (tid == 0) s_nu = (1.0 - s0 + red[0]) / (double)sig1;
+  if (tid == 0) s_nu = (1.0 - s0 + ((red[0] + red[1]) + (red[2] + red[3]))) / (double)sig1;
   __syncthreads();
   const double nu = s_nu;
   for (int j = tid; j < kg; j += 256) rhs[j] = t[j] + nu * (double)cv[j];
@@ -570,6 +909,7 @@ __global__ __launch_bounds__(256) void ksolve_kernel(KArgs A) {
     double s = 0.0;
     if (j < kg)
       // K^-1 is symmetric: read column j (consecutive j -> consecutive words)
+#pragma unroll 8
       for (int l = 0; l < kg; ++l) s += (double)Kinv[l * kp + j] * rhs[l];
     pprime[j] = (float)s;
   }
@@ -598,15 +938,12 @@ __global__ __launch_bounds__(256) void ksolve_kernel(KArgs A) {
     band_res = fabsf(ax - zn);
     zb[g] = zn;
   }
-  red[tid] = band_res;
-  __syncthreads();
-  for (int o = 128; o >= 1; o >>= 1) {
-    if (tid < o) red[tid] = fmax(red[tid], red[tid + o]);
-    __syncthreads();
-  }
+  // band residual: only the first G <= 64 threads (wave 0) contribute
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) band_res = fmaxf(band_res, __shfl_xor(band_res, o, 64));
   if (tid == 0) {
     par[P_NU] = (float)nu;
-    A.res[(size_t)a * 4 + 0] = fmaxf(sst[ST_RPRIM], (float)red[0]);
+    A.res[(size_t)a * 4 + 0] = fmaxf(sst[ST_RPRIM], band_res);
     A.iters[a] += 1;
   }
 }
@@ -614,20 +951,40 @@ __global__ __launch_bounds__(256) void ksolve_kernel(KArgs A) {
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
-template <int NCH>
+// LDS of one workgroup (mirrors the layout at the top of iter_kernel); the
+// two passes need different regions, which keeps each under half a CU's
+// LDS so that two workgroups share a CU
+template <int NCH, int MODE>
 static size_t iter_smem() {
   constexpr int kp = NCH * 32, BS = kp + 1;
-  return sizeof(float) * ((size_t)kRowsPerChunk * BS + kTM * BS + kWaves * 32 * 33 +
-                          kTM * kNPar) + sizeof(int) * kTM;
+  constexpr int kXs = (MODE == MODE_PROJECT) ? kTM * BS + kWaves * kTM : kWaves * 32 * 33;
+  return sizeof(float) * ((size_t)kRowsPerChunk * BS + kXs + 8 * kTM) + 2 * sizeof(int) * kTM;
+}
+
+template <int NCH, int MODE>
+static size_t iter_smem_bf() {
+  return sizeof(float) * ((size_t)bf_lds_floats<NCH, MODE>() + 8 * kTM) + 2 * sizeof(int) * kTM;
 }
 
 template <int NCH>
-static hipError_t launch_iter_t(const IterArgs& A, int mode, dim3 grid, hipStream_t st) {
-  size_t smem = iter_smem<NCH>();
+static hipError_t launch_iter_t(const IterArgs& A, int mode, int prec, dim3 grid,
+                                hipStream_t st) {
+  if (prec == FQP_PREC_BF16X3 && NCH * 32 <= kMaxKpBf) {
+    constexpr int NB = NCH * 32 <= kMaxKpBf ? NCH : 1;   // instantiate narrow widths only
+    if (mode == MODE_CONTRACT)
+      hipLaunchKernelGGL((iter_kernel_bf<NB, MODE_CONTRACT>), grid, dim3(256),
+                         (iter_smem_bf<NB, MODE_CONTRACT>()), st, A);
+    else
+      hipLaunchKernelGGL((iter_kernel_bf<NB, MODE_PROJECT>), grid, dim3(256),
+                         (iter_smem_bf<NB, MODE_PROJECT>()), st, A);
+    return hipGetLastError();
+  }
   if (mode == MODE_CONTRACT) {
-    hipLaunchKernelGGL((iter_kernel<NCH, MODE_CONTRACT>), grid, dim3(256), smem, st, A);
+    hipLaunchKernelGGL((iter_kernel<NCH, MODE_CONTRACT>), grid, dim3(256),
+                       (iter_smem<NCH, MODE_CONTRACT>()), st, A);
   } else {
-    hipLaunchKernelGGL((iter_kernel<NCH, MODE_PROJECT>), grid, dim3(256), smem, st, A);
+    hipLaunchKernelGGL((iter_kernel<NCH, MODE_PROJECT>), grid, dim3(256),
+                       (iter_smem<NCH, MODE_PROJECT>()), st, A);
   }
   return hipGetLastError();
 }
@@ -636,24 +993,31 @@ hipError_t configure_iter_kernels() {
   hipError_t e = hipSuccess;
 #define FQP_CFG(N)                                                                     \
   e = hipFuncSetAttribute((const void*)iter_kernel<N, MODE_CONTRACT>,                  \
-                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)iter_smem<N>()); \
+                          hipFuncAttributeMaxDynamicSharedMemorySize,                  \
+                          (int)iter_smem<N, MODE_CONTRACT>());                         \
   if (e != hipSuccess) return e;                                                       \
   e = hipFuncSetAttribute((const void*)iter_kernel<N, MODE_PROJECT>,                   \
-                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)iter_smem<N>()); \
+                          hipFuncAttributeMaxDynamicSharedMemorySize,                  \
+                          (int)iter_smem<N, MODE_PROJECT>());                          \
+  if (e != hipSuccess) return e;                                                       \
+  e = hipFuncSetAttribute((const void*)iter_kernel_bf<(N * 32 <= kMaxKpBf ? N : 1), MODE_CONTRACT>, \
+                          hipFuncAttributeMaxDynamicSharedMemorySize,                  \
+                          (int)iter_smem_bf<(N * 32 <= kMaxKpBf ? N : 1), MODE_CONTRACT>()); \
   if (e != hipSuccess) return e;
   FQP_CFG(1) FQP_CFG(2) FQP_CFG(3) FQP_CFG(4) FQP_CFG(5) FQP_CFG(6)
 #undef FQP_CFG
   return e;
 }
 
-hipError_t launch_iter(const IterArgs& A, int kp, int mode, dim3 grid, hipStream_t st) {
+hipError_t launch_iter(const IterArgs& A, int kp, int mode, int prec, dim3 grid,
+                       hipStream_t st) {
   switch (kp / 32) {
-    case 1: return launch_iter_t<1>(A, mode, grid, st);
-    case 2: return launch_iter_t<2>(A, mode, grid, st);
-    case 3: return launch_iter_t<3>(A, mode, grid, st);
-    case 4: return launch_iter_t<4>(A, mode, grid, st);
-    case 5: return launch_iter_t<5>(A, mode, grid, st);
-    case 6: return launch_iter_t<6>(A, mode, grid, st);
+    case 1: return launch_iter_t<1>(A, mode, prec, grid, st);
+    case 2: return launch_iter_t<2>(A, mode, prec, grid, st);
+    case 3: return launch_iter_t<3>(A, mode, prec, grid, st);
+    case 4: return launch_iter_t<4>(A, mode, prec, grid, st);
+    case 5: return launch_iter_t<5>(A, mode, prec, grid, st);
+    case 6: return launch_iter_t<6>(A, mode, prec, grid, st);
     default: return hipErrorInvalidValue;
   }
 }
@@ -671,6 +1035,15 @@ hipError_t launch_materialize_z(const IterArgs& A, int m_total, float* z, hipStr
 
 hipError_t launch_ksolve(const KArgs& A, int m_total, hipStream_t st) {
   hipLaunchKernelGGL(ksolve_kernel, dim3(m_total), dim3(256), 0, st, A);
+  return hipGetLastError();
+}
+
+hipError_t launch_split_bt(int n, int npad, int kp, const float* Bt, uint16_t* bh, uint16_t* bl,
+                           uint16_t* bth, uint16_t* btl, hipStream_t st) {
+  const size_t total = (size_t)npad * kp;
+  const unsigned blocks = (unsigned)std::min<size_t>((total + 255) / 256, 8192);
+  hipLaunchKernelGGL(split_bt_kernel, dim3(blocks), dim3(256), 0, st, n, npad, kp, Bt, bh, bl,
+                     bth, btl);
   return hipGetLastError();
 }
 

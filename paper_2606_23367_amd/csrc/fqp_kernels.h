@@ -23,6 +23,12 @@ struct IterArgs {
   const int32_t* hold_tax;   // [nnz_h]
   const float* tax_brk;      // [nnz_t][3]
   const float* tax_slope;    // [nnz_t][4]
+  const float4* hold_rec;    // [nnz_h][2]: {w0, b1, b2, b3}, {s0, s1, s2, s3}; b1 < 0: no lots
+  int npad;                  // rows of the bf16 copies of B~ (n padded to whole chunks)
+  const uint16_t* bt_hi;     // [npad][kp] bf16 hi part of B~ (row-major)
+  const uint16_t* bt_lo;     // [npad][kp] bf16 lo part
+  const uint16_t* btt_hi;    // [kp][npad] bf16 hi part (column-major)
+  const uint16_t* btt_lo;    // [kp][npad] bf16 lo part
   const float* pp;           // [m][kp]
   const float* par;          // [m][kNPar]
   float* par_rw;             // same array, written by the cap kernel
@@ -52,7 +58,10 @@ struct KArgs {
 };
 
 hipError_t configure_iter_kernels();
-hipError_t launch_iter(const IterArgs& A, int kp, int mode, dim3 grid, hipStream_t st);
+hipError_t launch_iter(const IterArgs& A, int kp, int mode, int prec, dim3 grid,
+                       hipStream_t st);
+hipError_t launch_split_bt(int n, int npad, int kp, const float* Bt, uint16_t* bh, uint16_t* bl,
+                           uint16_t* bth, uint16_t* btl, hipStream_t st);
 hipError_t launch_cap(const IterArgs& A, int m_total, hipStream_t st);
 hipError_t launch_materialize_z(const IterArgs& A, int m_total, float* z, hipStream_t st);
 hipError_t launch_ksolve(const KArgs& A, int m_total, hipStream_t st);
@@ -94,6 +103,7 @@ struct PackArgs {
 hipError_t launch_pack_count(const PackArgs& A, hipStream_t st);
 hipError_t launch_pack_scan(const PackArgs& A, hipStream_t st);
 hipError_t launch_pack_fill(const PackArgs& A, hipStream_t st);
+hipError_t launch_pack_rec(const PackArgs& A, float4* rec, int total, hipStream_t st);
 
 // ---- polish / certification (float64) -------------------------------------
 // ints of polish bookkeeping per account
@@ -135,6 +145,8 @@ struct PolishArgs {
   int first_round;           // classify from z when nonzero
   int nf_gate;               // skip patterns with more free rows (0: never)
   int nf_small;              // larger free sets wait for a repeated pattern
+  int* pcount;               // [2] reduced solves formed, attempts gated
+  int max_prop;              // a failed pattern with more proposals stops refining
 };
 hipError_t launch_polish_solve(const PolishArgs& A, hipStream_t st);
 size_t polish_wk_stride(int k, int G);

@@ -187,6 +187,31 @@ __global__ __launch_bounds__(256) void pack_fill_kernel(PackArgs A) {
   }
 }
 
+// held-asset records in the layout the iteration kernels read: two float4
+// per record, w0 and the lot data side by side (one dependent load level)
+__global__ void pack_rec_kernel(PackArgs A, float4* rec, int total) {
+  for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+       idx += gridDim.x * blockDim.x) {
+    const float w0 = A.hold_w0[idx];
+    const int ti = A.hold_tax[idx];
+    if (ti >= 0) {
+      rec[2 * idx] = make_float4(w0, A.tax_brk[3 * ti], A.tax_brk[3 * ti + 1], A.tax_brk[3 * ti + 2]);
+      rec[2 * idx + 1] = make_float4(A.tax_slope[4 * ti], A.tax_slope[4 * ti + 1],
+                                     A.tax_slope[4 * ti + 2], A.tax_slope[4 * ti + 3]);
+    } else {
+      rec[2 * idx] = make_float4(w0, -1.f, 0.f, 0.f);
+      rec[2 * idx + 1] = make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+  }
+}
+
+hipError_t launch_pack_rec(const PackArgs& A, float4* rec, int total, hipStream_t st) {
+  if (total <= 0) return hipSuccess;
+  const int blocks = (total + 255) / 256 < 4096 ? (total + 255) / 256 : 4096;
+  hipLaunchKernelGGL(pack_rec_kernel, dim3(blocks), dim3(256), 0, st, A, rec, total);
+  return hipGetLastError();
+}
+
 hipError_t launch_pack_count(const PackArgs& A, hipStream_t st) {
   hipLaunchKernelGGL(pack_count_kernel, dim3(A.m), dim3(256), 0, st, A);
   return hipGetLastError();

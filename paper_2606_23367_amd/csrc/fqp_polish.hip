@@ -371,16 +371,14 @@ __global__ __launch_bounds__(kPT) void polish_solve_kernel(PolishArgs A) {
   const int nF = s_cnt[0], nX = s_cnt[1];
   // a pattern with many free coordinates belongs to an iterate that is far
   // from the optimum's vertex structure: skip the (costly) solve for now
-  if (A.nf_gate > 0 && nF > A.nf_gate) {
-    if (tid == 0) { ps[PS_STALL] = 1; ps[PS_NF] = nF; }
+  if ((A.nf_gate > 0 && nF > A.nf_gate) ||
+      // a larger free set is solved only when the iterate shows the same
+      // pattern at two consecutive checks
+      (A.first_round && A.nf_small > 0 && nF > A.nf_small && !s_same)) {
+    if (tid == 0) { ps[PS_STALL] = 1; ps[PS_NF] = nF; atomicAdd(A.pcount + 1, 1); }
     return;
   }
-  // a larger free set is solved only when the iterate shows the same
-  // pattern at two consecutive checks
-  if (A.first_round && A.nf_small > 0 && nF > A.nf_small && !s_same) {
-    if (tid == 0) { ps[PS_STALL] = 1; ps[PS_NF] = nF; }
-    return;
-  }
+  if (tid == 0) atomicAdd(A.pcount, 1);
 
   // ---- fixed contributions ----------------------------------------------
   // yX = B_X^T w_X, budget / band / cap sums of the fixed rows
@@ -1073,8 +1071,10 @@ __global__ __launch_bounds__(kPTC) void polish_check_kernel(PolishArgs A, fqp_re
         if (ps[PS_CAP] && lam < 0.0) { ps[PS_CAP] = 0; ++nchg; }
         else if (!ps[PS_CAP] && turn > tau + 0.1 * A.eps_prim) { ps[PS_CAP] = 1; ++nchg; }
       }
-      // no proposal: further rounds on this iterate cannot help
-      if (nchg == 0) ps[PS_STALL] = 1;
+      // no proposal: further rounds on this iterate cannot help; many
+      // proposals: the iterate is still far from its final pattern, and the
+      // next block of iterations is a cheaper way to get closer
+      if (nchg == 0 || nchg > A.max_prop) ps[PS_STALL] = 1;
     }
   }
   __syncthreads();

@@ -173,6 +173,7 @@ void fqp_default_settings(fqp_settings* s) {
   s->use_graph = 1;
   s->profile = 0;
   s->time_limit_ms = 0.0;
+  s->precision = FQP_PREC_BF16X3;
 }
 
 const char* fqp_error_string(int e) {
@@ -298,7 +299,7 @@ extern "C" fqp_error fqp_solve_batch(fqp_handle* h, const fqp_universe* U, const
     return FQP_ERR_INVALID_ARG;
   }
   if (S.max_iter < 1 || S.check_every < 1 || !(S.alpha > 0.f && S.alpha < 2.f) ||
-      S.polish_rounds < 1) {
+      S.polish_rounds < 1 || (S.precision != FQP_PREC_FP32 && S.precision != FQP_PREC_BF16X3)) {
     h->err = "invalid settings";
     return FQP_ERR_INVALID_ARG;
   }
@@ -408,6 +409,7 @@ extern "C" fqp_error fqp_solve_batch(fqp_handle* h, const fqp_universe* U, const
   WS(mult, double, "mult", (size_t)m * (2 + G));
   WS(gbase, double, "gbase", (size_t)m * n);
   WS(pstate, int32_t, "pstate", (size_t)m * kPStateStride);
+  WS(pcount, int32_t, "pcount", 2);
 
   // iteration geometry: ~1024 workgroups over (row tiles x account tiles)
   const int acc_tiles = (m + kTM - 1) / kTM;
@@ -418,10 +420,19 @@ extern "C" fqp_error fqp_solve_batch(fqp_handle* h, const fqp_universe* U, const
   const int n_rt = (n + rows_per_wg - 1) / rows_per_wg;
   WS(part, float, "part", (size_t)n_rt * m * kp);
   WS(stat, float, "stat", (size_t)n_rt * m * kNStat);
+  // bf16 hi/lo copies of B~ for the split-precision contractions
+  const int npad = ((n + kRowsPerChunk - 1) / kRowsPerChunk) * kRowsPerChunk;
+  const bool split = S.precision == FQP_PREC_BF16X3 && kp <= kMaxKpBf;
+  const size_t nbf = split ? (size_t)npad * kp : 1;
+  WS(bt_hi, uint16_t, "bt_hi", nbf);
+  WS(bt_lo, uint16_t, "bt_lo", nbf);
+  WS(btt_hi, uint16_t, "btt_hi", nbf);
+  WS(btt_lo, uint16_t, "btt_lo", nbf);
   h->stats.workspace_bytes = h->total_bytes;
 
   // ---- universe ------------------------------------------------------------
   HIP_CHECK(launch_build_bt(n, k, G, kp, U->B, U->group, Bt, st));
+  if (split) HIP_CHECK(launch_split_bt(n, npad, kp, Bt, bt_hi, bt_lo, btt_hi, btt_lo, st));
   HIP_CHECK(hipMemcpyAsync(rho_d, rho_cls.data(), sizeof(float) * ncls, hipMemcpyHostToDevice, st));
   HIP_CHECK(hipMemcpyAsync(cls_d, cls_h.data(), sizeof(int) * m, hipMemcpyHostToDevice, st));
   for (int c = 0; c < ncls; ++c) {
@@ -461,6 +472,7 @@ extern "C" fqp_error fqp_solve_batch(fqp_handle* h, const fqp_universe* U, const
   ia.tax_brk = P->tax_brk; ia.tax_slope = P->tax_slope; ia.pp = pp; ia.par = par;
   ia.par_rw = par;
   ia.part = part; ia.stat = stat;
+  ia.npad = npad; ia.bt_hi = bt_hi; ia.bt_lo = bt_lo; ia.btt_hi = btt_hi; ia.btt_lo = btt_lo;
   KArgs ka{};
   ka.kp = kp; ka.k = k; ka.G = G; ka.n_rt = n_rt; ka.m_total = m; ka.m_act = m_act; ka.act = act;
   ka.part = part; ka.stat = stat; ka.par = par; ka.pp = pp; ka.Kinv = Kinv; ka.cvec = cvec;
@@ -475,7 +487,8 @@ extern "C" fqp_error fqp_solve_batch(fqp_handle* h, const fqp_universe* U, const
   pa.tax_brk = P->tax_brk; pa.tax_slope = P->tax_slope; pa.par = par; pa.zb = zb; pa.vb = vb;
   pa.blo = G ? P->band_lo : nullptr; pa.bhi = G ? P->band_hi : nullptr;
   pa.code = code; pa.code_next = code_next; pa.flist = flist; pa.wk = wk; pa.wk_stride = wks; pa.wout = R->w;
-  pa.mult = mult; pa.pstate = pstate; pa.gbase = gbase;
+  pa.mult = mult; pa.pstate = pstate; pa.gbase = gbase; pa.pcount = pcount;
+  HIP_CHECK(hipMemsetAsync(pcount, 0, 2 * sizeof(int32_t), st));
   pa.eps_prim = S.eps_prim; pa.eps_dual = S.eps_dual; pa.eps_comp = S.eps_comp;
 
   std::vector<hipEvent_t> evs;
@@ -489,22 +502,29 @@ extern "C" fqp_error fqp_solve_batch(fqp_handle* h, const fqp_universe* U, const
   } evguard{&evs};
   const dim3 igrid(n_rt, acc_tiles);
   HIP_CHECK(hipMemsetAsync(stat, 0, sizeof(float) * (size_t)n_rt * m * kNStat, st));
-  // the cap kernel runs only when some account has a finite cap
+  // the cap kernel runs only when some account has a finite cap; the
+  // held-asset records are sized by the packed count
   bool any_cap = false;
+  int n_held = 0;
   {
     std::vector<float> tau_h(m);
     HIP_CHECK(hipMemcpyAsync(tau_h.data(), P->tau, sizeof(float) * m, hipMemcpyDeviceToHost, st));
+    HIP_CHECK(hipMemcpyAsync(&n_held, hold_ptr + m, sizeof(int), hipMemcpyDeviceToHost, st));
     HIP_CHECK(hipStreamSynchronize(st));
     for (int a = 0; a < m; ++a) any_cap = any_cap || std::isfinite(tau_h[a]);
   }
+  WS(hold_rec, float4, "hold_rec", 2 * (size_t)std::max(n_held, 1));
+  HIP_CHECK(launch_pack_rec(pk, hold_rec, n_held, st));
+  ia.hold_rec = hold_rec;
+  h->stats.workspace_bytes = h->total_bytes;
   // one ADMM iteration: contract, factor-space solve, project, cap
   auto launch_iteration = [&](int c) -> hipError_t {
-    hipError_t e0 = launch_iter(ia, kp, 0, igrid, st);
+    hipError_t e0 = launch_iter(ia, kp, 0, S.precision, igrid, st);
     if (e0 != hipSuccess) return e0;
     e0 = launch_ksolve(ka, m, st);
     if (e0 != hipSuccess) return e0;
     if (S.profile) { e0 = hipEventRecord(evs[2 * c], st); if (e0 != hipSuccess) return e0; }
-    e0 = launch_iter(ia, kp, 1, igrid, st);
+    e0 = launch_iter(ia, kp, 1, S.precision, igrid, st);
     if (e0 != hipSuccess) return e0;
     if (S.profile) { e0 = hipEventRecord(evs[2 * c + 1], st); if (e0 != hipSuccess) return e0; }
     if (any_cap) e0 = launch_cap(ia, m, st);
@@ -571,6 +591,7 @@ extern "C" fqp_error fqp_solve_batch(fqp_handle* h, const fqp_universe* U, const
     HIP_CHECK(launch_materialize_z(ia, m, z, st));
     pa.nf_gate = std::max(4 * k + 64, n / 8 + 4 * k);
     pa.nf_small = 2 * k + 32;
+    pa.max_prop = 16;
     for (int r = 0; r < S.polish_rounds; ++r) {
       pa.first_round = (r == 0);
       HIP_CHECK(launch_polish_solve(pa, st));
@@ -593,6 +614,7 @@ extern "C" fqp_error fqp_solve_batch(fqp_handle* h, const fqp_universe* U, const
     pa.first_round = 1;
     pa.nf_gate = 0;
     pa.nf_small = 0;
+    pa.max_prop = 1 << 30;
     HIP_CHECK(launch_polish_solve(pa, st));
     HIP_CHECK(launch_polish_check_r(pa, *R, 1, st));
     if (timed_out) {
@@ -606,6 +628,8 @@ extern "C" fqp_error fqp_solve_batch(fqp_handle* h, const fqp_universe* U, const
   // count solved accounts and account-iterations
   std::vector<int32_t> st_h(m);
   std::vector<int> it_h(m);
+  int32_t pc_h[2] = {0, 0};
+  HIP_CHECK(hipMemcpyAsync(pc_h, pcount, sizeof(pc_h), hipMemcpyDeviceToHost, st));
   HIP_CHECK(hipMemcpyAsync(st_h.data(), R->status, sizeof(int32_t) * m, hipMemcpyDeviceToHost, st));
   HIP_CHECK(hipMemcpyAsync(it_h.data(), iters, sizeof(int) * m, hipMemcpyDeviceToHost, st));
   HIP_CHECK(hipStreamSynchronize(st));
@@ -614,6 +638,8 @@ extern "C" fqp_error fqp_solve_batch(fqp_handle* h, const fqp_universe* U, const
     h->stats.account_iters += it_h[a];
   }
   h->stats.iterations = done_iters;
+  h->stats.polish_solves = pc_h[0];
+  h->stats.polish_gated = pc_h[1];
   {
     AdjArgs& L = h->last;
     L = AdjArgs{};
