@@ -82,29 +82,43 @@ __device__ __forceinline__ int popc_below(uint32_t word, int bit) {
   return __popc(word & ((1u << bit) - 1u));
 }
 
-// Y <- L^-T L^-1 Y for the k x ncol matrix Y (global), L lower in LDS.
+// Y <- L^-T L^-1 Y for the k x ncol matrix Y (row-major, any memory), L
+// lower (k <= 128).  Columns are independent: wave q solves columns q,
+// q + nwaves, ... with lane i holding rows i and i + 64, so the substitution
+// runs on shuffles without workgroup barriers.  Ends with a barrier.
 __device__ inline void chol_solve_cols(const double* L, int k, double* Y, int ncol) {
-  const int tid = threadIdx.x;
-  for (int j = 0; j < k; ++j) {
-    const double djj = L[j * k + j];
-    for (int c = tid; c < ncol; c += (int)blockDim.x) Y[j * ncol + c] /= djj;
-    __syncthreads();
-    for (int e = tid; e < (k - j - 1) * ncol; e += (int)blockDim.x) {
-      const int i = j + 1 + e / ncol, c = e % ncol;
-      Y[i * ncol + c] -= L[i * k + j] * Y[j * ncol + c];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int nw = (int)(blockDim.x >> 6);
+  for (int c = wv; c < ncol; c += nw) {
+    double y0 = (lane < k) ? Y[lane * ncol + c] : 0.0;
+    double y1 = (lane + 64 < k) ? Y[(lane + 64) * ncol + c] : 0.0;
+    for (int j = 0; j < k; ++j) {              // L z = y
+      const double yj = (j < 64) ? __shfl(y0, j, 64) : __shfl(y1, j - 64, 64);
+      const double zj = yj / L[j * k + j];
+      if (j < 64) {
+        if (lane == j) y0 = zj;
+        else if (lane > j && lane < k) y0 -= L[lane * k + j] * zj;
+      } else if (lane == j - 64) {
+        y1 = zj;
+      }
+      if (lane + 64 > j && lane + 64 < k) y1 -= L[(lane + 64) * k + j] * zj;
     }
-    __syncthreads();
-  }
-  for (int j = k - 1; j >= 0; --j) {
-    const double djj = L[j * k + j];
-    for (int c = tid; c < ncol; c += (int)blockDim.x) Y[j * ncol + c] /= djj;
-    __syncthreads();
-    for (int e = tid; e < j * ncol; e += (int)blockDim.x) {
-      const int i = e / ncol, c = e % ncol;
-      Y[i * ncol + c] -= L[j * k + i] * Y[j * ncol + c];
+    for (int j = k - 1; j >= 0; --j) {         // L^T x = z
+      const double zj = (j < 64) ? __shfl(y0, j, 64) : __shfl(y1, j - 64, 64);
+      const double xj = zj / L[j * k + j];
+      if (j < 64) {
+        if (lane == j) y0 = xj;
+        else if (lane < j) y0 -= L[j * k + lane] * xj;
+      } else {
+        if (lane == j - 64) y1 = xj;
+        else if (lane + 64 < j) y1 -= L[j * k + lane + 64] * xj;
+        y0 -= L[j * k + lane] * xj;            // every row i < 64 <= j
+      }
     }
-    __syncthreads();
+    if (lane < k) Y[lane * ncol + c] = y0;
+    if (lane + 64 < k) Y[(lane + 64) * ncol + c] = y1;
   }
+  __syncthreads();
 }
 
 }  // namespace fqp

@@ -122,6 +122,7 @@ struct PolishArgs {
   const uint32_t* elig;
   const uint32_t* hold;
   const int32_t* hold_pre;
+  const float4* hold_rec;    // [nnz_h][2] packed held records (as IterArgs)
   const int32_t* hold_ptr;
   const float* hold_w0;
   const int32_t* hold_tax;
@@ -147,9 +148,12 @@ struct PolishArgs {
   int nf_small;              // larger free sets wait for a repeated pattern
   int* pcount;               // [2] reduced solves formed, attempts gated
   int max_prop;              // a failed pattern with more proposals stops refining
+  int n_rb;                  // row blocks of the gradient-base pass
+  double* gpart;             // [m][n_rb][4] its per-block reductions
 };
 hipError_t launch_polish_solve(const PolishArgs& A, hipStream_t st);
 size_t polish_wk_stride(int k, int G);
+int polish_row_blocks(int n);
 
 // ---- KKT adjoint (float64) ---------------------------------------------------
 struct AdjArgs {

@@ -58,17 +58,46 @@ struct Geom {
   double w0;
 };
 
-__device__ void make_geom(Geom& g, bool el, float lbf, float ubf, float w0f, float kap,
-                          bool phi, int ti, const float* brk, const float* slp) {
+// eligibility, w0 and lot data of (account, row): the bitmask words, then
+// one dependent load of the packed record for a held row
+struct RowData {
+  bool el;
+  bool taxed;
+  float w0;
+  float b1, b2, b3, s0, s1, s2, s3;
+};
+
+__device__ __forceinline__ RowData row_data(const PolishArgs& A, int a, int i) {
+  RowData r;
+  const int wd = i >> 5, b = i & 31;
+  const size_t wi = (size_t)a * A.W + wd;
+  r.el = A.elig == nullptr || ((A.elig[wi] >> b) & 1u);
+  const uint32_t hw = A.hold[wi];
+  r.w0 = 0.f;
+  r.taxed = false;
+  r.b1 = r.b2 = r.b3 = r.s0 = r.s1 = r.s2 = r.s3 = 0.f;
+  if ((hw >> b) & 1u) {
+    const int idx = A.hold_ptr[a] + A.hold_pre[wi] + popc_below(hw, b);
+    const float4 r0 = A.hold_rec[2 * idx], r1 = A.hold_rec[2 * idx + 1];
+    r.w0 = r0.x;
+    r.taxed = r0.y > 0.f;
+    r.b1 = r0.y; r.b2 = r0.z; r.b3 = r0.w;
+    r.s0 = r1.x; r.s1 = r1.y; r.s2 = r1.z; r.s3 = r1.w;
+  }
+  return r;
+}
+
+__device__ void make_geom(Geom& g, float lbf, float ubf, float kap, bool phi, const RowData& r) {
+  const bool el = r.el;
+  const float w0f = r.w0;
   const double lb = el ? (double)lbf : 0.0, ub = el ? (double)ubf : 0.0;
   g.w0 = w0f;
   g.nk = 0;
   float kf[4];
   if (phi) {
-    if (ti >= 0) {
-      const float b1 = brk[3 * ti], b2 = brk[3 * ti + 1], b3 = brk[3 * ti + 2];
-      const float s0 = slp[4 * ti], s1 = slp[4 * ti + 1], s2 = slp[4 * ti + 2],
-                  s3 = slp[4 * ti + 3];
+    if (r.taxed) {
+      const float b1 = r.b1, b2 = r.b2, b3 = r.b3;
+      const float s0 = r.s0, s1 = r.s1, s2 = r.s2, s3 = r.s3;
       g.nk = 4;
       g.kink[0] = (double)w0f - b3; kf[0] = w0f - b3;
       g.kink[1] = (double)w0f - b2; kf[1] = w0f - b2;
@@ -125,37 +154,17 @@ __device__ __forceinline__ void subdiff(const Geom& g, double x, double lam, dou
   if (x >= ub - kSnap) { hi = INFINITY; snap = fmax(snap, fmax(ub - x, 0.0)); }
 }
 
-struct RowData {
-  bool el;
-  float w0;
-  int ti;
-};
-
-__device__ __forceinline__ RowData row_data(const PolishArgs& A, int a, int i) {
-  RowData r;
-  const int wd = i >> 5, b = i & 31;
-  r.el = A.elig == nullptr || ((A.elig[(size_t)a * A.W + wd] >> b) & 1u);
-  const uint32_t hw = A.hold[(size_t)a * A.W + wd];
-  r.w0 = 0.f;
-  r.ti = -1;
-  if ((hw >> b) & 1u) {
-    const int idx = A.hold_ptr[a] + A.hold_pre[(size_t)a * A.W + wd] + popc_below(hw, b);
-    r.w0 = A.hold_w0[idx];
-    r.ti = A.hold_tax[idx];
-  }
-  return r;
-}
 
 size_t polish_wk_stride(int k, int G) {
   const size_t ncol = (size_t)G + 3;
   // Waug, Y (k x ncol), CV (ncol^2), S (ncol^2), yX, Fy, sol (k), h, eta, eta0
   // (ncol), misc 16
   return 2 * (size_t)k * ncol + 2 * ncol * ncol + 3 * (size_t)k + 3 * ncol +
-         (size_t)kMaxNull * ncol + 16;
+         (size_t)kMaxNull * ncol + (size_t)k + (size_t)G + 1 + 16;
 }
 
 struct Wk {
-  double *Waug, *Y, *CV, *S, *yX, *Fy, *sol, *h, *eta, *eta0, *nul, *misc;
+  double *Waug, *Y, *CV, *S, *yX, *Fy, *sol, *h, *eta, *eta0, *nul, *yF, *gsum, *misc;
 };
 __device__ __forceinline__ Wk wk_of(const PolishArgs& A, int a) {
   Wk w;
@@ -173,6 +182,8 @@ __device__ __forceinline__ Wk wk_of(const PolishArgs& A, int a) {
   w.eta = p; p += ncol;
   w.eta0 = p; p += ncol;
   w.nul = p; p += (size_t)kMaxNull * ncol;   // [kMaxNull][ncol] null directions
+  w.yF = p; p += k;                            // F B^T w of the polished w
+  w.gsum = p; p += (size_t)A.G + 1;            // group sums of the polished w
   w.misc = p;
   return w;
 }
@@ -296,7 +307,7 @@ __global__ __launch_bounds__(kPT) void polish_solve_kernel(PolishArgs A) {
     for (int i = tid; i < n; i += kPT) {
       RowData r = row_data(A, a, i);
       Geom g;
-      make_geom(g, r.el, lbf, ubf, r.w0, kap, phi, r.ti, A.tax_brk, A.tax_slope);
+      make_geom(g, lbf, ubf, kap, phi, r);
       const float z = A.z[(size_t)a * n + i];
       int c = -1;
       for (int j = 0; j < g.np; ++j)
@@ -343,7 +354,7 @@ __global__ __launch_bounds__(kPT) void polish_solve_kernel(PolishArgs A) {
         } else {
           RowData r = row_data(A, a, i);
           Geom g;
-          make_geom(g, r.el, lbf, ubf, r.w0, kap, phi, r.ti, A.tax_brk, A.tax_slope);
+          make_geom(g, lbf, ubf, kap, phi, r);
           const double v = g.pt[c >> 1];
           w[i] = v;
           isnz = (v != 0.0);
@@ -513,7 +524,7 @@ __global__ __launch_bounds__(kPT) void polish_solve_kernel(PolishArgs A) {
         const int i = flist[f0 + rr];
         RowData r = row_data(A, a, i);
         Geom g;
-        make_geom(g, r.el, lbf, ubf, r.w0, kap, phi, r.ti, A.tax_brk, A.tax_slope);
+        make_geom(g, lbf, ubf, kap, phi, r);
         double slope, sgn;
         piece_slope(g, code[i] >> 1, slope, sgn);
         double* x = stg + rr * CS;
@@ -567,11 +578,12 @@ __global__ __launch_bounds__(kPT) void polish_solve_kernel(PolishArgs A) {
 
   // ---- Cholesky of Kf (lower, in LDS) -------------------------------------
   for (int j = 0; j < k; ++j) {
-    if (tid == 0) Kf[j * k + j] = sqrt(fmax(Kf[j * k + j], 1e-300));
-    __syncthreads();
-    const double djj = Kf[j * k + j];
+    // every thread takes the pivot itself; thread 0 stores it after the
+    // barrier that ends this step's reads of the unscaled diagonal
+    const double djj = sqrt(fmax(Kf[j * k + j], 1e-300));
     for (int i = j + 1 + tid; i < k; i += kPT) Kf[i * k + j] /= djj;
     __syncthreads();
+    if (tid == 0) Kf[j * k + j] = djj;
     const int m = k - j - 1;
     for (int e = tid; e < m * m; e += kPT) {
       const int i = j + 1 + e / m, l = j + 1 + e % m;
@@ -697,7 +709,7 @@ __global__ __launch_bounds__(kPT) void polish_solve_kernel(PolishArgs A) {
     const int i = flist[t];
     RowData r = row_data(A, a, i);
     Geom g;
-    make_geom(g, r.el, lbf, ubf, r.w0, kap, phi, r.ti, A.tax_brk, A.tax_slope);
+    make_geom(g, lbf, ubf, kap, phi, r);
     double slope, sgn;
     piece_slope(g, code[i] >> 1, slope, sgn);
     double cross = 0.0, bs = 0.0;
@@ -720,13 +732,103 @@ __global__ __launch_bounds__(kPT) void polish_solve_kernel(PolishArgs A) {
 }
 
 // ---------------------------------------------------------------------------
+// polish_sums: y = F B^T w and group sums of the polished w over its
+// nonzero rows (free list and nonzero fixed list), one workgroup per account
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kPTC) void polish_sums_kernel(PolishArgs A, int final_pass) {
+  extern __shared__ float sBrow[];        // [64][k + 1] staged B rows
+  __shared__ double s_sw[64];
+  __shared__ int s_si[64];
+  const int k = A.k, G = A.G, n = A.n;
+  const int slot = blockIdx.x;
+  if (slot >= *A.m_act) return;
+  const int a = A.act[slot];
+  const int* ps = A.pstate + (size_t)a * kPStateStride;
+  if (ps[PS_DONE] || (ps[PS_STALL] && !final_pass)) return;
+  const int tid = threadIdx.x;
+  const int32_t* flist = A.flist + (size_t)a * n;
+  const double* w = A.wout + (size_t)a * n;
+  double ys = 0.0, gs = 0.0;
+  list_sums(A, flist, n, ps[PS_NF], 0, w, sBrow, s_sw, s_si, ys, gs);
+  list_sums(A, flist, n, ps[PS_NX], 1, w, sBrow, s_sw, s_si, ys, gs);
+  const Wk wk = wk_of(A, a);
+  if (tid < k) wk.yF[tid] = ys * (double)A.f[tid];
+  if (tid < G) wk.gsum[tid] = gs;
+}
+
+// ---------------------------------------------------------------------------
+// polish_gbase: gb_i = gamma (Sigma w)_i - mu_i for every row, spread over
+// (row block, account) workgroups; per block: max |gamma Sigma w|, max |mu|,
+// turnover and a non-finite flag
+// ---------------------------------------------------------------------------
+constexpr int kGbRows = 256;              // rows per gbase workgroup
+
+__global__ __launch_bounds__(256) void polish_gbase_kernel(PolishArgs A, int final_pass) {
+  __shared__ double s_y[kMaxK];
+  __shared__ double s_red[4][4];
+  const int k = A.k, n = A.n;
+  const int slot = blockIdx.y;
+  if (slot >= *A.m_act) return;
+  const int a = A.act[slot];
+  const int* ps = A.pstate + (size_t)a * kPStateStride;
+  if (ps[PS_DONE] || (ps[PS_STALL] && !final_pass)) return;
+  const int tid = threadIdx.x;
+  const Wk wk = wk_of(A, a);
+  for (int j = tid; j < k; j += 256) s_y[j] = wk.yF[j];
+  __syncthreads();
+  const double gam = A.par[(size_t)a * kNPar + P_GAMMA];
+  const double* w = A.wout + (size_t)a * n;
+  double* gb = A.gbase + (size_t)a * n;
+  double gmax = 0.0, mumax = 0.0, turn = 0.0, bad = 0.0;
+  const int q4 = tid & 3;
+  const int r_begin = blockIdx.x * kGbRows;
+  // four lanes per row split b_i . y; a wave covers 16 consecutive rows
+#pragma unroll
+  for (int it = 0; it < kGbRows / 64; ++it) {
+    const int i = r_begin + it * 64 + (tid >> 2);
+    double sig = 0.0;
+    if (i < n) {
+      const float* brow = A.Bt + (size_t)i * A.kp;
+      for (int j = q4; j < k; j += 4) sig += (double)brow[j] * s_y[j];
+    }
+    sig += __shfl_xor(sig, 1, 64);
+    sig += __shfl_xor(sig, 2, 64);
+    if (i < n && q4 == 0) {
+      sig += (double)A.d[i] * w[i];
+      const double mui = A.mu[(size_t)a * n + i];
+      const double v = gam * sig - mui;
+      gb[i] = v;
+      gmax = fmax(gmax, fabs(gam * sig));
+      mumax = fmax(mumax, fabs(mui));
+      turn += fabs(w[i] - (double)row_data(A, a, i).w0);
+      if (!isfinite(v) || !isfinite(w[i])) bad = 1.0;
+    }
+  }
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) {
+    gmax = fmax(gmax, __shfl_xor(gmax, o, 64));
+    mumax = fmax(mumax, __shfl_xor(mumax, o, 64));
+    turn += __shfl_xor(turn, o, 64);
+    bad = fmax(bad, __shfl_xor(bad, o, 64));
+  }
+  if ((tid & 63) == 0) {
+    s_red[tid >> 6][0] = gmax; s_red[tid >> 6][1] = mumax;
+    s_red[tid >> 6][2] = turn; s_red[tid >> 6][3] = bad;
+  }
+  __syncthreads();
+  if (tid < 4) {
+    double v = s_red[0][tid];
+    for (int q = 1; q < 4; ++q) v = (tid == 2) ? v + s_red[q][tid] : fmax(v, s_red[q][tid]);
+    A.gpart[((size_t)a * A.n_rb + blockIdx.x) * 4 + tid] = v;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // polish_check: external diagnostics in float64 and refinement
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kPTC) void polish_check_kernel(PolishArgs A, fqp_result R,
                                                           int final_pass) {
-  extern __shared__ float sBrow[];        // [64][k + 1] staged B rows
   __shared__ double shd[kPW];
-  __shared__ double s_y[kMaxK];
   __shared__ double s_gs[kMaxG];
   const int k = A.k, G = A.G, n = A.n;
   const int slot = blockIdx.x;
@@ -754,46 +856,18 @@ __global__ __launch_bounds__(kPTC) void polish_check_kernel(PolishArgs A, fqp_re
   __shared__ int s_bad, s_done;
   if (tid == 0) { s_bad = 0; s_done = 0; }
 
-  // y = F B^T w and group sums over the rows with w != 0 (free list and
-  // nonzero fixed list), LDS-staged
-  {
-    __shared__ double s_sw[64];
-    __shared__ int s_si[64];
-    double ys = 0.0, gs = 0.0;
-    list_sums(A, flist, n, nF, 0, w, sBrow, s_sw, s_si, ys, gs);
-    list_sums(A, flist, n, nX, 1, w, sBrow, s_sw, s_si, ys, gs);
-    if (tid < k) s_y[tid] = ys * (double)A.f[tid];
-    if (tid < G) s_gs[tid] = gs;
-  }
-  __syncthreads();
-
-  // ---- gradient base  gb_i = gamma (Sigma w)_i - mu_i -----------------------
-  // four lanes per row split the dot product b_i . y (a wave reads 16
-  // consecutive rows of B~ at once), then one lane finishes the row
+  // group sums (from polish_sums) and the reductions of polish_gbase
+  __syncthreads();                        // flags above are initialised
+  const Wk wkc = wk_of(A, a);
+  for (int g = tid; g < G; g += kPTC) s_gs[g] = wkc.gsum[g];
   double gmax = 0.0, mumax = 0.0, turn0 = 0.0;
   int bad = 0;
-  {
-    const int q4 = tid & 3;
-    for (int base = 0; base < n; base += kPTC / 4) {
-      const int i = base + (tid >> 2);
-      double sig = 0.0;
-      if (i < n) {
-        const float* brow = A.Bt + (size_t)i * A.kp;
-        for (int j = q4; j < k; j += 4) sig += (double)brow[j] * s_y[j];
-      }
-      sig += __shfl_xor(sig, 1, 64);
-      sig += __shfl_xor(sig, 2, 64);
-      if (i < n && q4 == 0) {
-        sig += (double)A.d[i] * w[i];
-        const double mui = A.mu[(size_t)a * n + i];
-        const double v = gam * sig - mui;
-        gb[i] = v;
-        gmax = fmax(gmax, fabs(gam * sig));
-        mumax = fmax(mumax, fabs(mui));
-        turn0 += fabs(w[i] - (double)row_data(A, a, i).w0);
-        if (!isfinite(v) || !isfinite(w[i])) bad = 1;
-      }
-    }
+  for (int rb = tid; rb < A.n_rb; rb += kPTC) {
+    const double* gp = A.gpart + ((size_t)a * A.n_rb + rb) * 4;
+    gmax = fmax(gmax, gp[0]);
+    mumax = fmax(mumax, gp[1]);
+    turn0 += gp[2];
+    if (gp[3] != 0.0) bad = 1;
   }
   if (bad) atomicOr(&s_bad, 1);
   gmax = bmax<double>(gmax, shd);
@@ -834,7 +908,7 @@ __global__ __launch_bounds__(kPTC) void polish_check_kernel(PolishArgs A, fqp_re
           RowData r = row_data(A, a, i);
           if (!r.el) continue;
           Geom g;
-          make_geom(g, r.el, lbf, ubf, r.w0, kap, phi, r.ti, A.tax_brk, A.tax_slope);
+          make_geom(g, lbf, ubf, kap, phi, r);
           const double lb = lbf, ub = ubf;
           double nb = 0.0, lg = 0.0;
           if (G) {
@@ -951,7 +1025,7 @@ __global__ __launch_bounds__(kPTC) void polish_check_kernel(PolishArgs A, fqp_re
   for (int i = tid; i < n; i += kPTC) {
     RowData r = row_data(A, a, i);
     Geom g;
-    make_geom(g, r.el, lbf, ubf, r.w0, kap, phi, r.ti, A.tax_brk, A.tax_slope);
+    make_geom(g, lbf, ubf, kap, phi, r);
     const double lb = r.el ? (double)lbf : 0.0, ub = r.el ? (double)ubf : 0.0;
     const double wi = w[i];
     const double mui = A.mu[(size_t)a * n + i];
@@ -970,12 +1044,12 @@ __global__ __launch_bounds__(kPTC) void polish_check_kernel(PolishArgs A, fqp_re
     snapm = fmax(snapm, snap);
     // objective: (gamma/2) w.Sigma w - mu w + trade cost
     double tc = (double)kap * fabs(wi - g.w0);
-    if (r.ti >= 0 && wi < g.w0) {
+    if (r.taxed && wi < g.w0) {
       const double s = g.w0 - wi;
-      const double e[5] = {0.0, (double)A.tax_brk[3 * r.ti], (double)A.tax_brk[3 * r.ti + 1],
-                           (double)A.tax_brk[3 * r.ti + 2], INFINITY};
+      const double e[5] = {0.0, (double)r.b1, (double)r.b2, (double)r.b3, INFINITY};
+      const double sl[4] = {(double)r.s0, (double)r.s1, (double)r.s2, (double)r.s3};
       for (int L = 0; L < 4; ++L)
-        if (s > e[L]) tc += (double)A.tax_slope[4 * r.ti + L] * (fmin(s, e[L + 1]) - e[L]);
+        if (s > e[L]) tc += sl[L] * (fmin(s, e[L + 1]) - e[L]);
     }
     obj += 0.5 * gam * wi * sig - mui * wi + tc;
     // refinement proposal (applied only if the pattern fails)
@@ -1111,11 +1185,20 @@ hipError_t launch_polish_solve(const PolishArgs& A, hipStream_t st) {
 hipError_t launch_polish_check_r(const PolishArgs& A, const fqp_result& R, int final_pass,
                                  hipStream_t st) {
   const size_t smem = sizeof(float) * 64 * (size_t)(A.k + 1);
-  hipError_t e = hipFuncSetAttribute((const void*)polish_check_kernel,
+  hipError_t e = hipFuncSetAttribute((const void*)polish_sums_kernel,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(polish_check_kernel, dim3(A.m_total), dim3(kPTC), smem, st, A, R, final_pass);
+  hipLaunchKernelGGL(polish_sums_kernel, dim3(A.m_total), dim3(kPTC), smem, st, A, final_pass);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(polish_gbase_kernel, dim3(A.n_rb, A.m_total), dim3(256), 0, st, A,
+                     final_pass);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(polish_check_kernel, dim3(A.m_total), dim3(kPTC), 0, st, A, R, final_pass);
   return hipGetLastError();
 }
+
+int polish_row_blocks(int n) { return (n + kGbRows - 1) / kGbRows; }
 
 }  // namespace fqp

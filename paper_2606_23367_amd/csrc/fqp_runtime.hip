@@ -410,6 +410,8 @@ extern "C" fqp_error fqp_solve_batch(fqp_handle* h, const fqp_universe* U, const
   WS(gbase, double, "gbase", (size_t)m * n);
   WS(pstate, int32_t, "pstate", (size_t)m * kPStateStride);
   WS(pcount, int32_t, "pcount", 2);
+  const int n_rb = polish_row_blocks(n);
+  WS(gpart_p, double, "polish_gpart", (size_t)m * n_rb * 4);
 
   // iteration geometry: ~1024 workgroups over (row tiles x account tiles)
   const int acc_tiles = (m + kTM - 1) / kTM;
@@ -488,6 +490,7 @@ extern "C" fqp_error fqp_solve_batch(fqp_handle* h, const fqp_universe* U, const
   pa.blo = G ? P->band_lo : nullptr; pa.bhi = G ? P->band_hi : nullptr;
   pa.code = code; pa.code_next = code_next; pa.flist = flist; pa.wk = wk; pa.wk_stride = wks; pa.wout = R->w;
   pa.mult = mult; pa.pstate = pstate; pa.gbase = gbase; pa.pcount = pcount;
+  pa.n_rb = n_rb; pa.gpart = gpart_p;
   HIP_CHECK(hipMemsetAsync(pcount, 0, 2 * sizeof(int32_t), st));
   pa.eps_prim = S.eps_prim; pa.eps_dual = S.eps_dual; pa.eps_comp = S.eps_comp;
 
@@ -516,6 +519,7 @@ extern "C" fqp_error fqp_solve_batch(fqp_handle* h, const fqp_universe* U, const
   WS(hold_rec, float4, "hold_rec", 2 * (size_t)std::max(n_held, 1));
   HIP_CHECK(launch_pack_rec(pk, hold_rec, n_held, st));
   ia.hold_rec = hold_rec;
+  pa.hold_rec = hold_rec;
   h->stats.workspace_bytes = h->total_bytes;
   // one ADMM iteration: contract, factor-space solve, project, cap
   auto launch_iteration = [&](int c) -> hipError_t {
