@@ -8,12 +8,15 @@ polish and certification of every account.  Inputs are resident in HBM when
 the timed region starts.  value = accounts certified to 1e-6 KKT residuals
 per second.
 
-The roofline object describes the fused iteration kernel (the dominant one):
-algorithmic bytes per launch / average launch duration, timed with HIP
-events on the library's stream inside the timed steps.
+The roofline object describes the PROJECT pass (the dominant iteration
+kernel): algorithmic bytes per launch / average launch duration, timed with
+HIP events on the library's stream inside the timed steps.
 
-The cpu_baseline object times the float64 oracle on a bounded sample of the
-same book on the host cores.
+plain_fp32 is the same book solved one account per call with float32
+contractions (the unbatched form), on a bounded sample of accounts.
+
+cpu_baseline times the float64 oracle on a bounded sample of the same book
+on the host cores.
 """
 import argparse
 import json
@@ -26,20 +29,91 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 WORKLOAD = "c3"
-SETTINGS = dict(rho=10.0)
+# ADMM penalty, over-relaxation and certification interval for this book
+# shape; bf16-split contractions (the library default)
+SETTINGS = dict(rho=8.0, alpha=1.8, check_every=100, precision=1)
 
 
-def algorithmic_bytes(uni, book, iters):
-    """Algorithmic bytes of the timed kernel (the PROJECT pass: back-
-    projection, relaxation and the write of the new ADMM state).  Per
-    account-iteration: state v read + written (8 N), returns read (4 N),
-    eligibility bits (ceil(N/8)), held records (w0 + 7 tax-lot floats,
-    32 B each); per launch: B read once (4 N k) and d (4 N)."""
+def algorithmic_bytes(uni, book, iters, precision):
+    """Algorithmic bytes of the PROJECT pass (back-projection, relaxation and
+    the write of the new ADMM state).  Per account-iteration: state v read
+    and written (8 N), returns read (4 N), eligibility, holding and holding-
+    prefix words (12 B per 32 assets), held records (two float4 per held
+    name).  Per launch: the k + G + 1 used columns of B~ once (bf16 hi and
+    lo: 4 B per entry; float32: 4 B) and d (4 N)."""
     import numpy as np
     n, k = uni.n, uni.k
+    G = uni.n_groups
     held = np.count_nonzero(book.w0, axis=1)
-    per_acc = 12.0 * n + np.ceil(n / 8.0) + 32.0 * held
-    return float(np.sum(iters * per_acc)), float(4.0 * n * k + 4.0 * n)
+    per_acc = 12.0 * n + 12.0 * np.ceil(n / 32.0) + 32.0 * held
+    per_launch = 4.0 * n * (k + G + 1) + 4.0 * n
+    return float(np.sum(iters * per_acc)), float(per_launch)
+
+
+TRAFFIC_NOTE = os.path.join(ROOT, "profiles", "project_pass_c3_500x10000_hbm_traffic.md")
+KERNEL_SOURCES = ["paper_2606_23367_amd/csrc/fqp_iter.hip", "paper_2606_23367_amd/csrc/fqp_common.h",
+                  "paper_2606_23367_amd/csrc/fqp_kernels.h"]
+
+
+def measured_traffic():
+    """HBM bytes per PROJECT launch from the committed counter summary, or
+    None when the kernel sources changed since the counters were taken."""
+    import hashlib
+    try:
+        txt = open(TRAFFIC_NOTE).read()
+    except OSError:
+        return None
+    vals = dict(line.split(": ", 1) for line in txt.splitlines()
+                if line.startswith(("traffic_bytes_per_launch: ", "kernel_sources_sha256: ")))
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    if vals.get("kernel_sources_sha256", "").strip() != h.hexdigest():
+        return None
+    return float(vals["traffic_bytes_per_launch"])
+
+
+def timed_solves(solver, P, steps, settings):
+    """Run `steps` solves with per-launch events on the PROJECT pass; returns
+    (seconds, certified, kernel_ms, launches, iters per solve)."""
+    import torch
+    out = None
+    solved, kernel_ms, launches, iters = 0, 0.0, 0, []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        out = solver.solve(P, out=out, profile=1, **settings)
+        st = solver.stats()
+        iters.append(out["iters"].cpu().numpy())
+        solved += int((out["status"] == 0).sum().item())
+        kernel_ms += st["iter_kernel_ms"]
+        launches += st["iter_launches"]
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0, solved, kernel_ms, launches, iters
+
+
+def plain_fp32(uni, book, n_sample):
+    """The unbatched float32 form: one account per fqp_solve_batch call,
+    float32 MFMA contractions, the first n_sample accounts."""
+    from workloads import subset_accounts
+    from paper_2606_23367_amd.solver import Solver, to_device
+    settings = dict(SETTINGS, precision=0)
+    solver = Solver(0)
+    probs = [to_device(uni, subset_accounts(book, [a]), "cuda:0") for a in range(n_sample)]
+    timed_solves(solver, probs[0], 1, settings)                  # warm-up
+    dt, solved, kms, launches, alg = 0.0, 0, 0.0, 0, 0.0
+    for a, P in enumerate(probs):
+        t, s, km, la, it = timed_solves(solver, P, 1, settings)
+        dt += t; solved += s; kms += km; launches += la
+        per_acc, per_launch = algorithmic_bytes(uni, subset_accounts(book, [a]), it[0], 0)
+        alg += per_acc + per_launch * la
+    achieved = alg / (kms * 1e-3) / 1e9 if kms > 0 else None
+    return dict(value=solved / dt, unit="accounts/s", sample=f"first {n_sample} accounts, "
+                f"one per call, {solved} certified", precision="fp32 MFMA contractions",
+                project_achieved_gbs=achieved,
+                project_frac=(achieved / HBM_PEAK_GBS) if achieved else None,
+                avg_launch_us=kms * 1e3 / max(launches, 1))
 
 
 def cpu_baseline(uni, book, n_sample):
@@ -87,6 +161,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--cpu-sample", type=int, default=96)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--plain-sample", type=int, default=16,
+                    help="accounts of the one-account-per-call float32 comparison")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run 5 plain device copies of MIB MiB (the "
                          "reference kernel that scales HBM counters)")
@@ -113,28 +189,14 @@ def main():
     uni, book = make_config(WORKLOAD, 0)
     P = to_device(uni, book, "cuda:0")
     solver = Solver(0)
-    out = None
-    for _ in range(args.warmup):
-        out = solver.solve(P, out=out, profile=1, **SETTINGS)
-    torch.cuda.synchronize()
-
-    solved = 0
-    kernel_ms = 0.0
+    if args.warmup:
+        timed_solves(solver, P, args.warmup, SETTINGS)
+    dt, solved, kernel_ms, launches, iters = timed_solves(solver, P, args.steps, SETTINGS)
     alg_bytes = 0.0
-    launches = 0
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        out = solver.solve(P, out=out, profile=1, **SETTINGS)
-        st = solver.stats()
-        iters = out["iters"].cpu().numpy()
-        solved += int((out["status"] == 0).sum().item())
-        kernel_ms += st["iter_kernel_ms"]
-        per_acc, per_launch = algorithmic_bytes(uni, book, iters)
-        alg_bytes += per_acc + per_launch * st["iter_launches"]
-        launches += st["iter_launches"]
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
+    for it in iters:
+        per_acc, per_launch = algorithmic_bytes(uni, book, it, SETTINGS["precision"])
+        alg_bytes += per_acc
+    alg_bytes += per_launch * launches
 
     value = solved / dt
     achieved = alg_bytes / (kernel_ms * 1e-3) / 1e9 if kernel_ms > 0 else None
@@ -150,13 +212,15 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32+f64",
+        "dtype": "f32 (bf16-split MFMA) + f64",
         "data": "synthetic",
         "config": {
             "workload": "500 accounts x N=10,000 assets, k=80 factors; "
                         "exclusion masks (30-100% eligible), 4-lot tax on "
-                        "100-400 held names, turnover cap; FP32 ADMM + FP64 "
-                        "polish/certification",
+                        "100-400 held names, turnover cap; FP32 ADMM with "
+                        "bf16-split MFMA contractions + FP64 polish and "
+                        "certification",
+            "settings": SETTINGS,
             "accounts": book.m, "assets": uni.n, "factors": uni.k,
             "certified_per_step": solved / args.steps,
             "iter_launches_per_step": launches / args.steps,
@@ -167,12 +231,16 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
-            "traffic": None,
-            "kernel": "iter_kernel<PROJECT> (MFMA back-projection B~p, "
-                      "x-update, over-relaxation, new ADMM state)",
+            "traffic": measured_traffic(),
+            "kernel": "iter_kernel_bf<3, PROJECT> (bf16-split MFMA "
+                      "back-projection B~p, x-update, over-relaxation, new "
+                      "ADMM state)",
+            "alg_bytes_per_launch": alg_bytes / max(launches, 1),
             "avg_launch_us": kernel_ms * 1e3 / max(launches, 1),
         },
     }
+    if args.plain_sample > 0:
+        line["plain_fp32"] = plain_fp32(uni, book, args.plain_sample)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(uni, book, args.cpu_sample)
     print(json.dumps(line), flush=True)
