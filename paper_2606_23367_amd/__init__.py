@@ -8,7 +8,10 @@ from ._lib import STATUS_NAMES, SOLVED  # noqa: F401
 
 def __getattr__(name):
     if name in ("Solver", "solve_batch", "to_device", "DeviceProblem",
-                "pack_eligibility", "FqpFunction", "solve_differentiable"):
+                "pack_eligibility", "FqpFunction", "solve_differentiable", "subset"):
         from . import solver
         return getattr(solver, name)
+    if name == "autotune":
+        from .tune import autotune
+        return autotune
     raise AttributeError(name)

@@ -55,6 +55,30 @@ class DeviceProblem:
     tax_slope: Optional[torch.Tensor]
 
 
+def subset(P: DeviceProblem, idx) -> DeviceProblem:
+    """The accounts ``idx`` of a device book (same universe, same device)."""
+    idx_l = [int(a) for a in idx]
+    it = torch.as_tensor(idx_l, dtype=torch.long, device=P.mu.device)
+    rows = (lambda t: None if t is None else t.index_select(0, it).contiguous())
+    tax_ptr = tax_asset = tax_brk = tax_slope = None
+    if P.tax_ptr is not None:
+        ptr = P.tax_ptr.cpu().numpy()
+        sel = np.concatenate([np.arange(ptr[a], ptr[a + 1]) for a in idx_l]).astype(np.int64) \
+            if idx_l else np.zeros(0, np.int64)
+        new_ptr = np.concatenate([[0], np.cumsum([ptr[a + 1] - ptr[a] for a in idx_l])])
+        st = torch.as_tensor(sel, device=P.mu.device)
+        tax_ptr = torch.as_tensor(new_ptr.astype(np.int32), device=P.mu.device)
+        tax_asset = P.tax_asset.index_select(0, st).contiguous()
+        tax_brk = P.tax_brk.index_select(0, st).contiguous()
+        tax_slope = P.tax_slope.index_select(0, st).contiguous()
+    return DeviceProblem(
+        n=P.n, k=P.k, G=P.G, m=len(idx_l), B=P.B, f=P.f, d=P.d, group=P.group,
+        mu=rows(P.mu), w0=rows(P.w0), lb=rows(P.lb), ub=rows(P.ub),
+        eligible=rows(P.eligible), gamma=rows(P.gamma), kappa=rows(P.kappa),
+        tau=rows(P.tau), band_lo=rows(P.band_lo), band_hi=rows(P.band_hi),
+        tax_ptr=tax_ptr, tax_asset=tax_asset, tax_brk=tax_brk, tax_slope=tax_slope)
+
+
 def to_device(uni, book, device="cuda:0") -> DeviceProblem:
     """Lay out a (workloads.Universe, workloads.Book) pair on the device."""
     dev = torch.device(device)

@@ -1,0 +1,80 @@
+"""Autotuner of the ADMM schedule: penalty rho, over-relaxation alpha and
+the certification interval check_every.
+
+The right penalty depends on the scale of the book (box width, return
+spread, risk aversion) and the interval trades polish attempts against
+iterations, so both are picked by timing solves of a sample of accounts
+over a small grid.  The winner certifies the most sampled accounts, then
+takes the least time.  Results are cached per book shape (in memory, and in
+a JSON file when a path is given); tune on accounts that are not the ones
+being timed.
+"""
+from __future__ import annotations
+
+import itertools
+import json
+import os
+import time
+from typing import Optional
+
+import torch
+
+from .solver import DeviceProblem, Solver, subset
+
+DEFAULT_GRID = dict(rho=(1.0, 3.0, 10.0, 30.0), alpha=(1.6, 1.8), check_every=(50, 100))
+
+_CACHE: dict = {}
+
+
+def shape_key(P: DeviceProblem, precision: int) -> str:
+    """Book features the schedule depends on (not the account data)."""
+    has_tax = P.tax_ptr is not None and int(P.tax_ptr[-1].item()) > 0
+    has_cap = bool(torch.isfinite(P.tau).any().item())
+    ub = float(P.ub.max().item())
+    gam = float(P.gamma.max().item())
+    return (f"n{P.n}_k{P.k}_g{P.G}_tax{int(has_tax)}_cap{int(has_cap)}"
+            f"_elig{int(P.eligible is not None)}_ub{ub:.3g}_gam{gam:.3g}_p{precision}")
+
+
+def autotune(P: DeviceProblem, solver: Optional[Solver] = None, sample: int = 64,
+             grid: Optional[dict] = None, precision: int = 1,
+             cache_path: Optional[str] = None, verbose: bool = False) -> dict:
+    """Settings dict {rho, alpha, check_every, precision} for books shaped
+    like P, from timed solves of its first ``sample`` accounts."""
+    key = shape_key(P, precision)
+    if key in _CACHE:
+        return dict(_CACHE[key])
+    if cache_path and os.path.exists(cache_path):
+        with open(cache_path) as fh:
+            disk = json.load(fh)
+        if key in disk:
+            _CACHE[key] = disk[key]
+            return dict(disk[key])
+    grid = grid or DEFAULT_GRID
+    s = solver or Solver(P.mu.device.index or 0)
+    Q = subset(P, range(min(sample, P.m)))
+    s.solve(Q, precision=precision)                       # warm-up: workspace, code
+    best = None
+    for rho, alpha, ce in itertools.product(grid["rho"], grid["alpha"], grid["check_every"]):
+        cfg = dict(rho=float(rho), alpha=float(alpha), check_every=int(ce), precision=precision)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = s.solve(Q, **cfg)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        ok = int((out["status"] == 0).sum().item())
+        if verbose:
+            print(f"autotune {cfg}: {ok}/{Q.m} certified, {dt * 1e3:.1f} ms", flush=True)
+        score = (-ok, dt)
+        if best is None or score < best[0]:
+            best = (score, cfg)
+    _CACHE[key] = best[1]
+    if cache_path:
+        disk = {}
+        if os.path.exists(cache_path):
+            with open(cache_path) as fh:
+                disk = json.load(fh)
+        disk[key] = best[1]
+        with open(cache_path, "w") as fh:
+            json.dump(disk, fh, indent=1, sort_keys=True)
+    return dict(best[1])

@@ -1,0 +1,81 @@
+"""GPU parity at the full sizes of every workload shape, in the launch
+configuration the library uses for them: every account certified, every
+account's output re-checked by the float64 CPU checker (a property that
+holds at any size), and sampled accounts compared with the oracle one by
+one where the oracle finishes in seconds."""
+import numpy as np
+import pytest
+
+from workloads import make_config
+from oracle.problem import account
+from oracle.kkt import residuals
+from _gpu_helpers import run_gpu, check_account, TOL_PRIM, TOL_DUAL, TOL_COMP
+
+pytestmark = pytest.mark.gpu
+
+
+def _all_certified_by_cpu_checker(uni, book, host):
+    worst = 0.0
+    for a in range(book.m):
+        P = account(uni, book, a)
+        lam_band = host["lam_band"][a] if P.n_groups else None
+        r = residuals(P, host["w"][a], host["nu"][a], lam_band, host["lam_cap"][a])
+        assert r["r_prim"] <= TOL_PRIM and r["r_dual"] <= TOL_DUAL and \
+            r["r_comp"] <= TOL_COMP, (a, r)
+        worst = max(worst, r["r_prim"], r["r_dual"], r["r_comp"])
+    return worst
+
+
+@pytest.mark.parametrize("name,sample,settings", [
+    ("c2", (0, 31, 63), dict(rho=1.0)),          # 64 x 2,000, k=40, 10 bands
+    ("c4", (0, 77, 127), dict(rho=1.0)),         # 128 x 5,000, k=60, gamma=1000
+])
+def test_full_size_books(name, sample, settings):
+    uni, book = make_config(name, 0)
+    print(f"case {name} full size", flush=True)
+    host, st = run_gpu(uni, book, **settings)
+    print("stats", st, flush=True)
+    assert int(np.sum(host["status"] == 0)) == book.m
+    _all_certified_by_cpu_checker(uni, book, host)
+    for a in sample:
+        check_account(uni, book, a, host)
+
+
+def test_large_universe_c5():
+    """8 accounts over N = 384,800 names, k = 100, 50 one-hot groups with
+    bands, 2,000 held names with 4-lot tax: the factor block (k + G + 1 =
+    151 columns) takes the float32 contraction path.  The oracle needs
+    minutes per account here, so the check is the CPU checker on every
+    account's output."""
+    uni, book = make_config("c5", 0)
+    print("case c5 full size", flush=True)
+    host, st = run_gpu(uni, book, rho=10.0)
+    print("stats", st, flush=True)
+    assert int(np.sum(host["status"] == 0)) == book.m
+    _all_certified_by_cpu_checker(uni, book, host)
+
+
+def test_autotune_picks_a_certifying_schedule():
+    import torch
+    from paper_2606_23367_amd.solver import Solver, to_device
+    from paper_2606_23367_amd.tune import autotune
+    uni, book = make_config("c3", 5, N=2000, M=40, k=16)
+    P = to_device(uni, book)
+    s = Solver(0)
+    cfg = autotune(P, solver=s, sample=16, grid=dict(rho=(3.0, 10.0), alpha=(1.8,),
+                                                    check_every=(50,)))
+    assert cfg["rho"] in (3.0, 10.0) and cfg["check_every"] == 50
+    out = s.solve(P, **cfg)
+    torch.cuda.synchronize()
+    assert int((out["status"] == 0).sum().item()) == book.m
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_precisions_agree(precision):
+    """float32 and bf16-split contractions both certify every account and
+    match the oracle (the float64 polish decides the final answer)."""
+    uni, book = make_config("c3", 2, N=3000, M=24, k=40)
+    host, st = run_gpu(uni, book, rho=8.0, alpha=1.8, precision=precision)
+    assert int(np.sum(host["status"] == 0)) == book.m
+    for a in (0, 11, 23):
+        check_account(uni, book, a, host)

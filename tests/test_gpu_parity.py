@@ -16,7 +16,7 @@ SMALL = [
     ("c3", dict(N=1300, M=9, k=16), dict(rho=5.0)),          # masks, tax, cap
     ("c4", dict(N=900, M=5, k=12), dict(rho=1.0)),           # gamma = 1000
     ("c4", dict(N=900, M=5, k=12, gamma=1.0), dict(rho=1.0)),
-    ("c5", dict(N=6000, M=2, k=20, held=(300, 300)), dict(rho=1.0)),
+    ("c5", dict(N=6000, M=2, k=20, held=(300, 300)), dict(rho=10.0)),
 ]
 
 

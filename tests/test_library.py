@@ -75,3 +75,23 @@ def test_eligibility_packing():
     for a in range(3):
         for i in range(70):
             assert bool((int(w[a, i // 32]) >> (i % 32)) & 1) == e[a, i]
+
+
+def test_device_subset_matches_host_subset():
+    """solver.subset on a (CPU-resident) device book equals laying out the
+    host subset directly: same rows, re-based tax lots."""
+    import torch
+    from workloads import make_config, subset_accounts
+    from paper_2606_23367_amd.solver import to_device, subset
+    uni, book = make_config("c3", 1, N=300, M=6, k=4)
+    P = to_device(uni, book, "cpu")
+    idx = [4, 1, 5]
+    A = subset(P, idx)
+    B = to_device(uni, subset_accounts(book, idx), "cpu")
+    for name in ("mu", "w0", "lb", "ub", "gamma", "kappa", "tau", "eligible",
+                 "tax_ptr", "tax_asset", "tax_brk", "tax_slope"):
+        a, b = getattr(A, name), getattr(B, name)
+        assert (a is None) == (b is None), name
+        if a is not None:
+            assert torch.equal(a, b), name
+    assert A.m == 3
