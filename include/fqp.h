@@ -84,7 +84,7 @@ typedef struct fqp_universe {
   const int32_t *group;  /* [n]   labels in [0, n_groups); NULL if none    */
 } fqp_universe;
 
-/* Per-account data of Eq. 1 for m accounts. */
+/* Per-account data of Eq. 1 for m accounts (m * n < 2^31 per call). */
 typedef struct fqp_book {
   int32_t m;                 /* accounts, >= 1                              */
   const float *mu;           /* [m][n] expected returns                    */

@@ -266,10 +266,14 @@ __global__ __launch_bounds__(256, 2) void iter_kernel(IterArgs A) {
   float4* Acc = reinterpret_cast<float4*>(Xs + kXs);   // [32][2]
   int* Aid = (int*)(Acc + 2 * kTM);     // [32]
   int* Hp = Aid + kTM;                  // [32] first held record of each account
+  int* Ao = Hp + kTM;                   // [32] a * n (element offset of the account)
+  int* Wo = Ao + kTM;                   // [32] a * W (bitmask word offset)
 
   const int m_act = *A.m_act;
-  const int slot0 = blockIdx.y * kTM;
-  if (slot0 >= m_act) return;
+  const TileMap tm = tile_map(m_act, A.n, gridDim.x * gridDim.y,
+                              blockIdx.y * gridDim.x + blockIdx.x);
+  if (!tm.active) return;
+  const int slot0 = tm.tile * kTM;
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
   const int l32 = lane & 31, hi = lane >> 5;
   const int n = A.n;
@@ -279,6 +283,8 @@ __global__ __launch_bounds__(256, 2) void iter_kernel(IterArgs A) {
     const int a = (s < m_act) ? A.act[s] : -1;
     Aid[tid] = a;
     Hp[tid] = (a >= 0) ? A.hold_ptr[a] : 0;
+    Ao[tid] = (a >= 0) ? a * n : 0;        // m n < 2^31 (checked by the runtime)
+    Wo[tid] = (a >= 0) ? a * A.W : 0;
     float4 q0 = make_float4(1.f, 1.f, 0.f, 0.f), q1 = make_float4(0.f, 0.f, 0.f, 0.f);
     if (a >= 0) {
       const float* p = A.par + (size_t)a * kNPar;
@@ -308,9 +314,9 @@ __global__ __launch_bounds__(256, 2) void iter_kernel(IterArgs A) {
   for (int r = 0; r < 16; ++r) st_rp[r] = 0.f;
 
   float* Rw = Rt + w * 32 * 33;
-  const int row_begin = blockIdx.x * A.rows_per_wg;
+  const int row_begin = tm.row_begin;
 
-  for (int ch = 0; ch < A.chunks_per_wg; ++ch) {
+  for (int ch = 0; ch < tm.chunks; ++ch) {
     const int r0 = row_begin + ch * kRowsPerChunk;
     if (r0 >= n) break;
     __syncthreads();
@@ -351,8 +357,8 @@ __global__ __launch_bounds__(256, 2) void iter_kernel(IterArgs A) {
       const int a = Aid[m];
       mu_r[r] = 0.f; v_r[r] = 0.f; ew_r[r] = 0u; hw_r[r] = 0u; hp_r[r] = 0;
       if (a >= 0 && row_ok) {
-        const size_t off = (size_t)a * n + row;
-        const size_t wi = (size_t)a * A.W + wd;
+        const unsigned off = (unsigned)(Ao[m] + row);
+        const unsigned wi = (unsigned)(Wo[m] + wd);
         mu_r[r] = A.mu[off];
         v_r[r] = A.v[off];
         ew_r[r] = A.elig ? A.elig[wi] : 0xffffffffu;
@@ -369,7 +375,7 @@ __global__ __launch_bounds__(256, 2) void iter_kernel(IterArgs A) {
         const float4 q0 = Acc[2 * m], q1 = Acc[2 * m + 1];
         const float rho = q0.x, irho = q0.y;
         const float iDelta = __builtin_amdgcn_rcpf(q0.z * d_i + rho);
-        const size_t off = (size_t)a * n + row;
+        const unsigned off = (unsigned)(Ao[m] + row);
         const float mu = mu_r[r];
         const float vv = v_r[r];
         const RowInfo ri = row_info_w(A, row, q1.x, q1.y, ew_r[r], hw_r[r], hp_r[r], Hp[m]);
@@ -424,7 +430,7 @@ __global__ __launch_bounds__(256, 2) void iter_kernel(IterArgs A) {
     if (tid < kTM) {
       const int a = Aid[tid];
       if (a >= 0)
-        A.stat[((size_t)blockIdx.x * M + a) * kNStat + ST_RPRIM] =
+        A.stat[((size_t)tm.rt * M + a) * kNStat + ST_RPRIM] =
             fmaxf(fmaxf(sred[tid], sred[kTM + tid]), fmaxf(sred[2 * kTM + tid], sred[3 * kTM + tid]));
     }
     return;
@@ -446,7 +452,7 @@ __global__ __launch_bounds__(256, 2) void iter_kernel(IterArgs A) {
     if (a < 0) continue;
     float s = red[(0 * kTM + m) * kp + c] + red[(1 * kTM + m) * kp + c] +
               red[(2 * kTM + m) * kp + c] + red[(3 * kTM + m) * kp + c];
-    A.part[((size_t)blockIdx.x * M + a) * kp + c] = s;
+    A.part[((size_t)tm.rt * M + a) * kp + c] = s;
   }
 }
 
@@ -491,10 +497,14 @@ __global__ __launch_bounds__(256, 2) void iter_kernel_bf(IterArgs A) {
   float4* Acc = reinterpret_cast<float4*>(Xs + kX);    // [32][2] as in iter_kernel
   int* Aid = (int*)(Acc + 2 * kTM);     // [32]
   int* Hp = Aid + kTM;                  // [32]
+  int* Ao = Hp + kTM;                   // [32] a * n
+  int* Wo = Ao + kTM;                   // [32] a * W
 
   const int m_act = *A.m_act;
-  const int slot0 = blockIdx.y * kTM;
-  if (slot0 >= m_act) return;
+  const TileMap tm = tile_map(m_act, A.n, gridDim.x * gridDim.y,
+                              blockIdx.y * gridDim.x + blockIdx.x);
+  if (!tm.active) return;
+  const int slot0 = tm.tile * kTM;
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
   const int l32 = lane & 31, hi = lane >> 5;
   const int n = A.n;
@@ -508,6 +518,8 @@ __global__ __launch_bounds__(256, 2) void iter_kernel_bf(IterArgs A) {
     const int a = (s < m_act) ? A.act[s] : -1;
     Aid[tid] = a;
     Hp[tid] = (a >= 0) ? A.hold_ptr[a] : 0;
+    Ao[tid] = (a >= 0) ? a * n : 0;        // m n < 2^31 (checked by the runtime)
+    Wo[tid] = (a >= 0) ? a * A.W : 0;
     float4 q0 = make_float4(1.f, 1.f, 0.f, 0.f), q1 = make_float4(0.f, 0.f, 0.f, 0.f);
     if (a >= 0) {
       const float* p = A.par + (size_t)a * kNPar;
@@ -548,9 +560,9 @@ __global__ __launch_bounds__(256, 2) void iter_kernel_bf(IterArgs A) {
 
   __bf16* RwH = reinterpret_cast<__bf16*>(Xs) + w * 2 * 32 * kRwS;
   __bf16* RwL = RwH + 32 * kRwS;
-  const int row_begin = blockIdx.x * A.rows_per_wg;
+  const int row_begin = tm.row_begin;
 
-  for (int ch = 0; ch < A.chunks_per_wg; ++ch) {
+  for (int ch = 0; ch < tm.chunks; ++ch) {
     const int r0 = row_begin + ch * kRowsPerChunk;
     if (r0 >= n) break;
     const int row_base = r0 + 32 * w;     // < npad: rows are padded to whole chunks
@@ -588,8 +600,8 @@ __global__ __launch_bounds__(256, 2) void iter_kernel_bf(IterArgs A) {
       const int a = Aid[m];
       mu_r[r] = 0.f; v_r[r] = 0.f; ew_r[r] = 0u; hw_r[r] = 0u; hp_r[r] = 0;
       if (a >= 0 && row_ok) {
-        const size_t off = (size_t)a * n + row;
-        const size_t wi = (size_t)a * A.W + wd;
+        const unsigned off = (unsigned)(Ao[m] + row);
+        const unsigned wi = (unsigned)(Wo[m] + wd);
         mu_r[r] = A.mu[off];
         v_r[r] = A.v[off];
         ew_r[r] = A.elig ? A.elig[wi] : 0xffffffffu;
@@ -619,7 +631,7 @@ __global__ __launch_bounds__(256, 2) void iter_kernel_bf(IterArgs A) {
         const float4 q0 = Acc[2 * m], q1 = Acc[2 * m + 1];
         const float rho = q0.x, irho = q0.y;
         const float iDelta = __builtin_amdgcn_rcpf(q0.z * d_i + rho);
-        const size_t off = (size_t)a * n + row;
+        const unsigned off = (unsigned)(Ao[m] + row);
         const RowInfo ri = row_info_w(A, row, q1.x, q1.y, ew_r[r], hw_r[r], hp_r[r], Hp[m]);
         const float vv = v_r[r];
         const float z = prox_row(ri, vv, q0.w, irho, nullptr);
@@ -680,7 +692,7 @@ __global__ __launch_bounds__(256, 2) void iter_kernel_bf(IterArgs A) {
     if (tid < kTM) {
       const int a = Aid[tid];
       if (a >= 0)
-        A.stat[((size_t)blockIdx.x * M + a) * kNStat + ST_RPRIM] =
+        A.stat[((size_t)tm.rt * M + a) * kNStat + ST_RPRIM] =
             fmaxf(fmaxf(sred[tid], sred[kTM + tid]), fmaxf(sred[2 * kTM + tid], sred[3 * kTM + tid]));
     }
     return;
@@ -702,7 +714,7 @@ __global__ __launch_bounds__(256, 2) void iter_kernel_bf(IterArgs A) {
     if (a < 0) continue;
     float s = red[(0 * kTM + m) * kp + c] + red[(1 * kTM + m) * kp + c] +
               red[(2 * kTM + m) * kp + c] + red[(3 * kTM + m) * kp + c];
-    A.part[((size_t)blockIdx.x * M + a) * kp + c] = s;
+    A.part[((size_t)tm.rt * M + a) * kp + c] = s;
   }
 }
 
@@ -844,15 +856,17 @@ __global__ __launch_bounds__(256) void materialize_z_kernel(IterArgs A, float* z
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void ksolve_kernel(KArgs A) {
   __shared__ double t[kMaxKp], rhs[kMaxKp], red[256];
+  __shared__ float tsp[256];                // split partial sums
   __shared__ float pprime[kMaxKp];
   __shared__ double s_nu;
-  __shared__ float sst[kNStat];
+  __shared__ float sst[4];             // per-wave max of the primal residual
   const int slot = blockIdx.x;
   if (slot >= *A.m_act) return;
   const int a = A.act[slot];
   const int tid = threadIdx.x;
   const int kp = A.kp, k = A.k, G = A.G, kg = k + G;
   const size_t M = A.m_total;
+  const int n_rt = tile_map(*A.m_act, A.n, A.nblk, 0).n_rt;
   float* par = A.par + (size_t)a * kNPar;
   const int cls = (int)par[P_CLASS];
   const float* Kinv = A.Kinv + (size_t)cls * kp * kp;
@@ -861,18 +875,40 @@ __global__ __launch_bounds__(256) void ksolve_kernel(KArgs A) {
   const float sig1 = A.sig1[cls];
   const float rhob = par[P_RHOB];
 
-  for (int j = tid; j < kp; j += 256) {
-    // independent partial loads in flight together
+  // nsp threads per factor column split the row tiles (and below the
+  // K^-1 rows), so that more independent loads are in flight
+  const int nsp = kp <= 256 ? 256 / kp : 1;
+  if (tid < nsp * kp) {
+    const int j = tid % kp, q = tid / kp;
+    // batches of 16 loads issued before any is added
     float s = 0.f;
-#pragma unroll 8
-    for (int rt = 0; rt < A.n_rt; ++rt) s += A.part[((size_t)rt * M + a) * kp + j];
+    for (int r0 = q; r0 < n_rt; r0 += 16 * nsp) {
+      float buf[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const int rt = r0 + u * nsp;
+        buf[u] = rt < n_rt ? A.part[((size_t)rt * M + a) * kp + j] : 0.f;
+      }
+#pragma unroll
+      for (int u = 0; u < 16; ++u) s += buf[u];
+    }
+    tsp[tid] = s;
+  }
+  __syncthreads();
+  for (int j = tid; j < kp; j += 256) {
+    float s = 0.f;
+    for (int q = 0; q < nsp; ++q) s += tsp[q * kp + j];
     t[j] = s;
   }
-  if (tid < kNStat) {
+  {
+    // max over the row tiles of the primal residual estimate, one row tile
+    // per thread
     float v = 0.f;
-    for (int rt = 0; rt < A.n_rt; ++rt)
-      v = fmaxf(v, A.stat[((size_t)rt * M + a) * kNStat + tid]);
-    sst[tid] = v;
+    for (int rt = tid; rt < n_rt; rt += 256)
+      v = fmaxf(v, A.stat[((size_t)rt * M + a) * kNStat + ST_RPRIM]);
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+    if ((tid & 63) == 0) sst[tid >> 6] = v;
   }
   __syncthreads();
   // band terms: t += (K - F~^-1)[:, G] rho_b (zb - vb);  s0 += c_G . same
@@ -905,12 +941,33 @@ __global__ __launch_bounds__(256) void ksolve_kernel(KArgs A) {
   const double nu = s_nu;
   for (int j = tid; j < kg; j += 256) rhs[j] = t[j] + nu * (double)cv[j];
   __syncthreads();
+  __syncthreads();
+  if (tid < nsp * kp) {
+    const int j = tid % kp, q = tid / kp;
+    double s = 0.0;
+    if (j < kg) {
+      // K^-1 is symmetric: read column j (consecutive j -> consecutive
+      // words); batches of 16 loads issued before any is used
+      for (int l0 = q; l0 < kg; l0 += 16 * nsp) {
+        float buf[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+          const int l = l0 + u * nsp;
+          buf[u] = l < kg ? Kinv[l * kp + j] : 0.f;
+        }
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+          const int l = l0 + u * nsp;
+          if (l < kg) s += (double)buf[u] * rhs[l];
+        }
+      }
+    }
+    red[tid] = s;
+  }
+  __syncthreads();
   for (int j = tid; j < kp; j += 256) {
     double s = 0.0;
-    if (j < kg)
-      // K^-1 is symmetric: read column j (consecutive j -> consecutive words)
-#pragma unroll 8
-      for (int l = 0; l < kg; ++l) s += (double)Kinv[l * kp + j] * rhs[l];
+    for (int q = 0; q < nsp; ++q) s += red[q * kp + j];
     pprime[j] = (float)s;
   }
   __syncthreads();
@@ -943,7 +1000,7 @@ __global__ __launch_bounds__(256) void ksolve_kernel(KArgs A) {
   for (int o = 32; o >= 1; o >>= 1) band_res = fmaxf(band_res, __shfl_xor(band_res, o, 64));
   if (tid == 0) {
     par[P_NU] = (float)nu;
-    A.res[(size_t)a * 4 + 0] = fmaxf(sst[ST_RPRIM], band_res);
+    A.res[(size_t)a * 4 + 0] = fmaxf(fmaxf(fmaxf(sst[0], sst[1]), fmaxf(sst[2], sst[3])), band_res);
     A.iters[a] += 1;
   }
 }
@@ -958,12 +1015,12 @@ template <int NCH, int MODE>
 static size_t iter_smem() {
   constexpr int kp = NCH * 32, BS = kp + 1;
   constexpr int kXs = (MODE == MODE_PROJECT) ? kTM * BS + kWaves * kTM : kWaves * 32 * 33;
-  return sizeof(float) * ((size_t)kRowsPerChunk * BS + kXs + 8 * kTM) + 2 * sizeof(int) * kTM;
+  return sizeof(float) * ((size_t)kRowsPerChunk * BS + kXs + 8 * kTM) + 4 * sizeof(int) * kTM;
 }
 
 template <int NCH, int MODE>
 static size_t iter_smem_bf() {
-  return sizeof(float) * ((size_t)bf_lds_floats<NCH, MODE>() + 8 * kTM) + 2 * sizeof(int) * kTM;
+  return sizeof(float) * ((size_t)bf_lds_floats<NCH, MODE>() + 8 * kTM) + 4 * sizeof(int) * kTM;
 }
 
 template <int NCH>

@@ -3,11 +3,12 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "fqp_common.h"
+
 namespace fqp {
 
 struct IterArgs {
   int n, W;                  // assets, bitmask words per account
-  int rows_per_wg, chunks_per_wg;
   int m_total;               // accounts in the book (partials are indexed by id)
   const int* m_act;          // device: number of active accounts
   const int* act;            // device: active account ids [m_act]
@@ -32,12 +33,12 @@ struct IterArgs {
   const float* pp;           // [m][kp]
   const float* par;          // [m][kNPar]
   float* par_rw;             // same array, written by the cap kernel
-  float* part;               // [n_rt][m][kp]
-  float* stat;               // [n_rt][m][kNStat]
+  float* part;               // [row tiles][m][kp] (at most one per 128-row chunk)
+  float* stat;               // [row tiles][m][kNStat]
 };
 
 struct KArgs {
-  int kp, k, G, n_rt, m_total;
+  int kp, k, G, n, nblk, m_total;    // nblk: workgroups of the iteration passes
   const int* m_act;
   const int* act;
   const float* part;
@@ -56,6 +57,31 @@ struct KArgs {
   float* res;                // [m][4]  ADMM residual estimates
   int* iters;                // [m]
 };
+
+// Work split of the two iteration passes for the current number of active
+// accounts: the grid's workgroups are spread over the active 32-account
+// tiles, and each tile's rows are cut into as many row tiles as it gets
+// workgroups (whole 128-row chunks), so a short active list still fills the
+// chip.  The k-space solve uses the same split to find the partials.
+struct TileMap {
+  int tile, rt, n_rt, chunks, row_begin;
+  bool active;
+};
+__device__ __forceinline__ TileMap tile_map(int m_act, int n, int nblk, int lin) {
+  const int tiles = (m_act + kTM - 1) / kTM;
+  const int total_chunks = (n + kRowsPerChunk - 1) / kRowsPerChunk;
+  int r = tiles > 0 ? nblk / tiles : 1;
+  r = r < 1 ? 1 : (r > total_chunks ? total_chunks : r);
+  const int cpt = (total_chunks + r - 1) / r;        // chunks per row tile
+  TileMap t;
+  t.n_rt = (total_chunks + cpt - 1) / cpt;
+  t.chunks = cpt;
+  t.tile = lin / t.n_rt;
+  t.rt = lin % t.n_rt;
+  t.row_begin = t.rt * cpt * kRowsPerChunk;
+  t.active = t.tile < tiles;
+  return t;
+}
 
 hipError_t configure_iter_kernels();
 hipError_t launch_iter(const IterArgs& A, int kp, int mode, int prec, dim3 grid,

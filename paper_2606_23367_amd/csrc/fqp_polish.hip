@@ -303,43 +303,21 @@ __global__ __launch_bounds__(kPT) void polish_solve_kernel(PolishArgs A) {
         mult[2 + g] = (double)par[P_RHOB] * (double)A.vb[(size_t)a * G + g];
       }
     }
-    unsigned sig = 0u;                        // signature of the pattern
-    for (int i = tid; i < n; i += kPT) {
-      RowData r = row_data(A, a, i);
-      Geom g;
-      make_geom(g, lbf, ubf, kap, phi, r);
-      const float z = A.z[(size_t)a * n + i];
-      int c = -1;
-      for (int j = 0; j < g.np; ++j)
-        if (z == g.ptf[j]) { c = 2 * j; break; }
-      if (c < 0) {
-        int q = 0;
-        while (q + 2 < g.np && (double)z > g.pt[q + 1]) ++q;
-        c = (g.np == 1) ? 0 : 2 * q + 1;
-        if (g.np > 1 && (double)z <= g.pt[0]) c = 0;
-        if (g.np > 1 && (double)z >= g.pt[g.np - 1]) c = 2 * (g.np - 1);
-      }
-      code[i] = (int8_t)c;
-      sig += (unsigned)(c + 1) * ((unsigned)i * 2654435761u + 1u);
-    }
-    sig = bsum<unsigned>(sig, s_sig);
-    if (tid == 0) {
-      sig += (unsigned)ps[PS_CAP] * 97u + (unsigned)ps[PS_BACT0] * 31u + (unsigned)ps[PS_BACT1] * 7u +
-             (unsigned)ps[PS_BUP0] * 5u + (unsigned)ps[PS_BUP1] * 3u;
-      s_same = (unsigned)ps[PS_SIG] == sig;
-      ps[PS_SIG] = (int)sig;
-    }
     __syncthreads();
+  } else if (ps[PS_DONE] || ps[PS_STALL]) {
+    return;
   }
-  if (ps[PS_DONE] || ps[PS_STALL]) return;
   const int cap_on = ps[PS_CAP];
 
-  // ---- pass 1: fixed values, free list, nonzero-fixed list --------------
-  // free rows are listed from the front of flist, nonzero fixed rows from
-  // the back (wave ballots + a 4-entry prefix per chunk).
+  // ---- one pass over the rows: (first round) the pattern of the iterate,
+  // fixed values, the free list from the front of flist and the nonzero
+  // fixed list from its back (wave ballots + a per-wave prefix), the
+  // budget and turnover sums of the fixed rows
   __shared__ int s_wc[2][kPW][2];
   if (tid == 0) { s_cnt[0] = 0; s_cnt[1] = 0; }
   __syncthreads();
+  unsigned sig = 0u;                          // signature of the pattern
+  double sx = 0.0, sturn = 0.0;
   {
     const int lane = tid & 63, wv = tid >> 6;
     int it = 0;
@@ -347,17 +325,43 @@ __global__ __launch_bounds__(kPT) void polish_solve_kernel(PolishArgs A) {
       const int i = base + tid;
       int isfree = 0, isnz = 0;
       if (i < n) {
-        const int c = code[i];
+        int c;
+        Geom g;
+        RowData r;
+        bool have = false;
+        if (A.first_round) {
+          r = row_data(A, a, i);
+          make_geom(g, lbf, ubf, kap, phi, r);
+          have = true;
+          const float z = A.z[(size_t)a * n + i];
+          c = -1;
+          for (int j = 0; j < g.np; ++j)
+            if (z == g.ptf[j]) { c = 2 * j; break; }
+          if (c < 0) {
+            int q = 0;
+            while (q + 2 < g.np && (double)z > g.pt[q + 1]) ++q;
+            c = (g.np == 1) ? 0 : 2 * q + 1;
+            if (g.np > 1 && (double)z <= g.pt[0]) c = 0;
+            if (g.np > 1 && (double)z >= g.pt[g.np - 1]) c = 2 * (g.np - 1);
+          }
+          code[i] = (int8_t)c;
+          sig += (unsigned)(c + 1) * ((unsigned)i * 2654435761u + 1u);
+        } else {
+          c = code[i];
+        }
         if (c & 1) {
           isfree = 1;
           w[i] = 0.0;
         } else {
-          RowData r = row_data(A, a, i);
-          Geom g;
-          make_geom(g, lbf, ubf, kap, phi, r);
+          if (!have) {
+            r = row_data(A, a, i);
+            make_geom(g, lbf, ubf, kap, phi, r);
+          }
           const double v = g.pt[c >> 1];
           w[i] = v;
           isnz = (v != 0.0);
+          sx += v;
+          sturn += fabs(v - (double)r.w0);
         }
       }
       const unsigned long long mf = __ballot(isfree), mn = __ballot(isnz);
@@ -379,6 +383,17 @@ __global__ __launch_bounds__(kPT) void polish_solve_kernel(PolishArgs A) {
     }
     __syncthreads();
   }
+  if (A.first_round) {
+    sig = bsum<unsigned>(sig, s_sig);
+    if (tid == 0) {
+      sig += (unsigned)ps[PS_CAP] * 97u + (unsigned)ps[PS_BACT0] * 31u + (unsigned)ps[PS_BACT1] * 7u +
+             (unsigned)ps[PS_BUP0] * 5u + (unsigned)ps[PS_BUP1] * 3u;
+      s_same = (unsigned)ps[PS_SIG] == sig;
+      ps[PS_SIG] = (int)sig;
+    }
+  }
+  sx = bsum<double>(sx, shd);
+  sturn = bsum<double>(sturn, shd);
   const int nF = s_cnt[0], nX = s_cnt[1];
   // a pattern with many free coordinates belongs to an iterate that is far
   // from the optimum's vertex structure: skip the (costly) solve for now
@@ -409,16 +424,6 @@ __global__ __launch_bounds__(kPT) void polish_solve_kernel(PolishArgs A) {
   const int nc = 1 + nb + (cap_on ? 1 : 0);
   const int ncol = nc + 1;                      // + rhs column
   {
-    double sx = 0.0, sturn = 0.0;
-    for (int t = tid; t < nX; t += kPT) sx += w[flist[n - 1 - t]];
-    // turnover of fixed rows: every row not free (including zeros)
-    for (int i = tid; i < n; i += kPT) {
-      if (code[i] & 1) continue;
-      RowData r = row_data(A, a, i);
-      sturn += fabs(w[i] - (double)r.w0);
-    }
-    sx = bsum<double>(sx, shd);
-    sturn = bsum<double>(sturn, shd);
     if (tid == 0) {
       wk.h[0] = 1.0 - sx;
       int col = 1;

@@ -305,6 +305,10 @@ extern "C" fqp_error fqp_solve_batch(fqp_handle* h, const fqp_universe* U, const
   }
   const int kg = k + (G > 0 ? G : 0);
   const int kp = ((kg + 1 + 31) / 32) * 32;
+  if ((size_t)m * (size_t)n >= ((size_t)1 << 31)) {
+    h->err = "book of 2^31 or more (account, asset) entries: split it into several calls";
+    return FQP_ERR_UNSUPPORTED;
+  }
   if (k > kMaxK || G > kMaxG || kp > kMaxKp) {
     h->err = "factor count / group count beyond the library limits";
     return FQP_ERR_UNSUPPORTED;
@@ -419,9 +423,10 @@ extern "C" fqp_error fqp_solve_batch(fqp_handle* h, const fqp_universe* U, const
   int chunks = (n + kRowsPerChunk * target_rt - 1) / (kRowsPerChunk * target_rt);
   chunks = std::max(1, std::min(chunks, 64));
   const int rows_per_wg = chunks * kRowsPerChunk;
-  const int n_rt = (n + rows_per_wg - 1) / rows_per_wg;
-  WS(part, float, "part", (size_t)n_rt * m * kp);
-  WS(stat, float, "stat", (size_t)n_rt * m * kNStat);
+  const int n_rt = (n + rows_per_wg - 1) / rows_per_wg;    // at the full batch
+  const int max_rt = (n + kRowsPerChunk - 1) / kRowsPerChunk;   // short active lists
+  WS(part, float, "part", (size_t)max_rt * m * kp);
+  WS(stat, float, "stat", (size_t)max_rt * m * kNStat);
   // bf16 hi/lo copies of B~ for the split-precision contractions
   const int npad = ((n + kRowsPerChunk - 1) / kRowsPerChunk) * kRowsPerChunk;
   const bool split = S.precision == FQP_PREC_BF16X3 && kp <= kMaxKpBf;
@@ -467,7 +472,7 @@ extern "C" fqp_error fqp_solve_batch(fqp_handle* h, const fqp_universe* U, const
   HIP_CHECK(hipGetLastError());
 
   IterArgs ia{};
-  ia.n = n; ia.W = W; ia.rows_per_wg = rows_per_wg; ia.chunks_per_wg = chunks;
+  ia.n = n; ia.W = W;
   ia.m_total = m; ia.m_act = m_act; ia.act = act; ia.Bt = Bt; ia.d = U->d; ia.mu = P->mu;
   ia.v = v; ia.elig = P->eligible; ia.hold = hold; ia.hold_pre = hold_pre;
   ia.hold_ptr = hold_ptr; ia.hold_w0 = hold_w0; ia.hold_tax = hold_tax;
@@ -476,7 +481,8 @@ extern "C" fqp_error fqp_solve_batch(fqp_handle* h, const fqp_universe* U, const
   ia.part = part; ia.stat = stat;
   ia.npad = npad; ia.bt_hi = bt_hi; ia.bt_lo = bt_lo; ia.btt_hi = btt_hi; ia.btt_lo = btt_lo;
   KArgs ka{};
-  ka.kp = kp; ka.k = k; ka.G = G; ka.n_rt = n_rt; ka.m_total = m; ka.m_act = m_act; ka.act = act;
+  ka.kp = kp; ka.k = k; ka.G = G; ka.n = n; ka.nblk = n_rt * acc_tiles; ka.m_total = m;
+  ka.m_act = m_act; ka.act = act;
   ka.part = part; ka.stat = stat; ka.par = par; ka.pp = pp; ka.Kinv = Kinv; ka.cvec = cvec;
   ka.qvec = qvec; ka.sig1 = sig1; ka.mbg = mbg; ka.zb = zb; ka.vb = vb;
   ka.blo = G ? P->band_lo : nullptr; ka.bhi = G ? P->band_hi : nullptr;
@@ -504,7 +510,7 @@ extern "C" fqp_error fqp_solve_batch(fqp_handle* h, const fqp_universe* U, const
     ~EvGuard() { for (auto& ev : *v) (void)hipEventDestroy(ev); }
   } evguard{&evs};
   const dim3 igrid(n_rt, acc_tiles);
-  HIP_CHECK(hipMemsetAsync(stat, 0, sizeof(float) * (size_t)n_rt * m * kNStat, st));
+  HIP_CHECK(hipMemsetAsync(stat, 0, sizeof(float) * (size_t)max_rt * m * kNStat, st));
   // the cap kernel runs only when some account has a finite cap; the
   // held-asset records are sized by the packed count
   bool any_cap = false;
