@@ -243,6 +243,28 @@ __device__ __forceinline__ RowInfo row_info_w(const Args& A, int row, float lbp,
   return ri;
 }
 
+// the same with the holding prefix word loaded only for a held row
+template <typename Args>
+__device__ __forceinline__ RowInfo row_info_l(const Args& A, int row, float lbp, float ubp,
+                                              uint32_t ew, uint32_t hw, unsigned wi, int hptr) {
+  RowInfo ri;
+  const int b = row & 31;
+  const bool el = (ew >> b) & 1u;
+  ri.lb = el ? lbp : 0.f;
+  ri.ub = el ? ubp : 0.f;
+  ri.w0 = 0.f;
+  ri.taxed = false;
+  if ((hw >> b) & 1u) {
+    const int idx = hptr + A.hold_pre[wi] + popc_below(hw, b);
+    const float4 r0 = A.hold_rec[2 * idx], r1 = A.hold_rec[2 * idx + 1];
+    ri.w0 = r0.x;
+    ri.taxed = r0.y > 0.f;
+    ri.t.b1 = r0.y; ri.t.b2 = r0.z; ri.t.b3 = r0.w;
+    ri.t.s0 = r1.x; ri.t.s1 = r1.y; ri.t.s2 = r1.z; ri.t.s3 = r1.w;
+  }
+  return ri;
+}
+
 template <typename Args>
 __device__ __forceinline__ RowInfo row_info(const Args& A, int a, int row, float lbp, float ubp) {
   const size_t wi = (size_t)a * A.W + (row >> 5);
@@ -480,15 +502,16 @@ constexpr int kRwS = 40;   // bf16 stride of one account's transposed R' (16-B a
 template <int NCH, int MODE>
 constexpr int bf_lds_floats() {
   // CONTRACT: per-wave R' transposes (hi, lo) or, after the row loop, the
-  // cross-wave reduction [4][32][kp]; PROJECT: a [4][32] max reduction
+  // cross-wave reduction [4][32][kp]; PROJECT: a [4][32] max reduction and
+  // the split p of the tile (hi, lo) [2][32][kp + 8] bf16
   return (MODE == MODE_CONTRACT)
              ? ((kWaves * kTM * NCH * 32 > kWaves * 2 * 32 * kRwS / 2) ? kWaves * kTM * NCH * 32
                                                                      : kWaves * 2 * 32 * kRwS / 2)
-             : kWaves * kTM;
+             : kWaves * kTM + kTM * (NCH * 32 + 8);
 }
 
 template <int NCH, int MODE>
-__global__ __launch_bounds__(256, 2) void iter_kernel_bf(IterArgs A) {
+__global__ __launch_bounds__(256, 3) void iter_kernel_bf(IterArgs A) {
   constexpr int kp = NCH * 32;
   constexpr int KS = kp / 16;            // K steps of the PROJECT product
   constexpr int kX = bf_lds_floats<NCH, MODE>();
@@ -532,21 +555,22 @@ __global__ __launch_bounds__(256, 2) void iter_kernel_bf(IterArgs A) {
   }
   __syncthreads();
 
-  // PROJECT: the A operand (p of account l32, k = 16 s + 8 hi + t) for every
-  // K step, split once per workgroup
-  bf16x8 pH[MODE == MODE_PROJECT ? KS : 1], pL[MODE == MODE_PROJECT ? KS : 1];
+  // PROJECT: the A operand (p of the tile's accounts), split once per
+  // workgroup into LDS: PsH / PsL [32][kp + 8] bf16 (16-byte aligned rows)
+  constexpr int PS = kp + 8;
+  __bf16* PsH = reinterpret_cast<__bf16*>(Xs + kWaves * kTM);
+  __bf16* PsL = PsH + kTM * PS;
   if (MODE == MODE_PROJECT) {
-    const int a = Aid[l32];
-#pragma unroll
-    for (int s = 0; s < KS; ++s)
-#pragma unroll
-      for (int t = 0; t < 8; ++t) {
-        const float x = (a >= 0) ? A.pp[(size_t)a * kp + 16 * s + 8 * hi + t] : 0.f;
-        __bf16 h, l;
-        split_bf16(x, h, l);
-        pH[s][t] = h;
-        pL[s][t] = l;
-      }
+    for (int e = tid; e < kTM * kp; e += 256) {
+      const int j = e / kp, c = e % kp;
+      const int a = Aid[j];
+      const float x = (a >= 0) ? A.pp[(size_t)a * kp + c] : 0.f;
+      __bf16 h, l;
+      split_bf16(x, h, l);
+      PsH[j * PS + c] = h;
+      PsL[j * PS + c] = l;
+    }
+    __syncthreads();
   }
 
   floatx16 T[NCH];
@@ -570,35 +594,14 @@ __global__ __launch_bounds__(256, 2) void iter_kernel_bf(IterArgs A) {
     const bool row_ok = row < n;
     const float d_i = row_ok ? A.d[row] : 1.f;
 
-    // B~ operand loads first (independent of the element work)
-    bf16x8 bH[MODE == MODE_PROJECT ? KS : 2 * NCH], bL[MODE == MODE_PROJECT ? KS : 2 * NCH];
-    if (MODE == MODE_PROJECT) {
-#pragma unroll
-      for (int s = 0; s < KS; ++s) {
-        const size_t o = (size_t)row * kp + 16 * s + 8 * hi;
-        bH[s] = *reinterpret_cast<const bf16x8*>(bh + o);
-        bL[s] = *reinterpret_cast<const bf16x8*>(bl + o);
-      }
-    } else {
-#pragma unroll
-      for (int c = 0; c < NCH; ++c)
-#pragma unroll
-        for (int s = 0; s < 2; ++s) {
-          const size_t o = (size_t)(32 * c + l32) * A.npad + row_base + 16 * s + 8 * hi;
-          bH[2 * c + s] = *reinterpret_cast<const bf16x8*>(bth + o);
-          bL[2 * c + s] = *reinterpret_cast<const bf16x8*>(btl + o);
-        }
-    }
-
     float mu_r[16], v_r[16];
     uint32_t ew_r[16], hw_r[16];
-    int hp_r[16];
     const int wd = row >> 5;
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
       const int m = 8 * (r >> 2) + 4 * hi + (r & 3);
       const int a = Aid[m];
-      mu_r[r] = 0.f; v_r[r] = 0.f; ew_r[r] = 0u; hw_r[r] = 0u; hp_r[r] = 0;
+      mu_r[r] = 0.f; v_r[r] = 0.f; ew_r[r] = 0u; hw_r[r] = 0u;
       if (a >= 0 && row_ok) {
         const unsigned off = (unsigned)(Ao[m] + row);
         const unsigned wi = (unsigned)(Wo[m] + wd);
@@ -606,7 +609,6 @@ __global__ __launch_bounds__(256, 2) void iter_kernel_bf(IterArgs A) {
         v_r[r] = A.v[off];
         ew_r[r] = A.elig ? A.elig[wi] : 0xffffffffu;
         hw_r[r] = A.hold[wi];
-        hp_r[r] = A.hold_pre[wi];
       }
     }
 
@@ -616,9 +618,14 @@ __global__ __launch_bounds__(256, 2) void iter_kernel_bf(IterArgs A) {
     if (MODE == MODE_PROJECT) {
 #pragma unroll
       for (int s = 0; s < KS; ++s) {
-        X = __builtin_amdgcn_mfma_f32_32x32x16_bf16(pH[s], bH[s], X, 0, 0, 0);
-        X = __builtin_amdgcn_mfma_f32_32x32x16_bf16(pH[s], bL[s], X, 0, 0, 0);
-        X = __builtin_amdgcn_mfma_f32_32x32x16_bf16(pL[s], bH[s], X, 0, 0, 0);
+        const size_t o = (size_t)row * kp + 16 * s + 8 * hi;
+        const bf16x8 bH = *reinterpret_cast<const bf16x8*>(bh + o);
+        const bf16x8 bL = *reinterpret_cast<const bf16x8*>(bl + o);
+        const bf16x8 pH = *reinterpret_cast<const bf16x8*>(PsH + l32 * PS + 16 * s + 8 * hi);
+        const bf16x8 pL = *reinterpret_cast<const bf16x8*>(PsL + l32 * PS + 16 * s + 8 * hi);
+        X = __builtin_amdgcn_mfma_f32_32x32x16_bf16(pH, bH, X, 0, 0, 0);
+        X = __builtin_amdgcn_mfma_f32_32x32x16_bf16(pH, bL, X, 0, 0, 0);
+        X = __builtin_amdgcn_mfma_f32_32x32x16_bf16(pL, bH, X, 0, 0, 0);
       }
     }
 
@@ -632,7 +639,8 @@ __global__ __launch_bounds__(256, 2) void iter_kernel_bf(IterArgs A) {
         const float rho = q0.x, irho = q0.y;
         const float iDelta = __builtin_amdgcn_rcpf(q0.z * d_i + rho);
         const unsigned off = (unsigned)(Ao[m] + row);
-        const RowInfo ri = row_info_w(A, row, q1.x, q1.y, ew_r[r], hw_r[r], hp_r[r], Hp[m]);
+        const RowInfo ri = row_info_l(A, row, q1.x, q1.y, ew_r[r], hw_r[r],
+                                      (unsigned)(Wo[m] + wd), Hp[m]);
         const float vv = v_r[r];
         const float z = prox_row(ri, vv, q0.w, irho, nullptr);
         const float u = vv - z;
@@ -663,9 +671,12 @@ __global__ __launch_bounds__(256, 2) void iter_kernel_bf(IterArgs A) {
         const bf16x8 aL = *reinterpret_cast<const bf16x8*>(RwL + l32 * kRwS + 16 * s + 8 * hi);
 #pragma unroll
         for (int c = 0; c < NCH; ++c) {
-          T[c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aH, bH[2 * c + s], T[c], 0, 0, 0);
-          T[c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aH, bL[2 * c + s], T[c], 0, 0, 0);
-          T[c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aL, bH[2 * c + s], T[c], 0, 0, 0);
+          const size_t o = (size_t)(32 * c + l32) * A.npad + row_base + 16 * s + 8 * hi;
+          const bf16x8 bH = *reinterpret_cast<const bf16x8*>(bth + o);
+          const bf16x8 bL = *reinterpret_cast<const bf16x8*>(btl + o);
+          T[c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aH, bH, T[c], 0, 0, 0);
+          T[c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aH, bL, T[c], 0, 0, 0);
+          T[c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aL, bH, T[c], 0, 0, 0);
         }
       }
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
