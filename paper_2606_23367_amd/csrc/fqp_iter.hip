@@ -497,21 +497,43 @@ __device__ __forceinline__ void split_bf16(float x, __bf16& h, __bf16& l) {
   l = (__bf16)(x - (float)h);
 }
 
+// number of set bits of a wave-wide mask in lanes below this one
+__device__ __forceinline__ unsigned lanes_below(unsigned long long mask) {
+  return __builtin_amdgcn_mbcnt_hi((unsigned)(mask >> 32),
+                                   __builtin_amdgcn_mbcnt_lo((unsigned)mask, 0u));
+}
+
 constexpr int kRwS = 40;   // bf16 stride of one account's transposed R' (16-B aligned)
 
+// held (account, row) pairs of one wave's 32 x 32 block get their tax
+// records staged in LDS once per row chunk: kHS slots per wave, each an
+// absolute record index and the two float4 of the record
+constexpr int kHS = 64;
+constexpr int kHeldFloats = kHS + 8 * kHS;               // per wave
+constexpr int kRwFloats = kWaves * 2 * 32 * kRwS / 2;    // per-wave R' transposes
+
 template <int NCH, int MODE>
-constexpr int bf_lds_floats() {
-  // CONTRACT: per-wave R' transposes (hi, lo) or, after the row loop, the
-  // cross-wave reduction [4][32][kp]; PROJECT: a [4][32] max reduction and
-  // the split p of the tile (hi, lo) [2][32][kp + 8] bf16
-  return (MODE == MODE_CONTRACT)
-             ? ((kWaves * kTM * NCH * 32 > kWaves * 2 * 32 * kRwS / 2) ? kWaves * kTM * NCH * 32
-                                                                     : kWaves * 2 * 32 * kRwS / 2)
-             : kWaves * kTM + kTM * (NCH * 32 + 8);
+constexpr int bf_held_offset() {
+  // CONTRACT: after the R' transposes; PROJECT: after the max reduction and
+  // the split p of the tile
+  return (MODE == MODE_CONTRACT) ? kRwFloats : kWaves * kTM + kTM * (NCH * 32 + 8);
 }
 
 template <int NCH, int MODE>
-__global__ __launch_bounds__(256, 3) void iter_kernel_bf(IterArgs A) {
+constexpr int bf_lds_floats() {
+  // CONTRACT: per-wave R' transposes (hi, lo) and held records or, after the
+  // row loop, the cross-wave reduction [4][32][kp]; PROJECT: a [4][32] max
+  // reduction, the split p of the tile (hi, lo) [2][32][kp + 8] bf16 and the
+  // held records
+  return (MODE == MODE_CONTRACT)
+             ? ((kWaves * kTM * NCH * 32 > kRwFloats + kWaves * kHeldFloats)
+                    ? kWaves * kTM * NCH * 32
+                    : kRwFloats + kWaves * kHeldFloats)
+             : bf_held_offset<NCH, MODE>() + kWaves * kHeldFloats;
+}
+
+template <int NCH, int MODE>
+__global__ __launch_bounds__(256, (MODE == MODE_CONTRACT ? 2 : 3)) void iter_kernel_bf(IterArgs A) {
   constexpr int kp = NCH * 32;
   constexpr int KS = kp / 16;            // K steps of the PROJECT product
   constexpr int kX = bf_lds_floats<NCH, MODE>();
@@ -583,6 +605,8 @@ __global__ __launch_bounds__(256, 3) void iter_kernel_bf(IterArgs A) {
   for (int r = 0; r < 16; ++r) st_rp[r] = 0.f;
 
   __bf16* RwH = reinterpret_cast<__bf16*>(Xs) + w * 2 * 32 * kRwS;
+  int* HIdx = reinterpret_cast<int*>(Xs + bf_held_offset<NCH, MODE>() + w * kHeldFloats);
+  float4* HRec = reinterpret_cast<float4*>(HIdx + kHS);
   __bf16* RwL = RwH + 32 * kRwS;
   const int row_begin = tm.row_begin;
 
@@ -595,21 +619,54 @@ __global__ __launch_bounds__(256, 3) void iter_kernel_bf(IterArgs A) {
     const float d_i = row_ok ? A.d[row] : 1.f;
 
     float mu_r[16], v_r[16];
-    uint32_t ew_r[16], hw_r[16];
-    const int wd = row >> 5;
+    const int wd = row >> 5, b = row & 31;
+    // bit r: slot r holds an account and a row inside the book / the row is
+    // eligible / the row is held
+    unsigned ok_bits = 0u, el_bits = 0u, held_bits = 0u;
+    {
+      uint32_t ew_r[16], hw_r[16];
+      int hp_r[16];
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      const int m = 8 * (r >> 2) + 4 * hi + (r & 3);
-      const int a = Aid[m];
-      mu_r[r] = 0.f; v_r[r] = 0.f; ew_r[r] = 0u; hw_r[r] = 0u;
-      if (a >= 0 && row_ok) {
-        const unsigned off = (unsigned)(Ao[m] + row);
-        const unsigned wi = (unsigned)(Wo[m] + wd);
-        mu_r[r] = A.mu[off];
-        v_r[r] = A.v[off];
-        ew_r[r] = A.elig ? A.elig[wi] : 0xffffffffu;
-        hw_r[r] = A.hold[wi];
+      for (int r = 0; r < 16; ++r) {
+        const int m = 8 * (r >> 2) + 4 * hi + (r & 3);
+        const int a = Aid[m];
+        mu_r[r] = 0.f; v_r[r] = 0.f; ew_r[r] = 0u; hw_r[r] = 0u; hp_r[r] = 0;
+        if (a >= 0 && row_ok) {
+          const unsigned off = (unsigned)(Ao[m] + row);
+          const unsigned wi = (unsigned)(Wo[m] + wd);
+          mu_r[r] = A.mu[off];
+          v_r[r] = A.v[off];
+          ew_r[r] = A.elig ? A.elig[wi] : 0xffffffffu;
+          hw_r[r] = A.hold[wi];
+          hp_r[r] = A.hold_pre[wi];
+          ok_bits |= 1u << r;
+        }
       }
+      // record indices of the held pairs, in ballot order, into the wave's
+      // slot table; then one record load per lane
+      unsigned base = 0u;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int m = 8 * (r >> 2) + 4 * hi + (r & 3);
+        el_bits |= ((ew_r[r] >> b) & 1u) << r;
+        const bool held = ((ok_bits >> r) & 1u) && ((hw_r[r] >> b) & 1u);
+        held_bits |= (held ? 1u : 0u) << r;
+        const unsigned long long hm = __ballot(held);
+        const unsigned slot = base + lanes_below(hm);
+        if (held && slot < (unsigned)kHS) HIdx[slot] = Hp[m] + hp_r[r] + popc_below(hw_r[r], b);
+        base += (unsigned)__popcll(hm);
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      if ((unsigned)lane < base && lane < kHS) {
+        const int idx = HIdx[lane];
+        HRec[2 * lane] = A.hold_rec[2 * idx];
+        HRec[2 * lane + 1] = A.hold_rec[2 * idx + 1];
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
 
     floatx16 X;
@@ -629,18 +686,42 @@ __global__ __launch_bounds__(256, 3) void iter_kernel_bf(IterArgs A) {
       }
     }
 
+    unsigned hbase = 0u;
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
       const int m = 8 * (r >> 2) + 4 * hi + (r & 3);
-      const int a = Aid[m];
+      const bool held = (held_bits >> r) & 1u;
+      const unsigned long long hm = __ballot(held);
+      const unsigned slot = hbase + lanes_below(hm);
+      hbase += (unsigned)__popcll(hm);
       float Rp = 0.f;
-      if (a >= 0 && row_ok) {
+      if ((ok_bits >> r) & 1u) {
         const float4 q0 = Acc[2 * m], q1 = Acc[2 * m + 1];
         const float rho = q0.x, irho = q0.y;
         const float iDelta = __builtin_amdgcn_rcpf(q0.z * d_i + rho);
         const unsigned off = (unsigned)(Ao[m] + row);
-        const RowInfo ri = row_info_l(A, row, q1.x, q1.y, ew_r[r], hw_r[r],
-                                      (unsigned)(Wo[m] + wd), Hp[m]);
+        RowInfo ri;
+        const bool el = (el_bits >> r) & 1u;
+        ri.lb = el ? q1.x : 0.f;
+        ri.ub = el ? q1.y : 0.f;
+        ri.w0 = 0.f;
+        ri.taxed = false;
+        if (held) {
+          float4 r0, r1;
+          if (slot < (unsigned)kHS) {
+            r0 = HRec[2 * slot];
+            r1 = HRec[2 * slot + 1];
+          } else {                       // slot table full: direct loads
+            const unsigned wi = (unsigned)(Wo[m] + wd);
+            const int idx = Hp[m] + A.hold_pre[wi] + popc_below(A.hold[wi], b);
+            r0 = A.hold_rec[2 * idx];
+            r1 = A.hold_rec[2 * idx + 1];
+          }
+          ri.w0 = r0.x;
+          ri.taxed = r0.y > 0.f;
+          ri.t.b1 = r0.y; ri.t.b2 = r0.z; ri.t.b3 = r0.w;
+          ri.t.s0 = r1.x; ri.t.s1 = r1.y; ri.t.s2 = r1.z; ri.t.s3 = r1.w;
+        }
         const float vv = v_r[r];
         const float z = prox_row(ri, vv, q0.w, irho, nullptr);
         const float u = vv - z;
@@ -989,6 +1070,7 @@ __global__ __launch_bounds__(256) void ksolve_kernel(KArgs A) {
   const int kp = A.kp, k = A.k, G = A.G, kg = k + G;
   const size_t M = A.m_total;
   const int n_rt = tile_map(*A.m_act, A.n, A.nblk, 0).n_rt;
+  const int n_rt_p = tile_map(*A.m_act, A.n, A.nblk_p, 0).n_rt;   // PROJECT's row tiles
   float* par = A.par + (size_t)a * kNPar;
   const int cls = (int)par[P_CLASS];
   const float* Kinv = A.Kinv + (size_t)cls * kp * kp;
@@ -1026,7 +1108,7 @@ __global__ __launch_bounds__(256) void ksolve_kernel(KArgs A) {
     // max over the row tiles of the primal residual estimate, one row tile
     // per thread
     float v = 0.f;
-    for (int rt = tid; rt < n_rt; rt += 256)
+    for (int rt = tid; rt < n_rt_p; rt += 256)
       v = fmaxf(v, A.stat[((size_t)rt * M + a) * kNStat + ST_RPRIM]);
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
@@ -1186,6 +1268,47 @@ hipError_t configure_iter_kernels() {
   FQP_CFG(1) FQP_CFG(2) FQP_CFG(3) FQP_CFG(4) FQP_CFG(5) FQP_CFG(6)
 #undef FQP_CFG
   return e;
+}
+
+template <int NCH>
+static int iter_blocks_per_cu_t(int prec, int mode) {
+  int nb = 0;
+  hipError_t e;
+  if (prec == FQP_PREC_BF16X3 && NCH * 32 <= kMaxKpBf) {
+    constexpr int NB = NCH * 32 <= kMaxKpBf ? NCH : 1;
+    e = (mode == MODE_CONTRACT)
+            ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                  &nb, (const void*)iter_kernel_bf<NB, MODE_CONTRACT>, 256,
+                  iter_smem_bf<NB, MODE_CONTRACT>())
+            : hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                  &nb, (const void*)iter_kernel_bf<NB, MODE_PROJECT>, 256,
+                  iter_smem_bf<NB, MODE_PROJECT>());
+  } else {
+    e = (mode == MODE_CONTRACT)
+            ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                  &nb, (const void*)iter_kernel<NCH, MODE_CONTRACT>, 256,
+                  iter_smem<NCH, MODE_CONTRACT>())
+            : hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                  &nb, (const void*)iter_kernel<NCH, MODE_PROJECT>, 256,
+                  iter_smem<NCH, MODE_PROJECT>());
+  }
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return 0;
+  }
+  return nb;
+}
+
+int iter_blocks_per_cu(int kp, int prec, int mode) {
+  switch (kp / 32) {
+    case 1: return iter_blocks_per_cu_t<1>(prec, mode);
+    case 2: return iter_blocks_per_cu_t<2>(prec, mode);
+    case 3: return iter_blocks_per_cu_t<3>(prec, mode);
+    case 4: return iter_blocks_per_cu_t<4>(prec, mode);
+    case 5: return iter_blocks_per_cu_t<5>(prec, mode);
+    case 6: return iter_blocks_per_cu_t<6>(prec, mode);
+    default: return 0;
+  }
 }
 
 hipError_t launch_iter(const IterArgs& A, int kp, int mode, int prec, dim3 grid,

@@ -38,7 +38,8 @@ struct IterArgs {
 };
 
 struct KArgs {
-  int kp, k, G, n, nblk, m_total;    // nblk: workgroups of the iteration passes
+  int kp, k, G, n, nblk, m_total;    // nblk: workgroups of the CONTRACT pass
+  int nblk_p;                        // workgroups of the PROJECT pass
   const int* m_act;
   const int* act;
   const float* part;
@@ -84,6 +85,9 @@ __device__ __forceinline__ TileMap tile_map(int m_act, int n, int nblk, int lin)
 }
 
 hipError_t configure_iter_kernels();
+// workgroups of one iteration pass (mode) resident on one compute unit at
+// once; 0 if the runtime cannot tell
+int iter_blocks_per_cu(int kp, int prec, int mode);
 hipError_t launch_iter(const IterArgs& A, int kp, int mode, int prec, dim3 grid,
                        hipStream_t st);
 hipError_t launch_split_bt(int n, int npad, int kp, const float* Bt, uint16_t* bh, uint16_t* bl,

@@ -123,6 +123,7 @@ struct DevBuf {
 
 struct fqp_handle {
   int device = 0;
+  int n_cu = 0;                   // compute units of the device
   hipStream_t stream = nullptr;   // the handle's own stream (capturable)
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
   std::string err;
@@ -218,6 +219,11 @@ fqp_error fqp_create(fqp_handle** h, int device) {
   }
   fqp_handle* hh = new fqp_handle();
   hh->device = device;
+  if (hipDeviceGetAttribute(&hh->n_cu, hipDeviceAttributeMultiprocessorCount, device) !=
+      hipSuccess) {
+    (void)hipGetLastError();
+    hh->n_cu = 0;
+  }
   // default priority, non-blocking with respect to the legacy stream
   if (hipStreamCreateWithFlags(&hh->stream, hipStreamNonBlocking) != hipSuccess ||
       hipEventCreateWithFlags(&hh->ev_in, hipEventDisableTiming) != hipSuccess ||
@@ -417,13 +423,20 @@ extern "C" fqp_error fqp_solve_batch(fqp_handle* h, const fqp_universe* U, const
   const int n_rb = polish_row_blocks(n);
   WS(gpart_p, double, "polish_gpart", (size_t)m * n_rb * 4);
 
-  // iteration geometry: ~1024 workgroups over (row tiles x account tiles)
+  // iteration geometry, per pass: (row tiles x account tiles) workgroups, as
+  // many as the compute units hold at once (one round: a partial second
+  // round of workgroups would double the pass), else ~1024
   const int acc_tiles = (m + kTM - 1) / kTM;
-  const int target_rt = std::max(1, 1024 / acc_tiles);
-  int chunks = (n + kRowsPerChunk * target_rt - 1) / (kRowsPerChunk * target_rt);
-  chunks = std::max(1, std::min(chunks, 64));
-  const int rows_per_wg = chunks * kRowsPerChunk;
-  const int n_rt = (n + rows_per_wg - 1) / rows_per_wg;    // at the full batch
+  auto row_tiles = [&](int mode) {
+    const int per_cu = iter_blocks_per_cu(kp, S.precision, mode);
+    const int slots = (per_cu > 0 && h->n_cu > 0) ? per_cu * h->n_cu : 1024;
+    const int target_rt = std::max(1, slots / acc_tiles);
+    int chunks = (n + kRowsPerChunk * target_rt - 1) / (kRowsPerChunk * target_rt);
+    chunks = std::max(1, std::min(chunks, 64));
+    const int rows_per_wg = chunks * kRowsPerChunk;
+    return (n + rows_per_wg - 1) / rows_per_wg;            // at the full batch
+  };
+  const int n_rt = row_tiles(0), n_rt_p = row_tiles(1);
   const int max_rt = (n + kRowsPerChunk - 1) / kRowsPerChunk;   // short active lists
   WS(part, float, "part", (size_t)max_rt * m * kp);
   WS(stat, float, "stat", (size_t)max_rt * m * kNStat);
@@ -482,6 +495,7 @@ extern "C" fqp_error fqp_solve_batch(fqp_handle* h, const fqp_universe* U, const
   ia.npad = npad; ia.bt_hi = bt_hi; ia.bt_lo = bt_lo; ia.btt_hi = btt_hi; ia.btt_lo = btt_lo;
   KArgs ka{};
   ka.kp = kp; ka.k = k; ka.G = G; ka.n = n; ka.nblk = n_rt * acc_tiles; ka.m_total = m;
+  ka.nblk_p = n_rt_p * acc_tiles;
   ka.m_act = m_act; ka.act = act;
   ka.part = part; ka.stat = stat; ka.par = par; ka.pp = pp; ka.Kinv = Kinv; ka.cvec = cvec;
   ka.qvec = qvec; ka.sig1 = sig1; ka.mbg = mbg; ka.zb = zb; ka.vb = vb;
@@ -509,7 +523,7 @@ extern "C" fqp_error fqp_solve_batch(fqp_handle* h, const fqp_universe* U, const
     std::vector<hipEvent_t>* v;
     ~EvGuard() { for (auto& ev : *v) (void)hipEventDestroy(ev); }
   } evguard{&evs};
-  const dim3 igrid(n_rt, acc_tiles);
+  const dim3 igrid(n_rt, acc_tiles), igrid_p(n_rt_p, acc_tiles);
   HIP_CHECK(hipMemsetAsync(stat, 0, sizeof(float) * (size_t)max_rt * m * kNStat, st));
   // the cap kernel runs only when some account has a finite cap; the
   // held-asset records are sized by the packed count
@@ -534,7 +548,7 @@ extern "C" fqp_error fqp_solve_batch(fqp_handle* h, const fqp_universe* U, const
     e0 = launch_ksolve(ka, m, st);
     if (e0 != hipSuccess) return e0;
     if (S.profile) { e0 = hipEventRecord(evs[2 * c], st); if (e0 != hipSuccess) return e0; }
-    e0 = launch_iter(ia, kp, 1, S.precision, igrid, st);
+    e0 = launch_iter(ia, kp, 1, S.precision, igrid_p, st);
     if (e0 != hipSuccess) return e0;
     if (S.profile) { e0 = hipEventRecord(evs[2 * c + 1], st); if (e0 != hipSuccess) return e0; }
     if (any_cap) e0 = launch_cap(ia, m, st);
