@@ -533,7 +533,7 @@ constexpr int bf_lds_floats() {
 }
 
 template <int NCH, int MODE>
-__global__ __launch_bounds__(256, (MODE == MODE_CONTRACT ? 2 : 3)) void iter_kernel_bf(IterArgs A) {
+__global__ __launch_bounds__(256, 3) void iter_kernel_bf(IterArgs A) {
   constexpr int kp = NCH * 32;
   constexpr int KS = kp / 16;            // K steps of the PROJECT product
   constexpr int kX = bf_lds_floats<NCH, MODE>();
@@ -624,36 +624,51 @@ __global__ __launch_bounds__(256, (MODE == MODE_CONTRACT ? 2 : 3)) void iter_ker
     // eligible / the row is held
     unsigned ok_bits = 0u, el_bits = 0u, held_bits = 0u;
     {
-      uint32_t ew_r[16], hw_r[16];
-      int hp_r[16];
+      // the 32 rows of a half-wave share one eligibility, holding and
+      // holding-prefix word per account: lane j < 16 of the half loads the
+      // first two for slot j, lane 16 + j the third; the others read them
+      // by lane shuffles
+      uint32_t w_a = 0u;      // lanes j < 16: eligibility word of slot j
+      int w_b = 0;            // lanes j < 16: holding word; 16 + j: prefix
+      if (row_base < n) {     // uniform per wave: the words exist
+        const int rr = l32 & 15;
+        const int mm = 8 * (rr >> 2) + 4 * hi + (rr & 3);
+        if (Aid[mm] >= 0) {
+          const unsigned wi = (unsigned)(Wo[mm] + wd);
+          if (l32 < 16) {
+            w_a = A.elig ? A.elig[wi] : 0xffffffffu;
+            w_b = (int)A.hold[wi];
+          } else {
+            w_b = A.hold_pre[wi];
+          }
+        }
+      }
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
         const int m = 8 * (r >> 2) + 4 * hi + (r & 3);
-        const int a = Aid[m];
-        mu_r[r] = 0.f; v_r[r] = 0.f; ew_r[r] = 0u; hw_r[r] = 0u; hp_r[r] = 0;
-        if (a >= 0 && row_ok) {
+        mu_r[r] = 0.f; v_r[r] = 0.f;
+        if (Aid[m] >= 0 && row_ok) {
           const unsigned off = (unsigned)(Ao[m] + row);
-          const unsigned wi = (unsigned)(Wo[m] + wd);
           mu_r[r] = A.mu[off];
           v_r[r] = A.v[off];
-          ew_r[r] = A.elig ? A.elig[wi] : 0xffffffffu;
-          hw_r[r] = A.hold[wi];
-          hp_r[r] = A.hold_pre[wi];
           ok_bits |= 1u << r;
         }
       }
       // record indices of the held pairs, in ballot order, into the wave's
       // slot table; then one record load per lane
       unsigned base = 0u;
-#pragma unroll
+#pragma nounroll
       for (int r = 0; r < 16; ++r) {
         const int m = 8 * (r >> 2) + 4 * hi + (r & 3);
-        el_bits |= ((ew_r[r] >> b) & 1u) << r;
-        const bool held = ((ok_bits >> r) & 1u) && ((hw_r[r] >> b) & 1u);
+        const uint32_t ew = (uint32_t)__shfl((int)w_a, 32 * hi + r, 64);
+        const uint32_t hw = (uint32_t)__shfl(w_b, 32 * hi + r, 64);
+        const int hp = __shfl(w_b, 32 * hi + 16 + r, 64);
+        el_bits |= ((ew >> b) & 1u) << r;
+        const bool held = ((ok_bits >> r) & 1u) && ((hw >> b) & 1u);
         held_bits |= (held ? 1u : 0u) << r;
         const unsigned long long hm = __ballot(held);
         const unsigned slot = base + lanes_below(hm);
-        if (held && slot < (unsigned)kHS) HIdx[slot] = Hp[m] + hp_r[r] + popc_below(hw_r[r], b);
+        if (held && slot < (unsigned)kHS) HIdx[slot] = Hp[m] + hp + popc_below(hw, b);
         base += (unsigned)__popcll(hm);
       }
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
