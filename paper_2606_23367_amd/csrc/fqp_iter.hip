@@ -879,18 +879,145 @@ __device__ __forceinline__ float cap_step(float gt, float nft, float tau, float 
   return fmaxf(nl, 0.f);
 }
 
-// Two layouts.  Resident (n <= kCapQ * kCapT, at most kCapH held rows): one
-// pass loads the account; rows that are eligible and not held keep v in a
-// register (an excluded row, never held, has z = 0 for every multiplier and
-// keeps 0), each held row moves with its tax record to the thread whose
-// index is the row's record number; every evaluation then runs on registers,
-// and every thread takes the same Newton step from the same sums (one
-// barrier per evaluation, double-buffered sums).  Streaming (otherwise): each
-// evaluation re-reads the account.
-__global__ __launch_bounds__(kCapT) void cap_kernel(IterArgs A) {
+// Resident layout (n <= kCapQ * kCapT and at most kCapH held rows in every
+// account of the book; the host picks the layout per solve): one pass loads
+// the account; rows that are eligible and not held keep v in a register (an
+// excluded row, never held, has z = 0 for every multiplier and keeps 0);
+// held row j moves to LDS, and thread j keeps the first kCapT held rows' tax
+// records in registers (records past that are re-read from the cache at each
+// evaluation); every evaluation then runs on registers and LDS, and every
+// thread takes the same Newton step from the same sums (one barrier per
+// evaluation, double-buffered sums).  At most 64 registers per lane, so that
+// two accounts share a compute unit.
+__global__ __launch_bounds__(kCapT, 8) void cap_kernel(IterArgs A) {
   __shared__ float s_g[2][kCapT / 64], s_n[2][kCapT / 64];
   __shared__ float s_hv[kCapH];
   __shared__ unsigned char s_hel[kCapH];
+  const int slot = blockIdx.x;
+  if (slot >= *A.m_act) return;
+  const int a = A.act[slot];
+  float* par = A.par_rw + (size_t)a * kNPar;
+  const float tau = par[P_TAU];
+  if (!isfinite(tau)) return;
+  const int tid = threadIdx.x, n = A.n, wv = tid >> 6;
+  const float rho = par[P_RHO], irho = 1.f / rho, kap = par[P_KAPPA];
+  const float lbp = par[P_LB], ubp = par[P_UB];
+  float lam = par[P_LAM];
+  const int hptr = A.hold_ptr[a];
+  const int H = A.hold_ptr[a + 1] - hptr;
+  float lo = 0.f, hi_b = INFINITY, best_feas = INFINITY;
+  bool done = false;
+
+  const float* va = A.v + (size_t)a * n;
+  const size_t wa = (size_t)a * A.W;
+  float vr[kCapQ];
+  // four groups of loads in flight at a time (register budget)
+#pragma unroll
+  for (int h2 = 0; h2 < 4; ++h2) {
+    float x[kCapQ / 4];
+    uint32_t ew[kCapQ / 4], hw[kCapQ / 4];
+#pragma unroll
+    for (int q = 0; q < kCapQ / 4; ++q) {
+      const int i = (h2 * (kCapQ / 4) + q) * kCapT + tid;
+      x[q] = 0.f; ew[q] = 0u; hw[q] = 0u;
+      if (i < n) {
+        ew[q] = A.elig ? A.elig[wa + (i >> 5)] : 0xffffffffu;
+        hw[q] = A.hold[wa + (i >> 5)];
+        x[q] = va[i];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < kCapQ / 4; ++q) {
+      const int i = (h2 * (kCapQ / 4) + q) * kCapT + tid;
+      const int b = i & 31;
+      const bool el = (ew[q] >> b) & 1u;
+      float keep = el ? x[q] : 0.f;
+      if ((hw[q] >> b) & 1u) {
+        const int j = A.hold_pre[wa + (i >> 5)] + popc_below(hw[q], b);
+        s_hv[j] = x[q];
+        s_hel[j] = el ? 1 : 0;
+        keep = 0.f;
+      }
+      vr[h2 * (kCapQ / 4) + q] = keep;
+    }
+  }
+  __syncthreads();
+  // held row tid: v, box and tax record in registers
+  float hv = 0.f, hw0 = 0.f, hlb = 0.f, hub = 0.f;
+  TaxLots ht{};
+  bool htx = false;
+  if (tid < H) {
+    const float4 r0 = A.hold_rec[2 * (hptr + tid)], r1 = A.hold_rec[2 * (hptr + tid) + 1];
+    hv = s_hv[tid];
+    const bool el = s_hel[tid] != 0;
+    hlb = el ? lbp : 0.f;
+    hub = el ? ubp : 0.f;
+    hw0 = r0.x;
+    htx = r0.y > 0.f;
+    ht.b1 = r0.y; ht.b2 = r0.z; ht.b3 = r0.w;
+    ht.s0 = r1.x; ht.s1 = r1.y; ht.s2 = r1.z; ht.s3 = r1.w;
+  }
+  for (int it = 0; it < 48; ++it) {
+    const float th = (kap + lam) * irho;
+    float g = 0.f, nf = 0.f;
+#pragma unroll
+    for (int q = 0; q < kCapQ; ++q) {
+      if (q * kCapT < n) {                 // uniform
+        float z = fminf(vr[q] + th, fmaxf(0.f, vr[q] - th));
+        z = fminf(fmaxf(z, lbp), ubp);
+        g += fabsf(z);
+        nf += (z != 0.f && z > lbp && z < ubp) ? 1.f : 0.f;
+      }
+    }
+    if (tid < H) {
+      RowInfo ri;
+      ri.lb = hlb; ri.ub = hub; ri.w0 = hw0; ri.taxed = htx; ri.t = ht;
+      bool kink;
+      const float z = prox_row(ri, hv, th, irho, &kink);
+      g += fabsf(z - ri.w0);
+      nf += kink ? 0.f : 1.f;
+    }
+    if (H > kCapT && tid + kCapT < H) {          // uniform test first
+      const int j = tid + kCapT;
+      const float4 r0 = A.hold_rec[2 * (hptr + j)], r1 = A.hold_rec[2 * (hptr + j) + 1];
+      RowInfo ri;
+      const bool el = s_hel[j] != 0;
+      ri.lb = el ? lbp : 0.f;
+      ri.ub = el ? ubp : 0.f;
+      ri.w0 = r0.x;
+      ri.taxed = r0.y > 0.f;
+      ri.t.b1 = r0.y; ri.t.b2 = r0.z; ri.t.b3 = r0.w;
+      ri.t.s0 = r1.x; ri.t.s1 = r1.y; ri.t.s2 = r1.z; ri.t.s3 = r1.w;
+      bool kink;
+      const float z = prox_row(ri, s_hv[j], th, irho, &kink);
+      g += fabsf(z - ri.w0);
+      nf += kink ? 0.f : 1.f;
+    }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+      g += __shfl_xor(g, o, 64);
+      nf += __shfl_xor(nf, o, 64);
+    }
+    const int buf = it & 1;
+    if ((tid & 63) == 0) { s_g[buf][wv] = g; s_n[buf][wv] = nf; }
+    __syncthreads();
+    float gt = 0.f, nft = 0.f;
+#pragma unroll
+    for (int q = 0; q < kCapT / 64; ++q) { gt += s_g[buf][q]; nft += s_n[buf][q]; }
+    lam = cap_step(gt, nft, tau, rho, lam, lo, hi_b, best_feas, done);
+    if (done) break;
+  }
+  if (tid == 0) {
+    // never hand the prox a multiplier whose turnover is known to exceed tau
+    float out = lam;
+    if (!done && isfinite(best_feas)) out = best_feas;
+    par[P_LAM] = out;
+  }
+}
+
+// Streaming layout (any size): each evaluation re-reads the account.
+__global__ __launch_bounds__(kCapT) void cap_stream_kernel(IterArgs A) {
+  __shared__ float s_g[2][kCapT / 64], s_n[2][kCapT / 64];
   __shared__ float s_lam;
   __shared__ int s_done;
   const int slot = blockIdx.x;
@@ -908,147 +1035,63 @@ __global__ __launch_bounds__(kCapT) void cap_kernel(IterArgs A) {
   float lo = 0.f, hi_b = INFINITY, best_feas = INFINITY;
   bool done = false;
 
-  if (n <= kCapQ * kCapT && H <= kCapH) {
-    const float* va = A.v + (size_t)a * n;
-    const size_t wa = (size_t)a * A.W;
-    float vr[kCapQ];
+  if (tid == 0) s_done = 0;
+  for (int it = 0; it < 48; ++it) {
+    const float th = (kap + lam) * irho;
+    float g = 0.f, nf = 0.f;
+    // groups of 8 rows per thread: every load of a group is issued before
+    // the group is evaluated
+    for (int i0 = 0; i0 < n; i0 += 8 * kCapT) {
+      float vr[8];
+      uint32_t ew[8], hw[8];
+      int hp[8];
 #pragma unroll
-    for (int q = 0; q < kCapQ; ++q) {
-      const int i = q * kCapT + tid;
-      vr[q] = 0.f;
-      if (i < n) {
-        const int b = i & 31;
-        const uint32_t ew = A.elig ? A.elig[wa + (i >> 5)] : 0xffffffffu;
-        const uint32_t hw = A.hold[wa + (i >> 5)];
-        const float x = va[i];
-        const bool el = (ew >> b) & 1u;
-        if ((hw >> b) & 1u) {
-          const int j = A.hold_pre[wa + (i >> 5)] + popc_below(hw, b);
-          s_hv[j] = x;
-          s_hel[j] = el ? 1 : 0;
-        } else {
-          vr[q] = el ? x : 0.f;
-        }
-      }
-    }
-    __syncthreads();
-    // held rows tid and tid + kCapT: v, box and tax record in registers
-    float hv[2], hw0[2], hlb[2], hub[2];
-    TaxLots ht[2];
-    bool htx[2];
-#pragma unroll
-    for (int e = 0; e < 2; ++e) {
-      const int j = tid + e * kCapT;
-      hv[e] = 0.f; hw0[e] = 0.f; hlb[e] = 0.f; hub[e] = 0.f; htx[e] = false;
-      ht[e] = TaxLots{};
-      if (j < H) {
-        const float4 r0 = A.hold_rec[2 * (hptr + j)], r1 = A.hold_rec[2 * (hptr + j) + 1];
-        hv[e] = s_hv[j];
-        const bool el = s_hel[j] != 0;
-        hlb[e] = el ? lbp : 0.f;
-        hub[e] = el ? ubp : 0.f;
-        hw0[e] = r0.x;
-        htx[e] = r0.y > 0.f;
-        ht[e].b1 = r0.y; ht[e].b2 = r0.z; ht[e].b3 = r0.w;
-        ht[e].s0 = r1.x; ht[e].s1 = r1.y; ht[e].s2 = r1.z; ht[e].s3 = r1.w;
-      }
-    }
-    for (int it = 0; it < 48; ++it) {
-      const float th = (kap + lam) * irho;
-      float g = 0.f, nf = 0.f;
-#pragma unroll
-      for (int q = 0; q < kCapQ; ++q) {
-        if (q * kCapT < n) {                 // uniform
-          float z = fminf(vr[q] + th, fmaxf(0.f, vr[q] - th));
-          z = fminf(fmaxf(z, lbp), ubp);
-          g += fabsf(z);
-          nf += (z != 0.f && z > lbp && z < ubp) ? 1.f : 0.f;
+      for (int q = 0; q < 8; ++q) {
+        const int i = i0 + q * kCapT + tid;
+        vr[q] = 0.f; ew[q] = 0u; hw[q] = 0u; hp[q] = 0;
+        if (i < n) {
+          const size_t wi = (size_t)a * A.W + (i >> 5);
+          vr[q] = A.v[(size_t)a * n + i];
+          ew[q] = A.elig ? A.elig[wi] : 0xffffffffu;
+          hw[q] = A.hold[wi];
+          hp[q] = A.hold_pre[wi];
         }
       }
 #pragma unroll
-      for (int e = 0; e < 2; ++e) {
-        if (e * kCapT < H && tid + e * kCapT < H) {
-          RowInfo ri;
-          ri.lb = hlb[e]; ri.ub = hub[e]; ri.w0 = hw0[e]; ri.taxed = htx[e]; ri.t = ht[e];
+      for (int q = 0; q < 8; ++q) {
+        const int i = i0 + q * kCapT + tid;
+        if (i < n) {
+          const RowInfo ri = row_info_w(A, i, lbp, ubp, ew[q], hw[q], hp[q], hptr);
           bool kink;
-          const float z = prox_row(ri, hv[e], th, irho, &kink);
+          const float z = prox_row(ri, vr[q], th, irho, &kink);
           g += fabsf(z - ri.w0);
           nf += kink ? 0.f : 1.f;
         }
       }
+    }
 #pragma unroll
-      for (int o = 32; o >= 1; o >>= 1) {
-        g += __shfl_xor(g, o, 64);
-        nf += __shfl_xor(nf, o, 64);
-      }
-      const int buf = it & 1;
-      if ((tid & 63) == 0) { s_g[buf][wv] = g; s_n[buf][wv] = nf; }
-      __syncthreads();
+    for (int o = 32; o >= 1; o >>= 1) {
+      g += __shfl_xor(g, o, 64);
+      nf += __shfl_xor(nf, o, 64);
+    }
+    if ((tid & 63) == 0) { s_g[0][wv] = g; s_n[0][wv] = nf; }
+    __syncthreads();
+    if (tid == 0) {
       float gt = 0.f, nft = 0.f;
-#pragma unroll
-      for (int q = 0; q < kCapT / 64; ++q) { gt += s_g[buf][q]; nft += s_n[buf][q]; }
-      lam = cap_step(gt, nft, tau, rho, lam, lo, hi_b, best_feas, done);
-      if (done) break;
+      for (int q = 0; q < kCapT / 64; ++q) { gt += s_g[0][q]; nft += s_n[0][q]; }
+      bool dn;
+      s_lam = cap_step(gt, nft, tau, rho, lam, lo, hi_b, best_feas, dn);
+      s_done = dn ? 1 : 0;
     }
-  } else {
-    if (tid == 0) s_done = 0;
-    for (int it = 0; it < 48; ++it) {
-      const float th = (kap + lam) * irho;
-      float g = 0.f, nf = 0.f;
-      // groups of 8 rows per thread: every load of a group is issued before
-      // the group is evaluated
-      for (int i0 = 0; i0 < n; i0 += 8 * kCapT) {
-        float vr[8];
-        uint32_t ew[8], hw[8];
-        int hp[8];
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-          const int i = i0 + q * kCapT + tid;
-          vr[q] = 0.f; ew[q] = 0u; hw[q] = 0u; hp[q] = 0;
-          if (i < n) {
-            const size_t wi = (size_t)a * A.W + (i >> 5);
-            vr[q] = A.v[(size_t)a * n + i];
-            ew[q] = A.elig ? A.elig[wi] : 0xffffffffu;
-            hw[q] = A.hold[wi];
-            hp[q] = A.hold_pre[wi];
-          }
-        }
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-          const int i = i0 + q * kCapT + tid;
-          if (i < n) {
-            const RowInfo ri = row_info_w(A, i, lbp, ubp, ew[q], hw[q], hp[q], hptr);
-            bool kink;
-            const float z = prox_row(ri, vr[q], th, irho, &kink);
-            g += fabsf(z - ri.w0);
-            nf += kink ? 0.f : 1.f;
-          }
-        }
-      }
-#pragma unroll
-      for (int o = 32; o >= 1; o >>= 1) {
-        g += __shfl_xor(g, o, 64);
-        nf += __shfl_xor(nf, o, 64);
-      }
-      if ((tid & 63) == 0) { s_g[0][wv] = g; s_n[0][wv] = nf; }
-      __syncthreads();
-      if (tid == 0) {
-        float gt = 0.f, nft = 0.f;
-        for (int q = 0; q < kCapT / 64; ++q) { gt += s_g[0][q]; nft += s_n[0][q]; }
-        bool dn;
-        s_lam = cap_step(gt, nft, tau, rho, lam, lo, hi_b, best_feas, dn);
-        s_done = dn ? 1 : 0;
-      }
-      __syncthreads();
-      lam = s_lam;
-      done = s_done != 0;
-      if (done) break;
-      __syncthreads();
-    }
+    __syncthreads();
+    lam = s_lam;
+    done = s_done != 0;
+    if (done) break;
+    __syncthreads();
   }
   if (tid == 0) {
     // never hand the prox a multiplier whose turnover is known to exceed tau
-    // (tid 0 carries the bracket in both layouts)
+    // (tid 0 carries the bracket)
     float out = lam;
     if (!done && isfinite(best_feas)) out = best_feas;
     par[P_LAM] = out;
@@ -1339,8 +1382,15 @@ hipError_t launch_iter(const IterArgs& A, int kp, int mode, int prec, dim3 grid,
   }
 }
 
-hipError_t launch_cap(const IterArgs& A, int m_total, hipStream_t st) {
-  hipLaunchKernelGGL(cap_kernel, dim3(m_total), dim3(kCapT), 0, st, A);
+bool cap_resident_fits(int n, int max_held) {
+  return n <= kCapQ * kCapT && max_held <= kCapH;
+}
+
+hipError_t launch_cap(const IterArgs& A, int m_total, bool resident, hipStream_t st) {
+  if (resident)
+    hipLaunchKernelGGL(cap_kernel, dim3(m_total), dim3(kCapT), 0, st, A);
+  else
+    hipLaunchKernelGGL(cap_stream_kernel, dim3(m_total), dim3(kCapT), 0, st, A);
   return hipGetLastError();
 }
 

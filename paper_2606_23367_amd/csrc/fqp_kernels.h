@@ -92,7 +92,10 @@ hipError_t launch_iter(const IterArgs& A, int kp, int mode, int prec, dim3 grid,
                        hipStream_t st);
 hipError_t launch_split_bt(int n, int npad, int kp, const float* Bt, uint16_t* bh, uint16_t* bl,
                            uint16_t* bth, uint16_t* btl, hipStream_t st);
-hipError_t launch_cap(const IterArgs& A, int m_total, hipStream_t st);
+// turnover-cap multiplier search: the register-resident layout needs
+// n <= 16384 and at most 2048 held rows in every account
+bool cap_resident_fits(int n, int max_held);
+hipError_t launch_cap(const IterArgs& A, int m_total, bool resident, hipStream_t st);
 hipError_t launch_materialize_z(const IterArgs& A, int m_total, float* z, hipStream_t st);
 hipError_t launch_ksolve(const KArgs& A, int m_total, hipStream_t st);
 hipError_t launch_build_bt(int n, int k, int G, int kp, const float* B, const int32_t* group,

@@ -528,14 +528,21 @@ extern "C" fqp_error fqp_solve_batch(fqp_handle* h, const fqp_universe* U, const
   // the cap kernel runs only when some account has a finite cap; the
   // held-asset records are sized by the packed count
   bool any_cap = false;
-  int n_held = 0;
+  int n_held = 0, max_held = 0;
   {
     std::vector<float> tau_h(m);
+    std::vector<int32_t> hp_h(m + 1);
     HIP_CHECK(hipMemcpyAsync(tau_h.data(), P->tau, sizeof(float) * m, hipMemcpyDeviceToHost, st));
-    HIP_CHECK(hipMemcpyAsync(&n_held, hold_ptr + m, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIP_CHECK(hipMemcpyAsync(hp_h.data(), hold_ptr, sizeof(int32_t) * (m + 1),
+                             hipMemcpyDeviceToHost, st));
     HIP_CHECK(hipStreamSynchronize(st));
-    for (int a = 0; a < m; ++a) any_cap = any_cap || std::isfinite(tau_h[a]);
+    for (int a = 0; a < m; ++a) {
+      any_cap = any_cap || std::isfinite(tau_h[a]);
+      max_held = std::max(max_held, hp_h[a + 1] - hp_h[a]);
+    }
+    n_held = hp_h[m];
   }
+  const bool cap_resident = cap_resident_fits(n, max_held);
   WS(hold_rec, float4, "hold_rec", 2 * (size_t)std::max(n_held, 1));
   HIP_CHECK(launch_pack_rec(pk, hold_rec, n_held, st));
   ia.hold_rec = hold_rec;
@@ -551,7 +558,7 @@ extern "C" fqp_error fqp_solve_batch(fqp_handle* h, const fqp_universe* U, const
     e0 = launch_iter(ia, kp, 1, S.precision, igrid_p, st);
     if (e0 != hipSuccess) return e0;
     if (S.profile) { e0 = hipEventRecord(evs[2 * c + 1], st); if (e0 != hipSuccess) return e0; }
-    if (any_cap) e0 = launch_cap(ia, m, st);
+    if (any_cap) e0 = launch_cap(ia, m, cap_resident, st);
     return e0;
   };
 
