@@ -97,19 +97,35 @@ __global__ __launch_bounds__(256) void gram_partial_kernel(
 
 // sum the partials, add F~^-1, Cholesky, inverse, border vectors.
 // One workgroup per class.  Everything in float64 in global scratch.
-__global__ void kfactor_kernel(int k, int G, int kp, int nparts,
+// kg <= kKfLds: the factor and the inverse live in LDS (dynamic shared
+// memory of 2 kg^2 doubles) and the inverse comes from wave-parallel
+// triangular solves; wider blocks work in the global scratch Kw
+constexpr int kKfLds = 96;
+
+__global__ __launch_bounds__(1024) void kfactor_kernel(int k, int G, int kp, int nparts,
                                const double* part, const float* f,
                                double gamma, double rho_b, double* Kw,
                                float* Kinv_out, float* c_out, float* q_out,
                                float* sig_out, float* mbg_out) {
+  extern __shared__ double kf_smem[];
   const int kg = k + G, nk = kg + 1, ne = nk * nk;
+  const bool in_lds = kg <= kKfLds;
   double* Gm = Kw;                   // [nk][nk]
-  double* L = Kw + ne;               // [kg][kg] Cholesky factor
-  double* X = L + kg * kg;           // [kg][kg] inverse
-  double* qv = X + kg * kg;          // [kg]
+  double* L = in_lds ? kf_smem : Kw + ne;                 // [kg][kg] Cholesky factor
+  double* X = in_lds ? kf_smem + kg * kg : L + kg * kg;   // [kg][kg] inverse
+  double* qv = Kw + ne + 2 * kg * kg;                     // [kg]
+  // sum of the row-block partials: batches of 16 independent loads
   for (int e = threadIdx.x; e < ne; e += blockDim.x) {
     double s = 0.0;
-    for (int p = 0; p < nparts; ++p) s += part[(size_t)p * ne + e];
+    int p = 0;
+    for (; p + 16 <= nparts; p += 16) {
+      double b[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) b[u] = part[(size_t)(p + u) * ne + e];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) s += b[u];
+    }
+    for (; p < nparts; ++p) s += part[(size_t)p * ne + e];
     Gm[e] = s;
   }
   __syncthreads();
@@ -134,10 +150,14 @@ __global__ void kfactor_kernel(int k, int G, int kp, int nparts,
     }
     __syncthreads();
   }
-  // inverse: L L^T X = I by right-looking forward and backward sweeps, every
-  // thread updating a slice of the trailing block at each step
+  // inverse: L L^T X = I
   for (int e = threadIdx.x; e < kg * kg; e += blockDim.x) X[e] = (e / kg == e % kg) ? 1.0 : 0.0;
   __syncthreads();
+  if (in_lds) {
+    chol_solve_cols(L, kg, X, kg);               // ends with a barrier
+  } else {
+  // right-looking forward and backward sweeps, every thread updating a
+  // slice of the trailing block at each step
   for (int j = 0; j < kg; ++j) {
     const double djj = L[j * kg + j];
     for (int c = threadIdx.x; c < kg; c += blockDim.x) X[j * kg + c] /= djj;
@@ -157,6 +177,7 @@ __global__ void kfactor_kernel(int k, int G, int kp, int nparts,
       X[i * kg + c] -= L[j * kg + i] * X[j * kg + c];
     }
     __syncthreads();
+  }
   }
   // q = K^-1 c, sigma1 = 1^T Delta^-1 1 - c^T q
   for (int j = threadIdx.x; j < kg; j += blockDim.x) {
@@ -1325,6 +1346,9 @@ hipError_t configure_iter_kernels() {
   if (e != hipSuccess) return e;
   FQP_CFG(1) FQP_CFG(2) FQP_CFG(3) FQP_CFG(4) FQP_CFG(5) FQP_CFG(6)
 #undef FQP_CFG
+  e = hipFuncSetAttribute((const void*)kfactor_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)(2 * sizeof(double) * kKfLds * kKfLds));
+  if (e != hipSuccess) return e;
   return e;
 }
 
@@ -1434,7 +1458,9 @@ hipError_t launch_gram(int n, int kp, int kg, int nparts, int rows_per_blk, cons
 hipError_t launch_kfactor(int k, int G, int kp, int nparts, const double* part, const float* f,
                           double gamma, double rho_b, double* Kw, float* Kinv, float* c,
                           float* q, float* sig, float* mbg, hipStream_t st) {
-  hipLaunchKernelGGL(kfactor_kernel, dim3(1), dim3(256), 0, st, k, G, kp, nparts, part, f,
+  const int kg = k + G;
+  const size_t smem = kg <= kKfLds ? 2 * sizeof(double) * kg * kg : 0;
+  hipLaunchKernelGGL(kfactor_kernel, dim3(1), dim3(1024), smem, st, k, G, kp, nparts, part, f,
                      gamma, rho_b, Kw, Kinv, c, q, sig, mbg);
   return hipGetLastError();
 }
