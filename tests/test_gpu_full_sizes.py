@@ -70,6 +70,22 @@ def test_autotune_picks_a_certifying_schedule():
     assert int((out["status"] == 0).sum().item()) == book.m
 
 
+def test_autotune_confirms_finalists_on_a_second_book():
+    import torch
+    from paper_2606_23367_amd.solver import Solver, to_device
+    from paper_2606_23367_amd.tune import autotune
+    uni, book = make_config("c3", 6, N=2000, M=40, k=16)
+    uni2, book2 = make_config("c3", 7, N=2000, M=40, k=16)
+    P, P2 = to_device(uni, book), to_device(uni2, book2)
+    s = Solver(0)
+    cfg = autotune(P, solver=s, sample=16, second=P2, finalists=2,
+                   grid=dict(rho=(3.0, 8.0, 30.0), alpha=(1.8,), check_every=(50,)))
+    assert cfg["rho"] in (3.0, 8.0, 30.0) and cfg["alpha"] == 1.8
+    out = s.solve(P2, **cfg)
+    torch.cuda.synchronize()
+    assert int((out["status"] == 0).sum().item()) == book2.m
+
+
 @pytest.mark.parametrize("precision", [0, 1])
 def test_precisions_agree(precision):
     """float32 and bf16-split contractions both certify every account and
