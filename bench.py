@@ -166,6 +166,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--plain-sample", type=int, default=16,
                     help="accounts of the one-account-per-call float32 comparison")
+    ap.add_argument("--schedule", default="", metavar="RHO,ALPHA,CHECK",
+                    help="fixed ADMM schedule instead of the autotuner (profiling runs)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run 5 plain device copies of MIB MiB (the "
                          "reference kernel that scales HBM counters)")
@@ -192,11 +194,17 @@ def main():
     from paper_2606_23367_amd.tune import autotune
     solver = Solver(0)
     t_tune = time.perf_counter()
-    tu_uni, tu_book = make_config(WORKLOAD, TUNE_SEED)
-    tu_uni2, tu_book2 = make_config(WORKLOAD, TUNE_SEED2)
-    tuned = autotune(to_device(tu_uni, tu_book, "cuda:0"), solver=solver, sample=TUNE_SAMPLE,
-                     precision=SETTINGS["precision"],
-                     second=to_device(tu_uni2, tu_book2, "cuda:0"))
+    if args.schedule:
+        rho, alpha, ce = args.schedule.split(",")
+        tuned = dict(rho=float(rho), alpha=float(alpha), check_every=int(ce))
+        settings_from = "fixed on the command line"
+    else:
+        tu_uni, tu_book = make_config(WORKLOAD, TUNE_SEED)
+        tu_uni2, tu_book2 = make_config(WORKLOAD, TUNE_SEED2)
+        tuned = autotune(to_device(tu_uni, tu_book, "cuda:0"), solver=solver,
+                         sample=TUNE_SAMPLE, precision=SETTINGS["precision"],
+                         second=to_device(tu_uni2, tu_book2, "cuda:0"))
+        settings_from = None
     t_tune = time.perf_counter() - t_tune
     SETTINGS.update(tuned)
     uni, book = make_config(WORKLOAD, 0)
@@ -245,9 +253,10 @@ def main():
                         "bf16-split MFMA contractions + FP64 polish and "
                         "certification",
             "settings": SETTINGS,
-            "settings_from": f"autotune on {TUNE_SAMPLE} accounts of the seed-{TUNE_SEED} "
-                             f"book of the same shape, finalists confirmed on the "
-                             f"seed-{TUNE_SEED2} book ({t_tune:.1f} s, untimed)",
+            "settings_from": settings_from or (
+                f"autotune on {TUNE_SAMPLE} accounts of the seed-{TUNE_SEED} book of the "
+                f"same shape, finalists confirmed on the seed-{TUNE_SEED2} book "
+                f"({t_tune:.1f} s, untimed)"),
             "accounts": book.m, "assets": uni.n, "factors": uni.k,
             "certified_per_step": solved / args.steps,
             "iter_launches_per_step": launches / args.steps,

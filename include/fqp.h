@@ -126,7 +126,8 @@ typedef struct fqp_settings {
   float alpha;           /* over-relaxation in (0, 2)                     */
   int32_t polish_rounds; /* active-set refinement rounds per polish       */
   int32_t use_graph;     /* capture each block of iterations in a hipGraph */
-  int32_t profile;       /* time every fused iteration launch with events */
+  int32_t profile;       /* time every PROJECT-pass launch with events that
+                            the kernel's own start and end stamp (no graphs) */
   double time_limit_ms;  /* wall-clock limit of the call (<= 0: none)     */
   int32_t precision;     /* fqp_precision of the ADMM contractions        */
 } fqp_settings;
@@ -152,8 +153,8 @@ typedef struct fqp_stats {
   int32_t iter_launches;    /* fused iteration kernel launches              */
   int32_t polish_calls;     /* polish / certification kernel launches       */
   int32_t n_solved;         /* accounts with status SOLVED                  */
-  double iter_kernel_ms;    /* summed event time of fused launches
-                               (settings.profile only, else 0)             */
+  double iter_kernel_ms;    /* summed execution time of the PROJECT-pass
+                               launches (settings.profile only, else 0)    */
   double account_iters;     /* sum over accounts of iterations run          */
   double total_ms;          /* host wall-clock of the call                  */
   size_t workspace_bytes;   /* device workspace held by the handle          */

@@ -29,6 +29,8 @@
 // step on the turnover of the current z (the prox uses the previous value).
 #include <algorithm>
 
+#include <hip/hip_ext.h>
+
 #include "fqp_common.h"
 #include "fqp_kernels.h"
 #include "../../include/fqp.h"
@@ -1306,26 +1308,36 @@ static size_t iter_smem_bf() {
   return sizeof(float) * ((size_t)bf_lds_floats<NCH, MODE>() + 8 * kTM) + 4 * sizeof(int) * kTM;
 }
 
+// with events the launch goes through hipExtLaunchKernelGGL, which stamps
+// them at the kernel's own start and end
+template <typename K>
+static void launch_timed(K kernel, dim3 grid, size_t smem, hipStream_t st, hipEvent_t ev0,
+                         hipEvent_t ev1, const IterArgs& A) {
+  if (ev0 || ev1)
+    hipExtLaunchKernelGGL(kernel, grid, dim3(256), (std::uint32_t)smem, st, ev0, ev1, 0u, A);
+  else
+    hipLaunchKernelGGL(kernel, grid, dim3(256), smem, st, A);
+}
+
 template <int NCH>
 static hipError_t launch_iter_t(const IterArgs& A, int mode, int prec, dim3 grid,
-                                hipStream_t st) {
+                                hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
   if (prec == FQP_PREC_BF16X3 && NCH * 32 <= kMaxKpBf) {
     constexpr int NB = NCH * 32 <= kMaxKpBf ? NCH : 1;   // instantiate narrow widths only
     if (mode == MODE_CONTRACT)
-      hipLaunchKernelGGL((iter_kernel_bf<NB, MODE_CONTRACT>), grid, dim3(256),
-                         (iter_smem_bf<NB, MODE_CONTRACT>()), st, A);
+      launch_timed(iter_kernel_bf<NB, MODE_CONTRACT>, grid, iter_smem_bf<NB, MODE_CONTRACT>(),
+                   st, ev0, ev1, A);
     else
-      hipLaunchKernelGGL((iter_kernel_bf<NB, MODE_PROJECT>), grid, dim3(256),
-                         (iter_smem_bf<NB, MODE_PROJECT>()), st, A);
+      launch_timed(iter_kernel_bf<NB, MODE_PROJECT>, grid, iter_smem_bf<NB, MODE_PROJECT>(),
+                   st, ev0, ev1, A);
     return hipGetLastError();
   }
-  if (mode == MODE_CONTRACT) {
-    hipLaunchKernelGGL((iter_kernel<NCH, MODE_CONTRACT>), grid, dim3(256),
-                       (iter_smem<NCH, MODE_CONTRACT>()), st, A);
-  } else {
-    hipLaunchKernelGGL((iter_kernel<NCH, MODE_PROJECT>), grid, dim3(256),
-                       (iter_smem<NCH, MODE_PROJECT>()), st, A);
-  }
+  if (mode == MODE_CONTRACT)
+    launch_timed(iter_kernel<NCH, MODE_CONTRACT>, grid, iter_smem<NCH, MODE_CONTRACT>(), st,
+                 ev0, ev1, A);
+  else
+    launch_timed(iter_kernel<NCH, MODE_PROJECT>, grid, iter_smem<NCH, MODE_PROJECT>(), st,
+                 ev0, ev1, A);
   return hipGetLastError();
 }
 
@@ -1394,14 +1406,14 @@ int iter_blocks_per_cu(int kp, int prec, int mode) {
 }
 
 hipError_t launch_iter(const IterArgs& A, int kp, int mode, int prec, dim3 grid,
-                       hipStream_t st) {
+                       hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
   switch (kp / 32) {
-    case 1: return launch_iter_t<1>(A, mode, prec, grid, st);
-    case 2: return launch_iter_t<2>(A, mode, prec, grid, st);
-    case 3: return launch_iter_t<3>(A, mode, prec, grid, st);
-    case 4: return launch_iter_t<4>(A, mode, prec, grid, st);
-    case 5: return launch_iter_t<5>(A, mode, prec, grid, st);
-    case 6: return launch_iter_t<6>(A, mode, prec, grid, st);
+    case 1: return launch_iter_t<1>(A, mode, prec, grid, st, ev0, ev1);
+    case 2: return launch_iter_t<2>(A, mode, prec, grid, st, ev0, ev1);
+    case 3: return launch_iter_t<3>(A, mode, prec, grid, st, ev0, ev1);
+    case 4: return launch_iter_t<4>(A, mode, prec, grid, st, ev0, ev1);
+    case 5: return launch_iter_t<5>(A, mode, prec, grid, st, ev0, ev1);
+    case 6: return launch_iter_t<6>(A, mode, prec, grid, st, ev0, ev1);
     default: return hipErrorInvalidValue;
   }
 }

@@ -88,8 +88,10 @@ hipError_t configure_iter_kernels();
 // workgroups of one iteration pass (mode) resident on one compute unit at
 // once; 0 if the runtime cannot tell
 int iter_blocks_per_cu(int kp, int prec, int mode);
+// ev0 / ev1 (optional): events stamped at the start and the end of the
+// kernel's own execution (not of the queue around it)
 hipError_t launch_iter(const IterArgs& A, int kp, int mode, int prec, dim3 grid,
-                       hipStream_t st);
+                       hipStream_t st, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 hipError_t launch_split_bt(int n, int npad, int kp, const float* Bt, uint16_t* bh, uint16_t* bl,
                            uint16_t* bth, uint16_t* btl, hipStream_t st);
 // turnover-cap multiplier search: the register-resident layout needs

@@ -554,10 +554,10 @@ extern "C" fqp_error fqp_solve_batch(fqp_handle* h, const fqp_universe* U, const
     if (e0 != hipSuccess) return e0;
     e0 = launch_ksolve(ka, m, st);
     if (e0 != hipSuccess) return e0;
-    if (S.profile) { e0 = hipEventRecord(evs[2 * c], st); if (e0 != hipSuccess) return e0; }
-    e0 = launch_iter(ia, kp, 1, S.precision, igrid_p, st);
+    // profiling: events stamped by the PROJECT kernel's own start and end
+    e0 = S.profile ? launch_iter(ia, kp, 1, S.precision, igrid_p, st, evs[2 * c], evs[2 * c + 1])
+                   : launch_iter(ia, kp, 1, S.precision, igrid_p, st);
     if (e0 != hipSuccess) return e0;
-    if (S.profile) { e0 = hipEventRecord(evs[2 * c + 1], st); if (e0 != hipSuccess) return e0; }
     if (any_cap) e0 = launch_cap(ia, m, cap_resident, st);
     return e0;
   };
