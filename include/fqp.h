@@ -130,6 +130,9 @@ typedef struct fqp_settings {
                             the kernel's own start and end stamp (no graphs) */
   double time_limit_ms;  /* wall-clock limit of the call (<= 0: none)     */
   int32_t precision;     /* fqp_precision of the ADMM contractions        */
+  int32_t first_check;   /* iteration of the first polish / certification
+                            pass (<= check_every: at check_every); later
+                            passes every check_every iterations           */
 } fqp_settings;
 
 /* Outputs (device pointers, caller-owned).  Any may be NULL except w and

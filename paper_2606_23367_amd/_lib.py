@@ -46,7 +46,8 @@ class Settings(ctypes.Structure):
                 ("rho_band", c_float), ("alpha", c_float),
                 ("polish_rounds", c_int32),
                 ("use_graph", c_int32), ("profile", c_int32),
-                ("time_limit_ms", c_double), ("precision", c_int32)]
+                ("time_limit_ms", c_double), ("precision", c_int32),
+                ("first_check", c_int32)]
 
 
 class Result(ctypes.Structure):

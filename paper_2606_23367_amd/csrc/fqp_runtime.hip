@@ -175,6 +175,7 @@ void fqp_default_settings(fqp_settings* s) {
   s->profile = 0;
   s->time_limit_ms = 0.0;
   s->precision = FQP_PREC_BF16X3;
+  s->first_check = 0;
 }
 
 const char* fqp_error_string(int e) {
@@ -618,6 +619,8 @@ extern "C" fqp_error fqp_solve_batch(fqp_handle* h, const fqp_universe* U, const
     fqp_error be = run_block(count);
     if (be != FQP_OK) return be;
     done_iters += count;
+    // no pass before first_check (blocks stay whole, so graph replays too)
+    if (done_iters < S.first_check && done_iters < S.max_iter) continue;
     // polish + certification rounds on z = prox(v; lam*)
     HIP_CHECK(launch_materialize_z(ia, m, z, st));
     pa.nf_gate = std::max(4 * k + 64, n / 8 + 4 * k);
