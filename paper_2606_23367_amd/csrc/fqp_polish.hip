@@ -766,65 +766,96 @@ __global__ __launch_bounds__(kPTC) void polish_sums_kernel(PolishArgs A, int fin
 // (row block, account) workgroups; per block: max |gamma Sigma w|, max |mu|,
 // turnover and a non-finite flag
 // ---------------------------------------------------------------------------
-constexpr int kGbRows = 256;              // rows per gbase workgroup
+constexpr int kGbRows = 256;              // rows per gbase workgroup (one per thread)
+constexpr int kGbAcc = 16;                // accounts per gbase workgroup
 
+// g_i = gamma (d_i w_i + b_i . y) - mu_i for kGbRows rows x kGbAcc accounts:
+// each thread streams its row of B once (four columns at a time) against
+// the accounts' y vectors (LDS broadcasts), so the universe block is read
+// once per 16 accounts; per-(account, row block) maxima / sums go to gpart
 __global__ __launch_bounds__(256) void polish_gbase_kernel(PolishArgs A, int final_pass) {
-  __shared__ double s_y[kMaxK];
-  __shared__ double s_red[4][4];
-  const int k = A.k, n = A.n;
-  const int slot = blockIdx.y;
-  if (slot >= *A.m_act) return;
-  const int a = A.act[slot];
-  const int* ps = A.pstate + (size_t)a * kPStateStride;
-  if (ps[PS_DONE] || (ps[PS_STALL] && !final_pass)) return;
-  const int tid = threadIdx.x;
-  const Wk wk = wk_of(A, a);
-  for (int j = tid; j < k; j += 256) s_y[j] = wk.yF[j];
-  __syncthreads();
-  const double gam = A.par[(size_t)a * kNPar + P_GAMMA];
-  const double* w = A.wout + (size_t)a * n;
-  double* gb = A.gbase + (size_t)a * n;
-  double gmax = 0.0, mumax = 0.0, turn = 0.0, bad = 0.0;
-  const int q4 = tid & 3;
-  const int r_begin = blockIdx.x * kGbRows;
-  // four lanes per row split b_i . y; a wave covers 16 consecutive rows
-#pragma unroll
-  for (int it = 0; it < kGbRows / 64; ++it) {
-    const int i = r_begin + it * 64 + (tid >> 2);
-    double sig = 0.0;
-    if (i < n) {
-      const float* brow = A.Bt + (size_t)i * A.kp;
-      for (int j = q4; j < k; j += 4) sig += (double)brow[j] * s_y[j];
+  __shared__ double s_y[kGbAcc][kMaxK + 4];
+  __shared__ int s_a[kGbAcc];
+  __shared__ double s_gam[kGbAcc];
+  __shared__ double s_red[4][kGbAcc][4];
+  const int k = A.k, n = A.n, tid = threadIdx.x;
+  const int m_act = *A.m_act;
+  const int g0 = blockIdx.y * kGbAcc;
+  if (g0 >= m_act) return;
+  if (tid < kGbAcc) {
+    int a = -1;
+    if (g0 + tid < m_act) {
+      const int aa = A.act[g0 + tid];
+      const int* ps = A.pstate + (size_t)aa * kPStateStride;
+      if (!(ps[PS_DONE] || (ps[PS_STALL] && !final_pass))) a = aa;
     }
-    sig += __shfl_xor(sig, 1, 64);
-    sig += __shfl_xor(sig, 2, 64);
-    if (i < n && q4 == 0) {
-      sig += (double)A.d[i] * w[i];
+    s_a[tid] = a;
+    s_gam[tid] = a >= 0 ? (double)A.par[(size_t)a * kNPar + P_GAMMA] : 0.0;
+  }
+  __syncthreads();
+  const int k4 = (k + 3) & ~3;                 // <= kp: whole float4 of each row
+  for (int e = tid; e < kGbAcc * k4; e += 256) {
+    const int q = e / k4, j = e % k4;
+    const int a = s_a[q];
+    s_y[q][j] = (a >= 0 && j < k) ? wk_of(A, a).yF[j] : 0.0;
+  }
+  __syncthreads();
+  const int i = blockIdx.x * kGbRows + tid;
+  const bool row_ok = i < n;
+  double sig[kGbAcc];
+#pragma unroll
+  for (int q = 0; q < kGbAcc; ++q) sig[q] = 0.0;
+  if (row_ok) {
+    const float4* brow = reinterpret_cast<const float4*>(A.Bt + (size_t)i * A.kp);
+    for (int j4 = 0; j4 < k4 / 4; ++j4) {
+      const float4 b = brow[j4];
+      const double b0 = b.x, b1 = b.y, b2 = b.z, b3 = b.w;
+#pragma unroll
+      for (int q = 0; q < kGbAcc; ++q) {
+        const double* y = &s_y[q][4 * j4];
+        sig[q] += b0 * y[0] + b1 * y[1] + b2 * y[2] + b3 * y[3];
+      }
+    }
+  }
+  const double di = row_ok ? (double)A.d[i] : 0.0;
+  const int wv = tid >> 6;
+#pragma unroll
+  for (int q = 0; q < kGbAcc; ++q) {
+    const int a = s_a[q];
+    if (a < 0) continue;                       // uniform
+    double gmax = 0.0, mumax = 0.0, turn = 0.0, bad = 0.0;
+    if (row_ok) {
+      const double wi = A.wout[(size_t)a * n + i];
+      const double sg = sig[q] + di * wi;
       const double mui = A.mu[(size_t)a * n + i];
-      const double v = gam * sig - mui;
-      gb[i] = v;
-      gmax = fmax(gmax, fabs(gam * sig));
-      mumax = fmax(mumax, fabs(mui));
-      turn += fabs(w[i] - (double)row_data(A, a, i).w0);
-      if (!isfinite(v) || !isfinite(w[i])) bad = 1.0;
+      const double v = s_gam[q] * sg - mui;
+      A.gbase[(size_t)a * n + i] = v;
+      gmax = fabs(s_gam[q] * sg);
+      mumax = fabs(mui);
+      turn = fabs(wi - (double)row_data(A, a, i).w0);
+      if (!isfinite(v) || !isfinite(wi)) bad = 1.0;
+    }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+      gmax = fmax(gmax, __shfl_xor(gmax, o, 64));
+      mumax = fmax(mumax, __shfl_xor(mumax, o, 64));
+      turn += __shfl_xor(turn, o, 64);
+      bad = fmax(bad, __shfl_xor(bad, o, 64));
+    }
+    if ((tid & 63) == 0) {
+      s_red[wv][q][0] = gmax; s_red[wv][q][1] = mumax;
+      s_red[wv][q][2] = turn; s_red[wv][q][3] = bad;
     }
   }
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) {
-    gmax = fmax(gmax, __shfl_xor(gmax, o, 64));
-    mumax = fmax(mumax, __shfl_xor(mumax, o, 64));
-    turn += __shfl_xor(turn, o, 64);
-    bad = fmax(bad, __shfl_xor(bad, o, 64));
-  }
-  if ((tid & 63) == 0) {
-    s_red[tid >> 6][0] = gmax; s_red[tid >> 6][1] = mumax;
-    s_red[tid >> 6][2] = turn; s_red[tid >> 6][3] = bad;
-  }
   __syncthreads();
-  if (tid < 4) {
-    double v = s_red[0][tid];
-    for (int q = 1; q < 4; ++q) v = (tid == 2) ? v + s_red[q][tid] : fmax(v, s_red[q][tid]);
-    A.gpart[((size_t)a * A.n_rb + blockIdx.x) * 4 + tid] = v;
+  if (tid < 4 * kGbAcc) {
+    const int q = tid >> 2, c = tid & 3;
+    const int a = s_a[q];
+    if (a >= 0) {
+      double v = s_red[0][q][c];
+      for (int w = 1; w < 4; ++w) v = (c == 2) ? v + s_red[w][q][c] : fmax(v, s_red[w][q][c]);
+      A.gpart[((size_t)a * A.n_rb + blockIdx.x) * 4 + c] = v;
+    }
   }
 }
 
@@ -1196,8 +1227,8 @@ hipError_t launch_polish_check_r(const PolishArgs& A, const fqp_result& R, int f
   hipLaunchKernelGGL(polish_sums_kernel, dim3(A.m_total), dim3(kPTC), smem, st, A, final_pass);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(polish_gbase_kernel, dim3(A.n_rb, A.m_total), dim3(256), 0, st, A,
-                     final_pass);
+  hipLaunchKernelGGL(polish_gbase_kernel, dim3(A.n_rb, (A.m_total + kGbAcc - 1) / kGbAcc),
+                     dim3(256), 0, st, A, final_pass);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(polish_check_kernel, dim3(A.m_total), dim3(kPTC), 0, st, A, R, final_pass);
