@@ -166,7 +166,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--plain-sample", type=int, default=16,
                     help="accounts of the one-account-per-call float32 comparison")
-    ap.add_argument("--schedule", default="", metavar="RHO,ALPHA,CHECK",
+    ap.add_argument("--schedule", default="", metavar="RHO,ALPHA,CHECK[,FIRST]",
                     help="fixed ADMM schedule instead of the autotuner (profiling runs)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run 5 plain device copies of MIB MiB (the "
@@ -195,8 +195,9 @@ def main():
     solver = Solver(0)
     t_tune = time.perf_counter()
     if args.schedule:
-        rho, alpha, ce = args.schedule.split(",")
-        tuned = dict(rho=float(rho), alpha=float(alpha), check_every=int(ce))
+        parts = args.schedule.split(",")
+        tuned = dict(rho=float(parts[0]), alpha=float(parts[1]), check_every=int(parts[2]),
+                     first_check=int(parts[3]) if len(parts) > 3 else 0)
         settings_from = "fixed on the command line"
     else:
         tu_uni, tu_book = make_config(WORKLOAD, TUNE_SEED)

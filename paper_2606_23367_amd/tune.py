@@ -1,10 +1,12 @@
-"""Autotuner of the ADMM schedule: penalty rho, over-relaxation alpha and
-the certification interval check_every.
+"""Autotuner of the ADMM schedule: penalty rho, over-relaxation alpha, the
+certification interval check_every and the delay of the first
+certification pass (first_check = a multiple of check_every).
 
 The right penalty depends on the scale of the book (box width, return
 spread, risk aversion) and the interval trades polish attempts against
-iterations, so both are picked by timing solves of a sample of accounts
-over a small grid.  The winner certifies the most sampled accounts, then
+iterations (an early pass over a full batch costs a float64 polish of every
+account and certifies few of them), so all are picked by timing solves of a
+sample of accounts over a small grid.  The winner certifies the most sampled accounts, then
 takes the least time.  The wall time of a batch is set by its slowest
 accounts, which makes single timings of nearby settings noisy; with a
 second book of the same shape the best few settings are timed again on it
@@ -25,7 +27,7 @@ import torch
 from .solver import DeviceProblem, Solver, subset
 
 DEFAULT_GRID = dict(rho=(1.0, 3.0, 6.0, 8.0, 10.0, 14.0, 30.0), alpha=(1.6, 1.8),
-                    check_every=(50, 100))
+                    check_every=(50, 100), first_mult=(1, 2))
 
 _CACHE: dict = {}
 
@@ -52,8 +54,8 @@ def autotune(P: DeviceProblem, solver: Optional[Solver] = None, sample: int = 64
              grid: Optional[dict] = None, precision: int = 1,
              cache_path: Optional[str] = None, verbose: bool = False,
              second: Optional[DeviceProblem] = None, finalists: int = 3) -> dict:
-    """Settings dict {rho, alpha, check_every, precision} for books shaped
-    like P, from timed solves of its first ``sample`` accounts (and of the
+    """Settings dict {rho, alpha, check_every, first_check, precision} for
+    books shaped like P, from timed solves of its first ``sample`` accounts (and of the
     first ``sample`` accounts of ``second`` for the best ``finalists``)."""
     key = shape_key(P, precision)
     if key in _CACHE:
@@ -69,8 +71,10 @@ def autotune(P: DeviceProblem, solver: Optional[Solver] = None, sample: int = 64
     Q = subset(P, range(min(sample, P.m)))
     s.solve(Q, precision=precision)                       # warm-up: workspace, code
     ranked = []
-    for rho, alpha, ce in itertools.product(grid["rho"], grid["alpha"], grid["check_every"]):
-        cfg = dict(rho=float(rho), alpha=float(alpha), check_every=int(ce), precision=precision)
+    for rho, alpha, ce, fm in itertools.product(grid["rho"], grid["alpha"], grid["check_every"],
+                                                grid.get("first_mult", (1,))):
+        cfg = dict(rho=float(rho), alpha=float(alpha), check_every=int(ce),
+                   first_check=int(fm) * int(ce), precision=precision)
         ok, dt = _timed(s, Q, cfg)
         if verbose:
             print(f"autotune {cfg}: {ok}/{Q.m} certified, {dt * 1e3:.1f} ms", flush=True)
