@@ -1138,12 +1138,16 @@ __global__ __launch_bounds__(256) void materialize_z_kernel(IterArgs A, float* z
 // ---------------------------------------------------------------------------
 // per-account factor-space solve
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void ksolve_kernel(KArgs A) {
-  __shared__ double t[kMaxKp], rhs[kMaxKp], red[256];
-  __shared__ float tsp[256];                // split partial sums
+// threads per account: at kp = 96, five threads per factor column, so that
+// each thread's partial sums (up to 79 row tiles) and K^-1 rows come in one
+// batch of loads each
+constexpr int kKsT = 512;
+__global__ __launch_bounds__(kKsT) void ksolve_kernel(KArgs A) {
+  __shared__ double t[kMaxKp], rhs[kMaxKp], red[kKsT];
+  __shared__ float tsp[kKsT];                // split partial sums
   __shared__ float pprime[kMaxKp];
   __shared__ double s_nu;
-  __shared__ float sst[4];             // per-wave max of the primal residual
+  __shared__ float sst[kKsT / 64];     // per-wave max of the primal residual
   const int slot = blockIdx.x;
   if (slot >= *A.m_act) return;
   const int a = A.act[slot];
@@ -1162,7 +1166,7 @@ __global__ __launch_bounds__(256) void ksolve_kernel(KArgs A) {
 
   // nsp threads per factor column split the row tiles (and below the
   // K^-1 rows), so that more independent loads are in flight
-  const int nsp = kp <= 256 ? 256 / kp : 1;
+  const int nsp = kp <= kKsT ? kKsT / kp : 1;
   if (tid < nsp * kp) {
     const int j = tid % kp, q = tid / kp;
     // batches of 16 loads issued before any is added
@@ -1180,7 +1184,7 @@ __global__ __launch_bounds__(256) void ksolve_kernel(KArgs A) {
     tsp[tid] = s;
   }
   __syncthreads();
-  for (int j = tid; j < kp; j += 256) {
+  for (int j = tid; j < kp; j += kKsT) {
     float s = 0.f;
     for (int q = 0; q < nsp; ++q) s += tsp[q * kp + j];
     t[j] = s;
@@ -1189,7 +1193,7 @@ __global__ __launch_bounds__(256) void ksolve_kernel(KArgs A) {
     // max over the row tiles of the primal residual estimate, one row tile
     // per thread
     float v = 0.f;
-    for (int rt = tid; rt < n_rt_p; rt += 256)
+    for (int rt = tid; rt < n_rt_p; rt += kKsT)
       v = fmaxf(v, A.stat[((size_t)rt * M + a) * kNStat + ST_RPRIM]);
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
@@ -1202,7 +1206,7 @@ __global__ __launch_bounds__(256) void ksolve_kernel(KArgs A) {
     const float* mbg = A.mbg + (size_t)cls * kp * G;
     const float* zb = A.zb + (size_t)a * G;
     const float* vb = A.vb + (size_t)a * G;
-    for (int j = tid; j < kg; j += 256) {
+    for (int j = tid; j < kg; j += kKsT) {
       double s = 0.0;
       for (int g = 0; g < G; ++g) s += (double)mbg[j * G + g] * rhob * ((double)zb[g] - vb[g]);
       rhs[j] = s;
@@ -1211,20 +1215,24 @@ __global__ __launch_bounds__(256) void ksolve_kernel(KArgs A) {
     double cs = 0.0;
     for (int g = 0; g < G; ++g) cs += (double)cv[k + g] * rhob * ((double)zb[g] - vb[g]);
     s0 += cs;
-    for (int j = tid; j < kg; j += 256) t[j] += rhs[j];
+    for (int j = tid; j < kg; j += kKsT) t[j] += rhs[j];
     __syncthreads();
   }
   // nu = (1 - s0 + q^T t) / sigma1
   double part = 0.0;
-  for (int j = tid; j < kg; j += 256) part += (double)qv[j] * t[j];
+  for (int j = tid; j < kg; j += kKsT) part += (double)qv[j] * t[j];
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) part += __shfl_xor(part, o, 64);
   if ((tid & 63) == 0) red[tid >> 6] = part;
   __syncthreads();
-  if (tid == 0) s_nu = (1.0 - s0 + ((red[0] + red[1]) + (red[2] + red[3]))) / (double)sig1;
+  if (tid == 0) {
+    double qt = 0.0;
+    for (int q = 0; q < kKsT / 64; ++q) qt += red[q];
+    s_nu = (1.0 - s0 + qt) / (double)sig1;
+  }
   __syncthreads();
   const double nu = s_nu;
-  for (int j = tid; j < kg; j += 256) rhs[j] = t[j] + nu * (double)cv[j];
+  for (int j = tid; j < kg; j += kKsT) rhs[j] = t[j] + nu * (double)cv[j];
   __syncthreads();
   __syncthreads();
   if (tid < nsp * kp) {
@@ -1250,7 +1258,7 @@ __global__ __launch_bounds__(256) void ksolve_kernel(KArgs A) {
     red[tid] = s;
   }
   __syncthreads();
-  for (int j = tid; j < kp; j += 256) {
+  for (int j = tid; j < kp; j += kKsT) {
     double s = 0.0;
     for (int q = 0; q < nsp; ++q) s += red[q * kp + j];
     pprime[j] = (float)s;
@@ -1258,7 +1266,7 @@ __global__ __launch_bounds__(256) void ksolve_kernel(KArgs A) {
   __syncthreads();
   // back-projection coefficients: band directions carry -rho_b (zb - vb)
   float* pp = A.pp + (size_t)a * kp;
-  for (int j = tid; j < kp; j += 256) {
+  for (int j = tid; j < kp; j += kKsT) {
     float v = 0.f;
     if (j < k) v = pprime[j];
     else if (j < kg) v = pprime[j] - rhob * (A.zb[(size_t)a * G + (j - k)] - A.vb[(size_t)a * G + (j - k)]);
@@ -1285,7 +1293,9 @@ __global__ __launch_bounds__(256) void ksolve_kernel(KArgs A) {
   for (int o = 32; o >= 1; o >>= 1) band_res = fmaxf(band_res, __shfl_xor(band_res, o, 64));
   if (tid == 0) {
     par[P_NU] = (float)nu;
-    A.res[(size_t)a * 4 + 0] = fmaxf(fmaxf(fmaxf(sst[0], sst[1]), fmaxf(sst[2], sst[3])), band_res);
+    float rp = band_res;
+    for (int q = 0; q < kKsT / 64; ++q) rp = fmaxf(rp, sst[q]);
+    A.res[(size_t)a * 4 + 0] = rp;
     A.iters[a] += 1;
   }
 }
@@ -1437,7 +1447,7 @@ hipError_t launch_materialize_z(const IterArgs& A, int m_total, float* z, hipStr
 }
 
 hipError_t launch_ksolve(const KArgs& A, int m_total, hipStream_t st) {
-  hipLaunchKernelGGL(ksolve_kernel, dim3(m_total), dim3(256), 0, st, A);
+  hipLaunchKernelGGL(ksolve_kernel, dim3(m_total), dim3(kKsT), 0, st, A);
   return hipGetLastError();
 }
 
