@@ -934,14 +934,14 @@ __global__ __launch_bounds__(kCapT, 8) void cap_kernel(IterArgs A) {
   const float* va = A.v + (size_t)a * n;
   const size_t wa = (size_t)a * A.W;
   float vr[kCapQ];
-  // four groups of loads in flight at a time (register budget)
+  // every load of the account issued before any is used
 #pragma unroll
-  for (int h2 = 0; h2 < 4; ++h2) {
-    float x[kCapQ / 4];
-    uint32_t ew[kCapQ / 4], hw[kCapQ / 4];
+  for (int h2 = 0; h2 < 1; ++h2) {
+    float x[kCapQ / 1];
+    uint32_t ew[kCapQ / 1], hw[kCapQ / 1];
 #pragma unroll
-    for (int q = 0; q < kCapQ / 4; ++q) {
-      const int i = (h2 * (kCapQ / 4) + q) * kCapT + tid;
+    for (int q = 0; q < kCapQ / 1; ++q) {
+      const int i = (h2 * (kCapQ / 1) + q) * kCapT + tid;
       x[q] = 0.f; ew[q] = 0u; hw[q] = 0u;
       if (i < n) {
         ew[q] = A.elig ? A.elig[wa + (i >> 5)] : 0xffffffffu;
@@ -950,8 +950,8 @@ __global__ __launch_bounds__(kCapT, 8) void cap_kernel(IterArgs A) {
       }
     }
 #pragma unroll
-    for (int q = 0; q < kCapQ / 4; ++q) {
-      const int i = (h2 * (kCapQ / 4) + q) * kCapT + tid;
+    for (int q = 0; q < kCapQ / 1; ++q) {
+      const int i = (h2 * (kCapQ / 1) + q) * kCapT + tid;
       const int b = i & 31;
       const bool el = (ew[q] >> b) & 1u;
       float keep = el ? x[q] : 0.f;
@@ -961,7 +961,7 @@ __global__ __launch_bounds__(kCapT, 8) void cap_kernel(IterArgs A) {
         s_hel[j] = el ? 1 : 0;
         keep = 0.f;
       }
-      vr[h2 * (kCapQ / 4) + q] = keep;
+      vr[h2 * (kCapQ / 1) + q] = keep;
     }
   }
   __syncthreads();
