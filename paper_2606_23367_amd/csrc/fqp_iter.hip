@@ -935,13 +935,12 @@ __global__ __launch_bounds__(kCapT, 8) void cap_kernel(IterArgs A) {
   const size_t wa = (size_t)a * A.W;
   float vr[kCapQ];
   // every load of the account issued before any is used
+  {
+    float x[kCapQ];
+    uint32_t ew[kCapQ], hw[kCapQ];
 #pragma unroll
-  for (int h2 = 0; h2 < 1; ++h2) {
-    float x[kCapQ / 1];
-    uint32_t ew[kCapQ / 1], hw[kCapQ / 1];
-#pragma unroll
-    for (int q = 0; q < kCapQ / 1; ++q) {
-      const int i = (h2 * (kCapQ / 1) + q) * kCapT + tid;
+    for (int q = 0; q < kCapQ; ++q) {
+      const int i = q * kCapT + tid;
       x[q] = 0.f; ew[q] = 0u; hw[q] = 0u;
       if (i < n) {
         ew[q] = A.elig ? A.elig[wa + (i >> 5)] : 0xffffffffu;
@@ -950,8 +949,8 @@ __global__ __launch_bounds__(kCapT, 8) void cap_kernel(IterArgs A) {
       }
     }
 #pragma unroll
-    for (int q = 0; q < kCapQ / 1; ++q) {
-      const int i = (h2 * (kCapQ / 1) + q) * kCapT + tid;
+    for (int q = 0; q < kCapQ; ++q) {
+      const int i = q * kCapT + tid;
       const int b = i & 31;
       const bool el = (ew[q] >> b) & 1u;
       float keep = el ? x[q] : 0.f;
@@ -961,7 +960,7 @@ __global__ __launch_bounds__(kCapT, 8) void cap_kernel(IterArgs A) {
         s_hel[j] = el ? 1 : 0;
         keep = 0.f;
       }
-      vr[h2 * (kCapQ / 1) + q] = keep;
+      vr[q] = keep;
     }
   }
   __syncthreads();
