@@ -641,12 +641,26 @@ __global__ __launch_bounds__(256, 3) void iter_kernel_bf(IterArgs A) {
     const bool row_ok = row < n;
     const float d_i = row_ok ? A.d[row] : 1.f;
 
-    float mu_r[16], v_r[16];
+    float mu_r[16], v_r[16], z_r[16];
     const int wd = row >> 5, b = row & 31;
     // bit r: slot r holds an account and a row inside the book / the row is
     // eligible / the row is held
     unsigned ok_bits = 0u, el_bits = 0u, held_bits = 0u;
-    {
+    if (MODE == MODE_PROJECT) {
+      // z of this v comes from the CONTRACT pass: no row data needed here
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int m = 8 * (r >> 2) + 4 * hi + (r & 3);
+        mu_r[r] = 0.f; v_r[r] = 0.f; z_r[r] = 0.f;
+        if (Aid[m] >= 0 && row_ok) {
+          const unsigned off = (unsigned)(Ao[m] + row);
+          mu_r[r] = A.mu[off];
+          v_r[r] = A.v[off];
+          z_r[r] = A.zs[off];
+          ok_bits |= 1u << r;
+        }
+      }
+    } else {
       // the 32 rows of a half-wave share one eligibility, holding and
       // holding-prefix word per account: lane j < 16 of the half loads the
       // first two for slot j, lane 16 + j the third; the others read them
@@ -724,9 +738,29 @@ __global__ __launch_bounds__(256, 3) void iter_kernel_bf(IterArgs A) {
       }
     }
 
+    if (MODE == MODE_PROJECT) {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int m = 8 * (r >> 2) + 4 * hi + (r & 3);
+        if ((ok_bits >> r) & 1u) {
+          const float4 q0 = Acc[2 * m], q1 = Acc[2 * m + 1];
+          const float rho = q0.x;
+          const float iDelta = __builtin_amdgcn_rcpf(q0.z * d_i + rho);
+          const unsigned off = (unsigned)(Ao[m] + row);
+          const float vv = v_r[r], z = z_r[r];
+          const float u = vv - z;
+          const float r0v = mu_r[r] + rho * (z - u);
+          const float x = (r0v + q1.z - X[r]) * iDelta;
+          const float alpha = q1.w;
+          A.v[off] = alpha * x + (1.f - alpha) * z + u;
+          st_rp[r] = fmaxf(st_rp[r], fabsf(x - z));
+        }
+      }
+    }
+
     unsigned hbase = 0u;
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
+    for (int r = 0; r < (MODE == MODE_CONTRACT ? 16 : 0); ++r) {
       const int m = 8 * (r >> 2) + 4 * hi + (r & 3);
       const bool held = (held_bits >> r) & 1u;
       const unsigned long long hm = __ballot(held);
@@ -763,15 +797,8 @@ __global__ __launch_bounds__(256, 3) void iter_kernel_bf(IterArgs A) {
         const float vv = v_r[r];
         const float z = prox_row(ri, vv, q0.w, irho, nullptr);
         const float u = vv - z;
-        const float r0v = mu_r[r] + rho * (z - u);
-        if (MODE == MODE_CONTRACT) {
-          Rp = r0v * iDelta;
-        } else {
-          const float x = (r0v + q1.z - X[r]) * iDelta;
-          const float alpha = q1.w;
-          A.v[off] = alpha * x + (1.f - alpha) * z + u;
-          st_rp[r] = fmaxf(st_rp[r], fabsf(x - z));
-        }
+        Rp = (mu_r[r] + rho * (z - u)) * iDelta;
+        A.zs[off] = z;                   // for the PROJECT pass
       }
       if (MODE == MODE_CONTRACT) {
         __bf16 h, l;

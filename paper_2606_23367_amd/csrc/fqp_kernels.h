@@ -35,6 +35,8 @@ struct IterArgs {
   float* par_rw;             // same array, written by the cap kernel
   float* part;               // [row tiles][m][kp] (at most one per 128-row chunk)
   float* stat;               // [row tiles][m][kNStat]
+  float* zs;                 // [m][n] z = prox(v; lam*) of the current v: the
+                             // bf16-split CONTRACT pass writes it, PROJECT reads it
 };
 
 struct KArgs {

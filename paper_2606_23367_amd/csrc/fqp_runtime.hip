@@ -492,7 +492,7 @@ extern "C" fqp_error fqp_solve_batch(fqp_handle* h, const fqp_universe* U, const
   ia.hold_ptr = hold_ptr; ia.hold_w0 = hold_w0; ia.hold_tax = hold_tax;
   ia.tax_brk = P->tax_brk; ia.tax_slope = P->tax_slope; ia.pp = pp; ia.par = par;
   ia.par_rw = par;
-  ia.part = part; ia.stat = stat;
+  ia.part = part; ia.stat = stat; ia.zs = z;
   ia.npad = npad; ia.bt_hi = bt_hi; ia.bt_lo = bt_lo; ia.btt_hi = btt_hi; ia.btt_lo = btt_lo;
   KArgs ka{};
   ka.kp = kp; ka.k = k; ka.G = G; ka.n = n; ka.nblk = n_rt * acc_tiles; ka.m_total = m;
