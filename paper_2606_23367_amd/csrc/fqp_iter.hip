@@ -266,28 +266,6 @@ __device__ __forceinline__ RowInfo row_info_w(const Args& A, int row, float lbp,
   return ri;
 }
 
-// the same with the holding prefix word loaded only for a held row
-template <typename Args>
-__device__ __forceinline__ RowInfo row_info_l(const Args& A, int row, float lbp, float ubp,
-                                              uint32_t ew, uint32_t hw, unsigned wi, int hptr) {
-  RowInfo ri;
-  const int b = row & 31;
-  const bool el = (ew >> b) & 1u;
-  ri.lb = el ? lbp : 0.f;
-  ri.ub = el ? ubp : 0.f;
-  ri.w0 = 0.f;
-  ri.taxed = false;
-  if ((hw >> b) & 1u) {
-    const int idx = hptr + A.hold_pre[wi] + popc_below(hw, b);
-    const float4 r0 = A.hold_rec[2 * idx], r1 = A.hold_rec[2 * idx + 1];
-    ri.w0 = r0.x;
-    ri.taxed = r0.y > 0.f;
-    ri.t.b1 = r0.y; ri.t.b2 = r0.z; ri.t.b3 = r0.w;
-    ri.t.s0 = r1.x; ri.t.s1 = r1.y; ri.t.s2 = r1.z; ri.t.s3 = r1.w;
-  }
-  return ri;
-}
-
 template <typename Args>
 __device__ __forceinline__ RowInfo row_info(const Args& A, int a, int row, float lbp, float ubp) {
   const size_t wi = (size_t)a * A.W + (row >> 5);
