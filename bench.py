@@ -29,11 +29,11 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 WORKLOAD = "c3"
-# the ADMM schedule (rho, alpha, check_every) is picked by the autotuner on
-# the books of two other seeds of the same shape (grid on the first, the
-# finalists confirmed on the second); bf16-split contractions (the library
-# default)
-TUNE_SEED, TUNE_SEED2, TUNE_SAMPLE = 1, 2, 500
+# the ADMM schedule (rho, alpha, check_every, first_check) is picked by the
+# autotuner on the books of other seeds of the same shape (grid on the
+# first, the finalists confirmed on three more); bf16-split contractions
+# (the library default)
+TUNE_SEED, TUNE_SEEDS2, TUNE_SAMPLE = 1, (2, 3, 4), 500
 SETTINGS = dict(precision=1)
 
 
@@ -206,10 +206,10 @@ def main():
         settings_from = "fixed on the command line"
     else:
         tu_uni, tu_book = make_config(WORKLOAD, TUNE_SEED)
-        tu_uni2, tu_book2 = make_config(WORKLOAD, TUNE_SEED2)
+        others = [to_device(*make_config(WORKLOAD, sd), "cuda:0") for sd in TUNE_SEEDS2]
         tuned = autotune(to_device(tu_uni, tu_book, "cuda:0"), solver=solver,
-                         sample=TUNE_SAMPLE, precision=SETTINGS["precision"],
-                         second=to_device(tu_uni2, tu_book2, "cuda:0"))
+                         sample=TUNE_SAMPLE, precision=SETTINGS["precision"], second=others)
+        del others
         settings_from = None
     t_tune = time.perf_counter() - t_tune
     SETTINGS.update(tuned)
@@ -261,8 +261,8 @@ def main():
             "settings": SETTINGS,
             "settings_from": settings_from or (
                 f"autotune on {TUNE_SAMPLE} accounts of the seed-{TUNE_SEED} book of the "
-                f"same shape, finalists confirmed on the seed-{TUNE_SEED2} book "
-                f"({t_tune:.1f} s, untimed)"),
+                f"same shape, finalists confirmed on the books of seeds "
+                f"{', '.join(str(x) for x in TUNE_SEEDS2)} ({t_tune:.1f} s, untimed)"),
             "accounts": book.m, "assets": uni.n, "factors": uni.k,
             "certified_per_step": solved / args.steps,
             "iter_launches_per_step": launches / args.steps,

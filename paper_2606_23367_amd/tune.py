@@ -8,9 +8,9 @@ iterations (an early pass over a full batch costs a float64 polish of every
 account and certifies few of them), so all are picked by timing solves of a
 sample of accounts over a small grid.  The winner certifies the most sampled accounts, then
 takes the least time.  The wall time of a batch is set by its slowest
-accounts, which makes single timings of nearby settings noisy; with a
-second book of the same shape the best few settings are timed again on it
-and ranked by the two books together.  Results are cached per book shape
+accounts, which makes single timings of nearby settings noisy; with more
+books of the same shape the best few settings are timed again on them and
+ranked by all books together.  Results are cached per book shape
 (in memory, and in a JSON file when a path is given); tune on accounts
 that are not the ones being timed.
 """
@@ -20,7 +20,7 @@ import itertools
 import json
 import os
 import time
-from typing import Optional
+from typing import Optional, Sequence, Union
 
 import torch
 
@@ -53,10 +53,11 @@ def _timed(s: Solver, Q: DeviceProblem, cfg: dict):
 def autotune(P: DeviceProblem, solver: Optional[Solver] = None, sample: int = 64,
              grid: Optional[dict] = None, precision: int = 1,
              cache_path: Optional[str] = None, verbose: bool = False,
-             second: Optional[DeviceProblem] = None, finalists: int = 3) -> dict:
+             second: Union[DeviceProblem, Sequence[DeviceProblem], None] = None,
+             finalists: int = 3) -> dict:
     """Settings dict {rho, alpha, check_every, first_check, precision} for
     books shaped like P, from timed solves of its first ``sample`` accounts (and of the
-    first ``sample`` accounts of ``second`` for the best ``finalists``)."""
+    first ``sample`` accounts of each book in ``second`` for the best ``finalists``)."""
     key = shape_key(P, precision)
     if key in _CACHE:
         return dict(_CACHE[key])
@@ -81,18 +82,22 @@ def autotune(P: DeviceProblem, solver: Optional[Solver] = None, sample: int = 64
         ranked.append(((-ok, dt), cfg))
     ranked.sort(key=lambda r: r[0])
     best = ranked[0]
-    if second is not None and finalists > 1:
-        Q2 = subset(second, range(min(sample, second.m)))
-        s.solve(Q2, precision=precision)                  # warm-up
-        both = []
-        for (score, cfg) in ranked[:finalists]:
-            ok2, dt2 = _timed(s, Q2, cfg)
-            if verbose:
-                print(f"autotune second book {cfg}: {ok2}/{Q2.m} certified, "
-                      f"{dt2 * 1e3:.1f} ms", flush=True)
-            both.append(((score[0] - ok2, score[1] + dt2), cfg))
-        both.sort(key=lambda r: r[0])
-        best = both[0]
+    others = [] if second is None else (
+        [second] if isinstance(second, DeviceProblem) else list(second))
+    if others and finalists > 1:
+        fin = [[score[0], score[1], cfg] for (score, cfg) in ranked[:finalists]]
+        for B in others:
+            Q2 = subset(B, range(min(sample, B.m)))
+            s.solve(Q2, precision=precision)              # warm-up
+            for f in fin:
+                ok2, dt2 = _timed(s, Q2, f[2])
+                if verbose:
+                    print(f"autotune other book {f[2]}: {ok2}/{Q2.m} certified, "
+                          f"{dt2 * 1e3:.1f} ms", flush=True)
+                f[0] -= ok2
+                f[1] += dt2
+        fin.sort(key=lambda f: (f[0], f[1]))
+        best = ((fin[0][0], fin[0][1]), fin[0][2])
     _CACHE[key] = best[1]
     if cache_path:
         disk = {}
