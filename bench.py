@@ -82,23 +82,72 @@ def measured_traffic():
     return float(vals["traffic_bytes_per_launch"])
 
 
-def timed_solves(solver, P, steps, settings):
-    """Run `steps` solves with per-launch events on the PROJECT pass; returns
-    (seconds, certified, kernel_ms, launches, iters per solve)."""
+def timed_solves(solver, P, steps, settings, contract=None):
+    """Run `steps` solves with per-launch events on the PROJECT pass (and on
+    the CONTRACT pass when `contract` is given: its kernel ms are added to
+    contract[0]); returns (seconds, certified, PROJECT kernel_ms, launches,
+    iters per solve)."""
     import torch
     out = None
     solved, kernel_ms, launches, iters = 0, 0.0, 0, []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
-        out = solver.solve(P, out=out, profile=1, **settings)
+        out = solver.solve(P, out=out, profile=1 if contract is None else 3, **settings)
         st = solver.stats()
         iters.append(out["iters"].cpu().numpy())
         solved += int((out["status"] == 0).sum().item())
         kernel_ms += st["iter_kernel_ms"]
+        if contract is not None:
+            contract[0] += st["contract_kernel_ms"]
         launches += st["iter_launches"]
     torch.cuda.synchronize()
     return time.perf_counter() - t0, solved, kernel_ms, launches, iters
+
+
+def copy_bandwidth(nbytes=1 << 30, reps=5):
+    """Achievable HBM bandwidth: bytes read + written by a device-to-device
+    copy of a 1 GiB buffer (larger than the 256 MB last-level cache), best
+    of `reps`, timed with events on the current stream."""
+    import torch
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda:0").fill_(1.0)
+    b = torch.empty_like(a)
+    best = None
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        e1.synchronize()
+        ms = e0.elapsed_time(e1)
+        best = ms if best is None else min(best, ms)
+    del a, b
+    return 2.0 * nbytes / (best * 1e-3) / 1e9
+
+
+MFMA_BF16_PEAK_TFLOPS = 2500.0
+
+
+def mfma_report(uni, book, iters, project_ms, contract_ms):
+    """Matrix-core rates of the two contraction passes over one profiled step:
+    useful flops are the products with the k + G + 1 used columns of B~ (2 N
+    (k + G + 1) per account-iteration and pass); issued flops count the three
+    bf16 products per float32 product over the padded width kp."""
+    import numpy as np
+    n, k, G = uni.n, uni.k, uni.n_groups
+    kg1 = k + G + 1
+    kp = ((kg1 + 31) // 32) * 32
+    acc_iters = float(sum(np.sum(it) for it in iters))
+    useful = 2.0 * n * kg1 * acc_iters              # per pass
+    issued = useful * 3.0 * kp / kg1
+    out = {"instruction": "v_mfma_f32_32x32x16_bf16 (hi*hi + hi*lo + lo*hi)",
+           "peak_tflops": MFMA_BF16_PEAK_TFLOPS}
+    for name, ms in (("contract", contract_ms), ("project", project_ms)):
+        if ms > 0:
+            out[name] = {"useful_tflops": useful / (ms * 1e-3) / 1e12,
+                         "issued_tflops": issued / (ms * 1e-3) / 1e12,
+                         "issued_frac": issued / (ms * 1e-3) / 1e12 / MFMA_BF16_PEAK_TFLOPS}
+    return out
 
 
 def plain_fp32(uni, book, n_sample):
@@ -222,6 +271,9 @@ def main():
         if args.warmup > 1:
             timed_solves(solver, P, args.warmup - 1, SETTINGS)
     dt, solved, kernel_ms, launches, iters = timed_solves(solver, P, args.steps, SETTINGS)
+    # matrix-core rates from one more (untimed) step with both passes timed
+    contract_ms = [0.0]
+    _, _, mf_project_ms, _, mf_iters = timed_solves(solver, P, 1, SETTINGS, contract=contract_ms)
     it_all = np.concatenate(iters)
     # whole path against the per-account-iteration byte model of the method:
     # state z, u read + written, mu and w0 read (24 N), eligibility bits,
@@ -238,6 +290,7 @@ def main():
 
     value = solved / dt
     achieved = alg_bytes / (kernel_ms * 1e-3) / 1e9 if kernel_ms > 0 else None
+    achievable = copy_bandwidth()
     line = {
         "metric": "accounts solved/s to 1e-6 KKT residual (500 accts, N=10k), "
                   "% HBM roofline",
@@ -289,7 +342,10 @@ def main():
                       "ADMM state)",
             "alg_bytes_per_launch": alg_bytes / max(launches, 1),
             "avg_launch_us": kernel_ms * 1e3 / max(launches, 1),
+            "achievable_gbs": achievable,
+            "frac_of_achievable": (achieved / achievable) if (achieved and achievable) else None,
         },
+        "mfma": mfma_report(uni, book, mf_iters, mf_project_ms, contract_ms[0]),
     }
     if args.plain_sample > 0:
         line["plain_fp32"] = plain_fp32(uni, book, args.plain_sample)

@@ -126,8 +126,9 @@ typedef struct fqp_settings {
   float alpha;           /* over-relaxation in (0, 2)                     */
   int32_t polish_rounds; /* active-set refinement rounds per polish       */
   int32_t use_graph;     /* capture each block of iterations in a hipGraph */
-  int32_t profile;       /* time every PROJECT-pass launch with events that
-                            the kernel's own start and end stamp (no graphs) */
+  int32_t profile;       /* bit 0: time every PROJECT-pass launch, bit 1:
+                            every CONTRACT-pass launch, with events that the
+                            kernel's own start and end stamp (no graphs)    */
   double time_limit_ms;  /* wall-clock limit of the call (<= 0: none)     */
   int32_t precision;     /* fqp_precision of the ADMM contractions        */
   int32_t first_check;   /* iteration of the first polish / certification
@@ -157,7 +158,7 @@ typedef struct fqp_stats {
   int32_t polish_calls;     /* polish / certification kernel launches       */
   int32_t n_solved;         /* accounts with status SOLVED                  */
   double iter_kernel_ms;    /* summed execution time of the PROJECT-pass
-                               launches (settings.profile only, else 0)    */
+                               launches (settings.profile bit 0, else 0)   */
   double account_iters;     /* sum over accounts of iterations run          */
   double total_ms;          /* host wall-clock of the call                  */
   size_t workspace_bytes;   /* device workspace held by the handle          */
@@ -165,6 +166,8 @@ typedef struct fqp_stats {
                                x polish rounds)                            */
   int32_t polish_gated;     /* polish attempts skipped because the iterate's
                                pattern was not yet settled                 */
+  double contract_kernel_ms; /* summed execution time of the CONTRACT-pass
+                               launches (settings.profile bit 1, else 0)   */
 } fqp_stats;
 
 FQP_API void fqp_default_settings(fqp_settings *s);

@@ -62,7 +62,8 @@ class Stats(ctypes.Structure):
                 ("polish_calls", c_int32), ("n_solved", c_int32),
                 ("iter_kernel_ms", c_double), ("account_iters", c_double),
                 ("total_ms", c_double), ("workspace_bytes", c_size_t),
-                ("polish_solves", c_int32), ("polish_gated", c_int32)]
+                ("polish_solves", c_int32), ("polish_gated", c_int32),
+                ("contract_kernel_ms", c_double)]
 
 
 EXPORTS = ("fqp_default_settings", "fqp_create", "fqp_solve_batch",

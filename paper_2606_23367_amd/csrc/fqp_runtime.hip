@@ -517,7 +517,7 @@ extern "C" fqp_error fqp_solve_batch(fqp_handle* h, const fqp_universe* U, const
 
   std::vector<hipEvent_t> evs;
   if (S.profile) {
-    evs.resize(2 * S.check_every);
+    evs.resize(4 * S.check_every);      // PROJECT pairs, then CONTRACT pairs
     for (auto& ev : evs) HIP_CHECK(hipEventCreate(&ev));
   }
   struct EvGuard {
@@ -551,13 +551,17 @@ extern "C" fqp_error fqp_solve_batch(fqp_handle* h, const fqp_universe* U, const
   h->stats.workspace_bytes = h->total_bytes;
   // one ADMM iteration: contract, factor-space solve, project, cap
   auto launch_iteration = [&](int c) -> hipError_t {
-    hipError_t e0 = launch_iter(ia, kp, 0, S.precision, igrid, st);
+    // profiling: events stamped by the pass kernels' own start and end
+    const int cb = 2 * S.check_every;
+    hipError_t e0 = (S.profile & 2) ? launch_iter(ia, kp, 0, S.precision, igrid, st,
+                                                  evs[cb + 2 * c], evs[cb + 2 * c + 1])
+                                    : launch_iter(ia, kp, 0, S.precision, igrid, st);
     if (e0 != hipSuccess) return e0;
     e0 = launch_ksolve(ka, m, st);
     if (e0 != hipSuccess) return e0;
-    // profiling: events stamped by the PROJECT kernel's own start and end
-    e0 = S.profile ? launch_iter(ia, kp, 1, S.precision, igrid_p, st, evs[2 * c], evs[2 * c + 1])
-                   : launch_iter(ia, kp, 1, S.precision, igrid_p, st);
+    e0 = (S.profile & 1) ? launch_iter(ia, kp, 1, S.precision, igrid_p, st, evs[2 * c],
+                                       evs[2 * c + 1])
+                         : launch_iter(ia, kp, 1, S.precision, igrid_p, st);
     if (e0 != hipSuccess) return e0;
     if (any_cap) e0 = launch_cap(ia, m, cap_resident, st);
     return e0;
@@ -597,11 +601,18 @@ extern "C" fqp_error fqp_solve_batch(fqp_handle* h, const fqp_universe* U, const
     } else {
       for (int c = 0; c < count; ++c) HIP_CHECK(launch_iteration(c));
       if (S.profile) {
-        HIP_CHECK(hipEventSynchronize(evs[2 * count - 1]));
+        HIP_CHECK(hipStreamSynchronize(st));
+        const int cb = 2 * S.check_every;
         for (int c = 0; c < count; ++c) {
           float ms = 0.f;
-          HIP_CHECK(hipEventElapsedTime(&ms, evs[2 * c], evs[2 * c + 1]));
-          h->stats.iter_kernel_ms += ms;
+          if (S.profile & 1) {
+            HIP_CHECK(hipEventElapsedTime(&ms, evs[2 * c], evs[2 * c + 1]));
+            h->stats.iter_kernel_ms += ms;
+          }
+          if (S.profile & 2) {
+            HIP_CHECK(hipEventElapsedTime(&ms, evs[cb + 2 * c], evs[cb + 2 * c + 1]));
+            h->stats.contract_kernel_ms += ms;
+          }
         }
       }
     }
