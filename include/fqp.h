@@ -134,6 +134,12 @@ typedef struct fqp_settings {
   int32_t first_check;   /* iteration of the first polish / certification
                             pass (<= check_every: at check_every); later
                             passes every check_every iterations           */
+  int32_t warm_start;    /* 1: start from the ADMM state (v, band state, cap
+                            multiplier) this handle kept from its last
+                            completed solve, when that book had the same m,
+                            n and n_groups (e.g. the same accounts with the
+                            next day's returns); otherwise, or 0: cold.  Any
+                            start converges to the same optimum            */
 } fqp_settings;
 
 /* Outputs (device pointers, caller-owned).  Any may be NULL except w and

@@ -47,7 +47,7 @@ class Settings(ctypes.Structure):
                 ("polish_rounds", c_int32),
                 ("use_graph", c_int32), ("profile", c_int32),
                 ("time_limit_ms", c_double), ("precision", c_int32),
-                ("first_check", c_int32)]
+                ("first_check", c_int32), ("warm_start", c_int32)]
 
 
 class Result(ctypes.Structure):

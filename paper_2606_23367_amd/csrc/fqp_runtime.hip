@@ -34,7 +34,7 @@ __global__ void init_accounts_kernel(int m, int G, const int* cls, const float* 
                                      const float* ub, const float* tau, const int32_t* tax_ptr,
                                      float alpha, float rho_b, float* par, float* zb, float* vb,
                                      const float* blo, const float* bhi, int* iters,
-                                     int32_t* pstate, int npstate) {
+                                     int32_t* pstate, int npstate, int warm) {
   const int a = blockIdx.x * blockDim.x + threadIdx.x;
   if (a >= m) return;
   float* p = par + (size_t)a * kNPar;
@@ -42,7 +42,8 @@ __global__ void init_accounts_kernel(int m, int G, const int* cls, const float* 
   p[P_GAMMA] = gamma[a];
   p[P_RHO] = rho_cls[c];
   p[P_KAPPA] = kappa[a];
-  p[P_LAM] = 0.f;
+  // a warm start keeps the last cap multiplier and band state when finite
+  if (!warm || !(isfinite(p[P_LAM]) && p[P_LAM] >= 0.f)) p[P_LAM] = 0.f;
   p[P_NU] = 0.f;
   p[P_LB] = lb[a];
   p[P_UB] = ub[a];
@@ -52,11 +53,21 @@ __global__ void init_accounts_kernel(int m, int G, const int* cls, const float* 
   p[P_CLASS] = (float)c;
   p[P_HASTAX] = (tax_ptr && tax_ptr[a + 1] > tax_ptr[a]) ? 1.f : 0.f;
   for (int g = 0; g < G; ++g) {
-    zb[(size_t)a * G + g] = fminf(fmaxf(0.f, blo[(size_t)a * G + g]), bhi[(size_t)a * G + g]);
-    vb[(size_t)a * G + g] = 0.f;
+    const size_t e = (size_t)a * G + g;
+    if (warm && isfinite(zb[e]) && isfinite(vb[e])) continue;
+    zb[e] = fminf(fmaxf(0.f, blo[e]), bhi[e]);
+    vb[e] = 0.f;
   }
   iters[a] = 0;
   for (int q = 0; q < npstate; ++q) pstate[(size_t)a * npstate + q] = 0;
+}
+
+// warm start: a non-finite entry of the kept state (an account that failed
+// last time) restarts from 0
+__global__ void sanitize_state_kernel(size_t count, float* v) {
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < count;
+       e += (size_t)gridDim.x * blockDim.x)
+    if (!isfinite(v[e])) v[e] = 0.f;
 }
 
 // active list = accounts whose status is still -1 (valid, not certified)
@@ -133,6 +144,9 @@ struct fqp_handle {
   bool configured = false;
   // context of the last successful solve, for fqp_adjoint_batch
   bool have_last = false;
+  // shape of the last completed solve, whose ADMM state a warm start reuses
+  bool warm_ok = false;
+  int warm_m = 0, warm_n = 0, warm_G = 0;
   AdjArgs last{};
 
   template <typename T>
@@ -292,6 +306,11 @@ extern "C" fqp_error fqp_solve_batch(fqp_handle* h, const fqp_universe* U, const
   if (S_in) S = *S_in; else fqp_default_settings(&S);
   const int n = U->n, k = U->k, G = U->n_groups, m = P->m;
   if (n < 1 || k < 1 || m < 1 || G < 0) { h->err = "non-positive size"; return FQP_ERR_INVALID_ARG; }
+  // the kept state is reused only by a solve of the same shape; a solve
+  // that fails part-way leaves no state to reuse
+  const bool warm = S.warm_start && h->warm_ok && h->warm_m == m && h->warm_n == n &&
+                    h->warm_G == G;
+  h->warm_ok = false;
   if (!U->B || !U->f || !U->d || !P->mu || !P->w0 || !P->lb || !P->ub || !P->gamma ||
       !P->kappa || !P->tau || !R->w || !R->status) {
     h->err = "required pointer is null";
@@ -479,9 +498,15 @@ extern "C" fqp_error fqp_solve_batch(fqp_handle* h, const fqp_universe* U, const
   HIP_CHECK(launch_pack_fill(pk, st));
   hipLaunchKernelGGL(init_accounts_kernel, dim3((m + 255) / 256), dim3(256), 0, st, m, G, cls_d,
                      rho_d, P->gamma, P->kappa, P->lb, P->ub, P->tau, P->tax_ptr, S.alpha, rho_b,
-                     par, zb, vb, P->band_lo, P->band_hi, iters, pstate, kPStateStride);
+                     par, zb, vb, P->band_lo, P->band_hi, iters, pstate, kPStateStride,
+                     warm ? 1 : 0);
   HIP_CHECK(hipGetLastError());
-  HIP_CHECK(hipMemsetAsync(v, 0, sizeof(float) * (size_t)m * n, st));
+  if (warm) {
+    hipLaunchKernelGGL(sanitize_state_kernel, dim3(1024), dim3(256), 0, st, (size_t)m * n, v);
+    HIP_CHECK(hipGetLastError());
+  } else {
+    HIP_CHECK(hipMemsetAsync(v, 0, sizeof(float) * (size_t)m * n, st));
+  }
   hipLaunchKernelGGL(compact_kernel, dim3(1), dim3(256), 0, st, m, R->status, act, m_act);
   HIP_CHECK(hipGetLastError());
 
@@ -694,6 +719,8 @@ extern "C" fqp_error fqp_solve_batch(fqp_handle* h, const fqp_universe* U, const
     L.w = R->w; L.wk = wk; L.wk_stride = wks;
     h->have_last = true;
   }
+  h->warm_ok = true;
+  h->warm_m = m; h->warm_n = n; h->warm_G = G;
   h->stats.total_ms =
       std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
   return FQP_OK;
