@@ -181,6 +181,43 @@ def warm_lane(solver, uni, book, settings, sd=1e-4):
     return res
 
 
+E7_GRID = dict(rho=(0.3, 1.0, 3.0, 10.0), alpha=(1.6, 1.8), check_every=(25, 50),
+               first_mult=(1, 2))
+
+
+def e7_lane(solver, steps=5):
+    """Small-universe batch: 200 accounts over N = 481 names (k = 20, box
+    [0, 0.03], L1 transition cost 5e-3, drifted holdings), the shape of the
+    paper's 200-account real-data queue.  Schedule from the autotuner on the
+    seed-1 book (finalists confirmed on seeds 2-4); the timed book is seed
+    0; best of `steps` whole-book solves."""
+    import numpy as np
+    import torch
+    from workloads import make_config
+    from paper_2606_23367_amd.solver import to_device
+    from paper_2606_23367_amd.tune import autotune
+    u1, b1 = make_config("e7", 1)
+    others = [to_device(*make_config("e7", sd), "cuda:0") for sd in (2, 3, 4)]
+    cfg = autotune(to_device(u1, b1, "cuda:0"), solver=solver, sample=b1.m, grid=E7_GRID,
+                   second=others)
+    uni, book = make_config("e7", 0)
+    P = to_device(uni, book, "cuda:0")
+    solver.solve(P, **cfg)
+    best, solved, its = None, 0, None
+    for _ in range(steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = solver.solve(P, **cfg)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        if best is None or dt < best:
+            best, solved, its = dt, int((out["status"] == 0).sum().item()), out["iters"].cpu().numpy()
+    return {"value": solved / best, "unit": "accounts/s", "ms_per_book": best * 1e3,
+            "accounts": book.m, "certified": solved, "assets": uni.n, "factors": uni.k,
+            "settings": cfg, "iterations_p50_max": [float(np.median(its)), int(its.max())],
+            "data": "synthetic stand-in for the paper's 481-name real universe"}
+
+
 def plain_fp32(uni, book, n_sample):
     """The unbatched float32 form: one account per fqp_solve_batch call,
     float32 MFMA contractions, the first n_sample accounts."""
@@ -379,6 +416,7 @@ def main():
         "mfma": mfma_report(uni, book, mf_iters, mf_project_ms, contract_ms[0]),
     }
     line["warm_lane"] = warm_lane(solver, uni, book, SETTINGS)
+    line["e7_lane"] = e7_lane(solver)
     if args.plain_sample > 0:
         line["plain_fp32"] = plain_fp32(uni, book, args.plain_sample)
     if not args.no_cpu:

@@ -29,6 +29,7 @@ def _all_certified_by_cpu_checker(uni, book, host):
 @pytest.mark.parametrize("name,sample,settings", [
     ("c2", (0, 31, 63), dict(rho=1.0)),          # 64 x 2,000, k=40, 10 bands
     ("c4", (0, 77, 127), dict(rho=1.0)),         # 128 x 5,000, k=60, gamma=1000
+    ("e7", (0, 99, 199), dict(rho=1.0, check_every=25)),   # 200 x 481, k=20, L1 5e-3
 ])
 def test_full_size_books(name, sample, settings):
     uni, book = make_config(name, 0)

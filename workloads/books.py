@@ -15,6 +15,9 @@ this project:
   c4  128 accounts, N=5,000,  k=60,  as c2 with box [0, 0.02], gamma = 1000
   c5  8 accounts, N=384,800,  k=100, 50 one-hot groups (+/-0.005), box
       [0, 1e-3], L1 turnover 1e-3, 2,000 held names with 4-lot tax
+  e7  200 accounts, N=481,   k=20,  box [0, 0.03], L1 transition cost
+      5e-3|w-w0|, drifted holdings w0 ~ Dirichlet(1): the shape of the
+      paper's small-universe batch scenario on its real 481-name universe
 
 The paper's own instances (real S&P 500 data, Sec. "Operationally Constrained
 Real-Data Scenarios") are not available; these synthetic books stand in for
@@ -34,7 +37,7 @@ from typing import Optional
 
 import numpy as np
 
-CONFIG_NAMES = ("c1", "c2", "c3", "c4", "c5")
+CONFIG_NAMES = ("c1", "c2", "c3", "c4", "c5", "e7")
 _CFG_ID = {name: i for i, name in enumerate(CONFIG_NAMES)}
 
 
@@ -123,6 +126,9 @@ _DEFAULTS = {
     "c5": dict(N=384800, M=8, k=100, ub=1e-3, gamma=1.0, kappa=1e-3,
                groups=50, band_halfwidth=0.005, elig=(1.0, 1.0),
                held=(2000, 2000), tax=True, cap_slack=None),
+    "e7": dict(N=481, M=200, k=20, ub=0.03, gamma=1.0, kappa=5e-3, groups=0,
+               band_halfwidth=None, elig=(1.0, 1.0), held=None, tax=False,
+               cap_slack=None),
 }
 
 
