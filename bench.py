@@ -150,6 +150,21 @@ def mfma_report(uni, book, iters, project_ms, contract_ms):
     return out
 
 
+def queue_lane(solver, P, settings, budget_ms=500.0):
+    """Queue accounting of one more (untimed, graph-mode) solve of the timed
+    book: completion count, T_queue, p50 / p99 per-account completion and
+    the miss rate against a 0.5 s per-account budget (the paper's
+    deadline-bounded scenario), from the per-account audit records."""
+    import torch
+    from paper_2606_23367_amd.audit import audit_records, queue_summary
+    out = solver.solve(P, **settings)
+    torch.cuda.synchronize()
+    recs = audit_records(P, out, solver)
+    q = queue_summary(recs, budget_ms=budget_ms)
+    q["passes"] = [{"iterations": it, "ms": ms} for it, ms in solver.pass_times()]
+    return q
+
+
 def warm_lane(solver, uni, book, settings, sd=1e-4):
     """Repeated-rebalance lane: the same book with returns moved by
     N(0, sd^2) (about 1 % of their cross-sectional spread), solved cold with
@@ -415,6 +430,7 @@ def main():
         },
         "mfma": mfma_report(uni, book, mf_iters, mf_project_ms, contract_ms[0]),
     }
+    line["queue"] = queue_lane(solver, P, SETTINGS)
     line["warm_lane"] = warm_lane(solver, uni, book, SETTINGS)
     line["e7_lane"] = e7_lane(solver)
     if args.plain_sample > 0:

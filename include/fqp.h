@@ -200,6 +200,17 @@ FQP_API fqp_error fqp_adjoint_batch(fqp_handle *h, const double *dL_dw,
 
 FQP_API fqp_error fqp_get_stats(const fqp_handle *h, fqp_stats *out);
 
+/* Certification passes of the last fqp_solve_batch call (the queue lane of
+ * Sec. "Production Queue": an account certified after `iters[a]` ADMM
+ * iterations completed at the end of the pass run after that many
+ * iterations).  For pass p < *count: iter[p] = ADMM iterations before the
+ * pass, ms[p] = host wall-clock from the call's start to the end of the pass
+ * (the call synchronises the stream there).  Writes at most `cap` entries
+ * into the caller's host arrays; *count gets the number of passes.
+ * FQP_ERR_INVALID_ARG for null pointers. */
+FQP_API fqp_error fqp_get_pass_times(const fqp_handle *h, int32_t *iter, double *ms,
+                                     int32_t cap, int32_t *count);
+
 FQP_API const char *fqp_error_string(int e);
 FQP_API const char *fqp_status_string(int s);
 FQP_API const char *fqp_last_error(const fqp_handle *h);

@@ -14,4 +14,7 @@ def __getattr__(name):
     if name == "autotune":
         from .tune import autotune
         return autotune
+    if name in ("audit_records", "queue_summary"):
+        from . import audit
+        return getattr(audit, name)
     raise AttributeError(name)

@@ -67,8 +67,8 @@ class Stats(ctypes.Structure):
 
 
 EXPORTS = ("fqp_default_settings", "fqp_create", "fqp_solve_batch",
-           "fqp_adjoint_batch", "fqp_get_stats", "fqp_error_string", "fqp_status_string",
-           "fqp_last_error", "fqp_destroy")
+           "fqp_adjoint_batch", "fqp_get_stats", "fqp_get_pass_times", "fqp_error_string",
+           "fqp_status_string", "fqp_last_error", "fqp_destroy")
 
 _lib = None
 
@@ -97,6 +97,10 @@ def load(path: str = LIB_PATH):
     lib.fqp_adjoint_batch.restype = ctypes.c_int
     lib.fqp_get_stats.argtypes = [c_void_p, ctypes.POINTER(Stats)]
     lib.fqp_get_stats.restype = ctypes.c_int
+    lib.fqp_get_pass_times.argtypes = [c_void_p, ctypes.POINTER(ctypes.c_int32),
+                                       ctypes.POINTER(c_double), ctypes.c_int32,
+                                       ctypes.POINTER(ctypes.c_int32)]
+    lib.fqp_get_pass_times.restype = ctypes.c_int
     lib.fqp_error_string.argtypes = [ctypes.c_int]
     lib.fqp_error_string.restype = ctypes.c_char_p
     lib.fqp_status_string.argtypes = [ctypes.c_int]

@@ -147,6 +147,9 @@ struct fqp_handle {
   // shape of the last completed solve, whose ADMM state a warm start reuses
   bool warm_ok = false;
   int warm_m = 0, warm_n = 0, warm_G = 0;
+  // certification passes of the last solve: iterations before, end time
+  std::vector<int32_t> pass_iter;
+  std::vector<double> pass_ms;
   AdjArgs last{};
 
   template <typename T>
@@ -277,6 +280,18 @@ fqp_error fqp_get_stats(const fqp_handle* h, fqp_stats* out) {
   return FQP_OK;
 }
 
+fqp_error fqp_get_pass_times(const fqp_handle* h, int32_t* iter, double* ms, int32_t cap,
+                             int32_t* count) {
+  if (!h || !count || (cap > 0 && (!iter || !ms))) return FQP_ERR_INVALID_ARG;
+  const int np = (int)h->pass_iter.size();
+  for (int p = 0; p < np && p < cap; ++p) {
+    iter[p] = h->pass_iter[p];
+    ms[p] = h->pass_ms[p];
+  }
+  *count = np;
+  return FQP_OK;
+}
+
 }  // extern "C"
 
 #define HIP_CHECK(x)                                                              \
@@ -299,6 +314,8 @@ extern "C" fqp_error fqp_solve_batch(fqp_handle* h, const fqp_universe* U, const
   if (!h) return FQP_ERR_INVALID_ARG;
   h->err.clear();
   h->stats = fqp_stats{};
+  h->pass_iter.clear();
+  h->pass_ms.clear();
   auto t_start = std::chrono::steady_clock::now();
   h->have_last = false;
   if (!U || !P || !R) { h->err = "null universe/book/result"; return FQP_ERR_INVALID_ARG; }
@@ -672,6 +689,9 @@ extern "C" fqp_error fqp_solve_batch(fqp_handle* h, const fqp_universe* U, const
     HIP_CHECK(hipGetLastError());
     HIP_CHECK(hipMemcpyAsync(&active, m_act, sizeof(int), hipMemcpyDeviceToHost, st));
     HIP_CHECK(hipStreamSynchronize(st));
+    h->pass_iter.push_back(done_iters);
+    h->pass_ms.push_back(std::chrono::duration<double, std::milli>(
+                             std::chrono::steady_clock::now() - t_start).count());
     if (S.time_limit_ms > 0.0) {
       double el = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() -
                                                             t_start).count();

@@ -220,6 +220,17 @@ class Solver:
         self.lib.fqp_get_stats(self.h, ctypes.byref(st))
         return {name: getattr(st, name) for name, _ in _lib.Stats._fields_}
 
+    def pass_times(self) -> list:
+        """[(ADMM iterations before the pass, ms from the call's start to the
+        end of the pass)] for the certification passes of the last solve."""
+        count = ctypes.c_int32(0)
+        self.lib.fqp_get_pass_times(self.h, None, None, 0, ctypes.byref(count))
+        n = count.value
+        it = (ctypes.c_int32 * max(n, 1))()
+        ms = (ctypes.c_double * max(n, 1))()
+        self.lib.fqp_get_pass_times(self.h, it, ms, n, ctypes.byref(count))
+        return [(int(it[p]), float(ms[p])) for p in range(n)]
+
 
 def solve_batch(P: DeviceProblem, solver: Optional[Solver] = None, **settings):
     """One-shot convenience wrapper: returns (outputs, stats)."""

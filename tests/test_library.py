@@ -4,6 +4,8 @@ import ctypes
 import os
 import re
 
+import numpy as np
+
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -95,3 +97,20 @@ def test_device_subset_matches_host_subset():
         if a is not None:
             assert torch.equal(a, b), name
     assert A.m == 3
+
+
+def test_queue_summary_counts_and_percentiles():
+    from paper_2606_23367_amd.audit import queue_summary
+    from paper_2606_23367_amd._lib import SOLVED, FEASIBLE_UNCERTIFIED, MAX_ITER, STATUS_NAMES
+    codes = [SOLVED] * 7 + [FEASIBLE_UNCERTIFIED, MAX_ITER, SOLVED]
+    times = [10.0, 10.0, 20.0, 20.0, 20.0, 30.0, 30.0, 40.0, 40.0, 600.0]
+    recs = [{"status_code": c, "status": STATUS_NAMES[c], "completed_ms": t}
+            for c, t in zip(codes, times)]
+    q = queue_summary(recs, budget_ms=500.0)
+    assert q["accounts"] == 10 and q["completed"] == 9
+    assert q["t_queue_ms"] == 600.0
+    assert q["p50_ms"] == float(np.percentile(times, 50))
+    assert q["p99_ms"] == float(np.percentile(times, 99))
+    assert q["status_counts"][STATUS_NAMES[SOLVED]] == 8
+    # the iteration-cap account and the one past the budget
+    assert q["miss_rate"] == 0.2
