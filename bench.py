@@ -196,6 +196,50 @@ def warm_lane(solver, uni, book, settings, sd=1e-4):
     return res
 
 
+# constraint-burden bundles at N = 2,000 (64 accounts, k = 40), cumulative;
+# the factor-exposure bounds bundle (halfspace rows on B^T w) is not part of
+# the problem class built here
+BURDEN = (
+    ("B0 budget, long-only, box", dict(kappa=0.0, groups=0, band_halfwidth=None)),
+    ("B1 + turnover penalty", dict(kappa=1e-3, groups=0, band_halfwidth=None)),
+    ("B2 + sector bands", dict(kappa=1e-3)),
+    ("B4 + account exclusions", dict(kappa=1e-3, elig=(0.3, 1.0))),
+    ("B5 + tax lots", dict(kappa=1e-3, elig=(0.3, 1.0), held=(100, 400), tax=True)),
+)
+BURDEN_GRID = dict(rho=(0.3, 1.0, 3.0, 10.0), alpha=(1.8,), check_every=(25, 50))
+
+
+def burden_lane(solver, steps=3):
+    """Accounts/s of a 64 x 2,000 book as rule families accumulate (the
+    paper's constraint-burden curve, synthetic): schedule tuned per bundle
+    on its seed-1 book, best of `steps` solves of the seed-0 book."""
+    import torch
+    from workloads import make_config
+    from paper_2606_23367_amd.solver import to_device
+    from paper_2606_23367_amd.tune import autotune
+    rows = []
+    for label, over in BURDEN:
+        u1, b1 = make_config("c2", 1, **over)
+        cfg = autotune(to_device(u1, b1, "cuda:0"), solver=solver, sample=b1.m,
+                       grid=BURDEN_GRID)
+        uni, book = make_config("c2", 0, **over)
+        P = to_device(uni, book, "cuda:0")
+        solver.solve(P, **cfg)
+        best, solved = None, 0
+        for _ in range(steps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            out = solver.solve(P, **cfg)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            if best is None or dt < best:
+                best, solved = dt, int((out["status"] == 0).sum().item())
+        rows.append({"bundle": label, "ms_per_book": best * 1e3, "accounts_per_s": solved / best,
+                     "certified": solved, "accounts": book.m, "rho": cfg["rho"],
+                     "check_every": cfg["check_every"]})
+    return rows
+
+
 E7_GRID = dict(rho=(0.3, 1.0, 3.0, 10.0), alpha=(1.6, 1.8), check_every=(25, 50),
                first_mult=(1, 2))
 
@@ -433,6 +477,7 @@ def main():
     line["queue"] = queue_lane(solver, P, SETTINGS)
     line["warm_lane"] = warm_lane(solver, uni, book, SETTINGS)
     line["e7_lane"] = e7_lane(solver)
+    line["burden_lane"] = burden_lane(solver)
     if args.plain_sample > 0:
         line["plain_fp32"] = plain_fp32(uni, book, args.plain_sample)
     if not args.no_cpu:

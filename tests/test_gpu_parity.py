@@ -17,6 +17,8 @@ SMALL = [
     ("c4", dict(N=900, M=5, k=12), dict(rho=1.0)),           # gamma = 1000
     ("c4", dict(N=900, M=5, k=12, gamma=1.0), dict(rho=1.0)),
     ("c5", dict(N=6000, M=2, k=20, held=(300, 300)), dict(rho=10.0)),
+    # every rule family at once: L1 turnover, sector bands, exclusions, taxed lots
+    ("c2", dict(N=700, M=8, k=10, elig=(0.3, 1.0), held=(50, 120), tax=True), dict(rho=1.0)),
 ]
 
 
