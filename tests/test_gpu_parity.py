@@ -14,6 +14,7 @@ SMALL = [
     ("c1", dict(N=37, ub=0.13), dict(rho=0.05)),             # N < 64, ragged
     ("c2", dict(N=700, M=40, k=10), dict(rho=1.0)),          # 2 account tiles
     ("c3", dict(N=1300, M=9, k=16), dict(rho=5.0)),          # masks, tax, cap
+    ("c3", dict(N=37, M=3, k=4, ub=0.2, held=(3, 8)), dict(rho=5.0)),   # tiny, binding caps
     ("c4", dict(N=900, M=5, k=12), dict(rho=1.0)),           # gamma = 1000
     ("c4", dict(N=900, M=5, k=12, gamma=1.0), dict(rho=1.0)),
     ("c5", dict(N=6000, M=2, k=20, held=(300, 300)), dict(rho=10.0)),
