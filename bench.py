@@ -347,6 +347,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--plain-sample", type=int, default=16,
                     help="accounts of the one-account-per-call float32 comparison")
+    ap.add_argument("--no-lanes", action="store_true",
+                    help="skip the extra reports (MFMA step, queue, warm, e7 and burden lanes): "
+                         "the profiling runs")
     ap.add_argument("--schedule", default="", metavar="RHO,ALPHA,CHECK[,FIRST]",
                     help="fixed ADMM schedule instead of the autotuner (profiling runs)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -400,7 +403,10 @@ def main():
     dt, solved, kernel_ms, launches, iters = timed_solves(solver, P, args.steps, SETTINGS)
     # matrix-core rates from one more (untimed) step with both passes timed
     contract_ms = [0.0]
-    _, _, mf_project_ms, _, mf_iters = timed_solves(solver, P, 1, SETTINGS, contract=contract_ms)
+    mf_project_ms, mf_iters = 0.0, []
+    if not args.no_lanes:
+        _, _, mf_project_ms, _, mf_iters = timed_solves(solver, P, 1, SETTINGS,
+                                                        contract=contract_ms)
     it_all = np.concatenate(iters)
     # whole path against the per-account-iteration byte model of the method:
     # state z, u read + written, mu and w0 read (24 N), eligibility bits,
@@ -472,12 +478,14 @@ def main():
             "achievable_gbs": achievable,
             "frac_of_achievable": (achieved / achievable) if (achieved and achievable) else None,
         },
-        "mfma": mfma_report(uni, book, mf_iters, mf_project_ms, contract_ms[0]),
+        "mfma": None if args.no_lanes else mfma_report(uni, book, mf_iters, mf_project_ms,
+                                                       contract_ms[0]),
     }
-    line["queue"] = queue_lane(solver, P, SETTINGS)
-    line["warm_lane"] = warm_lane(solver, uni, book, SETTINGS)
-    line["e7_lane"] = e7_lane(solver)
-    line["burden_lane"] = burden_lane(solver)
+    if not args.no_lanes:
+        line["queue"] = queue_lane(solver, P, SETTINGS)
+        line["warm_lane"] = warm_lane(solver, uni, book, SETTINGS)
+        line["e7_lane"] = e7_lane(solver)
+        line["burden_lane"] = burden_lane(solver)
     if args.plain_sample > 0:
         line["plain_fp32"] = plain_fp32(uni, book, args.plain_sample)
     if not args.no_cpu:
