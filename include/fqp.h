@@ -27,9 +27,11 @@
  * workspace (grown on demand, freed by fqp_destroy).
  *
  * Errors: call-level problems (null pointers, non-positive sizes, HIP
- * failures, allocation failure) return a negative fqp_error and leave the
- * outputs undefined; fqp_last_error() describes the last one.  Problems of
- * one account (invalid data, provable infeasibility, non-finite values) are
+ * failures, allocation failure) return a negative fqp_error;
+ * fqp_last_error() describes the last one.  Argument errors and
+ * FQP_ERR_ALLOC (every workspace request precedes the first write) leave the
+ * outputs untouched; after FQP_ERR_HIP they are undefined.  Problems of one
+ * account (invalid data, provable infeasibility, non-finite values) are
  * reported in status[a] and never fail the batch.
  *
  * Threading: one handle per host thread.  The call is synchronous: it
@@ -89,7 +91,8 @@ typedef struct fqp_book {
   int32_t m;                 /* accounts, >= 1                              */
   const float *mu;           /* [m][n] expected returns                    */
   const float *w0;           /* [m][n] current weights                     */
-  const float *lb, *ub;      /* [m] box bounds (lb <= 0 <= ub)              */
+  const float *lb, *ub;      /* [m] box bounds lb <= ub of eligible names
+                                (excluded names: [0, 0])                    */
   const uint32_t *eligible;  /* [m][ceil(n/32)] bit i%32 of word i/32 set =
                                 asset i eligible; NULL = all eligible       */
   const float *gamma;        /* [m] risk aversion, > 0                     */
@@ -103,6 +106,13 @@ typedef struct fqp_book {
   const float *tax_brk;      /* [nnz][3] cumulative sale breakpoints,
                                 0 < b1 < b2 < b3                            */
   const float *tax_slope;    /* [nnz][4] lot slopes, 0 <= s0 <= .. <= s3     */
+  const float *warm_state;   /* NULL, or an ADMM state block of
+                                fqp_state_floats(m, n, n_groups) floats that an
+                                earlier call wrote to fqp_result.state (the
+                                same accounts, any handle or process); used
+                                when settings.warm_start = 1 (the cold /
+                                repeated / warm lanes of Sec. "Timing
+                                Lanes").  Non-finite entries restart from 0 */
 } fqp_book;
 
 /* Arithmetic of the factor contractions inside the ADMM iterations (the
@@ -125,7 +135,10 @@ typedef struct fqp_settings {
   float rho_band;        /* ADMM penalty on the band split (<= 0: auto)   */
   float alpha;           /* over-relaxation in (0, 2)                     */
   int32_t polish_rounds; /* active-set refinement rounds per polish       */
-  int32_t use_graph;     /* capture each block of iterations in a hipGraph */
+  int32_t use_graph;     /* capture a block of check_every iterations in a
+                            hipGraph; the handle keeps the executable graph
+                            and a later call with the same arguments (same
+                            buffers, sizes and schedule) replays it        */
   int32_t profile;       /* bit 0: time every PROJECT-pass launch, bit 1:
                             every CONTRACT-pass launch, with events that the
                             kernel's own start and end stamp (no graphs)    */
@@ -134,12 +147,21 @@ typedef struct fqp_settings {
   int32_t first_check;   /* iteration of the first polish / certification
                             pass (<= check_every: at check_every); later
                             passes every check_every iterations           */
-  int32_t warm_start;    /* 1: start from the ADMM state (v, band state, cap
+  int32_t warm_start;    /* 1: start from book.warm_state when given, else
+                            from the ADMM state (v, band state, cap
                             multiplier) this handle kept from its last
                             completed solve, when that book had the same m,
                             n and n_groups (e.g. the same accounts with the
                             next day's returns); otherwise, or 0: cold.  Any
                             start converges to the same optimum            */
+  int32_t debug_fail_alloc; /* test hook: > 0 makes the workspace request
+                            with that number (1-based, in call order) fail
+                            like a device allocation failure; the call then
+                            returns FQP_ERR_ALLOC with every output
+                            untouched.  0 in production                    */
+  int32_t tile_rows;     /* rows of one iteration-pass workgroup, in 128-row
+                            chunks (0: sized from the occupancy so that a
+                            full batch runs in one round of workgroups)    */
 } fqp_settings;
 
 /* Outputs (device pointers, caller-owned).  Any may be NULL except w and
@@ -155,7 +177,17 @@ typedef struct fqp_result {
   double *nu;         /* [m] budget multiplier                             */
   double *lam_cap;    /* [m] turnover-cap multiplier (>= 0)                */
   double *lam_band;   /* [m][n_groups] band multipliers (> 0: upper binds) */
+  float *state;       /* NULL, or fqp_state_floats(m, n, n_groups) floats:
+                         the final ADMM state (v [m][n], band z [m][G], band
+                         u [m][G], cap multiplier [m]) for a later warm
+                         start through fqp_book.warm_state                */
 } fqp_result;
+
+/* Size in floats of an ADMM state block (fqp_book.warm_state,
+ * fqp_result.state): m n + 2 m n_groups + m. */
+static inline size_t fqp_state_floats(int32_t m, int32_t n, int32_t n_groups) {
+  return (size_t)m * (size_t)n + 2 * (size_t)m * (size_t)n_groups + (size_t)m;
+}
 
 /* Host-side counters of the last fqp_solve_batch call. */
 typedef struct fqp_stats {
@@ -174,6 +206,16 @@ typedef struct fqp_stats {
                                pattern was not yet settled                 */
   double contract_kernel_ms; /* summed execution time of the CONTRACT-pass
                                launches (settings.profile bit 1, else 0)   */
+  double phase_ms[4];       /* device lane of the call by phase, from events
+                               on the handle's stream: [0] validation, packing
+                               and factor-space setup, [1] ADMM iterations,
+                               [2] polish / certification passes, [3] final
+                               polish of uncertified accounts and outputs   */
+  int32_t graph_reused;     /* 1: the blocks replayed the executable graph
+                               kept from an earlier call with the same
+                               arguments (no capture in this call)         */
+  int32_t workspace_requests; /* workspace requests the call made (the range
+                               of settings.debug_fail_alloc)               */
 } fqp_stats;
 
 FQP_API void fqp_default_settings(fqp_settings *s);

@@ -36,7 +36,8 @@ class Book(ctypes.Structure):
                 ("gamma", c_void_p), ("kappa", c_void_p), ("tau", c_void_p),
                 ("band_lo", c_void_p), ("band_hi", c_void_p),
                 ("tax_ptr", c_void_p), ("tax_asset", c_void_p),
-                ("tax_brk", c_void_p), ("tax_slope", c_void_p)]
+                ("tax_brk", c_void_p), ("tax_slope", c_void_p),
+                ("warm_state", c_void_p)]
 
 
 class Settings(ctypes.Structure):
@@ -47,14 +48,16 @@ class Settings(ctypes.Structure):
                 ("polish_rounds", c_int32),
                 ("use_graph", c_int32), ("profile", c_int32),
                 ("time_limit_ms", c_double), ("precision", c_int32),
-                ("first_check", c_int32), ("warm_start", c_int32)]
+                ("first_check", c_int32), ("warm_start", c_int32),
+                ("debug_fail_alloc", c_int32), ("tile_rows", c_int32)]
 
 
 class Result(ctypes.Structure):
     _fields_ = [("w", c_void_p), ("status", c_void_p), ("iters", c_void_p),
                 ("r_prim", c_void_p), ("r_dual", c_void_p),
                 ("r_comp", c_void_p), ("obj", c_void_p), ("nu", c_void_p),
-                ("lam_cap", c_void_p), ("lam_band", c_void_p)]
+                ("lam_cap", c_void_p), ("lam_band", c_void_p),
+                ("state", c_void_p)]
 
 
 class Stats(ctypes.Structure):
@@ -63,7 +66,13 @@ class Stats(ctypes.Structure):
                 ("iter_kernel_ms", c_double), ("account_iters", c_double),
                 ("total_ms", c_double), ("workspace_bytes", c_size_t),
                 ("polish_solves", c_int32), ("polish_gated", c_int32),
-                ("contract_kernel_ms", c_double)]
+                ("contract_kernel_ms", c_double), ("phase_ms", c_double * 4),
+                ("graph_reused", c_int32), ("workspace_requests", c_int32)]
+
+
+def state_floats(m: int, n: int, n_groups: int) -> int:
+    """Floats of an ADMM state block (fqp_book.warm_state / fqp_result.state)."""
+    return m * n + 2 * m * n_groups + m
 
 
 EXPORTS = ("fqp_default_settings", "fqp_create", "fqp_solve_batch",

@@ -28,18 +28,6 @@ enum AccPar {
   P_ALPHA, P_RHOB, P_CLASS, P_HASTAX, kNPar = 12
 };
 
-// per-account integer state
-enum AccState { S_ACTIVE = 0, S_STATUS, S_ITERS, kNState = 4 };
-
-// fused-iteration statistics per (row tile, account), [n_rt][m][kNStat]
-enum Stat { ST_RPRIM = 0, ST_RDUAL, ST_TURN, ST_NFREE, kNStat = 4 };
-
-// held-asset record: w0 and, when taxed, the lot data
-struct HoldRec {
-  float w0;
-  int32_t tax;   // index into tax arrays or -1
-};
-
 // ---------------------------------------------------------------------------
 // separable proximal step of phi_i + lam|. - w0| + box  (float32)
 //

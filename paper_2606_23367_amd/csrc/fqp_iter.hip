@@ -21,12 +21,14 @@
 //   K = F~^-1 + B~^T Delta^-1 B~,  c = B~^T Delta^-1 1,  q = K^-1 c,
 //   sigma1 = 1^T Delta^-1 1 - c^T q.
 //
-// One fused kernel per iteration streams the book once: back-projection
-// B~ p (MFMA), x, relaxation, prox, dual update, and the contraction
-// B~^T Delta^-1 r of the NEXT iteration (MFMA), with per-account partials.
-// A small per-account kernel then reduces the partials and solves in factor
-// space.  The cap multiplier is updated between passes by a damped Newton
-// step on the turnover of the current z (the prox uses the previous value).
+// The ADMM state kept per (account, asset) is v = xh + u only.  One iteration
+// is four launches (below): CONTRACT streams v and writes the per-row-tile
+// partials of t = B~^T Delta^-1 r (MFMA) and z = prox(v; lam*); a small
+// per-account kernel reduces the partials and solves in factor space (nu,
+// p); PROJECT streams v and z again and applies the back-projection B~ p
+// (MFMA), the x-step and the over-relaxation, writing the new v; the cap
+// kernel finds the exact turnover-cap multiplier lam* of the new v per
+// account (a safeguarded Newton search on the piecewise-linear turnover).
 #include <algorithm>
 
 #include <hip/hip_ext.h>
@@ -332,10 +334,6 @@ __global__ __launch_bounds__(256, 2) void iter_kernel(IterArgs A) {
   for (int c = 0; c < NCH; ++c)
 #pragma unroll
     for (int r = 0; r < 16; ++r) T[c][r] = 0.f;
-  float st_rp[16];
-#pragma unroll
-  for (int r = 0; r < 16; ++r) st_rp[r] = 0.f;
-
   float* Rw = Rt + w * 32 * 33;
   const int row_begin = tm.row_begin;
 
@@ -411,7 +409,6 @@ __global__ __launch_bounds__(256, 2) void iter_kernel(IterArgs A) {
           const float x = (r0v + q1.z - X[r]) * iDelta;
           const float alpha = q1.w;
           A.v[off] = alpha * x + (1.f - alpha) * z + u;
-          st_rp[r] = fmaxf(st_rp[r], fabsf(x - z));
         }
       }
       if (MODE == MODE_CONTRACT) Rw[m * 33 + l32] = Rp;
@@ -434,30 +431,7 @@ __global__ __launch_bounds__(256, 2) void iter_kernel(IterArgs A) {
   }
 
   const size_t M = A.m_total;
-  if (MODE == MODE_PROJECT) {
-    // primal residual estimate max |x - z| per account
-#pragma unroll
-    for (int r = 0; r < 16; ++r)
-#pragma unroll
-      for (int o = 16; o >= 1; o >>= 1) st_rp[r] = fmaxf(st_rp[r], __shfl_xor(st_rp[r], o, 32));
-    __syncthreads();
-    float* sred = Xs + kTM * BS;           // [4][32]
-    if (l32 == 0) {
-#pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int m = 8 * (r >> 2) + 4 * hi + (r & 3);
-        sred[w * kTM + m] = st_rp[r];
-      }
-    }
-    __syncthreads();
-    if (tid < kTM) {
-      const int a = Aid[tid];
-      if (a >= 0)
-        A.stat[((size_t)tm.rt * M + a) * kNStat + ST_RPRIM] =
-            fmaxf(fmaxf(sred[tid], sred[kTM + tid]), fmaxf(sred[2 * kTM + tid], sred[3 * kTM + tid]));
-    }
-    return;
-  }
+  if (MODE == MODE_PROJECT) return;
 
   __syncthreads();                       // all waves done with Bs / Rt
   float* red = Bs;                       // [4][32][kp]
@@ -601,10 +575,6 @@ __global__ __launch_bounds__(256, 3) void iter_kernel_bf(IterArgs A) {
   for (int c = 0; c < NCH; ++c)
 #pragma unroll
     for (int r = 0; r < 16; ++r) T[c][r] = 0.f;
-  float st_rp[16];
-#pragma unroll
-  for (int r = 0; r < 16; ++r) st_rp[r] = 0.f;
-
   __bf16* RwH = reinterpret_cast<__bf16*>(Xs) + w * 2 * 32 * kRwS;
   int* HIdx = reinterpret_cast<int*>(Xs + bf_held_offset<NCH, MODE>() + w * kHeldFloats);
   float4* HRec = reinterpret_cast<float4*>(HIdx + kHS);
@@ -731,7 +701,6 @@ __global__ __launch_bounds__(256, 3) void iter_kernel_bf(IterArgs A) {
           const float x = (r0v + q1.z - X[r]) * iDelta;
           const float alpha = q1.w;
           A.v[off] = alpha * x + (1.f - alpha) * z + u;
-          st_rp[r] = fmaxf(st_rp[r], fabsf(x - z));
         }
       }
     }
@@ -810,28 +779,7 @@ __global__ __launch_bounds__(256, 3) void iter_kernel_bf(IterArgs A) {
   }
 
   const size_t M = A.m_total;
-  if (MODE == MODE_PROJECT) {
-#pragma unroll
-    for (int r = 0; r < 16; ++r)
-#pragma unroll
-      for (int o = 16; o >= 1; o >>= 1) st_rp[r] = fmaxf(st_rp[r], __shfl_xor(st_rp[r], o, 32));
-    float* sred = Xs;                      // [4][32]
-    if (l32 == 0) {
-#pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int m = 8 * (r >> 2) + 4 * hi + (r & 3);
-        sred[w * kTM + m] = st_rp[r];
-      }
-    }
-    __syncthreads();
-    if (tid < kTM) {
-      const int a = Aid[tid];
-      if (a >= 0)
-        A.stat[((size_t)tm.rt * M + a) * kNStat + ST_RPRIM] =
-            fmaxf(fmaxf(sred[tid], sred[kTM + tid]), fmaxf(sred[2 * kTM + tid], sred[3 * kTM + tid]));
-    }
-    return;
-  }
+  if (MODE == MODE_PROJECT) return;
 
   __syncthreads();                       // all waves done with their transposes
   float* red = Xs;                       // [4][32][kp]
@@ -939,6 +887,9 @@ __global__ __launch_bounds__(kCapT, 8) void cap_kernel(IterArgs A) {
   const float* va = A.v + (size_t)a * n;
   const size_t wa = (size_t)a * A.W;
   float vr[kCapQ];
+  // bit q: slot q is an eligible, unheld row inside the book (box [lb, ub]);
+  // excluded rows and the padding past n have the box [0, 0] and add nothing
+  unsigned box_bits = 0u;
   // every load of the account issued before any is used
   {
     float x[kCapQ];
@@ -957,13 +908,15 @@ __global__ __launch_bounds__(kCapT, 8) void cap_kernel(IterArgs A) {
     for (int q = 0; q < kCapQ; ++q) {
       const int i = q * kCapT + tid;
       const int b = i & 31;
-      const bool el = (ew[q] >> b) & 1u;
+      const bool el = i < n && ((ew[q] >> b) & 1u);
       float keep = el ? x[q] : 0.f;
-      if ((hw[q] >> b) & 1u) {
+      if (i < n && ((hw[q] >> b) & 1u)) {
         const int j = A.hold_pre[wa + (i >> 5)] + popc_below(hw[q], b);
         s_hv[j] = x[q];
         s_hel[j] = el ? 1 : 0;
         keep = 0.f;
+      } else if (el) {
+        box_bits |= 1u << q;
       }
       vr[q] = keep;
     }
@@ -990,10 +943,11 @@ __global__ __launch_bounds__(kCapT, 8) void cap_kernel(IterArgs A) {
 #pragma unroll
     for (int q = 0; q < kCapQ; ++q) {
       if (q * kCapT < n) {                 // uniform
+        const bool in_box = (box_bits >> q) & 1u;
         float z = fminf(vr[q] + th, fmaxf(0.f, vr[q] - th));
-        z = fminf(fmaxf(z, lbp), ubp);
+        z = in_box ? fminf(fmaxf(z, lbp), ubp) : 0.f;
         g += fabsf(z);
-        nf += (z != 0.f && z > lbp && z < ubp) ? 1.f : 0.f;
+        nf += (in_box && z != 0.f && z > lbp && z < ubp) ? 1.f : 0.f;
       }
     }
     if (tid < H) {
@@ -1151,7 +1105,6 @@ __global__ __launch_bounds__(kKsT) void ksolve_kernel(KArgs A) {
   __shared__ float tsp[kKsT];                // split partial sums
   __shared__ float pprime[kMaxKp];
   __shared__ double s_nu;
-  __shared__ float sst[kKsT / 64];     // per-wave max of the primal residual
   const int slot = blockIdx.x;
   if (slot >= *A.m_act) return;
   const int a = A.act[slot];
@@ -1159,7 +1112,6 @@ __global__ __launch_bounds__(kKsT) void ksolve_kernel(KArgs A) {
   const int kp = A.kp, k = A.k, G = A.G, kg = k + G;
   const size_t M = A.m_total;
   const int n_rt = tile_map(*A.m_act, A.n, A.nblk, 0).n_rt;
-  const int n_rt_p = tile_map(*A.m_act, A.n, A.nblk_p, 0).n_rt;   // PROJECT's row tiles
   float* par = A.par + (size_t)a * kNPar;
   const int cls = (int)par[P_CLASS];
   const float* Kinv = A.Kinv + (size_t)cls * kp * kp;
@@ -1192,16 +1144,6 @@ __global__ __launch_bounds__(kKsT) void ksolve_kernel(KArgs A) {
     float s = 0.f;
     for (int q = 0; q < nsp; ++q) s += tsp[q * kp + j];
     t[j] = s;
-  }
-  {
-    // max over the row tiles of the primal residual estimate, one row tile
-    // per thread
-    float v = 0.f;
-    for (int rt = tid; rt < n_rt_p; rt += kKsT)
-      v = fmaxf(v, A.stat[((size_t)rt * M + a) * kNStat + ST_RPRIM]);
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
-    if ((tid & 63) == 0) sst[tid >> 6] = v;
   }
   __syncthreads();
   // band terms: t += (K - F~^-1)[:, G] rho_b (zb - vb);  s0 += c_G . same
@@ -1278,7 +1220,6 @@ __global__ __launch_bounds__(kKsT) void ksolve_kernel(KArgs A) {
   }
   __syncthreads();
   // band ADMM block:  A x = p'_G / rho_b
-  float band_res = 0.f;
   if (G > 0 && tid < G) {
     const int g = tid;
     const float alpha = par[P_ALPHA];
@@ -1289,17 +1230,10 @@ __global__ __launch_bounds__(kKsT) void ksolve_kernel(KArgs A) {
     float zn = zh + vb[g];
     zn = fminf(fmaxf(zn, A.blo[(size_t)a * G + g]), A.bhi[(size_t)a * G + g]);
     vb[g] = vb[g] + zh - zn;
-    band_res = fabsf(ax - zn);
     zb[g] = zn;
   }
-  // band residual: only the first G <= 64 threads (wave 0) contribute
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) band_res = fmaxf(band_res, __shfl_xor(band_res, o, 64));
   if (tid == 0) {
     par[P_NU] = (float)nu;
-    float rp = band_res;
-    for (int q = 0; q < kKsT / 64; ++q) rp = fmaxf(rp, sst[q]);
-    A.res[(size_t)a * 4 + 0] = rp;
     A.iters[a] += 1;
   }
 }

@@ -34,7 +34,6 @@ struct IterArgs {
   const float* par;          // [m][kNPar]
   float* par_rw;             // same array, written by the cap kernel
   float* part;               // [row tiles][m][kp] (at most one per 128-row chunk)
-  float* stat;               // [row tiles][m][kNStat]
   float* zs;                 // [m][n] z = prox(v; lam*) of the current v: the
                              // bf16-split CONTRACT pass writes it, PROJECT reads it
 };
@@ -45,7 +44,6 @@ struct KArgs {
   const int* m_act;
   const int* act;
   const float* part;
-  const float* stat;
   float* par;                // [m][kNPar]
   float* pp;                 // [m][kp]
   const float* Kinv;         // [ncls][kp][kp]
@@ -57,7 +55,6 @@ struct KArgs {
   float* vb;                 // [m][G]
   const float* blo;          // [m][G]
   const float* bhi;          // [m][G]
-  float* res;                // [m][4]  ADMM residual estimates
   int* iters;                // [m]
 };
 

@@ -34,15 +34,22 @@ __global__ void init_accounts_kernel(int m, int G, const int* cls, const float* 
                                      const float* ub, const float* tau, const int32_t* tax_ptr,
                                      float alpha, float rho_b, float* par, float* zb, float* vb,
                                      const float* blo, const float* bhi, int* iters,
-                                     int32_t* pstate, int npstate, int warm) {
+                                     int32_t* pstate, int npstate, int warm,
+                                     const float* wz, const float* wv, const float* wl,
+                                     const int32_t* st_in, int32_t* st_out) {
   const int a = blockIdx.x * blockDim.x + threadIdx.x;
   if (a >= m) return;
+  // statuses of the validation pass reach the caller's array only here,
+  // after every workspace request of the call has succeeded
+  st_out[a] = st_in[a];
   float* p = par + (size_t)a * kNPar;
   const int c = cls[a];
   p[P_GAMMA] = gamma[a];
   p[P_RHO] = rho_cls[c];
   p[P_KAPPA] = kappa[a];
   // a warm start keeps the last cap multiplier and band state when finite
+  // (from the caller's state block when given, else from the handle)
+  if (wl) p[P_LAM] = wl[a];
   if (!warm || !(isfinite(p[P_LAM]) && p[P_LAM] >= 0.f)) p[P_LAM] = 0.f;
   p[P_NU] = 0.f;
   p[P_LB] = lb[a];
@@ -54,12 +61,29 @@ __global__ void init_accounts_kernel(int m, int G, const int* cls, const float* 
   p[P_HASTAX] = (tax_ptr && tax_ptr[a + 1] > tax_ptr[a]) ? 1.f : 0.f;
   for (int g = 0; g < G; ++g) {
     const size_t e = (size_t)a * G + g;
+    if (wz) { zb[e] = wz[e]; vb[e] = wv[e]; }
     if (warm && isfinite(zb[e]) && isfinite(vb[e])) continue;
     zb[e] = fminf(fmaxf(0.f, blo[e]), bhi[e]);
     vb[e] = 0.f;
   }
   iters[a] = 0;
   for (int q = 0; q < npstate; ++q) pstate[(size_t)a * npstate + q] = 0;
+}
+
+// the ADMM state of a finished solve for the caller: v, band state, lam
+__global__ void export_state_kernel(int m, int n, int G, const float* v, const float* zb,
+                                    const float* vb, const float* par, float* out) {
+  const size_t mn = (size_t)m * n;
+  const size_t total = mn + 2 * (size_t)m * G + m;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (size_t)gridDim.x * blockDim.x) {
+    float x;
+    if (e < mn) x = v[e];
+    else if (e < mn + (size_t)m * G) x = zb[e - mn];
+    else if (e < mn + 2 * (size_t)m * G) x = vb[e - mn - (size_t)m * G];
+    else x = par[(e - mn - 2 * (size_t)m * G) * kNPar + P_LAM];
+    out[e] = x;
+  }
 }
 
 // warm start: a non-finite entry of the kept state (an account that failed
@@ -132,16 +156,29 @@ struct DevBuf {
   size_t bytes = 0;
 };
 
+// everything a captured block of iterations depends on: a later call whose
+// key is byte-identical replays the same executable graph
+struct GraphKey {
+  IterArgs ia;
+  KArgs ka;
+  unsigned gx, gy, gpx, gpy;
+  int m, kp, precision, count, any_cap, cap_resident;
+};
+
 struct fqp_handle {
   int device = 0;
   int n_cu = 0;                   // compute units of the device
   hipStream_t stream = nullptr;   // the handle's own stream (capturable)
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  hipEvent_t ev_t[4] = {nullptr, nullptr, nullptr, nullptr};   // phase timing
   std::string err;
   fqp_stats stats{};
   std::map<std::string, DevBuf> bufs;
   size_t total_bytes = 0;
   bool configured = false;
+  // debug hook of the current call: the workspace request with this number
+  // (1-based) fails as a device allocation failure would
+  int fail_at = 0, requests = 0;
   // context of the last successful solve, for fqp_adjoint_batch
   bool have_last = false;
   // shape of the last completed solve, whose ADMM state a warm start reuses
@@ -151,12 +188,33 @@ struct fqp_handle {
   std::vector<int32_t> pass_iter;
   std::vector<double> pass_ms;
   AdjArgs last{};
+  // executable graph of one block of iterations, kept across calls
+  hipGraphExec_t gexec = nullptr;
+  hipGraph_t graph = nullptr;
+  GraphKey gkey;
+  bool have_graph = false;
+
+  void drop_graph() {
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    if (graph) (void)hipGraphDestroy(graph);
+    gexec = nullptr;
+    graph = nullptr;
+    have_graph = false;
+  }
 
   template <typename T>
   T* get(const char* name, size_t count, fqp_error* e) {
+    ++requests;
+    if (fail_at > 0 && requests == fail_at) {
+      *e = FQP_ERR_ALLOC;
+      err = std::string("workspace allocation failed (debug_fail_alloc): ") + name;
+      return nullptr;
+    }
     DevBuf& b = bufs[name];
     const size_t need = count * sizeof(T) + 256;
     if (b.bytes < need) {
+      // a captured graph may point into the buffer being replaced
+      drop_graph();
       if (b.p) { (void)hipFree(b.p); total_bytes -= b.bytes; }
       b.p = nullptr;
       b.bytes = 0;
@@ -193,6 +251,9 @@ void fqp_default_settings(fqp_settings* s) {
   s->time_limit_ms = 0.0;
   s->precision = FQP_PREC_BF16X3;
   s->first_check = 0;
+  s->warm_start = 0;
+  s->debug_fail_alloc = 0;
+  s->tile_rows = 0;
 }
 
 const char* fqp_error_string(int e) {
@@ -243,13 +304,17 @@ fqp_error fqp_create(fqp_handle** h, int device) {
     hh->n_cu = 0;
   }
   // default priority, non-blocking with respect to the legacy stream
-  if (hipStreamCreateWithFlags(&hh->stream, hipStreamNonBlocking) != hipSuccess ||
-      hipEventCreateWithFlags(&hh->ev_in, hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&hh->ev_out, hipEventDisableTiming) != hipSuccess) {
+  bool ok = hipStreamCreateWithFlags(&hh->stream, hipStreamNonBlocking) == hipSuccess &&
+            hipEventCreateWithFlags(&hh->ev_in, hipEventDisableTiming) == hipSuccess &&
+            hipEventCreateWithFlags(&hh->ev_out, hipEventDisableTiming) == hipSuccess;
+  for (int q = 0; q < 4 && ok; ++q) ok = hipEventCreate(&hh->ev_t[q]) == hipSuccess;
+  if (!ok) {
     (void)hipGetLastError();
     if (hh->stream) (void)hipStreamDestroy(hh->stream);
     if (hh->ev_in) (void)hipEventDestroy(hh->ev_in);
     if (hh->ev_out) (void)hipEventDestroy(hh->ev_out);
+    for (int q = 0; q < 4; ++q)
+      if (hh->ev_t[q]) (void)hipEventDestroy(hh->ev_t[q]);
     delete hh;
     (void)hipSetDevice(cur);
     return FQP_ERR_HIP;
@@ -265,11 +330,14 @@ void fqp_destroy(fqp_handle* h) {
   (void)hipGetDevice(&cur);
   (void)hipSetDevice(h->device);
   if (h->stream) (void)hipStreamSynchronize(h->stream);
+  h->drop_graph();
   for (auto& kv : h->bufs)
     if (kv.second.p) (void)hipFree(kv.second.p);
   if (h->stream) (void)hipStreamDestroy(h->stream);
   if (h->ev_in) (void)hipEventDestroy(h->ev_in);
   if (h->ev_out) (void)hipEventDestroy(h->ev_out);
+  for (int q = 0; q < 4; ++q)
+    if (h->ev_t[q]) (void)hipEventDestroy(h->ev_t[q]);
   (void)hipSetDevice(cur);
   delete h;
 }
@@ -317,16 +385,24 @@ extern "C" fqp_error fqp_solve_batch(fqp_handle* h, const fqp_universe* U, const
   h->pass_iter.clear();
   h->pass_ms.clear();
   auto t_start = std::chrono::steady_clock::now();
+  auto ms_since_start = [&]() {
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start)
+        .count();
+  };
   h->have_last = false;
   if (!U || !P || !R) { h->err = "null universe/book/result"; return FQP_ERR_INVALID_ARG; }
   fqp_settings S;
   if (S_in) S = *S_in; else fqp_default_settings(&S);
+  h->fail_at = S.debug_fail_alloc;
+  h->requests = 0;
   const int n = U->n, k = U->k, G = U->n_groups, m = P->m;
   if (n < 1 || k < 1 || m < 1 || G < 0) { h->err = "non-positive size"; return FQP_ERR_INVALID_ARG; }
-  // the kept state is reused only by a solve of the same shape; a solve
-  // that fails part-way leaves no state to reuse
-  const bool warm = S.warm_start && h->warm_ok && h->warm_m == m && h->warm_n == n &&
-                    h->warm_G == G;
+  // a caller's state block, or the state the handle kept from its last
+  // solve of the same shape; a solve that fails part-way leaves no state
+  const bool warm_kept = S.warm_start && h->warm_ok && h->warm_m == m && h->warm_n == n &&
+                         h->warm_G == G;
+  const bool warm_given = S.warm_start && P->warm_state != nullptr;
+  const bool warm = warm_kept || warm_given;
   h->warm_ok = false;
   if (!U->B || !U->f || !U->d || !P->mu || !P->w0 || !P->lb || !P->ub || !P->gamma ||
       !P->kappa || !P->tau || !R->w || !R->status) {
@@ -342,7 +418,8 @@ extern "C" fqp_error fqp_solve_batch(fqp_handle* h, const fqp_universe* U, const
     return FQP_ERR_INVALID_ARG;
   }
   if (S.max_iter < 1 || S.check_every < 1 || !(S.alpha > 0.f && S.alpha < 2.f) ||
-      S.polish_rounds < 1 || (S.precision != FQP_PREC_FP32 && S.precision != FQP_PREC_BF16X3)) {
+      S.polish_rounds < 1 || (S.precision != FQP_PREC_FP32 && S.precision != FQP_PREC_BF16X3) ||
+      S.tile_rows < 0 || S.debug_fail_alloc < 0) {
     h->err = "invalid settings";
     return FQP_ERR_INVALID_ARG;
   }
@@ -390,6 +467,7 @@ extern "C" fqp_error fqp_solve_batch(fqp_handle* h, const fqp_universe* U, const
     h->configured = true;
   }
   const int W = (n + 31) / 32;
+  HIP_CHECK(hipEventRecord(h->ev_t[0], st));         // start of the device lane
 
   // ---- classes: distinct gamma values share one factor-space factorisation
   std::vector<float> gam_h(m);
@@ -419,6 +497,8 @@ extern "C" fqp_error fqp_solve_batch(fqp_handle* h, const fqp_universe* U, const
   std::vector<float> rho_cls(ncls, rho);
 
   // ---- workspace ----------------------------------------------------------
+  // Every request comes before the first write to the caller's outputs: a
+  // failed allocation returns FQP_ERR_ALLOC with the outputs untouched.
   WS(Bt, float, "Bt", (size_t)n * kp);
   const int gram_rows = 128;
   const int nparts = (n + gram_rows - 1) / gram_rows;
@@ -440,11 +520,11 @@ extern "C" fqp_error fqp_solve_batch(fqp_handle* h, const fqp_universe* U, const
   WS(hold_ptr, int32_t, "hold_ptr", (size_t)m + 1);
   WS(hold_w0, float, "hold_w0", (size_t)m * n);
   WS(hold_tax, int32_t, "hold_tax", (size_t)m * n);
+  WS(st_in, int32_t, "status_in", (size_t)m);
   WS(par, float, "par", (size_t)m * kNPar);
   WS(pp, float, "pp", (size_t)m * kp);
   WS(zb, float, "zb", (size_t)m * (G > 0 ? G : 1));
   WS(vb, float, "vb", (size_t)m * (G > 0 ? G : 1));
-  WS(res, float, "res", (size_t)m * 4);
   WS(iters, int, "iters", (size_t)m);
   WS(act, int, "act", (size_t)m);
   WS(m_act, int, "m_act", 1);
@@ -462,13 +542,19 @@ extern "C" fqp_error fqp_solve_batch(fqp_handle* h, const fqp_universe* U, const
 
   // iteration geometry, per pass: (row tiles x account tiles) workgroups, as
   // many as the compute units hold at once (one round: a partial second
-  // round of workgroups would double the pass), else ~1024
+  // round of workgroups would double the pass), else ~1024; tile_rows
+  // fixes the rows of a workgroup instead (whole 128-row chunks)
   const int acc_tiles = (m + kTM - 1) / kTM;
   auto row_tiles = [&](int mode) {
-    const int per_cu = iter_blocks_per_cu(kp, S.precision, mode);
-    const int slots = (per_cu > 0 && h->n_cu > 0) ? per_cu * h->n_cu : 1024;
-    const int target_rt = std::max(1, slots / acc_tiles);
-    int chunks = (n + kRowsPerChunk * target_rt - 1) / (kRowsPerChunk * target_rt);
+    int chunks;
+    if (S.tile_rows > 0) {
+      chunks = S.tile_rows;
+    } else {
+      const int per_cu = iter_blocks_per_cu(kp, S.precision, mode);
+      const int slots = (per_cu > 0 && h->n_cu > 0) ? per_cu * h->n_cu : 1024;
+      const int target_rt = std::max(1, slots / acc_tiles);
+      chunks = (n + kRowsPerChunk * target_rt - 1) / (kRowsPerChunk * target_rt);
+    }
     chunks = std::max(1, std::min(chunks, 64));
     const int rows_per_wg = chunks * kRowsPerChunk;
     return (n + rows_per_wg - 1) / rows_per_wg;            // at the full batch
@@ -476,7 +562,6 @@ extern "C" fqp_error fqp_solve_batch(fqp_handle* h, const fqp_universe* U, const
   const int n_rt = row_tiles(0), n_rt_p = row_tiles(1);
   const int max_rt = (n + kRowsPerChunk - 1) / kRowsPerChunk;   // short active lists
   WS(part, float, "part", (size_t)max_rt * m * kp);
-  WS(stat, float, "stat", (size_t)max_rt * m * kNStat);
   // bf16 hi/lo copies of B~ for the split-precision contractions
   const int npad = ((n + kRowsPerChunk - 1) / kRowsPerChunk) * kRowsPerChunk;
   const bool split = S.precision == FQP_PREC_BF16X3 && kp <= kMaxKpBf;
@@ -485,7 +570,6 @@ extern "C" fqp_error fqp_solve_batch(fqp_handle* h, const fqp_universe* U, const
   WS(bt_lo, uint16_t, "bt_lo", nbf);
   WS(btt_hi, uint16_t, "btt_hi", nbf);
   WS(btt_lo, uint16_t, "btt_lo", nbf);
-  h->stats.workspace_bytes = h->total_bytes;
 
   // ---- universe ------------------------------------------------------------
   HIP_CHECK(launch_build_bt(n, k, G, kp, U->B, U->group, Bt, st));
@@ -500,7 +584,7 @@ extern "C" fqp_error fqp_solve_batch(fqp_handle* h, const fqp_universe* U, const
                              st));
   }
 
-  // ---- book -----------------------------------------------------------------
+  // ---- book: validation and held records (workspace only) ----------------
   PackArgs pk{};
   pk.n = n; pk.W = W; pk.m = m; pk.G = G;
   pk.mu = P->mu; pk.w0 = P->w0; pk.lb = P->lb; pk.ub = P->ub; pk.elig = P->eligible;
@@ -509,65 +593,10 @@ extern "C" fqp_error fqp_solve_batch(fqp_handle* h, const fqp_universe* U, const
   pk.tax_ptr = P->tax_ptr; pk.tax_asset = P->tax_asset; pk.tax_brk = P->tax_brk;
   pk.tax_slope = P->tax_slope;
   pk.hold = hold; pk.hold_pre = hold_pre; pk.hold_cnt = hold_cnt; pk.hold_ptr = hold_ptr;
-  pk.hold_w0 = hold_w0; pk.hold_tax = hold_tax; pk.status = R->status; pk.par = par;
+  pk.hold_w0 = hold_w0; pk.hold_tax = hold_tax; pk.status = st_in; pk.par = par;
   HIP_CHECK(launch_pack_count(pk, st));
   HIP_CHECK(launch_pack_scan(pk, st));
   HIP_CHECK(launch_pack_fill(pk, st));
-  hipLaunchKernelGGL(init_accounts_kernel, dim3((m + 255) / 256), dim3(256), 0, st, m, G, cls_d,
-                     rho_d, P->gamma, P->kappa, P->lb, P->ub, P->tau, P->tax_ptr, S.alpha, rho_b,
-                     par, zb, vb, P->band_lo, P->band_hi, iters, pstate, kPStateStride,
-                     warm ? 1 : 0);
-  HIP_CHECK(hipGetLastError());
-  if (warm) {
-    hipLaunchKernelGGL(sanitize_state_kernel, dim3(1024), dim3(256), 0, st, (size_t)m * n, v);
-    HIP_CHECK(hipGetLastError());
-  } else {
-    HIP_CHECK(hipMemsetAsync(v, 0, sizeof(float) * (size_t)m * n, st));
-  }
-  hipLaunchKernelGGL(compact_kernel, dim3(1), dim3(256), 0, st, m, R->status, act, m_act);
-  HIP_CHECK(hipGetLastError());
-
-  IterArgs ia{};
-  ia.n = n; ia.W = W;
-  ia.m_total = m; ia.m_act = m_act; ia.act = act; ia.Bt = Bt; ia.d = U->d; ia.mu = P->mu;
-  ia.v = v; ia.elig = P->eligible; ia.hold = hold; ia.hold_pre = hold_pre;
-  ia.hold_ptr = hold_ptr; ia.hold_w0 = hold_w0; ia.hold_tax = hold_tax;
-  ia.tax_brk = P->tax_brk; ia.tax_slope = P->tax_slope; ia.pp = pp; ia.par = par;
-  ia.par_rw = par;
-  ia.part = part; ia.stat = stat; ia.zs = z;
-  ia.npad = npad; ia.bt_hi = bt_hi; ia.bt_lo = bt_lo; ia.btt_hi = btt_hi; ia.btt_lo = btt_lo;
-  KArgs ka{};
-  ka.kp = kp; ka.k = k; ka.G = G; ka.n = n; ka.nblk = n_rt * acc_tiles; ka.m_total = m;
-  ka.nblk_p = n_rt_p * acc_tiles;
-  ka.m_act = m_act; ka.act = act;
-  ka.part = part; ka.stat = stat; ka.par = par; ka.pp = pp; ka.Kinv = Kinv; ka.cvec = cvec;
-  ka.qvec = qvec; ka.sig1 = sig1; ka.mbg = mbg; ka.zb = zb; ka.vb = vb;
-  ka.blo = G ? P->band_lo : nullptr; ka.bhi = G ? P->band_hi : nullptr;
-  ka.res = res; ka.iters = iters;
-  PolishArgs pa{};
-  pa.n = n; pa.k = k; pa.G = G; pa.kp = kp; pa.W = W; pa.m_total = m; pa.m_act = m_act;
-  pa.act = act; pa.Bt = Bt; pa.f = U->f; pa.d = U->d; pa.group = G ? U->group : nullptr;
-  pa.mu = P->mu; pa.z = z; pa.elig = P->eligible; pa.hold = hold; pa.hold_pre = hold_pre;
-  pa.hold_ptr = hold_ptr; pa.hold_w0 = hold_w0; pa.hold_tax = hold_tax;
-  pa.tax_brk = P->tax_brk; pa.tax_slope = P->tax_slope; pa.par = par; pa.zb = zb; pa.vb = vb;
-  pa.blo = G ? P->band_lo : nullptr; pa.bhi = G ? P->band_hi : nullptr;
-  pa.code = code; pa.code_next = code_next; pa.flist = flist; pa.wk = wk; pa.wk_stride = wks; pa.wout = R->w;
-  pa.mult = mult; pa.pstate = pstate; pa.gbase = gbase; pa.pcount = pcount;
-  pa.n_rb = n_rb; pa.gpart = gpart_p;
-  HIP_CHECK(hipMemsetAsync(pcount, 0, 2 * sizeof(int32_t), st));
-  pa.eps_prim = S.eps_prim; pa.eps_dual = S.eps_dual; pa.eps_comp = S.eps_comp;
-
-  std::vector<hipEvent_t> evs;
-  if (S.profile) {
-    evs.resize(4 * S.check_every);      // PROJECT pairs, then CONTRACT pairs
-    for (auto& ev : evs) HIP_CHECK(hipEventCreate(&ev));
-  }
-  struct EvGuard {
-    std::vector<hipEvent_t>* v;
-    ~EvGuard() { for (auto& ev : *v) (void)hipEventDestroy(ev); }
-  } evguard{&evs};
-  const dim3 igrid(n_rt, acc_tiles), igrid_p(n_rt_p, acc_tiles);
-  HIP_CHECK(hipMemsetAsync(stat, 0, sizeof(float) * (size_t)max_rt * m * kNStat, st));
   // the cap kernel runs only when some account has a finite cap; the
   // held-asset records are sized by the packed count
   bool any_cap = false;
@@ -588,9 +617,76 @@ extern "C" fqp_error fqp_solve_batch(fqp_handle* h, const fqp_universe* U, const
   const bool cap_resident = cap_resident_fits(n, max_held);
   WS(hold_rec, float4, "hold_rec", 2 * (size_t)std::max(n_held, 1));
   HIP_CHECK(launch_pack_rec(pk, hold_rec, n_held, st));
-  ia.hold_rec = hold_rec;
-  pa.hold_rec = hold_rec;
   h->stats.workspace_bytes = h->total_bytes;
+  h->stats.workspace_requests = h->requests;
+
+  // ---- first writes to the caller's outputs --------------------------------
+  const float* ws_v = warm_given ? P->warm_state : nullptr;
+  const float* ws_z = warm_given ? P->warm_state + (size_t)m * n : nullptr;
+  const float* ws_vb = warm_given ? ws_z + (size_t)m * G : nullptr;
+  const float* ws_l = warm_given ? ws_vb + (size_t)m * G : nullptr;
+  hipLaunchKernelGGL(init_accounts_kernel, dim3((m + 255) / 256), dim3(256), 0, st, m, G, cls_d,
+                     rho_d, P->gamma, P->kappa, P->lb, P->ub, P->tau, P->tax_ptr, S.alpha, rho_b,
+                     par, zb, vb, P->band_lo, P->band_hi, iters, pstate, kPStateStride,
+                     warm ? 1 : 0, G ? ws_z : nullptr, G ? ws_vb : nullptr, ws_l, st_in,
+                     R->status);
+  HIP_CHECK(hipGetLastError());
+  if (warm) {
+    if (warm_given)
+      HIP_CHECK(hipMemcpyAsync(v, ws_v, sizeof(float) * (size_t)m * n, hipMemcpyDeviceToDevice, st));
+    hipLaunchKernelGGL(sanitize_state_kernel, dim3(1024), dim3(256), 0, st, (size_t)m * n, v);
+    HIP_CHECK(hipGetLastError());
+  } else {
+    HIP_CHECK(hipMemsetAsync(v, 0, sizeof(float) * (size_t)m * n, st));
+  }
+  hipLaunchKernelGGL(compact_kernel, dim3(1), dim3(256), 0, st, m, R->status, act, m_act);
+  HIP_CHECK(hipGetLastError());
+
+  IterArgs ia;
+  std::memset(&ia, 0, sizeof(ia));       // byte-comparable (graph key)
+  ia.n = n; ia.W = W;
+  ia.m_total = m; ia.m_act = m_act; ia.act = act; ia.Bt = Bt; ia.d = U->d; ia.mu = P->mu;
+  ia.v = v; ia.elig = P->eligible; ia.hold = hold; ia.hold_pre = hold_pre;
+  ia.hold_ptr = hold_ptr; ia.hold_w0 = hold_w0; ia.hold_tax = hold_tax;
+  ia.tax_brk = P->tax_brk; ia.tax_slope = P->tax_slope; ia.pp = pp; ia.par = par;
+  ia.par_rw = par;
+  ia.part = part; ia.zs = z;
+  ia.npad = npad; ia.bt_hi = bt_hi; ia.bt_lo = bt_lo; ia.btt_hi = btt_hi; ia.btt_lo = btt_lo;
+  ia.hold_rec = hold_rec;
+  KArgs ka;
+  std::memset(&ka, 0, sizeof(ka));
+  ka.kp = kp; ka.k = k; ka.G = G; ka.n = n; ka.nblk = n_rt * acc_tiles; ka.m_total = m;
+  ka.nblk_p = n_rt_p * acc_tiles;
+  ka.m_act = m_act; ka.act = act;
+  ka.part = part; ka.par = par; ka.pp = pp; ka.Kinv = Kinv; ka.cvec = cvec;
+  ka.qvec = qvec; ka.sig1 = sig1; ka.mbg = mbg; ka.zb = zb; ka.vb = vb;
+  ka.blo = G ? P->band_lo : nullptr; ka.bhi = G ? P->band_hi : nullptr;
+  ka.iters = iters;
+  PolishArgs pa{};
+  pa.n = n; pa.k = k; pa.G = G; pa.kp = kp; pa.W = W; pa.m_total = m; pa.m_act = m_act;
+  pa.act = act; pa.Bt = Bt; pa.f = U->f; pa.d = U->d; pa.group = G ? U->group : nullptr;
+  pa.mu = P->mu; pa.z = z; pa.elig = P->eligible; pa.hold = hold; pa.hold_pre = hold_pre;
+  pa.hold_ptr = hold_ptr; pa.hold_w0 = hold_w0; pa.hold_tax = hold_tax;
+  pa.tax_brk = P->tax_brk; pa.tax_slope = P->tax_slope; pa.par = par; pa.zb = zb; pa.vb = vb;
+  pa.blo = G ? P->band_lo : nullptr; pa.bhi = G ? P->band_hi : nullptr;
+  pa.code = code; pa.code_next = code_next; pa.flist = flist; pa.wk = wk; pa.wk_stride = wks; pa.wout = R->w;
+  pa.mult = mult; pa.pstate = pstate; pa.gbase = gbase; pa.pcount = pcount;
+  pa.n_rb = n_rb; pa.gpart = gpart_p;
+  pa.hold_rec = hold_rec;
+  HIP_CHECK(hipMemsetAsync(pcount, 0, 2 * sizeof(int32_t), st));
+  pa.eps_prim = S.eps_prim; pa.eps_dual = S.eps_dual; pa.eps_comp = S.eps_comp;
+  HIP_CHECK(hipEventRecord(h->ev_t[1], st));         // end of setup
+
+  std::vector<hipEvent_t> evs;
+  if (S.profile) {
+    evs.resize(4 * S.check_every);      // PROJECT pairs, then CONTRACT pairs
+    for (auto& ev : evs) HIP_CHECK(hipEventCreate(&ev));
+  }
+  struct EvGuard {
+    std::vector<hipEvent_t>* v;
+    ~EvGuard() { for (auto& ev : *v) (void)hipEventDestroy(ev); }
+  } evguard{&evs};
+  const dim3 igrid(n_rt, acc_tiles), igrid_p(n_rt_p, acc_tiles);
   // one ADMM iteration: contract, factor-space solve, project, cap
   auto launch_iteration = [&](int c) -> hipError_t {
     // profiling: events stamped by the pass kernels' own start and end
@@ -610,21 +706,22 @@ extern "C" fqp_error fqp_solve_batch(fqp_handle* h, const fqp_universe* U, const
   };
 
   // ---- iteration blocks -------------------------------------------------------
-  hipGraphExec_t gexec = nullptr;
-  hipGraph_t graph = nullptr;
-  struct GraphGuard {
-    hipGraphExec_t* ge;
-    hipGraph_t* g;
-    ~GraphGuard() {
-      if (*ge) (void)hipGraphExecDestroy(*ge);
-      if (*g) (void)hipGraphDestroy(*g);
-    }
-  } gguard{&gexec, &graph};
+  // A whole block of check_every iterations is one captured graph, kept by
+  // the handle: a later call with the same arguments replays it
   const bool use_graph = S.use_graph && !S.profile;
+  GraphKey key;
+  std::memset(&key, 0, sizeof(key));
+  key.ia = ia; key.ka = ka;
+  key.gx = igrid.x; key.gy = igrid.y; key.gpx = igrid_p.x; key.gpy = igrid_p.y;
+  key.m = m; key.kp = kp; key.precision = S.precision; key.count = S.check_every;
+  key.any_cap = any_cap ? 1 : 0; key.cap_resident = cap_resident ? 1 : 0;
 
   auto run_block = [&](int count) -> fqp_error {
     if (use_graph && count == S.check_every) {
-      if (!gexec) {
+      if (h->have_graph && std::memcmp(&h->gkey, &key, sizeof(key)) == 0) {
+        h->stats.graph_reused = 1;
+      } else {
+        h->drop_graph();
         HIP_CHECK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
         for (int c = 0; c < count; ++c) {
           hipError_t e1 = launch_iteration(c);
@@ -636,10 +733,12 @@ extern "C" fqp_error fqp_solve_batch(fqp_handle* h, const fqp_universe* U, const
             return FQP_ERR_HIP;
           }
         }
-        HIP_CHECK(hipStreamEndCapture(st, &graph));
-        HIP_CHECK(hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0));
+        HIP_CHECK(hipStreamEndCapture(st, &h->graph));
+        HIP_CHECK(hipGraphInstantiate(&h->gexec, h->graph, nullptr, nullptr, 0));
+        h->gkey = key;
+        h->have_graph = true;
       }
-      HIP_CHECK(hipGraphLaunch(gexec, st));
+      HIP_CHECK(hipGraphLaunch(h->gexec, st));
     } else {
       for (int c = 0; c < count; ++c) HIP_CHECK(launch_iteration(c));
       if (S.profile) {
@@ -662,10 +761,19 @@ extern "C" fqp_error fqp_solve_batch(fqp_handle* h, const fqp_universe* U, const
     return FQP_OK;
   };
 
+  // device-lane phases: ev_t[1] marks the start of the current stretch of
+  // iterations, ev_t[2] its end, ev_t[3] the end of the certification pass
+  auto add_elapsed = [&](double& acc, hipEvent_t a0, hipEvent_t a1) -> fqp_error {
+    float ms = 0.f;
+    HIP_CHECK(hipEventElapsedTime(&ms, a0, a1));
+    acc += ms;
+    return FQP_OK;
+  };
   int done_iters = 0;
   int active = 0;
   HIP_CHECK(hipMemcpyAsync(&active, m_act, sizeof(int), hipMemcpyDeviceToHost, st));
   HIP_CHECK(hipStreamSynchronize(st));
+  if ((e = add_elapsed(h->stats.phase_ms[0], h->ev_t[0], h->ev_t[1])) != FQP_OK) return e;
   bool timed_out = false;
   while (active > 0 && done_iters < S.max_iter) {
     const int count = std::min(S.check_every, S.max_iter - done_iters);
@@ -674,6 +782,7 @@ extern "C" fqp_error fqp_solve_batch(fqp_handle* h, const fqp_universe* U, const
     done_iters += count;
     // no pass before first_check (blocks stay whole, so graph replays too)
     if (done_iters < S.first_check && done_iters < S.max_iter) continue;
+    HIP_CHECK(hipEventRecord(h->ev_t[2], st));
     // polish + certification rounds on z = prox(v; lam*)
     HIP_CHECK(launch_materialize_z(ia, m, z, st));
     pa.nf_gate = std::max(4 * k + 64, n / 8 + 4 * k);
@@ -688,14 +797,16 @@ extern "C" fqp_error fqp_solve_batch(fqp_handle* h, const fqp_universe* U, const
     hipLaunchKernelGGL(compact_kernel, dim3(1), dim3(256), 0, st, m, R->status, act, m_act);
     HIP_CHECK(hipGetLastError());
     HIP_CHECK(hipMemcpyAsync(&active, m_act, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIP_CHECK(hipEventRecord(h->ev_t[3], st));
     HIP_CHECK(hipStreamSynchronize(st));
+    if ((e = add_elapsed(h->stats.phase_ms[1], h->ev_t[1], h->ev_t[2])) != FQP_OK) return e;
+    if ((e = add_elapsed(h->stats.phase_ms[2], h->ev_t[2], h->ev_t[3])) != FQP_OK) return e;
+    std::swap(h->ev_t[1], h->ev_t[3]);             // the next stretch starts here
     h->pass_iter.push_back(done_iters);
-    h->pass_ms.push_back(std::chrono::duration<double, std::milli>(
-                             std::chrono::steady_clock::now() - t_start).count());
-    if (S.time_limit_ms > 0.0) {
-      double el = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() -
-                                                            t_start).count();
-      if (el > S.time_limit_ms) { timed_out = true; break; }
+    h->pass_ms.push_back(ms_since_start());
+    if (S.time_limit_ms > 0.0 && ms_since_start() > S.time_limit_ms) {
+      timed_out = true;
+      break;
     }
   }
   if (active > 0) {
@@ -715,6 +826,14 @@ extern "C" fqp_error fqp_solve_batch(fqp_handle* h, const fqp_universe* U, const
   }
   hipLaunchKernelGGL(finalize_kernel, dim3(m), dim3(256), 0, st, m, n, R->status, iters, *R);
   HIP_CHECK(hipGetLastError());
+  if (R->state) {
+    const size_t total = (size_t)m * n + 2 * (size_t)m * G + m;
+    const unsigned blocks = (unsigned)std::min<size_t>((total + 255) / 256, 4096);
+    hipLaunchKernelGGL(export_state_kernel, dim3(blocks), dim3(256), 0, st, m, n, G, v, zb, vb,
+                       par, R->state);
+    HIP_CHECK(hipGetLastError());
+  }
+  HIP_CHECK(hipEventRecord(h->ev_t[2], st));
   // count solved accounts and account-iterations
   std::vector<int32_t> st_h(m);
   std::vector<int> it_h(m);
@@ -723,6 +842,7 @@ extern "C" fqp_error fqp_solve_batch(fqp_handle* h, const fqp_universe* U, const
   HIP_CHECK(hipMemcpyAsync(st_h.data(), R->status, sizeof(int32_t) * m, hipMemcpyDeviceToHost, st));
   HIP_CHECK(hipMemcpyAsync(it_h.data(), iters, sizeof(int) * m, hipMemcpyDeviceToHost, st));
   HIP_CHECK(hipStreamSynchronize(st));
+  if ((e = add_elapsed(h->stats.phase_ms[3], h->ev_t[1], h->ev_t[2])) != FQP_OK) return e;
   for (int a = 0; a < m; ++a) {
     h->stats.n_solved += (st_h[a] == FQP_SOLVED);
     h->stats.account_iters += it_h[a];
@@ -741,8 +861,7 @@ extern "C" fqp_error fqp_solve_batch(fqp_handle* h, const fqp_universe* U, const
   }
   h->warm_ok = true;
   h->warm_m = m; h->warm_n = n; h->warm_G = G;
-  h->stats.total_ms =
-      std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+  h->stats.total_ms = ms_since_start();
   return FQP_OK;
 }
 

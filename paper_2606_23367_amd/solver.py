@@ -150,9 +150,19 @@ class Solver:
         return s
 
     def solve(self, P: DeviceProblem, out: Optional[dict] = None, stream=None,
+              warm_state: Optional[torch.Tensor] = None, want_state: bool = False,
               **settings) -> dict:
+        """Solve every account of P.  ``warm_state`` (float32, the ``state``
+        output of an earlier solve of the same accounts, from any Solver)
+        seeds a warm start when settings carry warm_start=1; ``want_state``
+        adds that output ("state") for a later warm start."""
         dev = P.mu.device
         m, n, G = P.m, P.n, P.G
+        nstate = _lib.state_floats(m, n, G)
+        if warm_state is not None:
+            if warm_state.dtype != torch.float32 or warm_state.numel() != nstate \
+                    or not warm_state.is_contiguous() or warm_state.device != dev:
+                raise ValueError(f"warm_state: {nstate} contiguous float32 values on {dev}")
         if out is None:
             out = dict(
                 w=torch.empty((m, n), dtype=torch.float64, device=dev),
@@ -167,6 +177,8 @@ class Solver:
                 lam_band=torch.zeros((m, max(G, 1)), dtype=torch.float64,
                                      device=dev),
             )
+        if want_state and "state" not in out:
+            out["state"] = torch.empty(nstate, dtype=torch.float32, device=dev)
         U = _lib.Universe(n=n, k=P.k, n_groups=G, B=_ptr(P.B), f=_ptr(P.f),
                           d=_ptr(P.d), group=_ptr(P.group))
         Bk = _lib.Book(m=m, mu=_ptr(P.mu), w0=_ptr(P.w0), lb=_ptr(P.lb),
@@ -175,13 +187,14 @@ class Solver:
                        tau=_ptr(P.tau), band_lo=_ptr(P.band_lo),
                        band_hi=_ptr(P.band_hi), tax_ptr=_ptr(P.tax_ptr),
                        tax_asset=_ptr(P.tax_asset), tax_brk=_ptr(P.tax_brk),
-                       tax_slope=_ptr(P.tax_slope))
+                       tax_slope=_ptr(P.tax_slope), warm_state=_ptr(warm_state))
         R = _lib.Result(w=_ptr(out["w"]), status=_ptr(out["status"]),
                         iters=_ptr(out["iters"]), r_prim=_ptr(out["r_prim"]),
                         r_dual=_ptr(out["r_dual"]),
                         r_comp=_ptr(out["r_comp"]), obj=_ptr(out["obj"]),
                         nu=_ptr(out["nu"]), lam_cap=_ptr(out["lam_cap"]),
-                        lam_band=_ptr(out["lam_band"]) if G else None)
+                        lam_band=_ptr(out["lam_band"]) if G else None,
+                        state=_ptr(out.get("state")))
         S = self.settings(**settings)
         if stream is None:
             stream = torch.cuda.current_stream(dev)
@@ -194,6 +207,9 @@ class Solver:
                 f" {self.lib.fqp_last_error(self.h).decode()}")
         self._last_shape = (m, n, P.k)
         self._last_keep = (P, out)        # buffers the adjoint reads
+        # the handle keeps the state of its last solve only: a backward
+        # through an earlier solve must notice that it was replaced
+        self.generation = getattr(self, "generation", 0) + 1
         return out
 
     def adjoint(self, dL_dw: torch.Tensor, stream=None):
@@ -218,7 +234,9 @@ class Solver:
     def stats(self) -> dict:
         st = _lib.Stats()
         self.lib.fqp_get_stats(self.h, ctypes.byref(st))
-        return {name: getattr(st, name) for name, _ in _lib.Stats._fields_}
+        out = {name: getattr(st, name) for name, _ in _lib.Stats._fields_}
+        out["phase_ms"] = [float(x) for x in st.phase_ms]
+        return out
 
     def pass_times(self) -> list:
         """[(ADMM iterations before the pass, ms from the call's start to the
@@ -251,12 +269,18 @@ class FqpFunction(torch.autograd.Function):
                     B=B.detach().to(torch.float32).contiguous())
         out = solver.solve(P, **settings)
         ctx.solver = solver
+        ctx.generation = solver.generation
         ctx.keep = (P, out)
         ctx.dtypes = (mu.dtype, B.dtype)
         return out["w"].clone()
 
     @staticmethod
     def backward(ctx, grad_w):
+        if ctx.solver.generation != ctx.generation:
+            raise RuntimeError(
+                "FqpFunction.backward: the Solver has solved another book since this "
+                "forward (the adjoint differentiates the handle's last solve only); use "
+                "one Solver per differentiable call, or run backward before the next solve")
         dmu, dB = ctx.solver.adjoint(grad_w)
         return dmu.to(ctx.dtypes[0]), dB.to(ctx.dtypes[1]), None, None, None
 

@@ -37,9 +37,25 @@ def shape_key(P: DeviceProblem, precision: int) -> str:
     has_tax = P.tax_ptr is not None and int(P.tax_ptr[-1].item()) > 0
     has_cap = bool(torch.isfinite(P.tau).any().item())
     ub = float(P.ub.max().item())
+    lb = float(P.lb.min().item())
     gam = float(P.gamma.max().item())
+    kap = float(P.kappa.max().item())
     return (f"n{P.n}_k{P.k}_g{P.G}_tax{int(has_tax)}_cap{int(has_cap)}"
-            f"_elig{int(P.eligible is not None)}_ub{ub:.3g}_gam{gam:.3g}_p{precision}")
+            f"_elig{int(P.eligible is not None)}_lb{lb:.3g}_ub{ub:.3g}_gam{gam:.3g}"
+            f"_kap{kap:.3g}_p{precision}")
+
+
+def tune_key(P: DeviceProblem, precision: int, grid: dict, sample: int, n_second: int,
+             finalists: int) -> str:
+    """Cache key: the book's shape plus everything that changes the search
+    (grid, sample size, how many more books confirm the finalists)."""
+    g = ";".join(f"{k}={','.join(str(v) for v in grid[k])}" for k in sorted(grid))
+    return f"{shape_key(P, precision)}|s{sample}|b{n_second}|f{finalists}|{g}"
+
+
+def clear_cache() -> None:
+    """Forget the in-memory picks (the JSON file, if any, is kept)."""
+    _CACHE.clear()
 
 
 def _timed(s: Solver, Q: DeviceProblem, cfg: dict):
@@ -54,20 +70,23 @@ def autotune(P: DeviceProblem, solver: Optional[Solver] = None, sample: int = 64
              grid: Optional[dict] = None, precision: int = 1,
              cache_path: Optional[str] = None, verbose: bool = False,
              second: Union[DeviceProblem, Sequence[DeviceProblem], None] = None,
-             finalists: int = 3) -> dict:
+             finalists: int = 3, use_cache: bool = True) -> dict:
     """Settings dict {rho, alpha, check_every, first_check, precision} for
     books shaped like P, from timed solves of its first ``sample`` accounts (and of the
-    first ``sample`` accounts of each book in ``second`` for the best ``finalists``)."""
-    key = shape_key(P, precision)
-    if key in _CACHE:
+    first ``sample`` accounts of each book in ``second`` for the best ``finalists``).
+    ``use_cache=False`` always searches (and then refreshes the cache)."""
+    grid = grid or DEFAULT_GRID
+    others = [] if second is None else (
+        [second] if isinstance(second, DeviceProblem) else list(second))
+    key = tune_key(P, precision, grid, sample, len(others), finalists)
+    if use_cache and key in _CACHE:
         return dict(_CACHE[key])
-    if cache_path and os.path.exists(cache_path):
+    if use_cache and cache_path and os.path.exists(cache_path):
         with open(cache_path) as fh:
             disk = json.load(fh)
         if key in disk:
             _CACHE[key] = disk[key]
             return dict(disk[key])
-    grid = grid or DEFAULT_GRID
     s = solver or Solver(P.mu.device.index or 0)
     Q = subset(P, range(min(sample, P.m)))
     s.solve(Q, precision=precision)                       # warm-up: workspace, code
@@ -82,8 +101,6 @@ def autotune(P: DeviceProblem, solver: Optional[Solver] = None, sample: int = 64
         ranked.append(((-ok, dt), cfg))
     ranked.sort(key=lambda r: r[0])
     best = ranked[0]
-    others = [] if second is None else (
-        [second] if isinstance(second, DeviceProblem) else list(second))
     if others and finalists > 1:
         fin = [[score[0], score[1], cfg] for (score, cfg) in ranked[:finalists]]
         for B in others:

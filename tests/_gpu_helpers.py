@@ -59,6 +59,18 @@ def check_account(uni, book, a, host):
     info["werr2_bound"] = weight_error_bound(P, gap) + 10 * r["r_prim"]
     assert werr2 <= info["werr2_bound"], info
     # the GPU's own float64 diagnostics agree with the oracle's checker
-    assert abs(host["r_prim"][a] - r["r_prim"]) <= 1e-9, info
-    assert abs(host["obj"][a] - r["obj"]) <= 1e-12 * max(1.0, abs(r["obj"])), info
+    check_reported_diagnostics(host, a, r, info)
     return info
+
+
+def check_reported_diagnostics(host, a, r, info=None):
+    """The residuals and objective the GPU reports for account a (its own
+    float64 certification) equal what the CPU checker computes from the
+    returned weights and multipliers."""
+    info = info if info is not None else dict(a=a)
+    info.update(gpu_r_prim=float(host["r_prim"][a]), gpu_r_dual=float(host["r_dual"][a]),
+                gpu_r_comp=float(host["r_comp"][a]))
+    assert abs(host["r_prim"][a] - r["r_prim"]) <= 1e-9, info
+    assert abs(host["r_dual"][a] - r["r_dual"]) <= 1e-9, info
+    assert abs(host["r_comp"][a] - r["r_comp"]) <= 1e-9, info
+    assert abs(host["obj"][a] - r["obj"]) <= 1e-12 * max(1.0, abs(r["obj"])), info

@@ -45,15 +45,36 @@ def test_full_size_books(name, sample, settings):
 def test_large_universe_c5():
     """8 accounts over N = 384,800 names, k = 100, 50 one-hot groups with
     bands, 2,000 held names with 4-lot tax: the factor block (k + G + 1 =
-    151 columns) takes the float32 contraction path.  The oracle needs
-    minutes per account here, so the check is the CPU checker on every
-    account's output."""
+    151 columns) takes the float32 contraction path.  Every account is
+    re-checked by the CPU checker; accounts 0 and 1 are compared with the
+    oracle's answer stored by tests/golden/make_c5_golden.py (the oracle
+    needs about two minutes per account at this size)."""
+    import json
+    import os
+    from _gpu_helpers import weight_error_bound
     uni, book = make_config("c5", 0)
     print("case c5 full size", flush=True)
     host, st = run_gpu(uni, book, rho=10.0)
     print("stats", st, flush=True)
     assert int(np.sum(host["status"] == 0)) == book.m
     _all_certified_by_cpu_checker(uni, book, host)
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden",
+                                       "c5_full_oracle.json")))
+    for key, g in gold["accounts"].items():
+        a = int(key)
+        P = account(uni, book, a)
+        r = residuals(P, host["w"][a], host["nu"][a], host["lam_band"][a], host["lam_cap"][a])
+        relobj = abs(r["obj"] - g["obj"]) / abs(g["obj"])
+        w_ref = np.zeros(uni.n)
+        w_ref[np.asarray(g["support"], dtype=np.int64)] = g["w_support"]
+        werr2 = float(np.linalg.norm(host["w"][a] - w_ref))
+        bound = weight_error_bound(P, r["obj"] - g["obj"] + 1e-13 * abs(g["obj"])) \
+            + 10 * r["r_prim"]
+        info = dict(a=a, relobj=relobj, werr2=werr2, bound=bound,
+                    werr=float(np.max(np.abs(host["w"][a] - w_ref))))
+        print("c5 vs oracle", info, flush=True)
+        assert relobj <= 1e-6, info
+        assert werr2 <= bound, info
 
 
 def test_autotune_picks_a_certifying_schedule():

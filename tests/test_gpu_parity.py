@@ -18,6 +18,11 @@ SMALL = [
     ("c4", dict(N=900, M=5, k=12), dict(rho=1.0)),           # gamma = 1000
     ("c4", dict(N=900, M=5, k=12, gamma=1.0), dict(rho=1.0)),
     ("c5", dict(N=6000, M=2, k=20, held=(300, 300)), dict(rho=10.0)),
+    # factor blocks wider than the bf16-split passes take (k + G + 1 > 96):
+    # float32 contraction passes and the factor-space setup in global
+    # scratch; 151 columns (k = 100, G = 50) and 169 columns (k = 128, G = 40)
+    ("c5", dict(N=20000, M=3, k=100, held=(300, 300)), dict(rho=10.0)),
+    ("c5", dict(N=4100, M=2, k=128, groups=40, held=(200, 200)), dict(rho=10.0)),
     # every rule family at once: L1 turnover, sector bands, exclusions, taxed lots
     ("c2", dict(N=700, M=8, k=10, elig=(0.3, 1.0), held=(50, 120), tax=True), dict(rho=1.0)),
 ]
@@ -42,6 +47,48 @@ def test_headline_book_sampled():
     assert int(np.sum(host["status"] == 0)) == book.m
     for a in (0, 137, 499):
         check_account(uni, book, a, host)
+
+
+def test_headline_book_at_the_bench_schedule():
+    """The headline book at the schedule bench.py times (rho 8, alpha 1.8,
+    a pass every 100 iterations from iteration 200): all 500 certified, the
+    GPU's reported diagnostics equal the CPU checker's on every account,
+    three accounts against the oracle."""
+    from oracle.problem import account
+    from oracle.kkt import residuals
+    from _gpu_helpers import check_reported_diagnostics
+    uni, book = make_config("c3", 0)
+    host, st = run_gpu(uni, book, rho=8.0, alpha=1.8, check_every=100, first_check=200)
+    print("stats", st, flush=True)
+    assert int(np.sum(host["status"] == 0)) == book.m
+    for a in range(book.m):
+        P = account(uni, book, a)
+        r = residuals(P, host["w"][a], host["nu"][a], None, host["lam_cap"][a])
+        assert max(r["r_prim"], r["r_dual"], r["r_comp"]) <= 1e-6, (a, r)
+        check_reported_diagnostics(host, a, r)
+    for a in (0, 250, 499):
+        check_account(uni, book, a, host)
+
+
+def test_positive_lower_bound_with_masks_and_binding_cap():
+    """lb > 0 (a minimum holding for eligible names) with exclusion masks,
+    taxed holdings and a turnover cap close to its least feasible value, at
+    N = 3,000 (not a multiple of the 1,024-row slices of the cap search):
+    excluded names and the padding rows must stay at 0 in every pass."""
+    from workloads.books import to_f32_exact
+    uni, book = make_config("c3", 8, N=3000, M=6, k=12)
+    lb = float(to_f32_exact(2e-5))
+    book.lb[:] = lb
+    for a in range(book.m):
+        el = book.eligible[a]
+        c = np.clip(book.w0[a], np.where(el, lb, 0.0), np.where(el, book.ub[a], 0.0))
+        tmin = np.abs(book.w0[a] - c).sum() + abs(1.0 - c.sum())
+        book.tau[a] = float(to_f32_exact(tmin + 0.05))
+    host, st = run_gpu(uni, book, rho=5.0)
+    for a in range(book.m):
+        check_account(uni, book, a, host)
+    assert np.all(host["w"][~book.eligible] == 0.0)
+    assert np.any(host["lam_cap"] > 0.0)
 
 
 def test_invalid_accounts_do_not_poison_batch():
