@@ -716,11 +716,15 @@ extern "C" fqp_error fqp_solve_batch(fqp_handle* h, const fqp_universe* U, const
   key.m = m; key.kp = kp; key.precision = S.precision; key.count = S.check_every;
   key.any_cap = any_cap ? 1 : 0; key.cap_resident = cap_resident ? 1 : 0;
 
+  // graph_reused reports a call that captured nothing: every block replayed
+  // the graph kept from an earlier call
+  bool captured = false, replayed = false;
   auto run_block = [&](int count) -> fqp_error {
     if (use_graph && count == S.check_every) {
       if (h->have_graph && std::memcmp(&h->gkey, &key, sizeof(key)) == 0) {
-        h->stats.graph_reused = 1;
+        replayed = true;
       } else {
+        captured = true;
         h->drop_graph();
         HIP_CHECK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
         for (int c = 0; c < count; ++c) {
@@ -848,6 +852,7 @@ extern "C" fqp_error fqp_solve_batch(fqp_handle* h, const fqp_universe* U, const
     h->stats.account_iters += it_h[a];
   }
   h->stats.iterations = done_iters;
+  h->stats.graph_reused = (replayed && !captured) ? 1 : 0;
   h->stats.polish_solves = pc_h[0];
   h->stats.polish_gated = pc_h[1];
   {
