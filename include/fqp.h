@@ -240,6 +240,20 @@ FQP_API fqp_error fqp_adjoint_batch(fqp_handle *h, const double *dL_dw,
                                     double *dL_dmu, double *dL_dB,
                                     void *stream);
 
+/* fqp_adjoint_batch without any device allocation, for callers that cannot
+ * allocate: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc.  Same arguments, kernels and results as
+ * fqp_adjoint_batch; its per-account scratch (m * 2k float64 values) comes
+ * from a statically allocated device array of 2 MiB (262,144 float64) that
+ * each device the library runs on holds until the process ends.  Books with
+ * m * 2k above that return FQP_ERR_UNSUPPORTED and write nothing.  Every
+ * call on one device shares that device's array: calls that overlap on one
+ * device (several handles or streams at once) race; serialise them.  The
+ * array needs no clearing: each call writes every entry it reads. */
+FQP_API fqp_error fqp_adjoint_batch_noalloc(fqp_handle *h, const double *dL_dw,
+                                            double *dL_dmu, double *dL_dB,
+                                            void *stream);
+
 FQP_API fqp_error fqp_get_stats(const fqp_handle *h, fqp_stats *out);
 
 /* Certification passes of the last fqp_solve_batch call (the queue lane of

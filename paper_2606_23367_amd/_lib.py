@@ -76,7 +76,7 @@ def state_floats(m: int, n: int, n_groups: int) -> int:
 
 
 EXPORTS = ("fqp_default_settings", "fqp_create", "fqp_solve_batch",
-           "fqp_adjoint_batch", "fqp_get_stats", "fqp_get_pass_times", "fqp_error_string",
+           "fqp_adjoint_batch", "fqp_adjoint_batch_noalloc", "fqp_get_stats", "fqp_get_pass_times", "fqp_error_string",
            "fqp_status_string", "fqp_last_error", "fqp_destroy")
 
 _lib = None
@@ -104,6 +104,9 @@ def load(path: str = LIB_PATH):
     lib.fqp_adjoint_batch.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p,
                                       c_void_p]
     lib.fqp_adjoint_batch.restype = ctypes.c_int
+    lib.fqp_adjoint_batch_noalloc.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p,
+                                              c_void_p]
+    lib.fqp_adjoint_batch_noalloc.restype = ctypes.c_int
     lib.fqp_get_stats.argtypes = [c_void_p, ctypes.POINTER(Stats)]
     lib.fqp_get_stats.restype = ctypes.c_int
     lib.fqp_get_pass_times.argtypes = [c_void_p, ctypes.POINTER(ctypes.c_int32),

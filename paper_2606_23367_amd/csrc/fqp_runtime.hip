@@ -15,6 +15,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -149,6 +150,37 @@ __global__ void mark_time_limit_kernel(int m, int32_t* status) {
 using namespace fqp;
 
 // ---------------------------------------------------------------------------
+// statically allocated scratch of fqp_adjoint_batch_noalloc
+//
+// The adjoint's only workspace is the factor vectors gamma F B^T w and
+// gamma F B^T v of every account ([m][2k] float64).  The no-allocation
+// entry point takes them from this array instead: every device the library
+// runs on holds its own copy until the process ends.  Host code never uses
+// the array's name as an address: the device address comes from
+// hipGetSymbolAddress, taken once per device in fqp_create with that device
+// current.
+// ---------------------------------------------------------------------------
+static constexpr size_t kNoAllocDoubles = (size_t)1 << 18;   // 2 MiB per device
+static __device__ __align__(256) double scratch[kNoAllocDoubles];
+
+static std::mutex g_scratch_mu;
+static std::vector<double*> g_scratch_ptr;   // indexed by device
+
+// device address of `scratch` on `device`, which must be current
+static hipError_t scratch_address(int device, double** out) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if ((int)g_scratch_ptr.size() <= device) g_scratch_ptr.resize(device + 1, nullptr);
+  if (!g_scratch_ptr[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[device] = static_cast<double*>(p);
+  }
+  *out = g_scratch_ptr[device];
+  return hipSuccess;
+}
+
+// ---------------------------------------------------------------------------
 // handle
 // ---------------------------------------------------------------------------
 struct DevBuf {
@@ -168,6 +200,7 @@ struct GraphKey {
 struct fqp_handle {
   int device = 0;
   int n_cu = 0;                   // compute units of the device
+  double* scratch = nullptr;      // this device's copy of the static scratch
   hipStream_t stream = nullptr;   // the handle's own stream (capturable)
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
   hipEvent_t ev_t[4] = {nullptr, nullptr, nullptr, nullptr};   // phase timing
@@ -296,8 +329,15 @@ fqp_error fqp_create(fqp_handle** h, int device) {
     (void)hipGetLastError();
     return FQP_ERR_HIP;
   }
+  double* scr = nullptr;
+  if (scratch_address(device, &scr) != hipSuccess) {
+    (void)hipGetLastError();
+    (void)hipSetDevice(cur);
+    return FQP_ERR_HIP;
+  }
   fqp_handle* hh = new fqp_handle();
   hh->device = device;
+  hh->scratch = scr;
   if (hipDeviceGetAttribute(&hh->n_cu, hipDeviceAttributeMultiprocessorCount, device) !=
       hipSuccess) {
     (void)hipGetLastError();
@@ -870,8 +910,10 @@ extern "C" fqp_error fqp_solve_batch(fqp_handle* h, const fqp_universe* U, const
   return FQP_OK;
 }
 
-extern "C" fqp_error fqp_adjoint_batch(fqp_handle* h, const double* dL_dw, double* dL_dmu,
-                                       double* dL_dB, void* stream_v) {
+// the adjoint of the last solve; `scr` (a device array of at least m * 2k
+// doubles) replaces the workspace request when given
+static fqp_error adjoint_common(fqp_handle* h, const double* dL_dw, double* dL_dmu,
+                                double* dL_dB, void* stream_v, double* scr) {
   if (!h) return FQP_ERR_INVALID_ARG;
   if (!h->have_last) { h->err = "no solve to differentiate"; return FQP_ERR_INVALID_ARG; }
   if (!dL_dw || !dL_dmu || !dL_dB) { h->err = "null gradient pointer"; return FQP_ERR_INVALID_ARG; }
@@ -884,12 +926,16 @@ extern "C" fqp_error fqp_adjoint_batch(fqp_handle* h, const double* dL_dw, doubl
   } restore{prev_dev};
   hipStream_t caller = static_cast<hipStream_t>(stream_v);
   hipStream_t st = h->stream;
-  HIP_CHECK(hipEventRecord(h->ev_in, caller));
-  HIP_CHECK(hipStreamWaitEvent(st, h->ev_in, 0));
   fqp_error e = FQP_OK;
   AdjArgs A = h->last;
-  WS(yvw, double, "adj_yvw", (size_t)A.m * 2 * A.k);
-  A.yvw = yvw;
+  if (scr) {
+    A.yvw = scr;
+  } else {
+    WS(yvw, double, "adj_yvw", (size_t)A.m * 2 * A.k);
+    A.yvw = yvw;
+  }
+  HIP_CHECK(hipEventRecord(h->ev_in, caller));
+  HIP_CHECK(hipStreamWaitEvent(st, h->ev_in, 0));
   A.dLdw = dL_dw;
   A.dmu = dL_dmu;
   A.dB = dL_dB;
@@ -897,4 +943,23 @@ extern "C" fqp_error fqp_adjoint_batch(fqp_handle* h, const double* dL_dw, doubl
   HIP_CHECK(hipEventRecord(h->ev_out, st));
   HIP_CHECK(hipStreamWaitEvent(caller, h->ev_out, 0));
   return FQP_OK;
+}
+
+extern "C" fqp_error fqp_adjoint_batch(fqp_handle* h, const double* dL_dw, double* dL_dmu,
+                                       double* dL_dB, void* stream_v) {
+  return adjoint_common(h, dL_dw, dL_dmu, dL_dB, stream_v, nullptr);
+}
+
+extern "C" fqp_error fqp_adjoint_batch_noalloc(fqp_handle* h, const double* dL_dw,
+                                               double* dL_dmu, double* dL_dB, void* stream_v) {
+  if (!h) return FQP_ERR_INVALID_ARG;
+  if (!h->scratch) { h->err = "no static scratch on this device"; return FQP_ERR_HIP; }
+  if (h->have_last && (size_t)h->last.m * 2 * (size_t)h->last.k > kNoAllocDoubles) {
+    h->err = "fqp_adjoint_batch_noalloc: m * 2k = " +
+             std::to_string((size_t)h->last.m * 2 * (size_t)h->last.k) +
+             " float64 values exceed the static scratch of " + std::to_string(kNoAllocDoubles) +
+             " (use fqp_adjoint_batch)";
+    return FQP_ERR_UNSUPPORTED;
+  }
+  return adjoint_common(h, dL_dw, dL_dmu, dL_dB, stream_v, h->scratch);
 }

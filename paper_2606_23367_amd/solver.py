@@ -212,23 +212,32 @@ class Solver:
         self.generation = getattr(self, "generation", 0) + 1
         return out
 
-    def adjoint(self, dL_dw: torch.Tensor, stream=None):
+    def adjoint(self, dL_dw: torch.Tensor, stream=None, noalloc: bool = False, out=None):
         """dL/dmu [m, n] and dL/dB [n, k] (float64) of a loss with gradient
-        dL_dw through the last solve on this handle."""
+        dL_dw through the last solve on this handle.  noalloc: the entry
+        point that allocates no device memory (its scratch is a static
+        device array); out = (dmu, dB) reuses the caller's output tensors."""
         if not hasattr(self, "_last_shape"):
             raise RuntimeError("adjoint() needs a preceding solve()")
         m, n, k = self._last_shape
         dev = dL_dw.device
         g = dL_dw.detach().to(torch.float64).contiguous()
-        dmu = torch.empty((m, n), dtype=torch.float64, device=dev)
-        dB = torch.empty((n, k), dtype=torch.float64, device=dev)
+        if out is None:
+            dmu = torch.empty((m, n), dtype=torch.float64, device=dev)
+            dB = torch.empty((n, k), dtype=torch.float64, device=dev)
+        else:
+            dmu, dB = out
+            if dmu.shape != (m, n) or dB.shape != (n, k) or dmu.dtype != torch.float64 \
+                    or dB.dtype != torch.float64 or not (dmu.is_contiguous() and dB.is_contiguous()):
+                raise ValueError("out must be contiguous float64 tensors of shapes [m, n], [n, k]")
         if stream is None:
             stream = torch.cuda.current_stream(dev)
-        rc = self.lib.fqp_adjoint_batch(self.h, _ptr(g), _ptr(dmu), _ptr(dB),
-                                        ctypes.c_void_p(stream.cuda_stream))
+        fn = self.lib.fqp_adjoint_batch_noalloc if noalloc else self.lib.fqp_adjoint_batch
+        rc = fn(self.h, _ptr(g), _ptr(dmu), _ptr(dB), ctypes.c_void_p(stream.cuda_stream))
         if rc != 0:
-            raise RuntimeError(
-                f"fqp_adjoint_batch failed: {self.lib.fqp_last_error(self.h).decode()}")
+            name = "fqp_adjoint_batch_noalloc" if noalloc else "fqp_adjoint_batch"
+            raise RuntimeError(f"{name} failed ({rc}): "
+                               f"{self.lib.fqp_last_error(self.h).decode()}")
         return dmu, dB
 
     def stats(self) -> dict:
