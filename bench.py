@@ -38,22 +38,15 @@ SETTINGS = dict(precision=1)
 
 
 def algorithmic_bytes(uni, book, iters, precision):
-    """Algorithmic bytes of the PROJECT pass (back-projection, relaxation and
-    the write of the new ADMM state).  Per account-iteration: state v read
-    and written (8 N), returns read (4 N), and z = prox(v) -- with the
-    bf16-split passes read from the CONTRACT pass (4 N), with the float32
-    passes recomputed from the eligibility, holding and holding-prefix words
-    (12 B per 32 assets) and the held records (two float4 per held name).
-    Per launch: the k + G + 1 used columns of B~ once (bf16 hi and lo: 4 B
-    per entry; float32: 4 B) and d (4 N)."""
+    """Algorithmic bytes of the PROJECT pass (back-projection and the write
+    of the new ADMM state).  Per account-iteration: w = v + alpha (Delta^-1 r
+    - z) read (written by the CONTRACT pass) and the new state v written
+    (8 N).  Per launch: the k + G + 1 used columns of B~ once (bf16 hi and
+    lo: 4 B per entry; float32: 4 B) and d (4 N)."""
     import numpy as np
     n, k = uni.n, uni.k
     G = uni.n_groups
-    if precision == 1 and k + G + 1 <= 96:
-        per_acc = np.full(book.m, 16.0 * n)
-    else:
-        held = np.count_nonzero(book.w0, axis=1)
-        per_acc = 12.0 * n + 12.0 * np.ceil(n / 32.0) + 32.0 * held
+    per_acc = np.full(book.m, 8.0 * n)
     per_launch = 4.0 * n * (k + G + 1) + 4.0 * n
     return float(np.sum(iters * per_acc)), float(per_launch)
 

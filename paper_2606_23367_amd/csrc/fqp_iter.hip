@@ -21,14 +21,18 @@
 //   K = F~^-1 + B~^T Delta^-1 B~,  c = B~^T Delta^-1 1,  q = K^-1 c,
 //   sigma1 = 1^T Delta^-1 1 - c^T q.
 //
-// The ADMM state kept per (account, asset) is v = xh + u only.  One iteration
-// is four launches (below): CONTRACT streams v and writes the per-row-tile
-// partials of t = B~^T Delta^-1 r (MFMA) and z = prox(v; lam*); a small
-// per-account kernel reduces the partials and solves in factor space (nu,
-// p); PROJECT streams v and z again and applies the back-projection B~ p
-// (MFMA), the x-step and the over-relaxation, writing the new v; the cap
-// kernel finds the exact turnover-cap multiplier lam* of the new v per
-// account (a safeguarded Newton search on the piecewise-linear turnover).
+// The ADMM state kept per (account, asset) is v = xh + u.  With z = prox(v)
+// and r = mu + rho (z - u) the update of v splits into a part every row
+// computes alone and the back-projection,
+//   v' = alpha x + (1 - alpha) z + u = w + alpha Delta^-1 (nu - (B~ p)_i),
+//   w  = v + alpha (Delta^-1 r - z),
+// so one iteration is four launches (below): CONTRACT streams v and mu,
+// writes the per-row-tile partials of t = B~^T Delta^-1 r (MFMA) and w; a
+// small per-account kernel reduces the partials and solves in factor space
+// (nu, p); PROJECT streams w and applies the back-projection B~ p (MFMA),
+// writing the new v; the cap kernel finds the exact turnover-cap multiplier
+// lam* of the new v per account (a safeguarded Newton search on the
+// piecewise-linear turnover).
 #include <algorithm>
 
 #include <hip/hip_ext.h>
@@ -215,10 +219,10 @@ __global__ __launch_bounds__(1024) void kfactor_kernel(int k, int G, int kp, int
 // The ADMM state kept in HBM is v = xh + u per (account, asset).  With the
 // exact cap multiplier lam* of v, z = prox(v; lam*) and u = v - z are
 // recomputed wherever they are needed, so one iteration is
-//   CONTRACT  z, u from v; r = mu + rho (z - u); t = B~^T Delta^-1 r   (MFMA)
+//   CONTRACT  z, u from v; r = mu + rho (z - u); t = B~^T Delta^-1 r (MFMA);
+//             w = v + alpha (Delta^-1 r - z)
 //   k-solve   nu, p from t (factor space)
-//   PROJECT   z, u from v; x = Delta^-1 (r + nu - B~ p) (MFMA);
-//             v <- alpha x + (1 - alpha) z + u
+//   PROJECT   v <- w + alpha Delta^-1 (nu - B~ p)   (MFMA)
 //   cap       lam* of the new v (per account, exact)
 // ---------------------------------------------------------------------------
 enum PassMode { MODE_CONTRACT = 0, MODE_PROJECT = 1 };
@@ -366,6 +370,26 @@ __global__ __launch_bounds__(256, 2) void iter_kernel(IterArgs A) {
         X = __builtin_amdgcn_mfma_f32_32x32x2f32(pa[2 * s], pb[2 * s], X, 0, 0, 0);
     }
 
+    if (MODE == MODE_PROJECT) {
+      // v' = w + alpha Delta^-1 (nu - (B~ p)_i), w from the CONTRACT pass
+      float w_r[16];
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int m = 8 * (r >> 2) + 4 * hi + (r & 3);
+        w_r[r] = (Aid[m] >= 0 && row_ok) ? A.zs[(unsigned)(Ao[m] + row)] : 0.f;
+      }
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int m = 8 * (r >> 2) + 4 * hi + (r & 3);
+        if (Aid[m] >= 0 && row_ok) {
+          const float4 q0 = Acc[2 * m], q1 = Acc[2 * m + 1];
+          const float iDelta = __builtin_amdgcn_rcpf(q0.z * d_i + q0.x);
+          A.v[(unsigned)(Ao[m] + row)] = w_r[r] + q1.w * iDelta * (q1.z - X[r]);
+        }
+      }
+      continue;
+    }
+
     // issue every load of the lane's 16 (account, row) elements first, so
     // that they are in flight together
     float mu_r[16], v_r[16];
@@ -402,16 +426,11 @@ __global__ __launch_bounds__(256, 2) void iter_kernel(IterArgs A) {
         const RowInfo ri = row_info_w(A, row, q1.x, q1.y, ew_r[r], hw_r[r], hp_r[r], Hp[m]);
         const float z = prox_row(ri, vv, q0.w, irho, nullptr);
         const float u = vv - z;
-        const float r0v = mu + rho * (z - u);
-        if (MODE == MODE_CONTRACT) {
-          Rp = r0v * iDelta;
-        } else {
-          const float x = (r0v + q1.z - X[r]) * iDelta;
-          const float alpha = q1.w;
-          A.v[off] = alpha * x + (1.f - alpha) * z + u;
-        }
+        Rp = (mu + rho * (z - u)) * iDelta;
+        // the part of the new state that needs no back-projection, for PROJECT
+        A.zs[off] = vv + q1.w * (Rp - z);
       }
-      if (MODE == MODE_CONTRACT) Rw[m * 33 + l32] = Rp;
+      Rw[m * 33 + l32] = Rp;
     }
     if (MODE == MODE_CONTRACT) {
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -497,14 +516,13 @@ constexpr int bf_held_offset() {
 template <int NCH, int MODE>
 constexpr int bf_lds_floats() {
   // CONTRACT: per-wave R' transposes (hi, lo) and held records or, after the
-  // row loop, the cross-wave reduction [4][32][kp]; PROJECT: a [4][32] max
-  // reduction, the split p of the tile (hi, lo) [2][32][kp + 8] bf16 and the
-  // held records
+  // row loop, the cross-wave reduction [4][32][kp]; PROJECT: the split p of
+  // the tile (hi, lo) [2][32][kp + 8] bf16 (after 4 x 32 unused floats)
   return (MODE == MODE_CONTRACT)
              ? ((kWaves * kTM * NCH * 32 > kRwFloats + kWaves * kHeldFloats)
                     ? kWaves * kTM * NCH * 32
                     : kRwFloats + kWaves * kHeldFloats)
-             : bf_held_offset<NCH, MODE>() + kWaves * kHeldFloats;
+             : bf_held_offset<NCH, MODE>();
 }
 
 template <int NCH, int MODE>
@@ -589,22 +607,21 @@ __global__ __launch_bounds__(256, 3) void iter_kernel_bf(IterArgs A) {
     const bool row_ok = row < n;
     const float d_i = row_ok ? A.d[row] : 1.f;
 
-    float mu_r[16], v_r[16], z_r[16];
+    float mu_r[16], v_r[16];
     const int wd = row >> 5, b = row & 31;
     // bit r: slot r holds an account and a row inside the book / the row is
     // eligible / the row is held
     unsigned ok_bits = 0u, el_bits = 0u, held_bits = 0u;
     if (MODE == MODE_PROJECT) {
-      // z of this v comes from the CONTRACT pass: no row data needed here
+      // w of this iterate comes from the CONTRACT pass: no row data, no
+      // returns and no old state needed here
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
         const int m = 8 * (r >> 2) + 4 * hi + (r & 3);
-        mu_r[r] = 0.f; v_r[r] = 0.f; z_r[r] = 0.f;
+        v_r[r] = 0.f;
         if (Aid[m] >= 0 && row_ok) {
           const unsigned off = (unsigned)(Ao[m] + row);
-          mu_r[r] = A.mu[off];
-          v_r[r] = A.v[off];
-          z_r[r] = A.zs[off];
+          v_r[r] = A.zs[off];
           ok_bits |= 1u << r;
         }
       }
@@ -692,15 +709,10 @@ __global__ __launch_bounds__(256, 3) void iter_kernel_bf(IterArgs A) {
         const int m = 8 * (r >> 2) + 4 * hi + (r & 3);
         if ((ok_bits >> r) & 1u) {
           const float4 q0 = Acc[2 * m], q1 = Acc[2 * m + 1];
-          const float rho = q0.x;
-          const float iDelta = __builtin_amdgcn_rcpf(q0.z * d_i + rho);
+          const float iDelta = __builtin_amdgcn_rcpf(q0.z * d_i + q0.x);
           const unsigned off = (unsigned)(Ao[m] + row);
-          const float vv = v_r[r], z = z_r[r];
-          const float u = vv - z;
-          const float r0v = mu_r[r] + rho * (z - u);
-          const float x = (r0v + q1.z - X[r]) * iDelta;
-          const float alpha = q1.w;
-          A.v[off] = alpha * x + (1.f - alpha) * z + u;
+          // v' = w + alpha Delta^-1 (nu - (B~ p)_i)
+          A.v[off] = v_r[r] + q1.w * iDelta * (q1.z - X[r]);
         }
       }
     }
@@ -745,7 +757,8 @@ __global__ __launch_bounds__(256, 3) void iter_kernel_bf(IterArgs A) {
         const float z = prox_row(ri, vv, q0.w, irho, nullptr);
         const float u = vv - z;
         Rp = (mu_r[r] + rho * (z - u)) * iDelta;
-        A.zs[off] = z;                   // for the PROJECT pass
+        // the part of the new state that needs no back-projection, for PROJECT
+        A.zs[off] = vv + q1.w * (Rp - z);
       }
       if (MODE == MODE_CONTRACT) {
         __bf16 h, l;
@@ -1121,18 +1134,33 @@ __global__ __launch_bounds__(kKsT) void ksolve_kernel(KArgs A) {
   const float rhob = par[P_RHOB];
 
   // nsp threads per factor column split the row tiles (and below the
-  // K^-1 rows), so that more independent loads are in flight
+  // K^-1 rows), so that more independent loads are in flight.  Each thread
+  // issues its first batch of 16 partials, then its first 16 entries of
+  // K^-1 (used after the reduction), before any of them is waited on.
   const int nsp = kp <= kKsT ? kKsT / kp : 1;
+  const int jq = tid % kp, qq = tid / kp;
+  float kb[16];
   if (tid < nsp * kp) {
-    const int j = tid % kp, q = tid / kp;
-    // batches of 16 loads issued before any is added
+    float buf[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int rt = qq + u * nsp;
+      buf[u] = rt < n_rt ? A.part[((size_t)rt * M + a) * kp + jq] : 0.f;
+    }
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int l = qq + u * nsp;
+      kb[u] = (jq < kg && l < kg) ? Kinv[l * kp + jq] : 0.f;
+    }
     float s = 0.f;
-    for (int r0 = q; r0 < n_rt; r0 += 16 * nsp) {
-      float buf[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) s += buf[u];
+    // batches of 16 loads issued before any is added
+    for (int r0 = qq + 16 * nsp; r0 < n_rt; r0 += 16 * nsp) {
 #pragma unroll
       for (int u = 0; u < 16; ++u) {
         const int rt = r0 + u * nsp;
-        buf[u] = rt < n_rt ? A.part[((size_t)rt * M + a) * kp + j] : 0.f;
+        buf[u] = rt < n_rt ? A.part[((size_t)rt * M + a) * kp + jq] : 0.f;
       }
 #pragma unroll
       for (int u = 0; u < 16; ++u) s += buf[u];
@@ -1182,12 +1210,18 @@ __global__ __launch_bounds__(kKsT) void ksolve_kernel(KArgs A) {
   __syncthreads();
   __syncthreads();
   if (tid < nsp * kp) {
-    const int j = tid % kp, q = tid / kp;
+    const int j = jq, q = qq;
     double s = 0.0;
     if (j < kg) {
-      // K^-1 is symmetric: read column j (consecutive j -> consecutive
-      // words); batches of 16 loads issued before any is used
-      for (int l0 = q; l0 < kg; l0 += 16 * nsp) {
+      // K^-1 is symmetric: column j (consecutive j -> consecutive words);
+      // the first batch was loaded at the start, later ones here in
+      // batches of 16 loads issued before any is used
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const int l = q + u * nsp;
+        if (l < kg) s += (double)kb[u] * rhs[l];
+      }
+      for (int l0 = q + 16 * nsp; l0 < kg; l0 += 16 * nsp) {
         float buf[16];
 #pragma unroll
         for (int u = 0; u < 16; ++u) {

@@ -34,8 +34,10 @@ struct IterArgs {
   const float* par;          // [m][kNPar]
   float* par_rw;             // same array, written by the cap kernel
   float* part;               // [row tiles][m][kp] (at most one per 128-row chunk)
-  float* zs;                 // [m][n] z = prox(v; lam*) of the current v: the
-                             // bf16-split CONTRACT pass writes it, PROJECT reads it
+  float* zs;                 // [m][n] w = v + alpha (Delta^-1 r - z) of the
+                             // current iterate: CONTRACT writes it, PROJECT adds
+                             // the back-projection; before a polish it holds
+                             // z = prox(v; lam*) instead (materialize_z)
 };
 
 struct KArgs {
