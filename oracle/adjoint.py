@@ -2,23 +2,25 @@
 (oracle side; implicit differentiation of the KKT system at w*).
 
 Inside the active pattern of the optimum (fixed coordinates at bounds / kinks,
-free coordinates inside a linear piece, binding budget / bands / cap) the
-optimum of the build's Eq. 1 instance solves
+free coordinates inside a linear piece, binding budget / constraint rows /
+cap) the optimum of the build's Eq. 1 instance solves
 
-  gamma Sigma_FF w_F + C_F^T eta = mu_F - slope_F - gamma Sigma_FX w_X
-  C_F w_F = h
+  gamma Sigma_FF w_F + C_F^T eta = mu'_F - slope_F - gamma Sigma_FX w_X
+  C_F w_F = h,        mu' = eta mu + gamma Sigma w_b,
 
 so w_F is affine in mu and smooth in B.  For L = c^T w:
 
   [gamma Sigma_FF  C_F^T] [v_F]   [c_F]
   [C_F             0    ] [xi ] = [0  ]      (v = 0 off F)
 
-  dL/dmu = v,
-  dL/dB  = -gamma ( v (F B^T w)^T + w (F B^T v)^T ),
+  dL/dmu = eta v,
+  dL/dB  = -gamma ( v (F B^T e)^T + e (F B^T v)^T ),   e = w - w_b,
 
-the second from d(Sigma w) = dB F B^T w + B F dB^T w on the free rows.  A
-coordinate at a kink or bound is held fixed (the generic one-sided
-convention; the derivative does not exist where the pattern changes).
+the second from d(Sigma e) = dB F B^T e + B F dB^T e on the free rows (the
+risk term is (gamma/2) e^T Sigma e; the constraint rows are data of their
+own and do not move with B).  A coordinate at a kink or bound is held fixed
+(the generic one-sided convention; the derivative does not exist where the
+pattern changes).
 
 Test infrastructure only.
 """
@@ -27,7 +29,7 @@ from __future__ import annotations
 import numpy as np
 import scipy.linalg as sla
 
-from .problem import AccountProblem
+from .problem import AccountProblem, n_rows, rows_bounds, rows_mul, row_coeffs
 from .crossover import _classify
 
 
@@ -35,13 +37,14 @@ def reduced_pattern(P: AccountProblem, w, lam_band, lam_cap, tol=1e-12):
     fixed, val, slope, sgn = _classify(P, w, tol)
     F = np.nonzero(~fixed)[0]
     rows = [np.ones(len(F))]
-    G = P.n_groups
+    G = n_rows(P)
     if G:
-        Aw = np.bincount(P.group, weights=w, minlength=G)
+        row_lo, row_hi = rows_bounds(P)
+        Aw = rows_mul(P, w)
         for g in range(G):
-            at_bound = min(abs(Aw[g] - P.band_hi[g]), abs(Aw[g] - P.band_lo[g])) <= 1e-12
+            at_bound = min(abs(Aw[g] - row_hi[g]), abs(Aw[g] - row_lo[g])) <= 1e-12
             if at_bound and abs(lam_band[g]) > 0.0:
-                rows.append((P.group[F] == g).astype(float))
+                rows.append(row_coeffs(P, g, F))
     if np.isfinite(P.tau) and lam_cap > 0.0:
         rows.append(sgn[F])
     return F, np.vstack(rows)
@@ -64,7 +67,8 @@ def gradients(P: AccountProblem, w, lam_band, lam_cap, c):
         sol = np.linalg.lstsq(K, rhs, rcond=1e-14)[0]
         dmu[F] = sol[:len(F)]
     v = dmu
-    FBw = P.f * (P.B.T @ w)
+    e = w - P.wb if P.wb is not None else w
+    FBe = P.f * (P.B.T @ e)
     FBv = P.f * (P.B.T @ v)
-    dB = -P.gamma * (np.outer(v, FBw) + np.outer(w, FBv))
-    return dmu, dB
+    dB = -P.gamma * (np.outer(v, FBe) + np.outer(e, FBv))
+    return P.eta * dmu, dB

@@ -3,15 +3,17 @@
 At the optimum of the build's Eq. 1 instance every eligible coordinate either
 sits on a bound / kink of its piecewise-linear trade cost (fixed) or lies
 inside one linear piece (free, with a known slope).  Given that classification
-and the set of binding bands and cap, w* solves one equality-constrained QP:
+and the set of binding constraint rows (bands, halfspaces) and cap, w* solves
+one equality-constrained QP:
 
-  gamma (Sigma w)_F - mu_F + slope_F + lam_cap sgn_F - nu 1 + A_F^T lam = 0
-  1^T w = 1,   (A w)_g = bound_g (binding g),   sgn^T (w - w0) = tau (cap)
+  gamma (Sigma w)_F - mu'_F + slope_F + lam_cap sgn_F - nu 1 + R_F^T lam = 0
+  1^T w = 1,   (R w)_r = bound_r (binding r),   sgn^T (w - w0) = tau (cap)
 
-solved here in float64 (dense for moderate |F|, factor-space Woodbury
-otherwise).  The classification is read off the interior-point iterate with
-a snap tolerance; several tolerances are tried and the candidate with the
-smallest external KKT residual (``oracle.kkt``) is kept.
+(mu' = eta mu + gamma Sigma w_b) solved here in float64 (dense for moderate
+|F|, factor-space Woodbury otherwise).  The classification is read off the
+interior-point iterate with a snap tolerance; several tolerances are tried
+and the candidate with the smallest external KKT residual (``oracle.kkt``) is
+kept.
 
 Test infrastructure only.
 """
@@ -20,7 +22,8 @@ from __future__ import annotations
 import numpy as np
 import scipy.linalg as sla
 
-from .problem import AccountProblem, kinks_and_slopes
+from .problem import (AccountProblem, kinks_and_slopes, box, n_rows, rows_bounds,
+                      rows_mul, row_coeffs, linear_term)
 from .kkt import residuals
 
 
@@ -31,8 +34,9 @@ def _classify(P: AccountProblem, w, tol):
     slope = np.zeros(n)
     sgn = np.zeros(n)
     taxed = {int(i) for i in P.tax_asset}
-    lb, ub = P.lb, P.ub
+    lbv, ubv = box(P)
     for i in range(n):
+        lb, ub = lbv[i], ubv[i]
         if not P.eligible[i]:
             fixed[i] = True
             val[i] = 0.0
@@ -100,7 +104,8 @@ def _point_slopes(P: AccountProblem, i, x):
     """(lo0, s_lo, hi0, s_hi): the subdifferential of phi_i + lam|.-w0| +
     N_box at the fixed point x is [lo0 + s_lo lam, hi0 + s_hi lam]
     (lo0 = -inf / hi0 = +inf at a bound)."""
-    lb, ub = (P.lb, P.ub) if P.eligible[i] else (0.0, 0.0)
+    lbv, ubv = box(P)
+    lb, ub = lbv[i], ubv[i]
     kinks, slopes = kinks_and_slopes(P, i, 0.0)
     has_phi = P.kappa > 0 or np.isfinite(P.tau) or i in set(int(t) for t in P.tax_asset)
     if not has_phi:
@@ -137,12 +142,15 @@ def refine_multipliers(P: AccountProblem, w, fixed, C_rows, act, cap_on, eta,
         N = np.eye(nc)
     if N.shape[1] == 0:
         return eta
-    G = P.n_groups
+    _, row_hi = rows_bounds(P)
     band_col = {g_: 1 + j for j, (g_, _) in enumerate(act)}
-    up = {g_: (bnd == P.band_hi[g_]) for g_, bnd in act}
-    base = P.gamma * (P.B @ (P.f * (P.B.T @ w)) + P.d * w) - P.mu
+    up = {g_: (bnd == row_hi[g_]) for g_, bnd in act}
+    base = P.gamma * (P.B @ (P.f * (P.B.T @ w)) + P.d * w) - linear_term(P)
     rows = [i for i in range(P.n) if fixed[i] and P.eligible[i]]
     geo = {i: _point_slopes(P, i, w[i]) for i in rows}
+    idx = np.asarray(rows, dtype=np.int64)
+    # coefficients of the active rows at the fixed coordinates
+    coef = {g_: dict(zip(rows, row_coeffs(P, g_, idx))) for g_ in band_col}
     for _ in range(sweeps):
         for q in range(N.shape[1]):
             n = N[:, q]
@@ -157,9 +165,13 @@ def refine_multipliers(P: AccountProblem, w, fixed, C_rows, act, cap_on, eta,
                 elif alpha < -1e-300:
                     L = max(L, beta / alpha)
             for i in rows:
-                bc = band_col.get(int(P.group[i])) if G else None
-                T = -(base[i] + eta[0] + (eta[bc] if bc else 0.0))
-                a = n[0] + (n[bc] if bc else 0.0)
+                T = -(base[i] + eta[0])
+                a = n[0]
+                for g_, col in band_col.items():
+                    cf = coef[g_][i]
+                    if cf != 0.0:
+                        T -= cf * eta[col]
+                        a += cf * n[col]
                 lo0, s_lo, hi0, s_hi = geo[i]
                 if np.isfinite(lo0):      # lo0 + s_lo (lam + s n_c) <= T - a s
                     add(a + s_lo * n_c, T - lo0 - s_lo * lam)
@@ -191,24 +203,23 @@ def crossover_once(P: AccountProblem, w, tol, tol_con, nu0=0.0,
     F = np.nonzero(~fixed)[0]
     X = np.nonzero(fixed)[0]
     wX = val[X]
-    G = P.n_groups
-    # binding bands
+    G = n_rows(P)
+    # binding constraint rows (bands, then halfspaces)
     act = []
     if G:
-        Aw = np.bincount(P.group, weights=w, minlength=G)
+        row_lo, row_hi = rows_bounds(P)
+        Aw = rows_mul(P, w)
         for g_ in range(G):
-            if abs(Aw[g_] - P.band_hi[g_]) <= tol_con:
-                act.append((g_, P.band_hi[g_]))
-            elif abs(Aw[g_] - P.band_lo[g_]) <= tol_con:
-                act.append((g_, P.band_lo[g_]))
+            if abs(Aw[g_] - row_hi[g_]) <= tol_con:
+                act.append((g_, row_hi[g_]))
+            elif abs(Aw[g_] - row_lo[g_]) <= tol_con:
+                act.append((g_, row_lo[g_]))
     cap_on = bool(np.isfinite(P.tau) and
                   abs(np.abs(w - P.w0).sum() - P.tau) <= tol_con)
     rows, hs = [np.ones(len(F))], [1.0 - wX.sum()]
     for g_, bnd in act:
-        inF = (P.group[F] == g_).astype(float)
-        inX = P.group[X] == g_
-        rows.append(inF)
-        hs.append(bnd - wX[inX].sum())
+        rows.append(row_coeffs(P, g_, F))
+        hs.append(bnd - float(row_coeffs(P, g_, X) @ wX))
     if cap_on:
         rows.append(sgn[F])
         hs.append(P.tau + float(sgn[F] @ P.w0[F]) -
@@ -217,7 +228,7 @@ def crossover_once(P: AccountProblem, w, tol, tol_con, nu0=0.0,
     h = np.asarray(hs)
     # gamma Sigma_FX w_X = gamma B_F F (B_X^T w_X)   (d is diagonal)
     cross = P.gamma * (P.B[F] @ (P.f * (P.B[X].T @ wX))) if len(X) else 0.0
-    rhs = P.mu[F] - slope[F] - cross
+    rhs = linear_term(P)[F] - slope[F] - cross
     eta0 = [-nu0]
     for g_, _ in act:
         eta0.append(0.0 if lam_band0 is None else lam_band0[g_])

@@ -8,11 +8,15 @@ Hessian is diagonal:
 
   variables  w_i (eligible assets), y = B^T w (k), buys p_i >= 0, sales
              s_ij >= 0 split into tax lots (0 <= s_ij <= lot length, the last
-             lot unbounded), band values t_g in [b_lo, b_hi], cap slack
-             t_c >= 0
-  objective  (gamma/2)(sum_i d_i w_i^2 + sum_j f_j y_j^2) - mu^T w
-             + kappa sum_i p_i + sum_ij (kappa + sigma_ij) s_ij
-  equalities 1^T w = 1;  y - B^T w = 0;  A w - t = 0;
+             lot unbounded), row values t_r in [row_lo, row_hi] (exposure
+             bands, then policy halfspaces; an infinite bound is absent),
+             cap slack t_c >= 0
+  objective  (gamma/2)(sum_i d_i w_i^2 + sum_j f_j y_j^2) - mu'^T w
+             + kappa sum_i p_i + sum_ij (kappa + sigma_ij) s_ij, with
+             mu' = eta mu + gamma Sigma w_b (the benchmark term of Eq. 1
+             expanded; its constant does not move w*)
+  equalities 1^T w = 1;  y - B^T w = 0;  R w - t = 0 (R: band rows by
+             label, halfspace rows dense);
              w_i - p_i + sum_j s_ij = w0_i;  sum p + sum s + t_c = tau_eff
 
 Because the tax slopes are non-decreasing, cheapest lots fill first, so the
@@ -40,7 +44,7 @@ import scipy.linalg as sla
 import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 
-from .problem import AccountProblem
+from .problem import AccountProblem, box, rows_bounds, linear_term
 
 
 @dataclass
@@ -68,6 +72,8 @@ class Lifted:
     b: np.ndarray          # equality right-hand side
     BE: np.ndarray         # B rows of eligible assets (n_e, k)
     gE: np.ndarray         # group labels of eligible assets (or empty)
+    Gl: int                # band rows (by label); rows Gl..G-1 are halfspaces
+    hE: np.ndarray         # halfspace rows on the eligible assets (G - Gl, n_e)
     const: float           # objective constant from excluded assets
 
     @property
@@ -127,7 +133,9 @@ def lift(P: AccountProblem) -> Lifted:
     X = np.nonzero(~P.eligible)[0]
     n_e = len(E)
     k = P.k
-    G = P.n_groups
+    Gl = P.n_groups
+    H = 0 if P.half is None else P.half.shape[0]
+    G = Gl + H
     has_tax = len(P.tax_asset) > 0
     has_cap = bool(np.isfinite(P.tau))
     lift_ = bool(P.kappa > 0 or has_tax or has_cap)
@@ -170,17 +178,17 @@ def lift(P: AccountProblem) -> Lifted:
     nt = G
     nc = 1 if (lift_ and has_cap) else 0
 
+    lbv, ubv = box(P)
+    row_lo, row_hi = rows_bounds(P)
     q = np.concatenate([P.gamma * P.d[E], P.gamma * P.f,
                         np.zeros(np_ + ns + nt + nc)])
-    c = np.concatenate([-P.mu[E], np.zeros(ny),
+    c = np.concatenate([-linear_term(P)[E], np.zeros(ny),
                         np.full(np_, P.kappa), s_cost, np.zeros(nt + nc)])
-    lo = np.concatenate([np.full(nw, P.lb), np.full(ny, -np.inf),
-                         np.zeros(np_ + ns),
-                         P.band_lo if G else np.zeros(0),
+    lo = np.concatenate([lbv[E], np.full(ny, -np.inf),
+                         np.zeros(np_ + ns), row_lo,
                          np.zeros(nc)])
-    hi = np.concatenate([np.full(nw, P.ub), np.full(ny, np.inf),
-                         np.full(np_, np.inf), s_len,
-                         P.band_hi if G else np.zeros(0),
+    hi = np.concatenate([ubv[E], np.full(ny, np.inf),
+                         np.full(np_, np.inf), s_len, row_hi,
                          np.full(nc, np.inf)])
     # equality rows: [budget, factor (k), band (G), cap] then link rows
     b_coup = np.concatenate([[1.0], np.zeros(k), np.zeros(G),
@@ -191,7 +199,9 @@ def lift(P: AccountProblem) -> Lifted:
                   s_owner=s_owner, s_lot=s_lot,
                   nw=nw, ny=ny, np_=np_, ns=ns, nt=nt, nc=nc,
                   q=q, c=c, lo=lo, hi=hi, b=b,
-                  BE=P.B[E], gE=(P.group[E] if G else np.zeros(0, np.int64)),
+                  BE=P.B[E], gE=(P.group[E] if Gl else np.zeros(0, np.int64)),
+                  Gl=Gl, hE=(np.asarray(P.half, dtype=np.float64)[:, E] if H
+                             else np.zeros((0, n_e))),
                   const=const)
 
 
@@ -202,7 +212,8 @@ def A_mul(L: Lifted, x):
     w, y = x[L.sw()], x[L.sy()]
     out = [np.array([w.sum()]), y - L.BE.T @ w]
     if L.G:
-        out.append(np.bincount(L.gE, weights=w, minlength=L.G) - x[L.st()])
+        rw = np.concatenate([np.bincount(L.gE, weights=w, minlength=L.Gl), L.hE @ w])
+        out.append(rw - x[L.st()])
     if L.nc:
         out.append(np.array([x[L.sp()].sum() + x[L.ss()].sum() + x[L.sc()][0]]))
     if L.lift:
@@ -225,7 +236,9 @@ def AT_mul(L: Lifted, lam):
     ll = lam[o:o + L.n_link]
     gw = np.full(L.nw, lb_) - L.BE @ lf
     if G:
-        gw = gw + lg[L.gE]
+        gw = gw + L.hE.T @ lg[L.Gl:]
+        if L.Gl:
+            gw = gw + lg[:L.Gl][L.gE]
     if L.lift:
         gw = gw + ll
     gy = lf.copy()
@@ -252,10 +265,15 @@ def A_sparse(L: Lifted):
         vals += [-L.BE[:, j], np.array([1.0])]
         r += 1
     for g in range(L.G):
-        members = W[L.gE == g]
+        if g < L.Gl:
+            members = W[L.gE == g]
+            coef = np.ones(len(members))
+        else:
+            members = W
+            coef = L.hE[g - L.Gl]
         rows += [np.full(len(members), r, np.int64), np.array([r])]
         cols += [members, np.array([L.st().start + g])]
-        vals += [np.ones(len(members)), np.array([-1.0])]
+        vals += [coef, np.array([-1.0])]
         r += 1
     if L.nc:
         P_ = np.arange(L.sp().start, L.sp().stop)
@@ -294,8 +312,10 @@ class SchurSolver:
         Cw = np.zeros((m, L.nw))
         Cw[0] = 1.0
         Cw[1:1 + k] = -L.BE.T
-        if G:
+        if L.Gl:
             Cw[1 + k + L.gE, np.arange(L.nw)] = 1.0
+        if G > L.Gl:
+            Cw[1 + k + L.Gl:1 + k + G] = L.hE
         NCC = (Cw * hw) @ Cw.T
         NCC[np.arange(1, 1 + k), np.arange(1, 1 + k)] += hi[L.sy()]
         if G:
@@ -368,10 +388,11 @@ class IPMResult:
 def _initial_point(L: Lifted, P: AccountProblem):
     x = np.zeros(L.nvar)
     n_e = L.nw
-    span = P.ub - P.lb
-    theta = (1.0 - n_e * P.lb) / max(n_e * span, 1e-300)
+    lbE, ubE = L.lo[L.sw()], L.hi[L.sw()]
+    span = ubE - lbE
+    theta = (1.0 - lbE.sum()) / max(span.sum(), 1e-300)
     theta = min(max(theta, 0.05), 0.95)
-    w = np.full(n_e, P.lb + theta * span)
+    w = lbE + theta * span
     x[L.sw()] = w
     x[L.sy()] = L.BE.T @ w
     if L.lift:
@@ -391,7 +412,12 @@ def _initial_point(L: Lifted, P: AccountProblem):
         x[L.sp()] = p
         x[L.ss()] = sv
     if L.G:
-        x[L.st()] = 0.5 * (L.lo[L.st()] + L.hi[L.st()])
+        # the rows' values at the starting weights, moved inside their
+        # bounds below (a one-sided row has no midpoint)
+        x[L.st()] = np.concatenate([np.bincount(L.gE, weights=w, minlength=L.Gl),
+                                    L.hE @ w])
+        both_t = np.isfinite(L.lo[L.st()]) & np.isfinite(L.hi[L.st()])
+        x[L.st()] = np.where(both_t, 0.5 * (L.lo[L.st()] + L.hi[L.st()]), x[L.st()])
     if L.nc:
         x[L.sc()] = max(0.5 * L.b[L.n_coup - 1], 1e-3)
     # strictly inside bounds

@@ -1,28 +1,32 @@
 """External feasibility and KKT diagnostics (Sec. "External Diagnostics").
 
 Given returned weights and certificate data (nu for the budget, one signed
-multiplier per exposure band, lam_cap >= 0 for the turnover cap) this module
-computes, in float64 and from the inputs only:
+multiplier per constraint row -- exposure bands, then policy halfspaces --
+and lam_cap >= 0 for the turnover cap) this module computes, in float64 and
+from the inputs only:
 
   r_budget   = |1^T w - 1|
   r_box      = max(||(lb - w)_+||_inf, ||(w - ub)_+||_inf)   (excluded: ub = 0)
-  r_exposure = max(||(b_lo - A w)_+||_inf, ||(A w - b_hi)_+||_inf)
+  r_exposure = max(||(row_lo - R w)_+||_inf, ||(R w - row_hi)_+||_inf), R
+               the band rows and the halfspace rows
   r_turnover = (||w - w0||_1 - tau)_+
   r_prim     = max of the four, plus the largest snap distance below
 
 The stationarity check of the paper is written for smooth g_i; the trade costs
 here are piecewise linear, so stationarity is checked in its nonsmooth form:
-with g = gamma Sigma w - mu - nu 1 + A^T lam_band, every asset must satisfy
--g_i in J_i, the subdifferential of phi_i + lam_cap |. - w0_i| plus the normal
-cone of [lb, ub] at w_i.  A coordinate within eps_snap of a kink or bound is
-evaluated at that point; the distance moved is charged to r_prim.
+with g = gamma Sigma (w - w_b) - eta mu - nu 1 + R^T lam, every asset must
+satisfy -g_i in J_i, the subdifferential of phi_i + lam_cap |. - w0_i| plus
+the normal cone of [lb_i, ub_i] at w_i.  A coordinate within eps_snap of a
+kink or bound is evaluated at that point; the distance moved is charged to
+r_prim.
 
   r_dual = max_i dist(-g_i, J_i) / scale,  scale = max(||gamma Sigma w||_inf,
-           ||mu||_inf, 1e-12); a negative lam_cap is charged here too
-  r_comp = max(lam_cap |tau - ||w - w0||_1|, max_g |lam_g| slack_g) / scale
+           ||mu'||_inf, 1e-12) with mu' = eta mu + gamma Sigma w_b; a negative
+           lam_cap is charged here too
+  r_comp = max(lam_cap |tau - ||w - w0||_1|, max_r |lam_r| slack_r) / scale
 
-Sign convention for the band multipliers: lam_g > 0 means the upper band
-binds, lam_g < 0 the lower one.
+Sign convention for the row multipliers: lam_r > 0 means the upper bound of
+row r binds, lam_r < 0 the lower one.
 
 Test infrastructure only.
 """
@@ -30,17 +34,17 @@ from __future__ import annotations
 
 import numpy as np
 
-from .problem import AccountProblem, sigma_times, objective, kinks_and_slopes
+from .problem import (AccountProblem, sigma_times, objective, kinks_and_slopes, box,
+                      n_rows, rows_bounds, rows_mul, rows_tmul, linear_term)
 
 
 def residuals(P: AccountProblem, w, nu, lam_band=None, lam_cap=0.0,
               eps_snap=1e-10):
     w = np.asarray(w, dtype=np.float64)
     n = P.n
-    lb = np.where(P.eligible, P.lb, 0.0)
-    ub = np.where(P.eligible, P.ub, 0.0)
-    G = P.n_groups
-    lam_band = np.zeros(G) if lam_band is None or G == 0 else \
+    lb, ub = box(P)
+    R = n_rows(P)
+    lam_band = np.zeros(R) if lam_band is None or R == 0 else \
         np.asarray(lam_band, dtype=np.float64)
     lam_cap = float(lam_cap)
 
@@ -48,10 +52,11 @@ def residuals(P: AccountProblem, w, nu, lam_band=None, lam_cap=0.0,
     r_budget = abs(w.sum() - 1.0)
     r_box = max(float(np.max(lb - w, initial=0.0)),
                 float(np.max(w - ub, initial=0.0)), 0.0)
-    if G:
-        Aw = np.bincount(P.group, weights=w, minlength=G)
-        r_exp = max(float(np.max(P.band_lo - Aw, initial=0.0)),
-                    float(np.max(Aw - P.band_hi, initial=0.0)), 0.0)
+    if R:
+        row_lo, row_hi = rows_bounds(P)
+        Aw = rows_mul(P, w)
+        r_exp = max(float(np.max(row_lo - Aw, initial=0.0)),
+                    float(np.max(Aw - row_hi, initial=0.0)), 0.0)
     else:
         Aw = np.zeros(0)
         r_exp = 0.0
@@ -60,10 +65,11 @@ def residuals(P: AccountProblem, w, nu, lam_band=None, lam_cap=0.0,
 
     # ---- stationarity --------------------------------------------------
     Sw = sigma_times(P, w)
-    grad = P.gamma * Sw - P.mu
+    mu_eff = linear_term(P)
+    grad = P.gamma * Sw - mu_eff
     g = grad - nu
-    if G:
-        g = g + lam_band[P.group]
+    if R:
+        g = g + rows_tmul(P, lam_band)
     target = -g
     lo = np.empty(n)
     hi = np.empty(n)
@@ -95,7 +101,7 @@ def residuals(P: AccountProblem, w, nu, lam_band=None, lam_cap=0.0,
     lo = np.where(at_lb, -np.inf, lo)
     hi = np.where(at_ub, np.inf, hi)
     dist = np.maximum(np.maximum(lo - target, target - hi), 0.0)
-    scale = max(float(np.max(np.abs(P.gamma * Sw))), float(np.max(np.abs(P.mu))),
+    scale = max(float(np.max(np.abs(P.gamma * Sw))), float(np.max(np.abs(mu_eff))),
                 1e-12)
     r_dual = float(dist.max()) / scale if n else 0.0
     r_dual = max(r_dual, max(-lam_cap, 0.0) / scale)
@@ -106,9 +112,11 @@ def residuals(P: AccountProblem, w, nu, lam_band=None, lam_cap=0.0,
         comp = max(comp, max(lam_cap, 0.0) * abs(P.tau - turnover))
     else:
         comp = max(comp, abs(lam_cap))
-    if G:
-        slack = np.where(lam_band > 0, P.band_hi - Aw, Aw - P.band_lo)
-        comp = max(comp, float(np.max(np.abs(lam_band) * np.abs(slack))))
+    if R:
+        nz = lam_band != 0.0        # an infinite slack of a one-sided row
+        slack = np.where(lam_band > 0, row_hi - Aw, Aw - row_lo)
+        comp = max(comp, float(np.max(np.abs(lam_band[nz]) * np.abs(slack[nz]),
+                                      initial=0.0)))
     r_comp = comp / scale
 
     r_prim = max(r_budget, r_box, r_exp, r_turn) + float(snap.max(initial=0.0))

@@ -3,15 +3,19 @@
 The build's instantiation of the paper's problem class (Sec. "Benchmark
 Problem Class", Eq. 1) is
 
-    min_w  (gamma/2) w^T Sigma w - mu^T w + sum_i phi_i(w_i - w0_i)
-    s.t.   1^T w = 1,  lb <= w_i <= ub (w_i = 0 if excluded),
+    min_w  (gamma/2)(w - w_b)^T Sigma (w - w_b) - eta mu^T w
+           + sum_i phi_i(w_i - w0_i)
+    s.t.   1^T w = 1,  lb_i <= w_i <= ub_i (w_i = 0 if excluded),
            band_lo <= A w <= band_hi  (A one-hot by group label),
+           half_lo <= H w <= half_hi  (policy halfspace rows),
            sum_i |w_i - w0_i| <= tau,
 
 with Sigma = B diag(f) B^T + diag(d) and the separable trade cost
 phi_i(D) = kappa |D| + T_i((-D)_+), T_i the convex piecewise-linear tax on the
-sale amount.  This is Eq. 1 with Q = gamma Sigma, eta = 1, benchmark weights
-w_b = 0, no extra regulariser R and no policy halfspaces (D_a = I).
+sale amount.  This is Eq. 1 with Q = gamma Sigma, no extra regulariser R and
+D_a = I; the policy halfspaces G_a w <= h_a are rows H shared by the book
+with per-account two-sided bounds (one side may be infinite).  Without
+w_b and eta the instance is the budget / box / band / cap / tax problem.
 
 Test infrastructure only: nothing in the product path may import this package.
 """
@@ -43,6 +47,13 @@ class AccountProblem:
     tax_asset: np.ndarray
     tax_brk: np.ndarray
     tax_slope: np.ndarray
+    # the rest of Eq. 1: lb / ub may also be (n,) arrays; halfspace rows
+    # (H, n) with bounds (H,) (infinite: one-sided); benchmark w_b, eta
+    half: Optional[np.ndarray] = None
+    half_lo: Optional[np.ndarray] = None
+    half_hi: Optional[np.ndarray] = None
+    wb: Optional[np.ndarray] = None
+    eta: float = 1.0
 
     @property
     def n(self):
@@ -57,11 +68,17 @@ def account(uni, book, a: int) -> AccountProblem:
     """Extract account ``a`` of a (Universe, Book) pair."""
     ta, tb, ts = book.tax_of(a)
     G = uni.n_groups if book.band_lo is not None else 0
+    H = getattr(uni, "n_half", 0) if getattr(book, "half_lo", None) is not None else 0
+    lb_a = getattr(book, "lb_asset", None)
+    ub_a = getattr(book, "ub_asset", None)
+    wb = getattr(book, "wb", None)
+    eta = getattr(book, "eta", None)
     return AccountProblem(
         B=uni.B, f=uni.f, d=uni.d,
         group=uni.group if G else None, n_groups=G,
         mu=book.mu[a], w0=book.w0[a],
-        lb=float(book.lb[a]), ub=float(book.ub[a]),
+        lb=float(book.lb[a]) if lb_a is None else np.asarray(lb_a[a], dtype=np.float64),
+        ub=float(book.ub[a]) if ub_a is None else np.asarray(ub_a[a], dtype=np.float64),
         eligible=book.eligible[a],
         gamma=float(book.gamma[a]), kappa=float(book.kappa[a]),
         tau=float(book.tau[a]),
@@ -70,7 +87,95 @@ def account(uni, book, a: int) -> AccountProblem:
         tax_asset=np.asarray(ta, dtype=np.int64),
         tax_brk=np.asarray(tb, dtype=np.float64).reshape(-1, 3),
         tax_slope=np.asarray(ts, dtype=np.float64).reshape(-1, 4),
+        half=uni.half if H else None,
+        half_lo=book.half_lo[a] if H else None,
+        half_hi=book.half_hi[a] if H else None,
+        wb=None if wb is None else wb[a],
+        eta=1.0 if eta is None else float(eta[a]),
     )
+
+
+def box(P: AccountProblem):
+    """Per-asset bounds (lb, ub), [0, 0] for excluded assets."""
+    lb = np.broadcast_to(np.asarray(P.lb, dtype=np.float64), (P.n,))
+    ub = np.broadcast_to(np.asarray(P.ub, dtype=np.float64), (P.n,))
+    return np.where(P.eligible, lb, 0.0), np.where(P.eligible, ub, 0.0)
+
+
+def n_rows(P: AccountProblem) -> int:
+    """Constraint rows with two-sided bounds: exposure bands, then the
+    policy halfspaces."""
+    return P.n_groups + (0 if P.half is None else P.half.shape[0])
+
+
+def rows_matrix(P: AccountProblem):
+    """The (n_rows, n) matrix of those rows: one-hot band rows by group
+    label, then the halfspace rows."""
+    parts = []
+    if P.n_groups:
+        A = np.zeros((P.n_groups, P.n))
+        A[P.group, np.arange(P.n)] = 1.0
+        parts.append(A)
+    if P.half is not None:
+        parts.append(np.asarray(P.half, dtype=np.float64))
+    return np.vstack(parts) if parts else np.zeros((0, P.n))
+
+
+def rows_bounds(P: AccountProblem):
+    """(lo, hi) of the constraint rows, bands first."""
+    lo, hi = [], []
+    if P.n_groups:
+        lo.append(P.band_lo)
+        hi.append(P.band_hi)
+    if P.half is not None:
+        lo.append(P.half_lo)
+        hi.append(P.half_hi)
+    if not lo:
+        return np.zeros(0), np.zeros(0)
+    return (np.concatenate(lo).astype(np.float64), np.concatenate(hi).astype(np.float64))
+
+
+def rows_mul(P: AccountProblem, w):
+    """(A w, H w): the constraint rows applied to w (band sums by label,
+    then the halfspace rows)."""
+    w = np.asarray(w, dtype=np.float64)
+    out = []
+    if P.n_groups:
+        out.append(np.bincount(P.group, weights=w, minlength=P.n_groups))
+    if P.half is not None:
+        out.append(np.asarray(P.half, dtype=np.float64) @ w)
+    return np.concatenate(out) if out else np.zeros(0)
+
+
+def rows_tmul(P: AccountProblem, lam):
+    """A^T lam_band + H^T lam_half for one multiplier per constraint row."""
+    lam = np.asarray(lam, dtype=np.float64)
+    out = np.zeros(P.n)
+    G = P.n_groups
+    if G:
+        out += lam[:G][P.group]
+    if P.half is not None:
+        out += np.asarray(P.half, dtype=np.float64).T @ lam[G:]
+    return out
+
+
+def row_coeffs(P: AccountProblem, r: int, idx):
+    """Coefficients of constraint row r at the assets idx."""
+    G = P.n_groups
+    if r < G:
+        return (P.group[idx] == r).astype(np.float64)
+    return np.asarray(P.half[r - G], dtype=np.float64)[idx]
+
+
+def linear_term(P: AccountProblem):
+    """mu' = eta mu + gamma Sigma w_b: expanding (gamma/2)(w - w_b)^T Sigma
+    (w - w_b) - eta mu^T w gives (gamma/2) w^T Sigma w - mu'^T w plus the
+    constant (gamma/2) w_b^T Sigma w_b, so the optimum is that of the
+    instance without a benchmark and with mu' in place of mu."""
+    mu = P.eta * np.asarray(P.mu, dtype=np.float64)
+    if P.wb is not None:
+        mu = mu + P.gamma * sigma_times(P, np.asarray(P.wb, dtype=np.float64))
+    return mu
 
 
 def sigma_times(P: AccountProblem, w):
@@ -101,10 +206,18 @@ def trade_cost(P: AccountProblem, w):
     return total
 
 
-def objective(P: AccountProblem, w):
-    """f(w) of the build's Eq. 1 instance, recomputed in float64."""
+def _active(P: AccountProblem, w):
     w = np.asarray(w, dtype=np.float64)
-    return 0.5 * P.gamma * float(w @ sigma_times(P, w)) - float(P.mu @ w) \
+    return w - P.wb if P.wb is not None else w
+
+
+def objective(P: AccountProblem, w):
+    """f(w) of the build's Eq. 1 instance, recomputed in float64 from its
+    definition: (gamma/2)(w - w_b)^T Sigma (w - w_b) - eta mu^T w + trade
+    cost."""
+    w = np.asarray(w, dtype=np.float64)
+    e = _active(P, w)
+    return 0.5 * P.gamma * float(e @ sigma_times(P, e)) - P.eta * float(P.mu @ w) \
         + trade_cost(P, w)
 
 
@@ -112,10 +225,11 @@ def objective_scale(P: AccountProblem, w):
     """Denominator for relative objective errors: |f| or the sum of the
     magnitudes of its terms, whichever is larger (never zero)."""
     w = np.asarray(w, dtype=np.float64)
-    risk = 0.5 * P.gamma * float(w @ sigma_times(P, w))
-    ret = abs(float(P.mu @ w))
+    e = _active(P, w)
+    risk = 0.5 * P.gamma * float(e @ sigma_times(P, e))
+    ret = P.eta * float(P.mu @ w)
     tc = trade_cost(P, w)
-    return max(abs(risk - float(P.mu @ w) + tc), risk + ret + tc, 1e-300)
+    return max(abs(risk - ret + tc), risk + abs(ret) + tc, 1e-300)
 
 
 def kinks_and_slopes(P: AccountProblem, i: int, lam_cap: float = 0.0):

@@ -66,27 +66,63 @@ def closed_form_budget_only(B, f, d, mu, gamma):
     return w, nu
 
 
+def closed_form_benchmark(B, f, d, mu, gamma, wb, eta):
+    """min (gamma/2)(w - wb)^T Sigma (w - wb) - eta mu^T w  s.t. 1^T w = 1:
+    stationarity gamma Sigma (w - wb) - eta mu - nu 1 = 0, so
+    w = wb + Sigma^-1 (eta mu + nu 1) / gamma with nu from the budget."""
+    S = dense_sigma(B, f, d)
+    one = np.ones(len(mu))
+    Si_mu = np.linalg.solve(S, eta * mu)
+    Si_1 = np.linalg.solve(S, one)
+    nu = (gamma * (1.0 - one @ wb) - one @ Si_mu) / (one @ Si_1)
+    w = wb + (Si_mu + nu * Si_1) / gamma
+    return w, nu
+
+
 # ---------------------------------------------------------------------------
 # brute-force active-set enumeration (tiny N)
 # ---------------------------------------------------------------------------
 def brute_force(B, f, d, mu, gamma, lb, ub, w0=None, kappa=0.0, tax=None,
                 group=None, band_lo=None, band_hi=None, tau=np.inf,
-                tol=1e-9):
+                tol=1e-9, half=None, half_lo=None, half_hi=None, wb=None,
+                eta=1.0):
     """Enumerate, per asset, 'at point p' / 'inside piece q' states (points:
-    bounds and kinks of the trade cost inside the box), per band
-    off / at-lo / at-hi, and cap off / on.  Each pattern gives a linear
-    system; a pattern is accepted when its solution lies in the stated
-    pieces, satisfies every inactive constraint, and its multipliers have
-    the right signs and lie in the subdifferential at fixed coordinates.
+    bounds and kinks of the trade cost inside the box), per constraint row
+    (band by group label, or dense halfspace row) off / at-lo / at-hi (an
+    infinite bound has no 'at' state), and cap off / on.  Each pattern gives
+    a linear system; a pattern is accepted when its solution lies in the
+    stated pieces, satisfies every inactive constraint, and its multipliers
+    have the right signs and lie in the subdifferential at fixed
+    coordinates.  lb / ub may be per-asset arrays; the objective is
+    (1/2)(w - wb)^T (gamma Sigma) (w - wb) - eta mu^T w + trade cost, whose
+    gradient gamma Sigma (w - wb) - eta mu enters the stationarity rows.
 
-    Returns (w, nu, lam_band, lam_cap, n_accepted).
+    Returns (w, nu, lam_rows, lam_cap, n_accepted), lam_rows bands first.
     """
     n = len(mu)
     S = gamma * dense_sigma(B, f, d)
     w0 = np.zeros(n) if w0 is None else w0
     tax = tax or {}
     has_phi = kappa > 0 or bool(tax) or np.isfinite(tau)
-    G = 0 if group is None else int(band_lo.shape[0])
+    lbv = np.broadcast_to(np.asarray(lb, dtype=np.float64), (n,))
+    ubv = np.broadcast_to(np.asarray(ub, dtype=np.float64), (n,))
+    # constraint rows: one-hot bands, then dense halfspace rows
+    rows, rlo, rhi = [], [], []
+    if group is not None:
+        for g in range(int(band_lo.shape[0])):
+            rows.append((np.asarray(group) == g).astype(float))
+            rlo.append(band_lo[g])
+            rhi.append(band_hi[g])
+    if half is not None:
+        for h in range(half.shape[0]):
+            rows.append(np.asarray(half[h], dtype=np.float64))
+            rlo.append(half_lo[h])
+            rhi.append(half_hi[h])
+    G = len(rows)
+    Rm = np.vstack(rows) if G else np.zeros((0, n))
+    grad0 = -eta * np.asarray(mu, dtype=np.float64)
+    if wb is not None:
+        grad0 = grad0 - S @ wb
 
     per_asset = []
     for i in range(n):
@@ -95,6 +131,7 @@ def brute_force(B, f, d, mu, gamma, lb, ub, w0=None, kappa=0.0, tax=None,
             kinks, slopes = phi_pieces(w0[i], kappa, *(t if t else (None, None)))
         else:
             kinks, slopes = np.zeros(0), np.zeros(1)
+        lb, ub = lbv[i], ubv[i]
         pts = [lb, ub] + [c for c in kinks if lb < c < ub]
         pts = sorted(set(pts))
         states = [("at", p) for p in pts]
@@ -105,7 +142,9 @@ def brute_force(B, f, d, mu, gamma, lb, ub, w0=None, kappa=0.0, tax=None,
             states.append(("in", (a_, b_, slopes[q], sgn)))
         per_asset.append((states, kinks, slopes))
 
-    band_states = list(itertools.product(("off", "lo", "hi"), repeat=G))
+    band_states = list(itertools.product(*[
+        ["off"] + (["lo"] if np.isfinite(rlo[g]) else []) + (["hi"] if np.isfinite(rhi[g]) else [])
+        for g in range(G)]))
     cap_states = ("off", "on") if np.isfinite(tau) else ("off",)
 
     def subdiff(i, x, lam_cap):
@@ -124,9 +163,9 @@ def brute_force(B, f, d, mu, gamma, lb, ub, w0=None, kappa=0.0, tax=None,
                 lo_ = hi_ = sl[q]
         else:
             lo_ = hi_ = 0.0
-        if abs(x - lb) <= tol:
+        if abs(x - lbv[i]) <= tol:
             lo_ = -np.inf
-        if abs(x - ub) <= tol:
+        if abs(x - ubv[i]) <= tol:
             hi_ = np.inf
         return lo_, hi_
 
@@ -148,12 +187,12 @@ def brute_force(B, f, d, mu, gamma, lb, ub, w0=None, kappa=0.0, tax=None,
                     else:
                         M[i, :n] = S[i]
                         M[i, n] = -1.0
-                        r[i] = mu[i] - st[1][2]
+                        r[i] = -grad0[i] - st[1][2]
                         sgn_all[i] = st[1][3]
                 for j, g in enumerate(act):
                     for i, st in enumerate(combo):
-                        if st[0] == "in" and group[i] == g:
-                            M[i, n + 1 + j] = 1.0
+                        if st[0] == "in":
+                            M[i, n + 1 + j] = Rm[g, i]
                 if cst == "on":
                     for i, st in enumerate(combo):
                         if st[0] == "in":
@@ -162,8 +201,8 @@ def brute_force(B, f, d, mu, gamma, lb, ub, w0=None, kappa=0.0, tax=None,
                 M[row, :n] = 1.0
                 r[row] = 1.0
                 for j, g in enumerate(act):
-                    M[n + 1 + j, :n] = (group == g).astype(float)
-                    r[n + 1 + j] = band_lo[g] if bst[g] == "lo" else band_hi[g]
+                    M[n + 1 + j, :n] = Rm[g]
+                    r[n + 1 + j] = rlo[g] if bst[g] == "lo" else rhi[g]
                 if cst == "on":
                     M[m - 1, :n] = sgn_all
                     r[m - 1] = tau + sgn_all @ w0
@@ -189,10 +228,10 @@ def brute_force(B, f, d, mu, gamma, lb, ub, w0=None, kappa=0.0, tax=None,
                     continue
                 # inactive constraints, signs
                 if G:
-                    Aw = np.array([w[group == g].sum() for g in range(G)])
+                    Aw = Rm @ w
                     for g in range(G):
-                        if bst[g] == "off" and not (band_lo[g] - tol <= Aw[g]
-                                                    <= band_hi[g] + tol):
+                        if bst[g] == "off" and not (rlo[g] - tol <= Aw[g]
+                                                    <= rhi[g] + tol):
                             ok = False
                         if bst[g] == "hi" and lam[g] < -tol:
                             ok = False
@@ -206,9 +245,9 @@ def brute_force(B, f, d, mu, gamma, lb, ub, w0=None, kappa=0.0, tax=None,
                 if not ok:
                     continue
                 # subgradient condition at fixed coordinates
-                grad = S @ w - mu - nu
+                grad = S @ w + grad0 - nu
                 if G:
-                    grad = grad + lam[group]
+                    grad = grad + Rm.T @ lam
                 for i, st in enumerate(combo):
                     if st[0] == "at":
                         lo_, hi_ = subdiff(i, w[i], lam_cap)

@@ -58,6 +58,13 @@ class Universe:
     d: np.ndarray            # (N,)
     group: Optional[np.ndarray] = None   # (N,) int32
     n_groups: int = 0
+    # policy halfspace rows of Eq. 1 shared by the book (for example factor
+    # exposures B[:, j]^T w); each account bounds them with half_lo/half_hi
+    half: Optional[np.ndarray] = None    # (H, N)
+
+    @property
+    def n_half(self) -> int:
+        return 0 if self.half is None else self.half.shape[0]
 
     @property
     def n(self) -> int:
@@ -92,6 +99,15 @@ class Book:
     tax_asset: np.ndarray = field(default_factory=lambda: np.zeros(0, np.int32))
     tax_brk: np.ndarray = field(default_factory=lambda: np.zeros((0, 3)))
     tax_slope: np.ndarray = field(default_factory=lambda: np.zeros((0, 4)))
+    # the rest of Eq. 1 (all optional): per-asset bounds (replacing lb / ub
+    # for eligible names), bounds of the universe's halfspace rows (-inf /
+    # +inf: one-sided), benchmark weights w_b and the return scale eta
+    lb_asset: Optional[np.ndarray] = None  # (M, N)
+    ub_asset: Optional[np.ndarray] = None  # (M, N)
+    half_lo: Optional[np.ndarray] = None   # (M, H)
+    half_hi: Optional[np.ndarray] = None   # (M, H)
+    wb: Optional[np.ndarray] = None        # (M, N)
+    eta: Optional[np.ndarray] = None       # (M,)
 
     @property
     def m(self) -> int:
@@ -176,9 +192,20 @@ def make_config(name: str, seed: int = 0, **over) -> tuple[Universe, Book]:
     held, tax, cap_slack, mu_mean, mu_sd, w0) scale a configuration down for
     tests or switch features on and off.  ``w0='dirichlet'`` forces a dense
     Dirichlet(1) starting portfolio; ``w0='zero'`` forces an empty one.
+
+    The rest of Eq. 1, off by default: ``halfspaces=H`` adds H policy rows,
+    the exposures to the first H factors, bounded within
+    ``half_halfwidth`` of the equal-weight exposure (the last row one-sided,
+    upper bound only); ``asset_bounds=True`` draws per-asset upper bounds
+    ub * U[0.5, 1.5] and a minimum holding of a fifth of that on 2 % of the
+    eligible names; ``benchmark=True`` draws benchmark weights w_b (a
+    Dirichlet portfolio projected onto the box) and eta ~ U[0.5, 1.5].
+    These draws come after every other draw of the account, so switching
+    them on leaves the rest of the book unchanged.
     """
     p = config_defaults(name)
-    p.update(mu_mean=5e-4, mu_sd=1e-2, w0=None)
+    p.update(mu_mean=5e-4, mu_sd=1e-2, w0=None, halfspaces=0, half_halfwidth=2e-3,
+             asset_bounds=False, benchmark=False)
     for key, val in over.items():
         if key not in p:
             raise KeyError(f"unknown override {key!r}")
@@ -202,6 +229,22 @@ def make_config(name: str, seed: int = 0, **over) -> tuple[Universe, Book]:
         band_hi = np.tile(to_f32_exact(share + hw), (M, 1))
     t_ptr = [0]
     t_asset, t_brk, t_slope = [], [], []
+    H = int(p["halfspaces"])
+    if H > k:
+        raise ValueError("halfspaces: at most one row per factor")
+    half = half_lo = half_hi = None
+    if H:
+        half = np.ascontiguousarray(uni.B[:, :H].T)
+        uni = replace(uni, half=half)
+        ew = half.sum(axis=1) / N
+        hw = float(p["half_halfwidth"])
+        half_lo = np.tile(to_f32_exact(ew - hw), (M, 1))
+        half_hi = np.tile(to_f32_exact(ew + hw), (M, 1))
+        half_lo[:, H - 1] = -np.inf
+    lb_asset = np.zeros((M, N)) if p["asset_bounds"] else None
+    ub_asset = np.zeros((M, N)) if p["asset_bounds"] else None
+    wb = np.zeros((M, N)) if p["benchmark"] else None
+    eta = np.ones(M) if p["benchmark"] else None
 
     w0_mode = p["w0"]
     if w0_mode is None:
@@ -242,8 +285,19 @@ def make_config(name: str, seed: int = 0, **over) -> tuple[Universe, Book]:
                 t_brk.append(brk)
                 t_slope.append(slope)
         t_ptr.append(len(t_asset))
+        if p["asset_bounds"]:
+            ub_asset[a] = to_f32_exact(ub * rng.uniform(0.5, 1.5, size=N))
+            n_min = int(0.02 * np.count_nonzero(elig[a]))
+            pick = rng.choice(np.nonzero(elig[a])[0], size=n_min, replace=False)
+            lb_asset[a, pick] = to_f32_exact(0.2 * ub_asset[a, pick])
+        if p["benchmark"]:
+            cap_b = ub_asset[a] if p["asset_bounds"] else np.full(N, ub)
+            raw = rng.dirichlet(np.ones(N))
+            wb[a] = to_f32_exact(np.minimum(_project_capped_simplex(raw, float(cap_b.max())),
+                                            cap_b))
+            eta[a] = to_f32_exact(rng.uniform(0.5, 1.5))
         if p["cap_slack"] is not None:
-            u_a = np.where(elig[a], ub, 0.0)
+            u_a = np.where(elig[a], ub_asset[a] if p["asset_bounds"] else ub, 0.0)
             tau_min = 2.0 * np.maximum(w0[a] - u_a, 0.0).sum()
             t = np.float32(tau_min + float(p["cap_slack"]))
             tau[a] = float(t)
@@ -259,6 +313,8 @@ def make_config(name: str, seed: int = 0, **over) -> tuple[Universe, Book]:
         tax_asset=np.asarray(t_asset, dtype=np.int32).reshape(-1),
         tax_brk=np.asarray(t_brk, dtype=np.float64).reshape(-1, 3),
         tax_slope=np.asarray(t_slope, dtype=np.float64).reshape(-1, 4),
+        lb_asset=lb_asset, ub_asset=ub_asset, half_lo=half_lo, half_hi=half_hi,
+        wb=wb, eta=eta,
     )
     return uni, book
 
@@ -287,4 +343,10 @@ def subset_accounts(book: Book, idx) -> Book:
         tax_asset=cat(assets, (0,)).astype(np.int32),
         tax_brk=cat(brk, (0, 3)).reshape(-1, 3),
         tax_slope=cat(slope, (0, 4)).reshape(-1, 4),
+        lb_asset=None if book.lb_asset is None else book.lb_asset[idx].copy(),
+        ub_asset=None if book.ub_asset is None else book.ub_asset[idx].copy(),
+        half_lo=None if book.half_lo is None else book.half_lo[idx].copy(),
+        half_hi=None if book.half_hi is None else book.half_hi[idx].copy(),
+        wb=None if book.wb is None else book.wb[idx].copy(),
+        eta=None if book.eta is None else book.eta[idx].copy(),
     )
