@@ -4,15 +4,21 @@
  * Each account a of a book solves the paper's problem class (Eq. 1, Sec.
  * "Benchmark Problem Class") in this instantiation:
  *
- *   min_w (gamma_a/2) w^T Sigma w - mu_a^T w + sum_i phi_ai(w_i - w0_ai)
+ *   min_w (gamma_a/2)(w - wb_a)^T Sigma (w - wb_a) - eta_a mu_a^T w
+ *         + sum_i phi_ai(w_i - w0_ai)
  *   s.t.  1^T w = 1                                  (budget)
- *         lb_a <= w_i <= ub_a, w_i = 0 if excluded    (box, exclusion mask)
+ *         lb_ai <= w_i <= ub_ai, w_i = 0 if excluded  (box, exclusion mask)
  *         band_lo_a <= A w <= band_hi_a               (one-hot exposure bands)
+ *         half_lo_a <= H w <= half_hi_a               (policy halfspaces)
  *         sum_i |w_i - w0_ai| <= tau_a                (turnover cap)
  *
  *   Sigma  = B diag(f) B^T + diag(d)   (factor risk model shared by the book)
  *   phi_ai(D) = kappa_a |D| + T_ai((-D)_+), T_ai the convex piecewise-linear
  *              tax on the sold amount (four lots, three breakpoints).
+ *   H (n_half rows) is shared by the book (the policy halfspaces G_a w <= h_a
+ *   of Eq. 1 with G_a = H); each account bounds its rows, either side
+ *   possibly infinite.  Without wb / eta the risk is (gamma_a/2) w^T Sigma w
+ *   and eta_a = 1.
  *
  * The solver returns weights, a status per account, iteration counts and
  * the external diagnostics of Sec. "External Diagnostics" recomputed in
@@ -84,6 +90,9 @@ typedef struct fqp_universe {
   const float *f;        /* [k]   factor variances, > 0                    */
   const float *d;        /* [n]   idiosyncratic variances, > 0             */
   const int32_t *group;  /* [n]   labels in [0, n_groups); NULL if none    */
+  int32_t n_half;        /* policy halfspace rows, 0..64 - n_groups        */
+  const float *half;     /* [n_half][n] rows H of the halfspaces; NULL if
+                            n_half = 0                                     */
 } fqp_universe;
 
 /* Per-account data of Eq. 1 for m accounts (m * n < 2^31 per call). */
@@ -107,12 +116,22 @@ typedef struct fqp_book {
                                 0 < b1 < b2 < b3                            */
   const float *tax_slope;    /* [nnz][4] lot slopes, 0 <= s0 <= .. <= s3     */
   const float *warm_state;   /* NULL, or an ADMM state block of
-                                fqp_state_floats(m, n, n_groups) floats that an
+                                fqp_state_floats(m, n, n_groups + n_half)
+                                floats that an
                                 earlier call wrote to fqp_result.state (the
                                 same accounts, any handle or process); used
                                 when settings.warm_start = 1 (the cold /
                                 repeated / warm lanes of Sec. "Timing
                                 Lanes").  Non-finite entries restart from 0 */
+  /* The rest of Eq. 1; every pointer may be NULL. */
+  const float *lb_asset;     /* [m][n] per-asset lower bounds (replace lb for
+                                eligible names); NULL = lb[a] everywhere    */
+  const float *ub_asset;     /* [m][n] per-asset upper bounds; NULL = ub[a] */
+  const float *half_lo;      /* [m][n_half] lower bounds of H w (-INF: none);
+                                required when n_half > 0                    */
+  const float *half_hi;      /* [m][n_half] upper bounds of H w (+INF: none) */
+  const float *wb;           /* [m][n] benchmark weights w_b; NULL = 0       */
+  const float *eta;          /* [m] return scale eta >= 0; NULL = 1          */
 } fqp_book;
 
 /* Arithmetic of the factor contractions inside the ADMM iterations (the
@@ -121,7 +140,7 @@ typedef enum {
   FQP_PREC_FP32 = 0,    /* float32 MFMA (32x32x2)                           */
   FQP_PREC_BF16X3 = 1   /* bf16 MFMA on hi/lo splits of each float32 operand:
                            hi*hi + hi*lo + lo*hi, float32 accumulation
-                           (factor blocks k + n_groups + 1 <= 96; wider ones
+                           (factor blocks k + n_groups + n_half + 1 <= 96; wider ones
                            run the float32 contraction)                    */
 } fqp_precision;
 
@@ -151,7 +170,8 @@ typedef struct fqp_settings {
                             from the ADMM state (v, band state, cap
                             multiplier) this handle kept from its last
                             completed solve, when that book had the same m,
-                            n and n_groups (e.g. the same accounts with the
+                            n and constraint rows (n_groups + n_half; e.g.
+                            the same accounts with the
                             next day's returns); otherwise, or 0: cold.  Any
                             start converges to the same optimum            */
   int32_t debug_fail_alloc; /* test hook: > 0 makes the workspace request
@@ -176,15 +196,19 @@ typedef struct fqp_result {
   double *obj;        /* [m] objective recomputed in float64               */
   double *nu;         /* [m] budget multiplier                             */
   double *lam_cap;    /* [m] turnover-cap multiplier (>= 0)                */
-  double *lam_band;   /* [m][n_groups] band multipliers (> 0: upper binds) */
-  float *state;       /* NULL, or fqp_state_floats(m, n, n_groups) floats:
-                         the final ADMM state (v [m][n], band z [m][G], band
-                         u [m][G], cap multiplier [m]) for a later warm
-                         start through fqp_book.warm_state                */
+  double *lam_band;   /* [m][n_groups + n_half] multipliers of the band rows,
+                         then of the halfspace rows (> 0: the upper bound
+                         binds, < 0: the lower one)                      */
+  float *state;       /* NULL, or fqp_state_floats(m, n, n_groups + n_half)
+                         floats: the final ADMM state (v [m][n], row z
+                         [m][R], row u [m][R], cap multiplier [m], R =
+                         n_groups + n_half) for a later warm start through
+                         fqp_book.warm_state                             */
 } fqp_result;
 
 /* Size in floats of an ADMM state block (fqp_book.warm_state,
- * fqp_result.state): m n + 2 m n_groups + m. */
+ * fqp_result.state): m n + 2 m R + m, R = n_groups + n_half (the third
+ * argument). */
 static inline size_t fqp_state_floats(int32_t m, int32_t n, int32_t n_groups) {
   return (size_t)m * (size_t)n + 2 * (size_t)m * (size_t)n_groups + (size_t)m;
 }

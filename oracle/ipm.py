@@ -416,8 +416,17 @@ def _initial_point(L: Lifted, P: AccountProblem):
         # bounds below (a one-sided row has no midpoint)
         x[L.st()] = np.concatenate([np.bincount(L.gE, weights=w, minlength=L.Gl),
                                     L.hE @ w])
-        both_t = np.isfinite(L.lo[L.st()]) & np.isfinite(L.hi[L.st()])
-        x[L.st()] = np.where(both_t, 0.5 * (L.lo[L.st()] + L.hi[L.st()]), x[L.st()])
+        tlo, thi = L.lo[L.st()], L.hi[L.st()]
+        both_t = np.isfinite(tlo) & np.isfinite(thi)
+        rw = x[L.st()]
+        # one-sided rows: a tenth of the values' scale inside the finite bound
+        # (a start 1e-12 inside it is badly centred)
+        with np.errstate(invalid="ignore"):
+            margin = 0.1 * np.maximum(np.maximum(np.abs(np.where(np.isfinite(thi), thi, tlo)),
+                                                 np.abs(rw)), 1e-8)
+        t = np.where(np.isfinite(thi) & ~both_t, np.minimum(rw, thi - margin), rw)
+        t = np.where(np.isfinite(tlo) & ~both_t, np.maximum(t, tlo + margin), t)
+        x[L.st()] = np.where(both_t, 0.5 * (tlo + thi), t)
     if L.nc:
         x[L.sc()] = max(0.5 * L.b[L.n_coup - 1], 1e-3)
     # strictly inside bounds

@@ -27,7 +27,7 @@ STATUS_NAMES = {
 class Universe(ctypes.Structure):
     _fields_ = [("n", c_int32), ("k", c_int32), ("n_groups", c_int32),
                 ("B", c_void_p), ("f", c_void_p), ("d", c_void_p),
-                ("group", c_void_p)]
+                ("group", c_void_p), ("n_half", c_int32), ("half", c_void_p)]
 
 
 class Book(ctypes.Structure):
@@ -37,7 +37,10 @@ class Book(ctypes.Structure):
                 ("band_lo", c_void_p), ("band_hi", c_void_p),
                 ("tax_ptr", c_void_p), ("tax_asset", c_void_p),
                 ("tax_brk", c_void_p), ("tax_slope", c_void_p),
-                ("warm_state", c_void_p)]
+                ("warm_state", c_void_p),
+                ("lb_asset", c_void_p), ("ub_asset", c_void_p),
+                ("half_lo", c_void_p), ("half_hi", c_void_p),
+                ("wb", c_void_p), ("eta", c_void_p)]
 
 
 class Settings(ctypes.Structure):
@@ -70,9 +73,10 @@ class Stats(ctypes.Structure):
                 ("graph_reused", c_int32), ("workspace_requests", c_int32)]
 
 
-def state_floats(m: int, n: int, n_groups: int) -> int:
-    """Floats of an ADMM state block (fqp_book.warm_state / fqp_result.state)."""
-    return m * n + 2 * m * n_groups + m
+def state_floats(m: int, n: int, n_rows: int) -> int:
+    """Floats of an ADMM state block (fqp_book.warm_state / fqp_result.state);
+    n_rows = n_groups + n_half."""
+    return m * n + 2 * m * n_rows + m
 
 
 EXPORTS = ("fqp_default_settings", "fqp_create", "fqp_solve_batch",

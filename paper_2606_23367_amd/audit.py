@@ -26,7 +26,8 @@ def _host(t):
 def audit_records(P, out: dict, solver) -> list:
     """One record per account of the last ``solver.solve(P)`` whose outputs
     are ``out``: input_sha256 over the account's data (returns, holdings,
-    box, eligibility, scalars, bands, tax lots), output_sha256 over its
+    box, eligibility, scalars, bands, tax lots, and the halfspace bounds,
+    per-asset bounds, benchmark and return scale when given), output_sha256 over its
     float64 weights, status, iterations and completed_ms."""
     passes = solver.pass_times()
     total_ms = solver.stats()["total_ms"]
@@ -36,6 +37,9 @@ def audit_records(P, out: dict, solver) -> list:
     blo, bhi = _host(P.band_lo), _host(P.band_hi)
     tptr, tas, tbr, tsl = _host(P.tax_ptr), _host(P.tax_asset), _host(P.tax_brk), _host(P.tax_slope)
     w, status, iters = _host(out["w"]), _host(out["status"]), _host(out["iters"])
+    extra = [x for x in (_host(getattr(P, name, None)) for name in
+                         ("half_lo", "half_hi", "lb_asset", "ub_asset", "wb", "eta"))
+             if x is not None]
     recs = []
     for a in range(P.m):
         h = hashlib.sha256()
@@ -51,6 +55,8 @@ def audit_records(P, out: dict, solver) -> list:
             s, e = int(tptr[a]), int(tptr[a + 1])
             for arr in (tas[s:e], tbr[s:e], tsl[s:e]):
                 h.update(np.ascontiguousarray(arr).tobytes())
+        for arr in extra:                       # the rest of Eq. 1, when given
+            h.update(np.ascontiguousarray(arr[a]).tobytes())
         st = int(status[a])
         it = int(iters[a])
         recs.append({

@@ -10,8 +10,10 @@
 //
 // Differentiating, for a loss L with gradient c = dL/dw the adjoint solves
 //   [gamma Sigma_FF  C_F^T; C_F  0] [v; xi] = [c_F; 0],   v = 0 off F,
-// and then  dL/dmu = v  and  dL/dB = -sum_a gamma_a (v_a (F B^T w_a)^T +
-// w_a (F B^T v_a)^T)  (Sigma w changes by dB F B^T w + B F dB^T w).
+// and then  dL/dmu = eta v  and  dL/dB = -sum_a gamma_a (v_a (F B^T e_a)^T +
+// e_a (F B^T v_a)^T)  with e = w - w_b (Sigma e changes by dB F B^T e +
+// B F dB^T e; the halfspace rows are data of their own).  The constraint
+// rows C_F are the budget, the binding band and halfspace rows and the cap.
 // The solve reuses the polish's factor-space structure: Kf = diag(f)^-1 +
 // B_F^T D_F^-1 B_F in LDS, Schur complement on the constraint rows.
 #include "fqp_common.h"
@@ -124,7 +126,7 @@ __global__ __launch_bounds__(256) void adjoint_solve_kernel(AdjArgs A) {
         int col = 1;
         for (int g = 0; g < G; ++g) {
           if (!band_on(ps, g)) continue;
-          vv[col++] = (A.group[i] == g) ? 1.0 : 0.0;
+          vv[col++] = row_coef(A, i, g);
         }
         if (cap_on) {
           // side of w0 of the piece the free coordinate lies in
@@ -240,7 +242,7 @@ __global__ __launch_bounds__(256) void adjoint_solve_kernel(AdjArgs A) {
     int col = 1;
     for (int g = 0; g < G; ++g) {
       if (!band_on(ps, g)) continue;
-      if (A.group[i] == g) ct += xi[col];
+      ct += row_coef(A, i, g) * xi[col];
       ++col;
     }
     if (cap_on) ct += ((w[i] > (double)A.w0in[(size_t)a * n + i]) ? 1.0 : -1.0) * xi[col];
@@ -262,7 +264,8 @@ __global__ __launch_bounds__(256) void adjoint_solve_kernel(AdjArgs A) {
       const int i = flist[n - 1 - t];
       sw += (double)A.Bt[(size_t)i * A.kp + j] * w[i];
     }
-    A.yvw[(size_t)a * 2 * k + j] = gam * (double)A.f[j] * sw;        // gamma F B^T w
+    if (A.wb) sw -= A.ywb[(size_t)a * k + j];                         // e = w - w_b
+    A.yvw[(size_t)a * 2 * k + j] = gam * (double)A.f[j] * sw;        // gamma F B^T e
     A.yvw[(size_t)a * 2 * k + k + j] = gam * (double)A.f[j] * sv;    // gamma F B^T v
   }
   (void)code;
@@ -285,7 +288,8 @@ __global__ __launch_bounds__(256) void adjoint_db_kernel(AdjArgs A) {
     if (tid < 64) {
       const int i = r0 + tid;
       sv[tid] = (i < n) ? A.dmu[(size_t)a * n + i] : 0.0;
-      sw[tid] = (i < n) ? A.w[(size_t)a * n + i] : 0.0;
+      sw[tid] = (i < n) ? A.w[(size_t)a * n + i] - (A.wb ? (double)A.wb[(size_t)a * n + i] : 0.0)
+                        : 0.0;
     }
     __syncthreads();
     const double* y = A.yvw + (size_t)a * 2 * k;
@@ -308,6 +312,14 @@ __global__ __launch_bounds__(256) void adjoint_db_kernel(AdjArgs A) {
   }
 }
 
+// dL/dmu = eta dL/dmu' (mu' = eta mu + gamma Sigma w_b), after dL/dB used v
+__global__ void adjoint_eta_kernel(AdjArgs A) {
+  const size_t total = (size_t)A.m * A.n;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (size_t)gridDim.x * blockDim.x)
+    A.dmu[e] *= (double)A.eta[e / A.n];
+}
+
 hipError_t launch_adjoint(const AdjArgs& A, hipStream_t st) {
   const size_t smem = sizeof(double) * ((size_t)A.k * A.k + 16 * (size_t)(A.k + 4) +
                                         16 * (size_t)(kMaxG + 3));
@@ -318,6 +330,9 @@ hipError_t launch_adjoint(const AdjArgs& A, hipStream_t st) {
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(adjoint_db_kernel, dim3((A.n + 63) / 64), dim3(256), 0, st, A);
+  e = hipGetLastError();
+  if (e != hipSuccess || !A.eta) return e;
+  hipLaunchKernelGGL(adjoint_eta_kernel, dim3(1024), dim3(256), 0, st, A);
   return hipGetLastError();
 }
 

@@ -46,10 +46,12 @@ namespace fqp {
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 
 // ---------------------------------------------------------------------------
-// universe packing:  B~ = [B | onehot(group) | 1 | 0]
+// universe packing:  B~ = [B | onehot(group) | H^T | 1 | 0]
+// (the halfspace rows enter the x-update as further low-rank directions,
+// exactly as the one-hot band rows do)
 // ---------------------------------------------------------------------------
-__global__ void build_bt_kernel(int n, int k, int G, int kp, const float* B,
-                                const int32_t* group, float* Bt) {
+__global__ void build_bt_kernel(int n, int k, int G, int H, int kp, const float* B,
+                                const int32_t* group, const float* half, float* Bt) {
   size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   size_t total = (size_t)n * kp;
   if (e >= total) return;
@@ -57,7 +59,8 @@ __global__ void build_bt_kernel(int n, int k, int G, int kp, const float* B,
   float v = 0.f;
   if (j < k) v = B[(size_t)i * k + j];
   else if (j < k + G) v = (group[i] == j - k) ? 1.f : 0.f;
-  else if (j == k + G) v = 1.f;
+  else if (j < k + G + H) v = half[(size_t)(j - k - G) * n + i];
+  else if (j == k + G + H) v = 1.f;
   Bt[e] = v;
 }
 
@@ -252,13 +255,13 @@ __device__ __forceinline__ float prox_row(const RowInfo& ri, float v, float th, 
 // holding word and the holding prefix word (already loaded) and the
 // account's first record hptr: one more dependent load, only for held rows
 template <typename Args>
-__device__ __forceinline__ RowInfo row_info_w(const Args& A, int row, float lbp, float ubp,
-                                              uint32_t ew, uint32_t hw, int hpre, int hptr) {
+__device__ __forceinline__ RowInfo row_info_w(const Args& A, size_t off, int row, float lbp,
+                                              float ubp, uint32_t ew, uint32_t hw, int hpre,
+                                              int hptr) {
   RowInfo ri;
   const int b = row & 31;
   const bool el = (ew >> b) & 1u;
-  ri.lb = el ? lbp : 0.f;
-  ri.ub = el ? ubp : 0.f;
+  asset_box(A, off, el, lbp, ubp, ri.lb, ri.ub);
   ri.w0 = 0.f;
   ri.taxed = false;
   if ((hw >> b) & 1u) {
@@ -276,7 +279,8 @@ template <typename Args>
 __device__ __forceinline__ RowInfo row_info(const Args& A, int a, int row, float lbp, float ubp) {
   const size_t wi = (size_t)a * A.W + (row >> 5);
   const uint32_t ew = A.elig ? A.elig[wi] : 0xffffffffu;
-  return row_info_w(A, row, lbp, ubp, ew, A.hold[wi], A.hold_pre[wi], A.hold_ptr[a]);
+  return row_info_w(A, (size_t)a * A.n + row, row, lbp, ubp, ew, A.hold[wi], A.hold_pre[wi],
+                    A.hold_ptr[a]);
 }
 
 template <int NCH, int MODE>
@@ -423,7 +427,8 @@ __global__ __launch_bounds__(256, 2) void iter_kernel(IterArgs A) {
         const unsigned off = (unsigned)(Ao[m] + row);
         const float mu = mu_r[r];
         const float vv = v_r[r];
-        const RowInfo ri = row_info_w(A, row, q1.x, q1.y, ew_r[r], hw_r[r], hp_r[r], Hp[m]);
+        const RowInfo ri = row_info_w(A, (size_t)off, row, q1.x, q1.y, ew_r[r], hw_r[r],
+                                      hp_r[r], Hp[m]);
         const float z = prox_row(ri, vv, q0.w, irho, nullptr);
         const float u = vv - z;
         Rp = (mu + rho * (z - u)) * iDelta;
@@ -732,9 +737,7 @@ __global__ __launch_bounds__(256, 3) void iter_kernel_bf(IterArgs A) {
         const float iDelta = __builtin_amdgcn_rcpf(q0.z * d_i + rho);
         const unsigned off = (unsigned)(Ao[m] + row);
         RowInfo ri;
-        const bool el = (el_bits >> r) & 1u;
-        ri.lb = el ? q1.x : 0.f;
-        ri.ub = el ? q1.y : 0.f;
+        asset_box(A, (size_t)off, (el_bits >> r) & 1u, q1.x, q1.y, ri.lb, ri.ub);
         ri.w0 = 0.f;
         ri.taxed = false;
         if (held) {
@@ -1055,7 +1058,8 @@ __global__ __launch_bounds__(kCapT) void cap_stream_kernel(IterArgs A) {
       for (int q = 0; q < 8; ++q) {
         const int i = i0 + q * kCapT + tid;
         if (i < n) {
-          const RowInfo ri = row_info_w(A, i, lbp, ubp, ew[q], hw[q], hp[q], hptr);
+          const RowInfo ri = row_info_w(A, (size_t)a * n + i, i, lbp, ubp, ew[q], hw[q], hp[q],
+                                        hptr);
           bool kink;
           const float z = prox_row(ri, vr[q], th, irho, &kink);
           g += fabsf(z - ri.w0);
@@ -1403,6 +1407,8 @@ hipError_t launch_iter(const IterArgs& A, int kp, int mode, int prec, dim3 grid,
 bool cap_resident_fits(int n, int max_held) {
   return n <= kCapQ * kCapT && max_held <= kCapH;
 }
+// (the resident layout keeps one box per account; books with per-asset
+// bounds take the streaming layout)
 
 hipError_t launch_cap(const IterArgs& A, int m_total, bool resident, hipStream_t st) {
   if (resident)
@@ -1432,11 +1438,11 @@ hipError_t launch_split_bt(int n, int npad, int kp, const float* Bt, uint16_t* b
   return hipGetLastError();
 }
 
-hipError_t launch_build_bt(int n, int k, int G, int kp, const float* B, const int32_t* group,
-                           float* Bt, hipStream_t st) {
+hipError_t launch_build_bt(int n, int k, int G, int H, int kp, const float* B,
+                           const int32_t* group, const float* half, float* Bt, hipStream_t st) {
   size_t total = (size_t)n * kp;
   hipLaunchKernelGGL(build_bt_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st,
-                     n, k, G, kp, B, group, Bt);
+                     n, k, G, H, kp, B, group, half, Bt);
   return hipGetLastError();
 }
 

@@ -34,6 +34,8 @@ struct IterArgs {
   const float* par;          // [m][kNPar]
   float* par_rw;             // same array, written by the cap kernel
   float* part;               // [row tiles][m][kp] (at most one per 128-row chunk)
+  const float* lbv;          // [m][n] per-asset bounds, or null (the
+  const float* ubv;          //   account's scalars P_LB / P_UB)
   float* zs;                 // [m][n] w = v + alpha (Delta^-1 r - z) of the
                              // current iterate: CONTRACT writes it, PROJECT adds
                              // the back-projection; before a polish it holds
@@ -101,8 +103,8 @@ bool cap_resident_fits(int n, int max_held);
 hipError_t launch_cap(const IterArgs& A, int m_total, bool resident, hipStream_t st);
 hipError_t launch_materialize_z(const IterArgs& A, int m_total, float* z, hipStream_t st);
 hipError_t launch_ksolve(const KArgs& A, int m_total, hipStream_t st);
-hipError_t launch_build_bt(int n, int k, int G, int kp, const float* B, const int32_t* group,
-                           float* Bt, hipStream_t st);
+hipError_t launch_build_bt(int n, int k, int G, int H, int kp, const float* B,
+                           const int32_t* group, const float* half, float* Bt, hipStream_t st);
 hipError_t launch_gram(int n, int kp, int kg, int nparts, int rows_per_blk, const float* Bt,
                        const float* d, double gamma, double rho, double* part, hipStream_t st);
 hipError_t launch_kfactor(int k, int G, int kp, int nparts, const double* part, const float* f,
@@ -111,7 +113,11 @@ hipError_t launch_kfactor(int k, int G, int kp, int nparts, const double* part, 
 
 // ---- packing / validation -------------------------------------------------
 struct PackArgs {
-  int n, W, m, G;
+  int n, W, m, G;            // G: constraint rows (bands, then halfspaces)
+  int Gl;                    // band rows (finite bounds required)
+  const float* lbv;          // [m][n] per-asset bounds or null
+  const float* ubv;
+  const float* eta;          // [m] or null
   const float* mu;
   const float* w0;
   const float* lb;
@@ -146,7 +152,14 @@ hipError_t launch_pack_rec(const PackArgs& A, float4* rec, int total, hipStream_
 constexpr int kPStateStride = 16;
 
 struct PolishArgs {
-  int n, k, G, kp, W, m_total;
+  int n, k, G, kp, W, m_total;  // G: constraint rows, bands then halfspaces
+  int Gl;                    // band rows, one-hot by label; rows Gl..G-1 are
+                             // the halfspace columns k + Gl.. of B~
+  const float* lbv;          // [m][n] per-asset bounds or null
+  const float* ubv;
+  const double* obj_const;   // [m] (gamma/2) w_b^T Sigma w_b, or null
+  const double* mu64;        // [m][n] mu' = eta mu + gamma Sigma w_b in float64
+                             // (with a benchmark or eta; mu holds it in float32)
   const int* m_act;
   const int* act;
   const float* Bt;           // [n][kp] (first k columns = B)
@@ -193,7 +206,11 @@ int polish_row_blocks(int n);
 
 // ---- KKT adjoint (float64) ---------------------------------------------------
 struct AdjArgs {
-  int n, k, G, kp, m;
+  int n, k, G, kp, m;        // G: constraint rows (as PolishArgs)
+  int Gl;
+  const float* wb;           // [m][n] benchmark weights or null
+  const float* eta;          // [m] return scale or null
+  const double* ywb;         // [m][k] B^T w_b (with wb)
   const float* Bt;
   const float* f;
   const float* d;
@@ -213,5 +230,50 @@ struct AdjArgs {
   size_t wk_stride;
 };
 hipError_t launch_adjoint(const AdjArgs& A, hipStream_t st);
+
+// ---- the rest of Eq. 1 -------------------------------------------------------
+// box of (account a, asset i) of an eligible asset: the per-asset bounds
+// when the book has them, else the account's scalars (excluded: [0, 0])
+template <typename Args>
+__device__ __forceinline__ void asset_box(const Args& A, size_t off, bool el, float lbp,
+                                          float ubp, float& lb, float& ub) {
+  if (!el) { lb = 0.f; ub = 0.f; return; }
+  lb = A.lbv ? A.lbv[off] : lbp;
+  ub = A.ubv ? A.ubv[off] : ubp;
+}
+
+// the linear term of the polish and certificate: mu' in float64 when the
+// book has a benchmark term, else the caller's mu
+__device__ __forceinline__ double mu_at(const PolishArgs& A, size_t off) {
+  return A.mu64 ? A.mu64[off] : (double)A.mu[off];
+}
+
+// coefficient of constraint row g at asset i: band rows (g < Gl) are
+// one-hot by label, halfspace rows are the columns k + g of B~
+template <typename Args>
+__device__ __forceinline__ double row_coef(const Args& A, int i, int g) {
+  return g < A.Gl ? (A.group[i] == g ? 1.0 : 0.0) : (double)A.Bt[(size_t)i * A.kp + A.k + g];
+}
+
+// sum_g (row g at asset i) x[g] over every constraint row
+template <typename Args>
+__device__ __forceinline__ double rows_dot(const Args& A, int i, const double* x) {
+  double s = A.Gl ? x[A.group[i]] : 0.0;
+  for (int g = A.Gl; g < A.G; ++g) s += (double)A.Bt[(size_t)i * A.kp + A.k + g] * x[g];
+  return s;
+}
+
+// mu' = eta mu + gamma Sigma w_b and (gamma/2) w_b^T Sigma w_b per account
+// (the benchmark term of Eq. 1 expanded)
+hipError_t launch_benchmark_prep(int m, int n, int k, const float* B, const float* f,
+                                 const float* d, const float* mu, const float* wb,
+                                 const float* eta, const float* gamma, double* ywb,
+                                 double* part, float* mu_out, double* mu64_out,
+                                 double* obj_const, hipStream_t st);
+int benchmark_row_blocks(int n);
+// the band bounds then the halfspace bounds, [m][G + H]
+hipError_t launch_concat_rows(int m, int G, int H, const float* blo, const float* bhi,
+                              const float* hlo, const float* hhi, float* lo, float* hi,
+                              hipStream_t st);
 
 }  // namespace fqp

@@ -64,14 +64,18 @@ struct RowData {
   bool el;
   bool taxed;
   float w0;
+  float lb, ub;      // box of the asset ([0, 0] when excluded)
   float b1, b2, b3, s0, s1, s2, s3;
 };
 
-__device__ __forceinline__ RowData row_data(const PolishArgs& A, int a, int i) {
+// lbf / ubf: the account's scalar bounds (used without per-asset bounds)
+__device__ __forceinline__ RowData row_data(const PolishArgs& A, int a, int i, float lbf,
+                                            float ubf) {
   RowData r;
   const int wd = i >> 5, b = i & 31;
   const size_t wi = (size_t)a * A.W + wd;
   r.el = A.elig == nullptr || ((A.elig[wi] >> b) & 1u);
+  asset_box(A, (size_t)a * A.n + i, r.el, lbf, ubf, r.lb, r.ub);
   const uint32_t hw = A.hold[wi];
   r.w0 = 0.f;
   r.taxed = false;
@@ -87,10 +91,9 @@ __device__ __forceinline__ RowData row_data(const PolishArgs& A, int a, int i) {
   return r;
 }
 
-__device__ void make_geom(Geom& g, float lbf, float ubf, float kap, bool phi, const RowData& r) {
-  const bool el = r.el;
+__device__ void make_geom(Geom& g, float kap, bool phi, const RowData& r) {
   const float w0f = r.w0;
-  const double lb = el ? (double)lbf : 0.0, ub = el ? (double)ubf : 0.0;
+  const double lb = r.lb, ub = r.ub;
   g.w0 = w0f;
   g.nk = 0;
   float kf[4];
@@ -118,10 +121,10 @@ __device__ void make_geom(Geom& g, float lbf, float ubf, float kap, bool phi, co
     g.ks[0] = 0.0;
   }
   g.np = 0;
-  g.pt[g.np] = lb; g.ptf[g.np] = el ? lbf : 0.f; ++g.np;
+  g.pt[g.np] = lb; g.ptf[g.np] = r.lb; ++g.np;
   for (int j = 0; j < g.nk; ++j)
     if (g.kink[j] > lb && g.kink[j] < ub) { g.pt[g.np] = g.kink[j]; g.ptf[g.np] = kf[j]; ++g.np; }
-  if (ub > lb) { g.pt[g.np] = ub; g.ptf[g.np] = el ? ubf : 0.f; ++g.np; }
+  if (ub > lb) { g.pt[g.np] = ub; g.ptf[g.np] = r.ub; ++g.np; }
 }
 
 // slope of the trade cost (without cap) on the piece between points q, q+1
@@ -230,7 +233,8 @@ __device__ T bmax(T v, T* sh) {
 
 // Sums over a list of rows (LDS-staged, 64 rows at a time):
 //   ys[j] += sum_t B[i_t][j] w[i_t]   (thread j < k)
-//   gs[g] += sum_t [group(i_t) == g] w[i_t]   (thread g < G)
+//   gs[g] += sum_t (row g at i_t) w[i_t]   (thread g < G: band rows by
+//            label, halfspace rows from the columns k + g of B~)
 // Entries are list[t] (rev = 0) or list[n - 1 - t] (rev = 1), t < cnt.
 __device__ void list_sums(const PolishArgs& A, const int32_t* list, int n, int cnt, int rev,
                           const double* w, float* sB, double* sw, int* si, double& ys,
@@ -252,8 +256,11 @@ __device__ void list_sums(const PolishArgs& A, const int32_t* list, int n, int c
     __syncthreads();
     if (tid < k)
       for (int rr = 0; rr < rows; ++rr) ys += (double)sB[rr * (k + 1) + tid] * sw[rr];
-    if (tid < G)
+    if (tid < A.Gl)
       for (int rr = 0; rr < rows; ++rr) gs += (A.group[si[rr]] == tid) ? sw[rr] : 0.0;
+    else if (tid < G)             // halfspace rows: the columns k + tid of B~
+      for (int rr = 0; rr < rows; ++rr)
+        gs += (double)A.Bt[(size_t)si[rr] * A.kp + k + tid] * sw[rr];
   }
   __syncthreads();
 }
@@ -330,8 +337,8 @@ __global__ __launch_bounds__(kPT) void polish_solve_kernel(PolishArgs A) {
         RowData r;
         bool have = false;
         if (A.first_round) {
-          r = row_data(A, a, i);
-          make_geom(g, lbf, ubf, kap, phi, r);
+          r = row_data(A, a, i, lbf, ubf);
+          make_geom(g, kap, phi, r);
           have = true;
           const float z = A.z[(size_t)a * n + i];
           c = -1;
@@ -354,8 +361,8 @@ __global__ __launch_bounds__(kPT) void polish_solve_kernel(PolishArgs A) {
           w[i] = 0.0;
         } else {
           if (!have) {
-            r = row_data(A, a, i);
-            make_geom(g, lbf, ubf, kap, phi, r);
+            r = row_data(A, a, i, lbf, ubf);
+            make_geom(g, kap, phi, r);
           }
           const double v = g.pt[c >> 1];
           w[i] = v;
@@ -527,9 +534,9 @@ __global__ __launch_bounds__(kPT) void polish_solve_kernel(PolishArgs A) {
       if (tid < rows) {
         const int rr = tid;
         const int i = flist[f0 + rr];
-        RowData r = row_data(A, a, i);
+        RowData r = row_data(A, a, i, lbf, ubf);
         Geom g;
-        make_geom(g, lbf, ubf, kap, phi, r);
+        make_geom(g, kap, phi, r);
         double slope, sgn;
         piece_slope(g, code[i] >> 1, slope, sgn);
         double* x = stg + rr * CS;
@@ -540,10 +547,10 @@ __global__ __launch_bounds__(kPT) void polish_solve_kernel(PolishArgs A) {
         int col = 1;
         for (int gg = 0; gg < G; ++gg) {
           if (!band_active(ps, gg)) continue;
-          v[col++] = (A.group[i] == gg) ? 1.0 : 0.0;
+          v[col++] = row_coef(A, i, gg);
         }
         if (cap_on) v[col++] = sgn;
-        v[col] = (double)A.mu[(size_t)a * n + i] - slope - gam * cross;
+        v[col] = mu_at(A, (size_t)a * n + i) - slope - gam * cross;
         x[4 * xt] = 1.0 / (double)A.d[i];
         sgn_w0 += sgn * (double)r.w0;
       }
@@ -712,9 +719,9 @@ __global__ __launch_bounds__(kPT) void polish_solve_kernel(PolishArgs A) {
   // ---- free rows: w_i = (rhs_i - C_i^T eta - b_i . sol) / (gamma d_i) ----
   for (int t = tid; t < nF; t += kPT) {
     const int i = flist[t];
-    RowData r = row_data(A, a, i);
+    RowData r = row_data(A, a, i, lbf, ubf);
     Geom g;
-    make_geom(g, lbf, ubf, kap, phi, r);
+    make_geom(g, kap, phi, r);
     double slope, sgn;
     piece_slope(g, code[i] >> 1, slope, sgn);
     double cross = 0.0, bs = 0.0;
@@ -723,12 +730,12 @@ __global__ __launch_bounds__(kPT) void polish_solve_kernel(PolishArgs A) {
       cross += b * wk.Fy[j];
       bs += b * wk.sol[j];
     }
-    const double rhs = (double)A.mu[(size_t)a * n + i] - slope - gam * cross;
+    const double rhs = mu_at(A, (size_t)a * n + i) - slope - gam * cross;
     double ct = wk.eta[0];
     int col = 1;
     for (int gg = 0; gg < G; ++gg) {
       if (!band_active(ps, gg)) continue;
-      if (A.group[i] == gg) ct += wk.eta[col];
+      ct += row_coef(A, i, gg) * wk.eta[col];
       ++col;
     }
     if (cap_on) ct += sgn * wk.eta[col];
@@ -827,12 +834,12 @@ __global__ __launch_bounds__(256) void polish_gbase_kernel(PolishArgs A, int fin
     if (row_ok) {
       const double wi = A.wout[(size_t)a * n + i];
       const double sg = sig[q] + di * wi;
-      const double mui = A.mu[(size_t)a * n + i];
+      const double mui = mu_at(A, (size_t)a * n + i);
       const double v = s_gam[q] * sg - mui;
       A.gbase[(size_t)a * n + i] = v;
       gmax = fabs(s_gam[q] * sg);
       mumax = fabs(mui);
-      turn = fabs(wi - (double)row_data(A, a, i).w0);
+      turn = fabs(wi - (double)row_data(A, a, i, 0.f, 0.f).w0);
       if (!isfinite(v) || !isfinite(wi)) bad = 1.0;
     }
 #pragma unroll
@@ -941,19 +948,19 @@ __global__ __launch_bounds__(kPTC) void polish_check_kernel(PolishArgs A, fqp_re
         for (int i = tid; i < n; i += kPTC) {
           const int c = code_r[i];
           if (c & 1) continue;
-          RowData r = row_data(A, a, i);
+          RowData r = row_data(A, a, i, lbf, ubf);
           if (!r.el) continue;
           Geom g;
-          make_geom(g, lbf, ubf, kap, phi, r);
-          const double lb = lbf, ub = ubf;
+          make_geom(g, kap, phi, r);
+          const double lb = r.lb, ub = r.ub;
           double nb = 0.0, lg = 0.0;
           if (G) {
-            const int gg = A.group[i];
-            lg = mult[2 + gg];
-            if (band_active(ps, gg)) {
-              int col = 1;
-              for (int h2 = 0; h2 < gg; ++h2) col += band_active(ps, h2) ? 1 : 0;
-              nb = nv[col];
+            lg = rows_dot(A, i, mult + 2);
+            int col = 1;
+            for (int g2 = 0; g2 < G; ++g2) {
+              if (!band_active(ps, g2)) continue;
+              nb += row_coef(A, i, g2) * nv[col];
+              ++col;
             }
           }
           const double T = -(gb[i] - mult[0] + lg);
@@ -1059,15 +1066,15 @@ __global__ __launch_bounds__(kPTC) void polish_check_kernel(PolishArgs A, fqp_re
 
   double sw = 0.0, turn = 0.0, dmax = 0.0, box = 0.0, snapm = 0.0, obj = 0.0;
   for (int i = tid; i < n; i += kPTC) {
-    RowData r = row_data(A, a, i);
+    RowData r = row_data(A, a, i, lbf, ubf);
     Geom g;
-    make_geom(g, lbf, ubf, kap, phi, r);
-    const double lb = r.el ? (double)lbf : 0.0, ub = r.el ? (double)ubf : 0.0;
+    make_geom(g, kap, phi, r);
+    const double lb = r.lb, ub = r.ub;
     const double wi = w[i];
-    const double mui = A.mu[(size_t)a * n + i];
+    const double mui = mu_at(A, (size_t)a * n + i);
     const double sig = (gb[i] + mui) / gam;
     double gi = gb[i] - nu;
-    if (G) gi += mult[2 + A.group[i]];
+    if (G) gi += rows_dot(A, i, mult + 2);
     double lo, hi, snap;
     subdiff(g, wi, lam, lb, ub, lo, hi, snap);
     const double t = -gi;
@@ -1118,30 +1125,41 @@ __global__ __launch_bounds__(kPTC) void polish_check_kernel(PolishArgs A, fqp_re
   snapm = bmax<double>(snapm, shd);
 
   if (tid == 0) {
-    double rexp = 0.0, comp = 0.0;
+    // comp: the largest |multiplier| x slack; gap: their sum, the duality
+    // gap the multipliers leave (with stationarity and feasibility exact,
+    // f(w) - f* <= gap)
+    double rexp = 0.0, comp = 0.0, gap = 0.0;
     for (int g = 0; g < G; ++g) {
       const double lo = A.blo[(size_t)a * G + g], hi = A.bhi[(size_t)a * G + g];
       rexp = fmax(rexp, fmax(lo - s_gs[g], s_gs[g] - hi));
       const double lg = mult[2 + g];
-      const double slack = (lg > 0.0) ? hi - s_gs[g] : s_gs[g] - lo;
-      comp = fmax(comp, fabs(lg) * fabs(slack));
+      if (lg != 0.0) {              // (a one-sided row's other slack is infinite)
+        const double slack = (lg > 0.0) ? hi - s_gs[g] : s_gs[g] - lo;
+        comp = fmax(comp, fabs(lg) * fabs(slack));
+        gap += fabs(lg) * fabs(slack);
+      }
     }
     const double tau = tauf;
     double rturn = 0.0;
     if (isfinite(tauf)) {
       rturn = fmax(turn - tau, 0.0);
       comp = fmax(comp, fmax(lam, 0.0) * fabs(tau - turn));
+      gap += fmax(lam, 0.0) * fabs(tau - turn);
     } else {
       comp = fmax(comp, fabs(lam));
     }
+    const double obj_full = obj + (A.obj_const ? A.obj_const[a] : 0.0);
     const double r_prim = fmax(fmax(fabs(sw - 1.0), fmax(box, 0.0)), fmax(rexp, rturn)) + snapm;
     const double r_dual = fmax(dmax, fmax(-lam, 0.0)) / scale;
     const double r_comp = comp / scale;
     const bool finite = !s_bad && isfinite(sw) && isfinite(obj) && isfinite(nu) &&
                         isfinite(lam) && isfinite(r_prim) && isfinite(r_dual) &&
                         isfinite(r_comp);
+    // the certificate also bounds the relative objective error: the gap
+    // against |f| (when |f| is below the gradient scale, as a benchmark term
+    // can make it, r_comp <= eps alone does not)
     const bool ok = finite && r_prim <= A.eps_prim && r_dual <= A.eps_dual &&
-                    r_comp <= A.eps_comp;
+                    r_comp <= A.eps_comp && gap <= A.eps_comp * fmax(fabs(obj_full), 1e-12);
     for (int q = 0; q < 2 + G; ++q) gmult[q] = mult[q];
     ps[PS_ROUNDS] += 1;
     // keep the diagnostics of the latest pattern in the result arrays
@@ -1149,7 +1167,8 @@ __global__ __launch_bounds__(kPTC) void polish_check_kernel(PolishArgs A, fqp_re
       if (R.r_prim) R.r_prim[a] = r_prim;
       if (R.r_dual) R.r_dual[a] = r_dual;
       if (R.r_comp) R.r_comp[a] = r_comp;
-      if (R.obj) R.obj[a] = obj;
+      // (the benchmark's constant (gamma/2) w_b^T Sigma w_b completes Eq. 1)
+      if (R.obj) R.obj[a] = obj_full;
       if (R.nu) R.nu[a] = nu;
       if (R.lam_cap) R.lam_cap[a] = lam;
     }

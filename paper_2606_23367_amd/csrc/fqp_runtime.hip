@@ -435,8 +435,14 @@ extern "C" fqp_error fqp_solve_batch(fqp_handle* h, const fqp_universe* U, const
   if (S_in) S = *S_in; else fqp_default_settings(&S);
   h->fail_at = S.debug_fail_alloc;
   h->requests = 0;
-  const int n = U->n, k = U->k, G = U->n_groups, m = P->m;
-  if (n < 1 || k < 1 || m < 1 || G < 0) { h->err = "non-positive size"; return FQP_ERR_INVALID_ARG; }
+  // constraint rows with two-sided bounds: the Gl one-hot band rows, then
+  // the H policy halfspace rows; both join the factor block B~
+  const int n = U->n, k = U->k, Gl = U->n_groups, H = U->n_half, m = P->m;
+  const int G = Gl + H;
+  if (n < 1 || k < 1 || m < 1 || Gl < 0 || H < 0) {
+    h->err = "non-positive size";
+    return FQP_ERR_INVALID_ARG;
+  }
   // a caller's state block, or the state the handle kept from its last
   // solve of the same shape; a solve that fails part-way leaves no state
   const bool warm_kept = S.warm_start && h->warm_ok && h->warm_m == m && h->warm_n == n &&
@@ -449,8 +455,16 @@ extern "C" fqp_error fqp_solve_batch(fqp_handle* h, const fqp_universe* U, const
     h->err = "required pointer is null";
     return FQP_ERR_INVALID_ARG;
   }
-  if (G > 0 && (!U->group || !P->band_lo || !P->band_hi)) {
+  if (Gl > 0 && (!U->group || !P->band_lo || !P->band_hi)) {
     h->err = "n_groups > 0 needs group labels and band bounds";
+    return FQP_ERR_INVALID_ARG;
+  }
+  if (H > 0 && (!U->half || !P->half_lo || !P->half_hi)) {
+    h->err = "n_half > 0 needs the halfspace rows and their bounds";
+    return FQP_ERR_INVALID_ARG;
+  }
+  if ((P->lb_asset == nullptr) != (P->ub_asset == nullptr)) {
+    h->err = "per-asset bounds need both lb_asset and ub_asset";
     return FQP_ERR_INVALID_ARG;
   }
   if (P->tax_ptr && (!P->tax_asset || !P->tax_brk || !P->tax_slope)) {
@@ -470,7 +484,7 @@ extern "C" fqp_error fqp_solve_batch(fqp_handle* h, const fqp_universe* U, const
     return FQP_ERR_UNSUPPORTED;
   }
   if (k > kMaxK || G > kMaxG || kp > kMaxKp) {
-    h->err = "factor count / group count beyond the library limits";
+    h->err = "factor count / constraint rows (n_groups + n_half) beyond the library limits";
     return FQP_ERR_UNSUPPORTED;
   }
   {
@@ -579,6 +593,22 @@ extern "C" fqp_error fqp_solve_batch(fqp_handle* h, const fqp_universe* U, const
   WS(pcount, int32_t, "pcount", 2);
   const int n_rb = polish_row_blocks(n);
   WS(gpart_p, double, "polish_gpart", (size_t)m * n_rb * 4);
+  // the rest of Eq. 1: bounds of every constraint row [m][G] (bands, then
+  // halfspaces); mu' = eta mu + gamma Sigma w_b and the constant of the
+  // benchmark term when the book has a benchmark or a return scale
+  const bool concat_rows = Gl > 0 && H > 0;
+  WS(rlo_ws, float, "row_lo", concat_rows ? (size_t)m * G : 1);
+  WS(rhi_ws, float, "row_hi", concat_rows ? (size_t)m * G : 1);
+  const float* rlo = concat_rows ? rlo_ws : (Gl ? P->band_lo : (H ? P->half_lo : nullptr));
+  const float* rhi = concat_rows ? rhi_ws : (Gl ? P->band_hi : (H ? P->half_hi : nullptr));
+  const bool bench = P->wb != nullptr || P->eta != nullptr;
+  const int nbb = benchmark_row_blocks(n);
+  WS(mu_b, float, "mu_eff", bench ? (size_t)m * n : 1);
+  WS(mu_b64, double, "mu_eff64", bench ? (size_t)m * n : 1);
+  WS(obj_c, double, "obj_const", bench ? (size_t)m : 1);
+  WS(ywb, double, "ywb", P->wb ? (size_t)m * k : 1);
+  WS(bpart, double, "bench_part", P->wb ? (size_t)m * nbb * (k + 1) : (size_t)m * nbb);
+  const float* mu_use = bench ? mu_b : P->mu;
 
   // iteration geometry, per pass: (row tiles x account tiles) workgroups, as
   // many as the compute units hold at once (one round: a partial second
@@ -612,7 +642,13 @@ extern "C" fqp_error fqp_solve_batch(fqp_handle* h, const fqp_universe* U, const
   WS(btt_lo, uint16_t, "btt_lo", nbf);
 
   // ---- universe ------------------------------------------------------------
-  HIP_CHECK(launch_build_bt(n, k, G, kp, U->B, U->group, Bt, st));
+  HIP_CHECK(launch_build_bt(n, k, Gl, H, kp, U->B, U->group, U->half, Bt, st));
+  if (concat_rows)
+    HIP_CHECK(launch_concat_rows(m, Gl, H, P->band_lo, P->band_hi, P->half_lo, P->half_hi,
+                                 rlo_ws, rhi_ws, st));
+  if (bench)
+    HIP_CHECK(launch_benchmark_prep(m, n, k, U->B, U->f, U->d, P->mu, P->wb, P->eta, P->gamma,
+                                    ywb, bpart, mu_b, mu_b64, obj_c, st));
   if (split) HIP_CHECK(launch_split_bt(n, npad, kp, Bt, bt_hi, bt_lo, btt_hi, btt_lo, st));
   HIP_CHECK(hipMemcpyAsync(rho_d, rho_cls.data(), sizeof(float) * ncls, hipMemcpyHostToDevice, st));
   HIP_CHECK(hipMemcpyAsync(cls_d, cls_h.data(), sizeof(int) * m, hipMemcpyHostToDevice, st));
@@ -626,10 +662,11 @@ extern "C" fqp_error fqp_solve_batch(fqp_handle* h, const fqp_universe* U, const
 
   // ---- book: validation and held records (workspace only) ----------------
   PackArgs pk{};
-  pk.n = n; pk.W = W; pk.m = m; pk.G = G;
-  pk.mu = P->mu; pk.w0 = P->w0; pk.lb = P->lb; pk.ub = P->ub; pk.elig = P->eligible;
+  pk.n = n; pk.W = W; pk.m = m; pk.G = G; pk.Gl = Gl;
+  pk.lbv = P->lb_asset; pk.ubv = P->ub_asset; pk.eta = P->eta;
+  pk.mu = mu_use; pk.w0 = P->w0; pk.lb = P->lb; pk.ub = P->ub; pk.elig = P->eligible;
   pk.gamma = P->gamma; pk.kappa = P->kappa; pk.tau = P->tau;
-  pk.blo = G ? P->band_lo : nullptr; pk.bhi = G ? P->band_hi : nullptr;
+  pk.blo = rlo; pk.bhi = rhi;
   pk.tax_ptr = P->tax_ptr; pk.tax_asset = P->tax_asset; pk.tax_brk = P->tax_brk;
   pk.tax_slope = P->tax_slope;
   pk.hold = hold; pk.hold_pre = hold_pre; pk.hold_cnt = hold_cnt; pk.hold_ptr = hold_ptr;
@@ -654,7 +691,7 @@ extern "C" fqp_error fqp_solve_batch(fqp_handle* h, const fqp_universe* U, const
     }
     n_held = hp_h[m];
   }
-  const bool cap_resident = cap_resident_fits(n, max_held);
+  const bool cap_resident = cap_resident_fits(n, max_held) && P->lb_asset == nullptr;
   WS(hold_rec, float4, "hold_rec", 2 * (size_t)std::max(n_held, 1));
   HIP_CHECK(launch_pack_rec(pk, hold_rec, n_held, st));
   h->stats.workspace_bytes = h->total_bytes;
@@ -667,7 +704,7 @@ extern "C" fqp_error fqp_solve_batch(fqp_handle* h, const fqp_universe* U, const
   const float* ws_l = warm_given ? ws_vb + (size_t)m * G : nullptr;
   hipLaunchKernelGGL(init_accounts_kernel, dim3((m + 255) / 256), dim3(256), 0, st, m, G, cls_d,
                      rho_d, P->gamma, P->kappa, P->lb, P->ub, P->tau, P->tax_ptr, S.alpha, rho_b,
-                     par, zb, vb, P->band_lo, P->band_hi, iters, pstate, kPStateStride,
+                     par, zb, vb, rlo, rhi, iters, pstate, kPStateStride,
                      warm ? 1 : 0, G ? ws_z : nullptr, G ? ws_vb : nullptr, ws_l, st_in,
                      R->status);
   HIP_CHECK(hipGetLastError());
@@ -685,7 +722,8 @@ extern "C" fqp_error fqp_solve_batch(fqp_handle* h, const fqp_universe* U, const
   IterArgs ia;
   std::memset(&ia, 0, sizeof(ia));       // byte-comparable (graph key)
   ia.n = n; ia.W = W;
-  ia.m_total = m; ia.m_act = m_act; ia.act = act; ia.Bt = Bt; ia.d = U->d; ia.mu = P->mu;
+  ia.m_total = m; ia.m_act = m_act; ia.act = act; ia.Bt = Bt; ia.d = U->d; ia.mu = mu_use;
+  ia.lbv = P->lb_asset; ia.ubv = P->ub_asset;
   ia.v = v; ia.elig = P->eligible; ia.hold = hold; ia.hold_pre = hold_pre;
   ia.hold_ptr = hold_ptr; ia.hold_w0 = hold_w0; ia.hold_tax = hold_tax;
   ia.tax_brk = P->tax_brk; ia.tax_slope = P->tax_slope; ia.pp = pp; ia.par = par;
@@ -700,15 +738,18 @@ extern "C" fqp_error fqp_solve_batch(fqp_handle* h, const fqp_universe* U, const
   ka.m_act = m_act; ka.act = act;
   ka.part = part; ka.par = par; ka.pp = pp; ka.Kinv = Kinv; ka.cvec = cvec;
   ka.qvec = qvec; ka.sig1 = sig1; ka.mbg = mbg; ka.zb = zb; ka.vb = vb;
-  ka.blo = G ? P->band_lo : nullptr; ka.bhi = G ? P->band_hi : nullptr;
+  ka.blo = rlo; ka.bhi = rhi;
   ka.iters = iters;
   PolishArgs pa{};
-  pa.n = n; pa.k = k; pa.G = G; pa.kp = kp; pa.W = W; pa.m_total = m; pa.m_act = m_act;
-  pa.act = act; pa.Bt = Bt; pa.f = U->f; pa.d = U->d; pa.group = G ? U->group : nullptr;
-  pa.mu = P->mu; pa.z = z; pa.elig = P->eligible; pa.hold = hold; pa.hold_pre = hold_pre;
+  pa.n = n; pa.k = k; pa.G = G; pa.Gl = Gl; pa.kp = kp; pa.W = W; pa.m_total = m;
+  pa.m_act = m_act;
+  pa.act = act; pa.Bt = Bt; pa.f = U->f; pa.d = U->d; pa.group = Gl ? U->group : nullptr;
+  pa.lbv = P->lb_asset; pa.ubv = P->ub_asset; pa.obj_const = bench ? obj_c : nullptr;
+  pa.mu64 = bench ? mu_b64 : nullptr;
+  pa.mu = mu_use; pa.z = z; pa.elig = P->eligible; pa.hold = hold; pa.hold_pre = hold_pre;
   pa.hold_ptr = hold_ptr; pa.hold_w0 = hold_w0; pa.hold_tax = hold_tax;
   pa.tax_brk = P->tax_brk; pa.tax_slope = P->tax_slope; pa.par = par; pa.zb = zb; pa.vb = vb;
-  pa.blo = G ? P->band_lo : nullptr; pa.bhi = G ? P->band_hi : nullptr;
+  pa.blo = rlo; pa.bhi = rhi;
   pa.code = code; pa.code_next = code_next; pa.flist = flist; pa.wk = wk; pa.wk_stride = wks; pa.wout = R->w;
   pa.mult = mult; pa.pstate = pstate; pa.gbase = gbase; pa.pcount = pcount;
   pa.n_rb = n_rb; pa.gpart = gpart_p;
@@ -898,8 +939,9 @@ extern "C" fqp_error fqp_solve_batch(fqp_handle* h, const fqp_universe* U, const
   {
     AdjArgs& L = h->last;
     L = AdjArgs{};
-    L.n = n; L.k = k; L.G = G; L.kp = kp; L.m = m;
-    L.Bt = Bt; L.f = U->f; L.d = U->d; L.group = G ? U->group : nullptr; L.w0in = P->w0;
+    L.n = n; L.k = k; L.G = G; L.Gl = Gl; L.kp = kp; L.m = m;
+    L.Bt = Bt; L.f = U->f; L.d = U->d; L.group = Gl ? U->group : nullptr; L.w0in = P->w0;
+    L.wb = P->wb; L.eta = P->eta; L.ywb = P->wb ? ywb : nullptr;
     L.par = par; L.status = R->status; L.pstate = pstate; L.flist = flist; L.code = code;
     L.w = R->w; L.wk = wk; L.wk_stride = wks;
     h->have_last = true;

@@ -53,6 +53,22 @@ class DeviceProblem:
     tax_asset: Optional[torch.Tensor]
     tax_brk: Optional[torch.Tensor]
     tax_slope: Optional[torch.Tensor]
+    # the rest of Eq. 1 (optional): halfspace rows [H, n] shared by the book
+    # with per-account bounds [m, H]; per-asset bounds [m, n]; benchmark
+    # weights [m, n] and return scale [m]
+    H: int = 0
+    half: Optional[torch.Tensor] = None
+    half_lo: Optional[torch.Tensor] = None
+    half_hi: Optional[torch.Tensor] = None
+    lb_asset: Optional[torch.Tensor] = None
+    ub_asset: Optional[torch.Tensor] = None
+    wb: Optional[torch.Tensor] = None
+    eta: Optional[torch.Tensor] = None
+
+    @property
+    def n_rows(self) -> int:
+        """constraint rows: bands, then halfspaces"""
+        return self.G + self.H
 
 
 def subset(P: DeviceProblem, idx) -> DeviceProblem:
@@ -76,7 +92,9 @@ def subset(P: DeviceProblem, idx) -> DeviceProblem:
         mu=rows(P.mu), w0=rows(P.w0), lb=rows(P.lb), ub=rows(P.ub),
         eligible=rows(P.eligible), gamma=rows(P.gamma), kappa=rows(P.kappa),
         tau=rows(P.tau), band_lo=rows(P.band_lo), band_hi=rows(P.band_hi),
-        tax_ptr=tax_ptr, tax_asset=tax_asset, tax_brk=tax_brk, tax_slope=tax_slope)
+        tax_ptr=tax_ptr, tax_asset=tax_asset, tax_brk=tax_brk, tax_slope=tax_slope,
+        H=P.H, half=P.half, half_lo=rows(P.half_lo), half_hi=rows(P.half_hi),
+        lb_asset=rows(P.lb_asset), ub_asset=rows(P.ub_asset), wb=rows(P.wb), eta=rows(P.eta))
 
 
 def to_device(uni, book, device="cuda:0") -> DeviceProblem:
@@ -92,6 +110,8 @@ def to_device(uni, book, device="cuda:0") -> DeviceProblem:
                                device=dev)
 
     G = uni.n_groups if book.band_lo is not None else 0
+    H = getattr(uni, "n_half", 0) if getattr(book, "half_lo", None) is not None else 0
+    opt = (lambda x: None if x is None else f32(x))
     elig = None
     if not book.eligible.all():
         elig = torch.as_tensor(pack_eligibility(book.eligible).view(np.int32),
@@ -110,6 +130,10 @@ def to_device(uni, book, device="cuda:0") -> DeviceProblem:
         tax_asset=i32(book.tax_asset) if has_tax else None,
         tax_brk=f32(book.tax_brk) if has_tax else None,
         tax_slope=f32(book.tax_slope) if has_tax else None,
+        H=H, half=f32(uni.half) if H else None,
+        half_lo=f32(book.half_lo) if H else None, half_hi=f32(book.half_hi) if H else None,
+        lb_asset=opt(getattr(book, "lb_asset", None)), ub_asset=opt(getattr(book, "ub_asset", None)),
+        wb=opt(getattr(book, "wb", None)), eta=opt(getattr(book, "eta", None)),
     )
 
 
@@ -157,7 +181,7 @@ class Solver:
         seeds a warm start when settings carry warm_start=1; ``want_state``
         adds that output ("state") for a later warm start."""
         dev = P.mu.device
-        m, n, G = P.m, P.n, P.G
+        m, n, G = P.m, P.n, P.n_rows
         nstate = _lib.state_floats(m, n, G)
         if warm_state is not None:
             if warm_state.dtype != torch.float32 or warm_state.numel() != nstate \
@@ -179,15 +203,18 @@ class Solver:
             )
         if want_state and "state" not in out:
             out["state"] = torch.empty(nstate, dtype=torch.float32, device=dev)
-        U = _lib.Universe(n=n, k=P.k, n_groups=G, B=_ptr(P.B), f=_ptr(P.f),
-                          d=_ptr(P.d), group=_ptr(P.group))
+        U = _lib.Universe(n=n, k=P.k, n_groups=P.G, B=_ptr(P.B), f=_ptr(P.f),
+                          d=_ptr(P.d), group=_ptr(P.group), n_half=P.H, half=_ptr(P.half))
         Bk = _lib.Book(m=m, mu=_ptr(P.mu), w0=_ptr(P.w0), lb=_ptr(P.lb),
                        ub=_ptr(P.ub), eligible=_ptr(P.eligible),
                        gamma=_ptr(P.gamma), kappa=_ptr(P.kappa),
                        tau=_ptr(P.tau), band_lo=_ptr(P.band_lo),
                        band_hi=_ptr(P.band_hi), tax_ptr=_ptr(P.tax_ptr),
                        tax_asset=_ptr(P.tax_asset), tax_brk=_ptr(P.tax_brk),
-                       tax_slope=_ptr(P.tax_slope), warm_state=_ptr(warm_state))
+                       tax_slope=_ptr(P.tax_slope), warm_state=_ptr(warm_state),
+                       lb_asset=_ptr(P.lb_asset), ub_asset=_ptr(P.ub_asset),
+                       half_lo=_ptr(P.half_lo), half_hi=_ptr(P.half_hi),
+                       wb=_ptr(P.wb), eta=_ptr(P.eta))
         R = _lib.Result(w=_ptr(out["w"]), status=_ptr(out["status"]),
                         iters=_ptr(out["iters"]), r_prim=_ptr(out["r_prim"]),
                         r_dual=_ptr(out["r_dual"]),

@@ -40,7 +40,9 @@ def shape_key(P: DeviceProblem, precision: int) -> str:
     lb = float(P.lb.min().item())
     gam = float(P.gamma.max().item())
     kap = float(P.kappa.max().item())
-    return (f"n{P.n}_k{P.k}_g{P.G}_tax{int(has_tax)}_cap{int(has_cap)}"
+    extra = "".join(tag for tag, x in (("_half", P.half_lo), ("_abox", P.lb_asset),
+                                       ("_wb", P.wb), ("_eta", P.eta)) if x is not None)
+    return (f"n{P.n}_k{P.k}_g{P.G}h{P.H}{extra}_tax{int(has_tax)}_cap{int(has_cap)}"
             f"_elig{int(P.eligible is not None)}_lb{lb:.3g}_ub{ub:.3g}_gam{gam:.3g}"
             f"_kap{kap:.3g}_p{precision}")
 

@@ -3,7 +3,7 @@ compare with the float64 oracle on the same seeded inputs."""
 import numpy as np
 
 import oracle
-from oracle.problem import account
+from oracle.problem import account, n_rows
 from oracle.kkt import residuals
 
 # Acceptance of the headline target (1e-6 relative objective, 1e-6 primal
@@ -40,7 +40,7 @@ def check_account(uni, book, a, host):
     assert max(orc["res"]["r_prim"], orc["res"]["r_dual"],
                orc["res"]["r_comp"]) <= 1e-11, orc["res"]
     w = host["w"][a]
-    lam_band = host["lam_band"][a] if P.n_groups else None
+    lam_band = host["lam_band"][a] if n_rows(P) else None
     r = residuals(P, w, host["nu"][a], lam_band, host["lam_cap"][a])
     relobj = abs(r["obj"] - orc["obj"]) / max(abs(orc["obj"]), 1e-300)
     info = dict(a=a, status=int(host["status"][a]), r_prim=r["r_prim"],
