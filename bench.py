@@ -5,18 +5,20 @@ an N = 10,000 universe, k = 80 factors, exclusion masks leaving 30-100 % of
 names eligible, 4-lot piecewise-linear tax on 100-400 held names, turnover
 cap): packing and validation, factor-space setup, ADMM iterations, float64
 polish and certification of every account.  Inputs are resident in HBM when
-the timed region starts.  value = accounts certified to 1e-6 KKT residuals
-per second.
+the timed region starts; the timed steps run the library's captured-graph
+path.  value = accounts certified to 1e-6 KKT residuals per second.
 
-The roofline object describes the PROJECT pass (the dominant iteration
-kernel): algorithmic bytes per launch / average launch duration, timed with
-HIP events on the library's stream inside the timed steps.
+The roofline object describes the iteration pass that takes the most time
+per solve (CONTRACT or PROJECT): algorithmic bytes per launch / average
+launch duration, both from one more (untimed) solve whose pass launches are
+timed with events that each dispatch stamps (hipExtLaunchKernelGGL) on the
+library's stream.
 
 plain_fp32 is the same book solved one account per call with float32
 contractions (the unbatched form), on a bounded sample of accounts.
 
 cpu_baseline times the float64 oracle on a bounded sample of the same book
-on the host cores.
+on the host cores, and states the GPU's error against it per account.
 """
 import argparse
 import json
@@ -37,31 +39,55 @@ TUNE_SEED, TUNE_SEEDS2, TUNE_SAMPLE = 1, (2, 3, 4), 500
 SETTINGS = dict(precision=1)
 
 
-def algorithmic_bytes(uni, book, iters, precision):
-    """Algorithmic bytes of the PROJECT pass (back-projection and the write
-    of the new ADMM state).  Per account-iteration: w = v + alpha (Delta^-1 r
-    - z) read (written by the CONTRACT pass) and the new state v written
-    (8 N).  Per launch: the k + G + 1 used columns of B~ once (bf16 hi and
-    lo: 4 B per entry; float32: 4 B) and d (4 N)."""
+def factor_width(uni):
+    """Used columns of the factor block B~ = [B | band rows | halfspace rows | 1]."""
+    return uni.k + uni.n_groups + getattr(uni, "n_half", 0) + 1
+
+
+def algorithmic_bytes(uni, book, iters, precision, kind="project"):
+    """Algorithmic bytes of one iteration pass over a solve, from the
+    per-account iteration counts: (sum over account-iterations, per launch).
+
+    PROJECT (back-projection and the write of the new ADMM state): per
+    account-iteration w = v + alpha (Delta^-1 r - z) read and v written (8 N);
+    per launch the used columns of B~ (bf16 hi and lo: 4 B per entry;
+    float32: 4 B) and d (4 N).
+
+    CONTRACT (prox, r, the contraction t = B~^T Delta^-1 r and w): per
+    account-iteration v and mu read, w written (12 N), the eligibility bits
+    (N / 8 when the book has exclusions) and one 28-byte tax record per held
+    name (the per-account-iteration bytes of the method's own model, with the
+    w stream in place of the second state stream); per launch the used
+    columns of B~ at 2 B per entry (the bf16 width of the method's model) and
+    d (4 N)."""
     import numpy as np
-    n, k = uni.n, uni.k
-    G = uni.n_groups
-    per_acc = np.full(book.m, 8.0 * n)
-    per_launch = 4.0 * n * (k + G + 1) + 4.0 * n
+    n = uni.n
+    kw = factor_width(uni)
+    if kind == "project":
+        per_acc = np.full(book.m, 8.0 * n)
+        per_launch = 4.0 * n * kw + 4.0 * n
+    else:
+        held = np.count_nonzero(book.w0, axis=1)
+        mask = 0.0 if book.eligible.all() else np.ceil(n / 8.0)
+        per_acc = 12.0 * n + mask + 28.0 * held
+        per_launch = 2.0 * n * kw + 4.0 * n
     return float(np.sum(iters * per_acc)), float(per_launch)
 
 
-TRAFFIC_NOTE = os.path.join(ROOT, "profiles", "project_pass_c3_500x10000_hbm_traffic.md")
+TRAFFIC_NOTES = {
+    "contract": os.path.join(ROOT, "profiles", "contract_pass_c3_500x10000_hbm_traffic.md"),
+    "project": os.path.join(ROOT, "profiles", "project_pass_c3_500x10000_hbm_traffic.md"),
+}
 KERNEL_SOURCES = ["paper_2606_23367_amd/csrc/fqp_iter.hip", "paper_2606_23367_amd/csrc/fqp_common.h",
                   "paper_2606_23367_amd/csrc/fqp_kernels.h"]
 
 
-def measured_traffic():
-    """HBM bytes per PROJECT launch from the committed counter summary, or
-    None when the kernel sources changed since the counters were taken."""
+def measured_traffic(kind):
+    """HBM bytes per launch of the pass from the committed counter summary,
+    or None when the kernel sources changed since the counters were taken."""
     import hashlib
     try:
-        txt = open(TRAFFIC_NOTE).read()
+        txt = open(TRAFFIC_NOTES[kind]).read()
     except OSError:
         return None
     vals = dict(line.split(": ", 1) for line in txt.splitlines()
@@ -75,27 +101,26 @@ def measured_traffic():
     return float(vals["traffic_bytes_per_launch"])
 
 
-def timed_solves(solver, P, steps, settings, contract=None):
-    """Run `steps` solves with per-launch events on the PROJECT pass (and on
-    the CONTRACT pass when `contract` is given: its kernel ms are added to
-    contract[0]); returns (seconds, certified, PROJECT kernel_ms, launches,
+def timed_solves(solver, P, steps, settings, profile=0):
+    """Run `steps` solves; profile=0 is the library's captured-graph path,
+    bit 0 / bit 1 time every PROJECT / CONTRACT launch with events (no
+    graph).  Returns (seconds, certified, PROJECT ms, CONTRACT ms, launches,
     iters per solve)."""
     import torch
     out = None
-    solved, kernel_ms, launches, iters = 0, 0.0, 0, []
+    solved, proj_ms, con_ms, launches, iters = 0, 0.0, 0.0, 0, []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
-        out = solver.solve(P, out=out, profile=1 if contract is None else 3, **settings)
+        out = solver.solve(P, out=out, profile=profile, **settings)
         st = solver.stats()
         iters.append(out["iters"].cpu().numpy())
         solved += int((out["status"] == 0).sum().item())
-        kernel_ms += st["iter_kernel_ms"]
-        if contract is not None:
-            contract[0] += st["contract_kernel_ms"]
+        proj_ms += st["iter_kernel_ms"]
+        con_ms += st["contract_kernel_ms"]
         launches += st["iter_launches"]
     torch.cuda.synchronize()
-    return time.perf_counter() - t0, solved, kernel_ms, launches, iters
+    return time.perf_counter() - t0, solved, proj_ms, con_ms, launches, iters
 
 
 def copy_bandwidth(nbytes=1 << 30, reps=5):
@@ -189,15 +214,18 @@ def warm_lane(solver, uni, book, settings, sd=1e-4):
     return res
 
 
-# constraint-burden bundles at N = 2,000 (64 accounts, k = 40), cumulative;
-# the factor-exposure bounds bundle (halfspace rows on B^T w) is not part of
-# the problem class built here
+# constraint-burden bundles at N = 2,000 (64 accounts, k = 40), cumulative:
+# every bundle keeps the previous one's data and adds one rule family (B3:
+# factor-exposure bounds, 5 halfspace rows on B^T w within 5e-3 of the
+# equal-weight exposure; B5 puts tax lots on B4's holdings)
+_B3 = dict(halfspaces=5, half_halfwidth=5e-3)
 BURDEN = (
     ("B0 budget, long-only, box", dict(kappa=0.0, groups=0, band_halfwidth=None)),
     ("B1 + turnover penalty", dict(kappa=1e-3, groups=0, band_halfwidth=None)),
     ("B2 + sector bands", dict(kappa=1e-3)),
-    ("B4 + account exclusions", dict(kappa=1e-3, elig=(0.3, 1.0))),
-    ("B5 + tax lots", dict(kappa=1e-3, elig=(0.3, 1.0), held=(100, 400), tax=True)),
+    ("B3 + factor-exposure bounds", dict(kappa=1e-3, **_B3)),
+    ("B4 + account exclusions", dict(kappa=1e-3, elig=(0.3, 1.0), **_B3)),
+    ("B5 + tax lots", dict(kappa=1e-3, elig=(0.3, 1.0), tax=True, **_B3)),
 )
 BURDEN_GRID = dict(rho=(0.3, 1.0, 3.0, 10.0), alpha=(1.8,), check_every=(25, 50))
 
@@ -270,6 +298,100 @@ def e7_lane(solver, steps=5):
             "data": "synthetic stand-in for the paper's 481-name real universe"}
 
 
+# E7-shaped variants: the L1 transition cost and the position cap of the
+# paper's small-universe scenarios (5e-3 and 1e-2; caps of 3 % and 1.2 %)
+E7_VARIANTS = ((5e-3, 0.03), (1e-2, 0.03), (5e-3, 0.012), (1e-2, 0.012))
+
+
+def e7_variants_lane(solver, cfg, steps=3):
+    """The e7 book (200 x 481) at every (transition cost, position cap) pair,
+    with the schedule the autotuner picked for the base variant; best of
+    `steps` solves each."""
+    import torch
+    from workloads import make_config
+    from paper_2606_23367_amd.solver import to_device
+    rows = []
+    for kappa, cap in E7_VARIANTS:
+        uni, book = make_config("e7", 0, kappa=kappa, ub=cap)
+        P = to_device(uni, book, "cuda:0")
+        solver.solve(P, **cfg)
+        best, solved = None, 0
+        for _ in range(steps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            out = solver.solve(P, **cfg)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            if best is None or dt < best:
+                best, solved = dt, int((out["status"] == 0).sum().item())
+        rows.append({"transition_cost": kappa, "position_cap": cap, "ms_per_book": best * 1e3,
+                     "accounts_per_s": solved / best, "certified": solved, "accounts": book.m})
+    return rows
+
+
+def c5_lane(solver, steps=2):
+    """Large universe: 8 accounts over N = 384,800 names, k = 100, 50 one-hot
+    groups with bands, 2,000 held names with 4-lot tax (the factor block is
+    151 columns wide, so the contractions run on float32 MFMA); best of
+    `steps` solves after a warm-up."""
+    import numpy as np
+    import torch
+    from workloads import make_config
+    from paper_2606_23367_amd.solver import to_device
+    uni, book = make_config("c5", 0)
+    P = to_device(uni, book, "cuda:0")
+    cfg = dict(rho=10.0)
+    solver.solve(P, **cfg)
+    best, solved, its = None, 0, None
+    for _ in range(steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = solver.solve(P, **cfg)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        if best is None or dt < best:
+            best, solved, its = dt, int((out["status"] == 0).sum().item()), out["iters"].cpu().numpy()
+    del P
+    return {"value": solved / best, "unit": "accounts/s", "ms_per_book": best * 1e3,
+            "accounts": book.m, "certified": solved, "assets": uni.n, "factors": uni.k,
+            "groups": uni.n_groups, "settings": cfg,
+            "iterations_max": int(its.max()), "precision": "float32 MFMA contractions "
+            "(factor block 151 columns)", "data": "synthetic"}
+
+
+def c4_grad_lane(solver, steps=3):
+    """Differentiation: 128 accounts over N = 5,000, k = 60, gamma = 1000 --
+    a forward solve plus the KKT-adjoint backward for dL/dmu and dL/dB of
+    L = sum_a c_a^T w_a; best of `steps` forward+backward passes."""
+    import numpy as np
+    import torch
+    from workloads import make_config
+    from paper_2606_23367_amd.solver import to_device
+    uni, book = make_config("c4", 0)
+    P = to_device(uni, book, "cuda:0")
+    C = torch.as_tensor(np.random.default_rng(7).normal(size=(book.m, uni.n)), device="cuda:0")
+    cfg = dict(rho=1.0)
+    solver.solve(P, **cfg)
+    solver.adjoint(C)
+    best_f = best_b = None
+    solved = 0
+    for _ in range(steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = solver.solve(P, **cfg)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        solver.adjoint(C)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        if best_f is None or (t2 - t0) < best_f + best_b:
+            best_f, best_b = t1 - t0, t2 - t1
+            solved = int((out["status"] == 0).sum().item())
+    return {"value": solved / (best_f + best_b), "unit": "accounts/s (forward + backward)",
+            "forward_ms": best_f * 1e3, "backward_ms": best_b * 1e3, "accounts": book.m,
+            "certified": solved, "assets": uni.n, "factors": uni.k, "data": "synthetic"}
+
+
 def plain_fp32(uni, book, n_sample):
     """The unbatched float32 form: one account per fqp_solve_batch call,
     float32 MFMA contractions, the first n_sample accounts."""
@@ -278,10 +400,10 @@ def plain_fp32(uni, book, n_sample):
     settings = dict(SETTINGS, precision=0)    # same schedule, float32 contractions
     solver = Solver(0)
     probs = [to_device(uni, subset_accounts(book, [a]), "cuda:0") for a in range(n_sample)]
-    timed_solves(solver, probs[0], 1, settings)                  # warm-up
+    timed_solves(solver, probs[0], 1, settings, profile=1)      # warm-up
     dt, solved, kms, launches, alg = 0.0, 0, 0.0, 0, 0.0
     for a, P in enumerate(probs):
-        t, s, km, la, it = timed_solves(solver, P, 1, settings)
+        t, s, km, _, la, it = timed_solves(solver, P, 1, settings, profile=1)
         dt += t; solved += s; kms += km; launches += la
         per_acc, per_launch = algorithmic_bytes(uni, subset_accounts(book, [a]), it[0], 0)
         alg += per_acc + per_launch * la
@@ -293,32 +415,60 @@ def plain_fp32(uni, book, n_sample):
                 avg_launch_us=kms * 1e3 / max(launches, 1))
 
 
-def cpu_baseline(uni, book, n_sample):
+def cpu_baseline(uni, book, n_sample, gpu_out=None):
     """Oracle (float64 IPM + crossover) on the first n_sample accounts, one
-    account per worker process, BLAS pinned to one thread per worker."""
+    account per worker process, BLAS pinned to one thread per worker; the
+    clock starts once every worker has built the book.  With the GPU's
+    output of the same book, the GPU's error against the oracle on each
+    sampled account: relative objective and the CPU checker's residuals of
+    the GPU weights."""
     import multiprocessing as mp
+    import numpy as np
     os.environ["OPENBLAS_NUM_THREADS"] = "1"
     os.environ["OMP_NUM_THREADS"] = "1"
     cores = min(len(os.sched_getaffinity(0)), 16, n_sample)
     ctx = mp.get_context("spawn")
-    t0 = time.perf_counter()
-    with ctx.Pool(cores, initializer=_pool_init) as pool:
-        res = pool.map(_oracle_one, [(WORKLOAD, a) for a in range(n_sample)])
-    dt = time.perf_counter() - t0
-    ok = sum(1 for r in res if r)
-    return dict(value=ok / dt, unit="accounts/s", cores=cores, kind="oracle",
+    ready = ctx.Barrier(cores + 1)          # every worker has built the book
+    with ctx.Pool(cores, initializer=_pool_init, initargs=(ready,)) as pool:
+        ready.wait(timeout=900)
+        t0 = time.perf_counter()
+        res = pool.map(_oracle_one, [(WORKLOAD, a) for a in range(n_sample)], chunksize=1)
+        dt = time.perf_counter() - t0
+    ok = sum(1 for r in res if r["certified"])
+    line = dict(value=ok / dt, unit="accounts/s", cores=cores, kind="oracle",
                 sample=f"first {n_sample} accounts of the 500-account book, "
-                       f"{ok} certified, wall {dt:.1f} s")
+                       f"{ok} certified, wall {dt:.1f} s after the workers built the book")
+    if gpu_out is not None:
+        from oracle.problem import account
+        from oracle.kkt import residuals
+        errs = []
+        for a, r in enumerate(res):
+            P = account(uni, book, a)
+            lam_band = gpu_out["lam_band"][a] if uni.n_groups else None
+            g = residuals(P, gpu_out["w"][a], gpu_out["nu"][a], lam_band, gpu_out["lam_cap"][a])
+            errs.append((abs(g["obj"] - r["obj"]) / abs(r["obj"]), g["r_prim"], g["r_dual"],
+                         g["r_comp"], float(np.max(np.abs(gpu_out["w"][a] - r["w"])))))
+        e = np.asarray(errs)
+        line["gpu_vs_oracle"] = {
+            "accounts": len(errs),
+            "rel_obj_max": float(e[:, 0].max()), "rel_obj_median": float(np.median(e[:, 0])),
+            "r_prim_max": float(e[:, 1].max()), "r_dual_max": float(e[:, 2].max()),
+            "r_comp_max": float(e[:, 3].max()), "weight_abs_err_max": float(e[:, 4].max()),
+            "note": "GPU float64-polished weights of the timed solve against the float64 oracle "
+                    "on the same accounts; residuals from the CPU checker",
+        }
+    return line
 
 
 _POOL = {}
 
 
-def _pool_init():
+def _pool_init(ready):
     os.environ["OPENBLAS_NUM_THREADS"] = "1"
     sys.path.insert(0, ROOT)
     from workloads import make_config
     _POOL["book"] = make_config(WORKLOAD, 0)
+    ready.wait(timeout=900)
 
 
 def _oracle_one(args):
@@ -328,7 +478,8 @@ def _oracle_one(args):
     uni, book = _POOL["book"]
     out = oracle.solve_account(account(uni, book, a))
     r = out["res"]
-    return max(r["r_prim"], r["r_dual"], r["r_comp"]) <= 1e-6
+    return {"certified": max(r["r_prim"], r["r_dual"], r["r_comp"]) <= 1e-6,
+            "obj": out["obj"], "w": out["w"]}
 
 
 def main():
@@ -389,17 +540,32 @@ def main():
     P = to_device(uni, book, "cuda:0")
     cold_ms = None
     if args.warmup:
-        t_cold, _, _, _, _ = timed_solves(solver, P, 1, SETTINGS)   # first call on this book
+        t_cold = timed_solves(solver, P, 1, SETTINGS)[0]     # first call on this book
         cold_ms = t_cold * 1e3
         if args.warmup > 1:
             timed_solves(solver, P, args.warmup - 1, SETTINGS)
-    dt, solved, kernel_ms, launches, iters = timed_solves(solver, P, args.steps, SETTINGS)
-    # matrix-core rates from one more (untimed) step with both passes timed
-    contract_ms = [0.0]
-    mf_project_ms, mf_iters = 0.0, []
-    if not args.no_lanes:
-        _, _, mf_project_ms, _, mf_iters = timed_solves(solver, P, 1, SETTINGS,
-                                                        contract=contract_ms)
+    # the timed steps: the library's captured-graph path
+    dt, solved, _, _, launches, iters = timed_solves(solver, P, args.steps, SETTINGS)
+    graph_reused = solver.stats()["graph_reused"]
+    gpu_out = None
+    if not args.no_cpu:
+        last = solver.solve(P, **SETTINGS)
+        torch.cuda.synchronize()
+        gpu_out = {key: v.cpu().numpy() for key, v in last.items()}
+    # one more (untimed) solve with every launch of both iteration passes
+    # timed by events stamped at the kernels' own start and end
+    _, pr_solved, pr_proj_ms, pr_con_ms, pr_launches, pr_iters = timed_solves(
+        solver, P, 1, SETTINGS, profile=3)
+    passes = {}
+    for kind, ms in (("contract", pr_con_ms), ("project", pr_proj_ms)):
+        per_acc, per_launch = algorithmic_bytes(uni, book, pr_iters[0], SETTINGS["precision"],
+                                                kind)
+        alg = per_acc + per_launch * pr_launches
+        passes[kind] = {"ms_per_solve": ms, "launches": pr_launches,
+                        "avg_launch_us": ms * 1e3 / max(pr_launches, 1),
+                        "alg_bytes_per_launch": alg / max(pr_launches, 1),
+                        "achieved_gbs": alg / (ms * 1e-3) / 1e9 if ms > 0 else None}
+    dom = max(passes, key=lambda kd: passes[kd]["ms_per_solve"])
     it_all = np.concatenate(iters)
     # whole path against the per-account-iteration byte model of the method:
     # state z, u read + written, mu and w0 read (24 N), eligibility bits,
@@ -408,15 +574,14 @@ def main():
     model = float(np.sum(np.concatenate([it * (24.0 * uni.n + np.ceil(uni.n / 8.0) + 28.0 * held)
                                          for it in iters])))
     model += float(np.sum([it.max() for it in iters])) * (4.0 * uni.n * uni.k + 4.0 * uni.n)
-    alg_bytes = 0.0
-    for it in iters:
-        per_acc, per_launch = algorithmic_bytes(uni, book, it, SETTINGS["precision"])
-        alg_bytes += per_acc
-    alg_bytes += per_launch * launches
 
     value = solved / dt
-    achieved = alg_bytes / (kernel_ms * 1e-3) / 1e9 if kernel_ms > 0 else None
+    achieved = passes[dom]["achieved_gbs"]
     achievable = copy_bandwidth()
+    names = {"contract": "iter_kernel_bf<3, CONTRACT> (prox, r, bf16-split MFMA contraction "
+                         "B~^T Delta^-1 r, w)",
+             "project": "iter_kernel_bf<3, PROJECT> (bf16-split MFMA back-projection B~p, "
+                        "new ADMM state)"}
     line = {
         "metric": "accounts solved/s to 1e-6 KKT residual (500 accts, N=10k), "
                   "% HBM roofline",
@@ -448,6 +613,8 @@ def main():
             "iterations_p50_p90_p99_max": [float(np.percentile(it_all, q)) for q in (50, 90, 99)]
                                           + [int(it_all.max())],
             "cold_call_ms": cold_ms,
+            "timed_path": "captured hipGraph per block of iterations (graph_reused="
+                          f"{graph_reused} on the last timed call)",
         },
         "whole_path": {
             "model_bytes_per_step": model / args.steps,
@@ -462,27 +629,33 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
-            "traffic": measured_traffic(),
-            "kernel": "iter_kernel_bf<3, PROJECT> (bf16-split MFMA "
-                      "back-projection B~p, x-update, over-relaxation, new "
-                      "ADMM state)",
-            "alg_bytes_per_launch": alg_bytes / max(launches, 1),
-            "avg_launch_us": kernel_ms * 1e3 / max(launches, 1),
+            "traffic": measured_traffic(dom),
+            "kernel": names[dom],
+            "alg_bytes_per_launch": passes[dom]["alg_bytes_per_launch"],
+            "avg_launch_us": passes[dom]["avg_launch_us"],
             "achievable_gbs": achievable,
             "frac_of_achievable": (achieved / achievable) if (achieved and achievable) else None,
+            "note": "the pass with the largest time per solve, from one more solve whose "
+                    "launches are timed by events the dispatches stamp",
         },
-        "mfma": None if args.no_lanes else mfma_report(uni, book, mf_iters, mf_project_ms,
-                                                       contract_ms[0]),
+        "passes": passes,
+        "mfma": mfma_report(uni, book, pr_iters, pr_proj_ms, pr_con_ms),
     }
     if not args.no_lanes:
         line["queue"] = queue_lane(solver, P, SETTINGS)
         line["warm_lane"] = warm_lane(solver, uni, book, SETTINGS)
-        line["e7_lane"] = e7_lane(solver)
+        e7 = e7_lane(solver)
+        line["e7_lane"] = e7
+        line["e7_variants"] = e7_variants_lane(solver, e7["settings"])
         line["burden_lane"] = burden_lane(solver)
+        line["c4_grad_lane"] = c4_grad_lane(solver)
+        del P
+        torch.cuda.empty_cache()
+        line["c5_lane"] = c5_lane(solver)
     if args.plain_sample > 0:
         line["plain_fp32"] = plain_fp32(uni, book, args.plain_sample)
     if not args.no_cpu:
-        line["cpu_baseline"] = cpu_baseline(uni, book, args.cpu_sample)
+        line["cpu_baseline"] = cpu_baseline(uni, book, args.cpu_sample, gpu_out)
     print(json.dumps(line), flush=True)
 
 
