@@ -9,7 +9,7 @@ the timed region starts; the timed steps run the library's captured-graph
 path.  value = accounts certified to 1e-6 KKT residuals per second.
 
 The roofline object describes the iteration pass that takes the most time
-per solve (CONTRACT or PROJECT): algorithmic bytes per launch / average
+per solve (PROX, CONTRACT or PROJECT): algorithmic bytes per launch / average
 launch duration, both from one more (untimed) solve whose pass launches are
 timed with events that each dispatch stamps (hipExtLaunchKernelGGL) on the
 library's stream.
@@ -48,33 +48,39 @@ def algorithmic_bytes(uni, book, iters, precision, kind="project"):
     """Algorithmic bytes of one iteration pass over a solve, from the
     per-account iteration counts: (sum over account-iterations, per launch).
 
-    PROJECT (back-projection and the write of the new ADMM state): per
-    account-iteration w = v + alpha (Delta^-1 r - z) read and v written (8 N);
-    per launch the used columns of B~ (bf16 hi and lo: 4 B per entry;
-    float32: 4 B) and d (4 N).
+    PROX (the cap multiplier, then z, r and the two streams of the rest of
+    the iteration): per account-iteration v and mu read, R' = r / Delta and
+    w = v + alpha (R' - z) written (16 N), the eligibility bits (N / 8 when
+    the book has exclusions) and one 28-byte tax record per held name; per
+    launch d (4 N).
 
-    CONTRACT (prox, r, the contraction t = B~^T Delta^-1 r and w): per
-    account-iteration v and mu read, w written (12 N), the eligibility bits
-    (N / 8 when the book has exclusions) and one 28-byte tax record per held
-    name (the per-account-iteration bytes of the method's own model, with the
-    w stream in place of the second state stream); per launch the used
-    columns of B~ at 2 B per entry (the bf16 width of the method's model) and
-    d (4 N)."""
+    CONTRACT (the contraction t = B~^T R'): per account-iteration R' read
+    (4 N); per launch the used columns of B~ at 2 B per entry (the bf16
+    width of the method's model) and d (4 N).
+
+    PROJECT (back-projection and the write of the new ADMM state): per
+    account-iteration w read and v written (8 N); per launch the used
+    columns of B~ (bf16 hi and lo: 4 B per entry; float32: 4 B) and d
+    (4 N)."""
     import numpy as np
     n = uni.n
     kw = factor_width(uni)
     if kind == "project":
         per_acc = np.full(book.m, 8.0 * n)
         per_launch = 4.0 * n * kw + 4.0 * n
+    elif kind == "contract":
+        per_acc = np.full(book.m, 4.0 * n)
+        per_launch = 2.0 * n * kw + 4.0 * n
     else:
         held = np.count_nonzero(book.w0, axis=1)
         mask = 0.0 if book.eligible.all() else np.ceil(n / 8.0)
-        per_acc = 12.0 * n + mask + 28.0 * held
-        per_launch = 2.0 * n * kw + 4.0 * n
+        per_acc = 16.0 * n + mask + 28.0 * held
+        per_launch = 4.0 * n
     return float(np.sum(iters * per_acc)), float(per_launch)
 
 
 TRAFFIC_NOTES = {
+    "prox": os.path.join(ROOT, "profiles", "prox_pass_c3_500x10000_hbm_traffic.md"),
     "contract": os.path.join(ROOT, "profiles", "contract_pass_c3_500x10000_hbm_traffic.md"),
     "project": os.path.join(ROOT, "profiles", "project_pass_c3_500x10000_hbm_traffic.md"),
 }
@@ -101,11 +107,12 @@ def measured_traffic(kind):
     return float(vals["traffic_bytes_per_launch"])
 
 
-def timed_solves(solver, P, steps, settings, profile=0):
+def timed_solves(solver, P, steps, settings, profile=0, prox=None):
     """Run `steps` solves; profile=0 is the library's captured-graph path,
-    bit 0 / bit 1 time every PROJECT / CONTRACT launch with events (no
-    graph).  Returns (seconds, certified, PROJECT ms, CONTRACT ms, launches,
-    iters per solve)."""
+    bits 0 / 1 / 2 time every PROJECT / CONTRACT / PROX launch with events
+    (no graph; the PROX milliseconds are added to prox[0]).  Returns
+    (seconds, certified, PROJECT ms, CONTRACT ms, launches, iters per
+    solve)."""
     import torch
     out = None
     solved, proj_ms, con_ms, launches, iters = 0, 0.0, 0.0, 0, []
@@ -118,6 +125,8 @@ def timed_solves(solver, P, steps, settings, profile=0):
         solved += int((out["status"] == 0).sum().item())
         proj_ms += st["iter_kernel_ms"]
         con_ms += st["contract_kernel_ms"]
+        if prox is not None:
+            prox[0] += st["prox_kernel_ms"]
         launches += st["iter_launches"]
     torch.cuda.synchronize()
     return time.perf_counter() - t0, solved, proj_ms, con_ms, launches, iters
@@ -554,10 +563,11 @@ def main():
         gpu_out = {key: v.cpu().numpy() for key, v in last.items()}
     # one more (untimed) solve with every launch of both iteration passes
     # timed by events stamped at the kernels' own start and end
+    pr_prox = [0.0]
     _, pr_solved, pr_proj_ms, pr_con_ms, pr_launches, pr_iters = timed_solves(
-        solver, P, 1, SETTINGS, profile=3)
+        solver, P, 1, SETTINGS, profile=7, prox=pr_prox)
     passes = {}
-    for kind, ms in (("contract", pr_con_ms), ("project", pr_proj_ms)):
+    for kind, ms in (("prox", pr_prox[0]), ("contract", pr_con_ms), ("project", pr_proj_ms)):
         per_acc, per_launch = algorithmic_bytes(uni, book, pr_iters[0], SETTINGS["precision"],
                                                 kind)
         alg = per_acc + per_launch * pr_launches
@@ -578,8 +588,9 @@ def main():
     value = solved / dt
     achieved = passes[dom]["achieved_gbs"]
     achievable = copy_bandwidth()
-    names = {"contract": "iter_kernel_bf<3, CONTRACT> (prox, r, bf16-split MFMA contraction "
-                         "B~^T Delta^-1 r, w)",
+    names = {"prox": "prox_kernel (exact turnover-cap multiplier, then z, r, R' = r / Delta "
+                     "and w for every (account, asset))",
+             "contract": "iter_kernel_bf<3, CONTRACT> (bf16-split MFMA contraction B~^T R')",
              "project": "iter_kernel_bf<3, PROJECT> (bf16-split MFMA back-projection B~p, "
                         "new ADMM state)"}
     line = {

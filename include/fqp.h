@@ -159,8 +159,9 @@ typedef struct fqp_settings {
                             and a later call with the same arguments (same
                             buffers, sizes and schedule) replays it        */
   int32_t profile;       /* bit 0: time every PROJECT-pass launch, bit 1:
-                            every CONTRACT-pass launch, with events that the
-                            kernel's own start and end stamp (no graphs)    */
+                            every CONTRACT-pass launch, bit 2: every PROX-
+                            pass launch, with events that the kernel's own
+                            start and end stamp (no graphs)                */
   double time_limit_ms;  /* wall-clock limit of the call (<= 0: none)     */
   int32_t precision;     /* fqp_precision of the ADMM contractions        */
   int32_t first_check;   /* iteration of the first polish / certification
@@ -240,6 +241,8 @@ typedef struct fqp_stats {
                                arguments (no capture in this call)         */
   int32_t workspace_requests; /* workspace requests the call made (the range
                                of settings.debug_fail_alloc)               */
+  double prox_kernel_ms;    /* summed execution time of the PROX-pass
+                               launches (settings.profile bit 2, else 0)   */
 } fqp_stats;
 
 FQP_API void fqp_default_settings(fqp_settings *s);

@@ -70,7 +70,8 @@ class Stats(ctypes.Structure):
                 ("total_ms", c_double), ("workspace_bytes", c_size_t),
                 ("polish_solves", c_int32), ("polish_gated", c_int32),
                 ("contract_kernel_ms", c_double), ("phase_ms", c_double * 4),
-                ("graph_reused", c_int32), ("workspace_requests", c_int32)]
+                ("graph_reused", c_int32), ("workspace_requests", c_int32),
+                ("prox_kernel_ms", c_double)]
 
 
 def state_floats(m: int, n: int, n_rows: int) -> int:

@@ -26,13 +26,14 @@
 // computes alone and the back-projection,
 //   v' = alpha x + (1 - alpha) z + u = w + alpha Delta^-1 (nu - (B~ p)_i),
 //   w  = v + alpha (Delta^-1 r - z),
-// so one iteration is four launches (below): CONTRACT streams v and mu,
-// writes the per-row-tile partials of t = B~^T Delta^-1 r (MFMA) and w; a
-// small per-account kernel reduces the partials and solves in factor space
-// (nu, p); PROJECT streams w and applies the back-projection B~ p (MFMA),
-// writing the new v; the cap kernel finds the exact turnover-cap multiplier
-// lam* of the new v per account (a safeguarded Newton search on the
-// piecewise-linear turnover).
+// so one iteration is four launches (below): PROX, per account, finds the
+// exact turnover-cap multiplier lam* of v (a safeguarded Newton search on
+// the piecewise-linear turnover) and writes R' = r / Delta and w for every
+// row -- the only pass that reads the row data (masks, holdings, tax
+// records); CONTRACT contracts R' with B~ (MFMA) into per-row-tile partials
+// of t = B~^T R'; a small per-account kernel reduces the partials and solves
+// in factor space (nu, p); PROJECT streams w and applies the back-projection
+// B~ p (MFMA), writing the new v.
 #include <algorithm>
 
 #include <hip/hip_ext.h>
@@ -219,14 +220,14 @@ __global__ __launch_bounds__(1024) void kfactor_kernel(int k, int G, int kp, int
 // ---------------------------------------------------------------------------
 // the fused passes
 //
-// The ADMM state kept in HBM is v = xh + u per (account, asset).  With the
-// exact cap multiplier lam* of v, z = prox(v; lam*) and u = v - z are
-// recomputed wherever they are needed, so one iteration is
-//   CONTRACT  z, u from v; r = mu + rho (z - u); t = B~^T Delta^-1 r (MFMA);
-//             w = v + alpha (Delta^-1 r - z)
+// The ADMM state kept in HBM is v = xh + u per (account, asset).  One
+// iteration is
+//   PROX      lam* of v (per account, exact); z = prox(v; lam*), u = v - z,
+//             r = mu + rho (z - u); R' = r / Delta and
+//             w = v + alpha (R' - z) written
+//   CONTRACT  t = B~^T R' (MFMA), per row tile
 //   k-solve   nu, p from t (factor space)
 //   PROJECT   v <- w + alpha Delta^-1 (nu - B~ p)   (MFMA)
-//   cap       lam* of the new v (per account, exact)
 // ---------------------------------------------------------------------------
 enum PassMode { MODE_CONTRACT = 0, MODE_PROJECT = 1 };
 
@@ -394,48 +395,13 @@ __global__ __launch_bounds__(256, 2) void iter_kernel(IterArgs A) {
       continue;
     }
 
-    // issue every load of the lane's 16 (account, row) elements first, so
-    // that they are in flight together
-    float mu_r[16], v_r[16];
-    uint32_t ew_r[16], hw_r[16];
-    int hp_r[16];
-    const int wd = row >> 5;
+    // R' = r / Delta of the lane's 16 (account, row) elements, from the
+    // PROX pass, through a per-wave LDS transpose into the MFMA A operand
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
       const int m = 8 * (r >> 2) + 4 * hi + (r & 3);
       const int a = Aid[m];
-      mu_r[r] = 0.f; v_r[r] = 0.f; ew_r[r] = 0u; hw_r[r] = 0u; hp_r[r] = 0;
-      if (a >= 0 && row_ok) {
-        const unsigned off = (unsigned)(Ao[m] + row);
-        const unsigned wi = (unsigned)(Wo[m] + wd);
-        mu_r[r] = A.mu[off];
-        v_r[r] = A.v[off];
-        ew_r[r] = A.elig ? A.elig[wi] : 0xffffffffu;
-        hw_r[r] = A.hold[wi];
-        hp_r[r] = A.hold_pre[wi];
-      }
-    }
-#pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      const int m = 8 * (r >> 2) + 4 * hi + (r & 3);
-      const int a = Aid[m];
-      float Rp = 0.f;
-      if (a >= 0 && row_ok) {
-        const float4 q0 = Acc[2 * m], q1 = Acc[2 * m + 1];
-        const float rho = q0.x, irho = q0.y;
-        const float iDelta = __builtin_amdgcn_rcpf(q0.z * d_i + rho);
-        const unsigned off = (unsigned)(Ao[m] + row);
-        const float mu = mu_r[r];
-        const float vv = v_r[r];
-        const RowInfo ri = row_info_w(A, (size_t)off, row, q1.x, q1.y, ew_r[r], hw_r[r],
-                                      hp_r[r], Hp[m]);
-        const float z = prox_row(ri, vv, q0.w, irho, nullptr);
-        const float u = vv - z;
-        Rp = (mu + rho * (z - u)) * iDelta;
-        // the part of the new state that needs no back-projection, for PROJECT
-        A.zs[off] = vv + q1.w * (Rp - z);
-      }
-      Rw[m * 33 + l32] = Rp;
+      Rw[m * 33 + l32] = (a >= 0 && row_ok) ? A.rp[(size_t)a * A.npad + row] : 0.f;
     }
     if (MODE == MODE_CONTRACT) {
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -496,38 +462,13 @@ __device__ __forceinline__ void split_bf16(float x, __bf16& h, __bf16& l) {
   l = (__bf16)(x - (float)h);
 }
 
-// number of set bits of a wave-wide mask in lanes below this one
-__device__ __forceinline__ unsigned lanes_below(unsigned long long mask) {
-  return __builtin_amdgcn_mbcnt_hi((unsigned)(mask >> 32),
-                                   __builtin_amdgcn_mbcnt_lo((unsigned)mask, 0u));
-}
-
-constexpr int kRwS = 40;   // bf16 stride of one account's transposed R' (16-B aligned)
-
-// held (account, row) pairs of one wave's 32 x 32 block get their tax
-// records staged in LDS once per row chunk: kHS slots per wave, each an
-// absolute record index and the two float4 of the record
-constexpr int kHS = 64;
-constexpr int kHeldFloats = kHS + 8 * kHS;               // per wave
-constexpr int kRwFloats = kWaves * 2 * 32 * kRwS / 2;    // per-wave R' transposes
-
-template <int NCH, int MODE>
-constexpr int bf_held_offset() {
-  // CONTRACT: after the R' transposes; PROJECT: after the max reduction and
-  // the split p of the tile
-  return (MODE == MODE_CONTRACT) ? kRwFloats : kWaves * kTM + kTM * (NCH * 32 + 8);
-}
-
 template <int NCH, int MODE>
 constexpr int bf_lds_floats() {
-  // CONTRACT: per-wave R' transposes (hi, lo) and held records or, after the
-  // row loop, the cross-wave reduction [4][32][kp]; PROJECT: the split p of
-  // the tile (hi, lo) [2][32][kp + 8] bf16 (after 4 x 32 unused floats)
-  return (MODE == MODE_CONTRACT)
-             ? ((kWaves * kTM * NCH * 32 > kRwFloats + kWaves * kHeldFloats)
-                    ? kWaves * kTM * NCH * 32
-                    : kRwFloats + kWaves * kHeldFloats)
-             : bf_held_offset<NCH, MODE>();
+  // CONTRACT: the cross-wave reduction of the partial sums [4][32][kp];
+  // PROJECT: the split p of the tile (hi, lo) [2][32][kp + 8] bf16 (after
+  // 4 x 32 unused floats)
+  return (MODE == MODE_CONTRACT) ? kWaves * kTM * NCH * 32
+                                 : kWaves * kTM + kTM * (NCH * 32 + 8);
 }
 
 template <int NCH, int MODE>
@@ -539,9 +480,7 @@ __global__ __launch_bounds__(256, 3) void iter_kernel_bf(IterArgs A) {
   float* Xs = smem;
   float4* Acc = reinterpret_cast<float4*>(Xs + kX);    // [32][2] as in iter_kernel
   int* Aid = (int*)(Acc + 2 * kTM);     // [32]
-  int* Hp = Aid + kTM;                  // [32]
-  int* Ao = Hp + kTM;                   // [32] a * n
-  int* Wo = Ao + kTM;                   // [32] a * W
+  int* Ao = Aid + kTM;                  // [32] a * n
 
   const int m_act = *A.m_act;
   const TileMap tm = tile_map(m_act, A.n, gridDim.x * gridDim.y,
@@ -560,15 +499,13 @@ __global__ __launch_bounds__(256, 3) void iter_kernel_bf(IterArgs A) {
     int s = slot0 + tid;
     const int a = (s < m_act) ? A.act[s] : -1;
     Aid[tid] = a;
-    Hp[tid] = (a >= 0) ? A.hold_ptr[a] : 0;
     Ao[tid] = (a >= 0) ? a * n : 0;        // m n < 2^31 (checked by the runtime)
-    Wo[tid] = (a >= 0) ? a * A.W : 0;
+    // PROJECT: {rho, -, gamma, -}, {-, -, nu, alpha}
     float4 q0 = make_float4(1.f, 1.f, 0.f, 0.f), q1 = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (a >= 0) {
+    if (MODE == MODE_PROJECT && a >= 0) {
       const float* p = A.par + (size_t)a * kNPar;
-      const float rho = p[P_RHO], irho = 1.f / rho;
-      q0 = make_float4(rho, irho, p[P_GAMMA], (p[P_KAPPA] + p[P_LAM]) * irho);
-      q1 = make_float4(p[P_LB], p[P_UB], p[P_NU], p[P_ALPHA]);
+      q0 = make_float4(p[P_RHO], 0.f, p[P_GAMMA], 0.f);
+      q1 = make_float4(0.f, 0.f, p[P_NU], p[P_ALPHA]);
     }
     Acc[2 * tid] = q0;
     Acc[2 * tid + 1] = q1;
@@ -598,10 +535,6 @@ __global__ __launch_bounds__(256, 3) void iter_kernel_bf(IterArgs A) {
   for (int c = 0; c < NCH; ++c)
 #pragma unroll
     for (int r = 0; r < 16; ++r) T[c][r] = 0.f;
-  __bf16* RwH = reinterpret_cast<__bf16*>(Xs) + w * 2 * 32 * kRwS;
-  int* HIdx = reinterpret_cast<int*>(Xs + bf_held_offset<NCH, MODE>() + w * kHeldFloats);
-  float4* HRec = reinterpret_cast<float4*>(HIdx + kHS);
-  __bf16* RwL = RwH + 32 * kRwS;
   const int row_begin = tm.row_begin;
 
   for (int ch = 0; ch < tm.chunks; ++ch) {
@@ -610,91 +543,25 @@ __global__ __launch_bounds__(256, 3) void iter_kernel_bf(IterArgs A) {
     const int row_base = r0 + 32 * w;     // < npad: rows are padded to whole chunks
     const int row = row_base + l32;
     const bool row_ok = row < n;
-    const float d_i = row_ok ? A.d[row] : 1.f;
 
-    float mu_r[16], v_r[16];
-    const int wd = row >> 5, b = row & 31;
-    // bit r: slot r holds an account and a row inside the book / the row is
-    // eligible / the row is held
-    unsigned ok_bits = 0u, el_bits = 0u, held_bits = 0u;
     if (MODE == MODE_PROJECT) {
-      // w of this iterate comes from the CONTRACT pass: no row data, no
-      // returns and no old state needed here
+      // w of this iterate comes from the PROX pass: no row data, no returns
+      // and no old state needed here
+      const float d_i = row_ok ? A.d[row] : 1.f;
+      float w_r[16];
+      unsigned ok_bits = 0u;
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
         const int m = 8 * (r >> 2) + 4 * hi + (r & 3);
-        v_r[r] = 0.f;
+        w_r[r] = 0.f;
         if (Aid[m] >= 0 && row_ok) {
-          const unsigned off = (unsigned)(Ao[m] + row);
-          v_r[r] = A.zs[off];
+          w_r[r] = A.zs[(unsigned)(Ao[m] + row)];
           ok_bits |= 1u << r;
         }
       }
-    } else {
-      // the 32 rows of a half-wave share one eligibility, holding and
-      // holding-prefix word per account: lane j < 16 of the half loads the
-      // first two for slot j, lane 16 + j the third; the others read them
-      // by lane shuffles
-      uint32_t w_a = 0u;      // lanes j < 16: eligibility word of slot j
-      int w_b = 0;            // lanes j < 16: holding word; 16 + j: prefix
-      if (row_base < n) {     // uniform per wave: the words exist
-        const int rr = l32 & 15;
-        const int mm = 8 * (rr >> 2) + 4 * hi + (rr & 3);
-        if (Aid[mm] >= 0) {
-          const unsigned wi = (unsigned)(Wo[mm] + wd);
-          if (l32 < 16) {
-            w_a = A.elig ? A.elig[wi] : 0xffffffffu;
-            w_b = (int)A.hold[wi];
-          } else {
-            w_b = A.hold_pre[wi];
-          }
-        }
-      }
+      floatx16 X;
 #pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int m = 8 * (r >> 2) + 4 * hi + (r & 3);
-        mu_r[r] = 0.f; v_r[r] = 0.f;
-        if (Aid[m] >= 0 && row_ok) {
-          const unsigned off = (unsigned)(Ao[m] + row);
-          mu_r[r] = A.mu[off];
-          v_r[r] = A.v[off];
-          ok_bits |= 1u << r;
-        }
-      }
-      // record indices of the held pairs, in ballot order, into the wave's
-      // slot table; then one record load per lane
-      unsigned base = 0u;
-#pragma nounroll
-      for (int r = 0; r < 16; ++r) {
-        const int m = 8 * (r >> 2) + 4 * hi + (r & 3);
-        const uint32_t ew = (uint32_t)__shfl((int)w_a, 32 * hi + r, 64);
-        const uint32_t hw = (uint32_t)__shfl(w_b, 32 * hi + r, 64);
-        const int hp = __shfl(w_b, 32 * hi + 16 + r, 64);
-        el_bits |= ((ew >> b) & 1u) << r;
-        const bool held = ((ok_bits >> r) & 1u) && ((hw >> b) & 1u);
-        held_bits |= (held ? 1u : 0u) << r;
-        const unsigned long long hm = __ballot(held);
-        const unsigned slot = base + lanes_below(hm);
-        if (held && slot < (unsigned)kHS) HIdx[slot] = Hp[m] + hp + popc_below(hw, b);
-        base += (unsigned)__popcll(hm);
-      }
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      if ((unsigned)lane < base && lane < kHS) {
-        const int idx = HIdx[lane];
-        HRec[2 * lane] = A.hold_rec[2 * idx];
-        HRec[2 * lane + 1] = A.hold_rec[2 * idx + 1];
-      }
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    }
-
-    floatx16 X;
-#pragma unroll
-    for (int r = 0; r < 16; ++r) X[r] = 0.f;
-    if (MODE == MODE_PROJECT) {
+      for (int r = 0; r < 16; ++r) X[r] = 0.f;
 #pragma unroll
       for (int s = 0; s < KS; ++s) {
         const size_t o = (size_t)row * kp + 16 * s + 8 * hi;
@@ -706,9 +573,6 @@ __global__ __launch_bounds__(256, 3) void iter_kernel_bf(IterArgs A) {
         X = __builtin_amdgcn_mfma_f32_32x32x16_bf16(pH, bL, X, 0, 0, 0);
         X = __builtin_amdgcn_mfma_f32_32x32x16_bf16(pL, bH, X, 0, 0, 0);
       }
-    }
-
-    if (MODE == MODE_PROJECT) {
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
         const int m = 8 * (r >> 2) + 4 * hi + (r & 3);
@@ -717,67 +581,38 @@ __global__ __launch_bounds__(256, 3) void iter_kernel_bf(IterArgs A) {
           const float iDelta = __builtin_amdgcn_rcpf(q0.z * d_i + q0.x);
           const unsigned off = (unsigned)(Ao[m] + row);
           // v' = w + alpha Delta^-1 (nu - (B~ p)_i)
-          A.v[off] = v_r[r] + q1.w * iDelta * (q1.z - X[r]);
+          A.v[off] = w_r[r] + q1.w * iDelta * (q1.z - X[r]);
         }
       }
-    }
-
-    unsigned hbase = 0u;
-#pragma unroll
-    for (int r = 0; r < (MODE == MODE_CONTRACT ? 16 : 0); ++r) {
-      const int m = 8 * (r >> 2) + 4 * hi + (r & 3);
-      const bool held = (held_bits >> r) & 1u;
-      const unsigned long long hm = __ballot(held);
-      const unsigned slot = hbase + lanes_below(hm);
-      hbase += (unsigned)__popcll(hm);
-      float Rp = 0.f;
-      if ((ok_bits >> r) & 1u) {
-        const float4 q0 = Acc[2 * m], q1 = Acc[2 * m + 1];
-        const float rho = q0.x, irho = q0.y;
-        const float iDelta = __builtin_amdgcn_rcpf(q0.z * d_i + rho);
-        const unsigned off = (unsigned)(Ao[m] + row);
-        RowInfo ri;
-        asset_box(A, (size_t)off, (el_bits >> r) & 1u, q1.x, q1.y, ri.lb, ri.ub);
-        ri.w0 = 0.f;
-        ri.taxed = false;
-        if (held) {
-          float4 r0, r1;
-          if (slot < (unsigned)kHS) {
-            r0 = HRec[2 * slot];
-            r1 = HRec[2 * slot + 1];
-          } else {                       // slot table full: direct loads
-            const unsigned wi = (unsigned)(Wo[m] + wd);
-            const int idx = Hp[m] + A.hold_pre[wi] + popc_below(A.hold[wi], b);
-            r0 = A.hold_rec[2 * idx];
-            r1 = A.hold_rec[2 * idx + 1];
-          }
-          ri.w0 = r0.x;
-          ri.taxed = r0.y > 0.f;
-          ri.t.b1 = r0.y; ri.t.b2 = r0.z; ri.t.b3 = r0.w;
-          ri.t.s0 = r1.x; ri.t.s1 = r1.y; ri.t.s2 = r1.z; ri.t.s3 = r1.w;
-        }
-        const float vv = v_r[r];
-        const float z = prox_row(ri, vv, q0.w, irho, nullptr);
-        const float u = vv - z;
-        Rp = (mu_r[r] + rho * (z - u)) * iDelta;
-        // the part of the new state that needs no back-projection, for PROJECT
-        A.zs[off] = vv + q1.w * (Rp - z);
-      }
-      if (MODE == MODE_CONTRACT) {
-        __bf16 h, l;
-        split_bf16(Rp, h, l);
-        RwH[m * kRwS + l32] = h;
-        RwL[m * kRwS + l32] = l;
-      }
-    }
-    if (MODE == MODE_CONTRACT) {
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    } else if (row_base < n) {            // uniform per wave
+      // A operand straight from R' (PROX pass): lane l32 takes account
+      // Aid[l32], rows row_base + 16 s + 8 hi .. + 8 (the rows past n of the
+      // last chunk are masked: R' is not written there)
+      const int am = Aid[l32];
 #pragma unroll
       for (int s = 0; s < 2; ++s) {
-        const bf16x8 aH = *reinterpret_cast<const bf16x8*>(RwH + l32 * kRwS + 16 * s + 8 * hi);
-        const bf16x8 aL = *reinterpret_cast<const bf16x8*>(RwL + l32 * kRwS + 16 * s + 8 * hi);
+        const int rb = row_base + 16 * s + 8 * hi;
+        float rv[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) rv[j] = 0.f;
+        if (am >= 0) {
+          const float4* src = reinterpret_cast<const float4*>(A.rp + (size_t)am * A.npad + rb);
+          const float4 x0 = src[0], x1 = src[1];
+          rv[0] = x0.x; rv[1] = x0.y; rv[2] = x0.z; rv[3] = x0.w;
+          rv[4] = x1.x; rv[5] = x1.y; rv[6] = x1.z; rv[7] = x1.w;
+          if (rb + 8 > n) {
+#pragma unroll
+            for (int j = 0; j < 8; ++j) rv[j] = (rb + j < n) ? rv[j] : 0.f;
+          }
+        }
+        bf16x8 aH, aL;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          __bf16 h, l;
+          split_bf16(rv[j], h, l);
+          aH[j] = h;
+          aL[j] = l;
+        }
 #pragma unroll
         for (int c = 0; c < NCH; ++c) {
           const size_t o = (size_t)(32 * c + l32) * A.npad + row_base + 16 * s + 8 * hi;
@@ -788,9 +623,6 @@ __global__ __launch_bounds__(256, 3) void iter_kernel_bf(IterArgs A) {
           T[c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aL, bH, T[c], 0, 0, 0);
         }
       }
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
   }
 
@@ -837,17 +669,30 @@ __global__ void split_bt_kernel(int n, int npad, int kp, const float* Bt, uint16
 }
 
 // ---------------------------------------------------------------------------
-// exact turnover-cap multiplier of the current v (one workgroup per account)
+// PROX: the per-account pass of an iteration (one workgroup per account)
 //
-// turnover(lam) = sum_i |prox_i(v_i; lam) - w0_i| is piecewise linear and
-// non-increasing in lam, with slope -(number of coordinates strictly inside
-// a linear piece)/rho.  lam* = 0 when turnover(0) <= tau, else the root of
-// turnover(lam) = tau, found by Newton steps from the previous lam* inside a
-// bracket that every evaluation tightens (bisection when a step leaves it).
+// 1. The exact turnover-cap multiplier lam* of the current v (accounts with
+//    a finite cap): turnover(lam) = sum_i |prox_i(v_i; lam) - w0_i| is
+//    piecewise linear and non-increasing in lam, with slope -(number of
+//    coordinates strictly inside a linear piece)/rho.  lam* = 0 when
+//    turnover(0) <= tau, else the root of turnover(lam) = tau, found by
+//    Newton steps from the previous lam* inside a bracket that every
+//    evaluation tightens (bisection when a step leaves it).
+// 2. For every row, z = prox(v; lam*), u = v - z, r = mu + rho (z - u) and
+//    the two streams the rest of the iteration needs: R' = r / Delta (the
+//    CONTRACT pass contracts it with B~) and w = v + alpha (R' - z) (the
+//    PROJECT pass adds the back-projection to it).  With zmode the pass
+//    writes z instead (the input of the polish).
+// The row data (masks, holdings, tax records) is read here only: the
+// CONTRACT pass is a plain contraction of R'.
 // ---------------------------------------------------------------------------
 constexpr int kCapT = 1024;             // 16 waves per account: latency-bound passes
 constexpr int kCapQ = 16;               // rows per thread kept in registers (n <= 16384)
 constexpr int kCapH = 2 * kCapT;        // held rows kept in registers (two per thread)
+// the resident layout is compiled for 4, 8, 10, 12 and 16 rows per thread, the
+// smallest that holds the book taken: registers beyond the book's rows would
+// push the kernel past the 64 registers a lane may use with two accounts per
+// compute unit
 
 // one safeguarded Newton step on turnover(lam) = tau from the summed
 // turnover gt and free count nft at lam; updates the bracket [lo, hi_b], the
@@ -871,47 +716,68 @@ __device__ __forceinline__ float cap_step(float gt, float nft, float tau, float 
   return fmaxf(nl, 0.f);
 }
 
-// Resident layout (n <= kCapQ * kCapT and at most kCapH held rows in every
-// account of the book; the host picks the layout per solve): one pass loads
-// the account; rows that are eligible and not held keep v in a register (an
-// excluded row, never held, has z = 0 for every multiplier and keeps 0);
-// held row j moves to LDS, and thread j keeps the first kCapT held rows' tax
-// records in registers (records past that are re-read from the cache at each
-// evaluation); every evaluation then runs on registers and LDS, and every
-// thread takes the same Newton step from the same sums (one barrier per
-// evaluation, double-buffered sums).  At most 64 registers per lane, so that
-// two accounts share a compute unit.
-__global__ __launch_bounds__(kCapT, 8) void cap_kernel(IterArgs A) {
+// the multiplier the search hands on: never one whose turnover is known to
+// exceed tau
+__device__ __forceinline__ float cap_result(float lam, bool done, float best_feas) {
+  return (!done && isfinite(best_feas)) ? best_feas : lam;
+}
+
+// the row's outputs from v and its z (zmode: z itself)
+__device__ __forceinline__ void prox_out(const IterArgs& A, int zmode, size_t off, size_t roff,
+                                         float v, float z, float d_i, float rho, float gam,
+                                         float alpha) {
+  if (zmode) {
+    A.zs[off] = z;
+    return;
+  }
+  const float iDelta = __builtin_amdgcn_rcpf(gam * d_i + rho);
+  const float u = v - z;
+  const float Rp = (A.mu[off] + rho * (z - u)) * iDelta;
+  A.rp[roff] = Rp;
+  A.zs[off] = v + alpha * (Rp - z);
+}
+
+// Resident layout (n <= kCapQ * kCapT, at most kCapH held rows in every
+// account of the book, one box per account; the host picks the layout per
+// solve): one pass loads the account; rows that are not held keep v in a
+// register (an excluded row has the box [0, 0], so z = 0 for every
+// multiplier); held row j moves to LDS, and thread j keeps the first kCapT
+// held rows' tax records in registers (records past that are re-read from
+// the cache at each evaluation); every evaluation then runs on registers and
+// LDS, and every thread takes the same Newton step from the same sums (one
+// barrier per evaluation, double-buffered sums).
+template <int Q>
+__global__ __launch_bounds__(kCapT, 8) void prox_kernel(IterArgs A, int zmode) {
   __shared__ float s_g[2][kCapT / 64], s_n[2][kCapT / 64];
   __shared__ float s_hv[kCapH];
-  __shared__ unsigned char s_hel[kCapH];
+  __shared__ int s_hrow[kCapH];          // row of held record j, sign bit: excluded
   const int slot = blockIdx.x;
   if (slot >= *A.m_act) return;
   const int a = A.act[slot];
   float* par = A.par_rw + (size_t)a * kNPar;
   const float tau = par[P_TAU];
-  if (!isfinite(tau)) return;
+  const bool capped = isfinite(tau);
   const int tid = threadIdx.x, n = A.n, wv = tid >> 6;
   const float rho = par[P_RHO], irho = 1.f / rho, kap = par[P_KAPPA];
   const float lbp = par[P_LB], ubp = par[P_UB];
-  float lam = par[P_LAM];
+  float lam = capped ? par[P_LAM] : 0.f;
   const int hptr = A.hold_ptr[a];
   const int H = A.hold_ptr[a + 1] - hptr;
   float lo = 0.f, hi_b = INFINITY, best_feas = INFINITY;
-  bool done = false;
+  bool done = !capped;
 
   const float* va = A.v + (size_t)a * n;
   const size_t wa = (size_t)a * A.W;
-  float vr[kCapQ];
+  float vr[Q];
   // bit q: slot q is an eligible, unheld row inside the book (box [lb, ub]);
-  // excluded rows and the padding past n have the box [0, 0] and add nothing
-  unsigned box_bits = 0u;
+  // held_bits: slot q is held (its row lives in LDS and with thread j)
+  unsigned box_bits = 0u, held_bits = 0u;
   // every load of the account issued before any is used
   {
-    float x[kCapQ];
-    uint32_t ew[kCapQ], hw[kCapQ];
+    float x[Q];
+    uint32_t ew[Q], hw[Q];
 #pragma unroll
-    for (int q = 0; q < kCapQ; ++q) {
+    for (int q = 0; q < Q; ++q) {
       const int i = q * kCapT + tid;
       x[q] = 0.f; ew[q] = 0u; hw[q] = 0u;
       if (i < n) {
@@ -921,16 +787,17 @@ __global__ __launch_bounds__(kCapT, 8) void cap_kernel(IterArgs A) {
       }
     }
 #pragma unroll
-    for (int q = 0; q < kCapQ; ++q) {
+    for (int q = 0; q < Q; ++q) {
       const int i = q * kCapT + tid;
       const int b = i & 31;
       const bool el = i < n && ((ew[q] >> b) & 1u);
-      float keep = el ? x[q] : 0.f;
+      float keep = x[q];
       if (i < n && ((hw[q] >> b) & 1u)) {
         const int j = A.hold_pre[wa + (i >> 5)] + popc_below(hw[q], b);
         s_hv[j] = x[q];
-        s_hel[j] = el ? 1 : 0;
+        s_hrow[j] = el ? i : ~i;
         keep = 0.f;
+        held_bits |= 1u << q;
       } else if (el) {
         box_bits |= 1u << q;
       }
@@ -945,7 +812,7 @@ __global__ __launch_bounds__(kCapT, 8) void cap_kernel(IterArgs A) {
   if (tid < H) {
     const float4 r0 = A.hold_rec[2 * (hptr + tid)], r1 = A.hold_rec[2 * (hptr + tid) + 1];
     hv = s_hv[tid];
-    const bool el = s_hel[tid] != 0;
+    const bool el = s_hrow[tid] >= 0;
     hlb = el ? lbp : 0.f;
     hub = el ? ubp : 0.f;
     hw0 = r0.x;
@@ -953,11 +820,22 @@ __global__ __launch_bounds__(kCapT, 8) void cap_kernel(IterArgs A) {
     ht.b1 = r0.y; ht.b2 = r0.z; ht.b3 = r0.w;
     ht.s0 = r1.x; ht.s1 = r1.y; ht.s2 = r1.z; ht.s3 = r1.w;
   }
-  for (int it = 0; it < 48; ++it) {
+  // held row j >= kCapT (second held row of thread j - kCapT): from the cache
+  auto held_far = [&](int j, RowInfo& ri) {
+    const float4 r0 = A.hold_rec[2 * (hptr + j)], r1 = A.hold_rec[2 * (hptr + j) + 1];
+    const bool el = s_hrow[j] >= 0;
+    ri.lb = el ? lbp : 0.f;
+    ri.ub = el ? ubp : 0.f;
+    ri.w0 = r0.x;
+    ri.taxed = r0.y > 0.f;
+    ri.t.b1 = r0.y; ri.t.b2 = r0.z; ri.t.b3 = r0.w;
+    ri.t.s0 = r1.x; ri.t.s1 = r1.y; ri.t.s2 = r1.z; ri.t.s3 = r1.w;
+  };
+  for (int it = 0; it < 48 && !done; ++it) {          // done is uniform
     const float th = (kap + lam) * irho;
     float g = 0.f, nf = 0.f;
 #pragma unroll
-    for (int q = 0; q < kCapQ; ++q) {
+    for (int q = 0; q < Q; ++q) {
       if (q * kCapT < n) {                 // uniform
         const bool in_box = (box_bits >> q) & 1u;
         float z = fminf(vr[q] + th, fmaxf(0.f, vr[q] - th));
@@ -975,18 +853,10 @@ __global__ __launch_bounds__(kCapT, 8) void cap_kernel(IterArgs A) {
       nf += kink ? 0.f : 1.f;
     }
     if (H > kCapT && tid + kCapT < H) {          // uniform test first
-      const int j = tid + kCapT;
-      const float4 r0 = A.hold_rec[2 * (hptr + j)], r1 = A.hold_rec[2 * (hptr + j) + 1];
       RowInfo ri;
-      const bool el = s_hel[j] != 0;
-      ri.lb = el ? lbp : 0.f;
-      ri.ub = el ? ubp : 0.f;
-      ri.w0 = r0.x;
-      ri.taxed = r0.y > 0.f;
-      ri.t.b1 = r0.y; ri.t.b2 = r0.z; ri.t.b3 = r0.w;
-      ri.t.s0 = r1.x; ri.t.s1 = r1.y; ri.t.s2 = r1.z; ri.t.s3 = r1.w;
+      held_far(tid + kCapT, ri);
       bool kink;
-      const float z = prox_row(ri, s_hv[j], th, irho, &kink);
+      const float z = prox_row(ri, s_hv[tid + kCapT], th, irho, &kink);
       g += fabsf(z - ri.w0);
       nf += kink ? 0.f : 1.f;
     }
@@ -1002,18 +872,49 @@ __global__ __launch_bounds__(kCapT, 8) void cap_kernel(IterArgs A) {
 #pragma unroll
     for (int q = 0; q < kCapT / 64; ++q) { gt += s_g[buf][q]; nft += s_n[buf][q]; }
     lam = cap_step(gt, nft, tau, rho, lam, lo, hi_b, best_feas, done);
-    if (done) break;
   }
-  if (tid == 0) {
-    // never hand the prox a multiplier whose turnover is known to exceed tau
-    float out = lam;
-    if (!done && isfinite(best_feas)) out = best_feas;
-    par[P_LAM] = out;
+  if (capped) {
+    lam = cap_result(lam, done, best_feas);      // the same in every thread
+    if (tid == 0) par[P_LAM] = lam;
+  }
+  // ---- the row outputs at lam* -------------------------------------------
+  // (gamma and alpha read only now: registers are short during the search)
+  const float gam = par[P_GAMMA], alpha = par[P_ALPHA];
+  const float th = (kap + lam) * irho;
+  const size_t ao = (size_t)a * n, ro = (size_t)a * A.npad;
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const int i = q * kCapT + tid;
+    if (q * kCapT < n && i < n && !((held_bits >> q) & 1u)) {
+      const bool in_box = (box_bits >> q) & 1u;
+      float z = fminf(vr[q] + th, fmaxf(0.f, vr[q] - th));
+      z = in_box ? fminf(fmaxf(z, lbp), ubp) : 0.f;
+      prox_out(A, zmode, ao + i, ro + i, vr[q], z, A.d[i], rho, gam, alpha);
+    }
+    // one row's loads at a time: issuing all of them ahead would not fit in
+    // the registers two accounts per compute unit leave
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  if (tid < H) {
+    RowInfo ri;
+    ri.lb = hlb; ri.ub = hub; ri.w0 = hw0; ri.taxed = htx; ri.t = ht;
+    const float z = prox_row(ri, hv, th, irho, nullptr);
+    const int i = s_hrow[tid] >= 0 ? s_hrow[tid] : ~s_hrow[tid];
+    prox_out(A, zmode, ao + i, ro + i, hv, z, A.d[i], rho, gam, alpha);
+  }
+  if (H > kCapT && tid + kCapT < H) {
+    RowInfo ri;
+    held_far(tid + kCapT, ri);
+    const float v = s_hv[tid + kCapT];
+    const float z = prox_row(ri, v, th, irho, nullptr);
+    const int i = s_hrow[tid + kCapT] >= 0 ? s_hrow[tid + kCapT] : ~s_hrow[tid + kCapT];
+    prox_out(A, zmode, ao + i, ro + i, v, z, A.d[i], rho, gam, alpha);
   }
 }
 
-// Streaming layout (any size): each evaluation re-reads the account.
-__global__ __launch_bounds__(kCapT) void cap_stream_kernel(IterArgs A) {
+// Streaming layout (any size, per-asset bounds): each evaluation re-reads
+// the account; a last pass writes the row outputs.
+__global__ __launch_bounds__(kCapT) void prox_stream_kernel(IterArgs A, int zmode) {
   __shared__ float s_g[2][kCapT / 64], s_n[2][kCapT / 64];
   __shared__ float s_lam;
   __shared__ int s_done;
@@ -1022,18 +923,18 @@ __global__ __launch_bounds__(kCapT) void cap_stream_kernel(IterArgs A) {
   const int a = A.act[slot];
   float* par = A.par_rw + (size_t)a * kNPar;
   const float tau = par[P_TAU];
-  if (!isfinite(tau)) return;
+  const bool capped = isfinite(tau);
   const int tid = threadIdx.x, n = A.n, wv = tid >> 6;
   const float rho = par[P_RHO], irho = 1.f / rho, kap = par[P_KAPPA];
   const float lbp = par[P_LB], ubp = par[P_UB];
-  float lam = par[P_LAM];
+  const float gam = par[P_GAMMA], alpha = par[P_ALPHA];
+  float lam = capped ? par[P_LAM] : 0.f;
   const int hptr = A.hold_ptr[a];
-  const int H = A.hold_ptr[a + 1] - hptr;
   float lo = 0.f, hi_b = INFINITY, best_feas = INFINITY;
-  bool done = false;
+  bool done = !capped;
 
   if (tid == 0) s_done = 0;
-  for (int it = 0; it < 48; ++it) {
+  for (int it = 0; it < 48 && !done; ++it) {          // done is uniform
     const float th = (kap + lam) * irho;
     float g = 0.f, nf = 0.f;
     // groups of 8 rows per thread: every load of a group is issued before
@@ -1080,33 +981,44 @@ __global__ __launch_bounds__(kCapT) void cap_stream_kernel(IterArgs A) {
       bool dn;
       s_lam = cap_step(gt, nft, tau, rho, lam, lo, hi_b, best_feas, dn);
       s_done = dn ? 1 : 0;
+      // tid 0 carries the bracket: the hand-on multiplier, ready when done
+      if (dn || it == 47) s_lam = cap_result(s_lam, dn, best_feas);
     }
     __syncthreads();
     lam = s_lam;
     done = s_done != 0;
-    if (done) break;
     __syncthreads();
   }
-  if (tid == 0) {
-    // never hand the prox a multiplier whose turnover is known to exceed tau
-    // (tid 0 carries the bracket)
-    float out = lam;
-    if (!done && isfinite(best_feas)) out = best_feas;
-    par[P_LAM] = out;
-  }
-}
-
-// z = prox(v; lam*) for every active account (input of the polish)
-__global__ __launch_bounds__(256) void materialize_z_kernel(IterArgs A, float* z) {
-  const int slot = blockIdx.y;
-  if (slot >= *A.m_act) return;
-  const int a = A.act[slot];
-  const float* par = A.par + (size_t)a * kNPar;
-  const float rho = par[P_RHO], irho = 1.f / rho;
-  const float th = (par[P_KAPPA] + par[P_LAM]) * irho;
-  for (int i = blockIdx.x * 256 + threadIdx.x; i < A.n; i += gridDim.x * 256) {
-    const RowInfo ri = row_info(A, a, i, par[P_LB], par[P_UB]);
-    z[(size_t)a * A.n + i] = prox_row(ri, A.v[(size_t)a * A.n + i], th, irho, nullptr);
+  if (capped && tid == 0) par[P_LAM] = lam;
+  // ---- the row outputs at lam* -------------------------------------------
+  const float th = (kap + lam) * irho;
+  for (int i0 = 0; i0 < n; i0 += 8 * kCapT) {
+    float vr[8];
+    uint32_t ew[8], hw[8];
+    int hp[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int i = i0 + q * kCapT + tid;
+      vr[q] = 0.f; ew[q] = 0u; hw[q] = 0u; hp[q] = 0;
+      if (i < n) {
+        const size_t wi = (size_t)a * A.W + (i >> 5);
+        vr[q] = A.v[(size_t)a * n + i];
+        ew[q] = A.elig ? A.elig[wi] : 0xffffffffu;
+        hw[q] = A.hold[wi];
+        hp[q] = A.hold_pre[wi];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int i = i0 + q * kCapT + tid;
+      if (i < n) {
+        const RowInfo ri = row_info_w(A, (size_t)a * n + i, i, lbp, ubp, ew[q], hw[q], hp[q],
+                                      hptr);
+        const float z = prox_row(ri, vr[q], th, irho, nullptr);
+        prox_out(A, zmode, (size_t)a * n + i, (size_t)a * A.npad + i, vr[q], z, A.d[i], rho, gam,
+                 alpha);
+      }
+    }
   }
 }
 
@@ -1410,17 +1322,24 @@ bool cap_resident_fits(int n, int max_held) {
 // (the resident layout keeps one box per account; books with per-asset
 // bounds take the streaming layout)
 
-hipError_t launch_cap(const IterArgs& A, int m_total, bool resident, hipStream_t st) {
-  if (resident)
-    hipLaunchKernelGGL(cap_kernel, dim3(m_total), dim3(kCapT), 0, st, A);
+template <typename K>
+static void launch_prox_t(K kernel, int m_total, const IterArgs& A, int zmode, hipStream_t st,
+                          hipEvent_t ev0, hipEvent_t ev1) {
+  if (ev0 || ev1)
+    hipExtLaunchKernelGGL(kernel, dim3(m_total), dim3(kCapT), 0u, st, ev0, ev1, 0u, A, zmode);
   else
-    hipLaunchKernelGGL(cap_stream_kernel, dim3(m_total), dim3(kCapT), 0, st, A);
-  return hipGetLastError();
+    hipLaunchKernelGGL(kernel, dim3(m_total), dim3(kCapT), 0, st, A, zmode);
 }
 
-hipError_t launch_materialize_z(const IterArgs& A, int m_total, float* z, hipStream_t st) {
-  const int gx = (A.n + 255) / 256 < 64 ? (A.n + 255) / 256 : 64;
-  hipLaunchKernelGGL(materialize_z_kernel, dim3(gx, m_total), dim3(256), 0, st, A, z);
+hipError_t launch_prox(const IterArgs& A, int m_total, bool resident, int zmode,
+                       hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
+  const int q = (A.n + kCapT - 1) / kCapT;
+  if (resident && q <= 4) launch_prox_t(prox_kernel<4>, m_total, A, zmode, st, ev0, ev1);
+  else if (resident && q <= 8) launch_prox_t(prox_kernel<8>, m_total, A, zmode, st, ev0, ev1);
+  else if (resident && q <= 10) launch_prox_t(prox_kernel<10>, m_total, A, zmode, st, ev0, ev1);
+  else if (resident && q <= 12) launch_prox_t(prox_kernel<12>, m_total, A, zmode, st, ev0, ev1);
+  else if (resident) launch_prox_t(prox_kernel<16>, m_total, A, zmode, st, ev0, ev1);
+  else launch_prox_t(prox_stream_kernel, m_total, A, zmode, st, ev0, ev1);
   return hipGetLastError();
 }
 

@@ -37,9 +37,11 @@ struct IterArgs {
   const float* lbv;          // [m][n] per-asset bounds, or null (the
   const float* ubv;          //   account's scalars P_LB / P_UB)
   float* zs;                 // [m][n] w = v + alpha (Delta^-1 r - z) of the
-                             // current iterate: CONTRACT writes it, PROJECT adds
+                             // current iterate: PROX writes it, PROJECT adds
                              // the back-projection; before a polish it holds
-                             // z = prox(v; lam*) instead (materialize_z)
+                             // z = prox(v; lam*) instead (PROX in z mode)
+  float* rp;                 // [m][npad] R' = r / Delta of the current iterate
+                             // (PROX writes rows < n, CONTRACT reads it)
 };
 
 struct KArgs {
@@ -97,11 +99,12 @@ hipError_t launch_iter(const IterArgs& A, int kp, int mode, int prec, dim3 grid,
                        hipStream_t st, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 hipError_t launch_split_bt(int n, int npad, int kp, const float* Bt, uint16_t* bh, uint16_t* bl,
                            uint16_t* bth, uint16_t* btl, hipStream_t st);
-// turnover-cap multiplier search: the register-resident layout needs
-// n <= 16384 and at most 2048 held rows in every account
+// the per-account PROX pass (cap multiplier, then R' and w; zmode: z): the
+// register-resident layout needs n <= 16384, at most 2048 held rows in
+// every account and no per-asset bounds
 bool cap_resident_fits(int n, int max_held);
-hipError_t launch_cap(const IterArgs& A, int m_total, bool resident, hipStream_t st);
-hipError_t launch_materialize_z(const IterArgs& A, int m_total, float* z, hipStream_t st);
+hipError_t launch_prox(const IterArgs& A, int m_total, bool resident, int zmode,
+                       hipStream_t st, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 hipError_t launch_ksolve(const KArgs& A, int m_total, hipStream_t st);
 hipError_t launch_build_bt(int n, int k, int G, int H, int kp, const float* B,
                            const int32_t* group, const float* half, float* Bt, hipStream_t st);

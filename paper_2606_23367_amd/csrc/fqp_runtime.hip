@@ -5,7 +5,8 @@
 //   pack   universe block B~, per-account validation and held-asset records
 //   setup  one factor-space Cholesky/inverse per distinct (gamma, rho) class
 //   init   z = u = 0, contraction of mu for the first x-step
-//   loop   blocks of `check_every` iterations [k-solve, fused pass] (captured
+//   loop   blocks of `check_every` iterations [prox, contract, k-solve,
+//          project] (captured
 //          once in a hipGraph and replayed), then float64 polish and
 //          certification rounds on every active account, then compaction
 //          of the active list; the host reads the number still active
@@ -194,7 +195,7 @@ struct GraphKey {
   IterArgs ia;
   KArgs ka;
   unsigned gx, gy, gpx, gpy;
-  int m, kp, precision, count, any_cap, cap_resident;
+  int m, kp, precision, count, cap_resident;
 };
 
 struct fqp_handle {
@@ -632,6 +633,9 @@ extern "C" fqp_error fqp_solve_batch(fqp_handle* h, const fqp_universe* U, const
   const int n_rt = row_tiles(0), n_rt_p = row_tiles(1);
   const int max_rt = (n + kRowsPerChunk - 1) / kRowsPerChunk;   // short active lists
   WS(part, float, "part", (size_t)max_rt * m * kp);
+  // R' = r / Delta of every (account, row), rows padded to whole chunks
+  const int npad_r = ((n + kRowsPerChunk - 1) / kRowsPerChunk) * kRowsPerChunk;
+  WS(rprime, float, "rprime", (size_t)m * npad_r);
   // bf16 hi/lo copies of B~ for the split-precision contractions
   const int npad = ((n + kRowsPerChunk - 1) / kRowsPerChunk) * kRowsPerChunk;
   const bool split = S.precision == FQP_PREC_BF16X3 && kp <= kMaxKpBf;
@@ -674,21 +678,15 @@ extern "C" fqp_error fqp_solve_batch(fqp_handle* h, const fqp_universe* U, const
   HIP_CHECK(launch_pack_count(pk, st));
   HIP_CHECK(launch_pack_scan(pk, st));
   HIP_CHECK(launch_pack_fill(pk, st));
-  // the cap kernel runs only when some account has a finite cap; the
-  // held-asset records are sized by the packed count
-  bool any_cap = false;
+  // the held-asset records are sized by the packed count; the PROX layout
+  // by the most held names of any account
   int n_held = 0, max_held = 0;
   {
-    std::vector<float> tau_h(m);
     std::vector<int32_t> hp_h(m + 1);
-    HIP_CHECK(hipMemcpyAsync(tau_h.data(), P->tau, sizeof(float) * m, hipMemcpyDeviceToHost, st));
     HIP_CHECK(hipMemcpyAsync(hp_h.data(), hold_ptr, sizeof(int32_t) * (m + 1),
                              hipMemcpyDeviceToHost, st));
     HIP_CHECK(hipStreamSynchronize(st));
-    for (int a = 0; a < m; ++a) {
-      any_cap = any_cap || std::isfinite(tau_h[a]);
-      max_held = std::max(max_held, hp_h[a + 1] - hp_h[a]);
-    }
+    for (int a = 0; a < m; ++a) max_held = std::max(max_held, hp_h[a + 1] - hp_h[a]);
     n_held = hp_h[m];
   }
   const bool cap_resident = cap_resident_fits(n, max_held) && P->lb_asset == nullptr;
@@ -728,7 +726,7 @@ extern "C" fqp_error fqp_solve_batch(fqp_handle* h, const fqp_universe* U, const
   ia.hold_ptr = hold_ptr; ia.hold_w0 = hold_w0; ia.hold_tax = hold_tax;
   ia.tax_brk = P->tax_brk; ia.tax_slope = P->tax_slope; ia.pp = pp; ia.par = par;
   ia.par_rw = par;
-  ia.part = part; ia.zs = z;
+  ia.part = part; ia.zs = z; ia.rp = rprime;
   ia.npad = npad; ia.bt_hi = bt_hi; ia.bt_lo = bt_lo; ia.btt_hi = btt_hi; ia.btt_lo = btt_lo;
   ia.hold_rec = hold_rec;
   KArgs ka;
@@ -760,7 +758,7 @@ extern "C" fqp_error fqp_solve_batch(fqp_handle* h, const fqp_universe* U, const
 
   std::vector<hipEvent_t> evs;
   if (S.profile) {
-    evs.resize(4 * S.check_every);      // PROJECT pairs, then CONTRACT pairs
+    evs.resize(6 * S.check_every);      // PROJECT pairs, CONTRACT pairs, PROX pairs
     for (auto& ev : evs) HIP_CHECK(hipEventCreate(&ev));
   }
   struct EvGuard {
@@ -768,21 +766,24 @@ extern "C" fqp_error fqp_solve_batch(fqp_handle* h, const fqp_universe* U, const
     ~EvGuard() { for (auto& ev : *v) (void)hipEventDestroy(ev); }
   } evguard{&evs};
   const dim3 igrid(n_rt, acc_tiles), igrid_p(n_rt_p, acc_tiles);
-  // one ADMM iteration: contract, factor-space solve, project, cap
+  // one ADMM iteration: prox (cap multiplier, R', w), contract,
+  // factor-space solve, project
   auto launch_iteration = [&](int c) -> hipError_t {
     // profiling: events stamped by the pass kernels' own start and end
-    const int cb = 2 * S.check_every;
-    hipError_t e0 = (S.profile & 2) ? launch_iter(ia, kp, 0, S.precision, igrid, st,
-                                                  evs[cb + 2 * c], evs[cb + 2 * c + 1])
-                                    : launch_iter(ia, kp, 0, S.precision, igrid, st);
+    const int cb = 2 * S.check_every, xb = 4 * S.check_every;
+    hipError_t e0 = (S.profile & 4) ? launch_prox(ia, m, cap_resident, 0, st, evs[xb + 2 * c],
+                                                  evs[xb + 2 * c + 1])
+                                    : launch_prox(ia, m, cap_resident, 0, st);
+    if (e0 != hipSuccess) return e0;
+    e0 = (S.profile & 2) ? launch_iter(ia, kp, 0, S.precision, igrid, st, evs[cb + 2 * c],
+                                       evs[cb + 2 * c + 1])
+                         : launch_iter(ia, kp, 0, S.precision, igrid, st);
     if (e0 != hipSuccess) return e0;
     e0 = launch_ksolve(ka, m, st);
     if (e0 != hipSuccess) return e0;
     e0 = (S.profile & 1) ? launch_iter(ia, kp, 1, S.precision, igrid_p, st, evs[2 * c],
                                        evs[2 * c + 1])
                          : launch_iter(ia, kp, 1, S.precision, igrid_p, st);
-    if (e0 != hipSuccess) return e0;
-    if (any_cap) e0 = launch_cap(ia, m, cap_resident, st);
     return e0;
   };
 
@@ -795,7 +796,7 @@ extern "C" fqp_error fqp_solve_batch(fqp_handle* h, const fqp_universe* U, const
   key.ia = ia; key.ka = ka;
   key.gx = igrid.x; key.gy = igrid.y; key.gpx = igrid_p.x; key.gpy = igrid_p.y;
   key.m = m; key.kp = kp; key.precision = S.precision; key.count = S.check_every;
-  key.any_cap = any_cap ? 1 : 0; key.cap_resident = cap_resident ? 1 : 0;
+  key.cap_resident = cap_resident ? 1 : 0;
 
   // graph_reused reports a call that captured nothing: every block replayed
   // the graph kept from an earlier call
@@ -839,6 +840,11 @@ extern "C" fqp_error fqp_solve_batch(fqp_handle* h, const fqp_universe* U, const
             HIP_CHECK(hipEventElapsedTime(&ms, evs[cb + 2 * c], evs[cb + 2 * c + 1]));
             h->stats.contract_kernel_ms += ms;
           }
+          if (S.profile & 4) {
+            const int xb = 4 * S.check_every;
+            HIP_CHECK(hipEventElapsedTime(&ms, evs[xb + 2 * c], evs[xb + 2 * c + 1]));
+            h->stats.prox_kernel_ms += ms;
+          }
         }
       }
     }
@@ -869,7 +875,7 @@ extern "C" fqp_error fqp_solve_batch(fqp_handle* h, const fqp_universe* U, const
     if (done_iters < S.first_check && done_iters < S.max_iter) continue;
     HIP_CHECK(hipEventRecord(h->ev_t[2], st));
     // polish + certification rounds on z = prox(v; lam*)
-    HIP_CHECK(launch_materialize_z(ia, m, z, st));
+    HIP_CHECK(launch_prox(ia, m, cap_resident, 1, st));   // z = prox(v; lam*)
     pa.nf_gate = std::max(4 * k + 64, n / 8 + 4 * k);
     pa.nf_small = 2 * k + 32;
     pa.max_prop = 16;
@@ -896,7 +902,7 @@ extern "C" fqp_error fqp_solve_batch(fqp_handle* h, const fqp_universe* U, const
   }
   if (active > 0) {
     // last pattern from the current iterate, diagnostics, final statuses
-    HIP_CHECK(launch_materialize_z(ia, m, z, st));
+    HIP_CHECK(launch_prox(ia, m, cap_resident, 1, st));   // z = prox(v; lam*)
     pa.first_round = 1;
     pa.nf_gate = 0;
     pa.nf_small = 0;
