@@ -722,19 +722,34 @@ __device__ __forceinline__ float cap_result(float lam, bool done, float best_fea
   return (!done && isfinite(best_feas)) ? best_feas : lam;
 }
 
+// the account's rows as seen by the output phase: base pointers the whole
+// workgroup shares, so that a row is addressed by its 32-bit index
+struct ProxRows {
+  const float* mu;   // mu (or mu') of the account
+  float* w;          // w (zmode: z) of the account
+  float* rp;         // R' of the account
+};
+
+__device__ __forceinline__ ProxRows prox_rows(const IterArgs& A, int a) {
+  ProxRows o;
+  o.mu = A.mu + (size_t)a * A.n;
+  o.w = A.zs + (size_t)a * A.n;
+  o.rp = A.rp + (size_t)a * A.npad;
+  return o;
+}
+
 // the row's outputs from v and its z (zmode: z itself)
-__device__ __forceinline__ void prox_out(const IterArgs& A, int zmode, size_t off, size_t roff,
-                                         float v, float z, float d_i, float rho, float gam,
-                                         float alpha) {
+__device__ __forceinline__ void prox_out(const ProxRows& o, int zmode, int i, float v, float z,
+                                         float d_i, float rho, float gam, float alpha) {
   if (zmode) {
-    A.zs[off] = z;
+    o.w[i] = z;
     return;
   }
   const float iDelta = __builtin_amdgcn_rcpf(gam * d_i + rho);
   const float u = v - z;
-  const float Rp = (A.mu[off] + rho * (z - u)) * iDelta;
-  A.rp[roff] = Rp;
-  A.zs[off] = v + alpha * (Rp - z);
+  const float Rp = (o.mu[i] + rho * (z - u)) * iDelta;
+  o.rp[i] = Rp;
+  o.w[i] = v + alpha * (Rp - z);
 }
 
 // Resident layout (n <= kCapQ * kCapT, at most kCapH held rows in every
@@ -751,6 +766,10 @@ __global__ __launch_bounds__(kCapT, 8) void prox_kernel(IterArgs A, int zmode) {
   __shared__ float s_g[2][kCapT / 64], s_n[2][kCapT / 64];
   __shared__ float s_hv[kCapH];
   __shared__ int s_hrow[kCapH];          // row of held record j, sign bit: excluded
+  // the account's eligibility, holding and prefix words (one per 32 rows)
+  __shared__ uint32_t s_ew[kCapQ * kCapT / 32], s_hw[kCapQ * kCapT / 32];
+  __shared__ int s_hp[kCapQ * kCapT / 32];
+  __shared__ float4 s_rec[2 * kCapT];    // tax records of the first kCapT held rows
   const int slot = blockIdx.x;
   if (slot >= *A.m_act) return;
   const int a = A.act[slot];
@@ -770,59 +789,57 @@ __global__ __launch_bounds__(kCapT, 8) void prox_kernel(IterArgs A, int zmode) {
   const size_t wa = (size_t)a * A.W;
   float vr[Q];
   // bit q: slot q is an eligible, unheld row inside the book (box [lb, ub]);
-  // held_bits: slot q is held (its row lives in LDS and with thread j)
-  unsigned box_bits = 0u, held_bits = 0u;
-  // every load of the account issued before any is used
+  // a held row lives in LDS and with thread j (its slot here holds 0)
+  unsigned box_bits = 0u;
+  // every load of the account issued before any is used: the words go to
+  // LDS (one load per word, not one per row), v to registers
   {
-    float x[Q];
-    uint32_t ew[Q], hw[Q];
-#pragma unroll
-    for (int q = 0; q < Q; ++q) {
-      const int i = q * kCapT + tid;
-      x[q] = 0.f; ew[q] = 0u; hw[q] = 0u;
-      if (i < n) {
-        ew[q] = A.elig ? A.elig[wa + (i >> 5)] : 0xffffffffu;
-        hw[q] = A.hold[wa + (i >> 5)];
-        x[q] = va[i];
-      }
+    const int nw = (n + 31) >> 5;                // <= kCapT
+    if (tid < nw) {
+      s_ew[tid] = A.elig ? A.elig[wa + tid] : 0xffffffffu;
+      s_hw[tid] = A.hold[wa + tid];
+      s_hp[tid] = A.hold_pre[wa + tid];
+    }
+    if (tid < H) {
+      s_rec[2 * tid] = A.hold_rec[2 * (hptr + tid)];
+      s_rec[2 * tid + 1] = A.hold_rec[2 * (hptr + tid) + 1];
     }
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
       const int i = q * kCapT + tid;
+      vr[q] = i < n ? va[i] : 0.f;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const int i = q * kCapT + tid;
+      const int wi = min(i, n - 1) >> 5;
       const int b = i & 31;
-      const bool el = i < n && ((ew[q] >> b) & 1u);
-      float keep = x[q];
-      if (i < n && ((hw[q] >> b) & 1u)) {
-        const int j = A.hold_pre[wa + (i >> 5)] + popc_below(hw[q], b);
-        s_hv[j] = x[q];
+      const uint32_t hw = s_hw[wi];
+      const bool el = i < n && ((s_ew[wi] >> b) & 1u);
+      const bool held = i < n && ((hw >> b) & 1u);
+      if (held) {
+        const int j = s_hp[wi] + popc_below(hw, b);
+        s_hv[j] = vr[q];
         s_hrow[j] = el ? i : ~i;
-        keep = 0.f;
-        held_bits |= 1u << q;
-      } else if (el) {
-        box_bits |= 1u << q;
       }
-      vr[q] = keep;
+      vr[q] = held ? 0.f : vr[q];
+      box_bits |= (el && !held) ? (1u << q) : 0u;
     }
   }
   __syncthreads();
-  // held row tid: v, box and tax record in registers
-  float hv = 0.f, hw0 = 0.f, hlb = 0.f, hub = 0.f;
-  TaxLots ht{};
-  bool htx = false;
-  if (tid < H) {
-    const float4 r0 = A.hold_rec[2 * (hptr + tid)], r1 = A.hold_rec[2 * (hptr + tid) + 1];
-    hv = s_hv[tid];
-    const bool el = s_hrow[tid] >= 0;
-    hlb = el ? lbp : 0.f;
-    hub = el ? ubp : 0.f;
-    hw0 = r0.x;
-    htx = r0.y > 0.f;
-    ht.b1 = r0.y; ht.b2 = r0.z; ht.b3 = r0.w;
-    ht.s0 = r1.x; ht.s1 = r1.y; ht.s2 = r1.z; ht.s3 = r1.w;
-  }
-  // held row j >= kCapT (second held row of thread j - kCapT): from the cache
-  auto held_far = [&](int j, RowInfo& ri) {
-    const float4 r0 = A.hold_rec[2 * (hptr + j)], r1 = A.hold_rec[2 * (hptr + j) + 1];
+  // held row j: v from LDS, its tax record from LDS (j < kCapT) or from the
+  // cache (j >= kCapT: the second held row of thread j - kCapT)
+  const float hv = tid < H ? s_hv[tid] : 0.f;
+  auto held_row = [&](int j, RowInfo& ri) {
+    float4 r0, r1;
+    if (j < kCapT) {
+      r0 = s_rec[2 * j];
+      r1 = s_rec[2 * j + 1];
+    } else {
+      r0 = A.hold_rec[2 * (hptr + j)];
+      r1 = A.hold_rec[2 * (hptr + j) + 1];
+    }
     const bool el = s_hrow[j] >= 0;
     ri.lb = el ? lbp : 0.f;
     ri.ub = el ? ubp : 0.f;
@@ -846,7 +863,7 @@ __global__ __launch_bounds__(kCapT, 8) void prox_kernel(IterArgs A, int zmode) {
     }
     if (tid < H) {
       RowInfo ri;
-      ri.lb = hlb; ri.ub = hub; ri.w0 = hw0; ri.taxed = htx; ri.t = ht;
+      held_row(tid, ri);
       bool kink;
       const float z = prox_row(ri, hv, th, irho, &kink);
       g += fabsf(z - ri.w0);
@@ -854,7 +871,7 @@ __global__ __launch_bounds__(kCapT, 8) void prox_kernel(IterArgs A, int zmode) {
     }
     if (H > kCapT && tid + kCapT < H) {          // uniform test first
       RowInfo ri;
-      held_far(tid + kCapT, ri);
+      held_row(tid + kCapT, ri);
       bool kink;
       const float z = prox_row(ri, s_hv[tid + kCapT], th, irho, &kink);
       g += fabsf(z - ri.w0);
@@ -881,15 +898,18 @@ __global__ __launch_bounds__(kCapT, 8) void prox_kernel(IterArgs A, int zmode) {
   // (gamma and alpha read only now: registers are short during the search)
   const float gam = par[P_GAMMA], alpha = par[P_ALPHA];
   const float th = (kap + lam) * irho;
-  const size_t ao = (size_t)a * n, ro = (size_t)a * A.npad;
+  const ProxRows o = prox_rows(A, a);
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
     const int i = q * kCapT + tid;
-    if (q * kCapT < n && i < n && !((held_bits >> q) & 1u)) {
-      const bool in_box = (box_bits >> q) & 1u;
+    // held rows are written below, by the thread that keeps them (the row
+    // class comes from the LDS words again: box_bits would have to live
+    // through the search in a register)
+    if (q * kCapT < n && i < n && !((s_hw[i >> 5] >> (i & 31)) & 1u)) {
+      const bool in_box = (s_ew[i >> 5] >> (i & 31)) & 1u;
       float z = fminf(vr[q] + th, fmaxf(0.f, vr[q] - th));
       z = in_box ? fminf(fmaxf(z, lbp), ubp) : 0.f;
-      prox_out(A, zmode, ao + i, ro + i, vr[q], z, A.d[i], rho, gam, alpha);
+      prox_out(o, zmode, i, vr[q], z, A.d[i], rho, gam, alpha);
     }
     // one row's loads at a time: issuing all of them ahead would not fit in
     // the registers two accounts per compute unit leave
@@ -897,18 +917,18 @@ __global__ __launch_bounds__(kCapT, 8) void prox_kernel(IterArgs A, int zmode) {
   }
   if (tid < H) {
     RowInfo ri;
-    ri.lb = hlb; ri.ub = hub; ri.w0 = hw0; ri.taxed = htx; ri.t = ht;
+    held_row(tid, ri);
     const float z = prox_row(ri, hv, th, irho, nullptr);
     const int i = s_hrow[tid] >= 0 ? s_hrow[tid] : ~s_hrow[tid];
-    prox_out(A, zmode, ao + i, ro + i, hv, z, A.d[i], rho, gam, alpha);
+    prox_out(o, zmode, i, hv, z, A.d[i], rho, gam, alpha);
   }
   if (H > kCapT && tid + kCapT < H) {
     RowInfo ri;
-    held_far(tid + kCapT, ri);
+    held_row(tid + kCapT, ri);
     const float v = s_hv[tid + kCapT];
     const float z = prox_row(ri, v, th, irho, nullptr);
     const int i = s_hrow[tid + kCapT] >= 0 ? s_hrow[tid + kCapT] : ~s_hrow[tid + kCapT];
-    prox_out(A, zmode, ao + i, ro + i, v, z, A.d[i], rho, gam, alpha);
+    prox_out(o, zmode, i, v, z, A.d[i], rho, gam, alpha);
   }
 }
 
@@ -992,6 +1012,7 @@ __global__ __launch_bounds__(kCapT) void prox_stream_kernel(IterArgs A, int zmod
   if (capped && tid == 0) par[P_LAM] = lam;
   // ---- the row outputs at lam* -------------------------------------------
   const float th = (kap + lam) * irho;
+  const ProxRows o = prox_rows(A, a);
   for (int i0 = 0; i0 < n; i0 += 8 * kCapT) {
     float vr[8];
     uint32_t ew[8], hw[8];
@@ -1015,8 +1036,7 @@ __global__ __launch_bounds__(kCapT) void prox_stream_kernel(IterArgs A, int zmod
         const RowInfo ri = row_info_w(A, (size_t)a * n + i, i, lbp, ubp, ew[q], hw[q], hp[q],
                                       hptr);
         const float z = prox_row(ri, vr[q], th, irho, nullptr);
-        prox_out(A, zmode, (size_t)a * n + i, (size_t)a * A.npad + i, vr[q], z, A.d[i], rho, gam,
-                 alpha);
+        prox_out(o, zmode, i, vr[q], z, A.d[i], rho, gam, alpha);
       }
     }
   }
