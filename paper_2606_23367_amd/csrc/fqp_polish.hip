@@ -40,12 +40,11 @@ enum PState {
 static_assert(kNPState <= kPStateStride, "polish bookkeeping does not fit");
 
 constexpr double kSnap = 1e-10;
+constexpr int kSmallF = 64;               // free sets solved in row space
 constexpr int kMaxNull = 8;
-// one workgroup per account: the row passes are latency bound, so an
-// account gets 16 waves in the solve and 8 in the check (whose per-row
-// geometry needs more than the 128 registers a 16-wave group allows)
+// one workgroup of 16 waves per account: the row passes are latency bound
 constexpr int kPT = 1024;                 // polish_solve
-constexpr int kPTC = 512;                 // polish_check
+constexpr int kPTC = 1024;                // polish_check
 constexpr int kPW = kPT / 64;             // most waves of either
 
 struct Geom {
@@ -268,6 +267,101 @@ __device__ void list_sums(const PolishArgs& A, const int32_t* list, int n, int c
 // ---------------------------------------------------------------------------
 // polish_solve: classify (first round), lists, reduced KKT solve, w
 // ---------------------------------------------------------------------------
+// Row-space solve of a small free set (nF <= kSmallF): with the free rows'
+// constraint coefficients V_r = [1, band coefficients, sgn_r | rhs_r] and
+// H = gamma Sigma_FF = gamma (B_F diag(f) B_F^T + diag(d_F)), it forms H,
+// factors it (Cholesky by one wave), solves X = H^-1 V and writes the Schur
+// block S = V_C^T X = C H^-1 [C^T | rhs] the factor-space path forms by
+// Woodbury.  It also adds sum_F sgn_r w0_r to the cap's right-hand side.
+// Returns X ([nF][ncol], LDS) for the free-row values.
+__device__ double* small_free_solve(const PolishArgs& A, int a, int nF, const int32_t* flist,
+                                    const int8_t* code, const int* ps, int nc, int ncol,
+                                    int cap_on, double gam, float lbf, float ubf, float kap,
+                                    bool phi, const Wk& wk, double* sm, double* shd) {
+  const int k = A.k, G = A.G, tid = threadIdx.x, n = A.n;
+  double* Hs = sm;                                   // [nF][nF]
+  double* Vs = Hs + kSmallF * kSmallF;               // [nF][ncol]
+  double* Xs = Vs + kSmallF * ncol;                  // [nF][ncol]
+  double* fs = Xs + kSmallF * ncol;                  // [k]
+  float* Bs = reinterpret_cast<float*>(fs + k);      // [nF][k]
+  // stage the free rows' B, f and the constraint / rhs rows
+  for (int e = tid; e < nF * k; e += kPT) {
+    const int r = e / k, j = e % k;
+    Bs[e] = A.Bt[(size_t)flist[r] * A.kp + j];
+  }
+  for (int j = tid; j < k; j += kPT) fs[j] = (double)A.f[j];
+  double sgn_w0 = 0.0;
+  for (int r = tid; r < nF; r += kPT) {
+    const int i = flist[r];
+    RowData rd = row_data(A, a, i, lbf, ubf);
+    Geom g;
+    make_geom(g, kap, phi, rd);
+    double slope, sgn;
+    piece_slope(g, code[i] >> 1, slope, sgn);
+    double cross = 0.0;
+    for (int j = 0; j < k; ++j) cross += (double)A.Bt[(size_t)i * A.kp + j] * wk.Fy[j];
+    double* v = Vs + r * ncol;
+    v[0] = 1.0;
+    int col = 1;
+    for (int gg = 0; gg < G; ++gg) {
+      if (!band_active(ps, gg)) continue;
+      v[col++] = row_coef(A, i, gg);
+    }
+    if (cap_on) v[col++] = sgn;
+    v[col] = mu_at(A, (size_t)a * n + i) - slope - gam * cross;
+    sgn_w0 += sgn * (double)rd.w0;
+  }
+  sgn_w0 = bsum<double>(sgn_w0, shd);            // (synchronises the staging)
+  if (tid == 0 && cap_on) wk.h[nc - 1] += sgn_w0;
+  // H, lower triangle
+  for (int e = tid; e < nF * nF; e += kPT) {
+    const int r = e / nF, c = e % nF;
+    if (c > r) continue;
+    const float* br = Bs + r * k;
+    const float* bc = Bs + c * k;
+    double h = 0.0;
+    for (int j = 0; j < k; ++j) h += (double)br[j] * fs[j] * (double)bc[j];
+    if (r == c) h += (double)A.d[flist[r]];
+    Hs[e] = gam * h;
+  }
+  for (int e = tid; e < nF * ncol; e += kPT) Xs[e] = Vs[e];
+  __syncthreads();
+  // Cholesky by wave 0: lane i keeps row i; column j is scaled, then each
+  // lane updates its own row of the trailing block (LDS accesses of one
+  // wave complete in order; the fences keep the compiler from moving them)
+  if (tid < 64) {
+    const int i = tid;
+    for (int j = 0; j < nF; ++j) {
+      const double djj = sqrt(fmax(Hs[j * nF + j], 1e-300));
+      double lij = 0.0;
+      if (i > j && i < nF) {
+        lij = Hs[i * nF + j] / djj;
+        Hs[i * nF + j] = lij;
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      if (i == j) Hs[j * nF + j] = djj;
+      if (i > j && i < nF) {
+        for (int l = j + 1; l <= i; ++l) Hs[i * nF + l] -= lij * Hs[l * nF + j];
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+  }
+  __syncthreads();
+  chol_solve_cols(Hs, nF, Xs, ncol);               // X = H^-1 V (ends synchronised)
+  // S = V_C^T X
+  for (int e = tid; e < nc * ncol; e += kPT) {
+    const int p = e / ncol, q = e % ncol;
+    double s = 0.0;
+    for (int r = 0; r < nF; ++r) s += Vs[r * ncol + p] * Xs[r * ncol + q];
+    wk.S[p * ncol + q] = s;
+  }
+  return Xs;
+}
+
 __global__ __launch_bounds__(kPT) void polish_solve_kernel(PolishArgs A) {
   extern __shared__ double smem_d[];
   const int k = A.k, G = A.G, n = A.n;
@@ -448,6 +542,15 @@ __global__ __launch_bounds__(kPT) void polish_solve_kernel(PolishArgs A) {
   }
   __syncthreads();
 
+  // A free set of at most kSmallF rows is solved in row space (its
+  // gamma Sigma_FF is at most 64 x 64: one wave factors it); a larger one
+  // through the factor space below.
+  const bool small = nF <= kSmallF;
+  double* Xs = nullptr;                   // small path: H^-1 [C | rhs] (LDS)
+  if (small) {
+    Xs = small_free_solve(A, a, nF, flist, code, ps, nc, ncol, cap_on, gam, lbf, ubf, kap,
+                          phi, wk, smem_d, shd);
+  } else {
   // ---- Kf = diag(1/f) + sum_F b b^T / d  (lower triangle, LDS) -----------
   // one 4 x 4 register tile of the lower triangle per thread; staged rows
   // are zero-padded to a multiple of 4 columns, 1/d_i follows them
@@ -615,6 +718,7 @@ __global__ __launch_bounds__(kPT) void polish_solve_kernel(PolishArgs A) {
     for (int j = 0; j < k; ++j) s -= wk.Waug[j * ncol + p] * wk.Y[j * ncol + q];
     wk.S[p * ncol + q] = s / gam;
   }
+  }                                       // factor-space path
   __syncthreads();
   if (tid == 0) {
     // eta0 from the ADMM iterate: -nu, band duals, lam_cap
@@ -709,6 +813,15 @@ __global__ __launch_bounds__(kPT) void polish_solve_kernel(PolishArgs A) {
     mult[1] = cap_on ? rr[col] : 0.0;
   }
   __syncthreads();
+  if (small) {
+    // w_F = H^-1 (rhs - C^T eta) = X[:, rhs] - X[:, C] eta
+    for (int t = tid; t < nF; t += kPT) {
+      double v = Xs[t * ncol + nc];
+      for (int p = 0; p < nc; ++p) v -= Xs[t * ncol + p] * wk.eta[p];
+      w[flist[t]] = v;
+    }
+    return;
+  }
   // sol = Y[:, rhs] - Y[:, C] eta
   for (int j = tid; j < k; j += kPT) {
     double s = wk.Y[j * ncol + nc];
@@ -1217,7 +1330,7 @@ __global__ __launch_bounds__(kPTC) void polish_check_kernel(PolishArgs A, fqp_re
   }
 }
 
-static size_t polish_smem(int k) {
+static size_t polish_smem(int k, int G) {
   // Kf (k^2 doubles) and a staging region; the Kf region first holds 64
   // staged B rows (64 (k + 1) floats) and the staging region 64 weights +
   // 64 indices
@@ -1225,11 +1338,16 @@ static size_t polish_smem(int k) {
   const size_t b = sizeof(float) * 64 * (size_t)(k + 1);
   // staging: 16 rows of [b | V | pad | 1/d]
   const size_t rest = sizeof(double) * 16 * (size_t)(4 * ((k + kMaxG + 3 + 3) / 4) + 4);
-  return (a > b ? a : b) + (rest > 64 * 12 ? rest : 64 * 12);
+  const size_t factor = (a > b ? a : b) + (rest > 64 * 12 ? rest : 64 * 12);
+  // row-space path: H, V, X, f (doubles) and the free rows of B (floats)
+  const size_t ncol = (size_t)G + 3;
+  const size_t rows = sizeof(double) * (kSmallF * kSmallF + 2 * kSmallF * ncol + (size_t)k) +
+                      sizeof(float) * kSmallF * (size_t)k;
+  return factor > rows ? factor : rows;
 }
 
 hipError_t launch_polish_solve(const PolishArgs& A, hipStream_t st) {
-  const size_t smem = polish_smem(A.k);
+  const size_t smem = polish_smem(A.k, A.G);
   hipError_t e = hipFuncSetAttribute((const void*)polish_solve_kernel,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
   if (e != hipSuccess) return e;
