@@ -47,14 +47,38 @@ constexpr int kPT = 1024;                 // polish_solve
 constexpr int kPTC = 1024;                // polish_check
 constexpr int kPW = kPT / 64;             // most waves of either
 
+// The points, kinks and slopes of one asset's line, as scalar fields: a
+// run-time index goes through the select chains below, never through an
+// array, so that the structure stays in registers (an indexed array would
+// live in scratch memory, one memory round trip per access).
 struct Geom {
   int np;            // points on the asset's line: bounds and inner kinks
-  double pt[6];
-  float ptf[6];      // the same points as the float32 prox evaluates them
   int nk;            // kinks of the trade cost (w0 last when present)
-  double kink[4];
-  double ks[5];      // slope of the trade cost on each side of the kinks
+  double p0, p1, p2, p3, p4, p5;       // the points (ascending)
+  float f0, f1, f2, f3, f4, f5;        // the same points as the float32 prox evaluates them
+  double k0, k1, k2, k3;               // kinks (ascending)
+  double s0, s1, s2, s3, s4;           // slope of the trade cost on each side of the kinks
   double w0;
+  __device__ __forceinline__ double pt(int i) const {
+    return i <= 0 ? p0 : i == 1 ? p1 : i == 2 ? p2 : i == 3 ? p3 : i == 4 ? p4 : p5;
+  }
+  __device__ __forceinline__ float ptf(int i) const {
+    return i <= 0 ? f0 : i == 1 ? f1 : i == 2 ? f2 : i == 3 ? f3 : i == 4 ? f4 : f5;
+  }
+  __device__ __forceinline__ double kink(int i) const {
+    return i <= 0 ? k0 : i == 1 ? k1 : i == 2 ? k2 : k3;
+  }
+  __device__ __forceinline__ double ks(int i) const {
+    return i <= 0 ? s0 : i == 1 ? s1 : i == 2 ? s2 : i == 3 ? s3 : s4;
+  }
+  // point i <- (x, xf) when `on` (i in 1..5)
+  __device__ __forceinline__ void put(int i, bool on, double x, float xf) {
+    p1 = (on && i == 1) ? x : p1; f1 = (on && i == 1) ? xf : f1;
+    p2 = (on && i == 2) ? x : p2; f2 = (on && i == 2) ? xf : f2;
+    p3 = (on && i == 3) ? x : p3; f3 = (on && i == 3) ? xf : f3;
+    p4 = (on && i == 4) ? x : p4; f4 = (on && i == 4) ? xf : f4;
+    p5 = (on && i == 5) ? x : p5; f5 = (on && i == 5) ? xf : f5;
+  }
 };
 
 // eligibility, w0 and lot data of (account, row): the bitmask words, then
@@ -90,48 +114,52 @@ __device__ __forceinline__ RowData row_data(const PolishArgs& A, int a, int i, f
   return r;
 }
 
-__device__ void make_geom(Geom& g, float kap, bool phi, const RowData& r) {
+__device__ __forceinline__ void make_geom(Geom& g, float kap, bool phi, const RowData& r) {
   const float w0f = r.w0;
   const double lb = r.lb, ub = r.ub;
   g.w0 = w0f;
-  g.nk = 0;
-  float kf[4];
-  if (phi) {
-    if (r.taxed) {
-      const float b1 = r.b1, b2 = r.b2, b3 = r.b3;
-      const float s0 = r.s0, s1 = r.s1, s2 = r.s2, s3 = r.s3;
-      g.nk = 4;
-      g.kink[0] = (double)w0f - b3; kf[0] = w0f - b3;
-      g.kink[1] = (double)w0f - b2; kf[1] = w0f - b2;
-      g.kink[2] = (double)w0f - b1; kf[2] = w0f - b1;
-      g.kink[3] = w0f;              kf[3] = w0f;
-      g.ks[0] = -((double)kap + s3);
-      g.ks[1] = -((double)kap + s2);
-      g.ks[2] = -((double)kap + s1);
-      g.ks[3] = -((double)kap + s0);
-      g.ks[4] = kap;
-    } else {
-      g.nk = 1;
-      g.kink[0] = w0f; kf[0] = w0f;
-      g.ks[0] = -(double)kap;
-      g.ks[1] = kap;
-    }
-  } else {
-    g.ks[0] = 0.0;
-  }
-  g.np = 0;
-  g.pt[g.np] = lb; g.ptf[g.np] = r.lb; ++g.np;
-  for (int j = 0; j < g.nk; ++j)
-    if (g.kink[j] > lb && g.kink[j] < ub) { g.pt[g.np] = g.kink[j]; g.ptf[g.np] = kf[j]; ++g.np; }
-  if (ub > lb) { g.pt[g.np] = ub; g.ptf[g.np] = r.ub; ++g.np; }
+  // every field is written on every path (selects, not branches)
+  const bool tx = phi && r.taxed, pl = phi && !r.taxed;
+  const double kd = kap;
+  g.nk = tx ? 4 : (pl ? 1 : 0);
+  const float kf0 = tx ? w0f - r.b3 : w0f, kf1 = tx ? w0f - r.b2 : 0.f;
+  const float kf2 = tx ? w0f - r.b1 : 0.f, kf3 = tx ? w0f : 0.f;
+  g.k0 = tx ? (double)w0f - r.b3 : (double)w0f;
+  g.k1 = tx ? (double)w0f - r.b2 : 0.0;
+  g.k2 = tx ? (double)w0f - r.b1 : 0.0;
+  g.k3 = tx ? (double)w0f : 0.0;
+  g.s0 = tx ? -(kd + r.s3) : (pl ? -kd : 0.0);
+  g.s1 = tx ? -(kd + r.s2) : (pl ? kd : 0.0);
+  g.s2 = tx ? -(kd + r.s1) : 0.0;
+  g.s3 = tx ? -(kd + r.s0) : 0.0;
+  g.s4 = tx ? kd : 0.0;
+  // points: lb, the kinks strictly inside (lb, ub) (ascending), ub
+  g.np = 1;
+  g.p0 = lb; g.f0 = r.lb;
+  g.p1 = g.p2 = g.p3 = g.p4 = g.p5 = 0.0;
+  g.f1 = g.f2 = g.f3 = g.f4 = g.f5 = 0.f;
+  const bool in0 = g.nk > 0 && g.k0 > lb && g.k0 < ub;
+  g.put(g.np, in0, g.k0, kf0); g.np += in0 ? 1 : 0;
+  const bool in1 = g.nk > 1 && g.k1 > lb && g.k1 < ub;
+  g.put(g.np, in1, g.k1, kf1); g.np += in1 ? 1 : 0;
+  const bool in2 = g.nk > 2 && g.k2 > lb && g.k2 < ub;
+  g.put(g.np, in2, g.k2, kf2); g.np += in2 ? 1 : 0;
+  const bool in3 = g.nk > 3 && g.k3 > lb && g.k3 < ub;
+  g.put(g.np, in3, g.k3, kf3); g.np += in3 ? 1 : 0;
+  const bool top = ub > lb;
+  g.put(g.np, top, ub, r.ub); g.np += top ? 1 : 0;
+}
+
+// number of kinks below x (the kinks ascend)
+__device__ __forceinline__ int kinks_below(const Geom& g, double x) {
+  return (g.nk > 0 && g.k0 < x ? 1 : 0) + (g.nk > 1 && g.k1 < x ? 1 : 0) +
+         (g.nk > 2 && g.k2 < x ? 1 : 0) + (g.nk > 3 && g.k3 < x ? 1 : 0);
 }
 
 // slope of the trade cost (without cap) on the piece between points q, q+1
 __device__ __forceinline__ void piece_slope(const Geom& g, int q, double& slope, double& sgn) {
-  const double mid = 0.5 * (g.pt[q] + g.pt[q + 1]);
-  int s = 0;
-  while (s < g.nk && g.kink[s] < mid) ++s;
-  slope = g.ks[s];
+  const double mid = 0.5 * (g.pt(q) + g.pt(q + 1));
+  slope = g.ks(kinks_below(g, mid));
   sgn = (mid > g.w0) ? 1.0 : -1.0;
 }
 
@@ -139,21 +167,33 @@ __device__ __forceinline__ void piece_slope(const Geom& g, int q, double& slope,
 __device__ __forceinline__ void subdiff(const Geom& g, double x, double lam, double lb,
                                         double ub, double& lo, double& hi, double& snap) {
   snap = 0.0;
-  int at = -1;
-  for (int j = 0; j < g.nk; ++j)
-    if (fabs(x - g.kink[j]) <= kSnap) { at = j; break; }
+  // the first kink within kSnap of x, or -1
+  const int at = (g.nk > 0 && fabs(x - g.k0) <= kSnap) ? 0
+               : (g.nk > 1 && fabs(x - g.k1) <= kSnap) ? 1
+               : (g.nk > 2 && fabs(x - g.k2) <= kSnap) ? 2
+               : (g.nk > 3 && fabs(x - g.k3) <= kSnap) ? 3 : -1;
   if (at >= 0) {
-    lo = g.ks[at] + ((at < g.nk) ? -lam : lam);
-    hi = g.ks[at + 1] + ((at + 1 < g.nk) ? -lam : lam);
-    snap = fabs(x - g.kink[at]);
+    lo = g.ks(at) + ((at < g.nk) ? -lam : lam);
+    hi = g.ks(at + 1) + ((at + 1 < g.nk) ? -lam : lam);
+    snap = fabs(x - g.kink(at));
   } else {
-    int s = 0;
-    while (s < g.nk && g.kink[s] < x) ++s;
-    lo = hi = g.ks[s] + ((s < g.nk) ? -lam : lam);
+    const int s = kinks_below(g, x);
+    lo = hi = g.ks(s) + ((s < g.nk) ? -lam : lam);
   }
   if (g.nk == 0) lo = hi = 0.0;
   if (x <= lb + kSnap) { lo = -INFINITY; snap = fmax(snap, fmax(x - lb, 0.0)); }
   if (x >= ub - kSnap) { hi = INFINITY; snap = fmax(snap, fmax(ub - x, 0.0)); }
+}
+
+// sale-side tax of selling s >= 0 from lots with breakpoints b1 < b2 < b3
+// and slopes t0..t3 (the last slope continues past b3)
+__device__ __forceinline__ double lot_tax(double s, const RowData& r) {
+  const double b1 = r.b1, b2 = r.b2, b3 = r.b3;
+  double tc = r.s0 * fmin(s, b1);
+  tc += (s > b1) ? r.s1 * (fmin(s, b2) - b1) : 0.0;
+  tc += (s > b2) ? r.s2 * (fmin(s, b3) - b2) : 0.0;
+  tc += (s > b3) ? r.s3 * (s - b3) : 0.0;
+  return tc;
 }
 
 
@@ -435,15 +475,18 @@ __global__ __launch_bounds__(kPT) void polish_solve_kernel(PolishArgs A) {
           make_geom(g, kap, phi, r);
           have = true;
           const float z = A.z[(size_t)a * n + i];
-          c = -1;
-          for (int j = 0; j < g.np; ++j)
-            if (z == g.ptf[j]) { c = 2 * j; break; }
+          // at point j (the float32 value the prox lands on), else inside
+          // the piece above the inner points below z (the points ascend)
+          c = (z == g.f0) ? 0 : (g.np > 1 && z == g.f1) ? 2 : (g.np > 2 && z == g.f2) ? 4
+            : (g.np > 3 && z == g.f3) ? 6 : (g.np > 4 && z == g.f4) ? 8
+            : (g.np > 5 && z == g.f5) ? 10 : -1;
           if (c < 0) {
-            int q = 0;
-            while (q + 2 < g.np && (double)z > g.pt[q + 1]) ++q;
+            const double zd = z;
+            const int q = (g.np > 2 && zd > g.p1 ? 1 : 0) + (g.np > 3 && zd > g.p2 ? 1 : 0) +
+                          (g.np > 4 && zd > g.p3 ? 1 : 0) + (g.np > 5 && zd > g.p4 ? 1 : 0);
             c = (g.np == 1) ? 0 : 2 * q + 1;
-            if (g.np > 1 && (double)z <= g.pt[0]) c = 0;
-            if (g.np > 1 && (double)z >= g.pt[g.np - 1]) c = 2 * (g.np - 1);
+            if (g.np > 1 && zd <= g.p0) c = 0;
+            if (g.np > 1 && zd >= g.pt(g.np - 1)) c = 2 * (g.np - 1);
           }
           code[i] = (int8_t)c;
           sig += (unsigned)(c + 1) * ((unsigned)i * 2654435761u + 1u);
@@ -458,7 +501,7 @@ __global__ __launch_bounds__(kPT) void polish_solve_kernel(PolishArgs A) {
             r = row_data(A, a, i, lbf, ubf);
             make_geom(g, kap, phi, r);
           }
-          const double v = g.pt[c >> 1];
+          const double v = g.pt(c >> 1);
           w[i] = v;
           isnz = (v != 0.0);
           sx += v;
@@ -1200,13 +1243,7 @@ __global__ __launch_bounds__(kPTC) void polish_check_kernel(PolishArgs A, fqp_re
     snapm = fmax(snapm, snap);
     // objective: (gamma/2) w.Sigma w - mu w + trade cost
     double tc = (double)kap * fabs(wi - g.w0);
-    if (r.taxed && wi < g.w0) {
-      const double s = g.w0 - wi;
-      const double e[5] = {0.0, (double)r.b1, (double)r.b2, (double)r.b3, INFINITY};
-      const double sl[4] = {(double)r.s0, (double)r.s1, (double)r.s2, (double)r.s3};
-      for (int L = 0; L < 4; ++L)
-        if (s > e[L]) tc += sl[L] * (fmin(s, e[L + 1]) - e[L]);
-    }
+    if (r.taxed && wi < g.w0) tc += lot_tax(g.w0 - wi, r);
     obj += 0.5 * gam * wi * sig - mui * wi + tc;
     // refinement proposal (applied only if the pattern fails)
     const int c = code_r[i];
@@ -1215,13 +1252,13 @@ __global__ __launch_bounds__(kPTC) void polish_check_kernel(PolishArgs A, fqp_re
       const double tolm = A.eps_dual * 0.1;
       if (c & 1) {
         const int q = c >> 1;
-        if (wi > g.pt[q + 1]) { code[i] = (int8_t)(2 * (q + 1)); ++changed; }
-        else if (wi < g.pt[q]) { code[i] = (int8_t)(2 * q); ++changed; }
+        if (wi > g.pt(q + 1)) { code[i] = (int8_t)(2 * (q + 1)); ++changed; }
+        else if (wi < g.pt(q)) { code[i] = (int8_t)(2 * q); ++changed; }
       } else {
         // move off a point when -g lies outside its subdifferential
         const int j = c >> 1;
         double l2, h2, sn2;
-        subdiff(g, g.pt[j], lam, lb, ub, l2, h2, sn2);
+        subdiff(g, g.pt(j), lam, lb, ub, l2, h2, sn2);
         const double sc = fmax(fabs(mui), 1e-12);
         if (t > h2 + tolm * sc && j + 1 < g.np) { code[i] = (int8_t)(2 * j + 1); ++changed; }
         else if (t < l2 - tolm * sc && j > 0) { code[i] = (int8_t)(2 * (j - 1) + 1); ++changed; }
