@@ -153,27 +153,30 @@ def copy_bandwidth(nbytes=1 << 30, reps=5):
 
 
 MFMA_BF16_PEAK_TFLOPS = 2500.0
+FP32_PEAK_TFLOPS = 157.3            # dense float32 MFMA, MI355X
 
 
-def mfma_report(uni, book, iters, project_ms, contract_ms):
+def mfma_report(uni, book, iters, project_ms, contract_ms, split=True):
     """Matrix-core rates of the two contraction passes over one profiled step:
-    useful flops are the products with the k + G + 1 used columns of B~ (2 N
-    (k + G + 1) per account-iteration and pass); issued flops count the three
-    bf16 products per float32 product over the padded width kp."""
+    useful flops are the products with the k + G + H + 1 used columns of B~
+    (2 N (k + G + H + 1) per account-iteration and pass); issued flops count
+    the padded width kp and, on the bf16-split path, its three bf16 products
+    per float32 product."""
     import numpy as np
-    n, k, G = uni.n, uni.k, uni.n_groups
+    n, k, G = uni.n, uni.k, uni.n_groups + getattr(uni, "n_half", 0)
     kg1 = k + G + 1
     kp = ((kg1 + 31) // 32) * 32
     acc_iters = float(sum(np.sum(it) for it in iters))
     useful = 2.0 * n * kg1 * acc_iters              # per pass
-    issued = useful * 3.0 * kp / kg1
-    out = {"instruction": "v_mfma_f32_32x32x16_bf16 (hi*hi + hi*lo + lo*hi)",
-           "peak_tflops": MFMA_BF16_PEAK_TFLOPS}
+    issued = useful * (3.0 if split else 1.0) * kp / kg1
+    peak = MFMA_BF16_PEAK_TFLOPS if split else FP32_PEAK_TFLOPS
+    out = {"instruction": "v_mfma_f32_32x32x16_bf16 (hi*hi + hi*lo + lo*hi)" if split
+           else "v_mfma_f32_32x32x2_f32", "peak_tflops": peak}
     for name, ms in (("contract", contract_ms), ("project", project_ms)):
         if ms > 0:
             out[name] = {"useful_tflops": useful / (ms * 1e-3) / 1e12,
                          "issued_tflops": issued / (ms * 1e-3) / 1e12,
-                         "issued_frac": issued / (ms * 1e-3) / 1e12 / MFMA_BF16_PEAK_TFLOPS}
+                         "issued_frac": issued / (ms * 1e-3) / 1e12 / peak}
     return out
 
 
@@ -588,11 +591,13 @@ def main():
     value = solved / dt
     achieved = passes[dom]["achieved_gbs"]
     achievable = copy_bandwidth()
+    split = SETTINGS["precision"] == 1
+    kern = "iter_kernel_bf" if split else "iter_kernel"
+    mm = "bf16-split MFMA" if split else "float32 MFMA"
     names = {"prox": "prox_kernel (exact turnover-cap multiplier, then z, r, R' = r / Delta "
                      "and w for every (account, asset))",
-             "contract": "iter_kernel_bf<3, CONTRACT> (bf16-split MFMA contraction B~^T R')",
-             "project": "iter_kernel_bf<3, PROJECT> (bf16-split MFMA back-projection B~p, "
-                        "new ADMM state)"}
+             "contract": f"{kern}<3, CONTRACT> ({mm} contraction B~^T R')",
+             "project": f"{kern}<3, PROJECT> ({mm} back-projection B~p, new ADMM state)"}
     line = {
         "metric": "accounts solved/s to 1e-6 KKT residual (500 accts, N=10k), "
                   "% HBM roofline",
@@ -605,14 +610,13 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32 (bf16-split MFMA) + f64",
+        "dtype": f"f32 ({mm}) + f64",
         "data": "synthetic",
         "config": {
             "workload": "500 accounts x N=10,000 assets, k=80 factors; "
                         "exclusion masks (30-100% eligible), 4-lot tax on "
-                        "100-400 held names, turnover cap; FP32 ADMM with "
-                        "bf16-split MFMA contractions + FP64 polish and "
-                        "certification",
+                        f"100-400 held names, turnover cap; FP32 ADMM with {mm} "
+                        "contractions + FP64 polish and certification",
             "settings": SETTINGS,
             "settings_from": settings_from or (
                 f"autotune on {TUNE_SAMPLE} accounts of the seed-{TUNE_SEED} book of the "
@@ -650,7 +654,7 @@ def main():
                     "launches are timed by events the dispatches stamp",
         },
         "passes": passes,
-        "mfma": mfma_report(uni, book, pr_iters, pr_proj_ms, pr_con_ms),
+        "mfma": mfma_report(uni, book, pr_iters, pr_proj_ms, pr_con_ms, split),
     }
     if not args.no_lanes:
         line["queue"] = queue_lane(solver, P, SETTINGS)

@@ -1128,17 +1128,23 @@ __global__ __launch_bounds__(kPTC) void polish_check_kernel(PolishArgs A, fqp_re
           double lo0, hi0, lo1, hi1, sn;
           subdiff(g, w[i], 0.0, lb, ub, lo0, hi0, sn);
           subdiff(g, w[i], 1.0, lb, ub, lo1, hi1, sn);
+          // a coefficient that cancels to rounding level (a fixed row whose
+          // interval moves with the free rows along v: the degenerate case
+          // of free rows that all trade one way) puts no bound on the step;
+          // taken at face value it would allow a step of 1/rounding
           if (isfinite(lo0)) {           // lo0 + s_lo (lamc + s ncap) <= T - al s
             const double slo = lo1 - lo0;
             const double aa = al + slo * ncap, bb = T - lo0 - slo * lamc;
-            if (aa > 1e-300) { const double u = bb / aa; if (u < Up) { Up = u; upKey = keyL; } }
-            else if (aa < -1e-300) { const double u = bb / aa; if (u > Lo) { Lo = u; loKey = keyL; } }
+            const double tz = 1e-12 * (fabs(al) + fabs(slo * ncap));
+            if (aa > tz) { const double u = bb / aa; if (u < Up) { Up = u; upKey = keyL; } }
+            else if (aa < -tz) { const double u = bb / aa; if (u > Lo) { Lo = u; loKey = keyL; } }
           }
           if (isfinite(hi0)) {           // T - al s <= hi0 + s_hi (lamc + s ncap)
             const double shi = hi1 - hi0;
             const double aa = -(al + shi * ncap), bb = hi0 + shi * lamc - T;
-            if (aa > 1e-300) { const double u = bb / aa; if (u < Up) { Up = u; upKey = keyU; } }
-            else if (aa < -1e-300) { const double u = bb / aa; if (u > Lo) { Lo = u; loKey = keyU; } }
+            const double tz = 1e-12 * (fabs(al) + fabs(shi * ncap));
+            if (aa > tz) { const double u = bb / aa; if (u < Up) { Up = u; upKey = keyU; } }
+            else if (aa < -tz) { const double u = bb / aa; if (u > Lo) { Lo = u; loKey = keyU; } }
           }
         }
         const double Lb = bmax<double>(Lo, shd);
@@ -1160,10 +1166,10 @@ __global__ __launch_bounds__(kPTC) void polish_check_kernel(PolishArgs A, fqp_re
           bool has_tgt = false;
           const double vtol = 0.1 * A.eps_prim;
           if (ps[PS_CAP]) {              // lam_cap + s ncap >= 0
-            if (ncap > 1e-300) { const double u = -lamc / ncap; if (u > Lo) { Lo = u; kLo = INT_MAX; } }
-            else if (ncap < -1e-300) { const double u = -lamc / ncap; if (u < Up) { Up = u; kUp = INT_MAX; } }
+            if (ncap > 1e-12) { const double u = -lamc / ncap; if (u > Lo) { Lo = u; kLo = INT_MAX; } }
+            else if (ncap < -1e-12) { const double u = -lamc / ncap; if (u < Up) { Up = u; kUp = INT_MAX; } }
             const double sl = (double)tauf - turn0;
-            if (fabs(ncap) > 1e-300) {
+            if (fabs(ncap) > 1e-12) {
               if (sl < -vtol && -sl > worst) {
                 worst = -sl; tgt = (ncap > 0.0) ? INFINITY : -INFINITY; has_tgt = true;
               } else if (worst == 0.0) {
@@ -1181,9 +1187,9 @@ __global__ __launch_bounds__(kPTC) void polish_check_kernel(PolishArgs A, fqp_re
             // upper band: lam >= 0 ; lower band: lam <= 0
             const double sgn_req = up ? 1.0 : -1.0;
             const double aa = sgn_req * nbv, bb = sgn_req * cur;   // bb + s aa >= 0
-            if (aa > 1e-300) { const double u = -bb / aa; if (u > Lo) { Lo = u; kLo = INT_MAX; } }
-            else if (aa < -1e-300) { const double u = -bb / aa; if (u < Up) { Up = u; kUp = INT_MAX; } }
-            if (fabs(nbv) <= 1e-300) continue;
+            if (aa > 1e-12) { const double u = -bb / aa; if (u > Lo) { Lo = u; kLo = INT_MAX; } }
+            else if (aa < -1e-12) { const double u = -bb / aa; if (u < Up) { Up = u; kUp = INT_MAX; } }
+            if (fabs(nbv) <= 1e-12) continue;
             const double sl = up ? (double)A.bhi[(size_t)a * G + gg] - s_gs[gg]
                                  : s_gs[gg] - (double)A.blo[(size_t)a * G + gg];
             if (sl < -vtol && -sl > worst) {

@@ -279,7 +279,7 @@ void fqp_default_settings(fqp_settings* s) {
   s->rho = 0.f;
   s->rho_band = 0.f;
   s->alpha = 1.6f;
-  s->polish_rounds = 4;
+  s->polish_rounds = 16;
   s->use_graph = 1;
   s->profile = 0;
   s->time_limit_ms = 0.0;

@@ -108,6 +108,29 @@ def test_autotune_confirms_finalists_on_a_second_book():
     assert int((out["status"] == 0).sum().item()) == book2.m
 
 
+def test_autotune_layout_stage():
+    """The layout stage times the winning schedule with each tile size and
+    precision and returns the pick; a single-valued layout grid returns
+    exactly that layout, and the pick certifies the book."""
+    import torch
+    from paper_2606_23367_amd.solver import Solver, to_device
+    from paper_2606_23367_amd.tune import autotune
+    uni, book = make_config("c3", 8, N=2000, M=40, k=16)
+    P = to_device(uni, book)
+    s = Solver(0)
+    grid = dict(rho=(3.0, 10.0), alpha=(1.8,), check_every=(50,), polish_rounds=(8, 16))
+    cfg = autotune(P, solver=s, sample=16, grid=grid,
+                   layouts=dict(tile_rows=(0, 2), precision=(1, 0)))
+    assert cfg["tile_rows"] in (0, 2) and cfg["precision"] in (0, 1)
+    assert cfg["polish_rounds"] in (8, 16)
+    fixed = autotune(P, solver=s, sample=16, grid=grid,
+                     layouts=dict(tile_rows=(1,), precision=(0,)))
+    assert fixed["tile_rows"] == 1 and fixed["precision"] == 0
+    out = s.solve(P, **cfg)
+    torch.cuda.synchronize()
+    assert int((out["status"] == 0).sum().item()) == book.m
+
+
 @pytest.mark.parametrize("precision", [0, 1])
 def test_precisions_agree(precision):
     """float32 and bf16-split contractions both certify every account and
