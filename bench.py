@@ -239,7 +239,8 @@ BURDEN = (
     ("B4 + account exclusions", dict(kappa=1e-3, elig=(0.3, 1.0), **_B3)),
     ("B5 + tax lots", dict(kappa=1e-3, elig=(0.3, 1.0), tax=True, **_B3)),
 )
-BURDEN_GRID = dict(rho=(0.3, 1.0, 3.0, 10.0), alpha=(1.8,), check_every=(25, 50))
+BURDEN_GRID = dict(rho=(0.3, 1.0, 3.0, 10.0), alpha=(1.8,), check_every=(25, 50),
+                   polish_rounds=(4, 16))
 
 
 def burden_lane(solver, steps=3):
@@ -269,12 +270,13 @@ def burden_lane(solver, steps=3):
                 best, solved = dt, int((out["status"] == 0).sum().item())
         rows.append({"bundle": label, "ms_per_book": best * 1e3, "accounts_per_s": solved / best,
                      "certified": solved, "accounts": book.m, "rho": cfg["rho"],
-                     "check_every": cfg["check_every"]})
+                     "check_every": cfg["check_every"],
+                     "polish_rounds": cfg.get("polish_rounds")})
     return rows
 
 
 E7_GRID = dict(rho=(0.3, 1.0, 3.0, 10.0), alpha=(1.6, 1.8), check_every=(25, 50),
-               first_mult=(1, 2))
+               first_mult=(1, 2), polish_rounds=(4, 8, 16))
 
 
 def e7_lane(solver, steps=5):
@@ -506,7 +508,7 @@ def main():
     ap.add_argument("--no-lanes", action="store_true",
                     help="skip the extra reports (MFMA step, queue, warm, e7 and burden lanes): "
                          "the profiling runs")
-    ap.add_argument("--schedule", default="", metavar="RHO,ALPHA,CHECK[,FIRST]",
+    ap.add_argument("--schedule", default="", metavar="RHO,ALPHA,CHECK[,FIRST[,ROUNDS[,TILE]]]",
                     help="fixed ADMM schedule instead of the autotuner (profiling runs)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run 5 plain device copies of MIB MiB (the "
@@ -538,6 +540,10 @@ def main():
         parts = args.schedule.split(",")
         tuned = dict(rho=float(parts[0]), alpha=float(parts[1]), check_every=int(parts[2]),
                      first_check=int(parts[3]) if len(parts) > 3 else 0)
+        if len(parts) > 4:
+            tuned["polish_rounds"] = int(parts[4])
+        if len(parts) > 5:
+            tuned["tile_rows"] = int(parts[5])
         settings_from = "fixed on the command line"
     else:
         tu_uni, tu_book = make_config(WORKLOAD, TUNE_SEED)

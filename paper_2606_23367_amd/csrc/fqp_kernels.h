@@ -204,6 +204,9 @@ struct PolishArgs {
   double* gpart;             // [m][n_rb][4] its per-block reductions
 };
 hipError_t launch_polish_solve(const PolishArgs& A, hipStream_t st);
+// pact / pm_act: the accounts of act / m_act that neither certified nor stalled
+hipError_t launch_polish_list(const int* m_act, const int* act, const int32_t* pstate, int* pact,
+                              int* pm_act, hipStream_t st);
 size_t polish_wk_stride(int k, int G);
 int polish_row_blocks(int n);
 

@@ -1092,7 +1092,8 @@ __global__ __launch_bounds__(kPTC) void polish_check_kernel(PolishArgs A, fqp_re
     const int ncol = G + 3;
     const double* nul = wk_of(A, a).nul;
     const double thr = 0.01 * A.eps_comp * scale;
-    for (int sweep = 0; sweep < 2 && nd > 0; ++sweep) {
+    // (a second sweep only matters when directions interact: nd > 1)
+    for (int sweep = 0; sweep < (nd > 1 ? 2 : 1) && nd > 0; ++sweep) {
       for (int q = 0; q < nd; ++q) {
         const double* nv = nul + q * ncol;
         // column of each multiplier inside eta = (-nu, bands..., lam_cap)
@@ -1416,5 +1417,50 @@ hipError_t launch_polish_check_r(const PolishArgs& A, const fqp_result& R, int f
 }
 
 int polish_row_blocks(int n) { return (n + kGbRows - 1) / kGbRows; }
+
+// The accounts of the active list still refining their pattern (neither
+// certified nor stalled in this pass), in list order: the later rounds of a
+// pass run on this list, so that their grids (the gradient base above all,
+// which works on groups of accounts) cover only those accounts.
+__global__ __launch_bounds__(1024) void polish_list_kernel(const int* m_act, const int* act,
+                                                           const int32_t* pstate, int* pact,
+                                                           int* pm_act) {
+  __shared__ int s_wc[16];
+  __shared__ int s_base;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int m = *m_act;
+  if (tid == 0) s_base = 0;
+  __syncthreads();
+  for (int b0 = 0; b0 < m; b0 += 1024) {
+    const int slot = b0 + tid;
+    int keep = 0, a = -1;
+    if (slot < m) {
+      a = act[slot];
+      const int32_t* ps = pstate + (size_t)a * kPStateStride;
+      keep = !(ps[PS_DONE] || ps[PS_STALL]);
+    }
+    const unsigned long long mk = __ballot(keep);
+    if (lane == 0) s_wc[wv] = __popcll(mk);
+    __syncthreads();
+    int off = s_base + __popcll(mk & ((lane == 0) ? 0ull : (~0ull >> (64 - lane))));
+    for (int q = 0; q < wv; ++q) off += s_wc[q];
+    if (keep) pact[off] = a;
+    __syncthreads();
+    if (tid == 0) {
+      int t = 0;
+      for (int q = 0; q < 16; ++q) t += s_wc[q];
+      s_base += t;
+    }
+    __syncthreads();
+  }
+  if (tid == 0) *pm_act = s_base;
+}
+
+hipError_t launch_polish_list(const int* m_act, const int* act, const int32_t* pstate, int* pact,
+                              int* pm_act, hipStream_t st) {
+  hipLaunchKernelGGL(polish_list_kernel, dim3(1), dim3(1024), 0, st, m_act, act, pstate, pact,
+                     pm_act);
+  return hipGetLastError();
+}
 
 }  // namespace fqp

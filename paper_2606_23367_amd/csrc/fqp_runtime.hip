@@ -590,6 +590,8 @@ extern "C" fqp_error fqp_solve_batch(fqp_handle* h, const fqp_universe* U, const
   WS(wk, double, "polish_wk", (size_t)m * wks);
   WS(mult, double, "mult", (size_t)m * (2 + G));
   WS(gbase, double, "gbase", (size_t)m * n);
+  WS(pact, int, "polish_act", (size_t)m);
+  WS(pm_act, int, "polish_m_act", 1);
   WS(pstate, int32_t, "pstate", (size_t)m * kPStateStride);
   WS(pcount, int32_t, "pcount", 2);
   const int n_rb = polish_row_blocks(n);
@@ -881,8 +883,15 @@ extern "C" fqp_error fqp_solve_batch(fqp_handle* h, const fqp_universe* U, const
     pa.max_prop = 16;
     for (int r = 0; r < S.polish_rounds; ++r) {
       pa.first_round = (r == 0);
-      HIP_CHECK(launch_polish_solve(pa, st));
-      HIP_CHECK(launch_polish_check_r(pa, *R, 0, st));
+      // later rounds: only the accounts still refining
+      PolishArgs pr = pa;
+      if (r > 0) {
+        HIP_CHECK(launch_polish_list(m_act, act, pstate, pact, pm_act, st));
+        pr.act = pact;
+        pr.m_act = pm_act;
+      }
+      HIP_CHECK(launch_polish_solve(pr, st));
+      HIP_CHECK(launch_polish_check_r(pr, *R, 0, st));
       h->stats.polish_calls += 1;
     }
     hipLaunchKernelGGL(compact_kernel, dim3(1), dim3(256), 0, st, m, R->status, act, m_act);

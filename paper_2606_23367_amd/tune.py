@@ -32,7 +32,7 @@ import torch
 from .solver import DeviceProblem, Solver, subset
 
 DEFAULT_GRID = dict(rho=(1.0, 3.0, 6.0, 8.0, 10.0, 14.0, 30.0), alpha=(1.6, 1.8),
-                    check_every=(50, 100), first_mult=(1, 2), polish_rounds=(8, 16, 24))
+                    check_every=(50, 100), first_mult=(1, 2, 3), polish_rounds=(8, 16, 24))
 # layouts tried for the winning schedule: tile_rows (in 128-row chunks; 0 =
 # from the occupancy) x precision (1 = bf16-split, 0 = float32 MFMA)
 DEFAULT_LAYOUTS = dict(tile_rows=(0, 1, 2, 4), precision=(1, 0))
