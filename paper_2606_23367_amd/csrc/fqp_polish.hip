@@ -863,8 +863,7 @@ __global__ __launch_bounds__(kPT) void polish_solve_kernel(PolishArgs A) {
       for (int p = 0; p < nc; ++p) v -= Xs[t * ncol + p] * wk.eta[p];
       w[flist[t]] = v;
     }
-    return;
-  }
+  } else {
   // sol = Y[:, rhs] - Y[:, C] eta
   for (int j = tid; j < k; j += kPT) {
     double s = wk.Y[j * ncol + nc];
@@ -897,31 +896,20 @@ __global__ __launch_bounds__(kPT) void polish_solve_kernel(PolishArgs A) {
     if (cap_on) ct += sgn * wk.eta[col];
     w[i] = (rhs - ct - bs) / (gam * (double)A.d[i]);
   }
-}
-
-// ---------------------------------------------------------------------------
-// polish_sums: y = F B^T w and group sums of the polished w over its
-// nonzero rows (free list and nonzero fixed list), one workgroup per account
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kPTC) void polish_sums_kernel(PolishArgs A, int final_pass) {
-  extern __shared__ float sBrow[];        // [64][k + 1] staged B rows
-  __shared__ double s_sw[64];
-  __shared__ int s_si[64];
-  const int k = A.k, G = A.G, n = A.n;
-  const int slot = blockIdx.x;
-  if (slot >= *A.m_act) return;
-  const int a = A.act[slot];
-  const int* ps = A.pstate + (size_t)a * kPStateStride;
-  if (ps[PS_DONE] || (ps[PS_STALL] && !final_pass)) return;
-  const int tid = threadIdx.x;
-  const int32_t* flist = A.flist + (size_t)a * n;
-  const double* w = A.wout + (size_t)a * n;
-  double ys = 0.0, gs = 0.0;
-  list_sums(A, flist, n, ps[PS_NF], 0, w, sBrow, s_sw, s_si, ys, gs);
-  list_sums(A, flist, n, ps[PS_NX], 1, w, sBrow, s_sw, s_si, ys, gs);
-  const Wk wk = wk_of(A, a);
-  if (tid < k) wk.yF[tid] = ys * (double)A.f[tid];
-  if (tid < G) wk.gsum[tid] = gs;
+  }                                       // factor-space path
+  // ---- y = F B^T w and the row sums of the polished w (nonzero rows), for
+  // the gradient base and the certification: the fixed rows' parts from
+  // above plus the free rows' --------------------------------------------
+  __syncthreads();
+  {
+    double ys = 0.0, gs = 0.0;
+    float* sB = reinterpret_cast<float*>(Kf);          // the solve is done with it
+    double* swv = stg;
+    int* siv = reinterpret_cast<int*>(stg + 64);
+    list_sums(A, flist, n, nF, 0, w, sB, swv, siv, ys, gs);
+    if (tid < k) wk.yF[tid] = (wk.yX[tid] + ys) * (double)A.f[tid];
+    if (tid < G) wk.gsum[tid] = s_gfix[tid] + gs;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1055,7 +1043,7 @@ __global__ __launch_bounds__(kPTC) void polish_check_kernel(PolishArgs A, fqp_re
   __shared__ int s_bad, s_done;
   if (tid == 0) { s_bad = 0; s_done = 0; }
 
-  // group sums (from polish_sums) and the reductions of polish_gbase
+  // row sums (from the solve) and the reductions of polish_gbase
   __syncthreads();                        // flags above are initialised
   const Wk wkc = wk_of(A, a);
   for (int g = tid; g < G; g += kPTC) s_gs[g] = wkc.gsum[g];
@@ -1401,16 +1389,9 @@ hipError_t launch_polish_solve(const PolishArgs& A, hipStream_t st) {
 
 hipError_t launch_polish_check_r(const PolishArgs& A, const fqp_result& R, int final_pass,
                                  hipStream_t st) {
-  const size_t smem = sizeof(float) * 64 * (size_t)(A.k + 1);
-  hipError_t e = hipFuncSetAttribute((const void*)polish_sums_kernel,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(polish_sums_kernel, dim3(A.m_total), dim3(kPTC), smem, st, A, final_pass);
-  e = hipGetLastError();
-  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(polish_gbase_kernel, dim3(A.n_rb, (A.m_total + kGbAcc - 1) / kGbAcc),
                      dim3(256), 0, st, A, final_pass);
-  e = hipGetLastError();
+  hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(polish_check_kernel, dim3(A.m_total), dim3(kPTC), 0, st, A, R, final_pass);
   return hipGetLastError();
