@@ -564,7 +564,8 @@ __global__ __launch_bounds__(256, 3) void iter_kernel_bf(IterArgs A) {
       for (int r = 0; r < 16; ++r) X[r] = 0.f;
 #pragma unroll
       for (int s = 0; s < KS; ++s) {
-        const size_t o = (size_t)row * kp + 16 * s + 8 * hi;
+        // the wave's 32 rows x 16 columns in MFMA operand order: 1 KB
+        const size_t o = ((size_t)(row_base >> 5) * KS + s) * 512 + (size_t)(hi * 32 + l32) * 8;
         const bf16x8 bH = *reinterpret_cast<const bf16x8*>(bh + o);
         const bf16x8 bL = *reinterpret_cast<const bf16x8*>(bl + o);
         const bf16x8 pH = *reinterpret_cast<const bf16x8*>(PsH + l32 * PS + 16 * s + 8 * hi);
@@ -615,7 +616,9 @@ __global__ __launch_bounds__(256, 3) void iter_kernel_bf(IterArgs A) {
         }
 #pragma unroll
         for (int c = 0; c < NCH; ++c) {
-          const size_t o = (size_t)(32 * c + l32) * A.npad + row_base + 16 * s + 8 * hi;
+          // 16 rows x 32 columns in MFMA operand order: 1 KB
+          const size_t o = ((size_t)((row_base >> 4) + s) * NCH + c) * 512 +
+                           (size_t)(hi * 32 + l32) * 8;
           const bf16x8 bH = *reinterpret_cast<const bf16x8*>(bth + o);
           const bf16x8 bL = *reinterpret_cast<const bf16x8*>(btl + o);
           T[c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aH, bH, T[c], 0, 0, 0);
@@ -649,11 +652,18 @@ __global__ __launch_bounds__(256, 3) void iter_kernel_bf(IterArgs A) {
   }
 }
 
-// hi/lo bf16 copies of B~: row-major [npad][kp] and column-major [kp][npad],
-// rows n..npad-1 zero
+// hi/lo bf16 copies of B~ (rows n..npad-1 zero), each in the operand order
+// of one pass's MFMA, so that a wave's operand load is 1 KB of contiguous
+// memory (64 lanes x 8 bf16) instead of 16 bytes from each of 32 rows or
+// columns:
+//   bh / bl (PROJECT, B operand: lane = row, 8 consecutive columns):
+//     [npad / 32 row blocks][kp / 16 column steps][hi][l32 = row][8 columns]
+//   bth / btl (CONTRACT, B operand: lane = column, 8 consecutive rows):
+//     [npad / 16 row steps][kp / 32 column blocks][hi][l32 = column][8 rows]
 __global__ void split_bt_kernel(int n, int npad, int kp, const float* Bt, uint16_t* bh,
                                 uint16_t* bl, uint16_t* bth, uint16_t* btl) {
   const size_t total = (size_t)npad * kp;
+  const int ks = kp >> 4, nch = kp >> 5;
   for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
        e += (size_t)gridDim.x * blockDim.x) {
     const int row = (int)(e / kp), col = (int)(e % kp);
@@ -661,10 +671,14 @@ __global__ void split_bt_kernel(int n, int npad, int kp, const float* Bt, uint16
     __bf16 h, l;
     split_bf16(x, h, l);
     const uint16_t hb = __builtin_bit_cast(uint16_t, h), lb = __builtin_bit_cast(uint16_t, l);
-    bh[e] = hb;
-    bl[e] = lb;
-    bth[(size_t)col * npad + row] = hb;
-    btl[(size_t)col * npad + row] = lb;
+    const size_t ep = (((size_t)(row >> 5) * ks + (col >> 4)) * 64 + ((col >> 3) & 1) * 32 +
+                       (row & 31)) * 8 + (col & 7);
+    const size_t ec = (((size_t)(row >> 4) * nch + (col >> 5)) * 64 + ((row >> 3) & 1) * 32 +
+                       (col & 31)) * 8 + (row & 7);
+    bh[ep] = hb;
+    bl[ep] = lb;
+    bth[ec] = hb;
+    btl[ec] = lb;
   }
 }
 

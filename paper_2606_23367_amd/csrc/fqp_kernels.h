@@ -26,10 +26,10 @@ struct IterArgs {
   const float* tax_slope;    // [nnz_t][4]
   const float4* hold_rec;    // [nnz_h][2]: {w0, b1, b2, b3}, {s0, s1, s2, s3}; b1 < 0: no lots
   int npad;                  // rows of the bf16 copies of B~ (n padded to whole chunks)
-  const uint16_t* bt_hi;     // [npad][kp] bf16 hi part of B~ (row-major)
-  const uint16_t* bt_lo;     // [npad][kp] bf16 lo part
-  const uint16_t* btt_hi;    // [kp][npad] bf16 hi part (column-major)
-  const uint16_t* btt_lo;    // [kp][npad] bf16 lo part
+  const uint16_t* bt_hi;     // npad x kp bf16 hi part of B~, PROJECT operand order
+  const uint16_t* bt_lo;     // its lo part
+  const uint16_t* btt_hi;    // npad x kp bf16 hi part of B~, CONTRACT operand order
+  const uint16_t* btt_lo;    // its lo part
   const float* pp;           // [m][kp]
   const float* par;          // [m][kNPar]
   float* par_rw;             // same array, written by the cap kernel
