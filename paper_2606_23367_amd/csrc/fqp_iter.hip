@@ -478,7 +478,7 @@ __global__ __launch_bounds__(256, 3) void iter_kernel_bf(IterArgs A) {
   constexpr int kX = bf_lds_floats<NCH, MODE>();
   extern __shared__ float smem[];
   float* Xs = smem;
-  float4* Acc = reinterpret_cast<float4*>(Xs + kX);    // [32][2] as in iter_kernel
+  float4* Acc = reinterpret_cast<float4*>(Xs + kX);    // [32] PROJECT constants (room for [32][2])
   int* Aid = (int*)(Acc + 2 * kTM);     // [32]
   int* Ao = Aid + kTM;                  // [32] a * n
 
@@ -500,15 +500,13 @@ __global__ __launch_bounds__(256, 3) void iter_kernel_bf(IterArgs A) {
     const int a = (s < m_act) ? A.act[s] : -1;
     Aid[tid] = a;
     Ao[tid] = (a >= 0) ? a * n : 0;        // m n < 2^31 (checked by the runtime)
-    // PROJECT: {rho, -, gamma, -}, {-, -, nu, alpha}
-    float4 q0 = make_float4(1.f, 1.f, 0.f, 0.f), q1 = make_float4(0.f, 0.f, 0.f, 0.f);
+    // PROJECT: {rho, gamma, nu, alpha} of the account
+    float4 q = make_float4(1.f, 0.f, 0.f, 0.f);
     if (MODE == MODE_PROJECT && a >= 0) {
       const float* p = A.par + (size_t)a * kNPar;
-      q0 = make_float4(p[P_RHO], 0.f, p[P_GAMMA], 0.f);
-      q1 = make_float4(0.f, 0.f, p[P_NU], p[P_ALPHA]);
+      q = make_float4(p[P_RHO], p[P_GAMMA], p[P_NU], p[P_ALPHA]);
     }
-    Acc[2 * tid] = q0;
-    Acc[2 * tid + 1] = q1;
+    Acc[tid] = q;
   }
   __syncthreads();
 
@@ -536,6 +534,14 @@ __global__ __launch_bounds__(256, 3) void iter_kernel_bf(IterArgs A) {
 #pragma unroll
     for (int r = 0; r < 16; ++r) T[c][r] = 0.f;
   const int row_begin = tm.row_begin;
+  // PROJECT: the lane's 16 accounts (MFMA output rows m = 8 (r / 4) + 4 hi +
+  // r % 4): offset a n of each, -1 for an empty slot of the tile
+  int ao[16];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int m = 8 * (r >> 2) + 4 * hi + (r & 3);
+    ao[r] = (MODE == MODE_PROJECT && Aid[m] >= 0) ? Ao[m] : -1;
+  }
 
   for (int ch = 0; ch < tm.chunks; ++ch) {
     const int r0 = row_begin + ch * kRowsPerChunk;
@@ -546,66 +552,90 @@ __global__ __launch_bounds__(256, 3) void iter_kernel_bf(IterArgs A) {
 
     if (MODE == MODE_PROJECT) {
       // w of this iterate comes from the PROX pass: no row data, no returns
-      // and no old state needed here
+      // and no old state needed here.  Every load of the chunk is issued
+      // before the first is used (an empty slot reads element 0 and drops
+      // it), so that the chunk costs one memory round trip.
       const float d_i = row_ok ? A.d[row] : 1.f;
       float w_r[16];
-      unsigned ok_bits = 0u;
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
-        const int m = 8 * (r >> 2) + 4 * hi + (r & 3);
-        w_r[r] = 0.f;
-        if (Aid[m] >= 0 && row_ok) {
-          w_r[r] = A.zs[(unsigned)(Ao[m] + row)];
-          ok_bits |= 1u << r;
-        }
+        const bool ok = ao[r] >= 0 && row_ok;
+        w_r[r] = A.zs[ok ? (unsigned)(ao[r] + row) : 0u];
       }
+      // the wave's 32 rows x 16 columns per K step in MFMA operand order: 1 KB
+      const size_t ob = (size_t)(row_base >> 5) * KS * 512 + (size_t)(hi * 32 + l32) * 8;
+      bf16x8 bH[KS], bL[KS];
+#pragma unroll
+      for (int s = 0; s < KS; ++s) {
+        bH[s] = *reinterpret_cast<const bf16x8*>(bh + ob + (size_t)s * 512);
+        bL[s] = *reinterpret_cast<const bf16x8*>(bl + ob + (size_t)s * 512);
+      }
+      // (keeps the scheduler from sinking the loads towards their uses)
+      __builtin_amdgcn_sched_barrier(0);
       floatx16 X;
 #pragma unroll
       for (int r = 0; r < 16; ++r) X[r] = 0.f;
 #pragma unroll
       for (int s = 0; s < KS; ++s) {
-        // the wave's 32 rows x 16 columns in MFMA operand order: 1 KB
-        const size_t o = ((size_t)(row_base >> 5) * KS + s) * 512 + (size_t)(hi * 32 + l32) * 8;
-        const bf16x8 bH = *reinterpret_cast<const bf16x8*>(bh + o);
-        const bf16x8 bL = *reinterpret_cast<const bf16x8*>(bl + o);
         const bf16x8 pH = *reinterpret_cast<const bf16x8*>(PsH + l32 * PS + 16 * s + 8 * hi);
         const bf16x8 pL = *reinterpret_cast<const bf16x8*>(PsL + l32 * PS + 16 * s + 8 * hi);
-        X = __builtin_amdgcn_mfma_f32_32x32x16_bf16(pH, bH, X, 0, 0, 0);
-        X = __builtin_amdgcn_mfma_f32_32x32x16_bf16(pH, bL, X, 0, 0, 0);
-        X = __builtin_amdgcn_mfma_f32_32x32x16_bf16(pL, bH, X, 0, 0, 0);
+        X = __builtin_amdgcn_mfma_f32_32x32x16_bf16(pH, bH[s], X, 0, 0, 0);
+        X = __builtin_amdgcn_mfma_f32_32x32x16_bf16(pH, bL[s], X, 0, 0, 0);
+        X = __builtin_amdgcn_mfma_f32_32x32x16_bf16(pL, bH[s], X, 0, 0, 0);
       }
+      // v' = w + alpha Delta^-1 (nu - (B~ p)_i), four accounts' constants
+      // read together
 #pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int m = 8 * (r >> 2) + 4 * hi + (r & 3);
-        if ((ok_bits >> r) & 1u) {
-          const float4 q0 = Acc[2 * m], q1 = Acc[2 * m + 1];
-          const float iDelta = __builtin_amdgcn_rcpf(q0.z * d_i + q0.x);
-          const unsigned off = (unsigned)(Ao[m] + row);
-          // v' = w + alpha Delta^-1 (nu - (B~ p)_i)
-          A.v[off] = w_r[r] + q1.w * iDelta * (q1.z - X[r]);
+      for (int g4 = 0; g4 < 4; ++g4) {
+        float4 q[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) q[j] = Acc[8 * g4 + 4 * hi + j];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int r = 4 * g4 + j;
+          if (ao[r] >= 0 && row_ok) {
+            const float iDelta = __builtin_amdgcn_rcpf(q[j].y * d_i + q[j].x);
+            A.v[(unsigned)(ao[r] + row)] = w_r[r] + q[j].w * iDelta * (q[j].z - X[r]);
+          }
         }
       }
     } else if (row_base < n) {            // uniform per wave
       // A operand straight from R' (PROX pass): lane l32 takes account
       // Aid[l32], rows row_base + 16 s + 8 hi .. + 8 (the rows past n of the
-      // last chunk are masked: R' is not written there)
+      // last chunk are masked: R' is not written there).  Both K steps' R'
+      // and B~ operands are loaded before any is used: one memory round
+      // trip per chunk.
       const int am = Aid[l32];
+      float4 x[2][2];
 #pragma unroll
       for (int s = 0; s < 2; ++s) {
         const int rb = row_base + 16 * s + 8 * hi;
-        float rv[8];
+        // (an empty slot of the tile reads account 0's rows and drops them)
+        const float4* src =
+            reinterpret_cast<const float4*>(A.rp + (size_t)(am >= 0 ? am : 0) * A.npad + rb);
+        x[s][0] = src[0];
+        x[s][1] = src[1];
+      }
+      // 16 rows x 32 columns per K step and column block in MFMA operand
+      // order: 1 KB
+      bf16x8 bH[2][NCH], bL[2][NCH];
 #pragma unroll
-        for (int j = 0; j < 8; ++j) rv[j] = 0.f;
-        if (am >= 0) {
-          const float4* src = reinterpret_cast<const float4*>(A.rp + (size_t)am * A.npad + rb);
-          const float4 x0 = src[0], x1 = src[1];
-          rv[0] = x0.x; rv[1] = x0.y; rv[2] = x0.z; rv[3] = x0.w;
-          rv[4] = x1.x; rv[5] = x1.y; rv[6] = x1.z; rv[7] = x1.w;
-          if (rb + 8 > n) {
+      for (int s = 0; s < 2; ++s)
 #pragma unroll
-            for (int j = 0; j < 8; ++j) rv[j] = (rb + j < n) ? rv[j] : 0.f;
-          }
+        for (int c = 0; c < NCH; ++c) {
+          const size_t o = ((size_t)((row_base >> 4) + s) * NCH + c) * 512 +
+                           (size_t)(hi * 32 + l32) * 8;
+          bH[s][c] = *reinterpret_cast<const bf16x8*>(bth + o);
+          bL[s][c] = *reinterpret_cast<const bf16x8*>(btl + o);
         }
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int s = 0; s < 2; ++s) {
+        const int rb = row_base + 16 * s + 8 * hi;
+        float rv[8] = {x[s][0].x, x[s][0].y, x[s][0].z, x[s][0].w,
+                       x[s][1].x, x[s][1].y, x[s][1].z, x[s][1].w};
+#pragma unroll
+        for (int j = 0; j < 8; ++j) rv[j] = (am >= 0 && rb + j < n) ? rv[j] : 0.f;
         bf16x8 aH, aL;
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
@@ -616,14 +646,9 @@ __global__ __launch_bounds__(256, 3) void iter_kernel_bf(IterArgs A) {
         }
 #pragma unroll
         for (int c = 0; c < NCH; ++c) {
-          // 16 rows x 32 columns in MFMA operand order: 1 KB
-          const size_t o = ((size_t)((row_base >> 4) + s) * NCH + c) * 512 +
-                           (size_t)(hi * 32 + l32) * 8;
-          const bf16x8 bH = *reinterpret_cast<const bf16x8*>(bth + o);
-          const bf16x8 bL = *reinterpret_cast<const bf16x8*>(btl + o);
-          T[c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aH, bH, T[c], 0, 0, 0);
-          T[c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aH, bL, T[c], 0, 0, 0);
-          T[c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aL, bH, T[c], 0, 0, 0);
+          T[c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aH, bH[s][c], T[c], 0, 0, 0);
+          T[c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aH, bL[s][c], T[c], 0, 0, 0);
+          T[c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aL, bH[s][c], T[c], 0, 0, 0);
         }
       }
     }
