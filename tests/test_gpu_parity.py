@@ -38,6 +38,20 @@ def test_small_books_match_oracle(name, over, settings, seed):
         check_account(uni, book, a, host)
 
 
+def test_large_free_set_takes_the_factor_space_polish():
+    """A wide long-short box: every asset is free at the optimum, more than
+    the 64 rows the row-space solve of the polish takes, so the polish
+    solves in factor space."""
+    uni, book = make_config("c1", 3, N=400, M=4)
+    book.lb[:] = -1.0
+    book.ub[:] = 1.0
+    print("case c1 N=400 long-short", flush=True)
+    host, st = run_gpu(uni, book, rho=0.05)
+    for a in range(book.m):
+        check_account(uni, book, a, host)
+    assert all(np.sum(np.abs(host["w"][a]) > 1e-9) > 64 for a in range(book.m))
+
+
 def test_headline_book_sampled():
     """500 accounts x N=10,000, k=80: every account certified; a sample
     checked against the oracle one by one."""
