@@ -809,6 +809,7 @@ __global__ __launch_bounds__(kCapT, 8) void prox_kernel(IterArgs A, int zmode) {
   __shared__ uint32_t s_ew[kCapQ * kCapT / 32], s_hw[kCapQ * kCapT / 32];
   __shared__ int s_hp[kCapQ * kCapT / 32];
   __shared__ float4 s_rec[2 * kCapT];    // tax records of the first kCapT held rows
+  __shared__ float s_hz[kCapH];          // z of held record j at the final multiplier
   const int slot = blockIdx.x;
   if (slot >= *A.m_act) return;
   const int a = A.act[slot];
@@ -938,36 +939,43 @@ __global__ __launch_bounds__(kCapT, 8) void prox_kernel(IterArgs A, int zmode) {
   const float gam = par[P_GAMMA], alpha = par[P_ALPHA];
   const float th = (kap + lam) * irho;
   const ProxRows o = prox_rows(A, a);
-#pragma unroll
-  for (int q = 0; q < Q; ++q) {
-    const int i = q * kCapT + tid;
-    // held rows are written below, by the thread that keeps them (the row
-    // class comes from the LDS words again: box_bits would have to live
-    // through the search in a register)
-    if (q * kCapT < n && i < n && !((s_hw[i >> 5] >> (i & 31)) & 1u)) {
-      const bool in_box = (s_ew[i >> 5] >> (i & 31)) & 1u;
-      float z = fminf(vr[q] + th, fmaxf(0.f, vr[q] - th));
-      z = in_box ? fminf(fmaxf(z, lbp), ubp) : 0.f;
-      prox_out(o, zmode, i, vr[q], z, A.d[i], rho, gam, alpha);
-    }
-    // one row's loads at a time: issuing all of them ahead would not fit in
-    // the registers two accounts per compute unit leave
-    __builtin_amdgcn_sched_barrier(0);
-  }
+  // held rows first: their z goes to LDS, so that every row's outputs are
+  // written below in row order (whole lines, not one word apart from the
+  // rest of its line)
   if (tid < H) {
     RowInfo ri;
     held_row(tid, ri);
-    const float z = prox_row(ri, hv, th, irho, nullptr);
-    const int i = s_hrow[tid] >= 0 ? s_hrow[tid] : ~s_hrow[tid];
-    prox_out(o, zmode, i, hv, z, A.d[i], rho, gam, alpha);
+    s_hz[tid] = prox_row(ri, hv, th, irho, nullptr);
   }
   if (H > kCapT && tid + kCapT < H) {
     RowInfo ri;
     held_row(tid + kCapT, ri);
-    const float v = s_hv[tid + kCapT];
-    const float z = prox_row(ri, v, th, irho, nullptr);
-    const int i = s_hrow[tid + kCapT] >= 0 ? s_hrow[tid + kCapT] : ~s_hrow[tid + kCapT];
-    prox_out(o, zmode, i, v, z, A.d[i], rho, gam, alpha);
+    s_hz[tid + kCapT] = prox_row(ri, s_hv[tid + kCapT], th, irho, nullptr);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const int i = q * kCapT + tid;
+    if (q * kCapT < n && i < n) {
+      // (the row class comes from the LDS words again: box_bits would have
+      // to live through the search in a register)
+      const uint32_t hw = s_hw[i >> 5];
+      const int b = i & 31;
+      float v = vr[q], z;
+      if ((hw >> b) & 1u) {
+        const int j = s_hp[i >> 5] + popc_below(hw, b);
+        v = s_hv[j];
+        z = s_hz[j];
+      } else {
+        const bool in_box = (s_ew[i >> 5] >> b) & 1u;
+        z = fminf(vr[q] + th, fmaxf(0.f, vr[q] - th));
+        z = in_box ? fminf(fmaxf(z, lbp), ubp) : 0.f;
+      }
+      prox_out(o, zmode, i, v, z, A.d[i], rho, gam, alpha);
+    }
+    // one row's loads at a time: issuing all of them ahead would not fit in
+    // the registers two accounts per compute unit leave
+    __builtin_amdgcn_sched_barrier(0);
   }
 }
 
