@@ -202,6 +202,11 @@ struct PolishArgs {
   int max_prop;              // a failed pattern with more proposals stops refining
   int n_rb;                  // row blocks of the gradient-base pass
   double* gpart;             // [m][n_rb][4] its per-block reductions
+  int n_sb;                  // row blocks of the other row passes
+  int32_t* fseg;             // [m][n] per-block free / nonzero fixed rows
+  double* rpart;             // [m][n_sb][polish_rpart_stride] pattern partials
+  double* spart;             // [m][n_sb][4] null-direction sweep partials
+  double* cpart;             // [m][n_sb][8] diagnostic partials
 };
 hipError_t launch_polish_solve(const PolishArgs& A, hipStream_t st);
 // pact / pm_act: the accounts of act / m_act that neither certified nor stalled
@@ -209,6 +214,8 @@ hipError_t launch_polish_list(const int* m_act, const int* act, const int32_t* p
                               int* pm_act, hipStream_t st);
 size_t polish_wk_stride(int k, int G);
 int polish_row_blocks(int n);
+int polish_pass_blocks(int n);
+int polish_rpart_stride(int k, int G);
 
 // ---- KKT adjoint (float64) ---------------------------------------------------
 struct AdjArgs {

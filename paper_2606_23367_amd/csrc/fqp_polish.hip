@@ -35,7 +35,9 @@ namespace fqp {
 
 enum PState {
   PS_CAP = 0, PS_NF, PS_NX, PS_NC, PS_DONE, PS_ROUNDS,
-  PS_BACT0, PS_BACT1, PS_BUP0, PS_BUP1, PS_STALL, PS_ND, PS_SIG, kNPState
+  PS_BACT0, PS_BACT1, PS_BUP0, PS_BUP1, PS_STALL, PS_ND, PS_SIG,
+  PS_BLOCK,            // the fixed row a null-direction step releases (row * 16 + code), or -1
+  kNPState
 };
 static_assert(kNPState <= kPStateStride, "polish bookkeeping does not fit");
 
@@ -112,6 +114,54 @@ __device__ __forceinline__ RowData row_data(const PolishArgs& A, int a, int i, f
     r.s0 = r1.x; r.s1 = r1.y; r.s2 = r1.z; r.s3 = r1.w;
   }
   return r;
+}
+
+// row_data of U rows (indices clamped into the account, so every load is
+// in bounds): the first-level loads of all U rows (the eligibility and
+// holding words, the word's held prefix, per-asset bounds) are issued before
+// the held records they index, so a thread waits for two memory round trips
+// per U rows instead of two per row
+template <int U>
+__device__ __forceinline__ void row_data_n(const PolishArgs& A, int a, const int (&ii)[U],
+                                           float lbf, float ubf, RowData (&r)[U]) {
+  uint32_t ew[U], hw[U];
+  int pre[U];
+  float lb[U], ub[U];
+  const int hp = A.hold_ptr[a];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int i = min(ii[u], A.n - 1);
+    const size_t wi = (size_t)a * A.W + (i >> 5);
+    ew[u] = A.elig ? A.elig[wi] : ~0u;
+    hw[u] = A.hold[wi];
+    pre[u] = A.hold_pre[wi];
+    lb[u] = A.lbv ? A.lbv[(size_t)a * A.n + i] : lbf;
+    ub[u] = A.ubv ? A.ubv[(size_t)a * A.n + i] : ubf;
+  }
+  float4 r0[U], r1[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int b = min(ii[u], A.n - 1) & 31;
+    r0[u] = make_float4(0.f, 0.f, 0.f, 0.f);
+    r1[u] = make_float4(0.f, 0.f, 0.f, 0.f);
+    if ((hw[u] >> b) & 1u) {
+      const int idx = hp + pre[u] + popc_below(hw[u], b);
+      r0[u] = A.hold_rec[2 * idx];
+      r1[u] = A.hold_rec[2 * idx + 1];
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int b = min(ii[u], A.n - 1) & 31;
+    RowData& q = r[u];
+    q.el = (ew[u] >> b) & 1u;
+    q.lb = q.el ? lb[u] : 0.f;
+    q.ub = q.el ? ub[u] : 0.f;
+    q.w0 = r0[u].x;
+    q.taxed = r0[u].y > 0.f;
+    q.b1 = r0[u].y; q.b2 = r0[u].z; q.b3 = r0[u].w;
+    q.s0 = r1[u].x; q.s1 = r1[u].y; q.s2 = r1[u].z; q.s3 = r1[u].w;
+  }
 }
 
 __device__ __forceinline__ void make_geom(Geom& g, float kap, bool phi, const RowData& r) {
@@ -270,37 +320,110 @@ __device__ T bmax(T v, T* sh) {
   return r;
 }
 
-// Sums over a list of rows (LDS-staged, 64 rows at a time):
-//   ys[j] += sum_t B[i_t][j] w[i_t]   (thread j < k)
-//   gs[g] += sum_t (row g at i_t) w[i_t]   (thread g < G: band rows by
-//            label, halfspace rows from the columns k + g of B~)
-// Entries are list[t] (rev = 0) or list[n - 1 - t] (rev = 1), t < cnt.
-__device__ void list_sums(const PolishArgs& A, const int32_t* list, int n, int cnt, int rev,
-                          const double* w, float* sB, double* sw, int* si, double& ys,
-                          double& gs) {
-  const int k = A.k, G = A.G, tid = threadIdx.x;
-  for (int c0 = 0; c0 < cnt; c0 += 64) {
-    const int rows = min(64, cnt - c0);
-    __syncthreads();
-    if (tid < rows) {
-      const int i = rev ? list[n - 1 - (c0 + tid)] : list[c0 + tid];
-      si[tid] = i;
-      sw[tid] = w[i];
-    }
-    __syncthreads();
-    for (int e = tid; e < rows * k; e += (int)blockDim.x) {
-      const int rr = e / k, j = e % k;
-      sB[rr * (k + 1) + j] = A.Bt[(size_t)si[rr] * A.kp + j];
-    }
-    __syncthreads();
-    if (tid < k)
-      for (int rr = 0; rr < rows; ++rr) ys += (double)sB[rr * (k + 1) + tid] * sw[rr];
-    if (tid < A.Gl)
-      for (int rr = 0; rr < rows; ++rr) gs += (A.group[si[rr]] == tid) ? sw[rr] : 0.0;
-    else if (tid < G)             // halfspace rows: the columns k + tid of B~
-      for (int rr = 0; rr < rows; ++rr)
-        gs += (double)A.Bt[(size_t)si[rr] * A.kp + k + tid] * sw[rr];
+// NS block sums and NM block maxima at once: one pair of barriers for all
+// (sh: (NS + NM) x nwaves doubles); every thread gets the results
+template <int NS, int NM>
+__device__ __forceinline__ void bred(double (&sv)[NS], double (&mv)[NM], double* sh) {
+  const int nw = (int)(blockDim.x >> 6), wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) {
+#pragma unroll
+    for (int q = 0; q < NS; ++q) sv[q] += __shfl_xor(sv[q], o, 64);
+#pragma unroll
+    for (int q = 0; q < NM; ++q) mv[q] = fmax(mv[q], __shfl_xor(mv[q], o, 64));
   }
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+    for (int q = 0; q < NS; ++q) sh[q * nw + wv] = sv[q];
+#pragma unroll
+    for (int q = 0; q < NM; ++q) sh[(NS + q) * nw + wv] = mv[q];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < NS; ++q) {
+    double r = sh[q * nw];
+    for (int w = 1; w < nw; ++w) r += sh[q * nw + w];
+    sv[q] = r;
+  }
+#pragma unroll
+  for (int q = 0; q < NM; ++q) {
+    double r = sh[(NS + q) * nw];
+    for (int w = 1; w < nw; ++w) r = fmax(r, sh[(NS + q) * nw + w]);
+    mv[q] = r;
+  }
+}
+
+// row_coef / rows_dot with the row's label already loaded (grp, unused
+// without band rows)
+__device__ __forceinline__ double row_coef_g(const PolishArgs& A, int i, int grp, int g) {
+  return g < A.Gl ? (grp == g ? 1.0 : 0.0) : (double)A.Bt[(size_t)i * A.kp + A.k + g];
+}
+__device__ __forceinline__ double rows_dot_g(const PolishArgs& A, int i, int grp,
+                                            const double* x) {
+  double s = A.Gl ? x[grp] : 0.0;
+  for (int g = A.Gl; g < A.G; ++g) s += (double)A.Bt[(size_t)i * A.kp + A.k + g] * x[g];
+  return s;
+}
+
+// Sums over a list of rows:
+//   ys[j] = sum_t B~[i_t][j] w[i_t]       (thread j < k)
+//   gs[g] = sum_t B~[i_t][k + g] w[i_t]   (thread g < G: the one-hot band
+//           columns and the halfspace columns of B~)
+// Entries are list[t] (rev = 0) or list[n - 1 - t] (rev = 1), t < cnt.
+// Each wave takes kLU entries at a time, every row loaded before the first
+// is used and the next entries' indices fetched meanwhile; its lanes are the
+// columns (lane, lane + 64, lane + 128).  The waves' partials meet in red
+// (nwaves x (k + G) doubles of LDS), summed in wave order.
+constexpr int kLU = 8;
+__device__ void list_sums(const PolishArgs& A, const int32_t* list, int n, int cnt, int rev,
+                          const double* w, double* red, double& ys, double& gs) {
+  const int k = A.k, G = A.G, kg = k + G, tid = threadIdx.x;
+  const int lane = tid & 63, wv = tid >> 6, nw = (int)(blockDim.x >> 6);
+  const bool on0 = lane < kg, on1 = lane + 64 < kg, on2 = lane + 128 < kg;
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+  auto index = [&](int t) {
+    t = min(t, cnt - 1);
+    return rev ? list[n - 1 - t] : list[t];
+  };
+  int ix[kLU];
+  if (kLU * wv < cnt) {
+#pragma unroll
+    for (int u = 0; u < kLU; ++u) ix[u] = index(kLU * wv + u);
+  }
+  for (int t0 = kLU * wv; t0 < cnt; t0 += kLU * nw) {
+    double wt[kLU];
+    float b0[kLU], b1[kLU], b2[kLU];
+#pragma unroll
+    for (int u = 0; u < kLU; ++u) {
+      const float* row = A.Bt + (size_t)ix[u] * A.kp;
+      wt[u] = w[ix[u]];
+      b0[u] = on0 ? row[lane] : 0.f;
+      b1[u] = on1 ? row[lane + 64] : 0.f;
+      b2[u] = on2 ? row[lane + 128] : 0.f;
+    }
+    const int t1 = t0 + kLU * nw;
+    if (t1 < cnt) {
+#pragma unroll
+      for (int u = 0; u < kLU; ++u) ix[u] = index(t1 + u);
+    }
+#pragma unroll
+    for (int u = 0; u < kLU; ++u) {
+      const double wu = (t0 + u < cnt) ? wt[u] : 0.0;   // the tail repeats the last entry
+      s0 += (double)b0[u] * wu;
+      s1 += (double)b1[u] * wu;
+      s2 += (double)b2[u] * wu;
+    }
+  }
+  __syncthreads();                       // red may alias the caller's staging
+  if (on0) red[wv * kg + lane] = s0;
+  if (on1) red[wv * kg + lane + 64] = s1;
+  if (on2) red[wv * kg + lane + 128] = s2;
+  __syncthreads();
+  if (tid < k)
+    for (int q = 0; q < nw; ++q) ys += red[q * kg + tid];
+  if (tid < G)
+    for (int q = 0; q < nw; ++q) gs += red[q * kg + k + tid];
   __syncthreads();
 }
 
@@ -323,13 +446,32 @@ __device__ double* small_free_solve(const PolishArgs& A, int a, int nF, const in
   double* Vs = Hs + kSmallF * kSmallF;               // [nF][ncol]
   double* Xs = Vs + kSmallF * ncol;                  // [nF][ncol]
   double* fs = Xs + kSmallF * ncol;                  // [k]
-  float* Bs = reinterpret_cast<float*>(fs + k);      // [nF][k]
-  // stage the free rows' B, f and the constraint / rhs rows
+  double* fys = fs + k;                              // [k] F yX
+  double* crs = fys + k;                             // [nF] b_r . F yX
+  float* Bs = reinterpret_cast<float*>(crs + kSmallF);   // [nF][k]
+  // stage the free rows' B, f and F yX
   for (int e = tid; e < nF * k; e += kPT) {
     const int r = e / k, j = e % k;
     Bs[e] = A.Bt[(size_t)flist[r] * A.kp + j];
   }
-  for (int j = tid; j < k; j += kPT) fs[j] = (double)A.f[j];
+  for (int j = tid; j < k; j += kPT) {
+    fs[j] = (double)A.f[j];
+    fys[j] = wk.Fy[j];
+  }
+  __syncthreads();
+  // b_r . F yX: one wave per free row, its lanes over the factors
+  {
+    const int lane = tid & 63, wv = tid >> 6;
+    for (int r = wv; r < nF; r += kPW) {
+      double c = 0.0;
+      for (int j = lane; j < k; j += 64) c += (double)Bs[r * k + j] * fys[j];
+#pragma unroll
+      for (int o = 32; o >= 1; o >>= 1) c += __shfl_xor(c, o, 64);
+      if (lane == 0) crs[r] = c;
+    }
+  }
+  __syncthreads();
+  // the constraint / rhs rows
   double sgn_w0 = 0.0;
   for (int r = tid; r < nF; r += kPT) {
     const int i = flist[r];
@@ -338,8 +480,7 @@ __device__ double* small_free_solve(const PolishArgs& A, int a, int nF, const in
     make_geom(g, kap, phi, rd);
     double slope, sgn;
     piece_slope(g, code[i] >> 1, slope, sgn);
-    double cross = 0.0;
-    for (int j = 0; j < k; ++j) cross += (double)A.Bt[(size_t)i * A.kp + j] * wk.Fy[j];
+    const double cross = crs[r];
     double* v = Vs + r * ncol;
     v[0] = 1.0;
     int col = 1;
@@ -402,6 +543,192 @@ __device__ double* small_free_solve(const PolishArgs& A, int a, int nF, const in
   return Xs;
 }
 
+// ---------------------------------------------------------------------------
+// Row-block passes: an account's rows are split into blocks of kRB rows, one
+// workgroup each, so that a pass over an account's rows spreads over many
+// compute units (with few accounts left refining, a pass confined to one
+// workgroup is bound by that unit's instruction issue).  Per-block results
+// go to [m][n_sb][...] partials that a per-account kernel gathers in block
+// order (deterministic).
+// ---------------------------------------------------------------------------
+constexpr int kRT = 256;                  // threads of a row-block workgroup
+constexpr int kRR = 2;                    // rows per thread
+constexpr int kRB = kRT * kRR;            // rows per block
+constexpr int kRW = kRT / 64;             // waves
+
+// polish_rows partials per (account, block): the column sums of B~ over the
+// block's nonzero fixed rows (k + G), then budget sum, turnover sum, free
+// count, nonzero-fixed count, pattern signature
+__host__ __device__ __forceinline__ int rpart_stride(int k, int G) { return k + G + 5; }
+
+// rows of block b: [b kRB, b kRB + rows_in_block)
+__device__ __forceinline__ int rows_in_block(int n, int b) { return min(kRB, n - b * kRB); }
+
+// polish_rows: (first round) the pattern of the iterate, else the
+// proposals of the last failed check adopted as the pattern; the fixed
+// rows' values; the block's free rows (front of its fseg segment, ascending)
+// and nonzero fixed rows (back of the segment, ascending from the end); the
+// partials above
+__global__ __launch_bounds__(kRT) void polish_rows_kernel(PolishArgs A) {
+  __shared__ int s_wc[kRR][kRW][2];
+  __shared__ int s_nz[kRB];
+  __shared__ double s_red[kRW * (kMaxK + kMaxG)];
+  __shared__ double s_sh[3 * kRW];
+  __shared__ unsigned s_sg[kRW];
+  const int k = A.k, G = A.G, n = A.n, tid = threadIdx.x;
+  const int b = blockIdx.x, slot = blockIdx.y;
+  if (slot >= *A.m_act) return;
+  const int a = A.act[slot];
+  const int* ps = A.pstate + (size_t)a * kPStateStride;
+  if (!A.first_round && (ps[PS_DONE] || ps[PS_STALL])) return;
+  const float* par = A.par + (size_t)a * kNPar;
+  const float lbf = par[P_LB], ubf = par[P_UB], kap = par[P_KAPPA], tauf = par[P_TAU];
+  const bool phi = (kap > 0.f) || isfinite(tauf) || (par[P_HASTAX] != 0.f);
+  int8_t* code = A.code + (size_t)a * n;
+  const int8_t* prop = A.code_next + (size_t)a * n;
+  double* w = A.wout + (size_t)a * n;
+  const int nrow = rows_in_block(n, b);
+  int32_t* seg = A.fseg + (size_t)a * n + (size_t)b * kRB;
+  const int lane = tid & 63, wv = tid >> 6;
+  const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  int ii[kRR], cc[kRR];
+  float zz[kRR];
+#pragma unroll
+  for (int u = 0; u < kRR; ++u) {
+    ii[u] = b * kRB + u * kRT + tid;
+    const int ic = min(ii[u], n - 1);
+    zz[u] = A.first_round ? A.z[(size_t)a * n + ic] : 0.f;
+    cc[u] = A.first_round ? 0 : (int)prop[ic];
+  }
+  RowData rd[kRR];
+  row_data_n<kRR>(A, a, ii, lbf, ubf, rd);
+  unsigned sig = 0u;                          // signature of the pattern
+  double sx = 0.0, sturn = 0.0;
+  unsigned long long mf[kRR], mn[kRR];
+#pragma unroll
+  for (int u = 0; u < kRR; ++u) {
+    const int i = ii[u];
+    int isfree = 0, isnz = 0;
+    if (i < n) {
+      Geom g;
+      make_geom(g, kap, phi, rd[u]);
+      int c = cc[u];
+      if (A.first_round) {
+        const float z = zz[u];
+        // at point j (the float32 value the prox lands on), else inside the
+        // piece above the inner points below z (the points ascend)
+        c = (z == g.f0) ? 0 : (g.np > 1 && z == g.f1) ? 2 : (g.np > 2 && z == g.f2) ? 4
+          : (g.np > 3 && z == g.f3) ? 6 : (g.np > 4 && z == g.f4) ? 8
+          : (g.np > 5 && z == g.f5) ? 10 : -1;
+        if (c < 0) {
+          const double zd = z;
+          const int q = (g.np > 2 && zd > g.p1 ? 1 : 0) + (g.np > 3 && zd > g.p2 ? 1 : 0) +
+                        (g.np > 4 && zd > g.p3 ? 1 : 0) + (g.np > 5 && zd > g.p4 ? 1 : 0);
+          c = (g.np == 1) ? 0 : 2 * q + 1;
+          if (g.np > 1 && zd <= g.p0) c = 0;
+          if (g.np > 1 && zd >= g.pt(g.np - 1)) c = 2 * (g.np - 1);
+        }
+        sig += (unsigned)(c + 1) * ((unsigned)i * 2654435761u + 1u);
+      }
+      code[i] = (int8_t)c;
+      if (c & 1) {
+        isfree = 1;
+        w[i] = 0.0;
+      } else {
+        const double v = g.pt(c >> 1);
+        w[i] = v;
+        isnz = (v != 0.0);
+        sx += v;
+        sturn += fabs(v - (double)rd[u].w0);
+      }
+    }
+    mf[u] = __ballot(isfree);
+    mn[u] = __ballot(isnz);
+  }
+  if (lane == 0) {
+#pragma unroll
+    for (int u = 0; u < kRR; ++u) {
+      s_wc[u][wv][0] = __popcll(mf[u]);
+      s_wc[u][wv][1] = __popcll(mn[u]);
+    }
+  }
+  __syncthreads();
+  int pf = 0, pn = 0;
+#pragma unroll
+  for (int u = 0; u < kRR; ++u) {
+    int bf = 0, bn = 0, tf = 0, tn = 0;
+#pragma unroll
+    for (int q = 0; q < kRW; ++q) {
+      const int xf = s_wc[u][q][0], xn = s_wc[u][q][1];
+      bf += (q < wv) ? xf : 0;
+      bn += (q < wv) ? xn : 0;
+      tf += xf;
+      tn += xn;
+    }
+    if ((mf[u] >> lane) & 1ull) seg[pf + bf + __popcll(mf[u] & below)] = ii[u];
+    if ((mn[u] >> lane) & 1ull) {
+      const int t = pn + bn + __popcll(mn[u] & below);
+      seg[nrow - 1 - t] = ii[u];
+      s_nz[t] = ii[u];
+    }
+    pf += tf;
+    pn += tn;
+  }
+  __syncthreads();
+  // column sums over the nonzero fixed rows: one wave per row, four rows at
+  // a time, the lanes over the columns (lane, lane + 64, lane + 128)
+  const int kg = k + G;
+  const bool on0 = lane < kg, on1 = lane + 64 < kg, on2 = lane + 128 < kg;
+  double c0 = 0.0, c1 = 0.0, c2 = 0.0;
+  for (int t0 = 4 * wv; t0 < pn; t0 += 4 * kRW) {
+    double wt[4];
+    float b0[4], b1[4], b2[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int i = s_nz[min(t0 + u, pn - 1)];
+      const float* row = A.Bt + (size_t)i * A.kp;
+      wt[u] = (t0 + u < pn) ? w[i] : 0.0;
+      b0[u] = on0 ? row[lane] : 0.f;
+      b1[u] = on1 ? row[lane + 64] : 0.f;
+      b2[u] = on2 ? row[lane + 128] : 0.f;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      c0 += (double)b0[u] * wt[u];
+      c1 += (double)b1[u] * wt[u];
+      c2 += (double)b2[u] * wt[u];
+    }
+  }
+  if (on0) s_red[wv * kg + lane] = c0;
+  if (on1) s_red[wv * kg + lane + 64] = c1;
+  if (on2) s_red[wv * kg + lane + 128] = c2;
+  // budget, turnover and signature partials
+  {
+    double sv[2] = {sx, sturn}, mv[1] = {0.0};
+    bred<2, 1>(sv, mv, s_sh);
+    sx = sv[0]; sturn = sv[1];
+  }
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) sig += __shfl_xor(sig, o, 64);
+  if (lane == 0) s_sg[wv] = sig;
+  __syncthreads();
+  double* rp = A.rpart + ((size_t)a * A.n_sb + b) * rpart_stride(k, G);
+  for (int j = tid; j < kg; j += kRT) {
+    double v = 0.0;
+    for (int q = 0; q < kRW; ++q) v += s_red[q * kg + j];
+    rp[j] = v;
+  }
+  if (tid == 0) {
+    unsigned sg = 0u;
+    for (int q = 0; q < kRW; ++q) sg += s_sg[q];
+    rp[kg] = sx;
+    rp[kg + 1] = sturn;
+    rp[kg + 2] = pf;
+    rp[kg + 3] = pn;
+    rp[kg + 4] = (double)sg;
+  }
+}
+
 __global__ __launch_bounds__(kPT) void polish_solve_kernel(PolishArgs A) {
   extern __shared__ double smem_d[];
   const int k = A.k, G = A.G, n = A.n;
@@ -410,8 +737,7 @@ __global__ __launch_bounds__(kPT) void polish_solve_kernel(PolishArgs A) {
   const int kfsz = max(k * k, (64 * (k + 1) + 1) / 2);
   double* stg = Kf + kfsz;                  // staging: 16 rows x (k + 4)
   __shared__ double shd[kPW];
-  __shared__ unsigned s_sig[kPW];
-  __shared__ int s_cnt[2], s_same;
+  __shared__ int s_same;
   const int slot = blockIdx.x;
   if (slot >= *A.m_act) return;
   const int a = A.act[slot];
@@ -450,95 +776,69 @@ __global__ __launch_bounds__(kPT) void polish_solve_kernel(PolishArgs A) {
   }
   const int cap_on = ps[PS_CAP];
 
-  // ---- one pass over the rows: (first round) the pattern of the iterate,
-  // fixed values, the free list from the front of flist and the nonzero
-  // fixed list from its back (wave ballots + a per-wave prefix), the
-  // budget and turnover sums of the fixed rows
-  __shared__ int s_wc[2][kPW][2];
-  if (tid == 0) { s_cnt[0] = 0; s_cnt[1] = 0; }
-  __syncthreads();
-  unsigned sig = 0u;                          // signature of the pattern
-  double sx = 0.0, sturn = 0.0;
-  {
-    const int lane = tid & 63, wv = tid >> 6;
-    int it = 0;
-    for (int base = 0; base < n; base += kPT, ++it) {
-      const int i = base + tid;
-      int isfree = 0, isnz = 0;
-      if (i < n) {
-        int c;
-        Geom g;
-        RowData r;
-        bool have = false;
-        if (A.first_round) {
-          r = row_data(A, a, i, lbf, ubf);
-          make_geom(g, kap, phi, r);
-          have = true;
-          const float z = A.z[(size_t)a * n + i];
-          // at point j (the float32 value the prox lands on), else inside
-          // the piece above the inner points below z (the points ascend)
-          c = (z == g.f0) ? 0 : (g.np > 1 && z == g.f1) ? 2 : (g.np > 2 && z == g.f2) ? 4
-            : (g.np > 3 && z == g.f3) ? 6 : (g.np > 4 && z == g.f4) ? 8
-            : (g.np > 5 && z == g.f5) ? 10 : -1;
-          if (c < 0) {
-            const double zd = z;
-            const int q = (g.np > 2 && zd > g.p1 ? 1 : 0) + (g.np > 3 && zd > g.p2 ? 1 : 0) +
-                          (g.np > 4 && zd > g.p3 ? 1 : 0) + (g.np > 5 && zd > g.p4 ? 1 : 0);
-            c = (g.np == 1) ? 0 : 2 * q + 1;
-            if (g.np > 1 && zd <= g.p0) c = 0;
-            if (g.np > 1 && zd >= g.pt(g.np - 1)) c = 2 * (g.np - 1);
-          }
-          code[i] = (int8_t)c;
-          sig += (unsigned)(c + 1) * ((unsigned)i * 2654435761u + 1u);
-        } else {
-          c = code[i];
-        }
-        if (c & 1) {
-          isfree = 1;
-          w[i] = 0.0;
-        } else {
-          if (!have) {
-            r = row_data(A, a, i, lbf, ubf);
-            make_geom(g, kap, phi, r);
-          }
-          const double v = g.pt(c >> 1);
-          w[i] = v;
-          isnz = (v != 0.0);
-          sx += v;
-          sturn += fabs(v - (double)r.w0);
-        }
-      }
-      const unsigned long long mf = __ballot(isfree), mn = __ballot(isnz);
-      const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-      const int par_ = it & 1;
-      if (lane == 0) { s_wc[par_][wv][0] = __popcll(mf); s_wc[par_][wv][1] = __popcll(mn); }
-      __syncthreads();
-      int pf = __popcll(mf & below), pn = __popcll(mn & below), tf = 0, tn = 0;
-      for (int q = 0; q < kPW; ++q) {
-        if (q < wv) { pf += s_wc[par_][q][0]; pn += s_wc[par_][q][1]; }
-        tf += s_wc[par_][q][0];
-        tn += s_wc[par_][q][1];
-      }
-      const int c0 = s_cnt[0], c1 = s_cnt[1];
-      if (isfree) flist[c0 + pf] = i;
-      if (isnz) flist[n - 1 - (c1 + pn)] = i;
-      __syncthreads();
-      if (tid == 0) { s_cnt[0] = c0 + tf; s_cnt[1] = c1 + tn; }
-    }
-    __syncthreads();
+  // ---- gather the row blocks of polish_rows: the free list at the front of
+  // flist and the nonzero fixed list at its back (both in ascending row
+  // order), the budget and turnover sums of the fixed rows, the pattern's
+  // signature, yX = B_X^T w_X and the fixed rows' constraint-row sums
+  const int S = A.n_sb, kg = k + G, rps = rpart_stride(k, G);
+  const double* rp = A.rpart + (size_t)a * S * rps;
+  const int32_t* fseg = A.fseg + (size_t)a * n;
+  int* s_of = reinterpret_cast<int*>(Kf);       // [S + 1] free-list offsets (Kf not built yet)
+  int* s_ox = s_of + (S + 1);                    // [S + 1] nonzero-list offsets
+  __shared__ double s_gfix[kMaxG];
+  __shared__ double s_sx[2];
+  for (int bb = tid; bb < S; bb += kPT) {
+    s_of[bb + 1] = (int)rp[(size_t)bb * rps + kg + 2];
+    s_ox[bb + 1] = (int)rp[(size_t)bb * rps + kg + 3];
   }
+  unsigned sig = 0u;
+  if (A.first_round)
+    for (int bb = 0; bb < S; ++bb) sig += (unsigned)rp[(size_t)bb * rps + kg + 4];
+  for (int j = tid; j < kg + 2; j += kPT) {
+    double v = 0.0;
+    for (int bb = 0; bb < S; ++bb) v += rp[(size_t)bb * rps + j];
+    if (j < k) { wk.yX[j] = v; wk.Fy[j] = v * (double)A.f[j]; }
+    else if (j < kg) s_gfix[j - k] = v;
+    else s_sx[j - kg] = v;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    s_of[0] = 0;
+    s_ox[0] = 0;
+    for (int bb = 0; bb < S; ++bb) {
+      s_of[bb + 1] += s_of[bb];
+      s_ox[bb + 1] += s_ox[bb];
+    }
+  }
+  __syncthreads();
+  const int nF = s_of[S], nX = s_ox[S];
+  // entry e of a list lies in the last block whose offset is <= e
+  auto block_of = [&](const int* off, int e) {
+    int lo = 0, hi = S;
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (off[mid] <= e) lo = mid; else hi = mid;
+    }
+    return lo;
+  };
+  for (int e = tid; e < nF; e += kPT) {
+    const int bb = block_of(s_of, e);
+    flist[e] = fseg[(size_t)bb * kRB + (e - s_of[bb])];
+  }
+  for (int e = tid; e < nX; e += kPT) {
+    const int bb = block_of(s_ox, e);
+    flist[n - 1 - e] = fseg[(size_t)bb * kRB + rows_in_block(n, bb) - 1 - (e - s_ox[bb])];
+  }
+  const double sx = s_sx[0], sturn = s_sx[1];
   if (A.first_round) {
-    sig = bsum<unsigned>(sig, s_sig);
     if (tid == 0) {
       sig += (unsigned)ps[PS_CAP] * 97u + (unsigned)ps[PS_BACT0] * 31u + (unsigned)ps[PS_BACT1] * 7u +
              (unsigned)ps[PS_BUP0] * 5u + (unsigned)ps[PS_BUP1] * 3u;
       s_same = (unsigned)ps[PS_SIG] == sig;
       ps[PS_SIG] = (int)sig;
     }
+    __syncthreads();
   }
-  sx = bsum<double>(sx, shd);
-  sturn = bsum<double>(sturn, shd);
-  const int nF = s_cnt[0], nX = s_cnt[1];
   // a pattern with many free coordinates belongs to an iterate that is far
   // from the optimum's vertex structure: skip the (costly) solve for now
   if ((A.nf_gate > 0 && nF > A.nf_gate) ||
@@ -549,19 +849,8 @@ __global__ __launch_bounds__(kPT) void polish_solve_kernel(PolishArgs A) {
     return;
   }
   if (tid == 0) atomicAdd(A.pcount, 1);
+  __syncthreads();                          // the lists are complete; s_of / s_ox are dead
 
-  // ---- fixed contributions ----------------------------------------------
-  // yX = B_X^T w_X, budget / band / cap sums of the fixed rows
-  __shared__ double s_gfix[kMaxG];
-  {
-    double ys = 0.0, gs = 0.0;
-    float* sB = reinterpret_cast<float*>(Kf);          // Kf is not built yet
-    double* swv = stg;
-    int* siv = reinterpret_cast<int*>(stg + 64);
-    list_sums(A, flist, n, nX, 1, w, sB, swv, siv, ys, gs);
-    if (tid < k) { wk.yX[tid] = ys; wk.Fy[tid] = ys * (double)A.f[tid]; }
-    if (tid < G) s_gfix[tid] = gs;
-  }
   // active constraint columns: 0 budget, bands (active order), cap
   int nb = 0;
   for (int g = 0; g < G; ++g) nb += band_active(ps, g) ? 1 : 0;
@@ -903,10 +1192,7 @@ __global__ __launch_bounds__(kPT) void polish_solve_kernel(PolishArgs A) {
   __syncthreads();
   {
     double ys = 0.0, gs = 0.0;
-    float* sB = reinterpret_cast<float*>(Kf);          // the solve is done with it
-    double* swv = stg;
-    int* siv = reinterpret_cast<int*>(stg + 64);
-    list_sums(A, flist, n, nF, 0, w, sB, swv, siv, ys, gs);
+    list_sums(A, flist, n, nF, 0, w, Kf, ys, gs);     // the solve is done with Kf
     if (tid < k) wk.yF[tid] = (wk.yX[tid] + ys) * (double)A.f[tid];
     if (tid < G) wk.gsum[tid] = s_gfix[tid] + gs;
   }
@@ -929,6 +1215,7 @@ __global__ __launch_bounds__(256) void polish_gbase_kernel(PolishArgs A, int fin
   __shared__ int s_a[kGbAcc];
   __shared__ double s_gam[kGbAcc];
   __shared__ double s_red[4][kGbAcc][4];
+  __shared__ int s_hp[kGbAcc];
   const int k = A.k, n = A.n, tid = threadIdx.x;
   const int m_act = *A.m_act;
   const int g0 = blockIdx.y * kGbAcc;
@@ -942,27 +1229,70 @@ __global__ __launch_bounds__(256) void polish_gbase_kernel(PolishArgs A, int fin
     }
     s_a[tid] = a;
     s_gam[tid] = a >= 0 ? (double)A.par[(size_t)a * kNPar + P_GAMMA] : 0.0;
+    s_hp[tid] = a >= 0 ? A.hold_ptr[a] : 0;
   }
   __syncthreads();
   const int k4 = (k + 3) & ~3;                 // <= kp: whole float4 of each row
-  for (int e = tid; e < kGbAcc * k4; e += 256) {
-    const int q = e / k4, j = e % k4;
-    const int a = s_a[q];
-    s_y[q][j] = (a >= 0 && j < k) ? wk_of(A, a).yF[j] : 0.0;
+  {
+    // kGbAcc k4 <= 2048 entries: eight per thread, all loads issued first
+    double yv[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = tid + 256 * u;
+      const int q = min(e / k4, kGbAcc - 1), j = e % k4;
+      const int a = s_a[q];
+      yv[u] = (e < kGbAcc * k4 && a >= 0 && j < k) ? wk_of(A, a).yF[j] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = tid + 256 * u;
+      if (e < kGbAcc * k4) s_y[e / k4][e % k4] = yv[u];
+    }
   }
   __syncthreads();
+  // the accounts present (uniform): the products skip the others
+  unsigned amask = 0u;
+#pragma unroll
+  for (int q = 0; q < kGbAcc; ++q) amask |= (s_a[q] >= 0 ? 1u : 0u) << q;
+  amask = __builtin_amdgcn_readfirstlane(amask);
   const int i = blockIdx.x * kGbRows + tid;
   const bool row_ok = i < n;
+  // the accounts' own data of the row first (w, mu, the holding word and
+  // the held record it points to), so that their memory round trips overlap
+  // the B row's instead of following one another account by account
+  const int ic = min(i, n - 1), wd = ic >> 5, bit = ic & 31;
+  double wq[kGbAcc], mq[kGbAcc];
+  uint32_t hq[kGbAcc];
+  int pq[kGbAcc];
+#pragma unroll
+  for (int q = 0; q < kGbAcc; ++q) {
+    const int a = s_a[q];
+    wq[q] = 0.0; mq[q] = 0.0; hq[q] = 0u; pq[q] = 0;
+    if (a >= 0) {                              // uniform
+      wq[q] = A.wout[(size_t)a * n + ic];
+      mq[q] = mu_at(A, (size_t)a * n + ic);
+      hq[q] = A.hold[(size_t)a * A.W + wd];
+      pq[q] = A.hold_pre[(size_t)a * A.W + wd];
+    }
+  }
+  float w0q[kGbAcc];
+#pragma unroll
+  for (int q = 0; q < kGbAcc; ++q) {
+    w0q[q] = 0.f;
+    if ((hq[q] >> bit) & 1u) w0q[q] = A.hold_rec[2 * (s_hp[q] + pq[q] + popc_below(hq[q], bit))].x;
+  }
   double sig[kGbAcc];
 #pragma unroll
   for (int q = 0; q < kGbAcc; ++q) sig[q] = 0.0;
   if (row_ok) {
     const float4* brow = reinterpret_cast<const float4*>(A.Bt + (size_t)i * A.kp);
+#pragma unroll 4
     for (int j4 = 0; j4 < k4 / 4; ++j4) {
       const float4 b = brow[j4];
       const double b0 = b.x, b1 = b.y, b2 = b.z, b3 = b.w;
 #pragma unroll
       for (int q = 0; q < kGbAcc; ++q) {
+        if (!((amask >> q) & 1u)) continue;
         const double* y = &s_y[q][4 * j4];
         sig[q] += b0 * y[0] + b1 * y[1] + b2 * y[2] + b3 * y[3];
       }
@@ -976,14 +1306,14 @@ __global__ __launch_bounds__(256) void polish_gbase_kernel(PolishArgs A, int fin
     if (a < 0) continue;                       // uniform
     double gmax = 0.0, mumax = 0.0, turn = 0.0, bad = 0.0;
     if (row_ok) {
-      const double wi = A.wout[(size_t)a * n + i];
+      const double wi = wq[q];
       const double sg = sig[q] + di * wi;
-      const double mui = mu_at(A, (size_t)a * n + i);
+      const double mui = mq[q];
       const double v = s_gam[q] * sg - mui;
       A.gbase[(size_t)a * n + i] = v;
       gmax = fabs(s_gam[q] * sg);
       mumax = fabs(mui);
-      turn = fabs(wi - (double)row_data(A, a, i, 0.f, 0.f).w0);
+      turn = fabs(wi - (double)w0q[q]);
       if (!isfinite(v) || !isfinite(wi)) bad = 1.0;
     }
 #pragma unroll
@@ -1011,39 +1341,248 @@ __global__ __launch_bounds__(256) void polish_gbase_kernel(PolishArgs A, int fin
 }
 
 // ---------------------------------------------------------------------------
-// polish_check: external diagnostics in float64 and refinement
+// polish_check: external diagnostics in float64 and refinement, after the
+// gradient base, in four launches: the null-direction sweep rows (row
+// blocks; the common case of one open direction), polish_pre (per account:
+// the gradient scale and the sweep decisions), the diagnostic rows (row
+// blocks: residual partials and refinement proposals) and polish_decide
+// (per account: the certificate and the refinement decisions)
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kPTC) void polish_check_kernel(PolishArgs A, fqp_result R,
-                                                          int final_pass) {
+
+// Along a stored null direction v of the free-row equations the free rows
+// stay stationary, and every fixed row's stationarity interval becomes a
+// pair of linear inequalities in the step s.  The step aims at zeroing the
+// multiplier of an active constraint that is not tight (its row was
+// dependent, so the solve could not enforce it); otherwise it stays nearest
+// to 0.  When a fixed row blocks that target, the row is the one to release
+// (dual active-set step).
+struct SweepDir {
+  const double* nv;     // the direction, in the column order of eta
+  double n0, ncap, lamc;
+};
+
+__device__ __forceinline__ SweepDir sweep_dir(const int* ps, const double* nv,
+                                              const double* mult) {
+  SweepDir D;
+  D.nv = nv;
+  // column of each multiplier inside eta = (-nu, bands..., lam_cap)
+  D.n0 = nv[0];
+  D.ncap = ps[PS_CAP] ? nv[ps[PS_NC] - 1] : 0.0;
+  D.lamc = mult[1];
+  return D;
+}
+
+// one row's bounds on the step: Lo <= s <= Up keeps it stationary; the keys
+// name the row and the piece it would move into (row * 16 + code)
+__device__ __forceinline__ void sweep_row(const PolishArgs& A, const int* ps, const SweepDir& D,
+                                          const double* mult, int i, int c, double gbi,
+                                          double wi, int grp, const RowData& r, float kap,
+                                          bool phi, double& Lo, double& Up, int& loKey,
+                                          int& upKey) {
+  if ((c & 1) || !r.el) return;
+  const int G = A.G;
+  Geom g;
+  make_geom(g, kap, phi, r);
+  const double lb = r.lb, ub = r.ub;
+  double nb = 0.0, lg = 0.0;
+  if (G) {
+    lg = rows_dot_g(A, i, grp, mult + 2);
+    int col = 1;
+    for (int g2 = 0; g2 < G; ++g2) {
+      if (!band_active(ps, g2)) continue;
+      nb += row_coef_g(A, i, grp, g2) * D.nv[col];
+      ++col;
+    }
+  }
+  const double T = -(gbi - mult[0] + lg);
+  const double al = D.n0 + nb;
+  const int j = c >> 1;
+  // leaving the interval at its lower end: the row wants to go down
+  const int keyL = (j > 0) ? i * 16 + 2 * (j - 1) + 1 : INT_MAX;
+  const int keyU = (j + 1 < g.np) ? i * 16 + 2 * j + 1 : INT_MAX;
+  double lo0, hi0, lo1, hi1, sn;
+  subdiff(g, wi, 0.0, lb, ub, lo0, hi0, sn);
+  subdiff(g, wi, 1.0, lb, ub, lo1, hi1, sn);
+  // a coefficient that cancels to rounding level (a fixed row whose
+  // interval moves with the free rows along v: the degenerate case of free
+  // rows that all trade one way) puts no bound on the step; taken at face
+  // value it would allow a step of 1/rounding
+  if (isfinite(lo0)) {           // lo0 + s_lo (lamc + s ncap) <= T - al s
+    const double slo = lo1 - lo0;
+    const double aa = al + slo * D.ncap, bb = T - lo0 - slo * D.lamc;
+    const double tz = 1e-12 * (fabs(al) + fabs(slo * D.ncap));
+    if (aa > tz) { const double x = bb / aa; if (x < Up) { Up = x; upKey = keyL; } }
+    else if (aa < -tz) { const double x = bb / aa; if (x > Lo) { Lo = x; loKey = keyL; } }
+  }
+  if (isfinite(hi0)) {           // T - al s <= hi0 + s_hi (lamc + s ncap)
+    const double shi = hi1 - hi0;
+    const double aa = -(al + shi * D.ncap), bb = hi0 + shi * D.lamc - T;
+    const double tz = 1e-12 * (fabs(al) + fabs(shi * D.ncap));
+    if (aa > tz) { const double x = bb / aa; if (x < Up) { Up = x; upKey = keyU; } }
+    else if (aa < -tz) { const double x = bb / aa; if (x > Lo) { Lo = x; loKey = keyU; } }
+  }
+}
+
+// the step along D given the rows' bounds [Lo, Up] (keys kLo, kUp): updates
+// mult; *block takes the row to release when one blocks the target
+__device__ void sweep_step(const PolishArgs& A, int a, const int* ps, const SweepDir& D,
+                           double Lo, double Up, int kLo, int kUp, double thr, double turn0,
+                           float tauf, const double* s_gs, double* mult, int* block) {
+  const int G = A.G;
+  const double ncap = D.ncap, lamc = D.lamc;
+  // targets along this direction, by priority: (1) an active constraint the
+  // solve could not enforce (dependent row) and that is violated: push its
+  // multiplier outward until a fixed row blocks, and release that row; (2)
+  // an active constraint that is slack: zero its multiplier
+  // (complementarity)
+  double tgt = 0.0, best = 0.0, worst = 0.0;
+  bool has_tgt = false;
+  const double vtol = 0.1 * A.eps_prim;
+  if (ps[PS_CAP]) {              // lam_cap + s ncap >= 0
+    if (ncap > 1e-12) { const double u = -lamc / ncap; if (u > Lo) { Lo = u; kLo = INT_MAX; } }
+    else if (ncap < -1e-12) { const double u = -lamc / ncap; if (u < Up) { Up = u; kUp = INT_MAX; } }
+    const double sl = (double)tauf - turn0;
+    if (fabs(ncap) > 1e-12) {
+      if (sl < -vtol && -sl > worst) {
+        worst = -sl; tgt = (ncap > 0.0) ? INFINITY : -INFINITY; has_tgt = true;
+      } else if (worst == 0.0) {
+        const double v = fabs(lamc) * fmax(sl, 0.0);
+        if (v > thr && v > best) { best = v; tgt = -lamc / ncap; has_tgt = true; }
+      }
+    }
+  }
+  int col = 1;
+  for (int gg = 0; gg < G; ++gg) {
+    if (!band_active(ps, gg)) continue;
+    const double nbv = D.nv[col++];
+    const double cur = mult[2 + gg];
+    const bool up = band_upper(ps, gg);
+    // upper band: lam >= 0 ; lower band: lam <= 0
+    const double sgn_req = up ? 1.0 : -1.0;
+    const double aa = sgn_req * nbv, bb = sgn_req * cur;   // bb + s aa >= 0
+    if (aa > 1e-12) { const double u = -bb / aa; if (u > Lo) { Lo = u; kLo = INT_MAX; } }
+    else if (aa < -1e-12) { const double u = -bb / aa; if (u < Up) { Up = u; kUp = INT_MAX; } }
+    if (fabs(nbv) <= 1e-12) continue;
+    const double sl = up ? (double)A.bhi[(size_t)a * G + gg] - s_gs[gg]
+                         : s_gs[gg] - (double)A.blo[(size_t)a * G + gg];
+    if (sl < -vtol && -sl > worst) {
+      worst = -sl; tgt = (aa > 0.0) ? INFINITY : -INFINITY; has_tgt = true;
+    } else if (worst == 0.0) {
+      const double v = fabs(cur) * fmax(sl, 0.0);
+      if (v > thr && v > best) { best = v; tgt = -cur / nbv; has_tgt = true; }
+    }
+  }
+  double st;
+  if (Lo <= Up) {
+    st = fmin(fmax(tgt, Lo), Up);
+    if (has_tgt) {
+      const int key = (tgt < Lo) ? kLo : (tgt > Up) ? kUp : INT_MAX;
+      if (key != INT_MAX && *block < 0) *block = key;
+    } else if (isfinite(Lo) && isfinite(Up)) {
+      st += 1e-3 * (0.5 * (Lo + Up) - st);
+    }
+  } else {
+    st = 0.5 * (Lo + Up);
+  }
+  if (!isfinite(st)) st = 0.0;
+  // eta += st * v  ->  nu -= st v0, bands += st v_b, lam_cap += st v_cap
+  mult[0] -= st * D.n0;
+  col = 1;
+  for (int gg = 0; gg < G; ++gg)
+    if (band_active(ps, gg)) mult[2 + gg] += st * D.nv[col++];
+  if (ps[PS_CAP]) mult[1] += st * ncap;
+}
+
+// the check passes' per-row inputs of kRR rows (all loads issued together)
+struct CheckIn {
+  int ii[kRR], cc[kRR], grp[kRR];
+  double gb[kRR], w[kRR], mu[kRR];
+  RowData rd[kRR];
+};
+__device__ __forceinline__ void check_in(const PolishArgs& A, int a, int base, int stride,
+                                         bool want_mu, float lbf, float ubf, CheckIn& I) {
+  const int n = A.n;
+#pragma unroll
+  for (int u = 0; u < kRR; ++u) {
+    I.ii[u] = base + u * stride + (int)threadIdx.x;
+    const int ic = min(I.ii[u], n - 1);
+    const size_t off = (size_t)a * n + ic;
+    I.cc[u] = A.code[off];
+    I.gb[u] = A.gbase[off];
+    I.w[u] = A.wout[off];
+    I.mu[u] = want_mu ? mu_at(A, off) : 0.0;
+    I.grp[u] = A.Gl ? A.group[ic] : 0;
+  }
+  row_data_n<kRR>(A, a, I.ii, lbf, ubf, I.rd);
+}
+
+// per-block bounds of the one-direction sweep: [m][n_sb][4] = Lo, Up and
+// the smallest keys of the rows attaining them
+__global__ __launch_bounds__(kRT) void polish_sweep_kernel(PolishArgs A, int final_pass) {
+  __shared__ double mult[2 + kMaxG];
+  __shared__ double s_sh[3 * kRW];
+  __shared__ int s_key[2];
+  const int G = A.G, tid = threadIdx.x;
+  const int b = blockIdx.x, slot = blockIdx.y;
+  if (slot >= *A.m_act) return;
+  const int a = A.act[slot];
+  const int* ps = A.pstate + (size_t)a * kPStateStride;
+  if (ps[PS_DONE] || (ps[PS_STALL] && !final_pass) || ps[PS_ND] != 1) return;
+  const float* par = A.par + (size_t)a * kNPar;
+  const float lbf = par[P_LB], ubf = par[P_UB], kap = par[P_KAPPA], tauf = par[P_TAU];
+  const bool phi = (kap > 0.f) || isfinite(tauf) || (par[P_HASTAX] != 0.f);
+  const double* gmult = A.mult + (size_t)a * (2 + G);
+  for (int q = tid; q < 2 + G; q += kRT) mult[q] = gmult[q];
+  if (tid == 0) { s_key[0] = INT_MAX; s_key[1] = INT_MAX; }
+  CheckIn I;
+  check_in(A, a, b * kRB, kRT, false, lbf, ubf, I);
+  __syncthreads();
+  const SweepDir D = sweep_dir(ps, wk_of(A, a).nul, mult);
+  double Lo = -INFINITY, Up = INFINITY;
+  int loKey = INT_MAX, upKey = INT_MAX;
+#pragma unroll
+  for (int u = 0; u < kRR; ++u)
+    if (I.ii[u] < A.n)
+      sweep_row(A, ps, D, mult, I.ii[u], I.cc[u], I.gb[u], I.w[u], I.grp[u], I.rd[u], kap, phi,
+                Lo, Up, loKey, upKey);
+  double sv[1] = {0.0}, mv[2] = {Lo, -Up};
+  bred<1, 2>(sv, mv, s_sh);
+  const double Lb = mv[0], Ub = -mv[1];
+  if (Lo == Lb && isfinite(Lb)) atomicMin(&s_key[0], loKey);
+  if (Up == Ub && isfinite(Ub)) atomicMin(&s_key[1], upKey);
+  __syncthreads();
+  if (tid == 0) {
+    double* sp = A.spart + ((size_t)a * A.n_sb + b) * 4;
+    sp[0] = Lb;
+    sp[1] = Ub;
+    sp[2] = s_key[0];
+    sp[3] = s_key[1];
+  }
+}
+
+// per account: the gradient scale (from polish_gbase's blocks), then the
+// multipliers the free rows leave open (one direction: from the sweep
+// blocks; more: swept here, twice, as the directions interact); stores the
+// multipliers, the row to release and the scale for the passes after it
+__global__ __launch_bounds__(kPTC) void polish_pre_kernel(PolishArgs A, int final_pass) {
   __shared__ double shd[kPW];
+  __shared__ double s_red6[6 * kPW];
   __shared__ double s_gs[kMaxG];
-  const int k = A.k, G = A.G, n = A.n;
+  __shared__ double mult[2 + kMaxG];
+  __shared__ int s_block, s_key[2], s_bad;
+  const int G = A.G, n = A.n;
   const int slot = blockIdx.x;
   if (slot >= *A.m_act) return;
   const int a = A.act[slot];
   const int tid = threadIdx.x;
   int* ps = A.pstate + (size_t)a * kPStateStride;
   if (ps[PS_DONE] || (ps[PS_STALL] && !final_pass)) return;
-  __shared__ int s_changed;
-  if (tid == 0) s_changed = 0;
   const float* par = A.par + (size_t)a * kNPar;
   const float lbf = par[P_LB], ubf = par[P_UB], kap = par[P_KAPPA], tauf = par[P_TAU];
-  const double gam = par[P_GAMMA];
   const bool phi = (kap > 0.f) || isfinite(tauf) || (par[P_HASTAX] != 0.f);
-  int changed = 0;
-  int8_t* code_r = A.code + (size_t)a * n;
-  int8_t* code = A.code_next + (size_t)a * n;    // proposals
-  const int32_t* flist = A.flist + (size_t)a * n;
-  const double* w = A.wout + (size_t)a * n;
   double* gmult = A.mult + (size_t)a * (2 + G);
-  __shared__ double mult[2 + kMaxG];
   for (int q = tid; q < 2 + G; q += kPTC) mult[q] = gmult[q];
-  const int nF = ps[PS_NF], nX = ps[PS_NX];
-  double* gb = A.gbase + (size_t)a * n;
-  __shared__ int s_bad, s_done;
-  if (tid == 0) { s_bad = 0; s_done = 0; }
-
-  // row sums (from the solve) and the reductions of polish_gbase
+  if (tid == 0) { s_bad = 0; s_block = -1; }
   __syncthreads();                        // flags above are initialised
   const Wk wkc = wk_of(A, a);
   for (int g = tid; g < G; g += kPTC) s_gs[g] = wkc.gsum[g];
@@ -1057,175 +1596,116 @@ __global__ __launch_bounds__(kPTC) void polish_check_kernel(PolishArgs A, fqp_re
     if (gp[3] != 0.0) bad = 1;
   }
   if (bad) atomicOr(&s_bad, 1);
-  gmax = bmax<double>(gmax, shd);
-  mumax = bmax<double>(mumax, shd);
-  turn0 = bsum<double>(turn0, shd);
-  const double scale = fmax(fmax(gmax, mumax), 1e-12);
-
-  // ---- multipliers the free rows leave open -----------------------------
-  // Along a stored null direction v of the free-row equations the free rows
-  // stay stationary, and every fixed row's stationarity interval becomes a
-  // pair of linear inequalities in the step s.  The step aims at zeroing
-  // the multiplier of an active constraint that is not tight (its row was
-  // dependent, so the solve could not enforce it); otherwise it stays
-  // nearest to 0.  When a fixed row blocks that target, the row is the
-  // one to release (dual active-set step): it is proposed below.
-  __shared__ int s_block;                 // row * 16 + proposed code, or -1
-  __shared__ int s_key[2];
-  __shared__ double s_st;
-  if (tid == 0) s_block = -1;
   {
-    const int nd = ps[PS_ND];
-    const int nc = ps[PS_NC];
-    const int ncol = G + 3;
-    const double* nul = wk_of(A, a).nul;
-    const double thr = 0.01 * A.eps_comp * scale;
+    double sv[1] = {turn0}, mv[2] = {gmax, mumax};
+    bred<1, 2>(sv, mv, s_red6);           // (also publishes s_gs)
+    turn0 = sv[0]; gmax = mv[0]; mumax = mv[1];
+  }
+  const double scale = fmax(fmax(gmax, mumax), 1e-12);
+  const int nd = ps[PS_ND];
+  const int ncol = G + 3;
+  const double thr = 0.01 * A.eps_comp * scale;
+  if (nd == 1) {
+    if (tid == 0) {
+      // the blocks' bounds in block order: the extreme and the smallest key
+      // among the blocks attaining it
+      double Lo = -INFINITY, Up = INFINITY;
+      int kLo = INT_MAX, kUp = INT_MAX;
+      for (int bb = 0; bb < A.n_sb; ++bb) {
+        const double* sp = A.spart + ((size_t)a * A.n_sb + bb) * 4;
+        const double l = sp[0], u = sp[1];
+        const int kl = (int)sp[2], ku = (int)sp[3];
+        if (l > Lo) { Lo = l; kLo = kl; } else if (l == Lo) kLo = min(kLo, kl);
+        if (u < Up) { Up = u; kUp = ku; } else if (u == Up) kUp = min(kUp, ku);
+      }
+      if (!isfinite(Lo)) kLo = INT_MAX;
+      if (!isfinite(Up)) kUp = INT_MAX;
+      const SweepDir D = sweep_dir(ps, wkc.nul, mult);
+      sweep_step(A, a, ps, D, Lo, Up, kLo, kUp, thr, turn0, tauf, s_gs, mult, &s_block);
+    }
+    __syncthreads();
+  } else if (nd > 1) {
     // (a second sweep only matters when directions interact: nd > 1)
-    for (int sweep = 0; sweep < (nd > 1 ? 2 : 1) && nd > 0; ++sweep) {
+    for (int sweep = 0; sweep < 2; ++sweep) {
       for (int q = 0; q < nd; ++q) {
-        const double* nv = nul + q * ncol;
-        // column of each multiplier inside eta = (-nu, bands..., lam_cap)
-        const double n0 = nv[0];
-        const double ncap = ps[PS_CAP] ? nv[nc - 1] : 0.0;
-        const double lamc = mult[1];
+        const SweepDir D = sweep_dir(ps, wkc.nul + q * ncol, mult);
         double Lo = -INFINITY, Up = INFINITY;
         int loKey = INT_MAX, upKey = INT_MAX;
-        for (int i = tid; i < n; i += kPTC) {
-          const int c = code_r[i];
-          if (c & 1) continue;
-          RowData r = row_data(A, a, i, lbf, ubf);
-          if (!r.el) continue;
-          Geom g;
-          make_geom(g, kap, phi, r);
-          const double lb = r.lb, ub = r.ub;
-          double nb = 0.0, lg = 0.0;
-          if (G) {
-            lg = rows_dot(A, i, mult + 2);
-            int col = 1;
-            for (int g2 = 0; g2 < G; ++g2) {
-              if (!band_active(ps, g2)) continue;
-              nb += row_coef(A, i, g2) * nv[col];
-              ++col;
-            }
-          }
-          const double T = -(gb[i] - mult[0] + lg);
-          const double al = n0 + nb;
-          const int j = c >> 1;
-          // leaving the interval at its lower end: the row wants to go down
-          const int keyL = (j > 0) ? i * 16 + 2 * (j - 1) + 1 : INT_MAX;
-          const int keyU = (j + 1 < g.np) ? i * 16 + 2 * j + 1 : INT_MAX;
-          double lo0, hi0, lo1, hi1, sn;
-          subdiff(g, w[i], 0.0, lb, ub, lo0, hi0, sn);
-          subdiff(g, w[i], 1.0, lb, ub, lo1, hi1, sn);
-          // a coefficient that cancels to rounding level (a fixed row whose
-          // interval moves with the free rows along v: the degenerate case
-          // of free rows that all trade one way) puts no bound on the step;
-          // taken at face value it would allow a step of 1/rounding
-          if (isfinite(lo0)) {           // lo0 + s_lo (lamc + s ncap) <= T - al s
-            const double slo = lo1 - lo0;
-            const double aa = al + slo * ncap, bb = T - lo0 - slo * lamc;
-            const double tz = 1e-12 * (fabs(al) + fabs(slo * ncap));
-            if (aa > tz) { const double u = bb / aa; if (u < Up) { Up = u; upKey = keyL; } }
-            else if (aa < -tz) { const double u = bb / aa; if (u > Lo) { Lo = u; loKey = keyL; } }
-          }
-          if (isfinite(hi0)) {           // T - al s <= hi0 + s_hi (lamc + s ncap)
-            const double shi = hi1 - hi0;
-            const double aa = -(al + shi * ncap), bb = hi0 + shi * lamc - T;
-            const double tz = 1e-12 * (fabs(al) + fabs(shi * ncap));
-            if (aa > tz) { const double u = bb / aa; if (u < Up) { Up = u; upKey = keyU; } }
-            else if (aa < -tz) { const double u = bb / aa; if (u > Lo) { Lo = u; loKey = keyU; } }
-          }
+        for (int base = 0; base < n; base += kRR * kPTC) {
+          CheckIn I;
+          check_in(A, a, base, kPTC, false, lbf, ubf, I);
+#pragma unroll
+          for (int u = 0; u < kRR; ++u)
+            if (I.ii[u] < n)
+              sweep_row(A, ps, D, mult, I.ii[u], I.cc[u], I.gb[u], I.w[u], I.grp[u], I.rd[u],
+                        kap, phi, Lo, Up, loKey, upKey);
         }
-        const double Lb = bmax<double>(Lo, shd);
-        const double Ub = -bmax<double>(-Up, shd);
+        double sv[1] = {0.0}, mv[2] = {Lo, -Up};
+        bred<1, 2>(sv, mv, s_red6);
+        const double Lb = mv[0], Ub = -mv[1];
         if (tid == 0) { s_key[0] = INT_MAX; s_key[1] = INT_MAX; }
         __syncthreads();
         if (Lo == Lb && isfinite(Lb)) atomicMin(&s_key[0], loKey);
         if (Up == Ub && isfinite(Ub)) atomicMin(&s_key[1], upKey);
         __syncthreads();
-        if (tid == 0) {
-          Lo = Lb; Up = Ub;
-          int kLo = s_key[0], kUp = s_key[1];
-          // targets along this direction, by priority: (1) an active
-          // constraint the solve could not enforce (dependent row) and that
-          // is violated: push its multiplier outward until a fixed row
-          // blocks, and release that row; (2) an active constraint that is
-          // slack: zero its multiplier (complementarity)
-          double tgt = 0.0, best = 0.0, worst = 0.0;
-          bool has_tgt = false;
-          const double vtol = 0.1 * A.eps_prim;
-          if (ps[PS_CAP]) {              // lam_cap + s ncap >= 0
-            if (ncap > 1e-12) { const double u = -lamc / ncap; if (u > Lo) { Lo = u; kLo = INT_MAX; } }
-            else if (ncap < -1e-12) { const double u = -lamc / ncap; if (u < Up) { Up = u; kUp = INT_MAX; } }
-            const double sl = (double)tauf - turn0;
-            if (fabs(ncap) > 1e-12) {
-              if (sl < -vtol && -sl > worst) {
-                worst = -sl; tgt = (ncap > 0.0) ? INFINITY : -INFINITY; has_tgt = true;
-              } else if (worst == 0.0) {
-                const double v = fabs(lamc) * fmax(sl, 0.0);
-                if (v > thr && v > best) { best = v; tgt = -lamc / ncap; has_tgt = true; }
-              }
-            }
-          }
-          int col = 1;
-          for (int gg = 0; gg < G; ++gg) {
-            if (!band_active(ps, gg)) continue;
-            const double nbv = nv[col++];
-            const double cur = mult[2 + gg];
-            const bool up = band_upper(ps, gg);
-            // upper band: lam >= 0 ; lower band: lam <= 0
-            const double sgn_req = up ? 1.0 : -1.0;
-            const double aa = sgn_req * nbv, bb = sgn_req * cur;   // bb + s aa >= 0
-            if (aa > 1e-12) { const double u = -bb / aa; if (u > Lo) { Lo = u; kLo = INT_MAX; } }
-            else if (aa < -1e-12) { const double u = -bb / aa; if (u < Up) { Up = u; kUp = INT_MAX; } }
-            if (fabs(nbv) <= 1e-12) continue;
-            const double sl = up ? (double)A.bhi[(size_t)a * G + gg] - s_gs[gg]
-                                 : s_gs[gg] - (double)A.blo[(size_t)a * G + gg];
-            if (sl < -vtol && -sl > worst) {
-              worst = -sl; tgt = (aa > 0.0) ? INFINITY : -INFINITY; has_tgt = true;
-            } else if (worst == 0.0) {
-              const double v = fabs(cur) * fmax(sl, 0.0);
-              if (v > thr && v > best) { best = v; tgt = -cur / nbv; has_tgt = true; }
-            }
-          }
-          double st;
-          if (Lo <= Up) {
-            st = fmin(fmax(tgt, Lo), Up);
-            if (has_tgt) {
-              const int key = (tgt < Lo) ? kLo : (tgt > Up) ? kUp : INT_MAX;
-              if (key != INT_MAX && s_block < 0) s_block = key;
-            } else if (isfinite(Lo) && isfinite(Up)) {
-              st += 1e-3 * (0.5 * (Lo + Up) - st);
-            }
-          } else {
-            st = 0.5 * (Lo + Up);
-          }
-          if (!isfinite(st)) st = 0.0;
-          // eta += st * v  ->  nu -= st v0, bands += st v_b, lam_cap += st v_cap
-          mult[0] -= st * n0;
-          col = 1;
-          for (int gg = 0; gg < G; ++gg)
-            if (band_active(ps, gg)) mult[2 + gg] += st * nv[col++];
-          if (ps[PS_CAP]) mult[1] += st * ncap;
-          s_st = st;
-        }
+        if (tid == 0)
+          sweep_step(A, a, ps, D, Lb, Ub, s_key[0], s_key[1], thr, turn0, tauf, s_gs, mult,
+                     &s_block);
         __syncthreads();
       }
     }
   }
-  const double nu = mult[0], lam = mult[1];
+  for (int q = tid; q < 2 + G; q += kPTC) gmult[q] = mult[q];
+  if (tid == 0) {
+    ps[PS_BLOCK] = s_block;
+    double* misc = wkc.misc;
+    misc[0] = scale;
+    misc[1] = turn0;
+    misc[2] = s_bad ? 1.0 : 0.0;
+  }
+}
 
-  double sw = 0.0, turn = 0.0, dmax = 0.0, box = 0.0, snapm = 0.0, obj = 0.0;
-  for (int i = tid; i < n; i += kPTC) {
-    RowData r = row_data(A, a, i, lbf, ubf);
+// per-block diagnostics of the pattern's w and the refinement proposals
+// (written to code_next for every row): [m][n_sb][8] = budget, turnover and
+// objective sums, largest stationarity distance, box violation and kink
+// snap, proposal count, non-finite flag
+__global__ __launch_bounds__(kRT) void polish_check_rows_kernel(PolishArgs A, int final_pass) {
+  __shared__ double mult[2 + kMaxG];
+  __shared__ double s_sh[7 * kRW];
+  __shared__ int s_ch;
+  const int G = A.G, n = A.n, tid = threadIdx.x;
+  const int b = blockIdx.x, slot = blockIdx.y;
+  if (slot >= *A.m_act) return;
+  const int a = A.act[slot];
+  const int* ps = A.pstate + (size_t)a * kPStateStride;
+  if (ps[PS_DONE] || (ps[PS_STALL] && !final_pass)) return;
+  const float* par = A.par + (size_t)a * kNPar;
+  const float lbf = par[P_LB], ubf = par[P_UB], kap = par[P_KAPPA], tauf = par[P_TAU];
+  const double gam = par[P_GAMMA];
+  const bool phi = (kap > 0.f) || isfinite(tauf) || (par[P_HASTAX] != 0.f);
+  int8_t* code = A.code_next + (size_t)a * n;    // proposals
+  const double* gmult = A.mult + (size_t)a * (2 + G);
+  for (int q = tid; q < 2 + G; q += kRT) mult[q] = gmult[q];
+  if (tid == 0) s_ch = 0;
+  CheckIn I;
+  check_in(A, a, b * kRB, kRT, true, lbf, ubf, I);
+  __syncthreads();
+  const double nu = mult[0], lam = mult[1];
+  double sw = 0.0, turn = 0.0, dmax = 0.0, box = 0.0, snapm = 0.0, obj = 0.0, bad = 0.0;
+  int changed = 0;
+#pragma unroll
+  for (int u = 0; u < kRR; ++u) {
+    const int i = I.ii[u];
+    if (i >= n) continue;
+    const RowData& r = I.rd[u];
     Geom g;
     make_geom(g, kap, phi, r);
     const double lb = r.lb, ub = r.ub;
-    const double wi = w[i];
-    const double mui = mu_at(A, (size_t)a * n + i);
-    const double sig = (gb[i] + mui) / gam;
-    double gi = gb[i] - nu;
-    if (G) gi += rows_dot(A, i, mult + 2);
+    const double wi = I.w[u];
+    const double mui = I.mu[u];
+    const double sig = (I.gb[u] + mui) / gam;
+    double gi = I.gb[u] - nu;
+    if (G) gi += rows_dot_g(A, i, I.grp[u], mult + 2);
     double lo, hi, snap;
     subdiff(g, wi, lam, lb, ub, lo, hi, snap);
     const double t = -gi;
@@ -1233,7 +1713,7 @@ __global__ __launch_bounds__(kPTC) void polish_check_kernel(PolishArgs A, fqp_re
     sw += wi;
     turn += fabs(wi - g.w0);
     dmax = fmax(dmax, dist);
-    if (!isfinite(dist)) bad = 1;
+    if (!isfinite(dist)) bad = 1.0;
     box = fmax(box, fmax(lb - wi, wi - ub));
     snapm = fmax(snapm, snap);
     // objective: (gamma/2) w.Sigma w - mu w + trade cost
@@ -1241,35 +1721,77 @@ __global__ __launch_bounds__(kPTC) void polish_check_kernel(PolishArgs A, fqp_re
     if (r.taxed && wi < g.w0) tc += lot_tax(g.w0 - wi, r);
     obj += 0.5 * gam * wi * sig - mui * wi + tc;
     // refinement proposal (applied only if the pattern fails)
-    const int c = code_r[i];
-    code[i] = (int8_t)c;
+    const int c = I.cc[u];
+    int cn = c;
     if (g.np > 1) {
       const double tolm = A.eps_dual * 0.1;
       if (c & 1) {
         const int q = c >> 1;
-        if (wi > g.pt(q + 1)) { code[i] = (int8_t)(2 * (q + 1)); ++changed; }
-        else if (wi < g.pt(q)) { code[i] = (int8_t)(2 * q); ++changed; }
+        if (wi > g.pt(q + 1)) cn = 2 * (q + 1);
+        else if (wi < g.pt(q)) cn = 2 * q;
       } else {
         // move off a point when -g lies outside its subdifferential
         const int j = c >> 1;
         double l2, h2, sn2;
         subdiff(g, g.pt(j), lam, lb, ub, l2, h2, sn2);
         const double sc = fmax(fabs(mui), 1e-12);
-        if (t > h2 + tolm * sc && j + 1 < g.np) { code[i] = (int8_t)(2 * j + 1); ++changed; }
-        else if (t < l2 - tolm * sc && j > 0) { code[i] = (int8_t)(2 * (j - 1) + 1); ++changed; }
+        if (t > h2 + tolm * sc && j + 1 < g.np) cn = 2 * j + 1;
+        else if (t < l2 - tolm * sc && j > 0) cn = 2 * (j - 1) + 1;
       }
     }
+    code[i] = (int8_t)cn;
+    changed += (cn != c) ? 1 : 0;
   }
-  if (changed) atomicAdd(&s_changed, changed);
-  if (bad) atomicOr(&s_bad, 1);
-  sw = bsum<double>(sw, shd);
-  turn = bsum<double>(turn, shd);
-  obj = bsum<double>(obj, shd);
-  dmax = bmax<double>(dmax, shd);
-  box = bmax<double>(box, shd);
-  snapm = bmax<double>(snapm, shd);
-
+  if (changed) atomicAdd(&s_ch, changed);
+  double sv[3] = {sw, turn, obj}, mv[4] = {dmax, box, snapm, bad};
+  bred<3, 4>(sv, mv, s_sh);                 // (its barriers also publish s_ch)
   if (tid == 0) {
+    double* cp = A.cpart + ((size_t)a * A.n_sb + b) * 8;
+    cp[0] = sv[0]; cp[1] = sv[1]; cp[2] = sv[2];
+    cp[3] = mv[0]; cp[4] = mv[1]; cp[5] = mv[2];
+    cp[6] = s_ch;
+    cp[7] = mv[3];
+  }
+}
+
+// per account: the diagnostics gathered in block order, the certificate,
+// and on failure the refinement of bands / cap and the row a null-direction
+// step releases (the next round's polish_rows adopts the proposals)
+__global__ __launch_bounds__(64) void polish_decide_kernel(PolishArgs A, fqp_result R,
+                                                           int final_pass) {
+  __shared__ int s_done;
+  const int G = A.G, tid = threadIdx.x;
+  const int slot = blockIdx.x;
+  if (slot >= *A.m_act) return;
+  const int a = A.act[slot];
+  int* ps = A.pstate + (size_t)a * kPStateStride;
+  if (ps[PS_DONE] || (ps[PS_STALL] && !final_pass)) return;
+  // lane l takes blocks l, l + 64, ... in order; then a fixed butterfly
+  double sw = 0.0, turn = 0.0, obj = 0.0, dmax = 0.0, box = 0.0, snapm = 0.0, chg = 0.0,
+         bad = 0.0;
+  for (int bb = tid; bb < A.n_sb; bb += 64) {
+    const double* cp = A.cpart + ((size_t)a * A.n_sb + bb) * 8;
+    sw += cp[0]; turn += cp[1]; obj += cp[2];
+    dmax = fmax(dmax, cp[3]); box = fmax(box, cp[4]); snapm = fmax(snapm, cp[5]);
+    chg += cp[6]; bad = fmax(bad, cp[7]);
+  }
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) {
+    sw += __shfl_xor(sw, o, 64); turn += __shfl_xor(turn, o, 64); obj += __shfl_xor(obj, o, 64);
+    dmax = fmax(dmax, __shfl_xor(dmax, o, 64)); box = fmax(box, __shfl_xor(box, o, 64));
+    snapm = fmax(snapm, __shfl_xor(snapm, o, 64)); chg += __shfl_xor(chg, o, 64);
+    bad = fmax(bad, __shfl_xor(bad, o, 64));
+  }
+  const float* par = A.par + (size_t)a * kNPar;
+  const float tauf = par[P_TAU];
+  const double* mult = A.mult + (size_t)a * (2 + G);
+  const Wk wkc = wk_of(A, a);
+  const double* s_gs = wkc.gsum;
+  int8_t* code = A.code_next + (size_t)a * A.n;
+  if (tid == 0) {
+    const double scale = wkc.misc[0];
+    const bool s_bad = wkc.misc[2] != 0.0 || bad != 0.0;
+    const double nu = mult[0], lam = mult[1];
     // comp: the largest |multiplier| x slack; gap: their sum, the duality
     // gap the multipliers leave (with stationarity and feasibility exact,
     // f(w) - f* <= gap)
@@ -1305,7 +1827,6 @@ __global__ __launch_bounds__(kPTC) void polish_check_kernel(PolishArgs A, fqp_re
     // can make it, r_comp <= eps alone does not)
     const bool ok = finite && r_prim <= A.eps_prim && r_dual <= A.eps_dual &&
                     r_comp <= A.eps_comp && gap <= A.eps_comp * fmax(fabs(obj_full), 1e-12);
-    for (int q = 0; q < 2 + G; ++q) gmult[q] = mult[q];
     ps[PS_ROUNDS] += 1;
     // keep the diagnostics of the latest pattern in the result arrays
     if (ok || final_pass) {
@@ -1328,9 +1849,10 @@ __global__ __launch_bounds__(kPTC) void polish_check_kernel(PolishArgs A, fqp_re
       R.status[a] = gates ? FQP_FEASIBLE_UNCERTIFIED : FQP_MAX_ITER;
     } else {
       // bands / cap refinement
-      int nchg = s_changed;
-      if (s_block >= 0) {                // release the row that blocks
-        code[s_block >> 4] = (int8_t)(s_block & 15);
+      int nchg = (int)chg;
+      const int blk = ps[PS_BLOCK];
+      if (blk >= 0) {                    // release the row that blocks
+        code[blk >> 4] = (int8_t)(blk & 15);
         ++nchg;
       }
       for (int g = 0; g < G; ++g) {
@@ -1352,36 +1874,37 @@ __global__ __launch_bounds__(kPTC) void polish_check_kernel(PolishArgs A, fqp_re
     }
   }
   __syncthreads();
-  if (final_pass || s_done) {
-    if (R.lam_band && G) {
-      for (int g = tid; g < G; g += kPTC) R.lam_band[(size_t)a * G + g] = mult[2 + g];
-    }
-  } else {
-    // the pattern failed: adopt the proposals for the next round
-    for (int i = tid; i < n; i += kPTC) code_r[i] = code[i];
-  }
+  if ((final_pass || s_done) && R.lam_band && G)
+    for (int g = tid; g < G; g += 64) R.lam_band[(size_t)a * G + g] = mult[2 + g];
 }
 
-static size_t polish_smem(int k, int G) {
-  // Kf (k^2 doubles) and a staging region; the Kf region first holds 64
-  // staged B rows (64 (k + 1) floats) and the staging region 64 weights +
-  // 64 indices
+static size_t polish_smem(int k, int G, int n_sb) {
+  // Kf (k^2 doubles) and a staging region; the Kf region also holds the
+  // list sums' per-wave partials (16 (k + G) doubles) and, before Kf is
+  // built, the row blocks' list offsets (2 (n_sb + 1) ints)
   const size_t a = sizeof(double) * ((size_t)k * k);
-  const size_t b = sizeof(float) * 64 * (size_t)(k + 1);
+  size_t b = sizeof(double) * (kPT / 64) * (size_t)(k + G);
+  const size_t c = sizeof(int) * 2 * ((size_t)n_sb + 1);
+  if (c > b) b = c;
   // staging: 16 rows of [b | V | pad | 1/d]
   const size_t rest = sizeof(double) * 16 * (size_t)(4 * ((k + kMaxG + 3 + 3) / 4) + 4);
-  const size_t factor = (a > b ? a : b) + (rest > 64 * 12 ? rest : 64 * 12);
-  // row-space path: H, V, X, f (doubles) and the free rows of B (floats)
+  const size_t factor = (a > b ? a : b) + rest;
+  // row-space path: H, V, X, f, F yX, b.F yX (doubles), the free rows of B (floats)
   const size_t ncol = (size_t)G + 3;
-  const size_t rows = sizeof(double) * (kSmallF * kSmallF + 2 * kSmallF * ncol + (size_t)k) +
+  const size_t rows = sizeof(double) * (kSmallF * kSmallF + 2 * kSmallF * ncol + 2 * (size_t)k +
+                                        kSmallF) +
                       sizeof(float) * kSmallF * (size_t)k;
-  return factor > rows ? factor : rows;
+  const size_t both = factor > rows ? factor : rows;
+  return both > c ? both : c;
 }
 
 hipError_t launch_polish_solve(const PolishArgs& A, hipStream_t st) {
-  const size_t smem = polish_smem(A.k, A.G);
-  hipError_t e = hipFuncSetAttribute((const void*)polish_solve_kernel,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
+  hipLaunchKernelGGL(polish_rows_kernel, dim3(A.n_sb, A.m_total), dim3(kRT), 0, st, A);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const size_t smem = polish_smem(A.k, A.G, A.n_sb);
+  e = hipFuncSetAttribute((const void*)polish_solve_kernel,
+                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(polish_solve_kernel, dim3(A.m_total), dim3(kPT), smem, st, A);
   return hipGetLastError();
@@ -1393,11 +1916,21 @@ hipError_t launch_polish_check_r(const PolishArgs& A, const fqp_result& R, int f
                      dim3(256), 0, st, A, final_pass);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(polish_check_kernel, dim3(A.m_total), dim3(kPTC), 0, st, A, R, final_pass);
+  hipLaunchKernelGGL(polish_sweep_kernel, dim3(A.n_sb, A.m_total), dim3(kRT), 0, st, A,
+                     final_pass);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(polish_pre_kernel, dim3(A.m_total), dim3(kPTC), 0, st, A, final_pass);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(polish_check_rows_kernel, dim3(A.n_sb, A.m_total), dim3(kRT), 0, st, A,
+                     final_pass);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(polish_decide_kernel, dim3(A.m_total), dim3(64), 0, st, A, R, final_pass);
   return hipGetLastError();
 }
 
 int polish_row_blocks(int n) { return (n + kGbRows - 1) / kGbRows; }
+int polish_pass_blocks(int n) { return (n + kRB - 1) / kRB; }
+int polish_rpart_stride(int k, int G) { return rpart_stride(k, G); }
 
 // The accounts of the active list still refining their pattern (neither
 // certified nor stalled in this pass), in list order: the later rounds of a

@@ -596,6 +596,11 @@ extern "C" fqp_error fqp_solve_batch(fqp_handle* h, const fqp_universe* U, const
   WS(pcount, int32_t, "pcount", 2);
   const int n_rb = polish_row_blocks(n);
   WS(gpart_p, double, "polish_gpart", (size_t)m * n_rb * 4);
+  const int n_sb = polish_pass_blocks(n);
+  WS(fseg, int32_t, "polish_fseg", (size_t)m * n);
+  WS(rpart, double, "polish_rpart", (size_t)m * n_sb * polish_rpart_stride(k, G));
+  WS(spart, double, "polish_spart", (size_t)m * n_sb * 4);
+  WS(cpart, double, "polish_cpart", (size_t)m * n_sb * 8);
   // the rest of Eq. 1: bounds of every constraint row [m][G] (bands, then
   // halfspaces); mu' = eta mu + gamma Sigma w_b and the constant of the
   // benchmark term when the book has a benchmark or a return scale
@@ -753,6 +758,7 @@ extern "C" fqp_error fqp_solve_batch(fqp_handle* h, const fqp_universe* U, const
   pa.code = code; pa.code_next = code_next; pa.flist = flist; pa.wk = wk; pa.wk_stride = wks; pa.wout = R->w;
   pa.mult = mult; pa.pstate = pstate; pa.gbase = gbase; pa.pcount = pcount;
   pa.n_rb = n_rb; pa.gpart = gpart_p;
+  pa.n_sb = n_sb; pa.fseg = fseg; pa.rpart = rpart; pa.spart = spart; pa.cpart = cpart;
   pa.hold_rec = hold_rec;
   HIP_CHECK(hipMemsetAsync(pcount, 0, 2 * sizeof(int32_t), st));
   pa.eps_prim = S.eps_prim; pa.eps_dual = S.eps_dual; pa.eps_comp = S.eps_comp;
