@@ -1215,7 +1215,6 @@ __global__ __launch_bounds__(256) void polish_gbase_kernel(PolishArgs A, int fin
   __shared__ int s_a[kGbAcc];
   __shared__ double s_gam[kGbAcc];
   __shared__ double s_red[4][kGbAcc][4];
-  __shared__ int s_hp[kGbAcc];
   const int k = A.k, n = A.n, tid = threadIdx.x;
   const int m_act = *A.m_act;
   const int g0 = blockIdx.y * kGbAcc;
@@ -1229,7 +1228,6 @@ __global__ __launch_bounds__(256) void polish_gbase_kernel(PolishArgs A, int fin
     }
     s_a[tid] = a;
     s_gam[tid] = a >= 0 ? (double)A.par[(size_t)a * kNPar + P_GAMMA] : 0.0;
-    s_hp[tid] = a >= 0 ? A.hold_ptr[a] : 0;
   }
   __syncthreads();
   const int k4 = (k + 3) & ~3;                 // <= kp: whole float4 of each row
@@ -1257,30 +1255,6 @@ __global__ __launch_bounds__(256) void polish_gbase_kernel(PolishArgs A, int fin
   amask = __builtin_amdgcn_readfirstlane(amask);
   const int i = blockIdx.x * kGbRows + tid;
   const bool row_ok = i < n;
-  // the accounts' own data of the row first (w, mu, the holding word and
-  // the held record it points to), so that their memory round trips overlap
-  // the B row's instead of following one another account by account
-  const int ic = min(i, n - 1), wd = ic >> 5, bit = ic & 31;
-  double wq[kGbAcc], mq[kGbAcc];
-  uint32_t hq[kGbAcc];
-  int pq[kGbAcc];
-#pragma unroll
-  for (int q = 0; q < kGbAcc; ++q) {
-    const int a = s_a[q];
-    wq[q] = 0.0; mq[q] = 0.0; hq[q] = 0u; pq[q] = 0;
-    if (a >= 0) {                              // uniform
-      wq[q] = A.wout[(size_t)a * n + ic];
-      mq[q] = mu_at(A, (size_t)a * n + ic);
-      hq[q] = A.hold[(size_t)a * A.W + wd];
-      pq[q] = A.hold_pre[(size_t)a * A.W + wd];
-    }
-  }
-  float w0q[kGbAcc];
-#pragma unroll
-  for (int q = 0; q < kGbAcc; ++q) {
-    w0q[q] = 0.f;
-    if ((hq[q] >> bit) & 1u) w0q[q] = A.hold_rec[2 * (s_hp[q] + pq[q] + popc_below(hq[q], bit))].x;
-  }
   double sig[kGbAcc];
 #pragma unroll
   for (int q = 0; q < kGbAcc; ++q) sig[q] = 0.0;
@@ -1306,14 +1280,14 @@ __global__ __launch_bounds__(256) void polish_gbase_kernel(PolishArgs A, int fin
     if (a < 0) continue;                       // uniform
     double gmax = 0.0, mumax = 0.0, turn = 0.0, bad = 0.0;
     if (row_ok) {
-      const double wi = wq[q];
+      const double wi = A.wout[(size_t)a * n + i];
       const double sg = sig[q] + di * wi;
-      const double mui = mq[q];
+      const double mui = mu_at(A, (size_t)a * n + i);
       const double v = s_gam[q] * sg - mui;
       A.gbase[(size_t)a * n + i] = v;
       gmax = fabs(s_gam[q] * sg);
       mumax = fabs(mui);
-      turn = fabs(wi - (double)w0q[q]);
+      turn = fabs(wi - (double)row_data(A, a, i, 0.f, 0.f).w0);
       if (!isfinite(v) || !isfinite(wi)) bad = 1.0;
     }
 #pragma unroll

@@ -205,6 +205,9 @@ struct fqp_handle {
   hipStream_t stream = nullptr;   // the handle's own stream (capturable)
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
   hipEvent_t ev_t[4] = {nullptr, nullptr, nullptr, nullptr};   // phase timing
+  // polish rounds: refining-account counts read back behind the launches
+  hipEvent_t ev_r[4] = {nullptr, nullptr, nullptr, nullptr};
+  int32_t* hcount = nullptr;      // [4] pinned host memory
   std::string err;
   fqp_stats stats{};
   std::map<std::string, DevBuf> bufs;
@@ -349,13 +352,20 @@ fqp_error fqp_create(fqp_handle** h, int device) {
             hipEventCreateWithFlags(&hh->ev_in, hipEventDisableTiming) == hipSuccess &&
             hipEventCreateWithFlags(&hh->ev_out, hipEventDisableTiming) == hipSuccess;
   for (int q = 0; q < 4 && ok; ++q) ok = hipEventCreate(&hh->ev_t[q]) == hipSuccess;
+  for (int q = 0; q < 4 && ok; ++q)
+    ok = hipEventCreateWithFlags(&hh->ev_r[q], hipEventDisableTiming) == hipSuccess;
+  ok = ok && hipHostMalloc((void**)&hh->hcount, 4 * sizeof(int32_t), hipHostMallocDefault) ==
+                 hipSuccess;
   if (!ok) {
     (void)hipGetLastError();
     if (hh->stream) (void)hipStreamDestroy(hh->stream);
     if (hh->ev_in) (void)hipEventDestroy(hh->ev_in);
     if (hh->ev_out) (void)hipEventDestroy(hh->ev_out);
-    for (int q = 0; q < 4; ++q)
+    for (int q = 0; q < 4; ++q) {
       if (hh->ev_t[q]) (void)hipEventDestroy(hh->ev_t[q]);
+      if (hh->ev_r[q]) (void)hipEventDestroy(hh->ev_r[q]);
+    }
+    if (hh->hcount) (void)hipHostFree(hh->hcount);
     delete hh;
     (void)hipSetDevice(cur);
     return FQP_ERR_HIP;
@@ -377,8 +387,11 @@ void fqp_destroy(fqp_handle* h) {
   if (h->stream) (void)hipStreamDestroy(h->stream);
   if (h->ev_in) (void)hipEventDestroy(h->ev_in);
   if (h->ev_out) (void)hipEventDestroy(h->ev_out);
-  for (int q = 0; q < 4; ++q)
+  for (int q = 0; q < 4; ++q) {
     if (h->ev_t[q]) (void)hipEventDestroy(h->ev_t[q]);
+    if (h->ev_r[q]) (void)hipEventDestroy(h->ev_r[q]);
+  }
+  if (h->hcount) (void)hipHostFree(h->hcount);
   (void)hipSetDevice(cur);
   delete h;
 }
@@ -889,16 +902,26 @@ extern "C" fqp_error fqp_solve_batch(fqp_handle* h, const fqp_universe* U, const
     pa.max_prop = 16;
     for (int r = 0; r < S.polish_rounds; ++r) {
       pa.first_round = (r == 0);
-      // later rounds: only the accounts still refining
+      // later rounds: only the accounts still refining; their count is also
+      // copied back, and the host stops launching rounds once the count of
+      // the round before this one (read without stalling the device, which
+      // still has this round queued) shows none left
       PolishArgs pr = pa;
       if (r > 0) {
         HIP_CHECK(launch_polish_list(m_act, act, pstate, pact, pm_act, st));
         pr.act = pact;
         pr.m_act = pm_act;
+        HIP_CHECK(hipMemcpyAsync(h->hcount + (r & 3), pm_act, sizeof(int32_t),
+                                 hipMemcpyDeviceToHost, st));
+        HIP_CHECK(hipEventRecord(h->ev_r[r & 3], st));
       }
       HIP_CHECK(launch_polish_solve(pr, st));
       HIP_CHECK(launch_polish_check_r(pr, *R, 0, st));
       h->stats.polish_calls += 1;
+      if (r >= 2) {
+        HIP_CHECK(hipEventSynchronize(h->ev_r[(r - 1) & 3]));
+        if (h->hcount[(r - 1) & 3] == 0) break;
+      }
     }
     hipLaunchKernelGGL(compact_kernel, dim3(1), dim3(256), 0, st, m, R->status, act, m_act);
     HIP_CHECK(hipGetLastError());
