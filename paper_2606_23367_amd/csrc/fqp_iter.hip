@@ -107,11 +107,30 @@ __global__ __launch_bounds__(256) void gram_partial_kernel(
   }
 }
 
-// sum the partials, add F~^-1, Cholesky, inverse, border vectors.
-// One workgroup per class.  Everything in float64 in global scratch.
-// kg <= kKfLds: the factor and the inverse live in LDS (dynamic shared
-// memory of 2 kg^2 doubles) and the inverse comes from wave-parallel
-// triangular solves; wider blocks work in the global scratch Kw
+// the Gram matrix: the row-block partials summed in block order, one entry
+// per thread (Gm = the first (kg + 1)^2 doubles of Kw)
+__global__ __launch_bounds__(256) void gram_reduce_kernel(int ne, int nparts, const double* part,
+                                                          double* Gm) {
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= ne) return;
+  double s = 0.0;
+  int p = 0;
+  for (; p + 8 <= nparts; p += 8) {
+    double b[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) b[u] = part[(size_t)(p + u) * ne + e];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s += b[u];
+  }
+  for (; p < nparts; ++p) s += part[(size_t)p * ne + e];
+  Gm[e] = s;
+}
+
+// add F~^-1 to the Gram matrix, invert, border vectors.  One workgroup per
+// class, everything in float64.  kg <= kKfLds: K is inverted in place in
+// LDS (dynamic shared memory of 2 kg^2 doubles) by Gauss-Jordan
+// elimination; wider blocks are factored (Cholesky) and inverted by
+// triangular sweeps in the global scratch Kw
 constexpr int kKfLds = 96;
 
 __global__ __launch_bounds__(1024) void kfactor_kernel(int k, int G, int kp, int nparts,
@@ -123,24 +142,13 @@ __global__ __launch_bounds__(1024) void kfactor_kernel(int k, int G, int kp, int
   const int kg = k + G, nk = kg + 1, ne = nk * nk;
   const bool in_lds = kg <= kKfLds;
   double* Gm = Kw;                   // [nk][nk]
-  double* L = in_lds ? kf_smem : Kw + ne;                 // [kg][kg] Cholesky factor
-  double* X = in_lds ? kf_smem + kg * kg : L + kg * kg;   // [kg][kg] inverse
+  // [kg][kg]: K, then (wide blocks) its Cholesky factor
+  double* L = in_lds ? kf_smem : Kw + ne;
+  double* X = in_lds ? kf_smem : L + kg * kg;             // [kg][kg] K^-1
   double* qv = Kw + ne + 2 * kg * kg;                     // [kg]
-  // sum of the row-block partials: batches of 16 independent loads
-  for (int e = threadIdx.x; e < ne; e += blockDim.x) {
-    double s = 0.0;
-    int p = 0;
-    for (; p + 16 <= nparts; p += 16) {
-      double b[16];
-#pragma unroll
-      for (int u = 0; u < 16; ++u) b[u] = part[(size_t)(p + u) * ne + e];
-#pragma unroll
-      for (int u = 0; u < 16; ++u) s += b[u];
-    }
-    for (; p < nparts; ++p) s += part[(size_t)p * ne + e];
-    Gm[e] = s;
-  }
-  __syncthreads();
+  // (Gm holds the sum of the row-block partials: gram_reduce_kernel)
+  (void)part;
+  (void)nparts;
   for (int e = threadIdx.x; e < kg * kg; e += blockDim.x) {
     int j = e / kg, l = e % kg;
     double v = Gm[j * nk + l];
@@ -148,6 +156,33 @@ __global__ __launch_bounds__(1024) void kfactor_kernel(int k, int G, int kp, int
     L[e] = v;
   }
   __syncthreads();
+  if (in_lds) {
+    // K^-1 by Gauss-Jordan elimination in place on the whole K: K is
+    // symmetric positive definite, so every pivot is positive and no row
+    // exchange is needed.  Step p scales row p by 1 / K_pp (its own entry
+    // becomes 1 / K_pp) and removes column p from every other row; a wave
+    // takes rows, its lanes consecutive columns (conflict-free LDS).
+    double* rowp = kf_smem + kg * kg;        // [kg] row p after scaling
+    double* colp = rowp + kg;                // [kg] column p before the step, 0 at p
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int nw = (int)(blockDim.x >> 6);
+    for (int p = 0; p < kg; ++p) {
+      const double ip = 1.0 / X[p * kg + p];
+      for (int j = threadIdx.x; j < kg; j += blockDim.x) {
+        rowp[j] = (j == p ? 1.0 : X[p * kg + j]) * ip;
+        colp[j] = (j == p) ? 0.0 : X[j * kg + p];
+      }
+      __syncthreads();
+      for (int i = wv; i < kg; i += nw) {
+        const double ci = colp[i];
+        for (int j = lane; j < kg; j += 64) {
+          const double x = (j == p) ? 0.0 : X[i * kg + j];
+          X[i * kg + j] = (i == p) ? rowp[j] : x - ci * rowp[j];
+        }
+      }
+      __syncthreads();
+    }
+  } else {
   // right-looking Cholesky, lower triangle of L
   for (int j = 0; j < kg; ++j) {
     if (threadIdx.x == 0) L[j * kg + j] = sqrt(fmax(L[j * kg + j], 1e-300));
@@ -165,9 +200,7 @@ __global__ __launch_bounds__(1024) void kfactor_kernel(int k, int G, int kp, int
   // inverse: L L^T X = I
   for (int e = threadIdx.x; e < kg * kg; e += blockDim.x) X[e] = (e / kg == e % kg) ? 1.0 : 0.0;
   __syncthreads();
-  if (in_lds) {
-    chol_solve_cols(L, kg, X, kg);               // ends with a barrier
-  } else {
+  {
   // right-looking forward and backward sweeps, every thread updating a
   // slice of the trailing block at each step
   for (int j = 0; j < kg; ++j) {
@@ -189,6 +222,7 @@ __global__ __launch_bounds__(1024) void kfactor_kernel(int k, int G, int kp, int
       X[i * kg + c] -= L[j * kg + i] * X[j * kg + c];
     }
     __syncthreads();
+  }
   }
   }
   // q = K^-1 c, sigma1 = 1^T Delta^-1 1 - c^T q
@@ -1446,6 +1480,11 @@ hipError_t launch_kfactor(int k, int G, int kp, int nparts, const double* part, 
                           float* q, float* sig, float* mbg, hipStream_t st) {
   const int kg = k + G;
   const size_t smem = kg <= kKfLds ? 2 * sizeof(double) * kg * kg : 0;
+  const int ne = (kg + 1) * (kg + 1);
+  hipLaunchKernelGGL(gram_reduce_kernel, dim3((ne + 255) / 256), dim3(256), 0, st, ne, nparts,
+                     part, Kw);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(kfactor_kernel, dim3(1), dim3(1024), smem, st, k, G, kp, nparts, part, f,
                      gamma, rho_b, Kw, Kinv, c, q, sig, mbg);
   return hipGetLastError();

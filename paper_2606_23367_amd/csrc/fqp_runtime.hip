@@ -568,7 +568,7 @@ extern "C" fqp_error fqp_solve_batch(fqp_handle* h, const fqp_universe* U, const
   // Every request comes before the first write to the caller's outputs: a
   // failed allocation returns FQP_ERR_ALLOC with the outputs untouched.
   WS(Bt, float, "Bt", (size_t)n * kp);
-  const int gram_rows = 128;
+  const int gram_rows = 32;          // row blocks of the Gram partials: 313 at n = 10,000
   const int nparts = (n + gram_rows - 1) / gram_rows;
   WS(gpart, double, "gram_part", (size_t)nparts * (kg + 1) * (kg + 1));
   const size_t kw_stride = (size_t)(kg + 1) * (kg + 1) + 2 * (size_t)kg * kg + kg + 16;
