@@ -1145,12 +1145,15 @@ __global__ __launch_bounds__(kPT) void polish_solve_kernel(PolishArgs A) {
     mult[1] = cap_on ? rr[col] : 0.0;
   }
   __syncthreads();
+  double turn_f = 0.0;                    // turnover of the free rows
   if (small) {
     // w_F = H^-1 (rhs - C^T eta) = X[:, rhs] - X[:, C] eta
     for (int t = tid; t < nF; t += kPT) {
       double v = Xs[t * ncol + nc];
       for (int p = 0; p < nc; ++p) v -= Xs[t * ncol + p] * wk.eta[p];
-      w[flist[t]] = v;
+      const int i = flist[t];
+      w[i] = v;
+      turn_f += fabs(v - (double)row_data(A, a, i, lbf, ubf).w0);
     }
   } else {
   // sol = Y[:, rhs] - Y[:, C] eta
@@ -1183,9 +1186,15 @@ __global__ __launch_bounds__(kPT) void polish_solve_kernel(PolishArgs A) {
       ++col;
     }
     if (cap_on) ct += sgn * wk.eta[col];
-    w[i] = (rhs - ct - bs) / (gam * (double)A.d[i]);
+    const double wi = (rhs - ct - bs) / (gam * (double)A.d[i]);
+    w[i] = wi;
+    turn_f += fabs(wi - (double)r.w0);
   }
   }                                       // factor-space path
+  // turnover of the polished w: the fixed rows' (from the row blocks) plus
+  // the free rows'
+  turn_f = bsum<double>(turn_f, shd);
+  if (tid == 0) wk.misc[3] = sturn + turn_f;
   // ---- y = F B^T w and the row sums of the polished w (nonzero rows), for
   // the gradient base and the certification: the fixed rows' parts from
   // above plus the free rows' --------------------------------------------
@@ -1200,8 +1209,8 @@ __global__ __launch_bounds__(kPT) void polish_solve_kernel(PolishArgs A) {
 
 // ---------------------------------------------------------------------------
 // polish_gbase: gb_i = gamma (Sigma w)_i - mu_i for every row, spread over
-// (row block, account) workgroups; per block: max |gamma Sigma w|, max |mu|,
-// turnover and a non-finite flag
+// (row block, account) workgroups; per block: max |gamma Sigma w|, max |mu|
+// and a non-finite flag (slot 2 unused: the turnover comes from the solve)
 // ---------------------------------------------------------------------------
 constexpr int kGbRows = 256;              // rows per gbase workgroup (one per thread)
 constexpr int kGbAcc = 16;                // accounts per gbase workgroup
@@ -1274,32 +1283,46 @@ __global__ __launch_bounds__(256) void polish_gbase_kernel(PolishArgs A, int fin
   }
   const double di = row_ok ? (double)A.d[i] : 0.0;
   const int wv = tid >> 6;
+  // the accounts four at a time: their w and mu loads in flight together
 #pragma unroll
-  for (int q = 0; q < kGbAcc; ++q) {
-    const int a = s_a[q];
-    if (a < 0) continue;                       // uniform
-    double gmax = 0.0, mumax = 0.0, turn = 0.0, bad = 0.0;
-    if (row_ok) {
-      const double wi = A.wout[(size_t)a * n + i];
-      const double sg = sig[q] + di * wi;
-      const double mui = mu_at(A, (size_t)a * n + i);
-      const double v = s_gam[q] * sg - mui;
-      A.gbase[(size_t)a * n + i] = v;
-      gmax = fabs(s_gam[q] * sg);
-      mumax = fabs(mui);
-      turn = fabs(wi - (double)row_data(A, a, i, 0.f, 0.f).w0);
-      if (!isfinite(v) || !isfinite(wi)) bad = 1.0;
+  for (int q0 = 0; q0 < kGbAcc; q0 += 4) {
+    double wq[4], mq[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int a = s_a[q0 + u];
+      wq[u] = 0.0;
+      mq[u] = 0.0;
+      if (a >= 0 && row_ok) {
+        wq[u] = A.wout[(size_t)a * n + i];
+        mq[u] = mu_at(A, (size_t)a * n + i);
+      }
     }
 #pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) {
-      gmax = fmax(gmax, __shfl_xor(gmax, o, 64));
-      mumax = fmax(mumax, __shfl_xor(mumax, o, 64));
-      turn += __shfl_xor(turn, o, 64);
-      bad = fmax(bad, __shfl_xor(bad, o, 64));
-    }
-    if ((tid & 63) == 0) {
-      s_red[wv][q][0] = gmax; s_red[wv][q][1] = mumax;
-      s_red[wv][q][2] = turn; s_red[wv][q][3] = bad;
+    for (int u = 0; u < 4; ++u) {
+      const int q = q0 + u;
+      const int a = s_a[q];
+      if (a < 0) continue;                     // uniform
+      double gmax = 0.0, mumax = 0.0, bad = 0.0;
+      if (row_ok) {
+        const double wi = wq[u];
+        const double sg = sig[q] + di * wi;
+        const double mui = mq[u];
+        const double v = s_gam[q] * sg - mui;
+        A.gbase[(size_t)a * n + i] = v;
+        gmax = fabs(s_gam[q] * sg);
+        mumax = fabs(mui);
+        if (!isfinite(v) || !isfinite(wi)) bad = 1.0;
+      }
+#pragma unroll
+      for (int o = 32; o >= 1; o >>= 1) {
+        gmax = fmax(gmax, __shfl_xor(gmax, o, 64));
+        mumax = fmax(mumax, __shfl_xor(mumax, o, 64));
+        bad = fmax(bad, __shfl_xor(bad, o, 64));
+      }
+      if ((tid & 63) == 0) {
+        s_red[wv][q][0] = gmax; s_red[wv][q][1] = mumax;
+        s_red[wv][q][2] = 0.0; s_red[wv][q][3] = bad;
+      }
     }
   }
   __syncthreads();
@@ -1560,21 +1583,21 @@ __global__ __launch_bounds__(kPTC) void polish_pre_kernel(PolishArgs A, int fina
   __syncthreads();                        // flags above are initialised
   const Wk wkc = wk_of(A, a);
   for (int g = tid; g < G; g += kPTC) s_gs[g] = wkc.gsum[g];
-  double gmax = 0.0, mumax = 0.0, turn0 = 0.0;
+  double gmax = 0.0, mumax = 0.0;
   int bad = 0;
   for (int rb = tid; rb < A.n_rb; rb += kPTC) {
     const double* gp = A.gpart + ((size_t)a * A.n_rb + rb) * 4;
     gmax = fmax(gmax, gp[0]);
     mumax = fmax(mumax, gp[1]);
-    turn0 += gp[2];
     if (gp[3] != 0.0) bad = 1;
   }
   if (bad) atomicOr(&s_bad, 1);
   {
-    double sv[1] = {turn0}, mv[2] = {gmax, mumax};
+    double sv[1] = {0.0}, mv[2] = {gmax, mumax};
     bred<1, 2>(sv, mv, s_red6);           // (also publishes s_gs)
-    turn0 = sv[0]; gmax = mv[0]; mumax = mv[1];
+    gmax = mv[0]; mumax = mv[1];
   }
+  const double turn0 = wkc.misc[3];       // turnover of w (polish_solve)
   const double scale = fmax(fmax(gmax, mumax), 1e-12);
   const int nd = ps[PS_ND];
   const int ncol = G + 3;
