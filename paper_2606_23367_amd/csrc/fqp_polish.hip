@@ -787,19 +787,35 @@ __global__ __launch_bounds__(kPT) void polish_solve_kernel(PolishArgs A) {
   int* s_ox = s_of + (S + 1);                    // [S + 1] nonzero-list offsets
   __shared__ double s_gfix[kMaxG];
   __shared__ double s_sx[2];
+  __shared__ unsigned s_sig;
   for (int bb = tid; bb < S; bb += kPT) {
     s_of[bb + 1] = (int)rp[(size_t)bb * rps + kg + 2];
     s_ox[bb + 1] = (int)rp[(size_t)bb * rps + kg + 3];
   }
+  // column j of the partials summed in block order, eight blocks' loads in
+  // flight at a time; the signature (column kg + 4) by one thread
   unsigned sig = 0u;
-  if (A.first_round)
-    for (int bb = 0; bb < S; ++bb) sig += (unsigned)rp[(size_t)bb * rps + kg + 4];
-  for (int j = tid; j < kg + 2; j += kPT) {
+  for (int j = tid; j < kg + 5; j += kPT) {
+    if (j >= kg + 2 && !(A.first_round && j == kg + 4)) continue;
     double v = 0.0;
-    for (int bb = 0; bb < S; ++bb) v += rp[(size_t)bb * rps + j];
+    unsigned su = 0u;
+    int bb = 0;
+    for (; bb + 8 <= S; bb += 8) {
+      double x[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) x[u] = rp[(size_t)(bb + u) * rps + j];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) { v += x[u]; su += (unsigned)x[u]; }
+    }
+    for (; bb < S; ++bb) {
+      const double x = rp[(size_t)bb * rps + j];
+      v += x;
+      su += (unsigned)x;
+    }
     if (j < k) { wk.yX[j] = v; wk.Fy[j] = v * (double)A.f[j]; }
     else if (j < kg) s_gfix[j - k] = v;
-    else s_sx[j - kg] = v;
+    else if (j < kg + 2) s_sx[j - kg] = v;
+    else s_sig = su;
   }
   __syncthreads();
   if (tid == 0) {
@@ -832,7 +848,7 @@ __global__ __launch_bounds__(kPT) void polish_solve_kernel(PolishArgs A) {
   const double sx = s_sx[0], sturn = s_sx[1];
   if (A.first_round) {
     if (tid == 0) {
-      sig += (unsigned)ps[PS_CAP] * 97u + (unsigned)ps[PS_BACT0] * 31u + (unsigned)ps[PS_BACT1] * 7u +
+      sig = s_sig + (unsigned)ps[PS_CAP] * 97u + (unsigned)ps[PS_BACT0] * 31u + (unsigned)ps[PS_BACT1] * 7u +
              (unsigned)ps[PS_BUP0] * 5u + (unsigned)ps[PS_BUP1] * 3u;
       s_same = (unsigned)ps[PS_SIG] == sig;
       ps[PS_SIG] = (int)sig;
@@ -1226,11 +1242,14 @@ __global__ __launch_bounds__(256) void polish_gbase_kernel(PolishArgs A, int fin
   __shared__ double s_red[4][kGbAcc][4];
   const int k = A.k, n = A.n, tid = threadIdx.x;
   const int m_act = *A.m_act;
-  const int g0 = blockIdx.y * kGbAcc;
+  // the active accounts spread over every account group of the grid (at
+  // most kGbAcc each): with few accounts left, more workgroups take part
+  const int gs = min(kGbAcc, (m_act + (int)gridDim.y - 1) / (int)gridDim.y);
+  const int g0 = blockIdx.y * gs;
   if (g0 >= m_act) return;
   if (tid < kGbAcc) {
     int a = -1;
-    if (g0 + tid < m_act) {
+    if (tid < gs && g0 + tid < m_act) {
       const int aa = A.act[g0 + tid];
       const int* ps = A.pstate + (size_t)aa * kPStateStride;
       if (!(ps[PS_DONE] || (ps[PS_STALL] && !final_pass))) a = aa;
