@@ -858,6 +858,9 @@ __global__ __launch_bounds__(kCapT, 8) void prox_kernel(IterArgs A, int zmode) {
   const int H = A.hold_ptr[a + 1] - hptr;
   float lo = 0.f, hi_b = INFINITY, best_feas = INFINITY;
   bool done = !capped;
+  // a zero lower bound (every long-only account): the soft threshold and
+  // the box reduce to min(max(v - th, 0), ub), the same value bit for bit
+  const bool lb0 = lbp == 0.f;
 
   const float* va = A.v + (size_t)a * n;
   const size_t wa = (size_t)a * A.W;
@@ -925,14 +928,26 @@ __global__ __launch_bounds__(kCapT, 8) void prox_kernel(IterArgs A, int zmode) {
   for (int it = 0; it < 48 && !done; ++it) {          // done is uniform
     const float th = (kap + lam) * irho;
     float g = 0.f, nf = 0.f;
+    if (lb0) {                             // uniform: z = min(max(v - th, 0), ub)
 #pragma unroll
-    for (int q = 0; q < Q; ++q) {
-      if (q * kCapT < n) {                 // uniform
-        const bool in_box = (box_bits >> q) & 1u;
-        float z = fminf(vr[q] + th, fmaxf(0.f, vr[q] - th));
-        z = in_box ? fminf(fmaxf(z, lbp), ubp) : 0.f;
-        g += fabsf(z);
-        nf += (in_box && z != 0.f && z > lbp && z < ubp) ? 1.f : 0.f;
+      for (int q = 0; q < Q; ++q) {
+        if (q * kCapT < n) {               // uniform
+          const bool in_box = (box_bits >> q) & 1u;
+          const float z = in_box ? fminf(fmaxf(vr[q] - th, 0.f), ubp) : 0.f;
+          g += z;
+          nf += (z > 0.f && z < ubp) ? 1.f : 0.f;
+        }
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < Q; ++q) {
+        if (q * kCapT < n) {               // uniform
+          const bool in_box = (box_bits >> q) & 1u;
+          float z = fminf(vr[q] + th, fmaxf(0.f, vr[q] - th));
+          z = in_box ? fminf(fmaxf(z, lbp), ubp) : 0.f;
+          g += fabsf(z);
+          nf += (in_box && z != 0.f && z > lbp && z < ubp) ? 1.f : 0.f;
+        }
       }
     }
     if (tid < H) {
@@ -1002,8 +1017,12 @@ __global__ __launch_bounds__(kCapT, 8) void prox_kernel(IterArgs A, int zmode) {
         z = s_hz[j];
       } else {
         const bool in_box = (s_ew[i >> 5] >> b) & 1u;
-        z = fminf(vr[q] + th, fmaxf(0.f, vr[q] - th));
-        z = in_box ? fminf(fmaxf(z, lbp), ubp) : 0.f;
+        if (lb0) {
+          z = in_box ? fminf(fmaxf(vr[q] - th, 0.f), ubp) : 0.f;
+        } else {
+          z = fminf(vr[q] + th, fmaxf(0.f, vr[q] - th));
+          z = in_box ? fminf(fmaxf(z, lbp), ubp) : 0.f;
+        }
       }
       prox_out(o, zmode, i, v, z, A.d[i], rho, gam, alpha);
     }
