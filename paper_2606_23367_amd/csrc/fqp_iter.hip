@@ -132,6 +132,7 @@ __global__ __launch_bounds__(256) void gram_reduce_kernel(int ne, int nparts, co
 // elimination; wider blocks are factored (Cholesky) and inverted by
 // triangular sweeps in the global scratch Kw
 constexpr int kKfLds = 96;
+constexpr int kKfRows = kKfLds / 16;     // rows per wave of the in-LDS inversion (16 waves)
 
 __global__ __launch_bounds__(1024) void kfactor_kernel(int k, int G, int kp, int nparts,
                                const double* part, const float* f,
@@ -173,12 +174,26 @@ __global__ __launch_bounds__(1024) void kfactor_kernel(int k, int G, int kp, int
         colp[j] = (j == p) ? 0.0 : X[j * kg + p];
       }
       __syncthreads();
-      for (int i = wv; i < kg; i += nw) {
-        const double ci = colp[i];
-        for (int j = lane; j < kg; j += 64) {
-          const double x = (j == p) ? 0.0 : X[i * kg + j];
-          X[i * kg + j] = (i == p) ? rowp[j] : x - ci * rowp[j];
-        }
+      // a wave's rows (at most kKfRows: kg <= 96 with 16 waves) are all
+      // read before any is written, so the LDS round trips overlap
+      const double r0 = lane < kg ? rowp[lane] : 0.0;
+      const double r1 = lane + 64 < kg ? rowp[lane + 64] : 0.0;
+      double x0[kKfRows], x1[kKfRows], cr[kKfRows];
+#pragma unroll
+      for (int t = 0; t < kKfRows; ++t) {
+        const int i = wv + nw * t;
+        x0[t] = (i < kg && lane < kg) ? X[i * kg + lane] : 0.0;
+        x1[t] = (i < kg && lane + 64 < kg) ? X[i * kg + lane + 64] : 0.0;
+        cr[t] = i < kg ? colp[i] : 0.0;
+      }
+#pragma unroll
+      for (int t = 0; t < kKfRows; ++t) {
+        const int i = wv + nw * t;
+        if (i >= kg) continue;
+        if (lane < kg)
+          X[i * kg + lane] = (i == p) ? r0 : ((lane == p) ? 0.0 : x0[t]) - cr[t] * r0;
+        if (lane + 64 < kg)
+          X[i * kg + lane + 64] = (i == p) ? r1 : ((lane + 64 == p) ? 0.0 : x1[t]) - cr[t] * r1;
       }
       __syncthreads();
     }
