@@ -1177,12 +1177,18 @@ __global__ __launch_bounds__(kKsT) void ksolve_kernel(KArgs A) {
   const size_t M = A.m_total;
   const int n_rt = tile_map(*A.m_act, A.n, A.nblk, 0).n_rt;
   float* par = A.par + (size_t)a * kNPar;
-  const int cls = (int)par[P_CLASS];
+  // (one class: no dependent load of the account's class before K^-1)
+  const int cls = A.ncls == 1 ? 0 : (int)par[P_CLASS];
   const float* Kinv = A.Kinv + (size_t)cls * kp * kp;
   const float* cv = A.cvec + (size_t)cls * kp;
   const float* qv = A.qvec + (size_t)cls * kp;
   const float sig1 = A.sig1[cls];
   const float rhob = par[P_RHOB];
+  // this thread's entries of q and c (kg <= kMaxKp <= kKsT: one each),
+  // loaded with the partials rather than on the way to nu and the rhs
+  static_assert(kMaxKp <= kKsT, "one factor column per thread");
+  const float qvj = tid < kg ? qv[tid] : 0.f;
+  const float cvj = tid < kg ? cv[tid] : 0.f;
 
   // nsp threads per factor column split the row tiles (and below the
   // K^-1 rows), so that more independent loads are in flight.  Each thread
@@ -1244,8 +1250,7 @@ __global__ __launch_bounds__(kKsT) void ksolve_kernel(KArgs A) {
     __syncthreads();
   }
   // nu = (1 - s0 + q^T t) / sigma1
-  double part = 0.0;
-  for (int j = tid; j < kg; j += kKsT) part += (double)qv[j] * t[j];
+  double part = tid < kg ? (double)qvj * t[tid] : 0.0;
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) part += __shfl_xor(part, o, 64);
   if ((tid & 63) == 0) red[tid >> 6] = part;
@@ -1257,8 +1262,7 @@ __global__ __launch_bounds__(kKsT) void ksolve_kernel(KArgs A) {
   }
   __syncthreads();
   const double nu = s_nu;
-  for (int j = tid; j < kg; j += kKsT) rhs[j] = t[j] + nu * (double)cv[j];
-  __syncthreads();
+  if (tid < kg) rhs[tid] = t[tid] + nu * (double)cvj;
   __syncthreads();
   if (tid < nsp * kp) {
     const int j = jq, q = qq;

@@ -47,6 +47,7 @@ struct IterArgs {
 struct KArgs {
   int kp, k, G, n, nblk, m_total;    // nblk: workgroups of the CONTRACT pass
   int nblk_p;                        // workgroups of the PROJECT pass
+  int ncls;                          // gamma classes (1: no per-account class lookup)
   const int* m_act;
   const int* act;
   const float* part;

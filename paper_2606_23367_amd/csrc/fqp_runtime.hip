@@ -753,6 +753,7 @@ extern "C" fqp_error fqp_solve_batch(fqp_handle* h, const fqp_universe* U, const
   std::memset(&ka, 0, sizeof(ka));
   ka.kp = kp; ka.k = k; ka.G = G; ka.n = n; ka.nblk = n_rt * acc_tiles; ka.m_total = m;
   ka.nblk_p = n_rt_p * acc_tiles;
+  ka.ncls = ncls;
   ka.m_act = m_act; ka.act = act;
   ka.part = part; ka.par = par; ka.pp = pp; ka.Kinv = Kinv; ka.cvec = cvec;
   ka.qvec = qvec; ka.sig1 = sig1; ka.mbg = mbg; ka.zb = zb; ka.vb = vb;
