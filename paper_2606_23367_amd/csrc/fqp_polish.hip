@@ -555,6 +555,7 @@ constexpr int kRT = 256;                  // threads of a row-block workgroup
 constexpr int kRR = 2;                    // rows per thread
 constexpr int kRB = kRT * kRR;            // rows per block
 constexpr int kRW = kRT / 64;             // waves
+constexpr int kPU = 2;                    // rows per thread and step of the one-workgroup sweeps
 
 // polish_rows partials per (account, block): the column sums of B~ over the
 // block's nonzero fixed rows (k + G), then budget sum, turnover sum, free
@@ -1509,17 +1510,19 @@ __device__ void sweep_step(const PolishArgs& A, int a, const int* ps, const Swee
   if (ps[PS_CAP]) mult[1] += st * ncap;
 }
 
-// the check passes' per-row inputs of kRR rows (all loads issued together)
+// the check passes' per-row inputs of U rows (all loads issued together)
+template <int U>
 struct CheckIn {
-  int ii[kRR], cc[kRR], grp[kRR];
-  double gb[kRR], w[kRR], mu[kRR];
-  RowData rd[kRR];
+  int ii[U], cc[U], grp[U];
+  double gb[U], w[U], mu[U];
+  RowData rd[U];
 };
+template <int U>
 __device__ __forceinline__ void check_in(const PolishArgs& A, int a, int base, int stride,
-                                         bool want_mu, float lbf, float ubf, CheckIn& I) {
+                                         bool want_mu, float lbf, float ubf, CheckIn<U>& I) {
   const int n = A.n;
 #pragma unroll
-  for (int u = 0; u < kRR; ++u) {
+  for (int u = 0; u < U; ++u) {
     I.ii[u] = base + u * stride + (int)threadIdx.x;
     const int ic = min(I.ii[u], n - 1);
     const size_t off = (size_t)a * n + ic;
@@ -1529,7 +1532,7 @@ __device__ __forceinline__ void check_in(const PolishArgs& A, int a, int base, i
     I.mu[u] = want_mu ? mu_at(A, off) : 0.0;
     I.grp[u] = A.Gl ? A.group[ic] : 0;
   }
-  row_data_n<kRR>(A, a, I.ii, lbf, ubf, I.rd);
+  row_data_n<U>(A, a, I.ii, lbf, ubf, I.rd);
 }
 
 // per-block bounds of the one-direction sweep: [m][n_sb][4] = Lo, Up and
@@ -1550,7 +1553,7 @@ __global__ __launch_bounds__(kRT) void polish_sweep_kernel(PolishArgs A, int fin
   const double* gmult = A.mult + (size_t)a * (2 + G);
   for (int q = tid; q < 2 + G; q += kRT) mult[q] = gmult[q];
   if (tid == 0) { s_key[0] = INT_MAX; s_key[1] = INT_MAX; }
-  CheckIn I;
+  CheckIn<kRR> I;
   check_in(A, a, b * kRB, kRT, false, lbf, ubf, I);
   __syncthreads();
   const SweepDir D = sweep_dir(ps, wk_of(A, a).nul, mult);
@@ -1647,11 +1650,11 @@ __global__ __launch_bounds__(kPTC) void polish_pre_kernel(PolishArgs A, int fina
         const SweepDir D = sweep_dir(ps, wkc.nul + q * ncol, mult);
         double Lo = -INFINITY, Up = INFINITY;
         int loKey = INT_MAX, upKey = INT_MAX;
-        for (int base = 0; base < n; base += kRR * kPTC) {
-          CheckIn I;
+        for (int base = 0; base < n; base += kPU * kPTC) {
+          CheckIn<kPU> I;
           check_in(A, a, base, kPTC, false, lbf, ubf, I);
 #pragma unroll
-          for (int u = 0; u < kRR; ++u)
+          for (int u = 0; u < kPU; ++u)
             if (I.ii[u] < n)
               sweep_row(A, ps, D, mult, I.ii[u], I.cc[u], I.gb[u], I.w[u], I.grp[u], I.rd[u],
                         kap, phi, Lo, Up, loKey, upKey);
@@ -1703,7 +1706,7 @@ __global__ __launch_bounds__(kRT) void polish_check_rows_kernel(PolishArgs A, in
   const double* gmult = A.mult + (size_t)a * (2 + G);
   for (int q = tid; q < 2 + G; q += kRT) mult[q] = gmult[q];
   if (tid == 0) s_ch = 0;
-  CheckIn I;
+  CheckIn<kRR> I;
   check_in(A, a, b * kRB, kRT, true, lbf, ubf, I);
   __syncthreads();
   const double nu = mult[0], lam = mult[1];
