@@ -44,9 +44,10 @@ static_assert(kNPState <= kPStateStride, "polish bookkeeping does not fit");
 constexpr double kSnap = 1e-10;
 constexpr int kSmallF = 64;               // free sets solved in row space
 constexpr int kMaxNull = 8;
-// one workgroup of 16 waves per account: the row passes are latency bound
+// the per-account kernels: one workgroup of 16 waves per account (their
+// serial parts are latency bound); the row passes run on row blocks below
 constexpr int kPT = 1024;                 // polish_solve
-constexpr int kPTC = 1024;                // polish_check
+constexpr int kPTC = 1024;                // polish_pre
 constexpr int kPW = kPT / 64;             // most waves of either
 
 // The points, kinks and slopes of one asset's line, as scalar fields: a
@@ -294,7 +295,7 @@ __device__ __forceinline__ void set_band(int* ps, int g, bool act, bool up) {
   *pu = up ? (*pu | (1 << b)) : (*pu & ~(1 << b));
 }
 
-// block reductions: wave shuffles, then one partial per wave
+// block sum: wave shuffles, then one partial per wave
 template <typename T>
 __device__ T bsum(T v, T* sh) {
 #pragma unroll
@@ -305,18 +306,6 @@ __device__ T bsum(T v, T* sh) {
   T r = sh[0];
   const int nw = (int)(blockDim.x >> 6);
   for (int q = 1; q < nw; ++q) r += sh[q];
-  return r;
-}
-template <typename T>
-__device__ T bmax(T v, T* sh) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-  __syncthreads();
-  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
-  __syncthreads();
-  T r = sh[0];
-  const int nw = (int)(blockDim.x >> 6);
-  for (int q = 1; q < nw; ++q) r = fmax(r, sh[q]);
   return r;
 }
 
