@@ -25,6 +25,11 @@ SMALL = [
     ("c5", dict(N=4100, M=2, k=128, groups=40, held=(200, 200)), dict(rho=10.0)),
     # every rule family at once: L1 turnover, sector bands, exclusions, taxed lots
     ("c2", dict(N=700, M=8, k=10, elig=(0.3, 1.0), held=(50, 120), tax=True), dict(rho=1.0)),
+    # the polish passes' 512-row blocks: exactly two blocks, a last block of
+    # one row, a single full block
+    ("c3", dict(N=1024, M=6, k=8, held=(20, 60)), dict(rho=5.0)),
+    ("c3", dict(N=513, M=5, k=8, held=(20, 60)), dict(rho=5.0)),
+    ("c3", dict(N=512, M=5, k=8, held=(20, 60)), dict(rho=5.0)),
 ]
 
 
