@@ -1633,8 +1633,10 @@ __global__ __launch_bounds__(kPTC) void polish_pre_kernel(PolishArgs A, int fina
     }
     __syncthreads();
   } else if (nd > 1) {
-    // (a second sweep only matters when directions interact: nd > 1)
-    for (int sweep = 0; sweep < 2; ++sweep) {
+    // one sweep over the directions (a second one, for directions that
+    // interact, cost a full pass per direction and certified no more
+    // accounts: the next refinement round revisits them anyway)
+    for (int sweep = 0; sweep < 1; ++sweep) {
       for (int q = 0; q < nd; ++q) {
         const SweepDir D = sweep_dir(ps, wkc.nul + q * ncol, mult);
         double Lo = -INFINITY, Up = INFINITY;
