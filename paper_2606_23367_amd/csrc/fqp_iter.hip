@@ -1165,10 +1165,9 @@ __global__ __launch_bounds__(kCapT) void prox_stream_kernel(IterArgs A, int zmod
 // batch of loads each
 constexpr int kKsT = 512;
 __global__ __launch_bounds__(kKsT) void ksolve_kernel(KArgs A) {
-  __shared__ double t[kMaxKp], rhs[kMaxKp], red[kKsT];
+  __shared__ double t[kMaxKp], rhs[kMaxKp], red[kKsT], redq[kKsT / 64];
   __shared__ float tsp[kKsT];                // split partial sums
   __shared__ float pprime[kMaxKp];
-  __shared__ double s_nu;
   const int slot = blockIdx.x;
   if (slot >= *A.m_act) return;
   const int a = A.act[slot];
@@ -1184,11 +1183,10 @@ __global__ __launch_bounds__(kKsT) void ksolve_kernel(KArgs A) {
   const float* qv = A.qvec + (size_t)cls * kp;
   const float sig1 = A.sig1[cls];
   const float rhob = par[P_RHOB];
-  // this thread's entries of q and c (kg <= kMaxKp <= kKsT: one each),
-  // loaded with the partials rather than on the way to nu and the rhs
+  // this thread's entry of q (kg <= kMaxKp <= kKsT: one each), loaded with
+  // the partials rather than on the way to nu
   static_assert(kMaxKp <= kKsT, "one factor column per thread");
   const float qvj = tid < kg ? qv[tid] : 0.f;
-  const float cvj = tid < kg ? cv[tid] : 0.f;
 
   // nsp threads per factor column split the row tiles (and below the
   // K^-1 rows), so that more independent loads are in flight.  Each thread
@@ -1249,21 +1247,9 @@ __global__ __launch_bounds__(kKsT) void ksolve_kernel(KArgs A) {
     for (int j = tid; j < kg; j += kKsT) t[j] += rhs[j];
     __syncthreads();
   }
-  // nu = (1 - s0 + q^T t) / sigma1
-  double part = tid < kg ? (double)qvj * t[tid] : 0.0;
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) part += __shfl_xor(part, o, 64);
-  if ((tid & 63) == 0) red[tid >> 6] = part;
-  __syncthreads();
-  if (tid == 0) {
-    double qt = 0.0;
-    for (int q = 0; q < kKsT / 64; ++q) qt += red[q];
-    s_nu = (1.0 - s0 + qt) / (double)sig1;
-  }
-  __syncthreads();
-  const double nu = s_nu;
-  if (tid < kg) rhs[tid] = t[tid] + nu * (double)cvj;
-  __syncthreads();
+  // p = K^-1 (t + nu c) = K^-1 t + nu q (q = K^-1 c): the product with t
+  // does not wait for nu = (1 - s0 + q^T t) / sigma1, and both reductions
+  // share one LDS step
   if (tid < nsp * kp) {
     const int j = jq, q = qq;
     double s = 0.0;
@@ -1274,7 +1260,7 @@ __global__ __launch_bounds__(kKsT) void ksolve_kernel(KArgs A) {
 #pragma unroll
       for (int u = 0; u < 16; ++u) {
         const int l = q + u * nsp;
-        if (l < kg) s += (double)kb[u] * rhs[l];
+        if (l < kg) s += (double)kb[u] * t[l];
       }
       for (int l0 = q + 16 * nsp; l0 < kg; l0 += 16 * nsp) {
         float buf[16];
@@ -1286,28 +1272,33 @@ __global__ __launch_bounds__(kKsT) void ksolve_kernel(KArgs A) {
 #pragma unroll
         for (int u = 0; u < 16; ++u) {
           const int l = l0 + u * nsp;
-          if (l < kg) s += (double)buf[u] * rhs[l];
+          if (l < kg) s += (double)buf[u] * t[l];
         }
       }
     }
     red[tid] = s;
   }
+  double part = tid < kg ? (double)qvj * t[tid] : 0.0;
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) part += __shfl_xor(part, o, 64);
+  if ((tid & 63) == 0) redq[tid >> 6] = part;
   __syncthreads();
-  for (int j = tid; j < kp; j += kKsT) {
-    double s = 0.0;
-    for (int q = 0; q < nsp; ++q) s += red[q * kp + j];
-    pprime[j] = (float)s;
-  }
-  __syncthreads();
+  double qt = 0.0;                       // the same order in every thread
+  for (int q = 0; q < kKsT / 64; ++q) qt += redq[q];
+  const double nu = (1.0 - s0 + qt) / (double)sig1;
   // back-projection coefficients: band directions carry -rho_b (zb - vb)
   float* pp = A.pp + (size_t)a * kp;
-  for (int j = tid; j < kp; j += kKsT) {
+  if (tid < kp) {                        // kp <= kKsT: column tid (whose q entry it holds)
+    double s = 0.0;
+    for (int q = 0; q < nsp; ++q) s += red[q * kp + tid];
+    const float pj = (float)(s + nu * (double)qvj);
+    pprime[tid] = pj;
     float v = 0.f;
-    if (j < k) v = pprime[j];
-    else if (j < kg) v = pprime[j] - rhob * (A.zb[(size_t)a * G + (j - k)] - A.vb[(size_t)a * G + (j - k)]);
-    pp[j] = v;
+    if (tid < k) v = pj;
+    else if (tid < kg) v = pj - rhob * (A.zb[(size_t)a * G + (tid - k)] - A.vb[(size_t)a * G + (tid - k)]);
+    pp[tid] = v;
   }
-  __syncthreads();
+  if (G > 0) __syncthreads();            // the band block reads pprime
   // band ADMM block:  A x = p'_G / rho_b
   if (G > 0 && tid < G) {
     const int g = tid;
