@@ -148,22 +148,32 @@ __global__ void pack_scan_kernel(PackArgs A) {
 __global__ __launch_bounds__(256) void pack_fill_kernel(PackArgs A) {
   __shared__ int sh[256];
   __shared__ int carry;
+  __shared__ uint32_t s_bits[256];
   const int a = blockIdx.x;
   const int n = A.n, W = A.W;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int base_rec = A.hold_ptr[a];
   const int t0 = A.tax_ptr ? A.tax_ptr[a] : 0;
   const int t1 = A.tax_ptr ? A.tax_ptr[a + 1] : 0;
   if (threadIdx.x == 0) carry = 0;
   __syncthreads();
   for (int wb = 0; wb < W; wb += 256) {
-    const int wd = wb + threadIdx.x;
-    uint32_t bits = 0;
-    if (wd < W) {
-      for (int b = 0; b < 32; ++b) {
-        const int i = 32 * wd + b;
-        if (i < n && A.w0[(size_t)a * n + i] != 0.f) bits |= (1u << b);
+    // the holding words wb .. wb + 255: their rows read coalesced, one per
+    // thread and step, each wave's 64 rows turned into two words by a ballot
+#pragma unroll 8
+    for (int s = 0; s < 32; ++s) {
+      const int i = 32 * wb + 256 * s + threadIdx.x;
+      const bool h = i < n && A.w0[(size_t)a * n + i] != 0.f;
+      const unsigned long long mk = __ballot(h);
+      if (lane == 0) {
+        const int wr = 8 * s + 2 * wv;           // (256 s + 64 wv) / 32
+        s_bits[wr] = (uint32_t)mk;
+        s_bits[wr + 1] = (uint32_t)(mk >> 32);
       }
     }
+    __syncthreads();
+    const int wd = wb + threadIdx.x;
+    const uint32_t bits = (wd < W) ? s_bits[threadIdx.x] : 0u;
     const int pc = __popc(bits);
     sh[threadIdx.x] = pc;
     __syncthreads();
@@ -184,20 +194,27 @@ __global__ __launch_bounds__(256) void pack_fill_kernel(PackArgs A) {
         const int idx = base_rec + pre + r;
         ++r;
         A.hold_w0[idx] = A.w0[(size_t)a * n + i];
-        // binary search of asset i among the account's lot entries
-        int lo = t0, hi = t1 - 1, found = -1;
-        while (lo <= hi) {
-          const int mid = (lo + hi) >> 1;
-          const int v = A.tax_asset[mid];
-          if (v == i) { found = mid; break; }
-          if (v < i) lo = mid + 1; else hi = mid - 1;
-        }
-        A.hold_tax[idx] = found;
+        A.hold_tax[idx] = -1;                    // set below for a taxed name
       }
     }
     __syncthreads();
     if (threadIdx.x == 255) carry += sh[255];
     __syncthreads();
+  }
+  // every lot entry points its name's record at itself: the record index is
+  // the name's rank among the held rows, from the word and prefix written
+  // above.  An entry off the book or on a name not held (an account the
+  // count pass already marked invalid) writes nothing, so it cannot reach
+  // another account's records.
+  __threadfence_block();
+  __syncthreads();
+  for (int j = t0 + threadIdx.x; j < t1; j += 256) {
+    const int i = A.tax_asset[j];
+    if (i < 0 || i >= n) continue;
+    const size_t wi = (size_t)a * W + (i >> 5);
+    const uint32_t hw = A.hold[wi];
+    if (!((hw >> (i & 31)) & 1u)) continue;
+    A.hold_tax[base_rec + A.hold_pre[wi] + __popc(hw & ((1u << (i & 31)) - 1u))] = j;
   }
 }
 
