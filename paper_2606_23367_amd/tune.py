@@ -145,9 +145,11 @@ def autotune(P: DeviceProblem, solver: Optional[Solver] = None, sample: int = 64
             ok_t, dt_t = 0, 0.0
             for B in books:
                 s.solve(B, **cfg)                          # warm-up of this layout
-                ok, dt = _timed(s, B, cfg)
+                # the layouts differ by about a percent: the better of two
+                # timings per book keeps one noisy run from deciding
+                (ok, dt), (_, dt2) = _timed(s, B, cfg), _timed(s, B, cfg)
                 ok_t += ok
-                dt_t += dt
+                dt_t += min(dt, dt2)
             if verbose:
                 print(f"autotune layout {cfg}: {ok_t} certified, {dt_t * 1e3:.1f} ms", flush=True)
             lay.append(((-ok_t, dt_t), cfg))
