@@ -120,16 +120,20 @@ def timed_solves(solver, P, steps, settings, profile=0, prox=None):
     t0 = time.perf_counter()
     for _ in range(steps):
         out = solver.solve(P, out=out, profile=profile, **settings)
+        # the call returns with its statuses counted (stats.n_solved: the
+        # accounts certified); the iteration counts are copied on the device
+        # and read after the timed region, so no step waits on the host
         st = solver.stats()
-        iters.append(out["iters"].cpu().numpy())
-        solved += int((out["status"] == 0).sum().item())
+        iters.append(out["iters"].clone())
+        solved += int(st["n_solved"])
         proj_ms += st["iter_kernel_ms"]
         con_ms += st["contract_kernel_ms"]
         if prox is not None:
             prox[0] += st["prox_kernel_ms"]
         launches += st["iter_launches"]
     torch.cuda.synchronize()
-    return time.perf_counter() - t0, solved, proj_ms, con_ms, launches, iters
+    dt = time.perf_counter() - t0
+    return dt, solved, proj_ms, con_ms, launches, [x.cpu().numpy() for x in iters]
 
 
 def copy_bandwidth(nbytes=1 << 30, reps=5):
