@@ -126,13 +126,13 @@ __global__ __launch_bounds__(256) void gram_reduce_kernel(int ne, int nparts, co
   Gm[e] = s;
 }
 
-// add F~^-1 to the Gram matrix, invert, border vectors.  One workgroup per
-// class, everything in float64.  kg <= kKfLds: K is inverted in place in
-// LDS (dynamic shared memory of 2 kg^2 doubles) by Gauss-Jordan
-// elimination; wider blocks are factored (Cholesky) and inverted by
-// triangular sweeps in the global scratch Kw
+// add F~^-1 to the Gram matrix, invert, border vectors.  One workgroup of
+// 16 waves per class, everything in float64.  kg <= kKfLds: K is inverted by
+// Gauss-Jordan elimination with the matrix held in registers (a wave owns
+// rows, its lanes two columns each); wider blocks are factored (Cholesky)
+// and inverted by triangular sweeps in the global scratch Kw
 constexpr int kKfLds = 96;
-constexpr int kKfRows = kKfLds / 16;     // rows per wave of the in-LDS inversion (16 waves)
+constexpr int kKfRows = kKfLds / 16;     // rows per wave of the in-register inversion (16 waves)
 
 __global__ __launch_bounds__(1024) void kfactor_kernel(int k, int G, int kp, int nparts,
                                const double* part, const float* f,
@@ -146,58 +146,92 @@ __global__ __launch_bounds__(1024) void kfactor_kernel(int k, int G, int kp, int
   // [kg][kg]: K, then (wide blocks) its Cholesky factor
   double* L = in_lds ? kf_smem : Kw + ne;
   double* X = in_lds ? kf_smem : L + kg * kg;             // [kg][kg] K^-1
-  double* qv = Kw + ne + 2 * kg * kg;                     // [kg]
+  // LDS after X (in-register path) or from its start (wide blocks): the
+  // border column c with its last entry (c_kg = 1^T Delta^-1 1), then q
+  double* cv = in_lds ? kf_smem + kg * kg + 4 * kg : kf_smem;   // [kg + 1]
+  double* qs = cv + kg + 1;                                     // [kg]
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int nw = (int)(blockDim.x >> 6);
   // (Gm holds the sum of the row-block partials: gram_reduce_kernel)
   (void)part;
   (void)nparts;
-  for (int e = threadIdx.x; e < kg * kg; e += blockDim.x) {
-    int j = e / kg, l = e % kg;
+  for (int j = threadIdx.x; j <= kg; j += blockDim.x) cv[j] = Gm[j * nk + kg];
+  auto k_entry = [&](int j, int l) {
     double v = Gm[j * nk + l];
     if (j == l) v += (j < k) ? 1.0 / (gamma * (double)f[j]) : 1.0 / rho_b;
-    L[e] = v;
-  }
-  __syncthreads();
+    return v;
+  };
   if (in_lds) {
-    // K^-1 by Gauss-Jordan elimination in place on the whole K: K is
-    // symmetric positive definite, so every pivot is positive and no row
-    // exchange is needed.  Step p scales row p by 1 / K_pp (its own entry
-    // becomes 1 / K_pp) and removes column p from every other row; a wave
-    // takes rows, its lanes consecutive columns (conflict-free LDS).
-    double* rowp = kf_smem + kg * kg;        // [kg] row p after scaling
-    double* colp = rowp + kg;                // [kg] column p before the step, 0 at p
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int nw = (int)(blockDim.x >> 6);
-    for (int p = 0; p < kg; ++p) {
-      const double ip = 1.0 / X[p * kg + p];
-      for (int j = threadIdx.x; j < kg; j += blockDim.x) {
-        rowp[j] = (j == p ? 1.0 : X[p * kg + j]) * ip;
-        colp[j] = (j == p) ? 0.0 : X[j * kg + p];
-      }
-      __syncthreads();
-      // a wave's rows (at most kKfRows: kg <= 96 with 16 waves) are all
-      // read before any is written, so the LDS round trips overlap
-      const double r0 = lane < kg ? rowp[lane] : 0.0;
-      const double r1 = lane + 64 < kg ? rowp[lane + 64] : 0.0;
-      double x0[kKfRows], x1[kKfRows], cr[kKfRows];
+    // K^-1 by Gauss-Jordan elimination in place: K is symmetric positive
+    // definite, so every pivot is positive and no row exchange is needed.
+    // Step p scales row p by 1 / K_pp (its own entry becomes 1 / K_pp) and
+    // removes column p from every other row.  Thread (wave w, lane) keeps
+    // entries (w + 16 t, lane) and (w + 16 t, lane + 64) in registers for
+    // the whole elimination; a step exchanges only row p and column p,
+    // through a pair of LDS buffers used alternately, so one barrier per
+    // step orders the writes of step p + 1 after every read of step p - 1.
+    double* rbuf = kf_smem + kg * kg;        // [2][kg] row p before scaling
+    double* cbuf = rbuf + 2 * kg;            // [2][kg] column p before the step
+    // every load is issued before any is used (indices clamped into the
+    // matrix, out-of-range entries set to zero afterwards)
+    const int c0 = min(lane, kg - 1), c1 = min(lane + 64, kg - 1);
+    const double fd0 = c0 < k ? (double)f[c0] : 1.0, fd1 = c1 < k ? (double)f[c1] : 1.0;
+    double x0[kKfRows], x1[kKfRows];
 #pragma unroll
-      for (int t = 0; t < kKfRows; ++t) {
-        const int i = wv + nw * t;
-        x0[t] = (i < kg && lane < kg) ? X[i * kg + lane] : 0.0;
-        x1[t] = (i < kg && lane + 64 < kg) ? X[i * kg + lane + 64] : 0.0;
-        cr[t] = i < kg ? colp[i] : 0.0;
-      }
-#pragma unroll
-      for (int t = 0; t < kKfRows; ++t) {
-        const int i = wv + nw * t;
-        if (i >= kg) continue;
-        if (lane < kg)
-          X[i * kg + lane] = (i == p) ? r0 : ((lane == p) ? 0.0 : x0[t]) - cr[t] * r0;
-        if (lane + 64 < kg)
-          X[i * kg + lane + 64] = (i == p) ? r1 : ((lane + 64 == p) ? 0.0 : x1[t]) - cr[t] * r1;
-      }
-      __syncthreads();
+    for (int t = 0; t < kKfRows; ++t) {
+      const int i = min(wv + nw * t, kg - 1);
+      x0[t] = Gm[i * nk + c0];
+      x1[t] = Gm[i * nk + c1];
     }
+    const double dg0 = c0 < k ? 1.0 / (gamma * fd0) : 1.0 / rho_b;
+    const double dg1 = c1 < k ? 1.0 / (gamma * fd1) : 1.0 / rho_b;
+#pragma unroll
+    for (int t = 0; t < kKfRows; ++t) {
+      const int i = wv + nw * t;
+      x0[t] = (i < kg && lane < kg) ? x0[t] + (i == lane ? dg0 : 0.0) : 0.0;
+      x1[t] = (i < kg && lane + 64 < kg) ? x1[t] + (i == lane + 64 ? dg1 : 0.0) : 0.0;
+    }
+    for (int p = 0; p < kg; ++p) {
+      double* rb = rbuf + (p & 1) * kg;
+      double* cb = cbuf + (p & 1) * kg;
+      const int pl = p & 63;
+      const bool phi = p >= 64;
+#pragma unroll
+      for (int t = 0; t < kKfRows; ++t) {
+        const int i = wv + nw * t;
+        if (i == p) {
+          if (lane < kg) rb[lane] = x0[t];
+          if (lane + 64 < kg) rb[lane + 64] = x1[t];
+        }
+        if (i < kg && lane == pl) cb[i] = phi ? x1[t] : x0[t];
+      }
+      __syncthreads();
+      // all of this step's LDS reads at once (clamped indices)
+      const double piv = rb[p], a0 = rb[c0], a1 = rb[c1];
+      double cr[kKfRows];
+#pragma unroll
+      for (int t = 0; t < kKfRows; ++t) cr[t] = cb[min(wv + nw * t, kg - 1)];
+      const double ip = 1.0 / piv;
+      const double r0 = lane < kg ? (lane == p ? 1.0 : a0) * ip : 0.0;
+      const double r1 = lane + 64 < kg ? (lane + 64 == p ? 1.0 : a1) * ip : 0.0;
+#pragma unroll
+      for (int t = 0; t < kKfRows; ++t) {
+        const int i = wv + nw * t;
+        const double c = (i < kg && i != p) ? cr[t] : 0.0;
+        x0[t] = (i == p) ? r0 : ((lane == p) ? 0.0 : x0[t]) - c * r0;
+        x1[t] = (i == p) ? r1 : ((lane + 64 == p) ? 0.0 : x1[t]) - c * r1;
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < kKfRows; ++t) {
+      const int i = wv + nw * t;
+      if (i < kg && lane < kg) X[i * kg + lane] = x0[t];
+      if (i < kg && lane + 64 < kg) X[i * kg + lane + 64] = x1[t];
+    }
+    __syncthreads();
   } else {
+  for (int e = threadIdx.x; e < kg * kg; e += blockDim.x) L[e] = k_entry(e / kg, e % kg);
+  __syncthreads();
   // right-looking Cholesky, lower triangle of L
   for (int j = 0; j < kg; ++j) {
     if (threadIdx.x == 0) L[j * kg + j] = sqrt(fmax(L[j * kg + j], 1e-300));
@@ -240,25 +274,27 @@ __global__ __launch_bounds__(1024) void kfactor_kernel(int k, int G, int kp, int
   }
   }
   }
-  // q = K^-1 c, sigma1 = 1^T Delta^-1 1 - c^T q
-  for (int j = threadIdx.x; j < kg; j += blockDim.x) {
+  // q = K^-1 c, a wave per row; sigma1 = 1^T Delta^-1 1 - c^T q
+  for (int j = wv; j < kg; j += nw) {
     double s = 0.0;
-    for (int l = 0; l < kg; ++l) s += X[j * kg + l] * Gm[l * nk + kg];
-    qv[j] = s;
+    for (int l = lane; l < kg; l += 64) s += X[j * kg + l] * cv[l];
+    for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o, 64);
+    if (lane == 0) qs[j] = s;
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
-    double s = Gm[kg * nk + kg];
-    for (int l = 0; l < kg; ++l) s -= Gm[l * nk + kg] * qv[l];
-    sig_out[0] = (float)s;
+  if (wv == 0) {
+    double s = 0.0;
+    for (int l = lane; l < kg; l += 64) s += cv[l] * qs[l];
+    for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o, 64);
+    if (lane == 0) sig_out[0] = (float)(cv[kg] - s);
   }
   for (int e = threadIdx.x; e < kp * kp; e += blockDim.x) {
     int j = e / kp, l = e % kp;
     Kinv_out[e] = (j < kg && l < kg) ? (float)X[j * kg + l] : 0.f;
   }
   for (int j = threadIdx.x; j < kp; j += blockDim.x) {
-    c_out[j] = (j < kg) ? (float)Gm[j * nk + kg] : 0.f;
-    q_out[j] = (j < kg) ? (float)qv[j] : 0.f;
+    c_out[j] = (j < kg) ? (float)cv[j] : 0.f;
+    q_out[j] = (j < kg) ? (float)qs[j] : 0.f;
   }
   for (int e = threadIdx.x; e < kp * G; e += blockDim.x) {
     int j = e / G, g = e % G;
@@ -1508,7 +1544,8 @@ hipError_t launch_kfactor(int k, int G, int kp, int nparts, const double* part, 
                           double gamma, double rho_b, double* Kw, float* Kinv, float* c,
                           float* q, float* sig, float* mbg, hipStream_t st) {
   const int kg = k + G;
-  const size_t smem = kg <= kKfLds ? 2 * sizeof(double) * kg * kg : 0;
+  // LDS: K^-1, the row and column buffers, c and q (wide blocks: c and q)
+  const size_t smem = sizeof(double) * (kg <= kKfLds ? (size_t)kg * kg + 6 * kg + 8 : 2 * kg + 8);
   const int ne = (kg + 1) * (kg + 1);
   hipLaunchKernelGGL(gram_reduce_kernel, dim3((ne + 255) / 256), dim3(256), 0, st, ne, nparts,
                      part, Kw);

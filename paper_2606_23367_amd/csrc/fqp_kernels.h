@@ -140,7 +140,7 @@ struct PackArgs {
   uint32_t* hold;
   int32_t* hold_pre;
   int32_t* hold_cnt;        // [m]
-  int32_t* hold_ptr;        // [m+1]
+  int32_t* hold_ptr;        // [m+2]: prefix [m+1], then the largest count
   float* hold_w0;
   int32_t* hold_tax;
   int32_t* status;          // [m]

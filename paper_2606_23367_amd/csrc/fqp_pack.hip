@@ -121,14 +121,20 @@ __global__ __launch_bounds__(256) void pack_count_kernel(PackArgs A) {
 }
 
 __global__ void pack_scan_kernel(PackArgs A) {
-  // exclusive scan of hold_cnt into hold_ptr (single workgroup)
-  __shared__ int carry;
+  // exclusive scan of hold_cnt into hold_ptr (single workgroup); the total
+  // goes to hold_ptr[m], the largest count of one account to hold_ptr[m + 1]
+  __shared__ int carry, most;
   __shared__ int sh[256];
-  if (threadIdx.x == 0) carry = 0;
+  if (threadIdx.x == 0) {
+    carry = 0;
+    most = 0;
+  }
   __syncthreads();
+  int mx = 0;
   for (int base = 0; base < A.m; base += 256) {
     const int i = base + threadIdx.x;
     const int v = (i < A.m) ? A.hold_cnt[i] : 0;
+    mx = max(mx, v);
     sh[threadIdx.x] = v;
     __syncthreads();
     for (int o = 1; o < 256; o <<= 1) {
@@ -142,7 +148,12 @@ __global__ void pack_scan_kernel(PackArgs A) {
     if (threadIdx.x == 255) carry += sh[255];
     __syncthreads();
   }
-  if (threadIdx.x == 0) A.hold_ptr[A.m] = carry;
+  atomicMax(&most, mx);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    A.hold_ptr[A.m] = carry;
+    A.hold_ptr[A.m + 1] = most;
+  }
 }
 
 __global__ __launch_bounds__(256) void pack_fill_kernel(PackArgs A) {

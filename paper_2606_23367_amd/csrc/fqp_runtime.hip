@@ -207,7 +207,12 @@ struct fqp_handle {
   hipEvent_t ev_t[4] = {nullptr, nullptr, nullptr, nullptr};   // phase timing
   // polish rounds: refining-account counts read back behind the launches
   hipEvent_t ev_r[4] = {nullptr, nullptr, nullptr, nullptr};
-  int32_t* hcount = nullptr;      // [4] pinned host memory
+  int32_t* hcount = nullptr;      // [8] pinned host memory: [0, 4) round counts, [4, 6) held names
+  hipEvent_t ev_pack = nullptr;   // the held-name counts copied back
+  // pinned host staging of the class tables: gamma [m], then the rho of
+  // each class [m at most] and the class of each account [m]; grown on demand
+  float* hstage = nullptr;
+  size_t hstage_n = 0;            // accounts it holds
   std::string err;
   fqp_stats stats{};
   std::map<std::string, DevBuf> bufs;
@@ -350,17 +355,19 @@ fqp_error fqp_create(fqp_handle** h, int device) {
   // default priority, non-blocking with respect to the legacy stream
   bool ok = hipStreamCreateWithFlags(&hh->stream, hipStreamNonBlocking) == hipSuccess &&
             hipEventCreateWithFlags(&hh->ev_in, hipEventDisableTiming) == hipSuccess &&
-            hipEventCreateWithFlags(&hh->ev_out, hipEventDisableTiming) == hipSuccess;
+            hipEventCreateWithFlags(&hh->ev_out, hipEventDisableTiming) == hipSuccess &&
+            hipEventCreateWithFlags(&hh->ev_pack, hipEventDisableTiming) == hipSuccess;
   for (int q = 0; q < 4 && ok; ++q) ok = hipEventCreate(&hh->ev_t[q]) == hipSuccess;
   for (int q = 0; q < 4 && ok; ++q)
     ok = hipEventCreateWithFlags(&hh->ev_r[q], hipEventDisableTiming) == hipSuccess;
-  ok = ok && hipHostMalloc((void**)&hh->hcount, 4 * sizeof(int32_t), hipHostMallocDefault) ==
+  ok = ok && hipHostMalloc((void**)&hh->hcount, 8 * sizeof(int32_t), hipHostMallocDefault) ==
                  hipSuccess;
   if (!ok) {
     (void)hipGetLastError();
     if (hh->stream) (void)hipStreamDestroy(hh->stream);
     if (hh->ev_in) (void)hipEventDestroy(hh->ev_in);
     if (hh->ev_out) (void)hipEventDestroy(hh->ev_out);
+    if (hh->ev_pack) (void)hipEventDestroy(hh->ev_pack);
     for (int q = 0; q < 4; ++q) {
       if (hh->ev_t[q]) (void)hipEventDestroy(hh->ev_t[q]);
       if (hh->ev_r[q]) (void)hipEventDestroy(hh->ev_r[q]);
@@ -387,11 +394,13 @@ void fqp_destroy(fqp_handle* h) {
   if (h->stream) (void)hipStreamDestroy(h->stream);
   if (h->ev_in) (void)hipEventDestroy(h->ev_in);
   if (h->ev_out) (void)hipEventDestroy(h->ev_out);
+  if (h->ev_pack) (void)hipEventDestroy(h->ev_pack);
   for (int q = 0; q < 4; ++q) {
     if (h->ev_t[q]) (void)hipEventDestroy(h->ev_t[q]);
     if (h->ev_r[q]) (void)hipEventDestroy(h->ev_r[q]);
   }
   if (h->hcount) (void)hipHostFree(h->hcount);
+  if (h->hstage) (void)hipHostFree(h->hstage);
   (void)hipSetDevice(cur);
   delete h;
 }
@@ -538,10 +547,23 @@ extern "C" fqp_error fqp_solve_batch(fqp_handle* h, const fqp_universe* U, const
   HIP_CHECK(hipEventRecord(h->ev_t[0], st));         // start of the device lane
 
   // ---- classes: distinct gamma values share one factor-space factorisation
-  std::vector<float> gam_h(m);
-  HIP_CHECK(hipMemcpyAsync(gam_h.data(), P->gamma, sizeof(float) * m, hipMemcpyDeviceToHost, st));
+  // (through pinned staging, so that the copies back to the device later
+  // on are asynchronous; the previous call's copies out of it are complete
+  // once the stream has drained here)
+  if (h->hstage_n < (size_t)m) {
+    HIP_CHECK(hipStreamSynchronize(st));
+    if (h->hstage) (void)hipHostFree(h->hstage);
+    h->hstage = nullptr;
+    h->hstage_n = 0;
+    HIP_CHECK(hipHostMalloc((void**)&h->hstage, 3 * sizeof(float) * (size_t)m,
+                            hipHostMallocDefault));
+    h->hstage_n = (size_t)m;
+  }
+  const float* gam_h = h->hstage;
+  float* rho_stage = h->hstage + m;
+  int* cls_h = reinterpret_cast<int*>(h->hstage + 2 * (size_t)m);
+  HIP_CHECK(hipMemcpyAsync(h->hstage, P->gamma, sizeof(float) * m, hipMemcpyDeviceToHost, st));
   HIP_CHECK(hipStreamSynchronize(st));
-  std::vector<int> cls_h(m);
   std::vector<float> cls_gamma;
   {
     std::map<float, int> seen;
@@ -585,7 +607,7 @@ extern "C" fqp_error fqp_solve_batch(fqp_handle* h, const fqp_universe* U, const
   WS(hold, uint32_t, "hold", (size_t)m * W);
   WS(hold_pre, int32_t, "hold_pre", (size_t)m * W);
   WS(hold_cnt, int32_t, "hold_cnt", (size_t)m);
-  WS(hold_ptr, int32_t, "hold_ptr", (size_t)m + 1);
+  WS(hold_ptr, int32_t, "hold_ptr", (size_t)m + 2);
   WS(hold_w0, float, "hold_w0", (size_t)m * n);
   WS(hold_tax, int32_t, "hold_tax", (size_t)m * n);
   WS(st_in, int32_t, "status_in", (size_t)m);
@@ -666,6 +688,9 @@ extern "C" fqp_error fqp_solve_batch(fqp_handle* h, const fqp_universe* U, const
   WS(btt_lo, uint16_t, "btt_lo", nbf);
 
   // ---- universe ------------------------------------------------------------
+  std::copy(rho_cls.begin(), rho_cls.end(), rho_stage);
+  HIP_CHECK(hipMemcpyAsync(rho_d, rho_stage, sizeof(float) * ncls, hipMemcpyHostToDevice, st));
+  HIP_CHECK(hipMemcpyAsync(cls_d, cls_h, sizeof(int) * m, hipMemcpyHostToDevice, st));
   HIP_CHECK(launch_build_bt(n, k, Gl, H, kp, U->B, U->group, U->half, Bt, st));
   if (concat_rows)
     HIP_CHECK(launch_concat_rows(m, Gl, H, P->band_lo, P->band_hi, P->half_lo, P->half_hi,
@@ -673,16 +698,6 @@ extern "C" fqp_error fqp_solve_batch(fqp_handle* h, const fqp_universe* U, const
   if (bench)
     HIP_CHECK(launch_benchmark_prep(m, n, k, U->B, U->f, U->d, P->mu, P->wb, P->eta, P->gamma,
                                     ywb, bpart, mu_b, mu_b64, obj_c, st));
-  if (split) HIP_CHECK(launch_split_bt(n, npad, kp, Bt, bt_hi, bt_lo, btt_hi, btt_lo, st));
-  HIP_CHECK(hipMemcpyAsync(rho_d, rho_cls.data(), sizeof(float) * ncls, hipMemcpyHostToDevice, st));
-  HIP_CHECK(hipMemcpyAsync(cls_d, cls_h.data(), sizeof(int) * m, hipMemcpyHostToDevice, st));
-  for (int c = 0; c < ncls; ++c) {
-    HIP_CHECK(launch_gram(n, kp, kg, nparts, gram_rows, Bt, U->d, cls_gamma[c], rho_cls[c], gpart, st));
-    HIP_CHECK(launch_kfactor(k, G, kp, nparts, gpart, U->f, cls_gamma[c], rho_b,
-                             Kw + kw_stride * c, Kinv + (size_t)c * kp * kp, cvec + (size_t)c * kp,
-                             qvec + (size_t)c * kp, sig1 + c, mbg + (size_t)c * kp * (G > 0 ? G : 1),
-                             st));
-  }
 
   // ---- book: validation and held records (workspace only) ----------------
   PackArgs pk{};
@@ -698,17 +713,24 @@ extern "C" fqp_error fqp_solve_batch(fqp_handle* h, const fqp_universe* U, const
   HIP_CHECK(launch_pack_count(pk, st));
   HIP_CHECK(launch_pack_scan(pk, st));
   HIP_CHECK(launch_pack_fill(pk, st));
-  // the held-asset records are sized by the packed count; the PROX layout
-  // by the most held names of any account
-  int n_held = 0, max_held = 0;
-  {
-    std::vector<int32_t> hp_h(m + 1);
-    HIP_CHECK(hipMemcpyAsync(hp_h.data(), hold_ptr, sizeof(int32_t) * (m + 1),
-                             hipMemcpyDeviceToHost, st));
-    HIP_CHECK(hipStreamSynchronize(st));
-    for (int a = 0; a < m; ++a) max_held = std::max(max_held, hp_h[a + 1] - hp_h[a]);
-    n_held = hp_h[m];
+  // the held-asset records are sized by the packed count, the PROX layout
+  // by the most held names of any account: both counts come back to pinned
+  // memory while the factor-space set-up below runs
+  HIP_CHECK(hipMemcpyAsync(h->hcount + 4, hold_ptr + m, 2 * sizeof(int32_t),
+                           hipMemcpyDeviceToHost, st));
+  HIP_CHECK(hipEventRecord(h->ev_pack, st));
+
+  // ---- universe: bf16 copies of B~ and the factor-space blocks per class
+  if (split) HIP_CHECK(launch_split_bt(n, npad, kp, Bt, bt_hi, bt_lo, btt_hi, btt_lo, st));
+  for (int c = 0; c < ncls; ++c) {
+    HIP_CHECK(launch_gram(n, kp, kg, nparts, gram_rows, Bt, U->d, cls_gamma[c], rho_cls[c], gpart, st));
+    HIP_CHECK(launch_kfactor(k, G, kp, nparts, gpart, U->f, cls_gamma[c], rho_b,
+                             Kw + kw_stride * c, Kinv + (size_t)c * kp * kp, cvec + (size_t)c * kp,
+                             qvec + (size_t)c * kp, sig1 + c, mbg + (size_t)c * kp * (G > 0 ? G : 1),
+                             st));
   }
+  HIP_CHECK(hipEventSynchronize(h->ev_pack));
+  const int n_held = h->hcount[4], max_held = h->hcount[5];
   const bool cap_resident = cap_resident_fits(n, max_held) && P->lb_asset == nullptr;
   WS(hold_rec, float4, "hold_rec", 2 * (size_t)std::max(n_held, 1));
   HIP_CHECK(launch_pack_rec(pk, hold_rec, n_held, st));
@@ -883,15 +905,28 @@ extern "C" fqp_error fqp_solve_batch(fqp_handle* h, const fqp_universe* U, const
     return FQP_OK;
   };
   int done_iters = 0;
-  int active = 0;
-  HIP_CHECK(hipMemcpyAsync(&active, m_act, sizeof(int), hipMemcpyDeviceToHost, st));
-  HIP_CHECK(hipStreamSynchronize(st));
-  if ((e = add_elapsed(h->stats.phase_ms[0], h->ev_t[0], h->ev_t[1])) != FQP_OK) return e;
+  // the number of valid accounts comes back to pinned memory while the
+  // first block of iterations runs (its passes skip every workgroup when
+  // no account is valid): the host does not wait for the set-up to drain
+  HIP_CHECK(hipMemcpyAsync(h->hcount + 6, m_act, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  HIP_CHECK(hipEventRecord(h->ev_pack, st));
+  bool count_known = false;
+  int active = 1;
+  auto first_count = [&]() -> fqp_error {
+    HIP_CHECK(hipEventSynchronize(h->ev_pack));
+    count_known = true;
+    active = h->hcount[6];
+    return add_elapsed(h->stats.phase_ms[0], h->ev_t[0], h->ev_t[1]);
+  };
   bool timed_out = false;
   while (active > 0 && done_iters < S.max_iter) {
     const int count = std::min(S.check_every, S.max_iter - done_iters);
     fqp_error be = run_block(count);
     if (be != FQP_OK) return be;
+    if (!count_known) {
+      if ((e = first_count()) != FQP_OK) return e;
+      if (active == 0) break;           // that block ran on an empty list
+    }
     done_iters += count;
     // no pass before first_check (blocks stay whole, so graph replays too)
     if (done_iters < S.first_check && done_iters < S.max_iter) continue;
@@ -939,6 +974,7 @@ extern "C" fqp_error fqp_solve_batch(fqp_handle* h, const fqp_universe* U, const
       break;
     }
   }
+  if (!count_known && (e = first_count()) != FQP_OK) return e;   // no block ran
   if (active > 0) {
     // last pattern from the current iterate, diagnostics, final statuses
     HIP_CHECK(launch_prox(ia, m, cap_resident, 1, st));   // z = prox(v; lam*)

@@ -132,6 +132,26 @@ def test_invalid_accounts_do_not_poison_batch():
         check_account(uni, book, a, host)
 
 
+def test_book_with_no_valid_account():
+    # every account rejected at set-up: the iteration passes see an empty
+    # active list, no iteration is counted and every output keeps its status
+    from paper_2606_23367_amd.solver import Solver
+    uni, book = make_config("c3", 3, N=700, M=4, k=8)
+    for a in range(book.m):
+        book.lb[a], book.ub[a] = 0.02, 0.01                  # lb > ub
+    s = Solver(0)
+    host, st = run_gpu(uni, book, solver=s, rho=5.0)
+    assert np.all(host["status"] == 5)
+    assert np.all(host["iters"] == 0)
+    assert st["iterations"] == 0 and st["n_solved"] == 0
+    assert np.all(host["w"] == 0.0) and np.all(np.isnan(host["obj"]))
+    # the same handle then solves a valid book of the same shape
+    uni2, book2 = make_config("c3", 3, N=700, M=4, k=8)
+    host2, _ = run_gpu(uni2, book2, solver=s, rho=5.0)
+    for a in range(book2.m):
+        check_account(uni2, book2, a, host2)
+
+
 def test_run_to_run_deterministic():
     uni, book = make_config("c3", 4, N=1500, M=6, k=12)
     h1, _ = run_gpu(uni, book, rho=5.0)
