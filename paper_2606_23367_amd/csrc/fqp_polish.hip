@@ -43,6 +43,7 @@ static_assert(kNPState <= kPStateStride, "polish bookkeeping does not fit");
 
 constexpr double kSnap = 1e-10;
 constexpr int kSmallF = 64;               // free sets solved in row space
+constexpr int kSchurL = 8;                // constraint systems solved in LDS
 constexpr int kMaxNull = 8;
 // the per-account kernels: one workgroup of 16 waves per account (their
 // serial parts are latency bound); the row passes run on row blocks below
@@ -429,7 +430,8 @@ __device__ void list_sums(const PolishArgs& A, const int32_t* list, int n, int c
 __device__ double* small_free_solve(const PolishArgs& A, int a, int nF, const int32_t* flist,
                                     const int8_t* code, const int* ps, int nc, int ncol,
                                     int cap_on, double gam, float lbf, float ubf, float kap,
-                                    bool phi, const Wk& wk, double* sm, double* shd) {
+                                    bool phi, const Wk& wk, double* sm, double* shd,
+                                    double* hd, double* Sd) {
   const int k = A.k, G = A.G, tid = threadIdx.x, n = A.n;
   double* Hs = sm;                                   // [nF][nF]
   double* Vs = Hs + kSmallF * kSmallF;               // [nF][ncol]
@@ -482,7 +484,7 @@ __device__ double* small_free_solve(const PolishArgs& A, int a, int nF, const in
     sgn_w0 += sgn * (double)rd.w0;
   }
   sgn_w0 = bsum<double>(sgn_w0, shd);            // (synchronises the staging)
-  if (tid == 0 && cap_on) wk.h[nc - 1] += sgn_w0;
+  if (tid == 0 && cap_on) hd[nc - 1] += sgn_w0;
   // H, lower triangle
   for (int e = tid; e < nF * nF; e += kPT) {
     const int r = e / nF, c = e % nF;
@@ -496,25 +498,23 @@ __device__ double* small_free_solve(const PolishArgs& A, int a, int nF, const in
   }
   for (int e = tid; e < nF * ncol; e += kPT) Xs[e] = Vs[e];
   __syncthreads();
-  // Cholesky by wave 0: lane i keeps row i; column j is scaled, then each
-  // lane updates its own row of the trailing block (LDS accesses of one
-  // wave complete in order; the fences keep the compiler from moving them)
+  // Cholesky by wave 0, column by column: at step j lane i >= j forms
+  // H_ij - sum_{l<j} L_il L_jl (the same subtractions, in the same order, as
+  // updating the trailing block after each column), reading only finished
+  // columns, so its loads do not wait on one another; the pivot comes from
+  // lane j by a shuffle.  (LDS accesses of one wave complete in order; the
+  // fences keep the compiler from moving them across the step boundary.)
   if (tid < 64) {
     const int i = tid;
     for (int j = 0; j < nF; ++j) {
-      const double djj = sqrt(fmax(Hs[j * nF + j], 1e-300));
-      double lij = 0.0;
-      if (i > j && i < nF) {
-        lij = Hs[i * nF + j] / djj;
-        Hs[i * nF + j] = lij;
+      double sij = 0.0;
+      if (i >= j && i < nF) {
+        sij = Hs[i * nF + j];
+        for (int l = 0; l < j; ++l) sij -= Hs[i * nF + l] * Hs[j * nF + l];
       }
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      const double djj = sqrt(fmax(__shfl(sij, j, 64), 1e-300));
       if (i == j) Hs[j * nF + j] = djj;
-      if (i > j && i < nF) {
-        for (int l = j + 1; l <= i; ++l) Hs[i * nF + l] -= lij * Hs[l * nF + j];
-      }
+      else if (i > j && i < nF) Hs[i * nF + j] = sij / djj;
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -527,7 +527,7 @@ __device__ double* small_free_solve(const PolishArgs& A, int a, int nF, const in
     const int p = e / ncol, q = e % ncol;
     double s = 0.0;
     for (int r = 0; r < nF; ++r) s += Vs[r * ncol + p] * Xs[r * ncol + q];
-    wk.S[p * ncol + q] = s;
+    Sd[p * ncol + q] = s;
   }
   return Xs;
 }
@@ -719,6 +719,78 @@ __global__ __launch_bounds__(kRT) void polish_rows_kernel(PolishArgs A) {
   }
 }
 
+// S eta = C H^-1 rhs - h for the multipliers of the active constraint
+// columns, with S = C H^-1 C^T positive semidefinite (nc x ncol, the rhs
+// column last).  A pivoted Cholesky finds the rank r; the pivot components
+// are solved for, the others keep their value in eta0, and the null
+// directions of S (the multipliers the free rows do not pin) go to nul
+// (rows of nul_stride).  One thread; Sm (nc x nc), perm, x and v are its
+// scratch.  Returns the number of null directions kept.
+__device__ __forceinline__ int schur_solve(int nc, int ncol, const double* Sv, const double* hv,
+                                           const double* e0, double* Sm, double* rr, int* perm,
+                                           double* x, double* v, double* nul, int nul_stride) {
+  double dmax = 0.0;
+  for (int p = 0; p < nc; ++p) {
+    perm[p] = p;
+    dmax = fmax(dmax, Sv[p * ncol + p]);
+    for (int q = 0; q < nc; ++q) Sm[p * nc + q] = Sv[p * ncol + q];
+  }
+  const double ptol = 1e-12 * dmax;
+  int rank = 0;
+  for (int j = 0; j < nc; ++j) {
+    int best = j;
+    for (int p = j + 1; p < nc; ++p)
+      if (Sm[p * nc + p] > Sm[best * nc + best]) best = p;
+    if (!(Sm[best * nc + best] > ptol)) break;
+    if (best != j) {
+      for (int q = 0; q < nc; ++q) { double t = Sm[j * nc + q]; Sm[j * nc + q] = Sm[best * nc + q]; Sm[best * nc + q] = t; }
+      for (int q = 0; q < nc; ++q) { double t = Sm[q * nc + j]; Sm[q * nc + j] = Sm[q * nc + best]; Sm[q * nc + best] = t; }
+      int t = perm[j]; perm[j] = perm[best]; perm[best] = t;
+    }
+    const double djj = sqrt(Sm[j * nc + j]);
+    Sm[j * nc + j] = djj;
+    for (int i = j + 1; i < nc; ++i) Sm[i * nc + j] /= djj;
+    for (int i = j + 1; i < nc; ++i)
+      for (int l = j + 1; l <= i; ++l) {
+        Sm[i * nc + l] -= Sm[i * nc + j] * Sm[l * nc + j];
+        Sm[l * nc + i] = Sm[i * nc + l];
+      }
+    ++rank;
+  }
+  // right-hand side on the pivot rows, null components from eta0
+  for (int j = 0; j < nc; ++j) x[j] = (j >= rank) ? e0[perm[j]] : 0.0;
+  for (int j = 0; j < rank; ++j) {
+    const int pj = perm[j];
+    double t = Sv[pj * ncol + nc] - hv[pj];
+    for (int q = rank; q < nc; ++q) t -= Sv[pj * ncol + perm[q]] * x[q];
+    x[j] = t;
+  }
+  for (int i = 0; i < rank; ++i) {
+    double t = x[i];
+    for (int l = 0; l < i; ++l) t -= Sm[i * nc + l] * x[l];
+    x[i] = t / Sm[i * nc + i];
+  }
+  for (int i = rank - 1; i >= 0; --i) {
+    double t = x[i];
+    for (int l = i + 1; l < rank; ++l) t -= Sm[l * nc + i] * x[l];
+    x[i] = t / Sm[i * nc + i];
+  }
+  for (int j = 0; j < nc; ++j) rr[perm[j]] = x[j];
+  // null directions: v_piv = -L11^-T L21^T e_t, v_t = 1
+  const int nd = min(nc - rank, kMaxNull);
+  for (int t = 0; t < nd; ++t) {
+    for (int j = 0; j < nc; ++j) v[j] = 0.0;
+    v[rank + t] = 1.0;
+    for (int i = rank - 1; i >= 0; --i) {
+      double u = -Sm[(rank + t) * nc + i];
+      for (int l = i + 1; l < rank; ++l) u -= Sm[l * nc + i] * v[l];
+      v[i] = u / Sm[i * nc + i];
+    }
+    for (int j = 0; j < nc; ++j) nul[t * nul_stride + perm[j]] = v[j];
+  }
+  return nd;
+}
+
 __global__ __launch_bounds__(kPT) void polish_solve_kernel(PolishArgs A) {
   extern __shared__ double smem_d[];
   const int k = A.k, G = A.G, n = A.n;
@@ -728,6 +800,10 @@ __global__ __launch_bounds__(kPT) void polish_solve_kernel(PolishArgs A) {
   double* stg = Kf + kfsz;                  // staging: 16 rows x (k + 4)
   __shared__ double shd[kPW];
   __shared__ int s_same;
+  // the constraint system when nc <= kSchurL
+  __shared__ double s_S[kSchurL * (kSchurL + 1)], s_Sm[kSchurL * kSchurL];
+  __shared__ double s_h[kSchurL], s_e0[kSchurL], s_eta[kSchurL], s_x[kSchurL], s_v[kSchurL];
+  __shared__ int s_perm[kSchurL];
   const int slot = blockIdx.x;
   if (slot >= *A.m_act) return;
   const int a = A.act[slot];
@@ -862,17 +938,23 @@ __global__ __launch_bounds__(kPT) void polish_solve_kernel(PolishArgs A) {
   for (int g = 0; g < G; ++g) nb += band_active(ps, g) ? 1 : 0;
   const int nc = 1 + nb + (cap_on ? 1 : 0);
   const int ncol = nc + 1;                      // + rhs column
+  // a constraint system of at most kSchurL columns lives in LDS (h, S and
+  // its factor): its thread-0 solve below is then a chain of LDS accesses,
+  // not of global memory round trips
+  const bool sl = nc <= kSchurL;
+  double* hd = sl ? s_h : wk.h;
+  double* Sd = sl ? s_S : wk.S;
   {
     if (tid == 0) {
-      wk.h[0] = 1.0 - sx;
+      hd[0] = 1.0 - sx;
       int col = 1;
       for (int g = 0; g < G; ++g) {
         if (!band_active(ps, g)) continue;
         const double bnd = band_upper(ps, g) ? A.bhi[(size_t)a * G + g] : A.blo[(size_t)a * G + g];
-        wk.h[col] = bnd - s_gfix[g];
+        hd[col] = bnd - s_gfix[g];
         ++col;
       }
-      if (cap_on) wk.h[col] = (double)tauf - sturn;   // + sum_F sgn w0 added below
+      if (cap_on) hd[col] = (double)tauf - sturn;     // + sum_F sgn w0 added below
       ps[PS_NF] = nF;
       ps[PS_NX] = nX;
       ps[PS_NC] = nc;
@@ -887,7 +969,7 @@ __global__ __launch_bounds__(kPT) void polish_solve_kernel(PolishArgs A) {
   double* Xs = nullptr;                   // small path: H^-1 [C | rhs] (LDS)
   if (small) {
     Xs = small_free_solve(A, a, nF, flist, code, ps, nc, ncol, cap_on, gam, lbf, ubf, kap,
-                          phi, wk, smem_d, shd);
+                          phi, wk, smem_d, shd, hd, Sd);
   } else {
   // ---- Kf = diag(1/f) + sum_F b b^T / d  (lower triangle, LDS) -----------
   // one 4 x 4 register tile of the lower triangle per thread; staged rows
@@ -1026,7 +1108,7 @@ __global__ __launch_bounds__(kPT) void polish_solve_kernel(PolishArgs A) {
     }
   }
   sgn_w0 = bsum<double>(sgn_w0, shd);
-  if (tid == 0 && cap_on) wk.h[nc - 1] += sgn_w0;
+  if (tid == 0 && cap_on) hd[nc - 1] += sgn_w0;
   __syncthreads();
 
   // ---- Cholesky of Kf (lower, in LDS) -------------------------------------
@@ -1054,15 +1136,16 @@ __global__ __launch_bounds__(kPT) void polish_solve_kernel(PolishArgs A) {
     const int p = e / ncol, q = e % ncol;
     double s = wk.CV[p * ncol + q];
     for (int j = 0; j < k; ++j) s -= wk.Waug[j * ncol + p] * wk.Y[j * ncol + q];
-    wk.S[p * ncol + q] = s / gam;
+    Sd[p * ncol + q] = s / gam;
   }
   }                                       // factor-space path
   __syncthreads();
   if (tid == 0) {
-    // eta0 from the ADMM iterate: -nu, band duals, lam_cap
-    // eta0: multipliers of the previous pattern (first pattern: ADMM's)
-    double* e0 = wk.eta0;
+    // eta0: multipliers of the previous pattern (first pattern: ADMM's):
+    // -nu, band duals, lam_cap
     const double* m0 = A.mult + (size_t)a * (2 + G);
+    double e0l[kMaxG + 3];
+    double* e0 = sl ? s_e0 : e0l;
     e0[0] = -m0[0];
     int col = 1;
     for (int g = 0; g < G; ++g) {
@@ -1070,77 +1153,17 @@ __global__ __launch_bounds__(kPT) void polish_solve_kernel(PolishArgs A) {
       e0[col++] = m0[2 + g];
     }
     if (cap_on) e0[col++] = fmax(m0[1], 0.0);
-    // S eta = C H^-1 rhs - h with S = C H^-1 C^T (PSD).  Pivoted Cholesky
-    // finds rank r; the pivot components are solved for, the others keep
-    // eta0, and the null directions of S (the multipliers the free rows do
-    // not pin) are stored for the certification step.
-    double* Sm = wk.CV;                  // CV is consumed: nc x nc factor
-    double* rr = wk.eta;
-    int perm[kMaxG + 3];
-    double dmax = 0.0;
-    for (int p = 0; p < nc; ++p) {
-      perm[p] = p;
-      dmax = fmax(dmax, wk.S[p * ncol + p]);
-      for (int q = 0; q < nc; ++q) Sm[p * nc + q] = wk.S[p * ncol + q];
-    }
-    const double ptol = 1e-12 * dmax;
-    int rank = 0;
-    for (int j = 0; j < nc; ++j) {
-      int best = j;
-      for (int p = j + 1; p < nc; ++p)
-        if (Sm[p * nc + p] > Sm[best * nc + best]) best = p;
-      if (!(Sm[best * nc + best] > ptol)) break;
-      if (best != j) {
-        for (int q = 0; q < nc; ++q) { double t = Sm[j * nc + q]; Sm[j * nc + q] = Sm[best * nc + q]; Sm[best * nc + q] = t; }
-        for (int q = 0; q < nc; ++q) { double t = Sm[q * nc + j]; Sm[q * nc + j] = Sm[q * nc + best]; Sm[q * nc + best] = t; }
-        int t = perm[j]; perm[j] = perm[best]; perm[best] = t;
-      }
-      const double djj = sqrt(Sm[j * nc + j]);
-      Sm[j * nc + j] = djj;
-      for (int i = j + 1; i < nc; ++i) Sm[i * nc + j] /= djj;
-      for (int i = j + 1; i < nc; ++i)
-        for (int l = j + 1; l <= i; ++l) {
-          Sm[i * nc + l] -= Sm[i * nc + j] * Sm[l * nc + j];
-          Sm[l * nc + i] = Sm[i * nc + l];
-        }
-      ++rank;
-    }
-    // right-hand side on the pivot rows, null components from eta0
-    double x[kMaxG + 3];
-    for (int j = 0; j < nc; ++j) x[j] = (j >= rank) ? e0[perm[j]] : 0.0;
-    for (int j = 0; j < rank; ++j) {
-      const int pj = perm[j];
-      double t = wk.S[pj * ncol + nc] - wk.h[pj];
-      for (int q = rank; q < nc; ++q) t -= wk.S[pj * ncol + perm[q]] * x[q];
-      x[j] = t;
-    }
-    for (int i = 0; i < rank; ++i) {
-      double t = x[i];
-      for (int l = 0; l < i; ++l) t -= Sm[i * nc + l] * x[l];
-      x[i] = t / Sm[i * nc + i];
-    }
-    for (int i = rank - 1; i >= 0; --i) {
-      double t = x[i];
-      for (int l = i + 1; l < rank; ++l) t -= Sm[l * nc + i] * x[l];
-      x[i] = t / Sm[i * nc + i];
-    }
-    for (int j = 0; j < nc; ++j) rr[perm[j]] = x[j];
-    // null directions: v_piv = -L11^-T L21^T e_t, v_t = 1
-    const int nd = min(nc - rank, kMaxNull);
-    for (int t = 0; t < nd; ++t) {
-      double v[kMaxG + 3];
-      for (int j = 0; j < nc; ++j) v[j] = 0.0;
-      v[rank + t] = 1.0;
-      for (int i = rank - 1; i >= 0; --i) {
-        double u = -Sm[(rank + t) * nc + i];
-        for (int l = i + 1; l < rank; ++l) u -= Sm[l * nc + i] * v[l];
-        v[i] = u / Sm[i * nc + i];
-      }
-      // rows of the null block have the workspace's full column stride
-      for (int j = 0; j < nc; ++j) wk.nul[t * (G + 3) + perm[j]] = v[j];
+    int nd;
+    if (sl) {
+      nd = schur_solve(nc, ncol, s_S, s_h, s_e0, s_Sm, s_eta, s_perm, s_x, s_v, wk.nul, G + 3);
+    } else {
+      int perm[kMaxG + 3];
+      double x[kMaxG + 3], v[kMaxG + 3];
+      nd = schur_solve(nc, ncol, wk.S, wk.h, e0l, wk.CV, wk.eta, perm, x, v, wk.nul, G + 3);
     }
     ps[PS_ND] = nd;
     // multipliers in the build's convention
+    const double* rr = sl ? s_eta : wk.eta;
     double* mult = A.mult + (size_t)a * (2 + G);
     mult[0] = -rr[0];
     col = 1;
@@ -1151,12 +1174,13 @@ __global__ __launch_bounds__(kPT) void polish_solve_kernel(PolishArgs A) {
     mult[1] = cap_on ? rr[col] : 0.0;
   }
   __syncthreads();
+  const double* etav = sl ? s_eta : wk.eta;
   double turn_f = 0.0;                    // turnover of the free rows
   if (small) {
     // w_F = H^-1 (rhs - C^T eta) = X[:, rhs] - X[:, C] eta
     for (int t = tid; t < nF; t += kPT) {
       double v = Xs[t * ncol + nc];
-      for (int p = 0; p < nc; ++p) v -= Xs[t * ncol + p] * wk.eta[p];
+      for (int p = 0; p < nc; ++p) v -= Xs[t * ncol + p] * etav[p];
       const int i = flist[t];
       w[i] = v;
       turn_f += fabs(v - (double)row_data(A, a, i, lbf, ubf).w0);
@@ -1165,7 +1189,7 @@ __global__ __launch_bounds__(kPT) void polish_solve_kernel(PolishArgs A) {
   // sol = Y[:, rhs] - Y[:, C] eta
   for (int j = tid; j < k; j += kPT) {
     double s = wk.Y[j * ncol + nc];
-    for (int p = 0; p < nc; ++p) s -= wk.Y[j * ncol + p] * wk.eta[p];
+    for (int p = 0; p < nc; ++p) s -= wk.Y[j * ncol + p] * etav[p];
     wk.sol[j] = s;
   }
   __syncthreads();
@@ -1184,14 +1208,14 @@ __global__ __launch_bounds__(kPT) void polish_solve_kernel(PolishArgs A) {
       bs += b * wk.sol[j];
     }
     const double rhs = mu_at(A, (size_t)a * n + i) - slope - gam * cross;
-    double ct = wk.eta[0];
+    double ct = etav[0];
     int col = 1;
     for (int gg = 0; gg < G; ++gg) {
       if (!band_active(ps, gg)) continue;
-      ct += row_coef(A, i, gg) * wk.eta[col];
+      ct += row_coef(A, i, gg) * etav[col];
       ++col;
     }
-    if (cap_on) ct += sgn * wk.eta[col];
+    if (cap_on) ct += sgn * etav[col];
     const double wi = (rhs - ct - bs) / (gam * (double)A.d[i]);
     w[i] = wi;
     turn_f += fabs(wi - (double)r.w0);
