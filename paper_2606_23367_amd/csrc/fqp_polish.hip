@@ -431,7 +431,7 @@ __device__ double* small_free_solve(const PolishArgs& A, int a, int nF, const in
                                     const int8_t* code, const int* ps, int nc, int ncol,
                                     int cap_on, double gam, float lbf, float ubf, float kap,
                                     bool phi, const Wk& wk, double* sm, double* shd,
-                                    double* hd, double* Sd) {
+                                    double* hd, double* Sd, int& i_mine, float& w0_mine) {
   const int k = A.k, G = A.G, tid = threadIdx.x, n = A.n;
   double* Hs = sm;                                   // [nF][nF]
   double* Vs = Hs + kSmallF * kSmallF;               // [nF][ncol]
@@ -462,11 +462,14 @@ __device__ double* small_free_solve(const PolishArgs& A, int a, int nF, const in
     }
   }
   __syncthreads();
-  // the constraint / rhs rows
+  // the constraint / rhs rows (free row r is the thread's own: nF <= kPT;
+  // its row and w0 are kept for the caller)
   double sgn_w0 = 0.0;
   for (int r = tid; r < nF; r += kPT) {
     const int i = flist[r];
     RowData rd = row_data(A, a, i, lbf, ubf);
+    i_mine = i;
+    w0_mine = rd.w0;
     Geom g;
     make_geom(g, kap, phi, rd);
     double slope, sgn;
@@ -804,6 +807,7 @@ __global__ __launch_bounds__(kPT) void polish_solve_kernel(PolishArgs A) {
   __shared__ double s_S[kSchurL * (kSchurL + 1)], s_Sm[kSchurL * kSchurL];
   __shared__ double s_h[kSchurL], s_e0[kSchurL], s_eta[kSchurL], s_x[kSchurL], s_v[kSchurL];
   __shared__ int s_perm[kSchurL];
+  __shared__ double s_m0[kMaxG + 2];       // multipliers of the previous pattern
   const int slot = blockIdx.x;
   if (slot >= *A.m_act) return;
   const int a = A.act[slot];
@@ -858,33 +862,51 @@ __global__ __launch_bounds__(kPT) void polish_solve_kernel(PolishArgs A) {
     s_of[bb + 1] = (int)rp[(size_t)bb * rps + kg + 2];
     s_ox[bb + 1] = (int)rp[(size_t)bb * rps + kg + 3];
   }
-  // column j of the partials summed in block order, eight blocks' loads in
-  // flight at a time; the signature (column kg + 4) by one thread
+  // the multipliers of the previous pattern, for the constraint system
+  // below (the first round's were written above)
+  for (int e = tid; e < 2 + G; e += kPT) s_m0[e] = A.mult[(size_t)a * (2 + G) + e];
+  // column j of the partials summed in block order, sixteen blocks' loads
+  // in flight at a time (past the last block: zeros, added at the end); the
+  // signature (column kg + 4) by one thread
   unsigned sig = 0u;
+  double yx_mine = 0.0, f_mine = 0.0;       // column tid < k: yX and f
   for (int j = tid; j < kg + 5; j += kPT) {
     if (j >= kg + 2 && !(A.first_round && j == kg + 4)) continue;
     double v = 0.0;
     unsigned su = 0u;
-    int bb = 0;
-    for (; bb + 8 <= S; bb += 8) {
-      double x[8];
+    for (int bb = 0; bb < S; bb += 16) {
+      double x[16];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) x[u] = rp[(size_t)(bb + u) * rps + j];
+      for (int u = 0; u < 16; ++u) x[u] = bb + u < S ? rp[(size_t)(bb + u) * rps + j] : 0.0;
 #pragma unroll
-      for (int u = 0; u < 8; ++u) { v += x[u]; su += (unsigned)x[u]; }
+      for (int u = 0; u < 16; ++u) { v += x[u]; su += (unsigned)x[u]; }
     }
-    for (; bb < S; ++bb) {
-      const double x = rp[(size_t)bb * rps + j];
-      v += x;
-      su += (unsigned)x;
+    if (j < k) {
+      const double fj = (double)A.f[j];
+      wk.yX[j] = v;
+      wk.Fy[j] = v * fj;
+      yx_mine = v;                          // (j = tid: kg + 5 <= kPT)
+      f_mine = fj;
     }
-    if (j < k) { wk.yX[j] = v; wk.Fy[j] = v * (double)A.f[j]; }
     else if (j < kg) s_gfix[j - k] = v;
     else if (j < kg + 2) s_sx[j - kg] = v;
     else s_sig = su;
   }
   __syncthreads();
-  if (tid == 0) {
+  // block offsets of the two lists: prefix sums (a wave scan when the
+  // account has at most 64 row blocks)
+  if (S <= 64) {
+    if (tid < 64) {
+      int vf = tid < S ? s_of[tid + 1] : 0, vx = tid < S ? s_ox[tid + 1] : 0;
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1) {
+        const int uf = __shfl_up(vf, o, 64), ux = __shfl_up(vx, o, 64);
+        if (tid >= o) { vf += uf; vx += ux; }
+      }
+      if (tid < S) { s_of[tid + 1] = vf; s_ox[tid + 1] = vx; }
+      if (tid == 0) { s_of[0] = 0; s_ox[0] = 0; }
+    }
+  } else if (tid == 0) {
     s_of[0] = 0;
     s_ox[0] = 0;
     for (int bb = 0; bb < S; ++bb) {
@@ -967,9 +989,11 @@ __global__ __launch_bounds__(kPT) void polish_solve_kernel(PolishArgs A) {
   // through the factor space below.
   const bool small = nF <= kSmallF;
   double* Xs = nullptr;                   // small path: H^-1 [C | rhs] (LDS)
+  int i_mine = 0;                         // small path: the thread's free row, its w0
+  float w0_mine = 0.f;
   if (small) {
     Xs = small_free_solve(A, a, nF, flist, code, ps, nc, ncol, cap_on, gam, lbf, ubf, kap,
-                          phi, wk, smem_d, shd, hd, Sd);
+                          phi, wk, smem_d, shd, hd, Sd, i_mine, w0_mine);
   } else {
   // ---- Kf = diag(1/f) + sum_F b b^T / d  (lower triangle, LDS) -----------
   // one 4 x 4 register tile of the lower triangle per thread; staged rows
@@ -1143,7 +1167,7 @@ __global__ __launch_bounds__(kPT) void polish_solve_kernel(PolishArgs A) {
   if (tid == 0) {
     // eta0: multipliers of the previous pattern (first pattern: ADMM's):
     // -nu, band duals, lam_cap
-    const double* m0 = A.mult + (size_t)a * (2 + G);
+    const double* m0 = s_m0;
     double e0l[kMaxG + 3];
     double* e0 = sl ? s_e0 : e0l;
     e0[0] = -m0[0];
@@ -1178,12 +1202,13 @@ __global__ __launch_bounds__(kPT) void polish_solve_kernel(PolishArgs A) {
   double turn_f = 0.0;                    // turnover of the free rows
   if (small) {
     // w_F = H^-1 (rhs - C^T eta) = X[:, rhs] - X[:, C] eta
-    for (int t = tid; t < nF; t += kPT) {
+    if (tid < nF) {
+      const int t = tid;
       double v = Xs[t * ncol + nc];
       for (int p = 0; p < nc; ++p) v -= Xs[t * ncol + p] * etav[p];
-      const int i = flist[t];
+      const int i = i_mine;
       w[i] = v;
-      turn_f += fabs(v - (double)row_data(A, a, i, lbf, ubf).w0);
+      turn_f += fabs(v - (double)w0_mine);
     }
   } else {
   // sol = Y[:, rhs] - Y[:, C] eta
@@ -1232,7 +1257,7 @@ __global__ __launch_bounds__(kPT) void polish_solve_kernel(PolishArgs A) {
   {
     double ys = 0.0, gs = 0.0;
     list_sums(A, flist, n, nF, 0, w, Kf, ys, gs);     // the solve is done with Kf
-    if (tid < k) wk.yF[tid] = (wk.yX[tid] + ys) * (double)A.f[tid];
+    if (tid < k) wk.yF[tid] = (yx_mine + ys) * f_mine;
     if (tid < G) wk.gsum[tid] = s_gfix[tid] + gs;
   }
 }
