@@ -250,7 +250,9 @@ BURDEN_GRID = dict(rho=(0.3, 1.0, 3.0, 10.0), alpha=(1.8,), check_every=(25, 50)
 def burden_lane(solver, steps=3):
     """Accounts/s of a 64 x 2,000 book as rule families accumulate (the
     paper's constraint-burden curve, synthetic): schedule tuned per bundle
-    on its seed-1 book, best of `steps` solves of the seed-0 book."""
+    on its seed-1 book with the finalists confirmed on the seed-2 and seed-3
+    books (schedules within a percent on one book can differ by a quarter on
+    another), best of `steps` solves of the seed-0 book."""
     import torch
     from workloads import make_config
     from paper_2606_23367_amd.solver import to_device
@@ -258,8 +260,9 @@ def burden_lane(solver, steps=3):
     rows = []
     for label, over in BURDEN:
         u1, b1 = make_config("c2", 1, **over)
+        others = [to_device(*make_config("c2", sd, **over), "cuda:0") for sd in (2, 3)]
         cfg = autotune(to_device(u1, b1, "cuda:0"), solver=solver, sample=b1.m,
-                       grid=BURDEN_GRID)
+                       grid=BURDEN_GRID, second=others)
         uni, book = make_config("c2", 0, **over)
         P = to_device(uni, book, "cuda:0")
         solver.solve(P, **cfg)
