@@ -145,6 +145,9 @@ struct PackArgs {
   int32_t* hold_tax;
   int32_t* status;          // [m]
   float* par;               // [m][kNPar]
+  // pinned host memory (device address) or null: the total of held names
+  // and the most held names of one account, stored by the scan
+  int32_t* host_counts;
 };
 hipError_t launch_pack_count(const PackArgs& A, hipStream_t st);
 hipError_t launch_pack_scan(const PackArgs& A, hipStream_t st);
@@ -210,9 +213,10 @@ struct PolishArgs {
   double* cpart;             // [m][n_sb][8] diagnostic partials
 };
 hipError_t launch_polish_solve(const PolishArgs& A, hipStream_t st);
-// pact / pm_act: the accounts of act / m_act that neither certified nor stalled
+// pact / pm_act: the accounts of act / m_act that neither certified nor stalled;
+// host_count (pinned host memory, device address, or null) also receives the count
 hipError_t launch_polish_list(const int* m_act, const int* act, const int32_t* pstate, int* pact,
-                              int* pm_act, hipStream_t st);
+                              int* pm_act, int* host_count, hipStream_t st);
 size_t polish_wk_stride(int k, int G);
 int polish_row_blocks(int n);
 int polish_pass_blocks(int n);

@@ -153,6 +153,10 @@ __global__ void pack_scan_kernel(PackArgs A) {
   if (threadIdx.x == 0) {
     A.hold_ptr[A.m] = carry;
     A.hold_ptr[A.m + 1] = most;
+    if (A.host_counts) {
+      A.host_counts[0] = carry;
+      A.host_counts[1] = most;
+    }
   }
 }
 

@@ -1997,7 +1997,7 @@ int polish_rpart_stride(int k, int G) { return rpart_stride(k, G); }
 // which works on groups of accounts) cover only those accounts.
 __global__ __launch_bounds__(1024) void polish_list_kernel(const int* m_act, const int* act,
                                                            const int32_t* pstate, int* pact,
-                                                           int* pm_act) {
+                                                           int* pm_act, int* host_count) {
   __shared__ int s_wc[16];
   __shared__ int s_base;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -2026,13 +2026,16 @@ __global__ __launch_bounds__(1024) void polish_list_kernel(const int* m_act, con
     }
     __syncthreads();
   }
-  if (tid == 0) *pm_act = s_base;
+  if (tid == 0) {
+    *pm_act = s_base;
+    if (host_count) *host_count = s_base;
+  }
 }
 
 hipError_t launch_polish_list(const int* m_act, const int* act, const int32_t* pstate, int* pact,
-                              int* pm_act, hipStream_t st) {
+                              int* pm_act, int* host_count, hipStream_t st) {
   hipLaunchKernelGGL(polish_list_kernel, dim3(1), dim3(1024), 0, st, m_act, act, pstate, pact,
-                     pm_act);
+                     pm_act, host_count);
   return hipGetLastError();
 }
 

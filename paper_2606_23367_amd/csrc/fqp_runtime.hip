@@ -97,7 +97,9 @@ __global__ void sanitize_state_kernel(size_t count, float* v) {
 }
 
 // active list = accounts whose status is still -1 (valid, not certified)
-__global__ void compact_kernel(int m, const int32_t* status, int* act, int* m_act) {
+// (host_count: pinned host memory that also receives the count, or null)
+__global__ void compact_kernel(int m, const int32_t* status, int* act, int* m_act,
+                               int* host_count) {
   __shared__ int sh[256];
   __shared__ int carry;
   if (threadIdx.x == 0) carry = 0;
@@ -118,7 +120,10 @@ __global__ void compact_kernel(int m, const int32_t* status, int* act, int* m_ac
     if (threadIdx.x == 255) carry += sh[255];
     __syncthreads();
   }
-  if (threadIdx.x == 0) *m_act = carry;
+  if (threadIdx.x == 0) {
+    *m_act = carry;
+    if (host_count) *host_count = carry;
+  }
 }
 
 // outputs of accounts that never ran (invalid / infeasible input)
@@ -207,7 +212,11 @@ struct fqp_handle {
   hipEvent_t ev_t[4] = {nullptr, nullptr, nullptr, nullptr};   // phase timing
   // polish rounds: refining-account counts read back behind the launches
   hipEvent_t ev_r[4] = {nullptr, nullptr, nullptr, nullptr};
-  int32_t* hcount = nullptr;      // [8] pinned host memory: [0, 4) round counts, [4, 6) held names
+  // [8] pinned host memory: [0, 4) round counts, [4, 6) held names, [6]
+  // valid accounts at set-up, [7] accounts left after a certification pass;
+  // kernels store the counts there themselves (no copy launch)
+  int32_t* hcount = nullptr;
+  int32_t* hcount_dev = nullptr;  // the same memory, as the device addresses it
   hipEvent_t ev_pack = nullptr;   // the held-name counts copied back
   // pinned host staging of the class tables: gamma [m], then the rho of
   // each class [m at most] and the class of each account [m]; grown on demand
@@ -362,6 +371,7 @@ fqp_error fqp_create(fqp_handle** h, int device) {
     ok = hipEventCreateWithFlags(&hh->ev_r[q], hipEventDisableTiming) == hipSuccess;
   ok = ok && hipHostMalloc((void**)&hh->hcount, 8 * sizeof(int32_t), hipHostMallocDefault) ==
                  hipSuccess;
+  ok = ok && hipHostGetDevicePointer((void**)&hh->hcount_dev, hh->hcount, 0) == hipSuccess;
   if (!ok) {
     (void)hipGetLastError();
     if (hh->stream) (void)hipStreamDestroy(hh->stream);
@@ -710,14 +720,13 @@ extern "C" fqp_error fqp_solve_batch(fqp_handle* h, const fqp_universe* U, const
   pk.tax_slope = P->tax_slope;
   pk.hold = hold; pk.hold_pre = hold_pre; pk.hold_cnt = hold_cnt; pk.hold_ptr = hold_ptr;
   pk.hold_w0 = hold_w0; pk.hold_tax = hold_tax; pk.status = st_in; pk.par = par;
+  pk.host_counts = h->hcount_dev + 4;
   HIP_CHECK(launch_pack_count(pk, st));
   HIP_CHECK(launch_pack_scan(pk, st));
   HIP_CHECK(launch_pack_fill(pk, st));
   // the held-asset records are sized by the packed count, the PROX layout
   // by the most held names of any account: both counts come back to pinned
   // memory while the factor-space set-up below runs
-  HIP_CHECK(hipMemcpyAsync(h->hcount + 4, hold_ptr + m, 2 * sizeof(int32_t),
-                           hipMemcpyDeviceToHost, st));
   HIP_CHECK(hipEventRecord(h->ev_pack, st));
 
   // ---- universe: bf16 copies of B~ and the factor-space blocks per class
@@ -756,7 +765,8 @@ extern "C" fqp_error fqp_solve_batch(fqp_handle* h, const fqp_universe* U, const
   } else {
     HIP_CHECK(hipMemsetAsync(v, 0, sizeof(float) * (size_t)m * n, st));
   }
-  hipLaunchKernelGGL(compact_kernel, dim3(1), dim3(256), 0, st, m, R->status, act, m_act);
+  hipLaunchKernelGGL(compact_kernel, dim3(1), dim3(256), 0, st, m, R->status, act, m_act,
+                     h->hcount_dev + 6);
   HIP_CHECK(hipGetLastError());
 
   IterArgs ia;
@@ -908,7 +918,6 @@ extern "C" fqp_error fqp_solve_batch(fqp_handle* h, const fqp_universe* U, const
   // the number of valid accounts comes back to pinned memory while the
   // first block of iterations runs (its passes skip every workgroup when
   // no account is valid): the host does not wait for the set-up to drain
-  HIP_CHECK(hipMemcpyAsync(h->hcount + 6, m_act, sizeof(int32_t), hipMemcpyDeviceToHost, st));
   HIP_CHECK(hipEventRecord(h->ev_pack, st));
   bool count_known = false;
   int active = 1;
@@ -938,17 +947,17 @@ extern "C" fqp_error fqp_solve_batch(fqp_handle* h, const fqp_universe* U, const
     pa.max_prop = 16;
     for (int r = 0; r < S.polish_rounds; ++r) {
       pa.first_round = (r == 0);
-      // later rounds: only the accounts still refining; their count is also
-      // copied back, and the host stops launching rounds once the count of
-      // the round before this one (read without stalling the device, which
-      // still has this round queued) shows none left
+      // later rounds: only the accounts still refining; the list kernel also
+      // stores their count to pinned host memory, and the host stops
+      // launching rounds once the count of the round before this one (read
+      // without stalling the device, which still has this round queued)
+      // shows none left
       PolishArgs pr = pa;
       if (r > 0) {
-        HIP_CHECK(launch_polish_list(m_act, act, pstate, pact, pm_act, st));
+        HIP_CHECK(launch_polish_list(m_act, act, pstate, pact, pm_act, h->hcount_dev + (r & 3),
+                                     st));
         pr.act = pact;
         pr.m_act = pm_act;
-        HIP_CHECK(hipMemcpyAsync(h->hcount + (r & 3), pm_act, sizeof(int32_t),
-                                 hipMemcpyDeviceToHost, st));
         HIP_CHECK(hipEventRecord(h->ev_r[r & 3], st));
       }
       HIP_CHECK(launch_polish_solve(pr, st));
@@ -959,11 +968,12 @@ extern "C" fqp_error fqp_solve_batch(fqp_handle* h, const fqp_universe* U, const
         if (h->hcount[(r - 1) & 3] == 0) break;
       }
     }
-    hipLaunchKernelGGL(compact_kernel, dim3(1), dim3(256), 0, st, m, R->status, act, m_act);
+    hipLaunchKernelGGL(compact_kernel, dim3(1), dim3(256), 0, st, m, R->status, act, m_act,
+                       h->hcount_dev + 7);
     HIP_CHECK(hipGetLastError());
-    HIP_CHECK(hipMemcpyAsync(&active, m_act, sizeof(int), hipMemcpyDeviceToHost, st));
     HIP_CHECK(hipEventRecord(h->ev_t[3], st));
     HIP_CHECK(hipStreamSynchronize(st));
+    active = h->hcount[7];
     if ((e = add_elapsed(h->stats.phase_ms[1], h->ev_t[1], h->ev_t[2])) != FQP_OK) return e;
     if ((e = add_elapsed(h->stats.phase_ms[2], h->ev_t[2], h->ev_t[3])) != FQP_OK) return e;
     std::swap(h->ev_t[1], h->ev_t[3]);             // the next stretch starts here
