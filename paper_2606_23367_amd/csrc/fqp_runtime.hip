@@ -126,6 +126,36 @@ __global__ void compact_kernel(int m, const int32_t* status, int* act, int* m_ac
   }
 }
 
+// the call's counters for the host, stored into pinned host memory (out:
+// certified accounts, account-iterations, polish solves, gated polish
+// attempts); one workgroup, so the host needs no copy of status or iters
+__global__ __launch_bounds__(256) void solve_stats_kernel(int m, const int32_t* status,
+                                                          const int* iters, const int32_t* pcount,
+                                                          long long* out) {
+  __shared__ long long s_c[4], s_i[4];
+  long long c = 0, it = 0;
+  for (int a = threadIdx.x; a < m; a += 256) {
+    c += status[a] == FQP_SOLVED ? 1 : 0;
+    it += iters[a];
+  }
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) {
+    c += __shfl_xor(c, o, 64);
+    it += __shfl_xor(it, o, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    s_c[threadIdx.x >> 6] = c;
+    s_i[threadIdx.x >> 6] = it;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    out[0] = s_c[0] + s_c[1] + s_c[2] + s_c[3];
+    out[1] = s_i[0] + s_i[1] + s_i[2] + s_i[3];
+    out[2] = pcount[0];
+    out[3] = pcount[1];
+  }
+}
+
 // outputs of accounts that never ran (invalid / infeasible input)
 __global__ void finalize_kernel(int m, int n, const int32_t* status, const int* iters_dev,
                                 fqp_result R) {
@@ -217,6 +247,10 @@ struct fqp_handle {
   // kernels store the counts there themselves (no copy launch)
   int32_t* hcount = nullptr;
   int32_t* hcount_dev = nullptr;  // the same memory, as the device addresses it
+  // [4] pinned host memory: certified accounts, account-iterations, polish
+  // solves, gated polish attempts of the last call (solve_stats_kernel)
+  long long* hstat = nullptr;
+  long long* hstat_dev = nullptr;
   hipEvent_t ev_pack = nullptr;   // the held-name counts copied back
   // pinned host staging of the class tables: gamma [m], then the rho of
   // each class [m at most] and the class of each account [m]; grown on demand
@@ -372,6 +406,9 @@ fqp_error fqp_create(fqp_handle** h, int device) {
   ok = ok && hipHostMalloc((void**)&hh->hcount, 8 * sizeof(int32_t), hipHostMallocDefault) ==
                  hipSuccess;
   ok = ok && hipHostGetDevicePointer((void**)&hh->hcount_dev, hh->hcount, 0) == hipSuccess;
+  ok = ok && hipHostMalloc((void**)&hh->hstat, 4 * sizeof(long long), hipHostMallocDefault) ==
+                 hipSuccess;
+  ok = ok && hipHostGetDevicePointer((void**)&hh->hstat_dev, hh->hstat, 0) == hipSuccess;
   if (!ok) {
     (void)hipGetLastError();
     if (hh->stream) (void)hipStreamDestroy(hh->stream);
@@ -383,6 +420,7 @@ fqp_error fqp_create(fqp_handle** h, int device) {
       if (hh->ev_r[q]) (void)hipEventDestroy(hh->ev_r[q]);
     }
     if (hh->hcount) (void)hipHostFree(hh->hcount);
+    if (hh->hstat) (void)hipHostFree(hh->hstat);
     delete hh;
     (void)hipSetDevice(cur);
     return FQP_ERR_HIP;
@@ -410,6 +448,7 @@ void fqp_destroy(fqp_handle* h) {
     if (h->ev_r[q]) (void)hipEventDestroy(h->ev_r[q]);
   }
   if (h->hcount) (void)hipHostFree(h->hcount);
+  if (h->hstat) (void)hipHostFree(h->hstat);
   if (h->hstage) (void)hipHostFree(h->hstage);
   (void)hipSetDevice(cur);
   delete h;
@@ -1010,23 +1049,19 @@ extern "C" fqp_error fqp_solve_batch(fqp_handle* h, const fqp_universe* U, const
     HIP_CHECK(hipGetLastError());
   }
   HIP_CHECK(hipEventRecord(h->ev_t[2], st));
-  // count solved accounts and account-iterations
-  std::vector<int32_t> st_h(m);
-  std::vector<int> it_h(m);
-  int32_t pc_h[2] = {0, 0};
-  HIP_CHECK(hipMemcpyAsync(pc_h, pcount, sizeof(pc_h), hipMemcpyDeviceToHost, st));
-  HIP_CHECK(hipMemcpyAsync(st_h.data(), R->status, sizeof(int32_t) * m, hipMemcpyDeviceToHost, st));
-  HIP_CHECK(hipMemcpyAsync(it_h.data(), iters, sizeof(int) * m, hipMemcpyDeviceToHost, st));
+  // count solved accounts and account-iterations (stored into pinned host
+  // memory by one small kernel: no copy of status or iters)
+  hipLaunchKernelGGL(solve_stats_kernel, dim3(1), dim3(256), 0, st, m, R->status, iters, pcount,
+                     h->hstat_dev);
+  HIP_CHECK(hipGetLastError());
   HIP_CHECK(hipStreamSynchronize(st));
   if ((e = add_elapsed(h->stats.phase_ms[3], h->ev_t[1], h->ev_t[2])) != FQP_OK) return e;
-  for (int a = 0; a < m; ++a) {
-    h->stats.n_solved += (st_h[a] == FQP_SOLVED);
-    h->stats.account_iters += it_h[a];
-  }
+  h->stats.n_solved += (int32_t)h->hstat[0];
+  h->stats.account_iters += (double)h->hstat[1];
   h->stats.iterations = done_iters;
   h->stats.graph_reused = (replayed && !captured) ? 1 : 0;
-  h->stats.polish_solves = pc_h[0];
-  h->stats.polish_gated = pc_h[1];
+  h->stats.polish_solves = (int32_t)h->hstat[2];
+  h->stats.polish_gated = (int32_t)h->hstat[3];
   {
     AdjArgs& L = h->last;
     L = AdjArgs{};
