@@ -251,7 +251,7 @@ struct fqp_handle {
   // solves, gated polish attempts of the last call (solve_stats_kernel)
   long long* hstat = nullptr;
   long long* hstat_dev = nullptr;
-  hipEvent_t ev_pack = nullptr;   // the held-name counts copied back
+  hipEvent_t ev_pack = nullptr;   // set-up counts (held names, valid accounts) are in hcount
   // pinned host staging of the class tables: gamma [m], then the rho of
   // each class [m at most] and the class of each account [m]; grown on demand
   float* hstage = nullptr;
