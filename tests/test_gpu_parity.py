@@ -152,6 +152,24 @@ def test_book_with_no_valid_account():
         check_account(uni2, book2, a, host2)
 
 
+def test_call_counters_match_the_outputs():
+    # the certified count and the account-iterations the library reports
+    # (reduced on the device into pinned host memory) equal what the
+    # outputs show, over two calls of different books on one handle (the
+    # second with invalid accounts and a smaller batch)
+    from paper_2606_23367_amd.solver import Solver
+    s = Solver(0)
+    for seed, M in ((7, 9), (8, 5)):
+        uni, book = make_config("c3", seed, N=1100, M=M, k=8)
+        if seed == 8:
+            book.lb[1], book.ub[1] = 0.02, 0.01              # invalid account
+        host, st = run_gpu(uni, book, solver=s, rho=5.0)
+        assert st["n_solved"] == int(np.sum(host["status"] == 0))
+        assert st["account_iters"] == float(np.sum(host["iters"]))
+        assert st["polish_solves"] >= st["n_solved"] and st["polish_gated"] >= 0
+        assert st["iterations"] == int(np.max(host["iters"]))
+
+
 def test_run_to_run_deterministic():
     uni, book = make_config("c3", 4, N=1500, M=6, k=12)
     h1, _ = run_gpu(uni, book, rho=5.0)
