@@ -170,6 +170,18 @@ def test_call_counters_match_the_outputs():
         assert st["iterations"] == int(np.max(host["iters"]))
 
 
+@pytest.mark.parametrize("cfg,k", [("c3", 63), ("c3", 64), ("c3", 65), ("c3", 96),
+                                   ("c2", 86), ("c2", 87)])
+def test_factor_block_widths_around_the_register_layout(cfg, k):
+    # K^-1 of a factor block of k + G columns: in registers up to 96 (lanes
+    # hold columns lane and lane + 64, waves rows w + 16 t), triangular
+    # sweeps beyond; the widths straddle 64 and 96 (c2 adds 10 band columns)
+    uni, book = make_config(cfg, 11, N=700, M=2, k=k)
+    host, _ = run_gpu(uni, book, rho=5.0)
+    for a in range(book.m):
+        check_account(uni, book, a, host)
+
+
 def test_run_to_run_deterministic():
     uni, book = make_config("c3", 4, N=1500, M=6, k=12)
     h1, _ = run_gpu(uni, book, rho=5.0)
