@@ -182,6 +182,18 @@ def test_factor_block_widths_around_the_register_layout(cfg, k):
         check_account(uni, book, a, host)
 
 
+@pytest.mark.parametrize("hw", [1e-4, 1e-3, 5e-3])
+def test_tight_sector_bands(hw):
+    # ten sector bands of half-width hw around the equal-weight shares: at
+    # 1e-4 nearly all bind (a constraint system past eight columns, whose
+    # band rows sum to the budget row: dependent, solved with null
+    # directions), wider bands leave a few active (the system in LDS)
+    uni, book = make_config("c2", 11, N=700, M=3, k=8, band_halfwidth=hw)
+    host, _ = run_gpu(uni, book, rho=5.0)
+    for a in range(book.m):
+        check_account(uni, book, a, host)
+
+
 def test_run_to_run_deterministic():
     uni, book = make_config("c3", 4, N=1500, M=6, k=12)
     h1, _ = run_gpu(uni, book, rho=5.0)
