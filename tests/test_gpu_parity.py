@@ -194,6 +194,19 @@ def test_tight_sector_bands(hw):
         check_account(uni, book, a, host)
 
 
+def test_one_handle_across_growing_books():
+    # a small book, then larger ones (more accounts, more assets) on the same
+    # handle: the pinned class staging and the workspaces grow between calls
+    from paper_2606_23367_amd.solver import Solver
+    s = Solver(0)
+    for seed, N, M in ((13, 600, 3), (14, 900, 12), (15, 1300, 20)):
+        uni, book = make_config("c3", seed, N=N, M=M, k=8)
+        host, st = run_gpu(uni, book, solver=s, rho=5.0)
+        assert st["n_solved"] == M
+        for a in (0, M // 2, M - 1):
+            check_account(uni, book, a, host)
+
+
 def test_run_to_run_deterministic():
     uni, book = make_config("c3", 4, N=1500, M=6, k=12)
     h1, _ = run_gpu(uni, book, rho=5.0)
